@@ -1,0 +1,122 @@
+"""Ways to apply M^{-1} (M = tA) for the oracle (test infrastructure).
+
+Section 4.1: for moderate n the paper factors A once by sparse LU and applies
+U \\ (L \\ w); for Toeplitz A it uses the Gohberg-Semencul formula; for very
+large n an iterative solve.  Each function returns a callable V -> M^{-1} V.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def splu_inverse(M: sp.spmatrix):
+    """Sparse LU of M once, then two triangular solves per column (Section 4.1)."""
+    lu = spla.splu(sp.csc_matrix(M))
+    return lambda V: lu.solve(np.asarray(V, dtype=np.float64))
+
+
+def laplacian_eigs(N: int, dim: int) -> np.ndarray:
+    """Eigenvalues of the unscaled dim-D Dirichlet Laplacian on N^dim, as an
+    array of shape (N,)*dim indexed like the grid (axis order z, y, x)."""
+    mu1 = 2.0 - 2.0 * np.cos(np.pi * np.arange(1, N + 1) / (N + 1))
+    grids = np.meshgrid(*([mu1] * dim), indexing="ij")
+    return sum(grids)
+
+
+def _dst_apply(V, N, dim, diag):
+    """S diag S^T V with S the orthonormal DST-I on each grid axis."""
+    n, q = V.shape
+    shp = (N,) * dim
+    out = np.empty_like(V)
+    axes = tuple(range(dim))
+    for j in range(q):
+        u = V[:, j].reshape(shp)
+        u = sfft.dstn(u, type=1, axes=axes, norm="ortho")
+        u *= diag
+        u = sfft.idstn(u, type=1, axes=axes, norm="ortho")
+        out[:, j] = u.ravel()
+    return out
+
+
+def dst_laplacian_inverse(N: int, dim: int, t: float):
+    """M = -t L exactly diagonalised by the DST-I: M^{-1} = S diag(-1/(t mu)) S."""
+    mu = laplacian_eigs(N, dim)
+    diag = -1.0 / (t * mu)
+    return lambda V: _dst_apply(np.asarray(V, np.float64), N, dim, diag)
+
+
+def dst_laplacian_function(N: int, dim: int, t: float, f, V):
+    """f(M) V for M = -t L, f applied to the exact eigenvalues -t mu."""
+    mu = laplacian_eigs(N, dim)
+    lam = -t * mu
+    vals = f(lam.ravel()).reshape(lam.shape)
+    return _dst_apply(np.asarray(V, np.float64), N, dim, vals)
+
+
+# ---- Toeplitz -----------------------------------------------------------------
+
+def toeplitz_matvec(col: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """T V for symmetric Toeplitz T = toeplitz(col) via circulant embedding of
+    size 2n (Section 2 remark on fast Toeplitz products)."""
+    n = len(col)
+    emb = np.concatenate([col, [0.0], col[1:][::-1]])
+    sym = sfft.rfft(emb)
+    W = sfft.irfft(sym[:, None] * sfft.rfft(V, n=2 * n, axis=0), n=2 * n, axis=0)
+    return W[:n]
+
+
+def levinson_first_column(col: np.ndarray) -> np.ndarray:
+    """x = T^{-1} e_1 for symmetric positive definite Toeplitz T (scipy's
+    Levinson-Durbin solver)."""
+    e1 = np.zeros(len(col))
+    e1[0] = 1.0
+    return sla.solve_toeplitz(col, e1)
+
+
+def gohberg_semencul_inverse(col: np.ndarray, scale: float):
+    """(scale*T)^{-1} V for symmetric positive definite Toeplitz T by the
+    Gohberg-Semencul formula (Section 4.1): with x = T^{-1} e_1,
+        T^{-1} = (1/x_0) (L(x) L(x)^T - L(Z x~) L(Z x~)^T),
+    L(y) the lower-triangular Toeplitz matrix with first column y, x~ the
+    reversal of x and Z the down-shift.  Each lower/upper triangular Toeplitz
+    product is a length-2n FFT convolution."""
+    n = len(col)
+    x = levinson_first_column(col)
+    xr = x[::-1]
+    y = np.concatenate([[0.0], xr[:-1]])      # Z x~
+
+    def lower(vec_col, V):                    # L(vec) V
+        F = sfft.rfft(vec_col, n=2 * n)
+        return sfft.irfft(F[:, None] * sfft.rfft(V, n=2 * n, axis=0), n=2 * n, axis=0)[:n]
+
+    def upper(vec_col, V):                    # L(vec)^T V = reverse(L(vec) reverse(V))
+        return lower(vec_col, V[::-1])[::-1]
+
+    def apply(V):
+        V = np.asarray(V, np.float64)
+        W = lower(x, upper(x, V)) - lower(y, upper(y, V))
+        return W / (x[0] * scale)
+    return apply
+
+
+# ---- iterative ----------------------------------------------------------------
+
+def krylov_inverse(M: sp.spmatrix, rtol: float = 1e-14, symmetric: bool = True, maxiter=100000):
+    """Column-by-column CG (on -M, SPD) or BiCGStab to relative residual rtol."""
+    Mneg = -sp.csr_matrix(M)
+    solver = spla.cg if symmetric else spla.bicgstab
+
+    def apply(V):
+        V = np.asarray(V, np.float64)
+        out = np.empty_like(V)
+        for j in range(V.shape[1]):
+            xj, infoj = solver(Mneg, -V[:, j], rtol=rtol, atol=0.0, maxiter=maxiter)
+            if infoj != 0:
+                raise RuntimeError(f"inner solve did not converge (info={infoj})")
+            out[:, j] = xj
+        return out
+    return apply
