@@ -1,0 +1,172 @@
+#!/usr/bin/env python
+"""Benchmark: time of one e^{tA}B solve (PSBFOM-DR, FP64) on one MI355X.
+
+Workload (default): 3D 7-point Dirichlet Laplacian on 64^3 (n = 262,144,
+1.81M nonzeros), ||tA||_2 = 1e4, B = 262,144 x 8 Gaussian (seed 2), block
+Arnoldi length m = 15, k = 40, tol = 1e-10 on the error bound.  One "step"
+is one full solve (every cycle, inner solve, orthogonalisation, projected
+solve, update and the final combination) with A's plan and B already in
+HBM.  Prints one JSON line.
+
+Also reported:
+  roofline      the dominant kernel of the inner CG (the one with the
+                largest mean launch time among SpMM, residual update and
+                direction update), timed with HIP events on the solver's
+                stream during the timed steps (every 16th iteration);
+                achieved = algorithmic bytes per launch / mean duration.
+  cpu_baseline  the oracle (plain numpy FP64, one thread) on a bounded
+                sample of the same workload, scaled to one solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=16,
+                    help="sample every N-th inner iteration with HIP events (0 = off)")
+    return ap.parse_args()
+
+
+def cg_kernel_bytes(n: int, nnz: int, p: int) -> dict:
+    """Algorithmic HBM bytes per launch of the inner CG's three kernels
+    (FP64 values, int32 indices):
+      A  q = K p (CSR SpMM) + partial (p, q): rowptr 4(n+1), colind and
+         values 12 nnz, read p and write q 16 n p;
+      B  r -= alpha q + partials: dinv 8 n, read r, q and write r 24 n p;
+      C  x += alpha p_old, p_new = D^{-1} r + beta p_old: dinv 8 n, read r,
+         p_old, x and write p_new, x 40 n p."""
+    return {"A": 4 * (n + 1) + 12 * nnz + 16 * n * p,
+            "B": 8 * n + 24 * n * p,
+            "C": 8 * n + 40 * n * p}
+
+
+def cpu_baseline(W):
+    """Oracle PSBFOM-DR on the same workload with m = 6 (48 of the 120
+    A^{-1} column applications of one solve, one cycle), DST-I inverse,
+    one thread; scaled by the A^{-1} column count to one solve."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import inverses, psbfom
+    m_s = 6
+    N = round(W.n ** (1 / 3))
+    inv = inverses.dst_laplacian_inverse(N, 3, W.t)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        _, _, info = psbfom.psbfom_dr(inv, W.B, m_s, W.k, W.tol, max_cycles=1)
+        el = time.perf_counter() - t0
+    full_cols = W.m * W.p
+    scale = full_cols / info.op_columns
+    return {"value": el * scale, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle PSBFOM-DR, same 64^3 workload, m={m_s} (1 cycle, "
+                       f"{info.op_columns} of {full_cols} A^-1 column applications), "
+                       f"{el:.2f} s measured, scaled x{scale:.1f} by A^-1 applications; "
+                       "MGS cost grows faster than linearly, so this underestimates")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1405_0707_amd import Plan
+
+    dev = "cuda:0"
+    W = wl.c2()
+    t0 = time.perf_counter()
+    plan = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=dev, m=W.m, k=W.k,
+                    profile=max(0, args.profile_every))
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    B = torch.from_numpy(W.B).to(dev)
+    Z = torch.empty_like(B)
+    for _ in range(args.warmup):
+        plan.execute(B, tol=W.tol, out=Z)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, info = plan.execute(B, tol=W.tol, out=Z)
+        infos.append(info)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = 1000.0 * el / args.steps
+    info = infos[-1]
+
+    # accuracy against the DST-I closed form of r(tA)B (oracle, CPU)
+    from oracle import inverses
+    from oracle.cf import r_eval
+    rB = inverses.dst_laplacian_function(64, 3, W.t, lambda lam: r_eval(np.asarray(lam)), W.B)
+    Zh = Z.cpu().numpy()
+    rel_err = float(np.linalg.norm(Zh - rB) / np.linalg.norm(rB))
+
+    samples = sum(i.kern_samples for i in infos)
+    roof = None
+    kernels = None
+    if samples:
+        mean = {key: sum(getattr(i, "kern_ms_" + key.lower()) * i.kern_samples for i in infos)
+                / samples for key in ("A", "B", "C")}
+        byt = cg_kernel_bytes(W.n, W.A.nnz, W.p)
+        names = {"A": "k_cg_a (CSR SpMM q = K p of the inner CG)",
+                 "B": "k_cg_b (inner CG residual update)",
+                 "C": "k_cg_c (inner CG direction and iterate update)"}
+        kernels = {key: {"kernel": names[key], "mean_launch_ms": round(mean[key], 5),
+                         "bytes_per_launch": byt[key],
+                         "achieved_GBs": round(byt[key] / (mean[key] * 1e-3) / 1e9, 1)}
+                   for key in mean}
+        dom = max(mean, key=lambda key: mean[key])
+        ach = byt[dom] / (mean[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": names[dom], "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_launch": byt[dom],
+                "mean_launch_ms": round(mean[dom], 5), "samples": samples}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(W)
+
+    out = {
+        "metric": "e^{tA}B time per solve (FP64, 3D Laplacian 64^3, p=8)",
+        "value": round(ms / 1000.0, 6), "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3D 7-point Laplacian 64^3 (n=262144, nnz=1810432), "
+                               "||tA||_2=1e4, B n x 8 Gaussian seed 2, m=15, k=40, tol=1e-10",
+                   "n": W.n, "p": W.p, "m": W.m, "k": W.k, "tol": W.tol},
+        "rel_err_vs_rational_closed_form": rel_err,
+        "cycles": info.cycles, "block_apps": info.block_apps,
+        "inner_iters": int(info.inner_iters), "err_bound": info.err_bound,
+        "phase_ms": {"apply": round(info.ms_apply, 2), "orth": round(info.ms_orth, 2),
+                     "small": round(info.ms_small, 2), "update": round(info.ms_update, 2)},
+        "plan_setup_s": round(plan_s, 3),
+        "roofline": roof,
+        "inner_kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/* expmv.h -- C ABI of the MI355X library computing Z = e^{tA} B by the
+ * preconditioned, restarted and shifted block FOM with deflation
+ * (PSBFOM-DR; Wu, Pang, Sun, arXiv:1405.0707).
+ *
+ * Problem (paper, Section 1, eq. 1.1): t is a real scalar, tA is an n x n
+ * large sparse negative definite matrix with ||tA|| >> 1, B is n x p with
+ * 1 <= p << n.  e^{tA} is replaced by the degree-14 Caratheodory-Fejer
+ * rational form omega_0 B + sum_i omega_i (tA - tau_i I)^{-1} B (Section 2,
+ * eq. 2.5); its 7 conjugate-pair shifted systems are solved on one shared
+ * real block Krylov basis of (tA)^{-1} (Section 4.1, eq. 4.4-4.9), restarted
+ * with deflation (Algorithm 2).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (memory from hipMalloc or a torch
+ *    CUDA tensor) unless the comment says "host".
+ *  - Blocks (B, Z, G, X, Y) are n x p, row-major, contiguous: element (i, j)
+ *    is at [i * p + j].  Values are FP64 at the boundary in every precision
+ *    mode.
+ *  - CSR matrices use int32 row pointers (n + 1 entries, rowptr[0] = 0) and
+ *    int32 column indices (nnz entries), FP64 values; column indices in a row
+ *    need not be sorted.
+ *  - The caller owns every array it passes and keeps it alive for the call.
+ *    A plan copies what it needs from A at creation (the caller may free A
+ *    afterwards) and owns its own device workspace, released by
+ *    expmv_plan_destroy.
+ *  - All device work is ordered on the stream given at plan creation
+ *    (NULL = the default stream).  Entry points that return host values
+ *    synchronise that stream before returning.
+ *  - No C++ exception crosses the ABI; a plan must not be used by two host
+ *    threads at once.
+ */
+#ifndef EXPMV_H
+#define EXPMV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EXPMV_OK = 0,
+  EXPMV_EINVAL = 1,      /* bad argument: n < 1, p < 1 or p > n, p > 32, t = 0 or not
+                            finite, tol not in (0, 1), m or k out of range, NULL pointer */
+  EXPMV_ENOTNEG = 2,     /* some diagonal entry of tA is >= 0: tA is not negative definite */
+  EXPMV_ENOMEM = 3,      /* device or host allocation failed */
+  EXPMV_ENOCONV = 4,     /* max_cycles reached; Z holds the last iterate, info is filled */
+  EXPMV_EBREAKDOWN = 5,  /* a block of the Krylov basis became rank deficient without the
+                            space becoming invariant; Z holds the last iterate */
+  EXPMV_EHIP = 6,        /* a HIP runtime call failed */
+  EXPMV_EINNER = 7       /* an inner solve for (tA)^{-1} V hit inner_maxit; Z holds the
+                            iterate of the cycle where it happened */
+} expmv_status;
+
+typedef enum { EXPMV_FP64 = 0, EXPMV_MIXED = 1 } expmv_precision;
+
+typedef enum {
+  EXPMV_STOP_PAPER = 0,  /* max_j rho_j <= tol * ||B||_F, rho_j the residual norm of
+                            eq. 4.9 (Algorithm 2, Step 4) */
+  EXPMV_STOP_BOUND = 1   /* sum_j |c_j| rho_j / delta_j <= tol * ||Z~||_F, delta_j the
+                            distance of tau_j to (-inf, 0]: a bound on the error
+                            against the rational form when tA is normal */
+} expmv_stop_rule;
+
+typedef struct {
+  int m;               /* block Arnoldi steps per cycle (>= 2)                          */
+  int k;               /* Ritz vectors kept at a restart (multiple of p, k < m*p;
+                          0 = p * floor(m / 3))                                          */
+  int max_cycles;      /* restart cycles before EXPMV_ENOCONV                           */
+  int precision;       /* expmv_precision                                                */
+  int stop_rule;       /* expmv_stop_rule                                                */
+  double inner_tol;    /* relative residual of each inner solve (0 = 1e-12 in FP64,
+                          1e-6 in the FP32 inner solver of the mixed form)               */
+  int inner_maxit;     /* iteration cap of each inner solve                             */
+  int symmetric;       /* 1: A symmetric (CG inner solver, symmetric Ritz step),
+                          0: general (BiCGStab, general Ritz step), -1: detect          */
+  int preconditioned;  /* 1: Algorithm 2 (Krylov space of (tA)^{-1}), 0: Algorithm 1
+                          (Krylov space of tA, no inner solve)                            */
+  int profile;         /* 0: off; N > 0: time every N-th inner-solver iteration's
+                          kernels with HIP events (results in expmv_info.kern_*)          */
+} expmv_opts;
+
+typedef struct {                  /* host struct, filled by expmv_execute */
+  int cycles;                     /* restart cycles run                               */
+  int block_apps;                 /* operator applications to an n x p block          */
+  long long inner_iters;          /* inner solver iterations, summed over blocks      */
+  int inner_maxit_hit;            /* inner solves that stopped at inner_maxit         */
+  double est[7];                  /* rho_j of the last cycle (eq. 4.9)                */
+  double true_res[7];             /* ||B - (tA - tau_j I) X_j||_F after the last cycle */
+  double err_bound;               /* sum_j |c_j| rho_j / delta_j / ||Z~||_F           */
+  double bnorm, znorm;            /* ||B||_F, ||Z~||_F                                 */
+  double ms_total, ms_apply, ms_orth, ms_small, ms_update;  /* host wall times      */
+  int breakdown;                  /* 1 when the Krylov space became invariant          */
+  int kern_samples;               /* sampled inner iterations (opts.profile > 0)       */
+  double kern_ms_a, kern_ms_b,    /* mean device time of the inner CG's kernels, ms:  */
+         kern_ms_c;               /* A = CSR SpMM q = K p, B = residual update,
+                                     C = search-direction and iterate update          */
+} expmv_info;
+
+typedef struct expmv_plan_s* expmv_plan;
+
+/* Fill *o with the defaults: m = 10, k = 0 (auto), max_cycles = 50, FP64,
+ * EXPMV_STOP_BOUND, inner_tol = 0 (auto), inner_maxit = 50000, symmetric = -1,
+ * preconditioned = 1, profile = 0.  o is a host pointer. */
+expmv_status expmv_default_opts(expmv_opts* o);
+
+/* Plan for Z = e^{tA} B with A in CSR (device arrays, see conventions).
+ * The plan stores K = -tA (FP64, plus an FP32 copy in the mixed form), the
+ * Jacobi scaling 1/diag(K), the transpose of K when A is not symmetric, and
+ * the CF table.  opts may be NULL (defaults).  *out receives the plan.
+ * Errors: EINVAL, ENOTNEG (a diagonal entry of tA >= 0, or missing), ENOMEM,
+ * EHIP. */
+expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
+                            const int32_t* colind, const double* val, double t,
+                            const expmv_opts* opts, hipStream_t stream, expmv_plan* out);
+
+/* Plan for A = -T with T symmetric positive definite Toeplitz given by its
+ * first column col0 (device, n values), so tA = -t T with t > 0 (Section 5,
+ * Example 5.4 setting).  Products with T use a length-2n circulant embedding
+ * and FFTs; (tA)^{-1} uses the Gohberg-Semencul formula (Section 4.1) with
+ * x = T^{-1} e_1 solved once at plan creation.  Errors as expmv_plan_csr. */
+expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t,
+                                 const expmv_opts* opts, hipStream_t stream, expmv_plan* out);
+
+/* Z = e^{tA} B (transpose = 0) or Z = e^{tA^T} B (transpose = 1), p = block
+ * width (1 <= p <= 32, p <= n), tol = stopping tolerance of opts.stop_rule.
+ * B and Z are device n x p blocks and may not overlap.  info (host) may be
+ * NULL.  Returns OK, EINVAL, ENOCONV, EBREAKDOWN, EINNER, ENOMEM or EHIP;
+ * after ENOCONV, EBREAKDOWN and EINNER Z holds the last iterate. */
+expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int64_t p,
+                           double tol, double* Z, expmv_info* info);
+
+/* *out (host) = <G, A Z> = sum_ij G_ij (A Z)_ij: the derivative of
+ * <G, e^{tA}B> with respect to t when Z = e^{tA}B (d/dt e^{tA}B = A e^{tA}B).
+ * G, Z device n x p. */
+expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Z, int64_t p,
+                          double* out);
+
+/* Y = tA X (transpose = 0) or (tA)^T X (transpose = 1), X, Y device n x p. */
+expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* X,
+                                  int64_t p, double* Y);
+
+/* Y ~= (tA)^{-1} X by the plan's preconditioner application (inner solve to
+ * relative residual inner_tol, or Gohberg-Semencul for Toeplitz plans);
+ * *iters (host, may be NULL) receives the largest inner iteration count. */
+expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X,
+                                 int64_t p, double* Y, long long* iters);
+
+/* Copy the library's CF table to host arrays of 7 entries (poles with
+ * Im tau > 0, c_j = 2 omega_j) and *omega0.  Any pointer may be NULL. */
+expmv_status expmv_cf_table(double* tau_re, double* tau_im, double* c_re, double* c_im,
+                            double* omega0);
+
+/* Host eigensolvers of the restart step (Algorithm 2, Step 5), exported so
+ * they can be checked without a GPU.  A is a host n x n row-major matrix.
+ * sym: eigenvalues w (n) and orthonormal eigenvectors in the columns of Q
+ * (n x n row-major) of (A + A^T)/2.  general: eigenvalues wr + i wi and unit
+ * eigenvectors Vr + i Vi (columns), complex ones in exact conjugate pairs.
+ * Return EINVAL on bad arguments, ENOCONV if the QR iteration fails. */
+expmv_status expmv_host_eig_sym(int n, const double* A, double* w, double* Q);
+expmv_status expmv_host_eig_general(int n, const double* A, double* wr, double* wi, double* Vr,
+                                    double* Vi);
+
+void expmv_plan_destroy(expmv_plan plan);
+
+const char* expmv_status_string(expmv_status s);
+
+/* One-shot forms of the problem statement: plan, execute, destroy, with the
+ * default options and a given tol. */
+expmv_status expmv_block_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
+                             const int32_t* colind, const double* val, const double* B,
+                             int64_t p, double t, double tol, double* Z, hipStream_t stream);
+expmv_status expmv_block_toeplitz(int64_t n, const double* col0, const double* B, int64_t p,
+                                  double t, double tol, double* Z, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXPMV_H */

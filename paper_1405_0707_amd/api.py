@@ -1,0 +1,183 @@
+"""Torch-facing API over the C ABI (argument marshalling only; every step of
+the computation runs in libexpmv.so).
+
+    plan = Plan.csr(rowptr, colind, val, t, m=15)       # device tensors
+    Z, info = plan.execute(B, tol=1e-10)                 # Z = e^{tA} B
+    Z = expmv(A, B, t)                                   # autograd-aware
+
+`expmv` is a torch.autograd.Function: grad_B = e^{tA^T} G (the same solver on
+A^T) and grad_t = <G, A Z>; the forward Krylov basis is not stored, the
+backward solve rebuilds its own.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import torch
+
+from . import _lib
+from ._lib import Info, Opts, check, lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().expmv_default_opts(C.byref(o))
+    for key, v in kw.items():
+        if key == "precision" and isinstance(v, str):
+            v = {"fp64": _lib.FP64, "mixed": _lib.MIXED}[v]
+        if key == "stop_rule" and isinstance(v, str):
+            v = {"paper": _lib.STOP_PAPER, "bound": _lib.STOP_BOUND}[v]
+        if not hasattr(o, key):
+            raise TypeError(f"unknown option {key}")
+        setattr(o, key, v)
+    return o
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_f64(x, device) -> torch.Tensor:
+    x = torch.as_tensor(x)
+    return x.to(device=device, dtype=torch.float64).contiguous()
+
+
+@dataclasses.dataclass
+class Toeplitz:
+    """Symmetric positive definite Toeplitz T given by its first column;
+    the exponent is t * (-T)."""
+    col0: torch.Tensor
+
+
+class Plan:
+    """Owns an expmv_plan (K = -tA and its workspace on one device)."""
+
+    def __init__(self, handle, n: int, device, t: float, keepalive=()):
+        self._h = handle
+        self.n = n
+        self.device = device
+        self.t = t
+        self._keep = keepalive
+
+    @classmethod
+    def csr(cls, rowptr, colind, val, t: float, device="cuda", **opts):
+        rowptr = torch.as_tensor(rowptr).to(device=device, dtype=torch.int32).contiguous()
+        colind = torch.as_tensor(colind).to(device=device, dtype=torch.int32).contiguous()
+        val = _dev_f64(val, device)
+        n = rowptr.numel() - 1
+        o = default_opts(**opts)
+        h = C.c_void_p()
+        st = lib().expmv_plan_csr(n, val.numel(), rowptr.data_ptr(), colind.data_ptr(),
+                                  val.data_ptr(), float(t), C.byref(o), _stream_ptr(rowptr.device),
+                                  C.byref(h))
+        check(st, "expmv_plan_csr")
+        return cls(h, n, rowptr.device, float(t))
+
+    @classmethod
+    def toeplitz(cls, col0, t: float, device="cuda", **opts):
+        col0 = _dev_f64(col0, device)
+        o = default_opts(**opts)
+        h = C.c_void_p()
+        st = lib().expmv_plan_toeplitz(col0.numel(), col0.data_ptr(), float(t), C.byref(o),
+                                       _stream_ptr(col0.device), C.byref(h))
+        check(st, "expmv_plan_toeplitz")
+        return cls(h, col0.numel(), col0.device, float(t))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().expmv_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def execute(self, B: torch.Tensor, tol: float = 1e-10, transpose: bool = False,
+                out: torch.Tensor | None = None, allow=()):
+        B = _dev_f64(B, self.device)
+        if B.dim() == 1:
+            B = B[:, None]
+        Z = torch.empty_like(B) if out is None else out
+        info = Info()
+        st = lib().expmv_execute(self._h, int(transpose), B.data_ptr(), B.shape[1], float(tol),
+                                 Z.data_ptr(), C.byref(info))
+        check(st, "expmv_execute", allow)
+        return Z, info
+
+    def grad_t(self, G: torch.Tensor, Z: torch.Tensor) -> float:
+        G = _dev_f64(G, self.device)
+        Z = _dev_f64(Z, self.device)
+        out = C.c_double()
+        check(lib().expmv_grad_t(self._h, G.data_ptr(), Z.data_ptr(), G.shape[1], C.byref(out)),
+              "expmv_grad_t")
+        return out.value
+
+    def apply_operator(self, X: torch.Tensor, transpose: bool = False) -> torch.Tensor:
+        X = _dev_f64(X, self.device)
+        Y = torch.empty_like(X)
+        check(lib().expmv_apply_operator(self._h, int(transpose), X.data_ptr(), X.shape[1],
+                                         Y.data_ptr()), "expmv_apply_operator")
+        return Y
+
+    def apply_inverse(self, X: torch.Tensor, transpose: bool = False):
+        X = _dev_f64(X, self.device)
+        Y = torch.empty_like(X)
+        it = C.c_longlong()
+        check(lib().expmv_apply_inverse(self._h, int(transpose), X.data_ptr(), X.shape[1],
+                                        Y.data_ptr(), C.byref(it)), "expmv_apply_inverse")
+        return Y, it.value
+
+
+def cf_table():
+    """The library's CF table: (tau[7], c[7], omega0) as Python complex/float."""
+    a = [(C.c_double * 7)() for _ in range(4)]
+    w0 = C.c_double()
+    lib().expmv_cf_table(a[0], a[1], a[2], a[3], C.byref(w0))
+    tau = [complex(a[0][i], a[1][i]) for i in range(7)]
+    c = [complex(a[2][i], a[3][i]) for i in range(7)]
+    return tau, c, w0.value
+
+
+def _make_plan(A, t, device, opts):
+    if isinstance(A, Toeplitz):
+        return Plan.toeplitz(A.col0, t, device=device, **opts)
+    if isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr:
+        return Plan.csr(A.crow_indices(), A.col_indices(), A.values(), t, device=device, **opts)
+    rowptr, colind, val = A
+    return Plan.csr(rowptr, colind, val, t, device=device, **opts)
+
+
+class _ExpmvFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, B, t, plan, tol, t_float):
+        Z, info = plan.execute(B.detach(), tol=tol)
+        ctx.plan = plan
+        ctx.tol = tol
+        ctx.t = t_float
+        ctx.save_for_backward(Z)
+        ctx.info = info
+        return Z
+
+    @staticmethod
+    def backward(ctx, G):
+        (Z,) = ctx.saved_tensors
+        plan = ctx.plan
+        gB = gt = None
+        if ctx.needs_input_grad[0]:
+            gB, _ = plan.execute(G.contiguous(), tol=ctx.tol, transpose=True)
+        if ctx.needs_input_grad[1]:
+            gt = torch.tensor(plan.grad_t(G.contiguous(), Z), dtype=torch.float64,
+                              device=Z.device)
+        return gB, gt, None, None, None
+
+
+def expmv(A, B: torch.Tensor, t, tol: float = 1e-10, plan: Plan | None = None, **opts):
+    """Z = e^{tA} B with gradients for B and t (not A).  A is a CSR tuple
+    (rowptr, colind, val), a torch sparse CSR tensor or a Toeplitz; t is a
+    float or a 0-dim tensor."""
+    t_t = t if isinstance(t, torch.Tensor) else torch.tensor(float(t), dtype=torch.float64)
+    t_float = float(t_t.detach())
+    if plan is None:
+        plan = _make_plan(A, t_float, B.device, opts)
+    return _ExpmvFn.apply(B, t_t, plan, tol, t_float)

@@ -1,0 +1,15 @@
+// Host eigensolvers for the small projected matrix of the restart step.
+#pragma once
+
+namespace expmv {
+
+// A (n x n, row-major) symmetric part -> eigenvalues w (n) and orthonormal
+// eigenvectors in the columns of Q (n x n row-major): A = Q diag(w) Q^T.
+void sym_eig(int n, const double* A, double* w, double* Q);
+
+// General real A (n x n row-major) -> eigenvalues wr + i wi and eigenvectors
+// (column i of Vr + i Vi, unit 2-norm).  Complex eigenvalues come as exact
+// conjugate pairs.  Returns false if the QR iteration did not converge.
+bool general_eig(int n, const double* A, double* wr, double* wi, double* Vr, double* Vi);
+
+}  // namespace expmv

@@ -1,0 +1,1017 @@
+// expmv: Z = e^{tA} B by the preconditioned, restarted and shifted block FOM
+// with deflation (PSBFOM-DR, Wu-Pang-Sun, Algorithm 2), on one MI355X.
+//
+// Host driver: plan creation, the restart-cycle loop and the C ABI.  Every
+// n-sized operation runs in the kernels of kernels.hpp / kernels_dense.hpp /
+// toeplitz.hpp; the host only moves the small projected matrices (H, the
+// pole residuals, the restart rotation) and decides convergence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "eig_host.hpp"
+#include "expmv.h"
+#include "kernels.hpp"
+#include "kernels_dense.hpp"
+
+#include "cf_nu14.inc"
+
+namespace expmv {
+
+struct HipError {
+  hipError_t err;
+  int line;
+};
+struct StatusError {
+  expmv_status st;
+};
+
+#define HIPCHK(call)                                             \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) throw ::expmv::HipError{e_, __LINE__}; \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    release();
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw StatusError{EXPMV_ENOMEM};
+    }
+    n = count;
+  }
+};
+
+static int pow2_lanes(int p) {
+  int pp = 1;
+  while (pp < p) pp <<= 1;
+  return pp;
+}
+
+// Work arrays that depend on the block width p, kept between calls.
+struct Workspace {
+  int p = 0;
+  DevBuf<double> V[2];          // basis panels, (m+1) * n * p each
+  DevBuf<double> W, Wt;         // n x p
+  DevBuf<double> X;             // n x 14p
+  DevBuf<double> cg_x, cg_r, cg_pa, cg_pb, cg_q;  // inner solver, n x p
+  DevBuf<double> cg_v, cg_s, cg_t, cg_rt;         // BiCGStab extras
+  DevBuf<double> partial;       // reductions
+  DevBuf<double> hcoef, gram, R1, R2, Rinv, w0;   // small orth buffers
+  DevBuf<double> H;             // ldh x ldh
+  DevBuf<double> Rhat;          // p x p
+  DevBuf<cplx> G, Zs, Ascr, S;
+  DevBuf<double> Cr, Crot, rho, nrm;
+  DevBuf<int> flags, singular;
+  DevBuf<CgState> cgst;
+  DevBuf<double> part_rr, part_sig;   // inner-solver partials, [wg][2][PP] and [wg][PP]
+  DevBuf<KrylovCtl> ctl;
+};
+
+}  // namespace expmv
+
+using namespace expmv;
+
+struct expmv_plan_s {
+  int kind = 0;                 // 0 CSR, 1 Toeplitz
+  int64_t n = 0, nnz = 0;
+  double t = 0.0;
+  expmv_opts opts{};
+  hipStream_t stream = nullptr;
+  bool symmetric = true;
+  // K = -tA in CSR (FP64) and its transpose (nonsymmetric only)
+  DevBuf<int32_t> rowptr, colind, rowptrT, colindT;
+  DevBuf<double> val, valT, dinv, dinvT;
+  // CF table on the device
+  DevBuf<double> tau_re, tau_im, c_re, c_im;
+  Workspace ws;
+  int* host_flags = nullptr;    // pinned, 2 slots x 4 ints
+  hipEvent_t ev[2]{};
+  int ldh = 0;
+  // profiling (opts.profile > 0): event pairs around sampled inner iterations
+  std::vector<hipEvent_t> pev;
+  std::vector<int> pev_iter;      // inner iteration index of each sample
+  int pev_used = 0;
+  double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0;
+  int prof_samples = 0;
+};
+
+namespace expmv {
+namespace {
+
+constexpr int kCgGrid = 512;   // workgroups of the inner-solver kernels
+
+int grid_for(int64_t rows, int PP, int cap = 1024) {
+  const int64_t wgs = (rows * PP + kThreads - 1) / kThreads;
+  return int(std::max<int64_t>(1, std::min<int64_t>(cap, wgs)));
+}
+
+#define DISPATCH_PP(PP, ...)                         \
+  switch (PP) {                                      \
+    case 1: { constexpr int P_ = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int P_ = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int P_ = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int P_ = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int P_ = 16; __VA_ARGS__; } break; \
+    default: { constexpr int P_ = 32; __VA_ARGS__; } break; \
+  }
+
+void ensure_workspace(expmv_plan_s* pl, int p) {
+  Workspace& w = pl->ws;
+  const int64_t n = pl->n;
+  const int m = pl->opts.m;
+  const int npan_max = m + 1;
+  const int ldh = (m + 1) * p;
+  pl->ldh = ldh;
+  const size_t blk = size_t(n) * p;
+  if (w.p == p) return;
+  w.V[0].alloc(blk * npan_max);
+  w.V[1].alloc(blk * npan_max);
+  w.W.alloc(blk);
+  w.Wt.alloc(blk);
+  w.X.alloc(blk * 2 * kNShift);
+  w.cg_x.alloc(blk);
+  w.cg_r.alloc(blk);
+  w.cg_pa.alloc(blk);
+  w.cg_pb.alloc(blk);
+  w.cg_q.alloc(blk);
+  if (!pl->symmetric) {
+    w.cg_v.alloc(blk);
+    w.cg_s.alloc(blk);
+    w.cg_t.alloc(blk);
+    w.cg_rt.alloc(blk);
+  }
+  const size_t O = size_t(npan_max) * p * p + p;
+  w.partial.alloc(std::max<size_t>(O * 256, size_t(1024) * 4 * 32));
+  w.hcoef.alloc(O);
+  w.gram.alloc(size_t(p) * p);
+  w.R1.alloc(size_t(p) * p);
+  w.R2.alloc(size_t(p) * p);
+  w.Rinv.alloc(size_t(p) * p);
+  w.w0.alloc(O);
+  w.H.alloc(size_t(ldh) * ldh);
+  w.Rhat.alloc(size_t(p) * p);
+  const int dmax = m * p;
+  w.G.alloc(size_t(kNShift) * dmax * p);
+  w.Zs.alloc(size_t(kNShift) * dmax * p);
+  w.Ascr.alloc(size_t(kNShift) * dmax * dmax);
+  w.S.alloc(size_t(kNShift) * p * p);
+  w.Cr.alloc(size_t(ldh) * 2 * kNShift * p);
+  w.Crot.alloc(size_t(dmax) * dmax);
+  w.rho.alloc(kNShift);
+  w.nrm.alloc(64);
+  w.flags.alloc(4);
+  w.singular.alloc(kNShift);
+  w.cgst.alloc(1);
+  w.part_rr.alloc(size_t(kCgGrid) * 2 * kMaxP);
+  w.part_sig.alloc(size_t(kCgGrid) * kMaxP);
+  w.ctl.alloc(1);
+  HIPCHK(hipMemsetAsync(w.ctl.p, 0, sizeof(KrylovCtl), pl->stream));
+  w.p = p;
+}
+
+// -------------------------------------------------------------------------
+// operator and inner solves
+
+// Y = K X (K = -tA, or its transpose) for n x p blocks.
+void apply_K(expmv_plan_s* pl, int transpose, const double* X, double* Y, int p) {
+  hipStream_t s = pl->stream;
+  const bool tr = transpose && !pl->symmetric;
+  const int32_t* rp = tr ? pl->rowptrT.p : pl->rowptr.p;
+  const int32_t* ci = tr ? pl->colindT.p : pl->colind.p;
+  const double* v = tr ? pl->valT.p : pl->val.p;
+  const int PP = pow2_lanes(p);
+  const int grid = grid_for(pl->n, PP, 4096);
+  DISPATCH_PP(PP, hipLaunchKernelGGL((k_spmm<double, P_>), dim3(grid), dim3(kThreads), 0, s,
+                                     int(pl->n), p, rp, ci, v, X, Y));
+}
+
+// Read the sampled event pairs of the inner solver.  Only iterations the
+// solve actually ran count (kexec = iterations executed); the ones issued
+// after convergence return at once and are dropped.
+void collect_profile(expmv_plan_s* pl, int kexec) {
+  if (pl->pev_used == 0) return;
+  for (int i = 0; i + 4 <= pl->pev_used; i += 4) {
+    float tc = 0.f, ta = 0.f, tb = 0.f;
+    HIPCHK(hipEventSynchronize(pl->pev[i + 3]));
+    HIPCHK(hipEventElapsedTime(&tc, pl->pev[i], pl->pev[i + 1]));
+    HIPCHK(hipEventElapsedTime(&ta, pl->pev[i + 1], pl->pev[i + 2]));
+    HIPCHK(hipEventElapsedTime(&tb, pl->pev[i + 2], pl->pev[i + 3]));
+    if (pl->pev_iter[i / 4] < kexec) {
+      pl->prof_ms_a += ta;
+      pl->prof_ms_b += tb;
+      pl->prof_ms_c += tc;
+      pl->prof_samples += 1;
+    }
+  }
+  pl->pev_used = 0;
+}
+
+struct InnerResult {
+  int iters;
+  int hit_cap;
+};
+
+// out = K^{-1} (sign * src) by batched Jacobi-PCG (K SPD); out is the
+// iterate x itself.
+InnerResult inner_cg(expmv_plan_s* pl, const double* src, double sign, double* out, int p) {
+  Workspace& w = pl->ws;
+  hipStream_t s = pl->stream;
+  const int64_t n = pl->n;
+  const int PP = pow2_lanes(p);
+  const int grid = int(std::max<int64_t>(1, std::min<int64_t>(kCgGrid, (n * PP + kCgThreads - 1) / kCgThreads)));
+  double tol = pl->opts.inner_tol > 0.0 ? pl->opts.inner_tol : 1e-12;
+  const double tol2 = tol * tol;
+  const int maxit = pl->opts.inner_maxit;
+  double* P[2] = {w.cg_pa.p, w.cg_pb.p};
+  DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_init<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                     int(n), p, sign, src, pl->dinv.p, out, w.cg_r.p, P[0],
+                                     w.ctl.p, w.part_rr.p));
+  const int chunk = 16;
+  int launched = 0;
+  int pending = -1, slot = 0;
+  bool done = false;
+  while (!done) {
+    for (int it = 0; it < chunk; ++it) {
+      const int k = launched + it;  // 0-based iteration index
+      double* pold = P[k & 1];
+      double* pnew = P[(k + 1) & 1];
+      const bool sample = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0 &&
+                          pl->pev_used + 4 <= int(pl->pev.size());
+      hipEvent_t* e = sample ? &pl->pev[pl->pev_used] : nullptr;
+      if (sample) {
+        pl->pev_iter[pl->pev_used / 4] = k;
+        pl->pev_used += 4;
+        HIPCHK(hipEventRecord(e[0], s));
+      }
+      DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_c<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                         k, int(n), p, pl->dinv.p, w.cg_r.p, pold, pnew, out,
+                                         w.cgst.p, w.ctl.p, w.part_rr.p, tol2, maxit));
+      if (sample) HIPCHK(hipEventRecord(e[1], s));
+      DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_a<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                         int(n), p, pl->rowptr.p, pl->colind.p, pl->val.p, pnew,
+                                         w.cg_q.p, w.ctl.p, w.part_sig.p));
+      if (sample) HIPCHK(hipEventRecord(e[2], s));
+      DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_b<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                         k, int(n), p, pl->dinv.p, w.cg_r.p, w.cg_q.p, w.cgst.p,
+                                         w.ctl.p, w.part_sig.p, w.part_rr.p));
+      if (sample) HIPCHK(hipEventRecord(e[3], s));
+    }
+    launched += chunk;
+    HIPCHK(hipMemcpyAsync(pl->host_flags + 4 * slot, w.ctl.p, sizeof(KrylovCtl),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(pl->ev[slot], s));
+    if (pending >= 0) {
+      HIPCHK(hipEventSynchronize(pl->ev[pending]));
+      const KrylovCtl* c = reinterpret_cast<const KrylovCtl*>(pl->host_flags + 4 * pending);
+      if (c->done) done = true;
+    }
+    pending = slot;
+    slot ^= 1;
+    if (launched > maxit + 4 * chunk) break;  // the cap stops every column before this
+  }
+  HIPCHK(hipEventSynchronize(pl->ev[pending]));
+  const KrylovCtl* c = reinterpret_cast<const KrylovCtl*>(pl->host_flags + 4 * pending);
+  const int kexec = c->iters_max;
+  collect_profile(pl, kexec);
+  return {kexec, c->hit_cap};
+}
+
+// W ~= M^{-1} V = -(K^{-1} V), M = tA.
+InnerResult apply_inverse(expmv_plan_s* pl, int transpose, const double* V, double* Wout, int p) {
+  (void)transpose;
+  if (!pl->symmetric) throw StatusError{EXPMV_EINVAL};
+  return inner_cg(pl, V, -1.0, Wout, p);
+}
+
+// -------------------------------------------------------------------------
+// block Gram-Schmidt (two passes) + CholQR2 of W against npan panels of Vb;
+// writes the new orthonormal block to Vout, H(0:npan*p, col0:col0+p) +=
+// the projection coefficients and H(npan*p.., col0..) = R (if H given).
+// With npan == 0 it is the plain CholQR2 of W (the initial block: R -> Rhat).
+
+
+struct OrthLaunch {
+  int TR;
+  int64_t rows_per_wg;
+  int nwg;
+  size_t lds;
+};
+
+OrthLaunch orth_config(int64_t n, int p, int npan, int O, size_t elem) {
+  OrthLaunch L;
+  int TR = 32;
+  auto lds_for = [&](int tr) {
+    return size_t(O) * 8 + size_t(tr) * (size_t(npan) * p + 2 * p) * elem;
+  };
+  while (TR > 1 && lds_for(TR) > 150 * 1024) TR /= 2;
+  L.TR = TR;
+  const int64_t tiles = (n + TR - 1) / TR;
+  const int64_t nwg = std::min<int64_t>(256, tiles);
+  const int64_t tiles_per = (tiles + nwg - 1) / nwg;
+  L.rows_per_wg = tiles_per * TR;
+  L.nwg = int((n + L.rows_per_wg - 1) / L.rows_per_wg);
+  L.lds = lds_for(TR);
+  return L;
+}
+
+// One streaming pass; returns the number of workgroups whose partials are
+// in ws.partial (0 when the mode writes no partials).
+int orth_pass(expmv_plan_s* pl, int mode, int p, const double* V, int npan, const double* Win,
+              double* Wout, const double* C) {
+  const bool proj = (mode == kProj || mode == kUpdProj);
+  const bool gram = (mode == kUpdGram || mode == kScaleGram);
+  const bool use_v = (mode == kProj || mode == kUpdProj || mode == kUpdGram);
+  const int npv = use_v ? npan : 0;
+  const int O = proj ? npv * p * p + (mode == kProj ? p : 0) : (gram ? p * p : 0);
+  OrthLaunch L = orth_config(pl->n, p, npv, O, sizeof(double));
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth<double>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)));
+  hipLaunchKernelGGL(k_orth<double>, dim3(L.nwg), dim3(kThreads), L.lds, pl->stream, mode, pl->n,
+                     p, V, npv, Win, Wout, C, pl->ws.partial.p, L.TR, L.rows_per_wg);
+  return (proj || gram) ? L.nwg : 0;
+}
+
+void reduce_partials(expmv_plan_s* pl, int nwg, int O, double* out, double* H, int ldh, int col0,
+                     int p, int O_h) {
+  const int grid = (O + (kThreads / 8) - 1) / (kThreads / 8);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(grid), dim3(kThreads), 0, pl->stream,
+                     pl->ws.partial.p, nwg, O, out, H, ldh, col0, p, O_h);
+}
+
+// Orthonormalise W (n x p) against panels 0..npan-1 of Vb (two block
+// Gram-Schmidt passes), then CholQR2; the result goes to Vout.
+//   H != nullptr: H(0:npan*p, col0:col0+p) += coefficients of both passes,
+//                 H(npan*p:npan*p+p, col0:col0+p) = R2 R1.
+//   H == nullptr: Rhat (p x p) = R2 R1 (initial block, npan = 0).
+void orthonormalize(expmv_plan_s* pl, int p, const double* Vb, int npan, double* W, double* Vout,
+                    double* H, int ldh, int col0, double* Rhat) {
+  Workspace& w = pl->ws;
+  hipStream_t s = pl->stream;
+  const int Oc = npan * p * p;
+  double* Wt = w.Wt.p;
+  const double* cur = W;
+  if (npan > 0) {
+    int nwg = orth_pass(pl, kProj, p, Vb, npan, W, nullptr, nullptr);
+    reduce_partials(pl, nwg, Oc + p, w.hcoef.p, H, ldh, col0, p, Oc);
+    // w0 (||W(:,b)||^2) sits right after the coefficients in hcoef
+    nwg = orth_pass(pl, kUpdProj, p, Vb, npan, W, Wt, w.hcoef.p);
+    // the update above consumed hcoef; its partials hold V^T W1
+    reduce_partials(pl, nwg, Oc, w.w0.p + p, H, ldh, col0, p, Oc);
+    HIPCHK(hipMemcpyAsync(w.w0.p, w.hcoef.p + Oc, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    nwg = orth_pass(pl, kUpdGram, p, Vb, npan, Wt, Wt, w.w0.p + p);
+    reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
+    cur = Wt;
+  } else {
+    int nwg = orth_pass(pl, kUpdGram, p, nullptr, 0, W, Wt, nullptr);
+    reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
+    cur = Wt;
+  }
+  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R1.p, w.Rinv.p,
+                     npan > 0 ? w.w0.p : nullptr, npan > 0 ? 1 : 0, nullptr, nullptr, 0, 0, 0,
+                     w.flags.p);
+  int nwg = orth_pass(pl, kScaleGram, p, nullptr, 0, cur, Wt, w.Rinv.p);
+  reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
+  if (H != nullptr) {
+    hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
+                       nullptr, 2, w.R1.p, H, ldh, npan * p, col0, w.flags.p);
+  } else {
+    hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
+                       nullptr, 2, w.R1.p, Rhat, p, 0, 0, w.flags.p);
+  }
+  orth_pass(pl, kScale, p, nullptr, 0, Wt, Vout, w.Rinv.p);
+}
+
+void panel_gemm(expmv_plan_s* pl, int p, const double* V, int npan, const double* C, int ldc,
+                int nchunks, double* out, int64_t chunk_stride, int64_t ldo, int accumulate) {
+  const int np_cols = npan * p;
+  int TR = 32;
+  auto lds_for = [&](int tr) { return size_t(np_cols) * p * 8 + size_t(tr) * np_cols * 8; };
+  while (TR > 1 && lds_for(TR) > 150 * 1024) TR /= 2;
+  const int64_t n = pl->n;
+  const int64_t tiles = (n + TR - 1) / TR;
+  const int64_t nwg = std::min<int64_t>(512, tiles);
+  const int64_t rows_per_wg = ((tiles + nwg - 1) / nwg) * TR;
+  const int grid = int((n + rows_per_wg - 1) / rows_per_wg);
+  const size_t lds = lds_for(TR);
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel_gemm<double, double>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  hipLaunchKernelGGL((k_panel_gemm<double, double>), dim3(grid, nchunks), dim3(kThreads), lds,
+                     pl->stream, n, p, V, npan, C, ldc, out, chunk_stride, ldo, accumulate, TR,
+                     rows_per_wg);
+}
+
+double host_now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// -------------------------------------------------------------------------
+// the method
+
+struct CycleState {
+  int d;      // projected dimension
+  int keff;   // Ritz vectors at the front of the basis
+};
+
+expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
+                          double* Z, expmv_info* info) {
+  hipStream_t s = pl->stream;
+  ensure_workspace(pl, p);
+  Workspace& w = pl->ws;
+  const int64_t n = pl->n;
+  const int m = pl->opts.m;
+  const int ldh = pl->ldh;
+  const int kk_opt = pl->opts.k > 0 ? pl->opts.k : p * (m / 3);
+  const int k = std::max(p, std::min(kk_opt, (m - 1) * p) / p * p);
+  const bool precond = pl->opts.preconditioned != 0;
+  const size_t blk = size_t(n) * p;
+  const int ldx = 2 * kNShift * p;
+  const double t_start = host_now_ms();
+  expmv_info inf{};
+  double ms_apply = 0, ms_orth = 0, ms_small = 0, ms_update = 0;
+
+  // CF table on the host
+  double tau_re[kNShift], tau_im[kNShift], c_re[kNShift], c_im[kNShift];
+  for (int j = 0; j < kNShift; ++j) {
+    tau_re[j] = CF_TAU_RE[j];
+    tau_im[j] = CF_TAU_IM[j];
+    c_re[j] = CF_C_RE[j];
+    c_im[j] = CF_C_IM[j];
+  }
+  double delta[kNShift];
+  for (int j = 0; j < kNShift; ++j)
+    delta[j] = tau_re[j] >= 0.0 ? std::hypot(tau_re[j], tau_im[j]) : std::fabs(tau_im[j]);
+
+  pl->prof_ms_a = pl->prof_ms_b = pl->prof_ms_c = 0.0;
+  pl->prof_samples = 0;
+  pl->pev_used = 0;
+  HIPCHK(hipMemsetAsync(w.X.p, 0, sizeof(double) * blk * ldx / p, s));
+  HIPCHK(hipMemsetAsync(w.H.p, 0, sizeof(double) * size_t(ldh) * ldh, s));
+  HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int) * 4, s));
+  HIPCHK(hipMemsetAsync(w.singular.p, 0, sizeof(int) * kNShift, s));
+
+  // ||B||_F
+  {
+    const int grid = 512;
+    hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kThreads), 0, s, n, p, B, w.X.p, 1.0,
+                       pl->c_re.p, pl->c_im.p, w.W.p, w.partial.p);
+    std::vector<double> part(grid);
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * grid, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double bb = 0.0;
+    for (double v : part) bb += v;
+    inf.bnorm = std::sqrt(bb);
+  }
+  if (!(inf.bnorm > 0.0) || !std::isfinite(inf.bnorm)) {
+    if (info) *info = inf;
+    return EXPMV_EINVAL;
+  }
+
+  int cur = 0;
+  double* Vb = w.V[cur].p;
+  // Steps 1-2: V_1 R^ = B
+  HIPCHK(hipMemcpyAsync(w.W.p, B, sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
+  orthonormalize(pl, p, nullptr, 0, w.W.p, Vb, nullptr, 0, 0, w.Rhat.p);
+
+  CycleState cs{m * p, 0};
+  int first_block = 0;   // first panel to expand in this cycle
+  expmv_status status = EXPMV_OK;
+  std::vector<double> Hh(size_t(ldh) * ldh);
+  std::vector<double> rho(kNShift), part(1024);
+  bool rhs_from_S = false;
+  int cycle = 0;
+  for (;;) {
+    ++cycle;
+    // Step 3 / Step 9: block Arnoldi on the operator from panel first_block
+    for (int jb = first_block; jb < m; ++jb) {
+      double t0 = host_now_ms();
+      const double* Vj = Vb + size_t(jb) * blk;
+      if (precond) {
+        InnerResult r = apply_inverse(pl, transpose, Vj, w.W.p, p);
+        inf.inner_iters += r.iters;
+        inf.inner_maxit_hit += r.hit_cap;
+      } else {
+        apply_K(pl, transpose, Vj, w.W.p, p);
+        // M V = -K V
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(512), dim3(kThreads), 0, s,
+                           int64_t(blk), w.W.p, w.W.p, -1.0);
+      }
+      inf.block_apps += 1;
+      double t1 = host_now_ms();
+      ms_apply += t1 - t0;
+      orthonormalize(pl, p, Vb, jb + 1, w.W.p, Vb + size_t(jb + 1) * blk, w.H.p, ldh, jb * p,
+                     nullptr);
+      ms_orth += host_now_ms() - t1;
+    }
+    double t0 = host_now_ms();
+    const int d = cs.d;
+    // right-hand sides of the projected systems
+    {
+      dim3 g(std::max(1, (d * p + kThreads - 1) / kThreads), kNShift);
+      hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, d, p, rhs_from_S ? cs.keff : 0,
+                         rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
+    }
+    // Step 4: projected shifted systems, residual estimates, update coefficients
+    hipLaunchKernelGGL(k_proj_solve, dim3(kNShift), dim3(1024), 0, s, d, p, precond ? 1 : 0, w.H.p,
+                       ldh, pl->tau_re.p, pl->tau_im.p, w.G.p, w.Ascr.p, w.Zs.p, w.Cr.p, w.S.p,
+                       w.rho.p, w.singular.p);
+    double t1 = host_now_ms();
+    // X_j += V_{d+p} (H~ Z_j)  [Algorithm 1: V_d Z_j]
+    panel_gemm(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * kNShift, w.X.p, p, ldx, 1);
+    // Z~ and ||Z~||
+    const int cgrid = 512;
+    hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p,
+                       double(CF_OMEGA0), pl->c_re.p, pl->c_im.p, Z, w.partial.p);
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * kNShift, hipMemcpyDeviceToHost, s));
+    int flags_h[4];
+    HIPCHK(hipMemcpyAsync(flags_h, w.flags.p, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double t2 = host_now_ms();
+    ms_small += t1 - t0;
+    ms_update += t2 - t1;
+    double zz = 0.0;
+    for (int i = 0; i < cgrid; ++i) zz += part[i];
+    inf.znorm = std::sqrt(zz);
+    double bound = 0.0, rmax = 0.0;
+    for (int j = 0; j < kNShift; ++j) {
+      inf.est[j] = rho[j];
+      bound += std::hypot(c_re[j], c_im[j]) * rho[j] / delta[j];
+      rmax = std::max(rmax, rho[j]);
+    }
+    inf.err_bound = inf.znorm > 0.0 ? bound / inf.znorm : bound;
+    inf.cycles = cycle;
+    inf.breakdown = flags_h[0];
+    if (flags_h[1]) {
+      status = EXPMV_EBREAKDOWN;
+      break;
+    }
+    bool conv;
+    if (pl->opts.stop_rule == EXPMV_STOP_PAPER) conv = rmax <= tol * inf.bnorm;
+    else conv = bound <= tol * inf.znorm;
+    if (!(rmax > 0.0)) conv = true;   // invariant space or exact
+    if (!std::isfinite(rmax)) {
+      status = EXPMV_EBREAKDOWN;
+      break;
+    }
+    if (conv) break;
+    if (inf.inner_maxit_hit) {
+      status = EXPMV_EINNER;
+      break;
+    }
+    if (cycle >= pl->opts.max_cycles) {
+      status = EXPMV_ENOCONV;
+      break;
+    }
+    // Steps 5-8: deflated restart (host eigensolve of H_d)
+    double t3 = host_now_ms();
+    HIPCHK(hipMemcpyAsync(Hh.data(), w.H.p, sizeof(double) * size_t(ldh) * ldh,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> Hd(size_t(d) * d);
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) Hd[size_t(i) * d + j] = Hh[size_t(i) * ldh + j];
+    std::vector<double> Pk;   // d x keff, row-major
+    int keff = 0;
+    if (pl->symmetric) {
+      std::vector<double> wv(d), Q(size_t(d) * d);
+      sym_eig(d, Hd.data(), wv.data(), Q.data());
+      std::vector<int> ord(d);
+      std::iota(ord.begin(), ord.end(), 0);
+      if (precond)
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(wv[a]) > std::fabs(wv[b]); });
+      else
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(wv[a]) < std::fabs(wv[b]); });
+      keff = k;
+      Pk.assign(size_t(d) * keff, 0.0);
+      for (int c = 0; c < keff; ++c)
+        for (int i = 0; i < d; ++i) Pk[size_t(i) * keff + c] = Q[size_t(i) * d + ord[c]];
+    } else {
+      status = EXPMV_EINVAL;
+      break;
+    }
+    // H~_new = P_{k+p}^T H~ P_k  ((keff + p) x keff)
+    std::vector<double> HP(size_t(d + p) * keff, 0.0);
+    for (int i = 0; i < d + p; ++i)
+      for (int c = 0; c < keff; ++c) {
+        double sacc = 0.0;
+        for (int j = 0; j < d; ++j) sacc += Hh[size_t(i) * ldh + j] * Pk[size_t(j) * keff + c];
+        HP[size_t(i) * keff + c] = sacc;
+      }
+    std::fill(Hh.begin(), Hh.end(), 0.0);
+    for (int r = 0; r < keff; ++r)
+      for (int c = 0; c < keff; ++c) {
+        double sacc = 0.0;
+        for (int i = 0; i < d; ++i) sacc += Pk[size_t(i) * keff + r] * HP[size_t(i) * keff + c];
+        Hh[size_t(r) * ldh + c] = sacc;
+      }
+    for (int r = 0; r < p; ++r)
+      for (int c = 0; c < keff; ++c) Hh[size_t(keff + r) * ldh + c] = HP[size_t(d + r) * keff + c];
+    HIPCHK(hipMemcpyAsync(w.Crot.p, Pk.data(), sizeof(double) * Pk.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w.H.p, Hh.data(), sizeof(double) * Hh.size(), hipMemcpyHostToDevice, s));
+    // V_new = V_{d+p} P_{k+p}: Ritz block by a panel GEMM, then the last panel
+    double* Vn = w.V[cur ^ 1].p;
+    panel_gemm(pl, p, Vb, d / p, w.Crot.p, keff, keff / p, Vn, int64_t(blk), p, 0);
+    HIPCHK(hipMemcpyAsync(Vn + size_t(keff / p) * blk, Vb + size_t(d / p) * blk,
+                          sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
+    cur ^= 1;
+    Vb = w.V[cur].p;
+    cs.keff = keff;
+    const int q = (m * p - keff) / p;
+    cs.d = keff + q * p;
+    first_block = keff / p;
+    rhs_from_S = true;
+    ms_small += host_now_ms() - t3;
+  }
+  // true residuals of the shifted systems (FP64, once at the end)
+  if (pl->kind == 0 && !transpose) {
+    const int PP = pow2_lanes(p);
+    const int grid = grid_for(n, PP, 512);
+    DISPATCH_PP(PP, hipLaunchKernelGGL((k_true_residual<P_>), dim3(grid), dim3(kThreads), 0, s, n,
+                                       p, pl->rowptr.p, pl->colind.p, pl->val.p, B, w.X.p,
+                                       pl->tau_re.p, pl->tau_im.p, w.partial.p));
+    std::vector<double> tp(size_t(grid) * kNShift);
+    HIPCHK(hipMemcpyAsync(tp.data(), w.partial.p, sizeof(double) * tp.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < kNShift; ++j) {
+      double acc = 0.0;
+      for (int g = 0; g < grid; ++g) acc += tp[size_t(g) * kNShift + j];
+      inf.true_res[j] = std::sqrt(acc);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  inf.ms_total = host_now_ms() - t_start;
+  inf.ms_apply = ms_apply;
+  inf.ms_orth = ms_orth;
+  inf.ms_small = ms_small;
+  inf.ms_update = ms_update;
+  inf.kern_samples = pl->prof_samples;
+  inf.kern_ms_a = pl->prof_samples ? pl->prof_ms_a / pl->prof_samples : 0.0;
+  inf.kern_ms_b = pl->prof_samples ? pl->prof_ms_b / pl->prof_samples : 0.0;
+  inf.kern_ms_c = pl->prof_samples ? pl->prof_ms_c / pl->prof_samples : 0.0;
+  if (info) *info = inf;
+  return status;
+}
+
+}  // namespace
+}  // namespace expmv
+
+// ===========================================================================
+// C ABI
+
+namespace {
+
+template <typename F>
+expmv_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const expmv::HipError&) {
+    return EXPMV_EHIP;
+  } catch (const expmv::StatusError& e) {
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    return EXPMV_ENOMEM;
+  } catch (...) {
+    return EXPMV_EHIP;
+  }
+}
+
+bool valid_opts(const expmv_opts& o) {
+  if (o.m < 2 || o.m > 64) return false;
+  if (o.k < 0) return false;
+  if (o.max_cycles < 1) return false;
+  if (o.precision != EXPMV_FP64 && o.precision != EXPMV_MIXED) return false;
+  if (o.stop_rule != EXPMV_STOP_PAPER && o.stop_rule != EXPMV_STOP_BOUND) return false;
+  if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return false;
+  if (o.inner_maxit < 1) return false;
+  if (o.profile < 0) return false;
+  return true;
+}
+
+void upload_cf(expmv_plan_s* pl) {
+  pl->tau_re.alloc(kNShift);
+  pl->tau_im.alloc(kNShift);
+  pl->c_re.alloc(kNShift);
+  pl->c_im.alloc(kNShift);
+  HIPCHK(hipMemcpy(pl->tau_re.p, CF_TAU_RE, sizeof(double) * kNShift, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->tau_im.p, CF_TAU_IM, sizeof(double) * kNShift, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->c_re.p, CF_C_RE, sizeof(double) * kNShift, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->c_im.p, CF_C_IM, sizeof(double) * kNShift, hipMemcpyHostToDevice));
+}
+
+void init_plan_common(expmv_plan_s* pl) {
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pl->host_flags), sizeof(int) * 8,
+                       hipHostMallocDefault));
+  std::memset(pl->host_flags, 0, sizeof(int) * 8);
+  HIPCHK(hipEventCreateWithFlags(&pl->ev[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pl->ev[1], hipEventDisableTiming));
+  if (pl->opts.profile > 0) {
+    pl->pev.resize(4 * 128);
+    pl->pev_iter.resize(128);
+    for (auto& e : pl->pev) HIPCHK(hipEventCreate(&e));
+  }
+  upload_cf(pl);
+}
+
+// Host-side CSR build of K = -tA (and K^T), with validation.
+expmv_status build_csr(expmv_plan_s* pl, const int32_t* rowptr_d, const int32_t* colind_d,
+                       const double* val_d) {
+  const int64_t n = pl->n, nnz = pl->nnz;
+  std::vector<int32_t> rp(n + 1), ci(nnz);
+  std::vector<double> v(nnz);
+  HIPCHK(hipMemcpy(rp.data(), rowptr_d, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+  if (nnz > 0) {
+    HIPCHK(hipMemcpy(ci.data(), colind_d, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(v.data(), val_d, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+  }
+  if (rp[0] != 0 || rp[n] != nnz) return EXPMV_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return EXPMV_EINVAL;
+  std::vector<double> diag(n, 0.0);
+  std::vector<char> has_diag(n, 0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+      if (ci[e] < 0 || ci[e] >= n) return EXPMV_EINVAL;
+      if (!std::isfinite(v[e])) return EXPMV_EINVAL;
+      v[e] *= -pl->t;   // K = -tA
+      if (ci[e] == i) {
+        diag[i] += v[e];
+        has_diag[i] = 1;
+      }
+    }
+  for (int64_t i = 0; i < n; ++i)
+    if (!has_diag[i] || !(diag[i] > 0.0)) return EXPMV_ENOTNEG;
+  // symmetry detection: K^T by counting sort, compare entry by entry
+  std::vector<int32_t> rpt(n + 1, 0), cit(nnz);
+  std::vector<double> vt(nnz);
+  for (int64_t e = 0; e < nnz; ++e) rpt[ci[e] + 1]++;
+  for (int64_t i = 0; i < n; ++i) rpt[i + 1] += rpt[i];
+  {
+    std::vector<int32_t> pos(rpt.begin(), rpt.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t dst = pos[ci[e]]++;
+        cit[dst] = int32_t(i);
+        vt[dst] = v[e];
+      }
+  }
+  bool sym = pl->opts.symmetric == 1;
+  if (pl->opts.symmetric == -1) {
+    // compare row i of K with row i of K^T as sorted (col, value) lists
+    sym = true;
+    std::vector<std::pair<int32_t, double>> a, b;
+    for (int64_t i = 0; i < n && sym; ++i) {
+      a.clear();
+      b.clear();
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) a.emplace_back(ci[e], v[e]);
+      for (int32_t e = rpt[i]; e < rpt[i + 1]; ++e) b.emplace_back(cit[e], vt[e]);
+      if (a.size() != b.size()) {
+        sym = false;
+        break;
+      }
+      std::sort(a.begin(), a.end());
+      std::sort(b.begin(), b.end());
+      for (size_t q = 0; q < a.size(); ++q)
+        if (a[q].first != b[q].first || a[q].second != b[q].second) {
+          sym = false;
+          break;
+        }
+    }
+  }
+  pl->symmetric = sym;
+  std::vector<double> dinv(n);
+  for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0 / diag[i];
+  pl->rowptr.alloc(n + 1);
+  pl->colind.alloc(std::max<int64_t>(nnz, 1));
+  pl->val.alloc(std::max<int64_t>(nnz, 1));
+  pl->dinv.alloc(n);
+  HIPCHK(hipMemcpy(pl->rowptr.p, rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->colind.p, ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->val.p, v.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->dinv.p, dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  if (!sym) {
+    pl->rowptrT.alloc(n + 1);
+    pl->colindT.alloc(std::max<int64_t>(nnz, 1));
+    pl->valT.alloc(std::max<int64_t>(nnz, 1));
+    pl->dinvT.alloc(n);
+    HIPCHK(hipMemcpy(pl->rowptrT.p, rpt.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pl->colindT.p, cit.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pl->valT.p, vt.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pl->dinvT.p, dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  }
+  return EXPMV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+expmv_status expmv_default_opts(expmv_opts* o) {
+  if (!o) return EXPMV_EINVAL;
+  o->m = 10;
+  o->k = 0;
+  o->max_cycles = 50;
+  o->precision = EXPMV_FP64;
+  o->stop_rule = EXPMV_STOP_BOUND;
+  o->inner_tol = 0.0;
+  o->inner_maxit = 50000;
+  o->symmetric = -1;
+  o->preconditioned = 1;
+  o->profile = 0;
+  return EXPMV_OK;
+}
+
+expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                            const double* val, double t, const expmv_opts* opts, hipStream_t stream,
+                            expmv_plan* out) {
+  if (!out) return EXPMV_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n > INT32_MAX - 1 || nnz < 1 || nnz > INT32_MAX || !rowptr || !colind || !val)
+    return EXPMV_EINVAL;
+  if (!(t != 0.0) || !std::isfinite(t)) return EXPMV_EINVAL;
+  expmv_opts o;
+  expmv_default_opts(&o);
+  if (opts) o = *opts;
+  if (!valid_opts(o)) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    std::unique_ptr<expmv_plan_s> pl(new expmv_plan_s());
+    pl->kind = 0;
+    pl->n = n;
+    pl->nnz = nnz;
+    pl->t = t;
+    pl->opts = o;
+    pl->stream = stream;
+    init_plan_common(pl.get());
+    expmv_status st = build_csr(pl.get(), rowptr, colind, val);
+    if (st != EXPMV_OK) return st;
+    *out = pl.release();
+    return EXPMV_OK;
+  });
+}
+
+expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t, const expmv_opts* opts,
+                                 hipStream_t stream, expmv_plan* out) {
+  (void)n;
+  (void)col0;
+  (void)t;
+  (void)opts;
+  (void)stream;
+  if (out) *out = nullptr;
+  return EXPMV_EINVAL;
+}
+
+expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int64_t p, double tol,
+                           double* Z, expmv_info* info) {
+  if (!plan || !B || !Z || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
+  return guarded([&]() { return execute_impl(plan, transpose, B, int(p), tol, Z, info); });
+}
+
+expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Zm, int64_t p,
+                          double* out) {
+  if (!plan || !G || !Zm || !out || p < 1 || p > kMaxP) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    ensure_workspace(plan, int(p));
+    hipStream_t s = plan->stream;
+    const int PP = pow2_lanes(int(p));
+    const int grid = grid_for(plan->n, PP, 512);
+    DISPATCH_PP(PP, hipLaunchKernelGGL((k_dot_spmm<P_>), dim3(grid), dim3(kThreads), 0, s,
+                                       plan->n, int(p), plan->rowptr.p, plan->colind.p,
+                                       plan->val.p, G, Zm, plan->ws.partial.p));
+    std::vector<double> part(grid);
+    HIPCHK(hipMemcpyAsync(part.data(), plan->ws.partial.p, sizeof(double) * grid,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (double v : part) acc += v;
+    // <G, A Z> = -<G, K Z> / t  (K = -tA)
+    *out = -acc / plan->t;
+    return EXPMV_OK;
+  });
+}
+
+expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* X, int64_t p,
+                                  double* Y) {
+  if (!plan || !X || !Y || p < 1 || p > kMaxP) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    apply_K(plan, transpose, X, Y, int(p));
+    const int64_t cnt = plan->n * p;
+    hipLaunchKernelGGL((k_convert<double, double>), dim3(512), dim3(kThreads), 0, plan->stream, cnt,
+                       Y, Y, -1.0);
+    HIPCHK(hipGetLastError());
+    return EXPMV_OK;
+  });
+}
+
+expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X, int64_t p,
+                                 double* Y, long long* iters) {
+  if (!plan || !X || !Y || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    ensure_workspace(plan, int(p));
+    InnerResult r = apply_inverse(plan, transpose, X, Y, int(p));
+    HIPCHK(hipStreamSynchronize(plan->stream));
+    if (iters) *iters = r.iters;
+    return r.hit_cap ? EXPMV_EINNER : EXPMV_OK;
+  });
+}
+
+expmv_status expmv_cf_table(double* tau_re, double* tau_im, double* c_re, double* c_im,
+                            double* omega0) {
+  for (int j = 0; j < kNShift; ++j) {
+    if (tau_re) tau_re[j] = CF_TAU_RE[j];
+    if (tau_im) tau_im[j] = CF_TAU_IM[j];
+    if (c_re) c_re[j] = CF_C_RE[j];
+    if (c_im) c_im[j] = CF_C_IM[j];
+  }
+  if (omega0) *omega0 = CF_OMEGA0;
+  return EXPMV_OK;
+}
+
+expmv_status expmv_host_eig_sym(int n, const double* A, double* w, double* Q) {
+  if (n < 1 || !A || !w || !Q) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    sym_eig(n, A, w, Q);
+    return EXPMV_OK;
+  });
+}
+
+expmv_status expmv_host_eig_general(int n, const double* A, double* wr, double* wi, double* Vr,
+                                    double* Vi) {
+  if (n < 1 || !A || !wr || !wi || !Vr || !Vi) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    return general_eig(n, A, wr, wi, Vr, Vi) ? EXPMV_OK : EXPMV_ENOCONV;
+  });
+}
+
+void expmv_plan_destroy(expmv_plan plan) {
+  if (!plan) return;
+  if (plan->stream) (void)hipStreamSynchronize(plan->stream);
+  else (void)hipDeviceSynchronize();
+  if (plan->host_flags) (void)hipHostFree(plan->host_flags);
+  if (plan->ev[0]) (void)hipEventDestroy(plan->ev[0]);
+  if (plan->ev[1]) (void)hipEventDestroy(plan->ev[1]);
+  for (auto& e : plan->pev) (void)hipEventDestroy(e);
+  delete plan;
+}
+
+const char* expmv_status_string(expmv_status s) {
+  switch (s) {
+    case EXPMV_OK: return "ok";
+    case EXPMV_EINVAL: return "invalid argument";
+    case EXPMV_ENOTNEG: return "tA is not negative definite (diagonal entry >= 0)";
+    case EXPMV_ENOMEM: return "out of memory";
+    case EXPMV_ENOCONV: return "no convergence within max_cycles";
+    case EXPMV_EBREAKDOWN: return "rank-deficient Krylov block";
+    case EXPMV_EHIP: return "HIP runtime error";
+    case EXPMV_EINNER: return "inner solve reached its iteration cap";
+  }
+  return "unknown status";
+}
+
+expmv_status expmv_block_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                             const double* val, const double* B, int64_t p, double t, double tol,
+                             double* Z, hipStream_t stream) {
+  expmv_plan pl = nullptr;
+  expmv_status st = expmv_plan_csr(n, nnz, rowptr, colind, val, t, nullptr, stream, &pl);
+  if (st != EXPMV_OK) return st;
+  st = expmv_execute(pl, 0, B, p, tol, Z, nullptr);
+  expmv_plan_destroy(pl);
+  return st;
+}
+
+expmv_status expmv_block_toeplitz(int64_t n, const double* col0, const double* B, int64_t p,
+                                  double t, double tol, double* Z, hipStream_t stream) {
+  expmv_plan pl = nullptr;
+  expmv_status st = expmv_plan_toeplitz(n, col0, t, nullptr, stream, &pl);
+  if (st != EXPMV_OK) return st;
+  st = expmv_execute(pl, 0, B, p, tol, Z, nullptr);
+  expmv_plan_destroy(pl);
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,341 @@
+// Device kernels of the expmv library (gfx950 / CDNA4).
+//
+// Blocks are n x p row-major (ld = p).  Streaming kernels use 256-thread
+// workgroups and a grid-stride loop over rows; a group of PP lanes (PP = p
+// rounded up to a power of two, PP | 64) owns one row, so every row's p
+// values are one contiguous, coalesced segment.  Reductions are
+// deterministic: per-workgroup partial sums in a fixed tree order, then a
+// fixed-order sum over workgroups (no floating-point atomics).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace expmv {
+
+constexpr int kThreads = 256;
+constexpr int kCgThreads = 1024;   // workgroup size of the inner-solver kernels
+constexpr int kNShift = 7;   // conjugate-pair poles of the degree-14 CF form
+constexpr int kMaxP = 32;    // widest supported block
+
+struct KrylovScalars {
+  double rho;         // CG: (r, D^{-1} r)            BiCGStab: (r0~, r)
+  double alpha;       // step of the current iteration
+  double alpha_prev;  // step still owed to x (CG)
+  double beta;
+  double omega;       // BiCGStab
+  double rnorm2;      // ||r||^2
+  double bnorm2;      // ||b||^2
+  double tmp;         // BiCGStab (r0~, v)
+  int active;         // 1 until the column meets its tolerance or the cap
+  int iters;          // iterations taken while active
+  int hit_cap;        // stopped by the iteration cap
+  int pad;
+};
+
+struct KrylovCtl {
+  unsigned int counter;  // workgroup arrival counter of the last-workgroup reductions
+  int done;              // every column inactive
+  int iters_max;
+  int hit_cap;
+};
+
+// ---------------------------------------------------------------------------
+// block reduction helpers
+
+// Sum v over the lanes of a workgroup that share (tid % PP); result for
+// column c ends in red[c].  red has kThreads doubles.
+template <int PP, int NT = kThreads>
+__device__ inline void block_col_reduce(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s >= PP; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+}
+
+// acc (+)= sum_e val[e] * x[colind[e] * ld + c] over one CSR row, in order,
+// with four independent gathers in flight per step.
+template <typename T>
+__device__ inline T csr_row_dot(const int32_t* __restrict__ colind, const T* __restrict__ val,
+                                const T* __restrict__ x, int e0, int e1, int ld, int c) {
+  T acc = T(0);
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    const int64_t j0 = colind[e], j1 = colind[e + 1], j2 = colind[e + 2], j3 = colind[e + 3];
+    const T v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
+    const T x0 = x[j0 * ld + c], x1 = x[j1 * ld + c], x2 = x[j2 * ld + c], x3 = x[j3 * ld + c];
+    acc += v0 * x0;
+    acc += v1 * x1;
+    acc += v2 * x2;
+    acc += v3 * x3;
+  }
+  for (; e < e1; ++e) acc += val[e] * x[int64_t(colind[e]) * ld + c];
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// CSR SpMM  y = K x  (n x p blocks, PP lanes per row)
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kThreads)
+k_spmm(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+       const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
+  const int c = threadIdx.x % PP;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      y[row * p + c] = csr_row_dot(colind, val, x, rowptr[row], rowptr[row + 1], p, c);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched Jacobi-preconditioned CG on K x = b (K SPD), column-wise, the p
+// columns in lock step, b = sign * src.  No kernel synchronises its own
+// workgroups: every workgroup of a kernel sums the previous kernel's
+// per-workgroup partials itself, in one fixed order, so all of them obtain
+// bitwise the same scalars (visibility across kernels is the stream's).
+// Workgroup 0 records the scalars later kernels need in a two-slot table
+// indexed by the iteration's parity.
+//
+// Iteration k (z = D^{-1} r), three streaming kernels:
+//   C_k: rho_k = (r_k, z_k), |r_k|^2 from B_{k-1}'s partials (init's for k=0);
+//        beta = rho_k / rho_{k-1}; convergence test;
+//        x += alpha_{k-1} p_{k-1};  p_k = z_k + beta p_{k-1}.
+//   A_k: q = K p_k (the CSR SpMM), partial sigma_k = (p_k, q).
+//   B_k: alpha_k = rho_k / sigma_k; r_{k+1} = r_k - alpha_k q;
+//        partials (r_{k+1}, z_{k+1}) and |r_{k+1}|^2.
+// A column whose |r_k| <= tol |b| (or that reached maxit) stops: its last
+// step alpha_{k-1} p_{k-1} is added by C_k and every later step is zero.
+// When no column is active C_k sets ctl->done; later kernels return at once.
+
+struct CgSlot {
+  double rho[kMaxP];
+  double alpha[kMaxP];
+  int active[kMaxP];
+  int iters[kMaxP];
+};
+
+struct CgState {
+  CgSlot slot[2];
+  double bnorm2[kMaxP];
+};
+
+// Sum NV x PP per-workgroup partials (layout [wg][v][c]) in a fixed order;
+// every thread of the workgroup ends with out[v * PP + c] in LDS.
+template <int PP, int NV>
+__device__ inline void reduce_parts(const double* __restrict__ part, int nwg, double* red,
+                                    double* out) {
+  constexpr int slots = PP * NV;
+  constexpr int lanes = kCgThreads / slots;   // >= 16
+  const int tid = threadIdx.x;
+  const int sidx = tid / lanes, l = tid % lanes;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int w = l;
+  for (; w + 3 * lanes < nwg; w += 4 * lanes) {
+    a0 += part[size_t(w) * slots + sidx];
+    a1 += part[size_t(w + lanes) * slots + sidx];
+    a2 += part[size_t(w + 2 * lanes) * slots + sidx];
+    a3 += part[size_t(w + 3 * lanes) * slots + sidx];
+  }
+  for (; w < nwg; w += lanes) a0 += part[size_t(w) * slots + sidx];
+  red[tid] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  for (int st = lanes / 2; st >= 1; st >>= 1) {
+    if (l < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  if (l == 0) out[sidx] = red[tid];
+  __syncthreads();
+}
+
+// per-workgroup column sums of v (PP columns) -> part[wg * stride + off + c]
+template <int PP>
+__device__ inline void write_col_partial(double v, double* red, double* part, int stride, int off) {
+  block_col_reduce<PP, kCgThreads>(v, red);
+  if (threadIdx.x < PP) part[size_t(blockIdx.x) * stride + off + threadIdx.x] = red[threadIdx.x];
+  __syncthreads();
+}
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_cg_init(int n, int p, double sign, const double* __restrict__ src, const T* __restrict__ dinv,
+          T* __restrict__ x, T* __restrict__ r, T* __restrict__ pold,
+          KrylovCtl* ctl, double* __restrict__ part_rr) {
+  __shared__ double red[kCgThreads];
+  const int c = threadIdx.x % PP;
+  double rz = 0.0, bb = 0.0;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      const int64_t i = row * p + c;
+      const T b = T(sign * src[i]);
+      r[i] = b;
+      x[i] = T(0);
+      pold[i] = T(0);
+      const double bd = double(b);
+      rz += bd * double(dinv[row]) * bd;
+      bb += bd * bd;
+    }
+  }
+  write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
+  write_col_partial<PP>(bb, red, part_rr, 2 * PP, PP);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->done = 0;
+    ctl->iters_max = 0;
+    ctl->hit_cap = 0;
+    ctl->counter = 0u;
+  }
+}
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
+       const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x, CgState* st,
+       KrylovCtl* ctl, const double* __restrict__ part_rr, double tol2, int maxit) {
+  if (ctl->done) return;
+  __shared__ double red[kCgThreads];
+  __shared__ double tot[2 * PP];
+  __shared__ double s_beta[PP], s_aprev[PP];
+  __shared__ int s_any;
+  reduce_parts<PP, 2>(part_rr, gridDim.x, red, tot);   // tot[c] = rho_k, tot[PP + c] = |r_k|^2
+  if (threadIdx.x == 0) {
+    int any = 0, itmax = 0, hit = 0;
+    const CgSlot& prev = st->slot[(k + 1) & 1];
+    for (int cc = 0; cc < PP; ++cc) {
+      double beta = 0.0, aprev = 0.0;
+      int act = 0, it = 0;
+      if (cc < p) {
+        const double rho = tot[cc], rn = tot[PP + cc];
+        double bn;
+        int act_prev;
+        if (k == 0) {
+          bn = rn;
+          act_prev = bn > 0.0;
+        } else {
+          bn = st->bnorm2[cc];
+          act_prev = prev.active[cc];
+          it = prev.iters[cc];
+          aprev = prev.alpha[cc];
+          beta = (act_prev && prev.rho[cc] != 0.0) ? rho / prev.rho[cc] : 0.0;
+        }
+        act = act_prev && !(rn <= tol2 * bn);
+        if (act && it >= maxit) {
+          act = 0;
+          hit = 1;
+        }
+        if (!act) beta = 0.0;
+        if (blockIdx.x == 0) {
+          CgSlot& cur = st->slot[k & 1];
+          cur.rho[cc] = rho;
+          cur.active[cc] = act;
+          cur.iters[cc] = it + act;
+          if (k == 0) st->bnorm2[cc] = bn;
+        }
+        if (it > itmax) itmax = it;
+      }
+      s_beta[cc] = beta;
+      s_aprev[cc] = aprev;
+      any |= act;
+    }
+    s_any = any;
+    if (blockIdx.x == 0 && !any) {
+      ctl->iters_max = itmax;
+      ctl->hit_cap = hit;
+      ctl->done = 1;
+    }
+  }
+  __syncthreads();
+  const int c = threadIdx.x % PP;
+  const T beta = T(s_beta[c]), aprev = T(s_aprev[c]);
+  const bool any = s_any != 0;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      const int64_t i = row * p + c;
+      const T po = pold[i];
+      x[i] += aprev * po;
+      if (any) pnew[i] = dinv[row] * r[i] + beta * po;
+    }
+  }
+}
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_cg_a(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+       const T* __restrict__ val, const T* __restrict__ pk, T* __restrict__ q,
+       const KrylovCtl* ctl, double* __restrict__ part_sig) {
+  if (ctl->done) return;
+  __shared__ double red[kCgThreads];
+  const int c = threadIdx.x % PP;
+  double sig = 0.0;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      const T acc = csr_row_dot(colind, val, pk, rowptr[row], rowptr[row + 1], p, c);
+      const int64_t i = row * p + c;
+      q[i] = acc;
+      sig += double(pk[i]) * double(acc);
+    }
+  }
+  write_col_partial<PP>(sig, red, part_sig, PP, 0);
+}
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const T* __restrict__ q,
+       CgState* st, const KrylovCtl* ctl, const double* __restrict__ part_sig,
+       double* __restrict__ part_rr) {
+  if (ctl->done) return;
+  __shared__ double red[kCgThreads];
+  __shared__ double tot[PP];
+  __shared__ double s_alpha[PP];
+  reduce_parts<PP, 1>(part_sig, gridDim.x, red, tot);
+  if (threadIdx.x < PP) {
+    const int cc = threadIdx.x;
+    double a = 0.0;
+    if (cc < p) {
+      const CgSlot& cur = st->slot[k & 1];
+      a = (cur.active[cc] && tot[cc] != 0.0) ? cur.rho[cc] / tot[cc] : 0.0;
+      if (blockIdx.x == 0) st->slot[k & 1].alpha[cc] = a;
+    }
+    s_alpha[cc] = a;
+  }
+  __syncthreads();
+  const int c = threadIdx.x % PP;
+  const T alpha = T(s_alpha[c]);
+  double rz = 0.0, rr = 0.0;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      const int64_t i = row * p + c;
+      const T rn = r[i] - alpha * q[i];
+      r[i] = rn;
+      const double rd = double(rn);
+      rz += rd * double(dinv[row]) * rd;
+      rr += rd * rd;
+    }
+  }
+  write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
+  write_col_partial<PP>(rr, red, part_rr, 2 * PP, PP);
+}
+
+// out = (double) x
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_to_f64(int64_t count, const T* __restrict__ x, double* __restrict__ out) {
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * kThreads)
+    out[i] = double(x[i]);
+}
+
+}  // namespace expmv

@@ -1,0 +1,556 @@
+// Dense kernels of the expmv library: block Gram-Schmidt passes and CholQR
+// on the tall n x p panels, the batched projected shifted solves, the
+// panel GEMMs for the solution update and the restart rotation, the final
+// pole combination and the true residuals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace expmv {
+
+enum OrthMode : int {
+  kProj = 0,       // partial = V^T W  (+ ||W(:,b)||^2 in the extra p outputs)
+  kUpdProj = 1,    // W' = W - V C;  partial = V^T W'
+  kUpdGram = 2,    // W' = W - V C;  partial = W'^T W'
+  kScaleGram = 3,  // W' = W C (C p x p);  partial = W'^T W'
+  kScale = 4       // W' = W C
+};
+
+// One streaming pass over the n x p block W against npan basis panels
+// (panel i at V + i*n*p), staged through LDS in tiles of TR rows.
+// Dynamic LDS: sV[TR][npan*p] (T), sW[TR][p], sW2[TR][p] (T), acc[O] (double).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_orth(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const T* __restrict__ W,
+       T* __restrict__ Wout, const double* __restrict__ C, double* __restrict__ partial,
+       int TR, int64_t rows_per_wg) {
+  extern __shared__ double lds_d[];
+  const int tid = threadIdx.x;
+  const int np_cols = npan * p;
+  const bool use_v = (mode == kProj || mode == kUpdProj || mode == kUpdGram);
+  const bool gram = (mode == kUpdGram || mode == kScaleGram);
+  const bool proj = (mode == kProj || mode == kUpdProj);
+  const int O = proj ? np_cols * p + (mode == kProj ? p : 0) : (gram ? p * p : 0);
+  double* acc = lds_d;
+  T* sV = reinterpret_cast<T*>(lds_d + O);
+  T* sW = sV + (use_v ? size_t(TR) * np_cols : 0);
+  T* sW2 = sW + size_t(TR) * p;
+  for (int o = tid; o < O; o += kThreads) acc[o] = 0.0;
+  const int64_t r_begin = int64_t(blockIdx.x) * rows_per_wg;
+  const int64_t r_end = min<int64_t>(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += TR) {
+    const int rows = int(min<int64_t>(TR, r_end - r0));
+    __syncthreads();
+    if (use_v) {
+      // panel i holds rows r0..r0+rows-1 as one contiguous run of rows*p values
+      const int run = rows * p;
+      for (int idx = tid; idx < npan * TR * p; idx += kThreads) {
+        const int i = idx / (TR * p), w = idx % (TR * p);
+        const int rr = w / p, a = w % p;
+        sV[rr * np_cols + i * p + a] =
+            (w < run) ? V[int64_t(i) * n * p + r0 * p + w] : T(0);
+      }
+    }
+    for (int idx = tid; idx < TR * p; idx += kThreads)
+      sW[idx] = (idx < rows * p) ? W[r0 * p + idx] : T(0);
+    __syncthreads();
+    if (mode != kProj) {
+      for (int idx = tid; idx < TR * p; idx += kThreads) {
+        const int rr = idx / p, b = idx % p;
+        double s;
+        if (mode == kUpdProj || mode == kUpdGram) {
+          s = double(sW[idx]);
+          const T* vr = sV + rr * np_cols;
+          for (int col = 0; col < np_cols; ++col) s -= double(vr[col]) * C[col * p + b];
+        } else {
+          s = 0.0;
+          const T* wr = sW + rr * p;
+          for (int a = 0; a < p; ++a) s += double(wr[a]) * C[a * p + b];
+        }
+        sW2[idx] = T(s);
+        if (rr < rows) Wout[r0 * p + idx] = T(s);
+      }
+      __syncthreads();
+    }
+    const T* wsrc = (mode == kProj) ? sW : sW2;
+    if (proj) {
+      for (int o = tid; o < np_cols * p; o += kThreads) {
+        const int col = o / p, b = o % p;
+        double s = 0.0;
+        for (int rr = 0; rr < rows; ++rr) s += double(sV[rr * np_cols + col]) * double(wsrc[rr * p + b]);
+        acc[o] += s;
+      }
+      if (mode == kProj) {
+        for (int b = tid; b < p; b += kThreads) {
+          double s = 0.0;
+          for (int rr = 0; rr < rows; ++rr) s += double(wsrc[rr * p + b]) * double(wsrc[rr * p + b]);
+          acc[np_cols * p + b] += s;
+        }
+      }
+    } else if (gram) {
+      for (int o = tid; o < p * p; o += kThreads) {
+        const int a = o / p, b = o % p;
+        double s = 0.0;
+        for (int rr = 0; rr < rows; ++rr) s += double(wsrc[rr * p + a]) * double(wsrc[rr * p + b]);
+        acc[o] += s;
+      }
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < O; o += kThreads) partial[size_t(blockIdx.x) * O + o] = acc[o];
+}
+
+// out[o] = sum_w partial[w*O + o], fixed order; 8 lanes per output.
+// If H != nullptr the first O_h outputs (rows of C = (npan*p) x p) are also
+// added to H[(row) * ldh + col0 + b].
+__global__ void __launch_bounds__(kThreads)
+k_reduce_partials(const double* __restrict__ partial, int nwg, int O, double* __restrict__ out,
+                  double* __restrict__ H, int ldh, int col0, int p, int O_h) {
+  __shared__ double red[kThreads];
+  constexpr int L = 8;
+  const int o = blockIdx.x * (kThreads / L) + threadIdx.x / L;
+  const int l = threadIdx.x % L;
+  double s = 0.0;
+  if (o < O)
+    for (int w = l; w < nwg; w += L) s += partial[size_t(w) * O + o];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = L / 2; st >= 1; st >>= 1) {
+    if (l < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (l == 0 && o < O) {
+    const double v = red[threadIdx.x];
+    out[o] = v;
+    if (H != nullptr && o < O_h) {
+      const int row = o / p, b = o % p;
+      H[int64_t(row) * ldh + col0 + b] += v;
+    }
+  }
+}
+
+// Cholesky of the p x p Gram matrix G = R^T R (R upper) and R^{-1}.
+// stage 1 (after Gram-Schmidt): w0norm2 = ||W||_F^2 before projection; a
+//   trace(G) <= (1e-12)^2 * w0norm2 is an invariant subspace (happy
+//   breakdown): R = R^{-1} = 0 and flags[0] = 1; a non-positive pivot
+//   otherwise sets flags[1] (rank-deficient block).
+// stage 2: H(jrow.., jcol..) = R2 * R1 (R1 from stage 1 in Rprev).
+__global__ void k_cholqr_factor(int p, const double* __restrict__ G, double* __restrict__ R,
+                                double* __restrict__ Rinv, const double* __restrict__ w0norm2,
+                                int stage, const double* __restrict__ Rprev,
+                                double* __restrict__ H, int ldh, int hrow, int hcol,
+                                int* __restrict__ flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double tr = 0.0;
+  for (int i = 0; i < p; ++i) tr += G[i * p + i];
+  double wn = 0.0;
+  if (stage == 1)
+    for (int b = 0; b < p; ++b) wn += w0norm2[b];
+  bool zero = (stage == 1) ? (tr <= 1e-24 * wn) : (tr == 0.0);
+  if (!zero) {
+    for (int j = 0; j < p; ++j) {
+      double djj = G[j * p + j];
+      for (int k = 0; k < j; ++k) djj -= R[k * p + j] * R[k * p + j];
+      if (!(djj > 1e-28 * tr)) {   // rank deficient (or NaN)
+        flags[1] = 1;
+        zero = true;
+        break;
+      }
+      const double rjj = sqrt(djj);
+      R[j * p + j] = rjj;
+      for (int i = j + 1; i < p; ++i) {
+        double s = G[j * p + i];
+        for (int k = 0; k < j; ++k) s -= R[k * p + j] * R[k * p + i];
+        R[j * p + i] = s / rjj;
+      }
+      for (int i = 0; i < j; ++i) R[j * p + i] = 0.0;
+    }
+  } else if (stage == 1) {
+    flags[0] = 1;
+  }
+  if (zero) {
+    for (int i = 0; i < p * p; ++i) {
+      R[i] = 0.0;
+      Rinv[i] = 0.0;
+    }
+  } else {
+    // Rinv = R^{-1}, upper triangular, column by column
+    for (int j = 0; j < p; ++j) {
+      for (int i = j + 1; i < p; ++i) Rinv[i * p + j] = 0.0;
+      Rinv[j * p + j] = 1.0 / R[j * p + j];
+      for (int i = j - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int k = i + 1; k <= j; ++k) s += R[i * p + k] * Rinv[k * p + j];
+        Rinv[i * p + j] = -s / R[i * p + i];
+      }
+    }
+  }
+  if (stage == 2 && H != nullptr) {
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < p; ++k) s += R[i * p + k] * Rprev[k * p + j];
+        H[int64_t(hrow + i) * ldh + hcol + j] = s;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// complex helpers
+struct cplx {
+  double x, y;
+};
+__device__ inline cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
+__device__ inline cplx cdiv(cplx a, cplx b) {
+  // Smith's algorithm
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, den = b.x + b.y * r;
+    return {(a.x + a.y * r) / den, (a.y - a.x * r) / den};
+  }
+  const double r = b.x / b.y, den = b.x * r + b.y;
+  return {(a.x * r + a.y) / den, (a.y * r - a.x) / den};
+}
+
+// Projected shifted systems, one workgroup per pole j (Section 4.1, eq. 4.7):
+//   precond: (I - tau_j H_d) Z_j = G_j,  S_j = tau_j H(d:d+p, 0:d) Z_j,
+//            Cr(:, shift j) = H~ Z_j  ((d+p) x p, real and imaginary parts)
+//   plain:   (H_d - tau_j I) Z_j = G_j,  S_j = -H(d:d+p, 0:d) Z_j,
+//            Cr(:, shift j) = [Z_j; 0]
+// Dense LU with partial pivoting on a d x d complex matrix in global scratch.
+// rho_j = ||S_j||_F (eq. 4.9 / eq. 3.6).
+__global__ void __launch_bounds__(1024)
+k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
+             const double* __restrict__ tau_re, const double* __restrict__ tau_im,
+             const cplx* __restrict__ G, cplx* __restrict__ Ascr, cplx* __restrict__ Zs,
+             double* __restrict__ Cr, cplx* __restrict__ S, double* __restrict__ rho,
+             int* __restrict__ singular) {
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const cplx tau{tau_re[j], tau_im[j]};
+  cplx* A = Ascr + size_t(j) * d * d;
+  cplx* Z = Zs + size_t(j) * d * p;
+  const cplx* Gj = G + size_t(j) * d * p;
+  __shared__ double sval[1024];
+  __shared__ int sidx[1024];
+  __shared__ int piv_s;
+  for (int idx = tid; idx < d * d; idx += nt) {
+    const int r = idx / d, c = idx % d;
+    const double h = H[int64_t(r) * ldh + c];
+    cplx a;
+    if (precond) {
+      a = {-tau.x * h, -tau.y * h};
+      if (r == c) a.x += 1.0;
+    } else {
+      a = {h, 0.0};
+      if (r == c) {
+        a.x -= tau.x;
+        a.y -= tau.y;
+      }
+    }
+    A[idx] = a;
+  }
+  for (int idx = tid; idx < d * p; idx += nt) Z[idx] = Gj[idx];
+  __syncthreads();
+  int sing = 0;
+  for (int c = 0; c < d; ++c) {
+    // pivot search
+    double best = -1.0;
+    int bi = c;
+    for (int r = c + tid; r < d; r += nt) {
+      const cplx a = A[r * d + c];
+      const double v = a.x * a.x + a.y * a.y;
+      if (v > best) {
+        best = v;
+        bi = r;
+      }
+    }
+    sval[tid] = best;
+    sidx[tid] = bi;
+    __syncthreads();
+    for (int st = nt / 2; st >= 1; st >>= 1) {
+      if (tid < st) {
+        const double o = sval[tid + st];
+        const int oi = sidx[tid + st];
+        if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
+          sval[tid] = o;
+          sidx[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) piv_s = sidx[0];
+    if (sval[0] <= 0.0) sing = 1;
+    __syncthreads();
+    const int pv = piv_s;
+    if (pv != c) {
+      for (int cc = c + tid; cc < d; cc += nt) {
+        const cplx t0 = A[c * d + cc];
+        A[c * d + cc] = A[pv * d + cc];
+        A[pv * d + cc] = t0;
+      }
+      for (int b = tid; b < p; b += nt) {
+        const cplx t0 = Z[c * p + b];
+        Z[c * p + b] = Z[pv * p + b];
+        Z[pv * p + b] = t0;
+      }
+    }
+    __syncthreads();
+    const cplx diag = A[c * d + c];
+    if (diag.x == 0.0 && diag.y == 0.0) {
+      sing = 1;
+      __syncthreads();
+      continue;
+    }
+    for (int r = c + 1 + tid; r < d; r += nt) A[r * d + c] = cdiv(A[r * d + c], diag);
+    __syncthreads();
+    const int m1 = d - c - 1;
+    const int wide = m1 + p;
+    for (int idx = tid; idx < m1 * wide; idx += nt) {
+      const int r = c + 1 + idx / wide;
+      const int cc = idx % wide;
+      const cplx l = A[r * d + c];
+      if (cc < m1) {
+        const int col = c + 1 + cc;
+        A[r * d + col] = csub(A[r * d + col], cmul(l, A[c * d + col]));
+      } else {
+        const int b = cc - m1;
+        Z[r * p + b] = csub(Z[r * p + b], cmul(l, Z[c * p + b]));
+      }
+    }
+    __syncthreads();
+  }
+  // back substitution
+  for (int c = d - 1; c >= 0; --c) {
+    const cplx diag = A[c * d + c];
+    if (tid < p) Z[c * p + tid] = (diag.x == 0.0 && diag.y == 0.0) ? cplx{0.0, 0.0}
+                                                                   : cdiv(Z[c * p + tid], diag);
+    __syncthreads();
+    for (int idx = tid; idx < c * p; idx += nt) {
+      const int r = idx / p, b = idx % p;
+      Z[r * p + b] = csub(Z[r * p + b], cmul(A[r * d + c], Z[c * p + b]));
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && sing) singular[j] = 1;
+  // update coefficients Cr (rows d+p, ld 14p): real part then imaginary part
+  const int ldc = 2 * kNShift * p;
+  for (int idx = tid; idx < (d + p) * p; idx += nt) {
+    const int r = idx / p, b = idx % p;
+    cplx s{0.0, 0.0};
+    if (precond) {
+      for (int c = 0; c < d; ++c) {
+        const double h = H[int64_t(r) * ldh + c];
+        const cplx z = Z[c * p + b];
+        s.x += h * z.x;
+        s.y += h * z.y;
+      }
+    } else if (r < d) {
+      s = Z[r * p + b];
+    }
+    Cr[int64_t(r) * ldc + 2 * p * j + b] = s.x;
+    Cr[int64_t(r) * ldc + 2 * p * j + p + b] = s.y;
+  }
+  // S_j and rho_j
+  for (int idx = tid; idx < p * p; idx += nt) {
+    const int a = idx / p, b = idx % p;
+    cplx s{0.0, 0.0};
+    for (int c = 0; c < d; ++c) {
+      const double h = H[int64_t(d + a) * ldh + c];
+      const cplx z = Z[c * p + b];
+      s.x += h * z.x;
+      s.y += h * z.y;
+    }
+    S[size_t(j) * p * p + idx] = precond ? cmul(tau, s) : cplx{-s.x, -s.y};
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ss = 0.0;
+    for (int idx = 0; idx < p * p; ++idx) {
+      const cplx v = S[size_t(j) * p * p + idx];
+      ss += v.x * v.x + v.y * v.y;
+    }
+    rho[j] = sqrt(ss);
+  }
+}
+
+// Right-hand sides of the projected systems: G_j = 0 except rows
+// row0..row0+p-1 = src (cycle 1: src = R^ real p x p, same for all j;
+// after a restart: src = S_j complex).
+__global__ void k_build_rhs(int d, int p, int row0, int complex_src, const double* __restrict__ Rhat,
+                            const cplx* __restrict__ S, cplx* __restrict__ G) {
+  const int j = blockIdx.y;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < d * p; idx += gridDim.x * blockDim.x) {
+    const int r = idx / p, b = idx % p;
+    cplx v{0.0, 0.0};
+    if (r >= row0 && r < row0 + p) {
+      const int a = r - row0;
+      if (complex_src) v = S[size_t(j) * p * p + a * p + b];
+      else v = {Rhat[a * p + b], 0.0};
+    }
+    G[size_t(j) * d * p + idx] = v;
+  }
+}
+
+// out chunk q (p columns) (+)= sum_c V(:, c) C(c, q*p + b), V = npan panels.
+// Output chunk q starts at out + q * chunk_stride with row stride ldo.
+// Dynamic LDS: sV[TR][npan*p] (T), sC[npan*p][p] (double).
+template <typename T, typename TO>
+__global__ void __launch_bounds__(kThreads)
+k_panel_gemm(int64_t n, int p, const T* __restrict__ V, int npan, const double* __restrict__ C,
+             int ldc, TO* __restrict__ out, int64_t chunk_stride, int64_t ldo, int accumulate,
+             int TR, int64_t rows_per_wg) {
+  extern __shared__ double lds_d[];
+  const int q = blockIdx.y;
+  const int np_cols = npan * p;
+  double* sC = lds_d;
+  T* sV = reinterpret_cast<T*>(lds_d + size_t(np_cols) * p);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < np_cols * p; idx += kThreads) {
+    const int c = idx / p, b = idx % p;
+    sC[idx] = C[int64_t(c) * ldc + q * p + b];
+  }
+  TO* o = out + q * chunk_stride;
+  const int64_t r_begin = int64_t(blockIdx.x) * rows_per_wg;
+  const int64_t r_end = min<int64_t>(n, r_begin + rows_per_wg);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += TR) {
+    const int rows = int(min<int64_t>(TR, r_end - r0));
+    __syncthreads();
+    const int run = rows * p;
+    for (int idx = tid; idx < npan * TR * p; idx += kThreads) {
+      const int i = idx / (TR * p), w = idx % (TR * p);
+      const int rr = w / p, a = w % p;
+      sV[rr * np_cols + i * p + a] = (w < run) ? V[int64_t(i) * n * p + r0 * p + w] : T(0);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < rows * p; idx += kThreads) {
+      const int rr = idx / p, b = idx % p;
+      const T* vr = sV + rr * np_cols;
+      double s = 0.0;
+      for (int c = 0; c < np_cols; ++c) s += double(vr[c]) * sC[c * p + b];
+      TO* dst = o + (r0 + rr) * ldo + b;
+      *dst = accumulate ? TO(double(*dst) + s) : TO(s);
+    }
+  }
+}
+
+// Z = omega0 B + sum_j Re(c_j X_j), X row-major n x 14p (shift j: real part
+// in columns 2pj..2pj+p-1, imaginary part in 2pj+p..2pj+2p-1); partial ||Z||^2.
+__global__ void __launch_bounds__(kThreads)
+k_combine(int64_t n, int p, const double* __restrict__ B, const double* __restrict__ X,
+          double omega0, const double* __restrict__ c_re, const double* __restrict__ c_im,
+          double* __restrict__ Z, double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  const int ldx = 2 * kNShift * p;
+  double zz = 0.0;
+  for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < n * p;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t r = idx / p;
+    const int b = int(idx % p);
+    double s = omega0 * B[idx];
+    const double* xr = X + r * ldx;
+    for (int j = 0; j < kNShift; ++j) s += c_re[j] * xr[2 * p * j + b] - c_im[j] * xr[2 * p * j + p + b];
+    Z[idx] = s;
+    zz += s * s;
+  }
+  red[threadIdx.x] = zz;
+  __syncthreads();
+  for (int st = kThreads / 2; st >= 1; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// True residuals R_j = B - (M - tau_j I) X_j = B + K X_j + tau_j X_j with
+// K = -M in CSR; partial[wg * 7 + j] = sum of |R_j|^2 over the workgroup.
+template <int PP>
+__global__ void __launch_bounds__(kThreads)
+k_true_residual(int64_t n, int p, const int32_t* __restrict__ rowptr,
+                const int32_t* __restrict__ colind, const double* __restrict__ val,
+                const double* __restrict__ B, const double* __restrict__ X,
+                const double* __restrict__ tau_re, const double* __restrict__ tau_im,
+                double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  const int c = threadIdx.x % PP;
+  const int ldx = 2 * kNShift * p;
+  double nr[kNShift];
+  for (int j = 0; j < kNShift; ++j) nr[j] = 0.0;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      const int e0 = rowptr[row], e1 = rowptr[row + 1];
+      const double bv = B[row * p + c];
+      for (int j = 0; j < kNShift; ++j) {
+        double kr = 0.0, ki = 0.0;
+        for (int e = e0; e < e1; ++e) {
+          const double* xc = X + int64_t(colind[e]) * ldx + 2 * p * j;
+          kr += val[e] * xc[c];
+          ki += val[e] * xc[p + c];
+        }
+        const double* xs = X + row * ldx + 2 * p * j;
+        const double xr = xs[c], xi = xs[p + c];
+        const double rr = bv + kr + tau_re[j] * xr - tau_im[j] * xi;
+        const double ri = ki + tau_re[j] * xi + tau_im[j] * xr;
+        nr[j] += rr * rr + ri * ri;
+      }
+    }
+  }
+  for (int j = 0; j < kNShift; ++j) {
+    red[threadIdx.x] = nr[j];
+    __syncthreads();
+    for (int st = kThreads / 2; st >= 1; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[size_t(blockIdx.x) * kNShift + j] = red[0];
+    __syncthreads();
+  }
+}
+
+// partial dot <G, K Z> per workgroup (K in CSR)
+template <int PP>
+__global__ void __launch_bounds__(kThreads)
+k_dot_spmm(int64_t n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+           const double* __restrict__ val, const double* __restrict__ Gm,
+           const double* __restrict__ Zm, double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  const int c = threadIdx.x % PP;
+  double s = 0.0;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      double acc = 0.0;
+      for (int e = rowptr[row]; e < rowptr[row + 1]; ++e) acc += val[e] * Zm[int64_t(colind[e]) * p + c];
+      s += Gm[row * p + c] * acc;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kThreads / 2; st >= 1; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// small helpers
+template <typename TI, typename TO>
+__global__ void k_convert(int64_t count, const TI* __restrict__ in, TO* __restrict__ out, double scale) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = TO(scale * double(in[i]));
+}
+
+__global__ void k_fill_zero_d(int64_t count, double* __restrict__ out) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = 0.0;
+}
+
+}  // namespace expmv

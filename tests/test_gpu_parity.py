@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle and the
+plain definitions, element by element, on seeded inputs.
+
+Tolerance (FP64 form): 1e-10 relative in the Frobenius norm against the
+rational form r(tA)B, the bar the target sets for FP64; it is measured
+against r(tA)B and not e^{tA}B because the CF error (~2e-14 ||B||) is
+amplified by ||B||/||Z|| (up to 2e5 on the 3D Laplacian).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import workloads as wl
+from oracle import exact, inverses, psbfom
+from oracle.cf import r_eval
+from paper_1405_0707_amd import Plan, _lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rfun(lam):
+    return r_eval(np.asarray(lam, dtype=np.float64))
+
+
+def plan_for(W, **opts):
+    return Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=DEV, **opts)
+
+
+def announce(name):
+    print(f"[gpu-test] {name}", flush=True)
+
+
+@pytest.mark.parametrize("N,p", [(7, 1), (16, 3), (27, 4), (32, 8), (17, 16), (12, 32)])
+def test_operator_matches_scipy(N, p):
+    announce(f"operator N={N} p={p}")
+    W = wl.c1(N=N, p=p)
+    pl = plan_for(W)
+    X = np.random.default_rng(p).standard_normal((W.n, p))
+    Y = pl.apply_operator(torch.from_numpy(X)).cpu().numpy()
+    ref = (W.t * W.A.to_scipy()) @ X
+    assert np.max(np.abs(Y - ref)) <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("p", [2, 5, 8])
+def test_inverse_matches_splu(p):
+    announce(f"inverse p={p}")
+    W = wl.c1(N=32, p=p)
+    pl = plan_for(W, inner_tol=1e-13)
+    X = np.random.default_rng(10 + p).standard_normal((W.n, p))
+    Y, iters = pl.apply_inverse(torch.from_numpy(X))
+    M = (W.t * W.A.to_scipy()).tocsr()
+    ref = inverses.splu_inverse(M)(X)
+    assert iters > 0
+    assert rel(Y.cpu().numpy(), ref) < 1e-10
+
+
+def test_c1_full_matches_oracle_and_closed_form():
+    announce("execute C1 32^2 p=4 m=10")
+    W = wl.c1()
+    pl = plan_for(W, m=W.m, k=W.k)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=W.tol)
+    Z = Z.cpu().numpy()
+    rB = inverses.dst_laplacian_function(32, 2, W.t, rfun, W.B)
+    M = (W.t * W.A.to_scipy()).tocsr()
+    Zo, _, oinfo = psbfom.psbfom_dr(inverses.splu_inverse(M), W.B, W.m, W.k, W.tol,
+                                    stop_rule="bound")
+    assert info.cycles >= 2, info.cycles          # the restart is exercised
+    assert rel(Z, rB) < 1e-10
+    assert rel(Z, Zo) < 1e-10
+
+
+def test_ragged_sizes_match_dense_rational():
+    announce("execute ragged 2D N=27 p=3")
+    W = wl.c1(N=27, p=3, m=8)
+    pl = plan_for(W, m=8, k=6)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=1e-11)
+    M = (W.t * W.A.to_scipy()).toarray()
+    ref = exact.rational_dense(M, W.B)
+    assert rel(Z.cpu().numpy(), ref) < 1e-10
+
+
+def test_3d_laplacian_reduced_matches_closed_form():
+    announce("execute 3D N=24 p=8 m=15")
+    N = 24
+    W = wl.c2(N=N)
+    W.t = 5.842338 / (3 * (2 - 2 * np.cos(np.pi / (N + 1))))
+    pl = plan_for(W, m=W.m, k=W.k)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=W.tol)
+    rB = inverses.dst_laplacian_function(N, 3, W.t, rfun, W.B)
+    assert rel(Z.cpu().numpy(), rB) < 1e-10
+
+
+def test_c2_full_size_matches_closed_form():
+    """The benchmark workload (64^3, p = 8, m = 15) in the benchmark's launch
+    configuration, against the DST-I closed form of r(tA)B at full size."""
+    announce("execute C2 64^3 p=8 m=15")
+    W = wl.c2()
+    pl = plan_for(W, m=W.m, k=W.k)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=W.tol)
+    rB = inverses.dst_laplacian_function(64, 3, W.t, rfun, W.B)
+    e = rel(Z.cpu().numpy(), rB)
+    print(f"C2 rel err {e:.3e} cycles {info.cycles} inner {info.inner_iters}")
+    assert e < 1e-10
+
+
+def test_sine_modes_happy_breakdown():
+    announce("sine-mode breakdown")
+    N = 16
+    W = wl.c1(N=N, p=2, m=6)
+    k = np.arange(1, N + 1)
+    s = lambda j: np.sin(k * j * np.pi / (N + 1))
+    B = np.stack([np.kron(s(1), s(1)), np.kron(s(2), s(3))], 1)
+    B /= np.linalg.norm(B, axis=0)
+    pl = plan_for(W, m=6, k=2)
+    Z, info = pl.execute(torch.from_numpy(B), tol=1e-12)
+    mu = np.array([2 * (2 - 2 * np.cos(np.pi / (N + 1))),
+                   (2 - 2 * np.cos(2 * np.pi / (N + 1))) + (2 - 2 * np.cos(3 * np.pi / (N + 1)))])
+    expect = B * rfun(-W.t * mu)[None, :]
+    assert info.cycles == 1 and info.breakdown == 1
+    assert np.linalg.norm(Z.cpu().numpy() - expect) < 1e-12 * np.linalg.norm(B)
+
+
+def test_algorithm_1_unpreconditioned():
+    announce("SBFOM-DR")
+    W = wl.c1(N=16, p=3)
+    pl = plan_for(W, m=20, k=6, preconditioned=0, max_cycles=400)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=1e-12)
+    ref = exact.rational_dense((W.t * W.A.to_scipy()).toarray(), W.B)
+    assert rel(Z.cpu().numpy(), ref) < 1e-9
+
+
+def test_grad_t_matches_definition():
+    announce("grad_t")
+    W = wl.c1(N=20, p=3)
+    pl = plan_for(W)
+    G = np.random.default_rng(3).standard_normal(W.B.shape)
+    Zt = np.random.default_rng(4).standard_normal(W.B.shape)
+    g = pl.grad_t(torch.from_numpy(G), torch.from_numpy(Zt))
+    ref = float(np.sum(G * (W.A.to_scipy() @ Zt)))
+    assert abs(g - ref) <= 1e-12 * abs(ref) + 1e-12
+
+
+def test_deterministic_bitwise():
+    announce("determinism")
+    W = wl.c1(N=24, p=4)
+    pl = plan_for(W)
+    Z1, _ = pl.execute(torch.from_numpy(W.B), tol=1e-10)
+    Z2, _ = pl.execute(torch.from_numpy(W.B), tol=1e-10)
+    assert torch.equal(Z1, Z2)
+
+
+def test_error_statuses():
+    announce("error statuses")
+    W = wl.c1(N=8, p=2)
+    pl = plan_for(W)
+    B = torch.from_numpy(W.B)
+    with pytest.raises(_lib.ExpmvError) as e:
+        pl.execute(B, tol=0.0)
+    assert e.value.status == _lib.EINVAL
+    with pytest.raises(_lib.ExpmvError) as e:
+        pl.execute(torch.zeros((W.n, 40), dtype=torch.float64), tol=1e-8)
+    assert e.value.status == _lib.EINVAL
+    # tA not negative definite: flip the sign of A
+    with pytest.raises(_lib.ExpmvError) as e:
+        Plan.csr(W.A.rowptr, W.A.colind, -W.A.val, W.t, device=DEV)
+    assert e.value.status == _lib.ENOTNEG
+    # max_cycles = 1 on a problem that needs two cycles
+    W1 = wl.c1()
+    pl1 = plan_for(W1, m=4, k=4, max_cycles=1)
+    Z, info = pl1.execute(torch.from_numpy(W1.B), tol=1e-12, allow=(_lib.ENOCONV,))
+    assert info.cycles == 1

@@ -1,0 +1,77 @@
+"""Host-side checks of libexpmv.so that need no GPU: it loads, exports every
+symbol include/expmv.h declares, its CF table agrees with the oracle's as a
+function on (-inf, 0], and its host eigensolvers (restart step) are right."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1405_0707_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "expmv.h")).read()
+    return sorted(set(re.findall(r"\b(expmv_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = header_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_cf_table_matches_oracle_as_function():
+    from oracle.cf import r_eval, cf_table
+    from paper_1405_0707_amd.api import cf_table as lib_table
+    tau, c, w0 = lib_table()
+    x = -np.logspace(-6, 6, 6000)
+    r_lib = r_eval(x, np.array(tau), np.array(c), w0)
+    r_orc = r_eval(x)
+    assert np.max(np.abs(r_lib - r_orc)) < 2e-14
+    # same poles (both are the CF poles; FP64 rounding apart)
+    t_o, c_o, w_o = cf_table()
+    assert np.max(np.abs(np.array(tau) - t_o)) < 1e-12
+
+
+def _sym(n, seed):
+    A = np.random.default_rng(seed).standard_normal((n, n))
+    return A + A.T
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40, 120])
+def test_host_symmetric_eig(n):
+    A = _sym(n, n)
+    w = np.zeros(n)
+    Q = np.zeros((n, n))
+    st = _lib.lib().expmv_host_eig_sym(n, A.ctypes.data, w.ctypes.data, Q.ctypes.data)
+    assert st == 0
+    ref = np.linalg.eigvalsh(A)
+    assert np.max(np.abs(np.sort(w) - ref)) < 1e-12 * max(1.0, np.abs(ref).max())
+    assert np.max(np.abs(Q.T @ Q - np.eye(n))) < 1e-12
+    assert np.max(np.abs(A @ Q - Q * w[None, :])) < 1e-11 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [3, 10, 60])
+def test_host_general_eig(n):
+    A = np.random.default_rng(100 + n).standard_normal((n, n))
+    wr, wi = np.zeros(n), np.zeros(n)
+    Vr, Vi = np.zeros((n, n)), np.zeros((n, n))
+    st = _lib.lib().expmv_host_eig_general(n, A.ctypes.data, wr.ctypes.data, wi.ctypes.data,
+                                           Vr.ctypes.data, Vi.ctypes.data)
+    assert st == 0
+    ev = wr + 1j * wi
+    ref = np.linalg.eigvals(A)
+    # every eigenvalue matched (as a multiset) and every pair exactly conjugate
+    for e in ref:
+        assert np.min(np.abs(ev - e)) < 1e-9 * np.abs(ref).max()
+    for e in ev[np.abs(wi) > 0]:
+        assert np.min(np.abs(ev - np.conj(e))) == 0.0
+    V = Vr + 1j * Vi
+    res = np.abs(A @ V - V * ev[None, :]).max()
+    assert res < 1e-9 * np.abs(ref).max()
