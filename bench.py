@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the solve, copy a 256 MiB buffer 3 times (a plain copy kernel "
+                         "of known size, used to scale HBM byte counters)")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="sample every N-th inner iteration with HIP events (0 = off)")
     return ap.parse_args()
@@ -141,6 +144,13 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": None, "bytes_per_launch": byt[dom],
                 "mean_launch_ms": round(mean[dom], 5), "samples": samples}
+
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:

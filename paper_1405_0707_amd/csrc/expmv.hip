@@ -6,6 +6,7 @@
 // toeplitz.hpp; the host only moves the small projected matrices (H, the
 // pole residuals, the restart rotation) and decides convergence.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <chrono>
@@ -214,13 +215,13 @@ void apply_K(expmv_plan_s* pl, int transpose, const double* X, double* Y, int p)
 // after convergence return at once and are dropped.
 void collect_profile(expmv_plan_s* pl, int kexec) {
   if (pl->pev_used == 0) return;
-  for (int i = 0; i + 4 <= pl->pev_used; i += 4) {
+  for (int i = 0; i + 6 <= pl->pev_used; i += 6) {
     float tc = 0.f, ta = 0.f, tb = 0.f;
-    HIPCHK(hipEventSynchronize(pl->pev[i + 3]));
+    HIPCHK(hipEventSynchronize(pl->pev[i + 5]));
     HIPCHK(hipEventElapsedTime(&tc, pl->pev[i], pl->pev[i + 1]));
-    HIPCHK(hipEventElapsedTime(&ta, pl->pev[i + 1], pl->pev[i + 2]));
-    HIPCHK(hipEventElapsedTime(&tb, pl->pev[i + 2], pl->pev[i + 3]));
-    if (pl->pev_iter[i / 4] < kexec) {
+    HIPCHK(hipEventElapsedTime(&ta, pl->pev[i + 2], pl->pev[i + 3]));
+    HIPCHK(hipEventElapsedTime(&tb, pl->pev[i + 4], pl->pev[i + 5]));
+    if (pl->pev_iter[i / 6] < kexec) {
       pl->prof_ms_a += ta;
       pl->prof_ms_b += tb;
       pl->prof_ms_c += tc;
@@ -260,25 +261,26 @@ InnerResult inner_cg(expmv_plan_s* pl, const double* src, double sign, double* o
       double* pold = P[k & 1];
       double* pnew = P[(k + 1) & 1];
       const bool sample = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0 &&
-                          pl->pev_used + 4 <= int(pl->pev.size());
+                          pl->pev_used + 6 <= int(pl->pev.size());
+      // sampled iterations: the kernels' own start/stop timestamps
       hipEvent_t* e = sample ? &pl->pev[pl->pev_used] : nullptr;
+      hipEvent_t z = nullptr;
       if (sample) {
-        pl->pev_iter[pl->pev_used / 4] = k;
-        pl->pev_used += 4;
-        HIPCHK(hipEventRecord(e[0], s));
+        pl->pev_iter[pl->pev_used / 6] = k;
+        pl->pev_used += 6;
       }
-      DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_c<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                         k, int(n), p, pl->dinv.p, w.cg_r.p, pold, pnew, out,
-                                         w.cgst.p, w.ctl.p, w.part_rr.p, tol2, maxit));
-      if (sample) HIPCHK(hipEventRecord(e[1], s));
-      DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_a<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                         int(n), p, pl->rowptr.p, pl->colind.p, pl->val.p, pnew,
-                                         w.cg_q.p, w.ctl.p, w.part_sig.p));
-      if (sample) HIPCHK(hipEventRecord(e[2], s));
-      DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_b<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                         k, int(n), p, pl->dinv.p, w.cg_r.p, w.cg_q.p, w.cgst.p,
-                                         w.ctl.p, w.part_sig.p, w.part_rr.p));
-      if (sample) HIPCHK(hipEventRecord(e[3], s));
+      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                            sample ? e[0] : z, sample ? e[1] : z, 0, k, int(n), p,
+                                            pl->dinv.p, w.cg_r.p, pold, pnew, out, w.cgst.p,
+                                            w.ctl.p, w.part_rr.p, tol2, maxit));
+      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_a<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                            sample ? e[2] : z, sample ? e[3] : z, 0, int(n), p,
+                                            pl->rowptr.p, pl->colind.p, pl->val.p, pnew, w.cg_q.p,
+                                            w.ctl.p, w.part_sig.p));
+      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_b<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                            sample ? e[4] : z, sample ? e[5] : z, 0, k, int(n), p,
+                                            pl->dinv.p, w.cg_r.p, w.cg_q.p, w.cgst.p, w.ctl.p,
+                                            w.part_sig.p, w.part_rr.p));
     }
     launched += chunk;
     HIPCHK(hipMemcpyAsync(pl->host_flags + 4 * slot, w.ctl.p, sizeof(KrylovCtl),
@@ -731,7 +733,7 @@ void init_plan_common(expmv_plan_s* pl) {
   HIPCHK(hipEventCreateWithFlags(&pl->ev[0], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pl->ev[1], hipEventDisableTiming));
   if (pl->opts.profile > 0) {
-    pl->pev.resize(4 * 128);
+    pl->pev.resize(6 * 128);
     pl->pev_iter.resize(128);
     for (auto& e : pl->pev) HIPCHK(hipEventCreate(&e));
   }

@@ -57,6 +57,41 @@ __device__ inline void block_col_reduce(double v, double* red) {
   }
 }
 
+// Column sums over a workgroup of NT threads (column = tid % PP) using
+// wavefront shuffles and one LDS exchange; the result for column c is left
+// in red[c] (red holds at least NT / 64 * PP doubles).  Fixed order.
+template <int PP, int NT>
+__device__ inline void wave_col_reduce(double v, double* red) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off >= PP; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = tid / 64, lane = tid % 64;
+  if (lane < PP) red[wave * PP + lane] = v;
+  __syncthreads();
+  if (tid < PP) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w * PP + tid];
+    red[NT / 64 * PP + tid] = s;
+  }
+  __syncthreads();
+  if (tid < PP) red[tid] = red[NT / 64 * PP + tid];
+  __syncthreads();
+}
+
+// Rows of workgroup blockIdx.x: one contiguous segment per workgroup, with
+// the segments of the workgroups that run on one XCD adjacent.  Workgroups
+// are handed to the 8 XCDs round-robin, so logical segment
+// (b % 8) * (G / 8) + b / 8 puts each XCD on one contiguous eighth of the
+// rows and keeps stencil neighbours in that XCD's L2.
+__device__ inline void xcd_rows(int64_t n, int64_t& r0, int64_t& r1) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int L = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int64_t per = (n + G - 1) / G;
+  r0 = min<int64_t>(n, int64_t(L) * per);
+  r1 = min<int64_t>(n, r0 + per);
+}
+
 // acc (+)= sum_e val[e] * x[colind[e] * ld + c] over one CSR row, in order,
 // with four independent gathers in flight per step.
 template <typename T>
@@ -132,32 +167,35 @@ template <int PP, int NV>
 __device__ inline void reduce_parts(const double* __restrict__ part, int nwg, double* red,
                                     double* out) {
   constexpr int slots = PP * NV;
-  constexpr int lanes = kCgThreads / slots;   // >= 16
+  constexpr int lanes = (kCgThreads / slots) > 64 ? 64 : kCgThreads / slots;
   const int tid = threadIdx.x;
   const int sidx = tid / lanes, l = tid % lanes;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int w = l;
-  for (; w + 3 * lanes < nwg; w += 4 * lanes) {
-    a0 += part[size_t(w) * slots + sidx];
-    a1 += part[size_t(w + lanes) * slots + sidx];
-    a2 += part[size_t(w + 2 * lanes) * slots + sidx];
-    a3 += part[size_t(w + 3 * lanes) * slots + sidx];
+  double v = 0.0;
+  if (sidx < slots) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int w = l;
+    for (; w + 3 * lanes < nwg; w += 4 * lanes) {
+      a0 += part[size_t(w) * slots + sidx];
+      a1 += part[size_t(w + lanes) * slots + sidx];
+      a2 += part[size_t(w + 2 * lanes) * slots + sidx];
+      a3 += part[size_t(w + 3 * lanes) * slots + sidx];
+    }
+    for (; w < nwg; w += lanes) a0 += part[size_t(w) * slots + sidx];
+    v = (a0 + a1) + (a2 + a3);
   }
-  for (; w < nwg; w += lanes) a0 += part[size_t(w) * slots + sidx];
-  red[tid] = (a0 + a1) + (a2 + a3);
+  // the `lanes` threads of one slot are consecutive and aligned inside one
+  // wavefront: reduce them with shuffles
+#pragma unroll
+  for (int st = lanes / 2; st >= 1; st >>= 1) v += __shfl_xor(v, st, 64);
+  if (l == 0 && sidx < slots) out[sidx] = v;
   __syncthreads();
-  for (int st = lanes / 2; st >= 1; st >>= 1) {
-    if (l < st) red[tid] += red[tid + st];
-    __syncthreads();
-  }
-  if (l == 0) out[sidx] = red[tid];
-  __syncthreads();
+  (void)red;
 }
 
 // per-workgroup column sums of v (PP columns) -> part[wg * stride + off + c]
 template <int PP>
 __device__ inline void write_col_partial(double v, double* red, double* part, int stride, int off) {
-  block_col_reduce<PP, kCgThreads>(v, red);
+  wave_col_reduce<PP, kCgThreads>(v, red);
   if (threadIdx.x < PP) part[size_t(blockIdx.x) * stride + off + threadIdx.x] = red[threadIdx.x];
   __syncthreads();
 }
@@ -170,9 +208,9 @@ k_cg_init(int n, int p, double sign, const double* __restrict__ src, const T* __
   __shared__ double red[kCgThreads];
   const int c = threadIdx.x % PP;
   double rz = 0.0, bb = 0.0;
-  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
-  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
-       row += rows_per_grid) {
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
     if (c < p) {
       const int64_t i = row * p + c;
       const T b = T(sign * src[i]);
@@ -255,9 +293,9 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
   const int c = threadIdx.x % PP;
   const T beta = T(s_beta[c]), aprev = T(s_aprev[c]);
   const bool any = s_any != 0;
-  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
-  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
-       row += rows_per_grid) {
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
     if (c < p) {
       const int64_t i = row * p + c;
       const T po = pold[i];
@@ -276,9 +314,9 @@ k_cg_a(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restri
   __shared__ double red[kCgThreads];
   const int c = threadIdx.x % PP;
   double sig = 0.0;
-  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
-  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
-       row += rows_per_grid) {
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
     if (c < p) {
       const T acc = csr_row_dot(colind, val, pk, rowptr[row], rowptr[row + 1], p, c);
       const int64_t i = row * p + c;
@@ -313,9 +351,9 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
   const int c = threadIdx.x % PP;
   const T alpha = T(s_alpha[c]);
   double rz = 0.0, rr = 0.0;
-  const int64_t rows_per_grid = int64_t(gridDim.x) * (kCgThreads / PP);
-  for (int64_t row = int64_t(blockIdx.x) * (kCgThreads / PP) + threadIdx.x / PP; row < n;
-       row += rows_per_grid) {
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
     if (c < p) {
       const int64_t i = row * p + c;
       const T rn = r[i] - alpha * q[i];
