@@ -72,23 +72,25 @@ static int pow2_lanes(int p) {
   return pp;
 }
 
-// Work arrays that depend on the block width p, kept between calls.
+// Work arrays that depend on the block width p, kept between calls.  The
+// basis, W and the inner solver's vectors hold the working type of the
+// plan (FP64, or FP32 in the mixed form); everything else is FP64.
 struct Workspace {
   int p = 0;
-  DevBuf<double> V[2];          // basis panels, (m+1) * n * p each
-  DevBuf<double> W, Wt;         // n x p
+  DevBuf<char> V[2];            // basis panels, (m+1) * n * p elements each
+  DevBuf<char> W, Wt;           // n x p
+  DevBuf<char> kr, kpa, kpb, kq, kv, ks, kt, krh;   // inner-solver vectors, n x p
   DevBuf<double> X;             // n x 14p
-  DevBuf<double> cg_x, cg_r, cg_pa, cg_pb, cg_q;  // inner solver, n x p
-  DevBuf<double> cg_v, cg_s, cg_t, cg_rt;         // BiCGStab extras
-  DevBuf<double> partial;       // reductions
+  DevBuf<double> partial;       // reductions of the dense kernels
   DevBuf<double> hcoef, gram, R1, R2, Rinv, w0;   // small orth buffers
   DevBuf<double> H;             // ldh x ldh
   DevBuf<double> Rhat;          // p x p
   DevBuf<cplx> G, Zs, Ascr, S;
-  DevBuf<double> Cr, Crot, rho, nrm;
+  DevBuf<double> Cr, Crot, rho;
   DevBuf<int> flags, singular;
   DevBuf<CgState> cgst;
-  DevBuf<double> part_rr, part_sig;   // inner-solver partials, [wg][2][PP] and [wg][PP]
+  DevBuf<BcgState> bcgst;
+  DevBuf<double> part_rr, part_sig;   // inner-solver partials
   DevBuf<KrylovCtl> ctl;
 };
 
@@ -106,6 +108,8 @@ struct expmv_plan_s {
   // K = -tA in CSR (FP64) and its transpose (nonsymmetric only)
   DevBuf<int32_t> rowptr, colind, rowptrT, colindT;
   DevBuf<double> val, valT, dinv, dinvT;
+  DevBuf<float> valf, valTf, dinvf, dinvTf;   // FP32 copies (mixed form)
+  bool mixed = false;
   // CF table on the device
   DevBuf<double> tau_re, tau_im, c_re, c_im;
   Workspace ws;
@@ -147,26 +151,26 @@ void ensure_workspace(expmv_plan_s* pl, int p) {
   const int npan_max = m + 1;
   const int ldh = (m + 1) * p;
   pl->ldh = ldh;
-  const size_t blk = size_t(n) * p;
   if (w.p == p) return;
-  w.V[0].alloc(blk * npan_max);
-  w.V[1].alloc(blk * npan_max);
-  w.W.alloc(blk);
-  w.Wt.alloc(blk);
-  w.X.alloc(blk * 2 * kNShift);
-  w.cg_x.alloc(blk);
-  w.cg_r.alloc(blk);
-  w.cg_pa.alloc(blk);
-  w.cg_pb.alloc(blk);
-  w.cg_q.alloc(blk);
+  const size_t el = pl->mixed ? sizeof(float) : sizeof(double);
+  const size_t blk = size_t(n) * p;
+  w.V[0].alloc(blk * npan_max * el);
+  w.V[1].alloc(blk * npan_max * el);
+  w.W.alloc(blk * el);
+  w.Wt.alloc(blk * el);
+  w.kr.alloc(blk * el);
+  w.kpa.alloc(blk * el);
+  w.kpb.alloc(blk * el);
+  w.kq.alloc(blk * el);
   if (!pl->symmetric) {
-    w.cg_v.alloc(blk);
-    w.cg_s.alloc(blk);
-    w.cg_t.alloc(blk);
-    w.cg_rt.alloc(blk);
+    w.kv.alloc(blk * el);
+    w.ks.alloc(blk * el);
+    w.kt.alloc(blk * el);
+    w.krh.alloc(blk * el);
   }
+  w.X.alloc(blk * 2 * kNShift);
   const size_t O = size_t(npan_max) * p * p + p;
-  w.partial.alloc(std::max<size_t>(O * 256, size_t(1024) * 4 * 32));
+  w.partial.alloc(std::max<size_t>(O * 256, size_t(512) * kNShift));
   w.hcoef.alloc(O);
   w.gram.alloc(size_t(p) * p);
   w.R1.alloc(size_t(p) * p);
@@ -183,36 +187,58 @@ void ensure_workspace(expmv_plan_s* pl, int p) {
   w.Cr.alloc(size_t(ldh) * 2 * kNShift * p);
   w.Crot.alloc(size_t(dmax) * dmax);
   w.rho.alloc(kNShift);
-  w.nrm.alloc(64);
   w.flags.alloc(4);
   w.singular.alloc(kNShift);
   w.cgst.alloc(1);
+  w.bcgst.alloc(1);
   w.part_rr.alloc(size_t(kCgGrid) * 2 * kMaxP);
-  w.part_sig.alloc(size_t(kCgGrid) * kMaxP);
+  w.part_sig.alloc(size_t(kCgGrid) * 2 * kMaxP);
   w.ctl.alloc(1);
   HIPCHK(hipMemsetAsync(w.ctl.p, 0, sizeof(KrylovCtl), pl->stream));
   w.p = p;
 }
 
-// -------------------------------------------------------------------------
-// operator and inner solves
+// ------------------------------------------------------------------------
+// operator data of the working type
 
-// Y = K X (K = -tA, or its transpose) for n x p blocks.
-void apply_K(expmv_plan_s* pl, int transpose, const double* X, double* Y, int p) {
-  hipStream_t s = pl->stream;
+template <typename T>
+struct Csr {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const T* val;
+  const T* dinv;
+};
+
+template <typename T>
+Csr<T> csr_of(expmv_plan_s* pl, int transpose);
+
+template <>
+Csr<double> csr_of<double>(expmv_plan_s* pl, int transpose) {
   const bool tr = transpose && !pl->symmetric;
-  const int32_t* rp = tr ? pl->rowptrT.p : pl->rowptr.p;
-  const int32_t* ci = tr ? pl->colindT.p : pl->colind.p;
-  const double* v = tr ? pl->valT.p : pl->val.p;
-  const int PP = pow2_lanes(p);
-  const int grid = grid_for(pl->n, PP, 4096);
-  DISPATCH_PP(PP, hipLaunchKernelGGL((k_spmm<double, P_>), dim3(grid), dim3(kThreads), 0, s,
-                                     int(pl->n), p, rp, ci, v, X, Y));
+  return tr ? Csr<double>{pl->rowptrT.p, pl->colindT.p, pl->valT.p, pl->dinvT.p}
+            : Csr<double>{pl->rowptr.p, pl->colind.p, pl->val.p, pl->dinv.p};
 }
 
-// Read the sampled event pairs of the inner solver.  Only iterations the
-// solve actually ran count (kexec = iterations executed); the ones issued
-// after convergence return at once and are dropped.
+template <>
+Csr<float> csr_of<float>(expmv_plan_s* pl, int transpose) {
+  const bool tr = transpose && !pl->symmetric;
+  return tr ? Csr<float>{pl->rowptrT.p, pl->colindT.p, pl->valTf.p, pl->dinvTf.p}
+            : Csr<float>{pl->rowptr.p, pl->colind.p, pl->valf.p, pl->dinvf.p};
+}
+
+// Y = K X (K = -tA, or its transpose) for n x p blocks of type T.
+template <typename T>
+void apply_K(expmv_plan_s* pl, int transpose, const T* X, T* Y, int p) {
+  Csr<T> A = csr_of<T>(pl, transpose);
+  const int PP = pow2_lanes(p);
+  const int grid = grid_for(pl->n, PP, 4096);
+  DISPATCH_PP(PP, hipLaunchKernelGGL((k_spmm<T, P_>), dim3(grid), dim3(kThreads), 0, pl->stream,
+                                     int(pl->n), p, A.rowptr, A.colind, A.val, X, Y));
+}
+
+// Read the sampled start/stop events of the inner solver (three kernels per
+// sampled iteration).  Only iterations the solve actually ran count (kexec
+// = iterations executed); the ones issued after convergence return at once.
 void collect_profile(expmv_plan_s* pl, int kexec) {
   if (pl->pev_used == 0) return;
   for (int i = 0; i + 6 <= pl->pev_used; i += 6) {
@@ -236,52 +262,28 @@ struct InnerResult {
   int hit_cap;
 };
 
-// out = K^{-1} (sign * src) by batched Jacobi-PCG (K SPD); out is the
-// iterate x itself.
-InnerResult inner_cg(expmv_plan_s* pl, const double* src, double sign, double* out, int p) {
+int cg_grid(int64_t n, int PP) {
+  return int(std::max<int64_t>(
+      1, std::min<int64_t>(kCgGrid, (n * PP + kCgThreads - 1) / kCgThreads)));
+}
+
+double inner_tol_of(expmv_plan_s* pl) {
+  if (pl->opts.inner_tol > 0.0) return pl->opts.inner_tol;
+  return pl->mixed ? 1e-6 : 1e-12;
+}
+
+// Poll the inner solver's control word every `chunk` iterations, one chunk
+// ahead of the device; returns when a chunk has seen every column stop.
+template <typename LaunchChunk>
+InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chunk) {
   Workspace& w = pl->ws;
   hipStream_t s = pl->stream;
-  const int64_t n = pl->n;
-  const int PP = pow2_lanes(p);
-  const int grid = int(std::max<int64_t>(1, std::min<int64_t>(kCgGrid, (n * PP + kCgThreads - 1) / kCgThreads)));
-  double tol = pl->opts.inner_tol > 0.0 ? pl->opts.inner_tol : 1e-12;
-  const double tol2 = tol * tol;
-  const int maxit = pl->opts.inner_maxit;
-  double* P[2] = {w.cg_pa.p, w.cg_pb.p};
-  DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_init<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                     int(n), p, sign, src, pl->dinv.p, out, w.cg_r.p, P[0],
-                                     w.ctl.p, w.part_rr.p));
   const int chunk = 16;
   int launched = 0;
   int pending = -1, slot = 0;
   bool done = false;
   while (!done) {
-    for (int it = 0; it < chunk; ++it) {
-      const int k = launched + it;  // 0-based iteration index
-      double* pold = P[k & 1];
-      double* pnew = P[(k + 1) & 1];
-      const bool sample = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0 &&
-                          pl->pev_used + 6 <= int(pl->pev.size());
-      // sampled iterations: the kernels' own start/stop timestamps
-      hipEvent_t* e = sample ? &pl->pev[pl->pev_used] : nullptr;
-      hipEvent_t z = nullptr;
-      if (sample) {
-        pl->pev_iter[pl->pev_used / 6] = k;
-        pl->pev_used += 6;
-      }
-      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[0] : z, sample ? e[1] : z, 0, k, int(n), p,
-                                            pl->dinv.p, w.cg_r.p, pold, pnew, out, w.cgst.p,
-                                            w.ctl.p, w.part_rr.p, tol2, maxit));
-      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_a<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[2] : z, sample ? e[3] : z, 0, int(n), p,
-                                            pl->rowptr.p, pl->colind.p, pl->val.p, pnew, w.cg_q.p,
-                                            w.ctl.p, w.part_sig.p));
-      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_b<double, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[4] : z, sample ? e[5] : z, 0, k, int(n), p,
-                                            pl->dinv.p, w.cg_r.p, w.cg_q.p, w.cgst.p, w.ctl.p,
-                                            w.part_sig.p, w.part_rr.p));
-    }
+    launch_chunk(launched, chunk);
     launched += chunk;
     HIPCHK(hipMemcpyAsync(pl->host_flags + 4 * slot, w.ctl.p, sizeof(KrylovCtl),
                           hipMemcpyDeviceToHost, s));
@@ -297,24 +299,111 @@ InnerResult inner_cg(expmv_plan_s* pl, const double* src, double sign, double* o
   }
   HIPCHK(hipEventSynchronize(pl->ev[pending]));
   const KrylovCtl* c = reinterpret_cast<const KrylovCtl*>(pl->host_flags + 4 * pending);
-  const int kexec = c->iters_max;
-  collect_profile(pl, kexec);
-  return {kexec, c->hit_cap};
+  return {c->iters_max, c->hit_cap};
+}
+
+// out = K^{-1} (sign * src) by batched Jacobi-PCG (K SPD); out is the iterate.
+template <typename T>
+InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p) {
+  Workspace& w = pl->ws;
+  hipStream_t s = pl->stream;
+  const int64_t n = pl->n;
+  const int PP = pow2_lanes(p);
+  const int grid = cg_grid(n, PP);
+  const double tol = inner_tol_of(pl);
+  const double tol2 = tol * tol;
+  const int maxit = pl->opts.inner_maxit;
+  Csr<T> A = csr_of<T>(pl, 0);
+  T* r = reinterpret_cast<T*>(w.kr.p);
+  T* q = reinterpret_cast<T*>(w.kq.p);
+  T* P[2] = {reinterpret_cast<T*>(w.kpa.p), reinterpret_cast<T*>(w.kpb.p)};
+  DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                     int(n), p, sign, src, A.dinv, out, r, P[0], w.ctl.p,
+                                     w.part_rr.p));
+  InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
+    for (int it = 0; it < chunk; ++it) {
+      const int k = launched + it;
+      T* pold = P[k & 1];
+      T* pnew = P[(k + 1) & 1];
+      const bool sample = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0 &&
+                          pl->pev_used + 6 <= int(pl->pev.size());
+      hipEvent_t* e = sample ? &pl->pev[pl->pev_used] : nullptr;
+      hipEvent_t z = nullptr;
+      if (sample) {
+        pl->pev_iter[pl->pev_used / 6] = k;
+        pl->pev_used += 6;
+      }
+      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                            sample ? e[0] : z, sample ? e[1] : z, 0, k, int(n), p,
+                                            A.dinv, r, pold, pnew, out, w.cgst.p, w.ctl.p,
+                                            w.part_rr.p, tol2, maxit));
+      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_a<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                            sample ? e[2] : z, sample ? e[3] : z, 0, int(n), p,
+                                            A.rowptr, A.colind, A.val, pnew, q, w.ctl.p,
+                                            w.part_sig.p));
+      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_b<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                            sample ? e[4] : z, sample ? e[5] : z, 0, k, int(n), p,
+                                            A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
+                                            w.part_rr.p));
+    }
+  });
+  collect_profile(pl, res.iters);
+  return res;
+}
+
+// out = K^{-1} (sign * src) (or K^{-T}) by batched BiCGStab with right
+// Jacobi preconditioning (K nonsymmetric).
+template <typename T>
+InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double sign, T* out,
+                           int p) {
+  Workspace& w = pl->ws;
+  hipStream_t s = pl->stream;
+  const int64_t n = pl->n;
+  const int PP = pow2_lanes(p);
+  const int grid = cg_grid(n, PP);
+  const double tol = inner_tol_of(pl);
+  const double tol2 = tol * tol;
+  const int maxit = pl->opts.inner_maxit;
+  Csr<T> A = csr_of<T>(pl, transpose);
+  T* r = reinterpret_cast<T*>(w.kr.p);
+  T* pv = reinterpret_cast<T*>(w.kpa.p);
+  T* v = reinterpret_cast<T*>(w.kv.p);
+  T* sv = reinterpret_cast<T*>(w.ks.p);
+  T* tv = reinterpret_cast<T*>(w.kt.p);
+  T* rh = reinterpret_cast<T*>(w.krh.p);
+  DISPATCH_PP(PP, hipLaunchKernelGGL((k_bcg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+                                     int(n), p, sign, src, out, r, rh, pv, v, w.ctl.p,
+                                     w.part_rr.p));
+  InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
+    for (int it = 0; it < chunk; ++it) {
+      const int i = launched + it;
+      DISPATCH_PP(PP, {
+        hipLaunchKernelGGL((k_bcg_u1<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
+                           r, pv, v, w.bcgst.p, w.ctl.p, w.part_rr.p, tol2, maxit);
+        hipLaunchKernelGGL((k_bcg_s<T, P_, 1>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p,
+                           A.rowptr, A.colind, A.val, A.dinv, pv, rh, v, w.ctl.p, w.part_sig.p);
+        hipLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p, r,
+                           v, sv, w.bcgst.p, w.ctl.p, w.part_sig.p);
+        hipLaunchKernelGGL((k_bcg_s<T, P_, 2>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p,
+                           A.rowptr, A.colind, A.val, A.dinv, sv, sv, tv, w.ctl.p, w.part_sig.p);
+        hipLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p,
+                           A.dinv, pv, sv, tv, rh, out, r, w.bcgst.p, w.ctl.p, w.part_sig.p,
+                           w.part_rr.p);
+      });
+    }
+  });
+  return res;
 }
 
 // W ~= M^{-1} V = -(K^{-1} V), M = tA.
-InnerResult apply_inverse(expmv_plan_s* pl, int transpose, const double* V, double* Wout, int p) {
-  (void)transpose;
-  if (!pl->symmetric) throw StatusError{EXPMV_EINVAL};
-  return inner_cg(pl, V, -1.0, Wout, p);
+template <typename T>
+InnerResult apply_inverse(expmv_plan_s* pl, int transpose, const T* V, T* Wout, int p) {
+  if (pl->symmetric) return inner_cg<T>(pl, V, -1.0, Wout, p);
+  return inner_bicgstab<T>(pl, transpose, V, -1.0, Wout, p);
 }
 
 // -------------------------------------------------------------------------
-// block Gram-Schmidt (two passes) + CholQR2 of W against npan panels of Vb;
-// writes the new orthonormal block to Vout, H(0:npan*p, col0:col0+p) +=
-// the projection coefficients and H(npan*p.., col0..) = R (if H given).
-// With npan == 0 it is the plain CholQR2 of W (the initial block: R -> Rhat).
-
+// block Gram-Schmidt (two passes) + CholQR2
 
 struct OrthLaunch {
   int TR;
@@ -342,18 +431,19 @@ OrthLaunch orth_config(int64_t n, int p, int npan, int O, size_t elem) {
 
 // One streaming pass; returns the number of workgroups whose partials are
 // in ws.partial (0 when the mode writes no partials).
-int orth_pass(expmv_plan_s* pl, int mode, int p, const double* V, int npan, const double* Win,
-              double* Wout, const double* C) {
+template <typename T>
+int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* Win, T* Wout,
+              const double* C) {
   const bool proj = (mode == kProj || mode == kUpdProj);
   const bool gram = (mode == kUpdGram || mode == kScaleGram);
   const bool use_v = (mode == kProj || mode == kUpdProj || mode == kUpdGram);
   const int npv = use_v ? npan : 0;
   const int O = proj ? npv * p * p + (mode == kProj ? p : 0) : (gram ? p * p : 0);
-  OrthLaunch L = orth_config(pl->n, p, npv, O, sizeof(double));
-  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth<double>),
+  OrthLaunch L = orth_config(pl->n, p, npv, O, sizeof(T));
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth<T>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)));
-  hipLaunchKernelGGL(k_orth<double>, dim3(L.nwg), dim3(kThreads), L.lds, pl->stream, mode, pl->n,
-                     p, V, npv, Win, Wout, C, pl->ws.partial.p, L.TR, L.rows_per_wg);
+  hipLaunchKernelGGL(k_orth<T>, dim3(L.nwg), dim3(kThreads), L.lds, pl->stream, mode, pl->n, p, V,
+                     npv, Win, Wout, C, pl->ws.partial.p, L.TR, L.rows_per_wg);
   return (proj || gram) ? L.nwg : 0;
 }
 
@@ -369,33 +459,31 @@ void reduce_partials(expmv_plan_s* pl, int nwg, int O, double* out, double* H, i
 //   H != nullptr: H(0:npan*p, col0:col0+p) += coefficients of both passes,
 //                 H(npan*p:npan*p+p, col0:col0+p) = R2 R1.
 //   H == nullptr: Rhat (p x p) = R2 R1 (initial block, npan = 0).
-void orthonormalize(expmv_plan_s* pl, int p, const double* Vb, int npan, double* W, double* Vout,
-                    double* H, int ldh, int col0, double* Rhat) {
+// Projections, Gram matrices and R are FP64 for either working type.
+template <typename T>
+void orthonormalize(expmv_plan_s* pl, int p, const T* Vb, int npan, T* W, T* Vout, double* H,
+                    int ldh, int col0, double* Rhat) {
   Workspace& w = pl->ws;
   hipStream_t s = pl->stream;
   const int Oc = npan * p * p;
-  double* Wt = w.Wt.p;
-  const double* cur = W;
+  T* Wt = reinterpret_cast<T*>(w.Wt.p);
   if (npan > 0) {
-    int nwg = orth_pass(pl, kProj, p, Vb, npan, W, nullptr, nullptr);
+    int nwg = orth_pass<T>(pl, kProj, p, Vb, npan, W, nullptr, nullptr);
+    // coefficients of pass 1, then ||W(:,b)||^2 in hcoef[Oc..Oc+p)
     reduce_partials(pl, nwg, Oc + p, w.hcoef.p, H, ldh, col0, p, Oc);
-    // w0 (||W(:,b)||^2) sits right after the coefficients in hcoef
-    nwg = orth_pass(pl, kUpdProj, p, Vb, npan, W, Wt, w.hcoef.p);
-    // the update above consumed hcoef; its partials hold V^T W1
+    nwg = orth_pass<T>(pl, kUpdProj, p, Vb, npan, W, Wt, w.hcoef.p);
     reduce_partials(pl, nwg, Oc, w.w0.p + p, H, ldh, col0, p, Oc);
     HIPCHK(hipMemcpyAsync(w.w0.p, w.hcoef.p + Oc, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
-    nwg = orth_pass(pl, kUpdGram, p, Vb, npan, Wt, Wt, w.w0.p + p);
+    nwg = orth_pass<T>(pl, kUpdGram, p, Vb, npan, Wt, Wt, w.w0.p + p);
     reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
-    cur = Wt;
   } else {
-    int nwg = orth_pass(pl, kUpdGram, p, nullptr, 0, W, Wt, nullptr);
+    int nwg = orth_pass<T>(pl, kUpdGram, p, static_cast<const T*>(nullptr), 0, W, Wt, nullptr);
     reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
-    cur = Wt;
   }
   hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R1.p, w.Rinv.p,
                      npan > 0 ? w.w0.p : nullptr, npan > 0 ? 1 : 0, nullptr, nullptr, 0, 0, 0,
                      w.flags.p);
-  int nwg = orth_pass(pl, kScaleGram, p, nullptr, 0, cur, Wt, w.Rinv.p);
+  int nwg = orth_pass<T>(pl, kScaleGram, p, static_cast<const T*>(nullptr), 0, Wt, Wt, w.Rinv.p);
   reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
   if (H != nullptr) {
     hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
@@ -404,14 +492,17 @@ void orthonormalize(expmv_plan_s* pl, int p, const double* Vb, int npan, double*
     hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
                        nullptr, 2, w.R1.p, Rhat, p, 0, 0, w.flags.p);
   }
-  orth_pass(pl, kScale, p, nullptr, 0, Wt, Vout, w.Rinv.p);
+  orth_pass<T>(pl, kScale, p, static_cast<const T*>(nullptr), 0, Wt, Vout, w.Rinv.p);
 }
 
-void panel_gemm(expmv_plan_s* pl, int p, const double* V, int npan, const double* C, int ldc,
-                int nchunks, double* out, int64_t chunk_stride, int64_t ldo, int accumulate) {
+template <typename T, typename TO>
+void panel_gemm(expmv_plan_s* pl, int p, const T* V, int npan, const double* C, int ldc,
+                int nchunks, TO* out, int64_t chunk_stride, int64_t ldo, int accumulate) {
   const int np_cols = npan * p;
   int TR = 32;
-  auto lds_for = [&](int tr) { return size_t(np_cols) * p * 8 + size_t(tr) * np_cols * 8; };
+  auto lds_for = [&](int tr) {
+    return size_t(np_cols) * p * 8 + size_t(tr) * np_cols * sizeof(T);
+  };
   while (TR > 1 && lds_for(TR) > 150 * 1024) TR /= 2;
   const int64_t n = pl->n;
   const int64_t tiles = (n + TR - 1) / TR;
@@ -419,11 +510,10 @@ void panel_gemm(expmv_plan_s* pl, int p, const double* V, int npan, const double
   const int64_t rows_per_wg = ((tiles + nwg - 1) / nwg) * TR;
   const int grid = int((n + rows_per_wg - 1) / rows_per_wg);
   const size_t lds = lds_for(TR);
-  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel_gemm<double, double>),
+  HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_panel_gemm<T, TO>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  hipLaunchKernelGGL((k_panel_gemm<double, double>), dim3(grid, nchunks), dim3(kThreads), lds,
-                     pl->stream, n, p, V, npan, C, ldc, out, chunk_stride, ldo, accumulate, TR,
-                     rows_per_wg);
+  hipLaunchKernelGGL((k_panel_gemm<T, TO>), dim3(grid, nchunks), dim3(kThreads), lds, pl->stream, n,
+                     p, V, npan, C, ldc, out, chunk_stride, ldo, accumulate, TR, rows_per_wg);
 }
 
 double host_now_ms() {
@@ -433,13 +523,107 @@ double host_now_ms() {
 }
 
 // -------------------------------------------------------------------------
-// the method
+// restart step on the host (Algorithm 1, Steps 5-8)
 
-struct CycleState {
-  int d;      // projected dimension
-  int keff;   // Ritz vectors at the front of the basis
+// Modified Gram-Schmidt (twice) on the columns of P (d x k row-major).
+// Returns the number of independent columns kept (dependent ones dropped).
+int host_orthonormalize_columns(int d, int k, std::vector<double>& P) {
+  int kept = 0;
+  std::vector<double> out(size_t(d) * k, 0.0);
+  for (int c = 0; c < k; ++c) {
+    std::vector<double> v(d);
+    for (int i = 0; i < d; ++i) v[i] = P[size_t(i) * k + c];
+    double n0 = 0.0;
+    for (double x : v) n0 += x * x;
+    n0 = std::sqrt(n0);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int q = 0; q < kept; ++q) {
+        double h = 0.0;
+        for (int i = 0; i < d; ++i) h += out[size_t(i) * k + q] * v[i];
+        for (int i = 0; i < d; ++i) v[i] -= h * out[size_t(i) * k + q];
+      }
+    double nv = 0.0;
+    for (double x : v) nv += x * x;
+    nv = std::sqrt(nv);
+    if (!(nv > 1e-10 * n0)) continue;
+    for (int i = 0; i < d; ++i) out[size_t(i) * k + kept] = v[i] / nv;
+    ++kept;
+  }
+  P = out;
+  return kept;
+}
+
+struct RitzBasis {
+  std::vector<double> Pk;   // dlive x keff, row-major, orthonormal columns
+  int keff = 0;
 };
 
+// The k wanted Ritz vectors of Hd (dlive x dlive): largest |theta| for
+// Algorithm 2 (Remark 4.1), smallest for Algorithm 1; a complex pair is kept
+// whole (real and imaginary parts), so keff may be k + 1.
+RitzBasis ritz_basis(bool symmetric, bool precond, int dl, const std::vector<double>& Hd, int k) {
+  RitzBasis rb;
+  std::vector<int> ord(dl);
+  std::iota(ord.begin(), ord.end(), 0);
+  if (symmetric) {
+    std::vector<double> wv(dl), Q(size_t(dl) * dl);
+    sym_eig(dl, Hd.data(), wv.data(), Q.data());
+    auto key = [&](int a) { return std::fabs(wv[a]); };
+    if (precond) std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) > key(b); });
+    else std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
+    rb.keff = std::min(k, dl);
+    rb.Pk.assign(size_t(dl) * rb.keff, 0.0);
+    for (int c = 0; c < rb.keff; ++c)
+      for (int i = 0; i < dl; ++i) rb.Pk[size_t(i) * rb.keff + c] = Q[size_t(i) * dl + ord[c]];
+    return rb;
+  }
+  std::vector<double> wr(dl), wi(dl), Vr(size_t(dl) * dl), Vi(size_t(dl) * dl);
+  if (!general_eig(dl, Hd.data(), wr.data(), wi.data(), Vr.data(), Vi.data()))
+    throw StatusError{EXPMV_EBREAKDOWN};
+  auto mag = [&](int a) { return std::hypot(wr[a], wi[a]); };
+  if (precond) std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return mag(a) > mag(b); });
+  else std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return mag(a) < mag(b); });
+  std::vector<char> taken(dl, 0);
+  std::vector<std::vector<double>> cols;
+  int chosen = 0;
+  for (int idx : ord) {
+    if (chosen >= k) break;
+    if (taken[idx]) continue;
+    taken[idx] = 1;
+    std::vector<double> re(dl), im(dl);
+    for (int i = 0; i < dl; ++i) {
+      re[i] = Vr[size_t(i) * dl + idx];
+      im[i] = Vi[size_t(i) * dl + idx];
+    }
+    cols.push_back(re);
+    ++chosen;
+    if (wi[idx] != 0.0) {
+      // the conjugate partner: exact pair from general_eig
+      for (int j = 0; j < dl; ++j)
+        if (!taken[j] && wr[j] == wr[idx] && wi[j] == -wi[idx]) {
+          taken[j] = 1;
+          break;
+        }
+      cols.push_back(im);
+      ++chosen;
+    }
+  }
+  const int kk = int(cols.size());
+  std::vector<double> P(size_t(dl) * kk);
+  for (int c = 0; c < kk; ++c)
+    for (int i = 0; i < dl; ++i) P[size_t(i) * kk + c] = cols[c][i];
+  const int kept = host_orthonormalize_columns(dl, kk, P);
+  rb.keff = kept;
+  rb.Pk.assign(size_t(dl) * kept, 0.0);
+  for (int i = 0; i < dl; ++i)
+    for (int c = 0; c < kept; ++c) rb.Pk[size_t(i) * kept + c] = P[size_t(i) * kk + c];
+  return rb;
+}
+
+// -------------------------------------------------------------------------
+// the method
+
+template <typename T>
 expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
                           double* Z, expmv_info* info) {
   hipStream_t s = pl->stream;
@@ -449,42 +633,37 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   const int m = pl->opts.m;
   const int ldh = pl->ldh;
   const int kk_opt = pl->opts.k > 0 ? pl->opts.k : p * (m / 3);
-  const int k = std::max(p, std::min(kk_opt, (m - 1) * p) / p * p);
+  const int k = std::max(p, std::min(kk_opt, (m - 2) * p) / p * p);
   const bool precond = pl->opts.preconditioned != 0;
   const size_t blk = size_t(n) * p;
   const int ldx = 2 * kNShift * p;
   const double t_start = host_now_ms();
   expmv_info inf{};
   double ms_apply = 0, ms_orth = 0, ms_small = 0, ms_update = 0;
-
-  // CF table on the host
-  double tau_re[kNShift], tau_im[kNShift], c_re[kNShift], c_im[kNShift];
-  for (int j = 0; j < kNShift; ++j) {
-    tau_re[j] = CF_TAU_RE[j];
-    tau_im[j] = CF_TAU_IM[j];
-    c_re[j] = CF_C_RE[j];
-    c_im[j] = CF_C_IM[j];
-  }
-  double delta[kNShift];
-  for (int j = 0; j < kNShift; ++j)
-    delta[j] = tau_re[j] >= 0.0 ? std::hypot(tau_re[j], tau_im[j]) : std::fabs(tau_im[j]);
-
   pl->prof_ms_a = pl->prof_ms_b = pl->prof_ms_c = 0.0;
   pl->prof_samples = 0;
   pl->pev_used = 0;
-  HIPCHK(hipMemsetAsync(w.X.p, 0, sizeof(double) * blk * ldx / p, s));
+
+  double c_re[kNShift], c_im[kNShift], delta[kNShift];
+  for (int j = 0; j < kNShift; ++j) {
+    c_re[j] = CF_C_RE[j];
+    c_im[j] = CF_C_IM[j];
+    delta[j] = CF_TAU_RE[j] >= 0.0 ? std::hypot(CF_TAU_RE[j], CF_TAU_IM[j]) : std::fabs(CF_TAU_IM[j]);
+  }
+
+  HIPCHK(hipMemsetAsync(w.X.p, 0, sizeof(double) * size_t(n) * ldx, s));
   HIPCHK(hipMemsetAsync(w.H.p, 0, sizeof(double) * size_t(ldh) * ldh, s));
   HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int) * 4, s));
   HIPCHK(hipMemsetAsync(w.singular.p, 0, sizeof(int) * kNShift, s));
 
-  // ||B||_F
+  const int cgrid = 512;
+  std::vector<double> part(cgrid);
+  // ||B||_F (k_combine with X = 0 and omega0 = 1 writes B to Z and its norm)
+  hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, 1.0, pl->c_re.p,
+                     pl->c_im.p, Z, w.partial.p);
+  HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   {
-    const int grid = 512;
-    hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kThreads), 0, s, n, p, B, w.X.p, 1.0,
-                       pl->c_re.p, pl->c_im.p, w.W.p, w.partial.p);
-    std::vector<double> part(grid);
-    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * grid, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
     double bb = 0.0;
     for (double v : part) bb += v;
     inf.bnorm = std::sqrt(bb);
@@ -495,16 +674,20 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   }
 
   int cur = 0;
-  double* Vb = w.V[cur].p;
+  T* Vb = reinterpret_cast<T*>(w.V[cur].p);
+  T* Wk = reinterpret_cast<T*>(w.W.p);
   // Steps 1-2: V_1 R^ = B
-  HIPCHK(hipMemcpyAsync(w.W.p, B, sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
-  orthonormalize(pl, p, nullptr, 0, w.W.p, Vb, nullptr, 0, 0, w.Rhat.p);
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(512), dim3(kThreads), 0, s, int64_t(blk), B, Wk,
+                     1.0);
+  orthonormalize<T>(pl, p, nullptr, 0, Wk, Vb, nullptr, 0, 0, w.Rhat.p);
 
-  CycleState cs{m * p, 0};
-  int first_block = 0;   // first panel to expand in this cycle
+  int d = m * p;          // projected dimension (padded coordinates)
+  int kp = 0;             // columns taken by the Ritz block (k_eff rounded up to p)
+  int keff = 0;           // live Ritz vectors
+  int first_block = 0;    // first panel to expand in this cycle
   expmv_status status = EXPMV_OK;
   std::vector<double> Hh(size_t(ldh) * ldh);
-  std::vector<double> rho(kNShift), part(1024);
+  std::vector<double> rho(kNShift);
   bool rhs_from_S = false;
   int cycle = 0;
   for (;;) {
@@ -512,30 +695,28 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     // Step 3 / Step 9: block Arnoldi on the operator from panel first_block
     for (int jb = first_block; jb < m; ++jb) {
       double t0 = host_now_ms();
-      const double* Vj = Vb + size_t(jb) * blk;
+      const T* Vj = Vb + size_t(jb) * blk;
       if (precond) {
-        InnerResult r = apply_inverse(pl, transpose, Vj, w.W.p, p);
+        InnerResult r = apply_inverse<T>(pl, transpose, Vj, Wk, p);
         inf.inner_iters += r.iters;
         inf.inner_maxit_hit += r.hit_cap;
       } else {
-        apply_K(pl, transpose, Vj, w.W.p, p);
+        apply_K<T>(pl, transpose, Vj, Wk, p);
         // M V = -K V
-        hipLaunchKernelGGL((k_convert<double, double>), dim3(512), dim3(kThreads), 0, s,
-                           int64_t(blk), w.W.p, w.W.p, -1.0);
+        hipLaunchKernelGGL((k_convert<T, T>), dim3(512), dim3(kThreads), 0, s, int64_t(blk), Wk, Wk,
+                           -1.0);
       }
       inf.block_apps += 1;
       double t1 = host_now_ms();
       ms_apply += t1 - t0;
-      orthonormalize(pl, p, Vb, jb + 1, w.W.p, Vb + size_t(jb + 1) * blk, w.H.p, ldh, jb * p,
-                     nullptr);
+      orthonormalize<T>(pl, p, Vb, jb + 1, Wk, Vb + size_t(jb + 1) * blk, w.H.p, ldh, jb * p,
+                        nullptr);
       ms_orth += host_now_ms() - t1;
     }
     double t0 = host_now_ms();
-    const int d = cs.d;
-    // right-hand sides of the projected systems
     {
       dim3 g(std::max(1, (d * p + kThreads - 1) / kThreads), kNShift);
-      hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, d, p, rhs_from_S ? cs.keff : 0,
+      hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, d, p, rhs_from_S ? kp : 0,
                          rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
     }
     // Step 4: projected shifted systems, residual estimates, update coefficients
@@ -544,9 +725,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
                        w.rho.p, w.singular.p);
     double t1 = host_now_ms();
     // X_j += V_{d+p} (H~ Z_j)  [Algorithm 1: V_d Z_j]
-    panel_gemm(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * kNShift, w.X.p, p, ldx, 1);
-    // Z~ and ||Z~||
-    const int cgrid = 512;
+    panel_gemm<T, double>(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * kNShift, w.X.p, p, ldx, 1);
     hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p,
                        double(CF_OMEGA0), pl->c_re.p, pl->c_im.p, Z, w.partial.p);
     HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost, s));
@@ -590,73 +769,74 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       status = EXPMV_ENOCONV;
       break;
     }
-    // Steps 5-8: deflated restart (host eigensolve of H_d)
+    // Steps 5-8: deflated restart (host eigensolve of the live part of H_d)
     double t3 = host_now_ms();
     HIPCHK(hipMemcpyAsync(Hh.data(), w.H.p, sizeof(double) * size_t(ldh) * ldh,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<double> Hd(size_t(d) * d);
+    // live padded coordinates: everything but the padding after the Ritz block
+    std::vector<int> live;
     for (int i = 0; i < d; ++i)
-      for (int j = 0; j < d; ++j) Hd[size_t(i) * d + j] = Hh[size_t(i) * ldh + j];
-    std::vector<double> Pk;   // d x keff, row-major
-    int keff = 0;
-    if (pl->symmetric) {
-      std::vector<double> wv(d), Q(size_t(d) * d);
-      sym_eig(d, Hd.data(), wv.data(), Q.data());
-      std::vector<int> ord(d);
-      std::iota(ord.begin(), ord.end(), 0);
-      if (precond)
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(wv[a]) > std::fabs(wv[b]); });
-      else
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return std::fabs(wv[a]) < std::fabs(wv[b]); });
-      keff = k;
-      Pk.assign(size_t(d) * keff, 0.0);
-      for (int c = 0; c < keff; ++c)
-        for (int i = 0; i < d; ++i) Pk[size_t(i) * keff + c] = Q[size_t(i) * d + ord[c]];
-    } else {
-      status = EXPMV_EINVAL;
+      if (!(i >= keff && i < kp)) live.push_back(i);
+    const int dl = int(live.size());
+    std::vector<double> Hd(size_t(dl) * dl);
+    for (int i = 0; i < dl; ++i)
+      for (int j = 0; j < dl; ++j) Hd[size_t(i) * dl + j] = Hh[size_t(live[i]) * ldh + live[j]];
+    RitzBasis rb = ritz_basis(pl->symmetric, precond, dl, Hd, k);
+    const int kn = rb.keff;
+    const int kpn = (kn + p - 1) / p * p;
+    if (kn < 1 || kpn / p + 1 > m) {
+      status = EXPMV_EBREAKDOWN;
       break;
     }
-    // H~_new = P_{k+p}^T H~ P_k  ((keff + p) x keff)
-    std::vector<double> HP(size_t(d + p) * keff, 0.0);
+    // P_k in padded coordinates: d x kpn (zero rows at padding, zero columns
+    // after kn)
+    std::vector<double> Pk(size_t(d) * kpn, 0.0);
+    for (int i = 0; i < dl; ++i)
+      for (int c = 0; c < kn; ++c) Pk[size_t(live[i]) * kpn + c] = rb.Pk[size_t(i) * kn + c];
+    // H~_new = P_{k+p}^T H~ P_k: top kn x kn block and the p rows below
+    std::vector<double> HP(size_t(d + p) * kn, 0.0);
     for (int i = 0; i < d + p; ++i)
-      for (int c = 0; c < keff; ++c) {
-        double sacc = 0.0;
-        for (int j = 0; j < d; ++j) sacc += Hh[size_t(i) * ldh + j] * Pk[size_t(j) * keff + c];
-        HP[size_t(i) * keff + c] = sacc;
+      for (int c = 0; c < kn; ++c) {
+        double acc = 0.0;
+        for (int j = 0; j < d; ++j) acc += Hh[size_t(i) * ldh + j] * Pk[size_t(j) * kpn + c];
+        HP[size_t(i) * kn + c] = acc;
       }
     std::fill(Hh.begin(), Hh.end(), 0.0);
-    for (int r = 0; r < keff; ++r)
-      for (int c = 0; c < keff; ++c) {
-        double sacc = 0.0;
-        for (int i = 0; i < d; ++i) sacc += Pk[size_t(i) * keff + r] * HP[size_t(i) * keff + c];
-        Hh[size_t(r) * ldh + c] = sacc;
+    for (int r = 0; r < kn; ++r)
+      for (int c = 0; c < kn; ++c) {
+        double acc = 0.0;
+        for (int i = 0; i < d; ++i) acc += Pk[size_t(i) * kpn + r] * HP[size_t(i) * kn + c];
+        Hh[size_t(r) * ldh + c] = acc;
       }
     for (int r = 0; r < p; ++r)
-      for (int c = 0; c < keff; ++c) Hh[size_t(keff + r) * ldh + c] = HP[size_t(d + r) * keff + c];
+      for (int c = 0; c < kn; ++c) Hh[size_t(kpn + r) * ldh + c] = HP[size_t(d + r) * kn + c];
     HIPCHK(hipMemcpyAsync(w.Crot.p, Pk.data(), sizeof(double) * Pk.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(w.H.p, Hh.data(), sizeof(double) * Hh.size(), hipMemcpyHostToDevice, s));
-    // V_new = V_{d+p} P_{k+p}: Ritz block by a panel GEMM, then the last panel
-    double* Vn = w.V[cur ^ 1].p;
-    panel_gemm(pl, p, Vb, d / p, w.Crot.p, keff, keff / p, Vn, int64_t(blk), p, 0);
-    HIPCHK(hipMemcpyAsync(Vn + size_t(keff / p) * blk, Vb + size_t(d / p) * blk,
-                          sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
+    // V_new = V_{d+p} P_{k+p}: the Ritz panels by a panel GEMM, then the last panel
+    T* Vn = reinterpret_cast<T*>(w.V[cur ^ 1].p);
+    panel_gemm<T, T>(pl, p, Vb, d / p, w.Crot.p, kpn, kpn / p, Vn, int64_t(blk), p, 0);
+    HIPCHK(hipMemcpyAsync(Vn + size_t(kpn / p) * blk, Vb + size_t(d / p) * blk, sizeof(T) * blk,
+                          hipMemcpyDeviceToDevice, s));
+    // Pk's constant header (host copy) must stay alive until the copies ran
+    HIPCHK(hipStreamSynchronize(s));
     cur ^= 1;
-    Vb = w.V[cur].p;
-    cs.keff = keff;
-    const int q = (m * p - keff) / p;
-    cs.d = keff + q * p;
-    first_block = keff / p;
+    Vb = reinterpret_cast<T*>(w.V[cur].p);
+    keff = kn;
+    kp = kpn;
+    d = m * p;   // kp + (m - kp/p) p
+    first_block = kp / p;
     rhs_from_S = true;
     ms_small += host_now_ms() - t3;
   }
-  // true residuals of the shifted systems (FP64, once at the end)
-  if (pl->kind == 0 && !transpose) {
+  // true residuals of the shifted systems (FP64 operator, once at the end)
+  if (pl->kind == 0) {
+    Csr<double> A = csr_of<double>(pl, transpose);
     const int PP = pow2_lanes(p);
     const int grid = grid_for(n, PP, 512);
     DISPATCH_PP(PP, hipLaunchKernelGGL((k_true_residual<P_>), dim3(grid), dim3(kThreads), 0, s, n,
-                                       p, pl->rowptr.p, pl->colind.p, pl->val.p, B, w.X.p,
-                                       pl->tau_re.p, pl->tau_im.p, w.partial.p));
+                                       p, A.rowptr, A.colind, A.val, B, w.X.p, pl->tau_re.p,
+                                       pl->tau_im.p, w.partial.p));
     std::vector<double> tp(size_t(grid) * kNShift);
     HIPCHK(hipMemcpyAsync(tp.data(), w.partial.p, sizeof(double) * tp.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -816,6 +996,20 @@ expmv_status build_csr(expmv_plan_s* pl, const int32_t* rowptr_d, const int32_t*
   HIPCHK(hipMemcpy(pl->colind.p, ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(pl->val.p, v.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(pl->dinv.p, dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  if (pl->mixed) {
+    std::vector<float> vf(v.begin(), v.end()), df(dinv.begin(), dinv.end());
+    pl->valf.alloc(std::max<int64_t>(nnz, 1));
+    pl->dinvf.alloc(n);
+    HIPCHK(hipMemcpy(pl->valf.p, vf.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pl->dinvf.p, df.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    if (!sym) {
+      std::vector<float> vtf(vt.begin(), vt.end());
+      pl->valTf.alloc(std::max<int64_t>(nnz, 1));
+      pl->dinvTf.alloc(n);
+      HIPCHK(hipMemcpy(pl->valTf.p, vtf.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(pl->dinvTf.p, df.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+    }
+  }
   if (!sym) {
     pl->rowptrT.alloc(n + 1);
     pl->colindT.alloc(std::max<int64_t>(nnz, 1));
@@ -868,6 +1062,7 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const
     pl->t = t;
     pl->opts = o;
     pl->stream = stream;
+    pl->mixed = (o.precision == EXPMV_MIXED);
     init_plan_common(pl.get());
     expmv_status st = build_csr(pl.get(), rowptr, colind, val);
     if (st != EXPMV_OK) return st;
@@ -891,7 +1086,10 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
                            double* Z, expmv_info* info) {
   if (!plan || !B || !Z || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
-  return guarded([&]() { return execute_impl(plan, transpose, B, int(p), tol, Z, info); });
+  return guarded([&]() {
+    return plan->mixed ? execute_impl<float>(plan, transpose, B, int(p), tol, Z, info)
+                       : execute_impl<double>(plan, transpose, B, int(p), tol, Z, info);
+  });
 }
 
 expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Zm, int64_t p,
@@ -921,7 +1119,7 @@ expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* 
                                   double* Y) {
   if (!plan || !X || !Y || p < 1 || p > kMaxP) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
-    apply_K(plan, transpose, X, Y, int(p));
+    apply_K<double>(plan, transpose, X, Y, int(p));
     const int64_t cnt = plan->n * p;
     hipLaunchKernelGGL((k_convert<double, double>), dim3(512), dim3(kThreads), 0, plan->stream, cnt,
                        Y, Y, -1.0);
@@ -935,7 +1133,19 @@ expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X
   if (!plan || !X || !Y || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
     ensure_workspace(plan, int(p));
-    InnerResult r = apply_inverse(plan, transpose, X, Y, int(p));
+    InnerResult r;
+    if (plan->mixed) {
+      float* xf = reinterpret_cast<float*>(plan->ws.W.p);
+      float* yf = reinterpret_cast<float*>(plan->ws.Wt.p);
+      const int64_t cnt = plan->n * p;
+      hipLaunchKernelGGL((k_convert<double, float>), dim3(512), dim3(kThreads), 0, plan->stream,
+                         cnt, X, xf, 1.0);
+      r = apply_inverse<float>(plan, transpose, xf, yf, int(p));
+      hipLaunchKernelGGL((k_convert<float, double>), dim3(512), dim3(kThreads), 0, plan->stream,
+                         cnt, yf, Y, 1.0);
+    } else {
+      r = apply_inverse<double>(plan, transpose, X, Y, int(p));
+    }
     HIPCHK(hipStreamSynchronize(plan->stream));
     if (iters) *iters = r.iters;
     return r.hit_cap ? EXPMV_EINNER : EXPMV_OK;

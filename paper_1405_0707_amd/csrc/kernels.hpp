@@ -200,9 +200,9 @@ __device__ inline void write_col_partial(double v, double* red, double* part, in
   __syncthreads();
 }
 
-template <typename T, int PP>
+template <typename T, typename TS, int PP>
 __global__ void __launch_bounds__(kCgThreads)
-k_cg_init(int n, int p, double sign, const double* __restrict__ src, const T* __restrict__ dinv,
+k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __restrict__ dinv,
           T* __restrict__ x, T* __restrict__ r, T* __restrict__ pold,
           KrylovCtl* ctl, double* __restrict__ part_rr) {
   __shared__ double red[kCgThreads];
@@ -213,7 +213,7 @@ k_cg_init(int n, int p, double sign, const double* __restrict__ src, const T* __
   for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
     if (c < p) {
       const int64_t i = row * p + c;
-      const T b = T(sign * src[i]);
+      const T b = T(sign * double(src[i]));
       r[i] = b;
       x[i] = T(0);
       pold[i] = T(0);
@@ -364,6 +364,237 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
     }
   }
   write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
+  write_col_partial<PP>(rr, red, part_rr, 2 * PP, PP);
+}
+
+// ---------------------------------------------------------------------------
+// Batched BiCGStab (right Jacobi preconditioning, y = D^{-1} p, z = D^{-1} s)
+// on K x = b for nonsymmetric K, column-wise, b = sign * src, r^ = b.  Same
+// scheme as the CG: every kernel re-sums the previous kernel's partials.
+// Iteration i:
+//   U1: rho_i = (r^, r), |r|^2 (partials of U3_{i-1} or init); convergence;
+//       beta = (rho_i / rho_{i-1}) (alpha / omega); p = r + beta (p - omega v)
+//   S1: v = K D^{-1} p, partial (r^, v)
+//   U2: alpha = rho_i / (r^, v); s = r - alpha v
+//   S2: t = K D^{-1} s, partials (t, s), (t, t)
+//   U3: omega = (t, s) / (t, t); x += alpha D^{-1} p + omega D^{-1} s;
+//       r = s - omega t; partials (r^, r), |r|^2
+// A column stops at |r| <= tol |b|, at the cap, or at a breakdown
+// (rho, (r^, v) or (t, t) zero); its later steps are zero.
+
+struct BcgState {
+  double rho[kMaxP], alpha[kMaxP], omega[kMaxP], bnorm2[kMaxP];
+  int active[kMaxP], iters[kMaxP];
+};
+
+template <typename T, typename TS, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_bcg_init(int n, int p, double sign, const TS* __restrict__ src, T* __restrict__ x,
+           T* __restrict__ r, T* __restrict__ rhat, T* __restrict__ pv, T* __restrict__ v,
+           KrylovCtl* ctl, double* __restrict__ part_rr) {
+  __shared__ double red[kCgThreads];
+  const int c = threadIdx.x % PP;
+  double bb = 0.0;
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
+    if (c < p) {
+      const int64_t i = row * p + c;
+      const T b = T(sign * double(src[i]));
+      r[i] = b;
+      rhat[i] = b;
+      x[i] = T(0);
+      pv[i] = T(0);
+      v[i] = T(0);
+      bb += double(b) * double(b);
+    }
+  }
+  write_col_partial<PP>(bb, red, part_rr, 2 * PP, 0);   // (r^, r) = |b|^2 at start
+  write_col_partial<PP>(bb, red, part_rr, 2 * PP, PP);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->done = 0;
+    ctl->iters_max = 0;
+    ctl->hit_cap = 0;
+    ctl->counter = 0u;
+  }
+}
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const T* __restrict__ v,
+         BcgState* st, KrylovCtl* ctl, const double* __restrict__ part_rr, double tol2, int maxit) {
+  if (ctl->done) return;
+  __shared__ double red[kCgThreads];
+  __shared__ double tot[2 * PP];
+  __shared__ double s_beta[PP], s_om[PP];
+  __shared__ int s_any;
+  reduce_parts<PP, 2>(part_rr, gridDim.x, red, tot);
+  if (threadIdx.x == 0) {
+    int any = 0, itmax = 0, hit = 0;
+    for (int cc = 0; cc < PP; ++cc) {
+      double beta = 0.0, om = 0.0;
+      int act = 0;
+      if (cc < p) {
+        const double rho = tot[cc], rn = tot[PP + cc];
+        double bn, rho_prev, a_prev, om_prev;
+        int act_prev, it;
+        if (i == 0) {
+          bn = rn;
+          act_prev = bn > 0.0;
+          it = 0;
+          rho_prev = a_prev = om_prev = 1.0;
+        } else {
+          bn = st->bnorm2[cc];
+          act_prev = st->active[cc];
+          it = st->iters[cc];
+          rho_prev = st->rho[cc];
+          a_prev = st->alpha[cc];
+          om_prev = st->omega[cc];
+        }
+        act = act_prev && !(rn <= tol2 * bn);
+        if (act && (it >= maxit || rho == 0.0 || om_prev == 0.0 || rho_prev == 0.0)) {
+          act = 0;
+          hit = 1;
+        }
+        if (act) {
+          beta = (rho / rho_prev) * (a_prev / om_prev);
+          om = om_prev;
+        }
+        if (blockIdx.x == 0) {
+          st->rho[cc] = rho;
+          st->active[cc] = act;
+          st->iters[cc] = it + act;
+          if (i == 0) st->bnorm2[cc] = bn;
+        }
+        if (it > itmax) itmax = it;
+      }
+      s_beta[cc] = beta;
+      s_om[cc] = om;
+      any |= act;
+    }
+    s_any = any;
+    if (blockIdx.x == 0 && !any) {
+      ctl->iters_max = itmax;
+      ctl->hit_cap = hit;
+      ctl->done = 1;
+    }
+  }
+  __syncthreads();
+  if (!s_any) return;
+  const int c = threadIdx.x % PP;
+  const T beta = T(s_beta[c]), om = T(s_om[c]);
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
+    if (c < p) {
+      const int64_t idx = row * p + c;
+      pv[idx] = r[idx] + beta * (pv[idx] - om * v[idx]);
+    }
+  }
+}
+
+// out = K D^{-1} in, partials (a, out) [NV = 1] or (out, a), (out, out) [NV = 2]
+template <typename T, int PP, int NV>
+__global__ void __launch_bounds__(kCgThreads)
+k_bcg_s(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+        const T* __restrict__ val, const T* __restrict__ dinv, const T* __restrict__ in,
+        const T* __restrict__ a, T* __restrict__ out, const KrylovCtl* ctl,
+        double* __restrict__ part) {
+  if (ctl->done) return;
+  __shared__ double red[kCgThreads];
+  const int c = threadIdx.x % PP;
+  double d0 = 0.0, d1 = 0.0;
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
+    if (c < p) {
+      const int e0 = rowptr[row], e1 = rowptr[row + 1];
+      T acc = T(0);
+      for (int e = e0; e < e1; ++e) {
+        const int64_t j = colind[e];
+        acc += val[e] * (dinv[j] * in[j * p + c]);
+      }
+      const int64_t idx = row * p + c;
+      out[idx] = acc;
+      const double o = double(acc), av = double(a[idx]);
+      d0 += av * o;
+      if (NV == 2) d1 += o * o;
+    }
+  }
+  write_col_partial<PP>(d0, red, part, NV * PP, 0);
+  if (NV == 2) write_col_partial<PP>(d1, red, part, NV * PP, PP);
+}
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_bcg_u2(int n, int p, const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ sv,
+         BcgState* st, const KrylovCtl* ctl, const double* __restrict__ part) {
+  if (ctl->done) return;
+  __shared__ double red[kCgThreads];
+  __shared__ double tot[PP];
+  __shared__ double s_a[PP];
+  reduce_parts<PP, 1>(part, gridDim.x, red, tot);
+  if (threadIdx.x < PP) {
+    const int cc = threadIdx.x;
+    double a = 0.0;
+    if (cc < p && st->active[cc] && tot[cc] != 0.0) a = st->rho[cc] / tot[cc];
+    if (cc < p && blockIdx.x == 0) st->alpha[cc] = a;
+    s_a[cc] = a;
+  }
+  __syncthreads();
+  const int c = threadIdx.x % PP;
+  const T a = T(s_a[c]);
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
+    if (c < p) {
+      const int64_t idx = row * p + c;
+      sv[idx] = r[idx] - a * v[idx];
+    }
+  }
+}
+
+template <typename T, int PP>
+__global__ void __launch_bounds__(kCgThreads)
+k_bcg_u3(int n, int p, const T* __restrict__ dinv, const T* __restrict__ pv,
+         const T* __restrict__ sv, const T* __restrict__ tv, const T* __restrict__ rhat,
+         T* __restrict__ x, T* __restrict__ r, BcgState* st, const KrylovCtl* ctl,
+         const double* __restrict__ part, double* __restrict__ part_rr) {
+  if (ctl->done) return;
+  __shared__ double red[kCgThreads];
+  __shared__ double tot[2 * PP];
+  __shared__ double s_a[PP], s_om[PP];
+  reduce_parts<PP, 2>(part, gridDim.x, red, tot);   // tot[c] = (t, s), tot[PP + c] = (t, t)
+  if (threadIdx.x < PP) {
+    const int cc = threadIdx.x;
+    double a = 0.0, om = 0.0;
+    if (cc < p && st->active[cc]) {
+      a = st->alpha[cc];
+      om = tot[PP + cc] != 0.0 ? tot[cc] / tot[PP + cc] : 0.0;
+    }
+    if (cc < p && blockIdx.x == 0) st->omega[cc] = om;
+    s_a[cc] = a;
+    s_om[cc] = om;
+  }
+  __syncthreads();
+  const int c = threadIdx.x % PP;
+  const T a = T(s_a[c]), om = T(s_om[c]);
+  double rr_hat = 0.0, rr = 0.0;
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
+    if (c < p) {
+      const int64_t idx = row * p + c;
+      const T dv = dinv[row];
+      const T sval = sv[idx];
+      x[idx] += a * (dv * pv[idx]) + om * (dv * sval);
+      const T rn = sval - om * tv[idx];
+      r[idx] = rn;
+      rr_hat += double(rhat[idx]) * double(rn);
+      rr += double(rn) * double(rn);
+    }
+  }
+  write_col_partial<PP>(rr_hat, red, part_rr, 2 * PP, 0);
   write_col_partial<PP>(rr, red, part_rr, 2 * PP, PP);
 }
 

@@ -175,3 +175,81 @@ def test_error_statuses():
     pl1 = plan_for(W1, m=4, k=4, max_cycles=1)
     Z, info = pl1.execute(torch.from_numpy(W1.B), tol=1e-12, allow=(_lib.ENOCONV,))
     assert info.cycles == 1
+
+
+# ---------------------------------------------------------------------------
+# nonsymmetric operator (upwind convection-diffusion): BiCGStab inner solver,
+# general restart eigenproblem with complex Ritz pairs, transpose
+
+def small_convdiff(N, p):
+    """Reduced upwind convection-diffusion with t set so that t lambda_min(K)
+    = 3.33, the value of the 128^3 workload."""
+    W = wl.c4(N=N, p=p, precision="fp64")
+    lam = np.linalg.eigvals(-W.A.to_scipy().toarray()) if W.n <= 4096 else None
+    if lam is not None:
+        W.t = 3.33 / lam.real.min()
+    return W
+
+
+def test_nonsymmetric_inverse_matches_splu():
+    announce("BiCGStab inverse")
+    W = small_convdiff(12, 4)
+    pl = plan_for(W, inner_tol=1e-13)
+    X = np.random.default_rng(21).standard_normal((W.n, 4))
+    Y, iters = pl.apply_inverse(torch.from_numpy(X))
+    M = (W.t * W.A.to_scipy()).tocsr()
+    assert rel(Y.cpu().numpy(), inverses.splu_inverse(M)(X)) < 1e-10
+    Yt, _ = pl.apply_inverse(torch.from_numpy(X), transpose=True)
+    assert rel(Yt.cpu().numpy(), inverses.splu_inverse(M.T.tocsr())(X)) < 1e-10
+
+
+@pytest.mark.parametrize("m,k", [(10, 12), (4, 4)])
+def test_nonsymmetric_matches_direct_rational(m, k):
+    announce(f"convdiff N=12 m={m} k={k}")
+    W = small_convdiff(12, 4)
+    pl = plan_for(W, m=m, k=k, max_cycles=200)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=1e-11)
+    M = (W.t * W.A.to_scipy()).tocsr()
+    ref = exact.rational_sparse(M, W.B)
+    if m == 4:
+        assert info.cycles > 2        # restarts with the general eigensolver
+    assert rel(Z.cpu().numpy(), ref) < 1e-10
+
+
+def test_nonsymmetric_transpose_execute():
+    announce("convdiff transpose")
+    W = small_convdiff(10, 3)
+    pl = plan_for(W, m=8, k=6)
+    G = np.random.default_rng(5).standard_normal(W.B.shape)
+    Zt, _ = pl.execute(torch.from_numpy(G), tol=1e-11, transpose=True)
+    M = (W.t * W.A.to_scipy()).tocsr()
+    ref = exact.rational_sparse(M.T.tocsr(), G)
+    assert rel(Zt.cpu().numpy(), ref) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP32 inner solver and basis, FP64 small side, X and sums
+
+def test_mixed_3d_laplacian_within_1e5():
+    announce("mixed 3D N=24")
+    N = 24
+    W = wl.c2(N=N)
+    W.t = 5.842338 / (3 * (2 - 2 * np.cos(np.pi / (N + 1))))
+    pl = plan_for(W, m=W.m, k=W.k, precision="mixed")
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=1e-6)
+    rB = inverses.dst_laplacian_function(N, 3, W.t, rfun, W.B)
+    e = rel(Z.cpu().numpy(), rB)
+    print(f"mixed 3D rel err {e:.2e}")
+    assert e < 1e-5
+
+
+def test_mixed_convdiff_within_1e5():
+    announce("mixed convdiff N=16")
+    W = small_convdiff(16, 4)
+    pl = plan_for(W, m=10, k=12, precision="mixed")
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=1e-6)
+    M = (W.t * W.A.to_scipy()).tocsr()
+    ref = exact.rational_sparse(M, W.B)
+    e = rel(Z.cpu().numpy(), ref)
+    print(f"mixed convdiff rel err {e:.2e}")
+    assert e < 1e-5
