@@ -21,6 +21,7 @@
 #include "expmv.h"
 #include "kernels.hpp"
 #include "kernels_dense.hpp"
+#include "toeplitz.hpp"
 
 #include "cf_nu14.inc"
 
@@ -110,6 +111,15 @@ struct expmv_plan_s {
   DevBuf<double> val, valT, dinv, dinvT;
   DevBuf<float> valf, valTf, dinvf, dinvTf;   // FP32 copies (mixed form)
   bool mixed = false;
+  // Toeplitz operator: L = 2n circulant embedding; spectra of the embedded
+  // first column (chat), of x = T^{-1} e_1 and of Z x~ (Gohberg-Semencul)
+  int64_t L = 0;
+  double x0 = 0.0;
+  std::vector<int> radices;
+  DevBuf<cplx> chat, xhat, yhat;
+  DevBuf<cplx> fb[4];            // L x q work arrays
+  int fq = 0;                    // complex columns the work arrays hold
+  DevBuf<double> kx;             // n x 14p (Toeplitz true residual)
   // CF table on the device
   DevBuf<double> tau_re, tau_im, c_re, c_im;
   Workspace ws;
@@ -228,7 +238,17 @@ Csr<float> csr_of<float>(expmv_plan_s* pl, int transpose) {
 
 // Y = K X (K = -tA, or its transpose) for n x p blocks of type T.
 template <typename T>
+void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy, int p,
+                    double scale, int accumulate);
+template <typename T>
+void toeplitz_gsf(expmv_plan_s* pl, const T* V, T* W, int p, double scale);
+
+template <typename T>
 void apply_K(expmv_plan_s* pl, int transpose, const T* X, T* Y, int p) {
+  if (pl->kind == 1) {   // K = t T, T symmetric
+    toeplitz_apply<T>(pl, X, p, Y, p, p, pl->t, 0);
+    return;
+  }
   Csr<T> A = csr_of<T>(pl, transpose);
   const int PP = pow2_lanes(p);
   const int grid = grid_for(pl->n, PP, 4096);
@@ -398,8 +418,127 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
 // W ~= M^{-1} V = -(K^{-1} V), M = tA.
 template <typename T>
 InnerResult apply_inverse(expmv_plan_s* pl, int transpose, const T* V, T* Wout, int p) {
+  if (pl->kind == 1) {   // M^{-1} = -(1/t) T^{-1}, Gohberg-Semencul
+    toeplitz_gsf<T>(pl, V, Wout, p, -1.0 / pl->t);
+    return {0, 0};
+  }
   if (pl->symmetric) return inner_cg<T>(pl, V, -1.0, Wout, p);
   return inner_bicgstab<T>(pl, transpose, V, -1.0, Wout, p);
+}
+
+// -------------------------------------------------------------------------
+// Toeplitz operator (FFT circulant embedding) and Gohberg-Semencul inverse
+
+std::vector<int> fft_radices(int64_t L) {
+  std::vector<int> r;
+  while (L % 8 == 0 && L > 4) {
+    r.push_back(8);
+    L /= 8;
+  }
+  while (L > 1) {
+    if (L % 4 == 0) {
+      r.push_back(4);
+      L /= 4;
+    } else {
+      r.push_back(2);
+      L /= 2;
+    }
+  }
+  return r;
+}
+
+int stream_grid(int64_t items) {
+  return int(std::max<int64_t>(1, std::min<int64_t>(4096, (items + kThreads - 1) / kThreads)));
+}
+
+// out = DFT(in) over L rows for q columns (sign -1 forward, +1 inverse,
+// unnormalised); in, out and tmp distinct.
+void fft(expmv_plan_s* pl, const cplx* in, cplx* out, cplx* tmp, int q, double sign) {
+  const int np = int(pl->radices.size());
+  const int64_t L = pl->L;
+  const cplx* src = in;
+  int64_t Ns = 1;
+  for (int i = 0; i < np; ++i) {
+    cplx* dst = ((np - 1 - i) % 2 == 0) ? out : tmp;
+    const int R = pl->radices[i];
+    const int grid = stream_grid((L / R) * q);
+    if (R == 8)
+      hipLaunchKernelGGL(k_fft_pass<8>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
+    else if (R == 4)
+      hipLaunchKernelGGL(k_fft_pass<4>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
+    else
+      hipLaunchKernelGGL(k_fft_pass<2>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
+    src = dst;
+    Ns *= R;
+  }
+}
+
+void ensure_fft_buffers(expmv_plan_s* pl, int q) {
+  if (pl->fq >= q) return;
+  for (auto& b : pl->fb) b.alloc(size_t(pl->L) * q);
+  pl->fq = q;
+}
+
+// Y (n x p, ld) = scale * T X (X n x p, ld) through the circulant embedding
+template <typename T>
+void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy, int p,
+                    double scale, int accumulate) {
+  const int q = (p + 1) / 2;
+  ensure_fft_buffers(pl, q);
+  const int64_t L = pl->L, n = pl->n;
+  cplx *A = pl->fb[0].p, *Bf = pl->fb[1].p, *C = pl->fb[2].p;
+  hipStream_t s = pl->stream;
+  hipLaunchKernelGGL((k_pack<T>), dim3(stream_grid(L * q)), dim3(kThreads), 0, s, n, p, ldx, q, L,
+                     X, A, 0, 1.0);
+  fft(pl, A, Bf, C, q, -1.0);
+  hipLaunchKernelGGL(k_spec_mul, dim3(stream_grid(L * q)), dim3(kThreads), 0, s, L, q, Bf,
+                     pl->chat.p, scale / double(L));
+  fft(pl, Bf, A, C, q, +1.0);
+  hipLaunchKernelGGL((k_unpack<T>), dim3(stream_grid(n * p)), dim3(kThreads), 0, s, n, p, ldy, q, A,
+                     Y, 0, 1.0, accumulate);
+}
+
+// W = scale * T^{-1} V by the Gohberg-Semencul formula
+//   T^{-1} = (1/x0) (L(x) L(x)^T - L(y) L(y)^T),  x = T^{-1} e_1, y = Z x~,
+// L(h)^T v = rev(L(h) rev(v)); six length-L FFTs per block.
+template <typename T>
+void toeplitz_gsf(expmv_plan_s* pl, const T* V, T* W, int p, double scale) {
+  const int q = (p + 1) / 2;
+  ensure_fft_buffers(pl, q);
+  const int64_t L = pl->L, n = pl->n;
+  cplx *A = pl->fb[0].p, *Bf = pl->fb[1].p, *C = pl->fb[2].p, *D = pl->fb[3].p;
+  hipStream_t s = pl->stream;
+  const int g = stream_grid(L * q);
+  const double inv = 1.0 / double(L);
+  hipLaunchKernelGGL((k_pack<T>), dim3(g), dim3(kThreads), 0, s, n, p, int64_t(p), q, L, V, A, 1,
+                     1.0);
+  fft(pl, A, Bf, C, q, -1.0);                                   // B = F rev(V)
+  hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, pl->xhat.p, C, inv);
+  hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, pl->yhat.p, D, inv);
+  fft(pl, C, A, Bf, q, +1.0);                                   // A = L(x) rev(V)
+  hipLaunchKernelGGL(k_rev_trunc, dim3(g), dim3(kThreads), 0, s, L, n, q, A, C, 1.0);  // C = L(x)^T V
+  fft(pl, D, A, Bf, q, +1.0);                                   // A = L(y) rev(V)
+  hipLaunchKernelGGL(k_rev_trunc, dim3(g), dim3(kThreads), 0, s, L, n, q, A, D, 1.0);  // D = L(y)^T V
+  fft(pl, C, A, Bf, q, -1.0);                                   // A = F C
+  fft(pl, D, C, Bf, q, -1.0);                                   // C = F D
+  hipLaunchKernelGGL(k_spec_mul2, dim3(g), dim3(kThreads), 0, s, L, q, A, pl->xhat.p, C,
+                     pl->yhat.p, Bf, inv);
+  fft(pl, Bf, A, C, q, +1.0);
+  hipLaunchKernelGGL((k_unpack<T>), dim3(stream_grid(n * p)), dim3(kThreads), 0, s, n, p,
+                     int64_t(p), q, A, W, 0, scale / pl->x0, 0);
+}
+
+double device_dot(expmv_plan_s* pl, int64_t len, const double* x, const double* y) {
+  const int grid = 256;
+  hipLaunchKernelGGL(k_dot_partial, dim3(grid), dim3(kThreads), 0, pl->stream, len, x, y,
+                     pl->ws.partial.p);
+  std::vector<double> part(grid);
+  HIPCHK(hipMemcpyAsync(part.data(), pl->ws.partial.p, sizeof(double) * grid,
+                        hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  double acc = 0.0;
+  for (double v : part) acc += v;
+  return acc;
 }
 
 // -------------------------------------------------------------------------
@@ -846,6 +985,24 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       inf.true_res[j] = std::sqrt(acc);
     }
   }
+  if (pl->kind == 1) {
+    const int64_t ldxr = 2 * kNShift * p;
+    pl->kx.alloc(size_t(n) * ldxr);
+    for (int j = 0; j < kNShift; ++j)
+      toeplitz_apply<double>(pl, w.X.p + 2 * p * j, ldxr, pl->kx.p + 2 * p * j, ldxr, 2 * p, pl->t,
+                             0);
+    const int grid = 512;
+    hipLaunchKernelGGL(k_residual_from_kx, dim3(grid), dim3(kThreads), 0, s, n, p, B, w.X.p,
+                       pl->kx.p, pl->tau_re.p, pl->tau_im.p, w.partial.p);
+    std::vector<double> tp(size_t(grid) * kNShift);
+    HIPCHK(hipMemcpyAsync(tp.data(), w.partial.p, sizeof(double) * tp.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int j = 0; j < kNShift; ++j) {
+      double acc = 0.0;
+      for (int g2 = 0; g2 < grid; ++g2) acc += tp[size_t(g2) * kNShift + j];
+      inf.true_res[j] = std::sqrt(acc);
+    }
+  }
   HIPCHK(hipStreamSynchronize(s));
   inf.ms_total = host_now_ms() - t_start;
   inf.ms_apply = ms_apply;
@@ -1073,13 +1230,97 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const
 
 expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t, const expmv_opts* opts,
                                  hipStream_t stream, expmv_plan* out) {
-  (void)n;
-  (void)col0;
-  (void)t;
-  (void)opts;
-  (void)stream;
-  if (out) *out = nullptr;
-  return EXPMV_EINVAL;
+  if (!out) return EXPMV_EINVAL;
+  *out = nullptr;
+  if (n < 2 || n > (int64_t(1) << 28) || !col0) return EXPMV_EINVAL;
+  if (!(t != 0.0) || !std::isfinite(t)) return EXPMV_EINVAL;
+  if (t < 0.0) return EXPMV_ENOTNEG;   // tA = -t T with T SPD needs t > 0
+  expmv_opts o;
+  expmv_default_opts(&o);
+  if (opts) o = *opts;
+  if (!valid_opts(o)) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    std::unique_ptr<expmv_plan_s> pl(new expmv_plan_s());
+    pl->kind = 1;
+    pl->n = n;
+    pl->nnz = 0;
+    pl->t = t;
+    pl->opts = o;
+    pl->stream = stream;
+    pl->mixed = (o.precision == EXPMV_MIXED);
+    pl->symmetric = true;
+    init_plan_common(pl.get());
+    hipStream_t s = stream;
+    std::vector<double> c(n);
+    HIPCHK(hipMemcpy(c.data(), col0, sizeof(double) * n, hipMemcpyDeviceToHost));
+    for (double v : c)
+      if (!std::isfinite(v)) return EXPMV_EINVAL;
+    if (!(c[0] > 0.0)) return EXPMV_ENOTNEG;
+    int64_t L = 1;
+    while (L < 2 * n) L <<= 1;
+    pl->L = L;
+    pl->radices = fft_radices(L);
+    pl->ws.partial.alloc(4096);
+    ensure_fft_buffers(pl.get(), 1);
+    // spectrum of the circulant embedding [c_0 .. c_{n-1}, 0 .., c_{n-1} .. c_1]
+    std::vector<double> emb(L, 0.0);
+    for (int64_t i = 0; i < n; ++i) emb[i] = c[i];
+    for (int64_t i = 1; i < n; ++i) emb[L - i] = c[i];
+    DevBuf<double> tmp;
+    tmp.alloc(L);
+    pl->chat.alloc(L);
+    pl->xhat.alloc(L);
+    pl->yhat.alloc(L);
+    auto spectrum = [&](const std::vector<double>& h, cplx* dst) {
+      HIPCHK(hipMemcpyAsync(tmp.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(L)), dim3(kThreads), 0, s, int64_t(h.size()),
+                         1, int64_t(1), 1, L, tmp.p, pl->fb[0].p, 0, 1.0);
+      fft(pl.get(), pl->fb[0].p, dst, pl->fb[1].p, 1, -1.0);
+      HIPCHK(hipStreamSynchronize(s));
+    };
+    spectrum(emb, pl->chat.p);
+    // x = T^{-1} e_1 by CG with the FFT product (once per plan)
+    DevBuf<double> x, r, pv, q;
+    x.alloc(n);
+    r.alloc(n);
+    pv.alloc(n);
+    q.alloc(n);
+    HIPCHK(hipMemsetAsync(x.p, 0, sizeof(double) * n, s));
+    HIPCHK(hipMemsetAsync(r.p, 0, sizeof(double) * n, s));
+    const double one = 1.0;
+    HIPCHK(hipMemcpyAsync(r.p, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(pv.p, r.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    double rr = 1.0;
+    bool ok = false;
+    const int g = stream_grid(n);
+    for (int it = 0; it < 20000; ++it) {
+      toeplitz_apply<double>(pl.get(), pv.p, 1, q.p, 1, 1, 1.0, 0);
+      const double pq = device_dot(pl.get(), n, pv.p, q.p);
+      if (!(pq > 0.0)) return EXPMV_ENOTNEG;   // T not positive definite
+      const double alpha = rr / pq;
+      hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, alpha, pv.p, 1.0, x.p);
+      hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, -alpha, q.p, 1.0, r.p);
+      const double rr2 = device_dot(pl.get(), n, r.p, r.p);
+      if (std::sqrt(rr2) <= 1e-14) {
+        ok = true;
+        break;
+      }
+      hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, 1.0, r.p, rr2 / rr, pv.p);
+      rr = rr2;
+    }
+    if (!ok) return EXPMV_ENOCONV;
+    std::vector<double> xh(n);
+    HIPCHK(hipMemcpy(xh.data(), x.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    pl->x0 = xh[0];
+    if (!(pl->x0 > 0.0)) return EXPMV_ENOTNEG;
+    std::vector<double> xe(L, 0.0), ye(L, 0.0);
+    for (int64_t i = 0; i < n; ++i) xe[i] = xh[i];
+    for (int64_t i = 1; i < n; ++i) ye[i] = xh[n - i];   // Z x~ = [0, x_{n-1}, .., x_1]
+    spectrum(xe, pl->xhat.p);
+    spectrum(ye, pl->yhat.p);
+    *out = pl.release();
+    return EXPMV_OK;
+  });
 }
 
 expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int64_t p, double tol,
@@ -1098,6 +1339,13 @@ expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Zm, in
   return guarded([&]() -> expmv_status {
     ensure_workspace(plan, int(p));
     hipStream_t s = plan->stream;
+    if (plan->kind == 1) {
+      // <G, A Z> = -<G, T Z>
+      plan->kx.alloc(size_t(plan->n) * p);
+      toeplitz_apply<double>(plan, Zm, p, plan->kx.p, p, int(p), 1.0, 0);
+      *out = -device_dot(plan, plan->n * p, G, plan->kx.p);
+      return EXPMV_OK;
+    }
     const int PP = pow2_lanes(int(p));
     const int grid = grid_for(plan->n, PP, 512);
     DISPATCH_PP(PP, hipLaunchKernelGGL((k_dot_spmm<P_>), dim3(grid), dim3(kThreads), 0, s,

@@ -1,0 +1,234 @@
+// Toeplitz operator kernels: a batched complex FFT (Stockham autosort,
+// mixed radix 8/4/2, q interleaved columns), real <-> complex packing of
+// two real columns per complex column, and the pointwise spectral products
+// of the circulant-embedding product T v and of the Gohberg-Semencul
+// formula for T^{-1} v (paper, Section 4.1 and the fast Toeplitz products of
+// Section 2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels_dense.hpp"
+
+namespace expmv {
+
+// One Stockham pass of radix R over a length-L transform, q columns
+// interleaved (element i of column c at [i * q + c]).  Ns = product of the
+// radices of the earlier passes.  Thread (j, c), j < L / R:
+//   v_r = in[j + r L/R] * w^{r (j mod Ns)},  w = exp(sign 2 pi i / (Ns R))
+//   V = DFT_R(v) (sign),  out[(j / Ns) Ns R + (j mod Ns) + r Ns] = V_r
+template <int R>
+__global__ void __launch_bounds__(kThreads)
+k_fft_pass(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __restrict__ out,
+           double sign) {
+  const int64_t total = (L / R) * q;
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < total;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t j = gid / q;
+    const int c = int(gid % q);
+    const int64_t k = j % Ns;
+    cplx v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[(j + r * (L / R)) * q + c];
+    if (Ns > 1) {
+      double sw, cw;
+      sincospi(sign * 2.0 * double(k) / double(Ns * R), &sw, &cw);
+      cplx w{cw, sw}, wr = w;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        v[r] = cmul(v[r], wr);
+        wr = cmul(wr, w);
+      }
+    }
+    cplx V[R];
+    if (R == 2) {
+      V[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
+      V[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
+    } else if (R == 4) {
+      const cplx a{v[0].x + v[2].x, v[0].y + v[2].y}, b{v[0].x - v[2].x, v[0].y - v[2].y};
+      const cplx c2{v[1].x + v[3].x, v[1].y + v[3].y}, d{v[1].x - v[3].x, v[1].y - v[3].y};
+      // d * (sign i)
+      const cplx di{-sign * d.y, sign * d.x};
+      V[0] = {a.x + c2.x, a.y + c2.y};
+      V[2] = {a.x - c2.x, a.y - c2.y};
+      V[1] = {b.x + di.x, b.y + di.y};
+      V[3] = {b.x - di.x, b.y - di.y};
+    } else {
+      // R == 8: V_m = sum_r v_r exp(sign 2 pi i r m / 8)
+      constexpr double h = 0.70710678118654752440;
+      const double cs[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
+      const double sn[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        double xr = 0.0, xi = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int e = (r * m) & 7;
+          const double wr = cs[e], wi = sign * sn[e];
+          xr += v[r].x * wr - v[r].y * wi;
+          xi += v[r].x * wi + v[r].y * wr;
+        }
+        V[m] = {xr, xi};
+      }
+    }
+    const int64_t idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[(idxD + r * Ns) * q + c] = V[r];
+  }
+}
+
+// out (L x q complex) = rows of src (n x p real, row-major), two real
+// columns per complex column (2c -> real part, 2c+1 -> imaginary part),
+// rows reversed if `reverse`, zero for rows >= n, times scale.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pack(int64_t n, int p, int64_t ld, int q, int64_t L, const T* __restrict__ src,
+       cplx* __restrict__ out, int reverse, double scale) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < L * q;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t i = gid / q;
+    const int c = int(gid % q);
+    cplx v{0.0, 0.0};
+    if (i < n) {
+      const int64_t row = reverse ? (n - 1 - i) : i;
+      v.x = scale * double(src[row * ld + 2 * c]);
+      if (2 * c + 1 < p) v.y = scale * double(src[row * ld + 2 * c + 1]);
+    }
+    out[gid] = v;
+  }
+}
+
+// dst (n x p real) (+)= scale * the first n rows of in (reversed if
+// `reverse`), unpacking the two real columns of each complex column.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_unpack(int64_t n, int p, int64_t ld, int q, const cplx* __restrict__ in, T* __restrict__ dst,
+         int reverse, double scale, int accumulate) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < n * p;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t i = gid / p;
+    const int col = int(gid % p);
+    const int64_t src_row = reverse ? (n - 1 - i) : i;
+    const cplx v = in[src_row * q + col / 2];
+    const double x = scale * ((col & 1) ? v.y : v.x);
+    T* d = dst + i * ld + col;
+    *d = accumulate ? T(double(*d) + x) : T(x);
+  }
+}
+
+// data[i, c] *= h[i] * scale
+__global__ void __launch_bounds__(kThreads)
+k_spec_mul(int64_t L, int q, cplx* __restrict__ data, const cplx* __restrict__ h, double scale) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < L * q;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const cplx w = h[gid / q];
+    const cplx v = cmul(data[gid], w);
+    data[gid] = {scale * v.x, scale * v.y};
+  }
+}
+
+// out[i, c] = in[i, c] * h[i] * scale
+__global__ void __launch_bounds__(kThreads)
+k_spec_mul_to(int64_t L, int q, const cplx* __restrict__ in, const cplx* __restrict__ h,
+              cplx* __restrict__ out, double scale) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < L * q;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const cplx v = cmul(in[gid], h[gid / q]);
+    out[gid] = {scale * v.x, scale * v.y};
+  }
+}
+
+// out[i, c] = (ha[i] a[i, c] - hb[i] b[i, c]) * scale
+__global__ void __launch_bounds__(kThreads)
+k_spec_mul2(int64_t L, int q, const cplx* __restrict__ a, const cplx* __restrict__ ha,
+            const cplx* __restrict__ b, const cplx* __restrict__ hb, cplx* __restrict__ out,
+            double scale) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < L * q;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t i = gid / q;
+    const cplx u = cmul(a[gid], ha[i]), v = cmul(b[gid], hb[i]);
+    out[gid] = {scale * (u.x - v.x), scale * (u.y - v.y)};
+  }
+}
+
+// out[i, c] = in[n - 1 - i, c] * scale for i < n, 0 for n <= i < L
+// (the reversal between the two triangular products of Gohberg-Semencul)
+__global__ void __launch_bounds__(kThreads)
+k_rev_trunc(int64_t L, int64_t n, int q, const cplx* __restrict__ in, cplx* __restrict__ out,
+            double scale) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < L * q;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t i = gid / q;
+    const int c = int(gid % q);
+    cplx v{0.0, 0.0};
+    if (i < n) {
+      const cplx s = in[(n - 1 - i) * q + c];
+      v = {scale * s.x, scale * s.y};
+    }
+    out[gid] = v;
+  }
+}
+
+// partial sums of x . y (FP64 vectors of length len) per workgroup
+__global__ void __launch_bounds__(kThreads)
+k_dot_partial(int64_t len, const double* __restrict__ x, const double* __restrict__ y,
+              double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < len;
+       i += int64_t(gridDim.x) * kThreads)
+    s += x[i] * y[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kThreads / 2; st >= 1; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// y = a x + b y  (length len)
+__global__ void __launch_bounds__(kThreads)
+k_axpby(int64_t len, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < len;
+       i += int64_t(gridDim.x) * kThreads)
+    y[i] = a * x[i] + b * y[i];
+}
+
+// Z = omega0 B + sum_j Re(c_j X_j) is k_combine; the Toeplitz true residual
+// needs K X: R_j = B + K X_j + tau_j X_j with KX (n x 14p, real) precomputed.
+__global__ void __launch_bounds__(kThreads)
+k_residual_from_kx(int64_t n, int p, const double* __restrict__ B, const double* __restrict__ X,
+                   const double* __restrict__ KX, const double* __restrict__ tau_re,
+                   const double* __restrict__ tau_im, double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  const int ldx = 2 * kNShift * p;
+  double nr[kNShift];
+  for (int j = 0; j < kNShift; ++j) nr[j] = 0.0;
+  for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < n * p;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t r = idx / p;
+    const int b = int(idx % p);
+    const double bv = B[idx];
+    for (int j = 0; j < kNShift; ++j) {
+      const double xr = X[r * ldx + 2 * p * j + b], xi = X[r * ldx + 2 * p * j + p + b];
+      const double kr = KX[r * ldx + 2 * p * j + b], ki = KX[r * ldx + 2 * p * j + p + b];
+      const double rr = bv + kr + tau_re[j] * xr - tau_im[j] * xi;
+      const double ri = ki + tau_re[j] * xi + tau_im[j] * xr;
+      nr[j] += rr * rr + ri * ri;
+    }
+  }
+  for (int j = 0; j < kNShift; ++j) {
+    red[threadIdx.x] = nr[j];
+    __syncthreads();
+    for (int st = kThreads / 2; st >= 1; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[size_t(blockIdx.x) * kNShift + j] = red[0];
+    __syncthreads();
+  }
+}
+
+}  // namespace expmv
