@@ -137,6 +137,16 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
 expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Z, int64_t p,
                           double* out);
 
+/* Adjoint of Z = e^{tA}B for a loss L with dL/dZ = G: one solve with A^T
+ * gives gradB = e^{tA^T} G (n x p, device), and *grad_t (host) =
+ * <G, A r(tA) B> evaluated, with M = tA and Y_j = (M^T - tau_j I)^{-1} G the
+ * shifted solutions of that same solve, as
+ *   (1/t) [omega_0 <G, M B> + Re(sum_j c_j) <G, B> + Re sum_j c_j tau_j <Y_j, B>]
+ * (partial fractions of x r(x)), which applies no operator to a computed
+ * iterate.  tol and info as in expmv_execute; returns its statuses. */
+expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, int64_t p,
+                           double tol, double* gradB, double* grad_t, expmv_info* info);
+
 /* Y = tA X (transpose = 0) or (tA)^T X (transpose = 1), X, Y device n x p. */
 expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* X,
                                   int64_t p, double* Y);

@@ -39,7 +39,7 @@ class Info(C.Structure):
 
 EXPORTS = [
     "expmv_default_opts", "expmv_plan_csr", "expmv_plan_toeplitz", "expmv_execute",
-    "expmv_grad_t", "expmv_apply_operator", "expmv_apply_inverse", "expmv_cf_table",
+    "expmv_grad_t", "expmv_adjoint", "expmv_apply_operator", "expmv_apply_inverse", "expmv_cf_table",
     "expmv_host_eig_sym", "expmv_host_eig_general", "expmv_plan_destroy",
     "expmv_status_string", "expmv_block_csr", "expmv_block_toeplitz",
 ]
@@ -62,6 +62,7 @@ def lib():
     L.expmv_plan_toeplitz.argtypes = [i64, vp, dbl, C.POINTER(Opts), vp, C.POINTER(vp)]
     L.expmv_execute.argtypes = [vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
     L.expmv_grad_t.argtypes = [vp, vp, vp, i64, C.POINTER(dbl)]
+    L.expmv_adjoint.argtypes = [vp, vp, vp, i64, dbl, vp, C.POINTER(dbl), C.POINTER(Info)]
     L.expmv_apply_operator.argtypes = [vp, i32, vp, i64, vp]
     L.expmv_apply_inverse.argtypes = [vp, i32, vp, i64, vp, C.POINTER(C.c_longlong)]
     L.expmv_cf_table.argtypes = [vp, vp, vp, vp, vp]

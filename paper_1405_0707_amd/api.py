@@ -6,7 +6,8 @@ the computation runs in libexpmv.so).
     Z = expmv(A, B, t)                                   # autograd-aware
 
 `expmv` is a torch.autograd.Function: grad_B = e^{tA^T} G (the same solver on
-A^T) and grad_t = <G, A Z>; the forward Krylov basis is not stored, the
+A^T) and grad_t = <G, A r(tA) B> from the shifted solutions of that same
+solve (expmv_adjoint); the forward Krylov basis is not stored (only B), the
 backward solve rebuilds its own.
 """
 from __future__ import annotations
@@ -113,6 +114,18 @@ class Plan:
               "expmv_grad_t")
         return out.value
 
+    def adjoint(self, G: torch.Tensor, B: torch.Tensor, tol: float = 1e-10, allow=()):
+        """(e^{tA^T} G, <G, A r(tA) B>, info) from one transposed solve."""
+        G = _dev_f64(G, self.device)
+        B = _dev_f64(B, self.device)
+        gB = torch.empty_like(G)
+        gt = C.c_double()
+        info = Info()
+        st = lib().expmv_adjoint(self._h, G.data_ptr(), B.data_ptr(), G.shape[1], float(tol),
+                                 gB.data_ptr(), C.byref(gt), C.byref(info))
+        check(st, "expmv_adjoint", allow)
+        return gB, gt.value, info
+
     def apply_operator(self, X: torch.Tensor, transpose: bool = False) -> torch.Tensor:
         X = _dev_f64(X, self.device)
         Y = torch.empty_like(X)
@@ -151,25 +164,21 @@ def _make_plan(A, t, device, opts):
 class _ExpmvFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, B, t, plan, tol, t_float):
-        Z, info = plan.execute(B.detach(), tol=tol)
+        Bd = B.detach()
+        Z, info = plan.execute(Bd, tol=tol)
         ctx.plan = plan
         ctx.tol = tol
-        ctx.t = t_float
-        ctx.save_for_backward(Z)
+        ctx.save_for_backward(Bd)
         ctx.info = info
         return Z
 
     @staticmethod
     def backward(ctx, G):
-        (Z,) = ctx.saved_tensors
-        plan = ctx.plan
-        gB = gt = None
-        if ctx.needs_input_grad[0]:
-            gB, _ = plan.execute(G.contiguous(), tol=ctx.tol, transpose=True)
-        if ctx.needs_input_grad[1]:
-            gt = torch.tensor(plan.grad_t(G.contiguous(), Z), dtype=torch.float64,
-                              device=Z.device)
-        return gB, gt, None, None, None
+        (B,) = ctx.saved_tensors
+        gB, gt, _ = ctx.plan.adjoint(G.contiguous(), B, tol=ctx.tol)
+        gt_t = torch.tensor(gt, dtype=torch.float64, device=gB.device)
+        return (gB if ctx.needs_input_grad[0] else None,
+                gt_t if ctx.needs_input_grad[1] else None, None, None, None)
 
 
 def expmv(A, B: torch.Tensor, t, tol: float = 1e-10, plan: Plan | None = None, **opts):

@@ -1333,6 +1333,45 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
   });
 }
 
+expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, int64_t p,
+                           double tol, double* gradB, double* grad_t, expmv_info* info) {
+  if (!plan || !G || !B || !gradB || !grad_t || p < 1 || p > kMaxP || p > plan->n)
+    return EXPMV_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    expmv_status st = plan->mixed ? execute_impl<float>(plan, 1, G, int(p), tol, gradB, info)
+                                  : execute_impl<double>(plan, 1, G, int(p), tol, gradB, info);
+    if (st != EXPMV_OK && st != EXPMV_ENOCONV) return st;
+    hipStream_t s = plan->stream;
+    Workspace& w = plan->ws;
+    // K B (K = -tA = -M), for the omega_0 <G, M B> term
+    plan->kx.alloc(size_t(plan->n) * p * 2 * kNShift);
+    double* KB = plan->kx.p;
+    apply_K<double>(plan, 0, B, KB, int(p));
+    const int grid = 512;
+    hipLaunchKernelGGL(k_adjoint_dots, dim3(grid), dim3(kThreads), 0, s, plan->n, int(p), w.X.p,
+                       B, G, KB, w.partial.p);
+    std::vector<double> part(size_t(grid) * 16);
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * part.size(),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double d[16] = {0};
+    for (int g = 0; g < grid; ++g)
+      for (int v = 0; v < 16; ++v) d[v] += part[size_t(g) * 16 + v];
+    double sum_c = 0.0, acc = 0.0;
+    for (int j = 0; j < kNShift; ++j) {
+      sum_c += CF_C_RE[j];
+      // Re(c_j tau_j (d_re + i d_im))
+      const double ctr = CF_C_RE[j] * CF_TAU_RE[j] - CF_C_IM[j] * CF_TAU_IM[j];
+      const double cti = CF_C_RE[j] * CF_TAU_IM[j] + CF_C_IM[j] * CF_TAU_RE[j];
+      acc += ctr * d[2 * j] - cti * d[2 * j + 1];
+    }
+    // <G, M B> = -<G, K B>
+    *grad_t = (CF_OMEGA0 * (-d[15]) + sum_c * d[14] + acc) / plan->t;
+    return st;
+  });
+}
+
 expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Zm, int64_t p,
                           double* out) {
   if (!plan || !G || !Zm || !out || p < 1 || p > kMaxP) return EXPMV_EINVAL;

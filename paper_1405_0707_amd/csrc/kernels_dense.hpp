@@ -539,6 +539,40 @@ k_dot_spmm(int64_t n, int p, const int32_t* __restrict__ rowptr, const int32_t* 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// partial[wg * 16 + v]: v = 2j, 2j+1: sum Re(X_j) . B and Im(X_j) . B
+// (j < 7); v = 14: G . B; v = 15: G . KB (KB given, may be null)
+__global__ void __launch_bounds__(kThreads)
+k_adjoint_dots(int64_t n, int p, const double* __restrict__ X, const double* __restrict__ B,
+               const double* __restrict__ G, const double* __restrict__ KB,
+               double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  const int ldx = 2 * kNShift * p;
+  double acc[16];
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0;
+  for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < n * p;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t r = idx / p;
+    const int b = int(idx % p);
+    const double bv = B[idx];
+    for (int j = 0; j < kNShift; ++j) {
+      acc[2 * j] += X[r * ldx + 2 * p * j + b] * bv;
+      acc[2 * j + 1] += X[r * ldx + 2 * p * j + p + b] * bv;
+    }
+    acc[14] += G[idx] * bv;
+    if (KB) acc[15] += G[idx] * KB[idx];
+  }
+  for (int v = 0; v < 16; ++v) {
+    red[threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int st = kThreads / 2; st >= 1; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[size_t(blockIdx.x) * 16 + v] = red[0];
+    __syncthreads();
+  }
+}
+
 // small helpers
 template <typename TI, typename TO>
 __global__ void k_convert(int64_t count, const TI* __restrict__ in, TO* __restrict__ out, double scale) {

@@ -1,0 +1,100 @@
+"""Gradients of L = sum(W * e^{tA} B) through paper_1405_0707_amd.expmv
+(torch.autograd.Function over the C ABI):
+grad_B = e^{tA^T} W (the same solver on A^T), grad_t = <W, A e^{tA} B>.
+Checked against the oracle's direct rational solves with A^T, an exact
+directional derivative in B (L is linear in B), and central differences in t.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import exact
+from paper_1405_0707_amd import expmv
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def announce(name):
+    print(f"[gpu-test] {name}", flush=True)
+
+
+def vardiff_small(N=48, p=4):
+    """Reduced 2D log-normal diffusion (seed 205) with t = 0.1 as at 1024^2."""
+    return wl.c5(N=N, p=p, precision="fp64")
+
+
+def csr_tuple(W):
+    return (torch.from_numpy(W.A.rowptr), torch.from_numpy(W.A.colind), torch.from_numpy(W.A.val))
+
+
+@pytest.mark.parametrize("precision,tol_b,tol_t", [("fp64", 1e-9, 1e-6), ("mixed", 1e-4, 1e-4)])
+def test_grad_b_and_t(precision, tol_b, tol_t):
+    announce(f"autograd vardiff {precision}")
+    W = vardiff_small()
+    Wt = np.random.default_rng(105).standard_normal(W.B.shape)
+    B = torch.from_numpy(W.B).to(DEV).requires_grad_(True)
+    t = torch.tensor(W.t, dtype=torch.float64, requires_grad=True)
+    Z = expmv(csr_tuple(W), B, t, tol=1e-11 if precision == "fp64" else 1e-7, precision=precision)
+    Lv = torch.sum(torch.from_numpy(Wt).to(DEV) * Z)
+    Lv.backward()
+    M = (W.t * W.A.to_scipy()).tocsr()
+    gB_ref = exact.rational_sparse(M.T.tocsr(), Wt)
+    eb = rel(B.grad.cpu().numpy(), gB_ref)
+    # grad_t = <W, A Z>, Z from the oracle's direct solves
+    Zref = exact.rational_sparse(M, W.B)
+    gt_ref = float(np.sum(Wt * (W.A.to_scipy() @ Zref)))
+    et = abs(float(t.grad) - gt_ref) / abs(gt_ref)
+    print(f"{precision}: grad_B rel err {eb:.2e}, grad_t rel err {et:.2e}")
+    assert eb < tol_b
+    assert et < tol_t
+
+
+def test_grad_t_central_difference():
+    announce("grad_t central difference")
+    W = vardiff_small(N=40, p=3)
+    Wt = torch.from_numpy(np.random.default_rng(6).standard_normal(W.B.shape)).to(DEV)
+    B = torch.from_numpy(W.B).to(DEV)
+    A = csr_tuple(W)
+    t = torch.tensor(W.t, dtype=torch.float64, requires_grad=True)
+    L = torch.sum(Wt * expmv(A, B, t, tol=1e-12))
+    L.backward()
+    h = 1e-4 * W.t
+    Lp = float(torch.sum(Wt * expmv(A, B, W.t + h, tol=1e-12)))
+    Lm = float(torch.sum(Wt * expmv(A, B, W.t - h, tol=1e-12)))
+    fd = (Lp - Lm) / (2 * h)
+    print(f"grad_t {float(t.grad):.10e} fd {fd:.10e}")
+    assert abs(float(t.grad) - fd) <= 1e-6 * abs(fd)
+
+
+def test_grad_b_directional_is_exact():
+    announce("grad_B directional")
+    W = vardiff_small(N=40, p=3)
+    Wt = torch.from_numpy(np.random.default_rng(7).standard_normal(W.B.shape)).to(DEV)
+    A = csr_tuple(W)
+    B = torch.from_numpy(W.B).to(DEV).requires_grad_(True)
+    L = torch.sum(Wt * expmv(A, B, W.t, tol=1e-12))
+    L.backward()
+    dB = torch.from_numpy(np.random.default_rng(8).standard_normal(W.B.shape)).to(DEV)
+    L2 = torch.sum(Wt * expmv(A, B.detach() + dB, W.t, tol=1e-12))
+    lhs = float(L2 - L)
+    rhs = float(torch.sum(B.grad * dB))
+    assert abs(lhs - rhs) <= 1e-9 * abs(lhs)
+
+
+def test_nonsymmetric_grad_b_uses_transpose():
+    announce("autograd convdiff")
+    Wc = wl.c4(N=10, p=3, precision="fp64")
+    lam = np.linalg.eigvals(-Wc.A.to_scipy().toarray())
+    Wc.t = 3.33 / lam.real.min()
+    G = np.random.default_rng(9).standard_normal(Wc.B.shape)
+    B = torch.from_numpy(Wc.B).to(DEV).requires_grad_(True)
+    Z = expmv(csr_tuple(Wc), B, Wc.t, tol=1e-11)
+    torch.sum(torch.from_numpy(G).to(DEV) * Z).backward()
+    M = (Wc.t * Wc.A.to_scipy()).tocsr()
+    assert rel(B.grad.cpu().numpy(), exact.rational_sparse(M.T.tocsr(), G)) < 1e-9
