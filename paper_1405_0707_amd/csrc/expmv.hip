@@ -311,7 +311,7 @@ InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chu
     if (pending >= 0) {
       HIPCHK(hipEventSynchronize(pl->ev[pending]));
       const KrylovCtl* c = reinterpret_cast<const KrylovCtl*>(pl->host_flags + 4 * pending);
-      if (c->done) done = true;
+      if (c->done >= 0) done = true;
     }
     pending = slot;
     slot ^= 1;
@@ -358,7 +358,7 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
                                             A.dinv, r, pold, pnew, out, w.cgst.p, w.ctl.p,
                                             w.part_rr.p, tol2, maxit));
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_a<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[2] : z, sample ? e[3] : z, 0, int(n), p,
+                                            sample ? e[2] : z, sample ? e[3] : z, 0, k, int(n), p,
                                             A.rowptr, A.colind, A.val, pnew, q, w.ctl.p,
                                             w.part_sig.p));
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_b<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
@@ -400,13 +400,13 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
       DISPATCH_PP(PP, {
         hipLaunchKernelGGL((k_bcg_u1<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
                            r, pv, v, w.bcgst.p, w.ctl.p, w.part_rr.p, tol2, maxit);
-        hipLaunchKernelGGL((k_bcg_s<T, P_, 1>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p,
+        hipLaunchKernelGGL((k_bcg_s<T, P_, 1>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
                            A.rowptr, A.colind, A.val, A.dinv, pv, rh, v, w.ctl.p, w.part_sig.p);
-        hipLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p, r,
+        hipLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p, r,
                            v, sv, w.bcgst.p, w.ctl.p, w.part_sig.p);
-        hipLaunchKernelGGL((k_bcg_s<T, P_, 2>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p,
+        hipLaunchKernelGGL((k_bcg_s<T, P_, 2>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
                            A.rowptr, A.colind, A.val, A.dinv, sv, sv, tv, w.ctl.p, w.part_sig.p);
-        hipLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, int(n), p,
+        hipLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
                            A.dinv, pv, sv, tv, rh, out, r, w.bcgst.p, w.ctl.p, w.part_sig.p,
                            w.part_rr.p);
       });

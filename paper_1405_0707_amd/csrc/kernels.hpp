@@ -34,11 +34,26 @@ struct KrylovScalars {
 };
 
 struct KrylovCtl {
-  unsigned int counter;  // workgroup arrival counter of the last-workgroup reductions
-  int done;              // every column inactive
+  unsigned int counter;  // unused
+  int done;              // -1 while running; else the iteration whose first kernel
+                         // found every column inactive
   int iters_max;
   int hit_cap;
 };
+
+// A kernel of iteration k returns at once if the solve finished at an
+// earlier iteration (first kernel of an iteration: strictly earlier; the
+// later kernels: at this iteration or earlier).  `done` is one 32-bit word
+// written once per solve, so every workgroup sees either -1 or its final
+// value.
+__device__ inline bool finished_before(const KrylovCtl* ctl, int k) {
+  const int d = ctl->done;
+  return d >= 0 && d < k;
+}
+__device__ inline bool finished_by(const KrylovCtl* ctl, int k) {
+  const int d = ctl->done;
+  return d >= 0 && d <= k;
+}
 
 // ---------------------------------------------------------------------------
 // block reduction helpers
@@ -225,7 +240,7 @@ k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __rest
   write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
   write_col_partial<PP>(bb, red, part_rr, 2 * PP, PP);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->done = 0;
+    ctl->done = -1;
     ctl->iters_max = 0;
     ctl->hit_cap = 0;
     ctl->counter = 0u;
@@ -237,7 +252,7 @@ __global__ void __launch_bounds__(kCgThreads)
 k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
        const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x, CgState* st,
        KrylovCtl* ctl, const double* __restrict__ part_rr, double tol2, int maxit) {
-  if (ctl->done) return;
+  if (finished_before(ctl, k)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
   __shared__ double s_beta[PP], s_aprev[PP];
@@ -286,7 +301,8 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
     if (blockIdx.x == 0 && !any) {
       ctl->iters_max = itmax;
       ctl->hit_cap = hit;
-      ctl->done = 1;
+      __threadfence();
+      ctl->done = k;
     }
   }
   __syncthreads();
@@ -307,10 +323,10 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
 
 template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
-k_cg_a(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+k_cg_a(int k, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
        const T* __restrict__ val, const T* __restrict__ pk, T* __restrict__ q,
        const KrylovCtl* ctl, double* __restrict__ part_sig) {
-  if (ctl->done) return;
+  if (finished_by(ctl, k)) return;
   __shared__ double red[kCgThreads];
   const int c = threadIdx.x % PP;
   double sig = 0.0;
@@ -332,7 +348,7 @@ __global__ void __launch_bounds__(kCgThreads)
 k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const T* __restrict__ q,
        CgState* st, const KrylovCtl* ctl, const double* __restrict__ part_sig,
        double* __restrict__ part_rr) {
-  if (ctl->done) return;
+  if (finished_by(ctl, k)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[PP];
   __shared__ double s_alpha[PP];
@@ -382,9 +398,16 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
 // A column stops at |r| <= tol |b|, at the cap, or at a breakdown
 // (rho, (r^, v) or (t, t) zero); its later steps are zero.
 
-struct BcgState {
-  double rho[kMaxP], alpha[kMaxP], omega[kMaxP], bnorm2[kMaxP];
+// Scalars of iteration i live in slot i & 1: U1_i reads slot (i-1) & 1 and
+// writes slot i & 1 while every workgroup still reads the previous one.
+struct BcgSlot {
+  double rho[kMaxP], alpha[kMaxP], omega[kMaxP];
   int active[kMaxP], iters[kMaxP];
+};
+
+struct BcgState {
+  BcgSlot slot[2];
+  double bnorm2[kMaxP];
 };
 
 template <typename T, typename TS, int PP>
@@ -412,7 +435,7 @@ k_bcg_init(int n, int p, double sign, const TS* __restrict__ src, T* __restrict_
   write_col_partial<PP>(bb, red, part_rr, 2 * PP, 0);   // (r^, r) = |b|^2 at start
   write_col_partial<PP>(bb, red, part_rr, 2 * PP, PP);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->done = 0;
+    ctl->done = -1;
     ctl->iters_max = 0;
     ctl->hit_cap = 0;
     ctl->counter = 0u;
@@ -423,7 +446,7 @@ template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const T* __restrict__ v,
          BcgState* st, KrylovCtl* ctl, const double* __restrict__ part_rr, double tol2, int maxit) {
-  if (ctl->done) return;
+  if (finished_before(ctl, i)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
   __shared__ double s_beta[PP], s_om[PP];
@@ -438,6 +461,7 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
         const double rho = tot[cc], rn = tot[PP + cc];
         double bn, rho_prev, a_prev, om_prev;
         int act_prev, it;
+        const BcgSlot& prev = st->slot[(i + 1) & 1];
         if (i == 0) {
           bn = rn;
           act_prev = bn > 0.0;
@@ -445,11 +469,11 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
           rho_prev = a_prev = om_prev = 1.0;
         } else {
           bn = st->bnorm2[cc];
-          act_prev = st->active[cc];
-          it = st->iters[cc];
-          rho_prev = st->rho[cc];
-          a_prev = st->alpha[cc];
-          om_prev = st->omega[cc];
+          act_prev = prev.active[cc];
+          it = prev.iters[cc];
+          rho_prev = prev.rho[cc];
+          a_prev = prev.alpha[cc];
+          om_prev = prev.omega[cc];
         }
         act = act_prev && !(rn <= tol2 * bn);
         if (act && (it >= maxit || rho == 0.0 || om_prev == 0.0 || rho_prev == 0.0)) {
@@ -461,9 +485,10 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
           om = om_prev;
         }
         if (blockIdx.x == 0) {
-          st->rho[cc] = rho;
-          st->active[cc] = act;
-          st->iters[cc] = it + act;
+          BcgSlot& cur = st->slot[i & 1];
+          cur.rho[cc] = rho;
+          cur.active[cc] = act;
+          cur.iters[cc] = it + act;
           if (i == 0) st->bnorm2[cc] = bn;
         }
         if (it > itmax) itmax = it;
@@ -476,7 +501,8 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
     if (blockIdx.x == 0 && !any) {
       ctl->iters_max = itmax;
       ctl->hit_cap = hit;
-      ctl->done = 1;
+      __threadfence();
+      ctl->done = i;
     }
   }
   __syncthreads();
@@ -496,11 +522,11 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
 // out = K D^{-1} in, partials (a, out) [NV = 1] or (out, a), (out, out) [NV = 2]
 template <typename T, int PP, int NV>
 __global__ void __launch_bounds__(kCgThreads)
-k_bcg_s(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
         const T* __restrict__ val, const T* __restrict__ dinv, const T* __restrict__ in,
         const T* __restrict__ a, T* __restrict__ out, const KrylovCtl* ctl,
         double* __restrict__ part) {
-  if (ctl->done) return;
+  if (finished_by(ctl, i)) return;
   __shared__ double red[kCgThreads];
   const int c = threadIdx.x % PP;
   double d0 = 0.0, d1 = 0.0;
@@ -527,18 +553,19 @@ k_bcg_s(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restr
 
 template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
-k_bcg_u2(int n, int p, const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ sv,
+k_bcg_u2(int i, int n, int p, const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ sv,
          BcgState* st, const KrylovCtl* ctl, const double* __restrict__ part) {
-  if (ctl->done) return;
+  if (finished_by(ctl, i)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[PP];
   __shared__ double s_a[PP];
   reduce_parts<PP, 1>(part, gridDim.x, red, tot);
   if (threadIdx.x < PP) {
     const int cc = threadIdx.x;
+    BcgSlot& cur = st->slot[i & 1];
     double a = 0.0;
-    if (cc < p && st->active[cc] && tot[cc] != 0.0) a = st->rho[cc] / tot[cc];
-    if (cc < p && blockIdx.x == 0) st->alpha[cc] = a;
+    if (cc < p && cur.active[cc] && tot[cc] != 0.0) a = cur.rho[cc] / tot[cc];
+    if (cc < p && blockIdx.x == 0) cur.alpha[cc] = a;
     s_a[cc] = a;
   }
   __syncthreads();
@@ -556,23 +583,24 @@ k_bcg_u2(int n, int p, const T* __restrict__ r, const T* __restrict__ v, T* __re
 
 template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
-k_bcg_u3(int n, int p, const T* __restrict__ dinv, const T* __restrict__ pv,
+k_bcg_u3(int i, int n, int p, const T* __restrict__ dinv, const T* __restrict__ pv,
          const T* __restrict__ sv, const T* __restrict__ tv, const T* __restrict__ rhat,
          T* __restrict__ x, T* __restrict__ r, BcgState* st, const KrylovCtl* ctl,
          const double* __restrict__ part, double* __restrict__ part_rr) {
-  if (ctl->done) return;
+  if (finished_by(ctl, i)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
   __shared__ double s_a[PP], s_om[PP];
   reduce_parts<PP, 2>(part, gridDim.x, red, tot);   // tot[c] = (t, s), tot[PP + c] = (t, t)
   if (threadIdx.x < PP) {
     const int cc = threadIdx.x;
+    BcgSlot& cur = st->slot[i & 1];
     double a = 0.0, om = 0.0;
-    if (cc < p && st->active[cc]) {
-      a = st->alpha[cc];
+    if (cc < p && cur.active[cc]) {
+      a = cur.alpha[cc];
       om = tot[PP + cc] != 0.0 ? tot[cc] / tot[PP + cc] : 0.0;
     }
-    if (cc < p && blockIdx.x == 0) st->omega[cc] = om;
+    if (cc < p && blockIdx.x == 0) cur.omega[cc] = om;
     s_a[cc] = a;
     s_om[cc] = om;
   }

@@ -42,10 +42,10 @@ k_fft_pass(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __re
       }
     }
     cplx V[R];
-    if (R == 2) {
+    if constexpr (R == 2) {
       V[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
       V[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
-    } else if (R == 4) {
+    } else if constexpr (R == 4) {
       const cplx a{v[0].x + v[2].x, v[0].y + v[2].y}, b{v[0].x - v[2].x, v[0].y - v[2].y};
       const cplx c2{v[1].x + v[3].x, v[1].y + v[3].y}, d{v[1].x - v[3].x, v[1].y - v[3].y};
       // d * (sign i)

@@ -317,3 +317,17 @@ def test_toeplitz_full_size_properties():
     lhs = float(torch.sum(Wt * Z))
     rhs = float(torch.sum(ZW * B))
     assert abs(lhs - rhs) <= 1e-9 * abs(lhs)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-11), ("mixed", 1e-5)])
+def test_bicgstab_wide_block_full_grid(precision, bar):
+    """p = 16 on 32^3 launches the inner solver's full 512-workgroup grid;
+    regression test for the scalars of one iteration being overwritten while
+    other workgroups of the same kernel still read them."""
+    announce(f"BiCGStab 32^3 p=16 {precision}")
+    W = wl.c4(N=32, p=16, precision="fp64")
+    pl = plan_for(W, precision=precision, inner_maxit=2000)
+    Y, iters = pl.apply_inverse(torch.from_numpy(W.B))
+    M = (W.t * W.A.to_scipy()).tocsr()
+    res = np.linalg.norm(M @ Y.cpu().numpy() - W.B) / np.linalg.norm(W.B)
+    assert iters < 200 and res < bar
