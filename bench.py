@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the solve, copy a 256 MiB buffer 3 times (a plain copy kernel "
                          "of known size, used to scale HBM byte counters)")
+    ap.add_argument("--suite", action="store_true",
+                    help="also time the Toeplitz, convection-diffusion (FP64 and mixed) and "
+                         "variable-coefficient (forward + adjoint) workloads; reported under "
+                         "'suite'")
+    ap.add_argument("--vardiff-n", type=int, default=256,
+                    help="grid side of the variable-coefficient workload in --suite")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="sample every N-th inner iteration with HIP events (0 = off)")
     return ap.parse_args()
@@ -81,6 +87,84 @@ def cpu_baseline(W):
                        f"{info.op_columns} of {full_cols} A^-1 column applications), "
                        f"{el:.2f} s measured, scaled x{scale:.1f} by A^-1 applications; "
                        "MGS cost grows faster than linearly, so this underestimates")}
+
+
+def run_suite(dev, vardiff_n):
+    """Secondary measurements: one timed solve each (the Toeplitz one after a
+    warm-up; the large ones cold, their first-call setup being negligible)."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1405_0707_amd import Plan
+
+    def timed(fn, name, warm=True):
+        if warm:
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            print(f"[suite] {name}: warm-up {time.perf_counter() - t0:.2f} s", file=sys.stderr,
+                  flush=True)
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(f"[suite] {name}: {el:.2f} s", file=sys.stderr, flush=True)
+        return el, out
+
+    res = {}
+    # Toeplitz 2^20, p = 16, FP64
+    W = wl.c3()
+    pl = Plan.toeplitz(torch.from_numpy(W.col), W.t, device=dev, m=W.m, k=W.k)
+    B = torch.from_numpy(W.B).to(dev)
+    el, (Z, info) = timed(lambda: pl.execute(B, tol=W.tol), "toeplitz")
+    res["toeplitz_2^20_p16_fp64"] = {"s": round(el, 4), "cycles": info.cycles,
+                                     "err_bound": info.err_bound}
+    del pl, B, Z
+    # convection-diffusion 128^3, p = 16: FP64 (tol 1e-10) and mixed (tol 1e-6)
+    W = wl.c4()
+    print("[suite] convection-diffusion 128^3 built", file=sys.stderr, flush=True)
+    B = torch.from_numpy(W.B).to(dev)
+    Zs = {}
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        pl = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=dev, m=W.m, k=W.k,
+                      precision=prec)
+        el, (Z, info) = timed(lambda: pl.execute(B, tol=tol, allow=(4,)), f"convdiff {prec}",
+                              warm=False)
+        Zs[prec] = Z
+        res[f"convdiff_128^3_p16_{prec}"] = {"s": round(el, 4), "cycles": info.cycles,
+                                             "inner_iters": int(info.inner_iters),
+                                             "err_bound": info.err_bound}
+        del pl
+    res["convdiff_mixed_vs_fp64_rel_diff"] = float(torch.linalg.norm(Zs["mixed"] - Zs["fp64"])
+                                                   / torch.linalg.norm(Zs["fp64"]))
+    del Zs, B
+    # variable-coefficient diffusion, forward + adjoint, mixed and FP64
+    N = vardiff_n
+    W = wl.c5(N=N)
+    G = torch.from_numpy(wl.gaussian_block(N * N, W.p, 105)).to(dev)
+    B = torch.from_numpy(W.B).to(dev)
+    outs = {}
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-6)):
+        pl = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=dev, m=W.m, k=W.k,
+                      precision=prec, inner_maxit=200000)
+        el_f, (Z, info_f) = timed(lambda: pl.execute(B, tol=tol, allow=(4,)),
+                                  f"vardiff fwd {prec}", warm=False)
+        el_b, (gB, gt, info_b) = timed(lambda: pl.adjoint(G, B, tol=tol, allow=(4,)),
+                                       f"vardiff adjoint {prec}", warm=False)
+        outs[prec] = (Z, gB, gt)
+        res[f"vardiff_{N}^2_p32_{prec}"] = {"forward_s": round(el_f, 4),
+                                            "adjoint_s": round(el_b, 4),
+                                            "cycles_fwd": info_f.cycles,
+                                            "inner_iters_fwd": int(info_f.inner_iters)}
+        del pl
+    z64, g64, t64 = outs["fp64"]
+    zm, gm, tm = outs["mixed"]
+    res["vardiff_mixed_vs_fp64"] = {
+        "Z_rel_diff": float(torch.linalg.norm(zm - z64) / torch.linalg.norm(z64)),
+        "gradB_rel_diff": float(torch.linalg.norm(gm - g64) / torch.linalg.norm(g64)),
+        "gradt_rel_diff": abs(tm - t64) / abs(t64)}
+    return res
 
 
 def main():
@@ -152,6 +236,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    suite = run_suite(dev, args.vardiff_n) if args.suite else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(W)
@@ -175,6 +261,8 @@ def main():
         "inner_kernels": kernels,
         "cpu_baseline": cpu,
     }
+    if suite is not None:
+        out["suite"] = suite
     print(json.dumps(out), flush=True)
 
 

@@ -53,7 +53,14 @@ typedef enum {
                             iterate of the cycle where it happened */
 } expmv_status;
 
-typedef enum { EXPMV_FP64 = 0, EXPMV_MIXED = 1 } expmv_precision;
+typedef enum {
+  EXPMV_FP64 = 0,         /* everything in FP64 */
+  EXPMV_MIXED = 1,        /* FP32 inner solver, SpMM vectors, Krylov basis and its
+                             Gram-Schmidt traffic; FP64 operator values, projections,
+                             Gram/Cholesky, H, projected solves, X, combination */
+  EXPMV_MIXED_INNER = 2   /* FP32 inner solver only (the dominant cost); Krylov basis
+                             and everything else FP64 */
+} expmv_precision;
 
 typedef enum {
   EXPMV_STOP_PAPER = 0,  /* max_j rho_j <= tol * ||B||_F, rho_j the residual norm of
@@ -79,6 +86,9 @@ typedef struct {
                           (Krylov space of tA, no inner solve)                            */
   int profile;         /* 0: off; N > 0: time every N-th inner-solver iteration's
                           kernels with HIP events (results in expmv_info.kern_*)          */
+  int inner_refine;    /* mixed forms: rounds of FP64 iterative refinement of each FP32
+                          inner solve (FP64 residual with the exact operator, FP32
+                          correction solve); -1 = 1 for nonsymmetric A, 0 otherwise      */
 } expmv_opts;
 
 typedef struct {                  /* host struct, filled by expmv_execute */
@@ -102,13 +112,12 @@ typedef struct expmv_plan_s* expmv_plan;
 
 /* Fill *o with the defaults: m = 10, k = 0 (auto), max_cycles = 50, FP64,
  * EXPMV_STOP_BOUND, inner_tol = 0 (auto), inner_maxit = 50000, symmetric = -1,
- * preconditioned = 1, profile = 0.  o is a host pointer. */
+ * preconditioned = 1, profile = 0, inner_refine = -1.  o is a host pointer. */
 expmv_status expmv_default_opts(expmv_opts* o);
 
 /* Plan for Z = e^{tA} B with A in CSR (device arrays, see conventions).
- * The plan stores K = -tA (FP64, plus an FP32 copy in the mixed form), the
- * Jacobi scaling 1/diag(K), the transpose of K when A is not symmetric, and
- * the CF table.  opts may be NULL (defaults).  *out receives the plan.
+ * The plan stores K = -tA (FP64 values in both forms), the Jacobi scaling
+ * 1/diag(K), the transpose of K when A is not symmetric, and the CF table.  opts may be NULL (defaults).  *out receives the plan.
  * Errors: EINVAL, ENOTNEG (a diagonal entry of tA >= 0, or missing), ENOMEM,
  * EHIP. */
 expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr,

@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libexpmv.so")
 
 OK, EINVAL, ENOTNEG, ENOMEM, ENOCONV, EBREAKDOWN, EHIP, EINNER = range(8)
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_INNER = 0, 1, 2
 STOP_PAPER, STOP_BOUND = 0, 1
 
 
@@ -16,7 +16,7 @@ class Opts(C.Structure):
     _fields_ = [("m", C.c_int), ("k", C.c_int), ("max_cycles", C.c_int),
                 ("precision", C.c_int), ("stop_rule", C.c_int), ("inner_tol", C.c_double),
                 ("inner_maxit", C.c_int), ("symmetric", C.c_int), ("preconditioned", C.c_int),
-                ("profile", C.c_int)]
+                ("profile", C.c_int), ("inner_refine", C.c_int)]
 
 
 class Info(C.Structure):

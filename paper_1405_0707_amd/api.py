@@ -26,7 +26,7 @@ def default_opts(**kw) -> Opts:
     lib().expmv_default_opts(C.byref(o))
     for key, v in kw.items():
         if key == "precision" and isinstance(v, str):
-            v = {"fp64": _lib.FP64, "mixed": _lib.MIXED}[v]
+            v = {"fp64": _lib.FP64, "mixed": _lib.MIXED, "mixed_inner": _lib.MIXED_INNER}[v]
         if key == "stop_rule" and isinstance(v, str):
             v = {"paper": _lib.STOP_PAPER, "bound": _lib.STOP_BOUND}[v]
         if not hasattr(o, key):

@@ -15,6 +15,7 @@
 #include <memory>
 #include <new>
 #include <numeric>
+#include <type_traits>
 #include <vector>
 
 #include "eig_host.hpp"
@@ -79,7 +80,9 @@ static int pow2_lanes(int p) {
 struct Workspace {
   int p = 0;
   DevBuf<char> V[2];            // basis panels, (m+1) * n * p elements each
-  DevBuf<char> W, Wt;           // n x p
+  DevBuf<char> W, Wt;           // n x p (basis type)
+  DevBuf<char> Win, Wout;       // n x p (inner-solver type, when it differs)
+  DevBuf<char> Rin, Din;        // n x p (inner-solver type, refinement)
   DevBuf<char> kr, kpa, kpb, kq, kv, ks, kt, krh;   // inner-solver vectors, n x p
   DevBuf<double> X;             // n x 14p
   DevBuf<double> partial;       // reductions of the dense kernels
@@ -109,8 +112,9 @@ struct expmv_plan_s {
   // K = -tA in CSR (FP64) and its transpose (nonsymmetric only)
   DevBuf<int32_t> rowptr, colind, rowptrT, colindT;
   DevBuf<double> val, valT, dinv, dinvT;
-  DevBuf<float> valf, valTf, dinvf, dinvTf;   // FP32 copies (mixed form)
-  bool mixed = false;
+  DevBuf<float> dinvf, dinvTf;   // FP32 Jacobi scaling (mixed forms)
+  bool mixed = false;            // FP32 inner solver
+  bool basis32 = false;          // FP32 Krylov basis (EXPMV_MIXED)
   // Toeplitz operator: L = 2n circulant embedding; spectra of the embedded
   // first column (chat), of x = T^{-1} e_1 and of Z x~ (Gohberg-Semencul)
   int64_t L = 0;
@@ -162,12 +166,19 @@ void ensure_workspace(expmv_plan_s* pl, int p) {
   const int ldh = (m + 1) * p;
   pl->ldh = ldh;
   if (w.p == p) return;
-  const size_t el = pl->mixed ? sizeof(float) : sizeof(double);
+  const size_t elb = pl->basis32 ? sizeof(float) : sizeof(double);   // basis
+  const size_t el = pl->mixed ? sizeof(float) : sizeof(double);      // inner solver
   const size_t blk = size_t(n) * p;
-  w.V[0].alloc(blk * npan_max * el);
-  w.V[1].alloc(blk * npan_max * el);
-  w.W.alloc(blk * el);
-  w.Wt.alloc(blk * el);
+  w.V[0].alloc(blk * npan_max * elb);
+  w.V[1].alloc(blk * npan_max * elb);
+  w.W.alloc(blk * std::max(elb, el));
+  w.Wt.alloc(blk * std::max(elb, el));
+  w.Win.alloc(blk * el);
+  w.Wout.alloc(blk * el);
+  if (pl->mixed) {
+    w.Rin.alloc(blk * el);
+    w.Din.alloc(blk * el);
+  }
   w.kr.alloc(blk * el);
   w.kpa.alloc(blk * el);
   w.kpb.alloc(blk * el);
@@ -215,8 +226,8 @@ template <typename T>
 struct Csr {
   const int32_t* rowptr;
   const int32_t* colind;
-  const T* val;
-  const T* dinv;
+  const double* val;   // FP64 in both forms
+  const T* dinv;       // Jacobi scaling in the working type
 };
 
 template <typename T>
@@ -232,8 +243,8 @@ Csr<double> csr_of<double>(expmv_plan_s* pl, int transpose) {
 template <>
 Csr<float> csr_of<float>(expmv_plan_s* pl, int transpose) {
   const bool tr = transpose && !pl->symmetric;
-  return tr ? Csr<float>{pl->rowptrT.p, pl->colindT.p, pl->valTf.p, pl->dinvTf.p}
-            : Csr<float>{pl->rowptr.p, pl->colind.p, pl->valf.p, pl->dinvf.p};
+  return tr ? Csr<float>{pl->rowptrT.p, pl->colindT.p, pl->valT.p, pl->dinvTf.p}
+            : Csr<float>{pl->rowptr.p, pl->colind.p, pl->val.p, pl->dinvf.p};
 }
 
 // Y = K X (K = -tA, or its transpose) for n x p blocks of type T.
@@ -762,7 +773,49 @@ RitzBasis ritz_basis(bool symmetric, bool precond, int dl, const std::vector<dou
 // -------------------------------------------------------------------------
 // the method
 
-template <typename T>
+// Preconditioner application between basis type T and inner-solver type TI.
+// In the mixed forms each FP32 solve may be followed by rounds of iterative
+// refinement: R = V - M W in FP64 with the exact operator, D = M^{-1} R by
+// the FP32 solver, W += D.
+template <typename T, typename TI>
+InnerResult apply_inverse_mixed(expmv_plan_s* pl, int transpose, const T* V, T* Wout, int p) {
+  int rounds = 0;
+  if (!std::is_same<TI, double>::value && pl->kind == 0)
+    rounds = pl->opts.inner_refine >= 0 ? pl->opts.inner_refine : (pl->symmetric ? 0 : 1);
+  const int64_t cnt = pl->n * int64_t(p);
+  hipStream_t s = pl->stream;
+  InnerResult total{0, 0};
+  auto accumulate = [&](InnerResult r) {
+    total.iters += r.iters;
+    total.hit_cap |= r.hit_cap;
+  };
+  if constexpr (std::is_same<T, TI>::value) {
+    accumulate(apply_inverse<T>(pl, transpose, V, Wout, p));
+  } else {
+    TI* vi = reinterpret_cast<TI*>(pl->ws.Win.p);
+    TI* wi = reinterpret_cast<TI*>(pl->ws.Wout.p);
+    hipLaunchKernelGGL((k_convert<T, TI>), dim3(512), dim3(kThreads), 0, s, cnt, V, vi, 1.0);
+    accumulate(apply_inverse<TI>(pl, transpose, vi, wi, p));
+    hipLaunchKernelGGL((k_convert<TI, T>), dim3(512), dim3(kThreads), 0, s, cnt, wi, Wout, 1.0);
+  }
+  if (rounds > 0) {
+    Csr<double> A = csr_of<double>(pl, transpose);
+    TI* ri = reinterpret_cast<TI*>(pl->ws.Rin.p);
+    TI* di = reinterpret_cast<TI*>(pl->ws.Din.p);
+    const int PP = pow2_lanes(p);
+    const int grid = grid_for(pl->n, PP, 4096);
+    for (int r = 0; r < rounds; ++r) {
+      DISPATCH_PP(PP, hipLaunchKernelGGL((k_refine_residual<T, TI, P_>), dim3(grid), dim3(kThreads),
+                                         0, s, int(pl->n), p, A.rowptr, A.colind, A.val, V, Wout,
+                                         ri));
+      accumulate(apply_inverse<TI>(pl, transpose, ri, di, p));
+      hipLaunchKernelGGL((k_add_to<T, TI>), dim3(512), dim3(kThreads), 0, s, cnt, di, Wout);
+    }
+  }
+  return total;
+}
+
+template <typename T, typename TI>
 expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
                           double* Z, expmv_info* info) {
   hipStream_t s = pl->stream;
@@ -836,7 +889,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       double t0 = host_now_ms();
       const T* Vj = Vb + size_t(jb) * blk;
       if (precond) {
-        InnerResult r = apply_inverse<T>(pl, transpose, Vj, Wk, p);
+        InnerResult r = apply_inverse_mixed<T, TI>(pl, transpose, Vj, Wk, p);
         inf.inner_iters += r.iters;
         inf.inner_maxit_hit += r.hit_cap;
       } else {
@@ -1017,6 +1070,13 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   return status;
 }
 
+expmv_status dispatch_execute(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
+                              double* Z, expmv_info* info) {
+  if (pl->basis32) return execute_impl<float, float>(pl, transpose, B, p, tol, Z, info);
+  if (pl->mixed) return execute_impl<double, float>(pl, transpose, B, p, tol, Z, info);
+  return execute_impl<double, double>(pl, transpose, B, p, tol, Z, info);
+}
+
 }  // namespace
 }  // namespace expmv
 
@@ -1044,11 +1104,13 @@ bool valid_opts(const expmv_opts& o) {
   if (o.m < 2 || o.m > 64) return false;
   if (o.k < 0) return false;
   if (o.max_cycles < 1) return false;
-  if (o.precision != EXPMV_FP64 && o.precision != EXPMV_MIXED) return false;
+  if (o.precision != EXPMV_FP64 && o.precision != EXPMV_MIXED && o.precision != EXPMV_MIXED_INNER)
+    return false;
   if (o.stop_rule != EXPMV_STOP_PAPER && o.stop_rule != EXPMV_STOP_BOUND) return false;
   if (!(o.inner_tol >= 0.0 && o.inner_tol < 1.0)) return false;
   if (o.inner_maxit < 1) return false;
   if (o.profile < 0) return false;
+  if (o.inner_refine < -1 || o.inner_refine > 8) return false;
   return true;
 }
 
@@ -1154,16 +1216,11 @@ expmv_status build_csr(expmv_plan_s* pl, const int32_t* rowptr_d, const int32_t*
   HIPCHK(hipMemcpy(pl->val.p, v.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(pl->dinv.p, dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
   if (pl->mixed) {
-    std::vector<float> vf(v.begin(), v.end()), df(dinv.begin(), dinv.end());
-    pl->valf.alloc(std::max<int64_t>(nnz, 1));
+    std::vector<float> df(dinv.begin(), dinv.end());
     pl->dinvf.alloc(n);
-    HIPCHK(hipMemcpy(pl->valf.p, vf.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(pl->dinvf.p, df.data(), sizeof(float) * n, hipMemcpyHostToDevice));
     if (!sym) {
-      std::vector<float> vtf(vt.begin(), vt.end());
-      pl->valTf.alloc(std::max<int64_t>(nnz, 1));
       pl->dinvTf.alloc(n);
-      HIPCHK(hipMemcpy(pl->valTf.p, vtf.data(), sizeof(float) * nnz, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(pl->dinvTf.p, df.data(), sizeof(float) * n, hipMemcpyHostToDevice));
     }
   }
@@ -1196,6 +1253,7 @@ expmv_status expmv_default_opts(expmv_opts* o) {
   o->symmetric = -1;
   o->preconditioned = 1;
   o->profile = 0;
+  o->inner_refine = -1;
   return EXPMV_OK;
 }
 
@@ -1219,7 +1277,8 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const
     pl->t = t;
     pl->opts = o;
     pl->stream = stream;
-    pl->mixed = (o.precision == EXPMV_MIXED);
+    pl->mixed = (o.precision != EXPMV_FP64);
+    pl->basis32 = (o.precision == EXPMV_MIXED);
     init_plan_common(pl.get());
     expmv_status st = build_csr(pl.get(), rowptr, colind, val);
     if (st != EXPMV_OK) return st;
@@ -1247,7 +1306,8 @@ expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t, const 
     pl->t = t;
     pl->opts = o;
     pl->stream = stream;
-    pl->mixed = (o.precision == EXPMV_MIXED);
+    pl->mixed = (o.precision != EXPMV_FP64);
+    pl->basis32 = (o.precision == EXPMV_MIXED);
     pl->symmetric = true;
     init_plan_common(pl.get());
     hipStream_t s = stream;
@@ -1327,10 +1387,7 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
                            double* Z, expmv_info* info) {
   if (!plan || !B || !Z || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
-  return guarded([&]() {
-    return plan->mixed ? execute_impl<float>(plan, transpose, B, int(p), tol, Z, info)
-                       : execute_impl<double>(plan, transpose, B, int(p), tol, Z, info);
-  });
+  return guarded([&]() { return dispatch_execute(plan, transpose, B, int(p), tol, Z, info); });
 }
 
 expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, int64_t p,
@@ -1339,8 +1396,7 @@ expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, in
     return EXPMV_EINVAL;
   if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
-    expmv_status st = plan->mixed ? execute_impl<float>(plan, 1, G, int(p), tol, gradB, info)
-                                  : execute_impl<double>(plan, 1, G, int(p), tol, gradB, info);
+    expmv_status st = dispatch_execute(plan, 1, G, int(p), tol, gradB, info);
     if (st != EXPMV_OK && st != EXPMV_ENOCONV) return st;
     hipStream_t s = plan->stream;
     Workspace& w = plan->ws;

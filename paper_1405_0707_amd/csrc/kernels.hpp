@@ -109,22 +109,26 @@ __device__ inline void xcd_rows(int64_t n, int64_t& r0, int64_t& r1) {
 
 // acc (+)= sum_e val[e] * x[colind[e] * ld + c] over one CSR row, in order,
 // with four independent gathers in flight per step.
+// The operator's values are FP64 for every working type T: in the mixed
+// form the FP32 inner solver thus works with the exact operator (rounding
+// its entries to FP32 would move the eigenvalues of a non-normal operator
+// by the eigenvector condition number times 6e-8).
 template <typename T>
-__device__ inline T csr_row_dot(const int32_t* __restrict__ colind, const T* __restrict__ val,
+__device__ inline T csr_row_dot(const int32_t* __restrict__ colind, const double* __restrict__ val,
                                 const T* __restrict__ x, int e0, int e1, int ld, int c) {
-  T acc = T(0);
+  double acc = 0.0;
   int e = e0;
   for (; e + 4 <= e1; e += 4) {
     const int64_t j0 = colind[e], j1 = colind[e + 1], j2 = colind[e + 2], j3 = colind[e + 3];
-    const T v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
+    const double v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
     const T x0 = x[j0 * ld + c], x1 = x[j1 * ld + c], x2 = x[j2 * ld + c], x3 = x[j3 * ld + c];
-    acc += v0 * x0;
-    acc += v1 * x1;
-    acc += v2 * x2;
-    acc += v3 * x3;
+    acc += v0 * double(x0);
+    acc += v1 * double(x1);
+    acc += v2 * double(x2);
+    acc += v3 * double(x3);
   }
-  for (; e < e1; ++e) acc += val[e] * x[int64_t(colind[e]) * ld + c];
-  return acc;
+  for (; e < e1; ++e) acc += val[e] * double(x[int64_t(colind[e]) * ld + c]);
+  return T(acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -133,7 +137,7 @@ __device__ inline T csr_row_dot(const int32_t* __restrict__ colind, const T* __r
 template <typename T, int PP>
 __global__ void __launch_bounds__(kThreads)
 k_spmm(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-       const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
+       const double* __restrict__ val, const T* __restrict__ x, T* __restrict__ y) {
   const int c = threadIdx.x % PP;
   const int64_t rows_per_grid = int64_t(gridDim.x) * (kThreads / PP);
   for (int64_t row = int64_t(blockIdx.x) * (kThreads / PP) + threadIdx.x / PP; row < n;
@@ -324,7 +328,7 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
 template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_a(int k, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-       const T* __restrict__ val, const T* __restrict__ pk, T* __restrict__ q,
+       const double* __restrict__ val, const T* __restrict__ pk, T* __restrict__ q,
        const KrylovCtl* ctl, double* __restrict__ part_sig) {
   if (finished_by(ctl, k)) return;
   __shared__ double red[kCgThreads];
@@ -523,7 +527,7 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
 template <typename T, int PP, int NV>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-        const T* __restrict__ val, const T* __restrict__ dinv, const T* __restrict__ in,
+        const double* __restrict__ val, const T* __restrict__ dinv, const T* __restrict__ in,
         const T* __restrict__ a, T* __restrict__ out, const KrylovCtl* ctl,
         double* __restrict__ part) {
   if (finished_by(ctl, i)) return;
@@ -535,11 +539,12 @@ k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* 
   for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
     if (c < p) {
       const int e0 = rowptr[row], e1 = rowptr[row + 1];
-      T acc = T(0);
+      double accd = 0.0;
       for (int e = e0; e < e1; ++e) {
         const int64_t j = colind[e];
-        acc += val[e] * (dinv[j] * in[j * p + c]);
+        accd += val[e] * double(dinv[j] * in[j * p + c]);
       }
+      const T acc = T(accd);
       const int64_t idx = row * p + c;
       out[idx] = acc;
       const double o = double(acc), av = double(a[idx]);
@@ -624,6 +629,35 @@ k_bcg_u3(int i, int n, int p, const T* __restrict__ dinv, const T* __restrict__ 
   }
   write_col_partial<PP>(rr_hat, red, part_rr, 2 * PP, 0);
   write_col_partial<PP>(rr, red, part_rr, 2 * PP, PP);
+}
+
+// R = V + K W (the residual of M W = V, M = -K) in FP64 from blocks of type
+// T, stored as TI: the right-hand side of a refinement step.
+template <typename T, typename TI, int PP>
+__global__ void __launch_bounds__(kThreads)
+k_refine_residual(int n, int p, const int32_t* __restrict__ rowptr,
+                  const int32_t* __restrict__ colind, const double* __restrict__ val,
+                  const T* __restrict__ V, const T* __restrict__ W, TI* __restrict__ R) {
+  const int c = threadIdx.x % PP;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (kThreads / PP);
+  for (int64_t row = int64_t(blockIdx.x) * (kThreads / PP) + threadIdx.x / PP; row < n;
+       row += rows_per_grid) {
+    if (c < p) {
+      double acc = double(V[row * p + c]);
+      for (int e = rowptr[row]; e < rowptr[row + 1]; ++e)
+        acc += val[e] * double(W[int64_t(colind[e]) * p + c]);
+      R[row * p + c] = TI(acc);
+    }
+  }
+}
+
+// W += D (types may differ)
+template <typename T, typename TI>
+__global__ void __launch_bounds__(kThreads)
+k_add_to(int64_t count, const TI* __restrict__ D, T* __restrict__ W) {
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < count;
+       i += int64_t(gridDim.x) * kThreads)
+    W[i] = T(double(W[i]) + double(D[i]));
 }
 
 // out = (double) x
