@@ -89,6 +89,13 @@ typedef struct {
   int inner_refine;    /* mixed forms: rounds of FP64 iterative refinement of each FP32
                           inner solve (FP64 residual with the exact operator, FP32
                           correction solve); -1 = 1 for nonsymmetric A, 0 otherwise      */
+  int inner_precond;   /* preconditioner of the CSR inner solver (the solve that applies
+                          (tA)^{-1}, Section 4.1): 0 Jacobi (diagonal scaling),
+                          1 smoothed-aggregation AMG V-cycle (symmetric A only; A with
+                          n <= 500 has no coarse level and keeps Jacobi),
+                          -1 auto = AMG for symmetric A with n >= 4096, else Jacobi     */
+  int amg_degree;      /* Chebyshev smoothing steps before and after each coarse
+                          correction (1..4; 0 = 2)                                       */
 } expmv_opts;
 
 typedef struct {                  /* host struct, filled by expmv_execute */
@@ -106,20 +113,27 @@ typedef struct {                  /* host struct, filled by expmv_execute */
   double kern_ms_a, kern_ms_b,    /* mean device time of the inner CG's kernels, ms:  */
          kern_ms_c;               /* A = CSR SpMM q = K p, B = residual update,
                                      C = search-direction and iterate update          */
+  int amg_levels;                 /* levels of the AMG hierarchy of the inner solver
+                                     (0: Jacobi preconditioning)                      */
 } expmv_info;
 
 typedef struct expmv_plan_s* expmv_plan;
 
 /* Fill *o with the defaults: m = 10, k = 0 (auto), max_cycles = 50, FP64,
  * EXPMV_STOP_BOUND, inner_tol = 0 (auto), inner_maxit = 50000, symmetric = -1,
- * preconditioned = 1, profile = 0, inner_refine = -1.  o is a host pointer. */
+ * preconditioned = 1, profile = 0, inner_refine = -1, inner_precond = -1,
+ * amg_degree = 0.  o is a host pointer. */
 expmv_status expmv_default_opts(expmv_opts* o);
 
 /* Plan for Z = e^{tA} B with A in CSR (device arrays, see conventions).
  * The plan stores K = -tA (FP64 values in both forms), the Jacobi scaling
- * 1/diag(K), the transpose of K when A is not symmetric, and the CF table.  opts may be NULL (defaults).  *out receives the plan.
- * Errors: EINVAL, ENOTNEG (a diagonal entry of tA >= 0, or missing), ENOMEM,
- * EHIP. */
+ * 1/diag(K), the transpose of K when A is not symmetric, the CF table, and,
+ * with the AMG inner preconditioner, the hierarchy built on the host from K
+ * (levels, prolongators, Galerkin operators, dense inverse of the coarsest
+ * operator).  opts may be NULL (defaults).  *out receives the plan.
+ * Errors: EINVAL (also: inner_precond = 1 with a nonsymmetric A, or an AMG
+ * hierarchy that cannot be built), ENOTNEG (a diagonal entry of tA >= 0, or
+ * missing), ENOMEM, EHIP. */
 expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
                             const int32_t* colind, const double* val, double t,
                             const expmv_opts* opts, hipStream_t stream, expmv_plan* out);
@@ -166,6 +180,14 @@ expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* 
 expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X,
                                  int64_t p, double* Y, long long* iters);
 
+/* Y = P X, one application of the CSR inner solver's preconditioner P for
+ * K = -tA (or K^T when transpose = 1): P = D^{-1} (Jacobi) or one AMG
+ * V-cycle, so that Y ~= K^{-1} X = -(tA)^{-1} X.  X, Y device n x p
+ * (1 <= p <= 32), not overlapping.  Errors: EINVAL (Toeplitz plan, bad
+ * arguments), EHIP. */
+expmv_status expmv_apply_preconditioner(expmv_plan plan, int transpose, const double* X,
+                                        int64_t p, double* Y);
+
 /* Copy the library's CF table to host arrays of 7 entries (poles with
  * Im tau > 0, c_j = 2 omega_j) and *omega0.  Any pointer may be NULL. */
 expmv_status expmv_cf_table(double* tau_re, double* tau_im, double* c_re, double* c_im,
@@ -180,6 +202,34 @@ expmv_status expmv_cf_table(double* tau_re, double* tau_im, double* c_re, double
 expmv_status expmv_host_eig_sym(int n, const double* A, double* w, double* Q);
 expmv_status expmv_host_eig_general(int n, const double* A, double* wr, double* wi, double* Vr,
                                     double* Vi);
+
+/* Host-side AMG hierarchy of a CSR matrix (all pointers host), the same
+ * construction a plan uses for its inner preconditioner, exported so it can
+ * be inspected without a GPU.  A is n x n CSR (int32 rowptr/colind, FP64
+ * values) with a positive diagonal; symmetric selects the eigenvalue
+ * estimate (Lanczos or power iteration); theta is the strength threshold of
+ * the finest level (halved per level); max_coarse the coarsest size.
+ * Errors: EINVAL (bad arguments, non-positive diagonal, coarsest operator
+ * singular or larger than 4096), ENOMEM. */
+typedef struct expmv_amg_s* expmv_amg;
+expmv_status expmv_host_amg_build(int64_t n, const int32_t* rowptr, const int32_t* colind,
+                                  const double* val, int symmetric, double theta,
+                                  int max_coarse, expmv_amg* out);
+/* Number of levels (>= 1; the last is the coarsest). */
+int expmv_host_amg_levels(expmv_amg h);
+/* Level `level`: dims[0] = n_l, dims[1] = nnz(A_l), dims[2] = n_{l+1} (0 on
+ * the coarsest), dims[3] = nnz(P_l); *lmax = the smoother's upper estimate
+ * of lambda_max(D_l^{-1} A_l).  Any array pointer may be NULL; otherwise it
+ * receives A_l (a_rowptr n_l + 1, a_colind and a_val nnz(A_l)), the
+ * prolongator P_l (n_l x n_{l+1}: p_rowptr n_l + 1, p_colind and p_val
+ * nnz(P_l)) and the aggregate of each unknown (agg, n_l). */
+expmv_status expmv_host_amg_level(expmv_amg h, int level, int64_t* dims, double* lmax,
+                                  int32_t* a_rowptr, int32_t* a_colind, double* a_val,
+                                  int32_t* p_rowptr, int32_t* p_colind, double* p_val,
+                                  int32_t* agg);
+/* Dense row-major inverse of the coarsest operator (n_c x n_c doubles). */
+expmv_status expmv_host_amg_coarse_inverse(expmv_amg h, double* inv);
+void expmv_host_amg_destroy(expmv_amg h);
 
 void expmv_plan_destroy(expmv_plan plan);
 

@@ -4,4 +4,4 @@ FOM with deflation (PSBFOM-DR; Wu, Pang, Sun, arXiv:1405.0707).
 The computation runs in libexpmv.so (hand-written HIP for gfx950, C ABI in
 include/expmv.h); this package only marshals torch tensors to it.
 """
-from .api import Plan, Toeplitz, expmv, cf_table, default_opts  # noqa: F401
+from .api import HostAmg, Plan, Toeplitz, expmv, cf_table, default_opts  # noqa: F401

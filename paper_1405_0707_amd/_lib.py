@@ -8,6 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libexpmv.so")
 
 OK, EINVAL, ENOTNEG, ENOMEM, ENOCONV, EBREAKDOWN, EHIP, EINNER = range(8)
+JACOBI, AMG, AUTO = 0, 1, -1
 FP64, MIXED, MIXED_INNER = 0, 1, 2
 STOP_PAPER, STOP_BOUND = 0, 1
 
@@ -16,7 +17,8 @@ class Opts(C.Structure):
     _fields_ = [("m", C.c_int), ("k", C.c_int), ("max_cycles", C.c_int),
                 ("precision", C.c_int), ("stop_rule", C.c_int), ("inner_tol", C.c_double),
                 ("inner_maxit", C.c_int), ("symmetric", C.c_int), ("preconditioned", C.c_int),
-                ("profile", C.c_int), ("inner_refine", C.c_int)]
+                ("profile", C.c_int), ("inner_refine", C.c_int), ("inner_precond", C.c_int),
+                ("amg_degree", C.c_int)]
 
 
 class Info(C.Structure):
@@ -27,7 +29,7 @@ class Info(C.Structure):
                 ("ms_apply", C.c_double), ("ms_orth", C.c_double), ("ms_small", C.c_double),
                 ("ms_update", C.c_double), ("breakdown", C.c_int), ("kern_samples", C.c_int),
                 ("kern_ms_a", C.c_double), ("kern_ms_b", C.c_double),
-                ("kern_ms_c", C.c_double)]
+                ("kern_ms_c", C.c_double), ("amg_levels", C.c_int)]
 
     def as_dict(self):
         d = {}
@@ -42,6 +44,8 @@ EXPORTS = [
     "expmv_grad_t", "expmv_adjoint", "expmv_apply_operator", "expmv_apply_inverse", "expmv_cf_table",
     "expmv_host_eig_sym", "expmv_host_eig_general", "expmv_plan_destroy",
     "expmv_status_string", "expmv_block_csr", "expmv_block_toeplitz",
+    "expmv_apply_preconditioner", "expmv_host_amg_build", "expmv_host_amg_levels",
+    "expmv_host_amg_level", "expmv_host_amg_coarse_inverse", "expmv_host_amg_destroy",
 ]
 
 _lib = None
@@ -74,8 +78,15 @@ def lib():
     L.expmv_status_string.restype = C.c_char_p
     L.expmv_block_csr.argtypes = [i64, i64, vp, vp, vp, vp, i64, dbl, dbl, vp, vp]
     L.expmv_block_toeplitz.argtypes = [i64, vp, vp, i64, dbl, dbl, vp, vp]
+    L.expmv_apply_preconditioner.argtypes = [vp, i32, vp, i64, vp]
+    L.expmv_host_amg_build.argtypes = [i64, vp, vp, vp, i32, dbl, i32, C.POINTER(vp)]
+    L.expmv_host_amg_levels.argtypes = [vp]
+    L.expmv_host_amg_level.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.expmv_host_amg_coarse_inverse.argtypes = [vp, vp]
+    L.expmv_host_amg_destroy.argtypes = [vp]
+    L.expmv_host_amg_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("expmv_plan_destroy", "expmv_status_string"):
+        if name not in ("expmv_plan_destroy", "expmv_status_string", "expmv_host_amg_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -29,6 +29,8 @@ def default_opts(**kw) -> Opts:
             v = {"fp64": _lib.FP64, "mixed": _lib.MIXED, "mixed_inner": _lib.MIXED_INNER}[v]
         if key == "stop_rule" and isinstance(v, str):
             v = {"paper": _lib.STOP_PAPER, "bound": _lib.STOP_BOUND}[v]
+        if key == "inner_precond" and isinstance(v, str):
+            v = {"jacobi": _lib.JACOBI, "amg": _lib.AMG, "auto": _lib.AUTO}[v]
         if not hasattr(o, key):
             raise TypeError(f"unknown option {key}")
         setattr(o, key, v)
@@ -133,6 +135,17 @@ class Plan:
                                          Y.data_ptr()), "expmv_apply_operator")
         return Y
 
+    def apply_preconditioner(self, X: torch.Tensor, transpose: bool = False) -> torch.Tensor:
+        """One application of the inner solver's preconditioner for K = -tA
+        (Jacobi D^{-1}, or one AMG V-cycle): Y ~= K^{-1} X."""
+        X = _dev_f64(X, self.device)
+        if X.dim() == 1:
+            X = X[:, None]
+        Y = torch.empty_like(X)
+        check(lib().expmv_apply_preconditioner(self._h, int(transpose), X.data_ptr(), X.shape[1],
+                                               Y.data_ptr()), "expmv_apply_preconditioner")
+        return Y
+
     def apply_inverse(self, X: torch.Tensor, transpose: bool = False):
         X = _dev_f64(X, self.device)
         Y = torch.empty_like(X)
@@ -140,6 +153,67 @@ class Plan:
         check(lib().expmv_apply_inverse(self._h, int(transpose), X.data_ptr(), X.shape[1],
                                         Y.data_ptr(), C.byref(it)), "expmv_apply_inverse")
         return Y, it.value
+
+
+class HostAmg:
+    """The library's AMG hierarchy of a host CSR matrix (numpy arrays), for
+    inspection: levels()[l] = dict(A=(rowptr, colind, val), P=(...) or None,
+    agg, lmax, n); coarse_inverse() the dense inverse of the coarsest A."""
+
+    def __init__(self, rowptr, colind, val, symmetric=True, theta=0.08, max_coarse=500):
+        import numpy as np
+        self._np = np
+        rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+        ci = np.ascontiguousarray(colind, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        h = C.c_void_p()
+        check(lib().expmv_host_amg_build(rp.size - 1, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                                         int(bool(symmetric)), float(theta), int(max_coarse),
+                                         C.byref(h)), "expmv_host_amg_build")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().expmv_host_amg_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def levels(self):
+        np = self._np
+        out = []
+        for lv in range(lib().expmv_host_amg_levels(self._h)):
+            dims = np.zeros(4, dtype=np.int64)
+            lmax = C.c_double()
+            check(lib().expmv_host_amg_level(self._h, lv, dims.ctypes.data, C.byref(lmax), None,
+                                             None, None, None, None, None, None),
+                  "expmv_host_amg_level")
+            n, nnz_a, nc, nnz_p = (int(x) for x in dims)
+            arp = np.zeros(n + 1, np.int32)
+            aci = np.zeros(nnz_a, np.int32)
+            av = np.zeros(nnz_a, np.float64)
+            prp = np.zeros(n + 1, np.int32)
+            pci = np.zeros(nnz_p, np.int32)
+            pv = np.zeros(nnz_p, np.float64)
+            agg = np.zeros(n, np.int32)
+            check(lib().expmv_host_amg_level(self._h, lv, dims.ctypes.data, C.byref(lmax),
+                                             arp.ctypes.data, aci.ctypes.data, av.ctypes.data,
+                                             prp.ctypes.data, pci.ctypes.data, pv.ctypes.data,
+                                             agg.ctypes.data), "expmv_host_amg_level")
+            out.append({"n": n, "A": (arp, aci, av), "lmax": lmax.value,
+                        "P": (prp, pci, pv, nc) if nc > 0 else None,
+                        "agg": agg if nc > 0 else None})
+        return out
+
+    def coarse_inverse(self):
+        np = self._np
+        nc = self.levels()[-1]["n"]
+        inv = np.zeros((nc, nc), np.float64)
+        check(lib().expmv_host_amg_coarse_inverse(self._h, inv.ctypes.data),
+              "expmv_host_amg_coarse_inverse")
+        return inv
 
 
 def cf_table():

@@ -1,0 +1,368 @@
+// Smoothed-aggregation AMG hierarchy, built on the host once per plan.
+#include "amg_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "eig_host.hpp"
+
+namespace expmv {
+
+HostCsr csr_transpose(const HostCsr& A) {
+  HostCsr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.rp.assign(T.nrows + 1, 0);
+  const int64_t nnz = A.nnz();
+  T.ci.resize(nnz);
+  T.v.resize(nnz);
+  for (int64_t e = 0; e < nnz; ++e) T.rp[A.ci[e] + 1]++;
+  for (int64_t i = 0; i < T.nrows; ++i) T.rp[i + 1] += T.rp[i];
+  std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
+  for (int64_t i = 0; i < A.nrows; ++i)
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int64_t d = pos[A.ci[e]]++;
+      T.ci[d] = int32_t(i);
+      T.v[d] = A.v[e];
+    }
+  return T;
+}
+
+// C = A B (Gustavson, row by row; entries of a row in first-touch order, so
+// the result and its summation order are deterministic).
+HostCsr csr_matmul(const HostCsr& A, const HostCsr& B) {
+  HostCsr C;
+  C.nrows = A.nrows;
+  C.ncols = B.ncols;
+  C.rp.assign(C.nrows + 1, 0);
+  std::vector<int64_t> mark(B.ncols, -1);
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    int64_t cnt = 0;
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int32_t k = A.ci[e];
+      for (int64_t f = B.rp[k]; f < B.rp[k + 1]; ++f) {
+        const int32_t j = B.ci[f];
+        if (mark[j] != i) {
+          mark[j] = i;
+          ++cnt;
+        }
+      }
+    }
+    C.rp[i + 1] = C.rp[i] + cnt;
+  }
+  C.ci.resize(C.nnz());
+  C.v.resize(C.nnz());
+  std::fill(mark.begin(), mark.end(), -1);
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    int64_t fill = C.rp[i];
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int32_t k = A.ci[e];
+      const double a = A.v[e];
+      for (int64_t f = B.rp[k]; f < B.rp[k + 1]; ++f) {
+        const int32_t j = B.ci[f];
+        if (mark[j] < C.rp[i]) {
+          mark[j] = fill;
+          C.ci[fill] = j;
+          C.v[fill] = a * B.v[f];
+          ++fill;
+        } else {
+          C.v[mark[j]] += a * B.v[f];
+        }
+      }
+    }
+  }
+  return C;
+}
+
+namespace {
+
+// Deterministic pseudo-random start vector for the eigenvalue estimates.
+double hash_unit(uint64_t i) {
+  uint64_t z = i + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return double(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+void spmv(const HostCsr& A, const std::vector<double>& x, std::vector<double>& y) {
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    double s = 0.0;
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) s += A.v[e] * x[A.ci[e]];
+    y[i] = s;
+  }
+}
+
+// Upper estimate of lambda_max(D^{-1} A): Lanczos on D^{-1/2} A D^{-1/2}
+// (symmetric A) or power iteration on D^{-1} A, times 1.1, never above the
+// Gershgorin bound max_i sum_j |a_ij| / a_ii.
+double estimate_lmax(const HostCsr& A, const std::vector<double>& dinv, bool symmetric) {
+  const int64_t n = A.nrows;
+  double gersh = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) s += std::fabs(A.v[e]);
+    gersh = std::max(gersh, s * dinv[i]);
+  }
+  std::vector<double> v(n), w(n), u(n);
+  for (int64_t i = 0; i < n; ++i) v[i] = hash_unit(uint64_t(i));
+  auto nrm = [&](const std::vector<double>& a) {
+    double s = 0.0;
+    for (double x : a) s += x * x;
+    return std::sqrt(s);
+  };
+  double est = 0.0;
+  if (symmetric) {
+    std::vector<double> sq(n);
+    for (int64_t i = 0; i < n; ++i) sq[i] = std::sqrt(dinv[i]);
+    const int steps = int(std::min<int64_t>(n, 25));
+    std::vector<double> alpha, beta;
+    std::vector<double> vprev(n, 0.0);
+    double b = nrm(v);
+    for (auto& x : v) x /= b;
+    b = 0.0;
+    for (int k = 0; k < steps; ++k) {
+      for (int64_t i = 0; i < n; ++i) u[i] = sq[i] * v[i];
+      spmv(A, u, w);
+      for (int64_t i = 0; i < n; ++i) w[i] = sq[i] * w[i] - b * vprev[i];
+      double a = 0.0;
+      for (int64_t i = 0; i < n; ++i) a += w[i] * v[i];
+      for (int64_t i = 0; i < n; ++i) w[i] -= a * v[i];
+      alpha.push_back(a);
+      b = nrm(w);
+      if (k + 1 == steps || b <= 1e-14 * std::fabs(a)) break;
+      beta.push_back(b);
+      vprev.swap(v);
+      for (int64_t i = 0; i < n; ++i) v[i] = w[i] / b;
+    }
+    const int m = int(alpha.size());
+    std::vector<double> Tm(size_t(m) * m, 0.0), ev(m), Q(size_t(m) * m);
+    for (int i = 0; i < m; ++i) {
+      Tm[size_t(i) * m + i] = alpha[i];
+      if (i + 1 < m) Tm[size_t(i) * m + i + 1] = Tm[size_t(i + 1) * m + i] = beta[i];
+    }
+    sym_eig(m, Tm.data(), ev.data(), Q.data());
+    for (double x : ev) est = std::max(est, x);
+  } else {
+    for (int k = 0; k < 30; ++k) {
+      const double b = nrm(v);
+      for (auto& x : v) x /= b;
+      spmv(A, v, w);
+      for (int64_t i = 0; i < n; ++i) v[i] = dinv[i] * w[i];
+    }
+    est = nrm(v);   // |D^{-1} A v| for the last unit v
+  }
+  return std::min(1.1 * est, gersh);
+}
+
+// Strength graph: j is a strong neighbour of i (j != i) when
+// |a_ij| >= theta sqrt(a_ii a_jj); symmetrised (i ~ j if either holds).
+// Returns the graph in CSR with the strength |a_ij| / sqrt(a_ii a_jj).
+HostCsr strength_graph(const HostCsr& A, const std::vector<double>& diag, double theta,
+                       bool symmetric) {
+  const int64_t n = A.nrows;
+  std::vector<int64_t> cnt(n + 1, 0);
+  auto strong = [&](int64_t i, int64_t e, double& s) {
+    const int32_t j = A.ci[e];
+    if (j == i || A.v[e] == 0.0) return false;
+    s = std::fabs(A.v[e]) / std::sqrt(diag[i] * diag[j]);
+    return s >= theta;
+  };
+  double s;
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e)
+      if (strong(i, e, s)) {
+        cnt[i + 1]++;
+        if (!symmetric) cnt[A.ci[e] + 1]++;
+      }
+  for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+  std::vector<std::pair<int32_t, double>> ent(cnt[n]);
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e)
+      if (strong(i, e, s)) {
+        ent[pos[i]++] = {A.ci[e], s};
+        if (!symmetric) ent[pos[A.ci[e]]++] = {int32_t(i), s};
+      }
+  HostCsr S;
+  S.nrows = S.ncols = n;
+  S.rp.assign(n + 1, 0);
+  S.ci.reserve(ent.size());
+  S.v.reserve(ent.size());
+  for (int64_t i = 0; i < n; ++i) {
+    auto b = ent.begin() + cnt[i], e = ent.begin() + cnt[i + 1];
+    std::sort(b, e);
+    for (auto it = b; it != e; ++it) {
+      if (!S.ci.empty() && int64_t(S.ci.size()) > S.rp[i] && S.ci.back() == it->first) {
+        S.v.back() = std::max(S.v.back(), it->second);
+      } else {
+        S.ci.push_back(it->first);
+        S.v.push_back(it->second);
+      }
+    }
+    S.rp[i + 1] = int64_t(S.ci.size());
+  }
+  return S;
+}
+
+// Greedy aggregation of the strength graph (three phases):
+//  1. an unaggregated node whose strong neighbours are all unaggregated
+//     starts an aggregate with them;
+//  2. a node still left joins the phase-1 aggregate of its strongest
+//     aggregated neighbour;
+//  3. what remains forms aggregates with its remaining neighbours.
+int32_t aggregate(const HostCsr& S, std::vector<int32_t>& agg) {
+  const int64_t n = S.nrows;
+  agg.assign(n, -1);
+  int32_t na = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free_nb = true;
+    for (int64_t e = S.rp[i]; e < S.rp[i + 1] && free_nb; ++e) free_nb = agg[S.ci[e]] < 0;
+    if (!free_nb) continue;
+    agg[i] = na;
+    for (int64_t e = S.rp[i]; e < S.rp[i + 1]; ++e) agg[S.ci[e]] = na;
+    ++na;
+  }
+  const std::vector<int32_t> agg1 = agg;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    double best = -1.0;
+    for (int64_t e = S.rp[i]; e < S.rp[i + 1]; ++e) {
+      const int32_t j = S.ci[e];
+      if (agg1[j] >= 0 && S.v[e] > best) {
+        best = S.v[e];
+        agg[i] = agg1[j];
+      }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    agg[i] = na;
+    for (int64_t e = S.rp[i]; e < S.rp[i + 1]; ++e)
+      if (agg[S.ci[e]] < 0) agg[S.ci[e]] = na;
+    ++na;
+  }
+  return na;
+}
+
+// P = (I - omega D^{-1} A) T with T the tentative prolongator of `agg`.
+HostCsr smoothed_prolongator(const HostCsr& A, const std::vector<double>& dinv,
+                             const std::vector<int32_t>& agg, int32_t na, double omega) {
+  const int64_t n = A.nrows;
+  std::vector<int64_t> size(na, 0);
+  for (int64_t i = 0; i < n; ++i) size[agg[i]]++;
+  std::vector<double> tval(n);
+  for (int64_t i = 0; i < n; ++i) tval[i] = 1.0 / std::sqrt(double(size[agg[i]]));
+  HostCsr P;
+  P.nrows = n;
+  P.ncols = na;
+  P.rp.assign(n + 1, 0);
+  std::vector<int64_t> mark(na, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t start = int64_t(P.ci.size());
+    auto add = [&](int32_t col, double val) {
+      if (mark[col] < start) {
+        mark[col] = int64_t(P.ci.size());
+        P.ci.push_back(col);
+        P.v.push_back(val);
+      } else {
+        P.v[mark[col]] += val;
+      }
+    };
+    add(agg[i], tval[i]);
+    const double f = -omega * dinv[i];
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int32_t j = A.ci[e];
+      add(agg[j], f * A.v[e] * tval[j]);
+    }
+    P.rp[i + 1] = int64_t(P.ci.size());
+  }
+  return P;
+}
+
+// Dense inverse by Gauss-Jordan elimination with partial pivoting.
+bool dense_inverse(const HostCsr& A, std::vector<double>& inv) {
+  const int64_t n = A.nrows;
+  std::vector<double> M(size_t(n) * n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) M[size_t(i) * n + A.ci[e]] += A.v[e];
+  inv.assign(size_t(n) * n, 0.0);
+  for (int64_t i = 0; i < n; ++i) inv[size_t(i) * n + i] = 1.0;
+  double scale = 0.0;
+  for (double x : M) scale = std::max(scale, std::fabs(x));
+  for (int64_t c = 0; c < n; ++c) {
+    int64_t piv = c;
+    for (int64_t r = c + 1; r < n; ++r)
+      if (std::fabs(M[size_t(r) * n + c]) > std::fabs(M[size_t(piv) * n + c])) piv = r;
+    const double pv = M[size_t(piv) * n + c];
+    if (!(std::fabs(pv) > 1e-14 * scale)) return false;
+    if (piv != c)
+      for (int64_t k = 0; k < n; ++k) {
+        std::swap(M[size_t(piv) * n + k], M[size_t(c) * n + k]);
+        std::swap(inv[size_t(piv) * n + k], inv[size_t(c) * n + k]);
+      }
+    const double ip = 1.0 / pv;
+    for (int64_t k = 0; k < n; ++k) {
+      M[size_t(c) * n + k] *= ip;
+      inv[size_t(c) * n + k] *= ip;
+    }
+    for (int64_t r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = M[size_t(r) * n + c];
+      if (f == 0.0) continue;
+      for (int64_t k = 0; k < n; ++k) {
+        M[size_t(r) * n + k] -= f * M[size_t(c) * n + k];
+        inv[size_t(r) * n + k] -= f * inv[size_t(c) * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+int amg_build(const HostCsr& A0, const AmgParams& prm, AmgHost& out) {
+  out.lv.clear();
+  out.coarse_inv.clear();
+  out.lv.emplace_back();
+  out.lv[0].A = A0;
+  double theta = prm.theta;
+  for (int l = 0;; ++l) {
+    AmgLevelHost& L = out.lv[l];
+    const HostCsr& A = L.A;
+    const int64_t n = A.nrows;
+    std::vector<double> diag(n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e)
+        if (A.ci[e] == i) diag[i] += A.v[e];
+    L.dinv.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+      if (!(diag[i] > 0.0)) return 1;
+      L.dinv[i] = 1.0 / diag[i];
+    }
+    L.lmax = estimate_lmax(A, L.dinv, prm.symmetric);
+    if (n <= prm.max_coarse || l + 1 >= prm.max_levels) break;
+    HostCsr S = strength_graph(A, diag, theta, prm.symmetric);
+    int32_t na = aggregate(S, L.agg);
+    if (na >= n || double(na) > 0.85 * double(n)) {   // no useful coarsening left
+      L.agg.clear();
+      break;
+    }
+    L.P = smoothed_prolongator(A, L.dinv, L.agg, na, (4.0 / 3.0) / L.lmax);
+    L.R = csr_transpose(L.P);
+    HostCsr AP = csr_matmul(A, L.P);
+    AmgLevelHost next;
+    next.A = csr_matmul(L.R, AP);
+    out.lv.push_back(std::move(next));
+    theta *= 0.5;
+  }
+  if (out.lv.back().A.nrows > 4096) return 2;
+  if (!dense_inverse(out.lv.back().A, out.coarse_inv)) return 2;
+  return 0;
+}
+
+}  // namespace expmv

@@ -1,0 +1,58 @@
+// Host-side set-up of the smoothed-aggregation algebraic multigrid (SA-AMG)
+// hierarchy that preconditions the inner solver of (tA)^{-1} V.
+//
+// The paper applies its preconditioner A^{-1} through a sparse LU
+// factorisation and, for matrices too large to factor, through an iterative
+// inner solver (Section 4.1).  On the GPU A^{-1} V is an inner Krylov solve;
+// this hierarchy is that solve's preconditioner, so the result is still
+// A^{-1} V to the inner tolerance.  Construction follows the
+// standard smoothed-aggregation recipe:
+//   strength   |a_ij| >= theta_l sqrt(a_ii a_jj), symmetrised, theta_l = theta / 2^l
+//   aggregates greedy three-phase aggregation of the strength graph
+//   T          piecewise-constant tentative prolongator, unit-norm columns
+//   P          (I - omega D^{-1} A) T, omega = (4/3) / lambda_max(D^{-1} A)
+//   A_{l+1}    P^T A_l P (Galerkin), R = P^T
+// down to at most max_coarse unknowns, whose operator is inverted densely.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace expmv {
+
+struct HostCsr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> rp;   // nrows + 1
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+struct AmgParams {
+  double theta = 0.08;         // strength threshold of the finest level
+  int max_coarse = 500;        // coarsest level size (dense inverse)
+  int max_levels = 12;
+  bool symmetric = true;       // A symmetric: Lanczos eigenvalue estimate
+};
+
+struct AmgLevelHost {
+  HostCsr A;                   // operator of the level (level 0: the input)
+  HostCsr P, R;                // prolongator to this level from the next, R = P^T
+  std::vector<int32_t> agg;    // aggregate of each unknown (empty on the coarsest)
+  std::vector<double> dinv;    // 1 / diag(A)
+  double lmax = 0.0;           // upper estimate of lambda_max(D^{-1} A)
+};
+
+struct AmgHost {
+  std::vector<AmgLevelHost> lv;      // lv.back() is the coarsest level
+  std::vector<double> coarse_inv;    // nc x nc row-major inverse of lv.back().A
+};
+
+// 0 on success; 1 for a zero or non-positive diagonal; 2 for a singular
+// coarsest operator.
+int amg_build(const HostCsr& A, const AmgParams& prm, AmgHost& out);
+
+HostCsr csr_transpose(const HostCsr& A);
+HostCsr csr_matmul(const HostCsr& A, const HostCsr& B);
+
+}  // namespace expmv

@@ -18,6 +18,8 @@
 #include <type_traits>
 #include <vector>
 
+#include "amg.hpp"
+#include "amg_host.hpp"
 #include "eig_host.hpp"
 #include "expmv.h"
 #include "kernels.hpp"
@@ -84,6 +86,7 @@ struct Workspace {
   DevBuf<char> Win, Wout;       // n x p (inner-solver type, when it differs)
   DevBuf<char> Rin, Din;        // n x p (inner-solver type, refinement)
   DevBuf<char> kr, kpa, kpb, kq, kv, ks, kt, krh;   // inner-solver vectors, n x p
+  DevBuf<char> kz;                                  // preconditioned residual (AMG)
   DevBuf<double> X;             // n x 14p
   DevBuf<double> partial;       // reductions of the dense kernels
   DevBuf<double> hcoef, gram, R1, R2, Rinv, w0;   // small orth buffers
@@ -96,6 +99,45 @@ struct Workspace {
   DevBuf<BcgState> bcgst;
   DevBuf<double> part_rr, part_sig;   // inner-solver partials
   DevBuf<KrylovCtl> ctl;
+};
+
+constexpr int kAmgMaxDeg = 4;
+constexpr double kAmgEigRatio = 20.0;   // Chebyshev interval [lmax / ratio, lmax]
+
+// One level of the AMG hierarchy on the device.  Level 0 borrows the plan's
+// CSR operator and Jacobi scaling; coarser levels own their Galerkin
+// operators.  P/R connect the level to the next one.  Vectors (n_l x p,
+// inner-solver type): b (right-hand side, levels >= 1), u/v (iterates),
+// d (Chebyshev direction), r (residual), o (the level's output, levels >= 1).
+struct AmgDevLevel {
+  int64_t n = 0;
+  const int32_t* arp = nullptr;
+  const int32_t* aci = nullptr;
+  const double* av = nullptr;
+  const double* dinv64 = nullptr;
+  const float* dinv32 = nullptr;
+  DevBuf<int32_t> Arp, Aci, Prp, Pci, Rrp, Rci;
+  DevBuf<double> Av, Pv, Rv, dinv;
+  DevBuf<float> dinvf;
+  double cd[kAmgMaxDeg] = {}, ad[kAmgMaxDeg] = {};   // Chebyshev step coefficients
+  double avg_a = 0.0, avg_p = 0.0, avg_r = 0.0;      // mean nonzeros per row of A, P, R
+  DevBuf<char> vb, vu, vv, vd, vr, vo;
+};
+
+// Sub-lanes per row for a matrix with `avg` nonzeros per row: the largest
+// power of two with at least 4 nonzeros per sub-lane, PP * G <= 64.
+inline int row_split(double avg, int PP) {
+  int G = 1;
+  while (2 * G * PP <= 64 && avg >= 4.0 * 2 * G) G *= 2;
+  return G;
+}
+
+struct AmgDev {
+  std::vector<std::unique_ptr<AmgDevLevel>> lv;
+  DevBuf<double> cinv;   // dense inverse of the coarsest operator
+  int degree = 2;
+  int p = 0;
+  size_t el = 0;
 };
 
 }  // namespace expmv
@@ -136,6 +178,8 @@ struct expmv_plan_s {
   int pev_used = 0;
   double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0;
   int prof_samples = 0;
+  // AMG preconditioner of the CSR inner solver (symmetric K)
+  std::unique_ptr<AmgDev> amg;
 };
 
 namespace expmv {
@@ -183,6 +227,7 @@ void ensure_workspace(expmv_plan_s* pl, int p) {
   w.kpa.alloc(blk * el);
   w.kpb.alloc(blk * el);
   w.kq.alloc(blk * el);
+  if (pl->amg) w.kz.alloc(blk * el);
   if (!pl->symmetric) {
     w.kv.alloc(blk * el);
     w.ks.alloc(blk * el);
@@ -306,10 +351,10 @@ double inner_tol_of(expmv_plan_s* pl) {
 // Poll the inner solver's control word every `chunk` iterations, one chunk
 // ahead of the device; returns when a chunk has seen every column stop.
 template <typename LaunchChunk>
-InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chunk) {
+InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chunk,
+                           int chunk = 16) {
   Workspace& w = pl->ws;
   hipStream_t s = pl->stream;
-  const int chunk = 16;
   int launched = 0;
   int pending = -1, slot = 0;
   bool done = false;
@@ -333,6 +378,114 @@ InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chu
   return {c->iters_max, c->hit_cap};
 }
 
+// ------------------------------------------------------------------------
+// AMG V-cycle (preconditioner of the inner CG)
+
+template <typename T>
+const T* dinv_of(const AmgDevLevel& L);
+template <>
+const double* dinv_of<double>(const AmgDevLevel& L) { return L.dinv64; }
+template <>
+const float* dinv_of<float>(const AmgDevLevel& L) { return L.dinv32; }
+
+void amg_vectors(AmgDev& H, int p, size_t el) {
+  if (H.p == p && H.el == el) return;
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    AmgDevLevel& L = *H.lv[l];
+    const size_t bytes = size_t(L.n) * p * el;
+    if (l + 1 < H.lv.size()) {
+      L.vu.alloc(bytes);
+      L.vv.alloc(bytes);
+      L.vd.alloc(bytes);
+      L.vr.alloc(bytes);
+    }
+    if (l > 0) {
+      L.vb.alloc(bytes);
+      L.vo.alloc(bytes);
+    }
+  }
+  H.p = p;
+  H.el = el;
+}
+
+// out = V-cycle(b) on level l (level 0: the inner solver's launch shape,
+// and with part_rz the (b, out) partials of the last smoothing step).
+template <typename T, int PP>
+void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
+               const KrylovCtl* ctl, double* part_rz) {
+  AmgDevLevel& L = *H.lv[l];
+  hipStream_t s = pl->stream;
+  const int n = int(L.n);
+  if (l + 1 == int(H.lv.size())) {
+    const int grid = std::max(1, std::min(n, 1024));
+    hipLaunchKernelGGL((k_amg_coarse<T, PP>), dim3(grid), dim3(kThreads), 0, s, k, ctl, n, p,
+                       H.cinv.p, b, out);
+    return;
+  }
+  const T* dinv = dinv_of<T>(L);
+  const bool fine = (l == 0);
+  const int gfine = cg_grid(n, PP);
+  const int GA = row_split(L.avg_a, PP), GP = row_split(L.avg_p, PP);
+  const int gcoarse_a = grid_for(n, PP * GA, 4096), gcoarse_p = grid_for(n, PP * GP, 4096);
+  auto step = [&](int mode, const T* x, T* o, double cd, double ad, double* part) {
+    T* d = reinterpret_cast<T*>(L.vd.p);
+    if (fine)
+      hipLaunchKernelGGL((k_amg_step<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads), 0,
+                         s, k, ctl, n, p, GA, L.arp, L.aci, L.av, dinv, b, x, d, o, L.ad[0], cd,
+                         ad, mode, part);
+    else
+      hipLaunchKernelGGL((k_amg_step<T, PP, kThreads, false>), dim3(gcoarse_a), dim3(kThreads), 0,
+                         s, k, ctl, n, p, GA, L.arp, L.aci, L.av, dinv, b, x, d, o, L.ad[0], cd,
+                         ad, mode, part);
+  };
+  T* x = reinterpret_cast<T*>(L.vu.p);
+  T* y = reinterpret_cast<T*>(L.vv.p);
+  // pre-smoothing from zero: the first step's iterate s0 D^{-1} b stays implicit
+  bool implicit = true;
+  for (int st = 1; st < H.degree; ++st) {
+    step(kAmgHasD | kAmgWriteD | (implicit ? kAmgX0 : 0), x, y, L.cd[st], L.ad[st], nullptr);
+    implicit = false;
+    std::swap(x, y);
+  }
+  T* r = reinterpret_cast<T*>(L.vr.p);
+  step(kAmgResid | (implicit ? kAmgX0 : 0), x, r, 0.0, 0.0, nullptr);
+  AmgDevLevel& C = *H.lv[l + 1];
+  T* bc = reinterpret_cast<T*>(C.vb.p);
+  const int nc = int(C.n);
+  const int GR = row_split(L.avg_r, PP);
+  hipLaunchKernelGGL((k_amg_restrict<T, PP, kThreads, false>), dim3(grid_for(nc, PP * GR, 4096)),
+                     dim3(kThreads), 0, s, k, ctl, nc, p, GR, L.Rrp.p, L.Rci.p, L.Rv.p, r, bc);
+  T* xc = reinterpret_cast<T*>(C.vo.p);
+  amg_level<T, PP>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr);
+  const int pmode = implicit ? kAmgX0 : 0;
+  if (fine)
+    hipLaunchKernelGGL((k_amg_prolong<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads), 0,
+                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, L.Pv.p, xc, dinv, b, L.ad[0], pmode,
+                       x);
+  else
+    hipLaunchKernelGGL((k_amg_prolong<T, PP, kThreads, false>), dim3(gcoarse_p), dim3(kThreads), 0,
+                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, L.Pv.p, xc, dinv, b, L.ad[0], pmode,
+                       x);
+  // post-smoothing from x, the same polynomial (symmetric V-cycle)
+  for (int st = 0; st < H.degree; ++st) {
+    const bool last = (st + 1 == H.degree);
+    T* o = last ? out : y;
+    const int mode = (st > 0 ? kAmgHasD : 0) | (last ? 0 : kAmgWriteD) |
+                     (last && part_rz ? kAmgRz : 0);
+    step(mode, x, o, L.cd[st], L.ad[st], last ? part_rz : nullptr);
+    if (!last) std::swap(x, y);
+  }
+}
+
+template <typename T>
+void amg_vcycle(expmv_plan_s* pl, int p, const T* b, T* out, int k, const KrylovCtl* ctl,
+                double* part_rz) {
+  AmgDev& H = *pl->amg;
+  amg_vectors(H, p, sizeof(T));
+  const int PP = pow2_lanes(p);
+  DISPATCH_PP(PP, amg_level<T, P_>(pl, H, 0, p, b, out, k, ctl, part_rz));
+}
+
 // out = K^{-1} (sign * src) by batched Jacobi-PCG (K SPD); out is the iterate.
 template <typename T>
 InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p) {
@@ -348,9 +501,12 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
   T* r = reinterpret_cast<T*>(w.kr.p);
   T* q = reinterpret_cast<T*>(w.kq.p);
   T* P[2] = {reinterpret_cast<T*>(w.kpa.p), reinterpret_cast<T*>(w.kpb.p)};
+  const bool amg = pl->amg != nullptr;
+  T* z = amg ? reinterpret_cast<T*>(w.kz.p) : nullptr;
   DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
                                      int(n), p, sign, src, A.dinv, out, r, P[0], w.ctl.p,
                                      w.part_rr.p));
+  if (amg) amg_vcycle<T>(pl, p, r, z, 0, w.ctl.p, w.part_rr.p);
   InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
     for (int it = 0; it < chunk; ++it) {
       const int k = launched + it;
@@ -359,25 +515,26 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
       const bool sample = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0 &&
                           pl->pev_used + 6 <= int(pl->pev.size());
       hipEvent_t* e = sample ? &pl->pev[pl->pev_used] : nullptr;
-      hipEvent_t z = nullptr;
+      hipEvent_t ez = nullptr;
       if (sample) {
         pl->pev_iter[pl->pev_used / 6] = k;
         pl->pev_used += 6;
       }
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[0] : z, sample ? e[1] : z, 0, k, int(n), p,
-                                            A.dinv, r, pold, pnew, out, w.cgst.p, w.ctl.p,
+                                            sample ? e[0] : ez, sample ? e[1] : ez, 0, k, int(n),
+                                            p, A.dinv, r, z, pold, pnew, out, w.cgst.p, w.ctl.p,
                                             w.part_rr.p, tol2, maxit));
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_a<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[2] : z, sample ? e[3] : z, 0, k, int(n), p,
-                                            A.rowptr, A.colind, A.val, pnew, q, w.ctl.p,
+                                            sample ? e[2] : ez, sample ? e[3] : ez, 0, k, int(n),
+                                            p, A.rowptr, A.colind, A.val, pnew, q, w.ctl.p,
                                             w.part_sig.p));
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_b<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[4] : z, sample ? e[5] : z, 0, k, int(n), p,
-                                            A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
-                                            w.part_rr.p));
+                                            sample ? e[4] : ez, sample ? e[5] : ez, 0, k, int(n),
+                                            p, A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
+                                            w.part_rr.p, amg ? 0 : 1));
+      if (amg) amg_vcycle<T>(pl, p, r, z, k, w.ctl.p, w.part_rr.p);
     }
-  });
+  }, amg ? 2 : 16);
   collect_profile(pl, res.iters);
   return res;
 }
@@ -1066,6 +1223,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   inf.kern_ms_a = pl->prof_samples ? pl->prof_ms_a / pl->prof_samples : 0.0;
   inf.kern_ms_b = pl->prof_samples ? pl->prof_ms_b / pl->prof_samples : 0.0;
   inf.kern_ms_c = pl->prof_samples ? pl->prof_ms_c / pl->prof_samples : 0.0;
+  inf.amg_levels = pl->amg ? int(pl->amg->lv.size()) : 0;
   if (info) *info = inf;
   return status;
 }
@@ -1111,6 +1269,8 @@ bool valid_opts(const expmv_opts& o) {
   if (o.inner_maxit < 1) return false;
   if (o.profile < 0) return false;
   if (o.inner_refine < -1 || o.inner_refine > 8) return false;
+  if (o.inner_precond < -1 || o.inner_precond > 1) return false;
+  if (o.amg_degree < 0 || o.amg_degree > kAmgMaxDeg) return false;
   return true;
 }
 
@@ -1237,7 +1397,102 @@ expmv_status build_csr(expmv_plan_s* pl, const int32_t* rowptr_d, const int32_t*
   return EXPMV_OK;
 }
 
+template <typename D, typename S>
+void upload_vec(DevBuf<D>& dst, const std::vector<S>& src) {
+  std::vector<D> tmp(src.begin(), src.end());
+  dst.alloc(std::max<size_t>(tmp.size(), 1));
+  if (!tmp.empty())
+    HIPCHK(hipMemcpy(dst.p, tmp.data(), sizeof(D) * tmp.size(), hipMemcpyHostToDevice));
+}
+
+void upload_csr(const HostCsr& A, DevBuf<int32_t>& rp, DevBuf<int32_t>& ci, DevBuf<double>& v) {
+  if (A.nnz() > INT32_MAX) throw StatusError{EXPMV_ENOMEM};
+  upload_vec(rp, A.rp);
+  upload_vec(ci, A.ci);
+  upload_vec(v, A.v);
+}
+
+// Chebyshev coefficients of the smoother on [lmax / ratio, lmax]: step 0
+// d = (1/theta) D^{-1} r; step k: d = rho_k rho_{k-1} d + (2 rho_k / delta) D^{-1} r.
+void chebyshev_coefficients(double lmax, int degree, double* cd, double* ad) {
+  const double lmin = lmax / kAmgEigRatio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  cd[0] = 0.0;
+  ad[0] = 1.0 / theta;
+  for (int k = 1; k < degree; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    cd[k] = rn * rho;
+    ad[k] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+// Build the AMG hierarchy of K on the host and upload it (symmetric K).
+expmv_status build_amg(expmv_plan_s* pl) {
+  const int64_t n = pl->n, nnz = pl->nnz;
+  HostCsr K;
+  K.nrows = K.ncols = n;
+  {
+    std::vector<int32_t> rp(n + 1);
+    HIPCHK(hipMemcpy(rp.data(), pl->rowptr.p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    K.rp.assign(rp.begin(), rp.end());
+    K.ci.resize(nnz);
+    K.v.resize(nnz);
+    HIPCHK(hipMemcpy(K.ci.data(), pl->colind.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(K.v.data(), pl->val.p, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+  }
+  AmgParams prm;
+  prm.symmetric = true;
+  AmgHost h;
+  if (amg_build(K, prm, h) != 0) return EXPMV_EINVAL;
+  if (h.lv.size() < 2) return EXPMV_OK;   // n <= max_coarse: no coarse level, Jacobi
+  std::unique_ptr<AmgDev> H(new AmgDev());
+  H->degree = pl->opts.amg_degree > 0 ? pl->opts.amg_degree : 2;
+  for (size_t l = 0; l < h.lv.size(); ++l) {
+    const AmgLevelHost& Lh = h.lv[l];
+    std::unique_ptr<AmgDevLevel> L(new AmgDevLevel());
+    L->n = Lh.A.nrows;
+    if (l == 0) {
+      L->arp = pl->rowptr.p;
+      L->aci = pl->colind.p;
+      L->av = pl->val.p;
+      L->dinv64 = pl->dinv.p;
+      L->dinv32 = pl->dinvf.p;
+    } else {
+      upload_csr(Lh.A, L->Arp, L->Aci, L->Av);
+      upload_vec(L->dinv, Lh.dinv);
+      L->arp = L->Arp.p;
+      L->aci = L->Aci.p;
+      L->av = L->Av.p;
+      L->dinv64 = L->dinv.p;
+      if (pl->mixed) {
+        upload_vec(L->dinvf, Lh.dinv);
+        L->dinv32 = L->dinvf.p;
+      }
+    }
+    L->avg_a = double(Lh.A.nnz()) / double(std::max<int64_t>(1, Lh.A.nrows));
+    if (l + 1 < h.lv.size()) {
+      upload_csr(Lh.P, L->Prp, L->Pci, L->Pv);
+      upload_csr(Lh.R, L->Rrp, L->Rci, L->Rv);
+      L->avg_p = double(Lh.P.nnz()) / double(std::max<int64_t>(1, Lh.P.nrows));
+      L->avg_r = double(Lh.R.nnz()) / double(std::max<int64_t>(1, Lh.R.nrows));
+    }
+    chebyshev_coefficients(Lh.lmax, H->degree, L->cd, L->ad);
+    H->lv.push_back(std::move(L));
+  }
+  upload_vec(H->cinv, h.coarse_inv);
+  pl->amg = std::move(H);
+  pl->ws.p = 0;   // workspace re-sized with the AMG vectors on the next call
+  return EXPMV_OK;
+}
+
 }  // namespace
+
+struct expmv_amg_s {
+  expmv::AmgHost h;
+};
 
 extern "C" {
 
@@ -1254,6 +1509,8 @@ expmv_status expmv_default_opts(expmv_opts* o) {
   o->preconditioned = 1;
   o->profile = 0;
   o->inner_refine = -1;
+  o->inner_precond = -1;
+  o->amg_degree = 0;
   return EXPMV_OK;
 }
 
@@ -1282,6 +1539,12 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const
     init_plan_common(pl.get());
     expmv_status st = build_csr(pl.get(), rowptr, colind, val);
     if (st != EXPMV_OK) return st;
+    const int ip = o.inner_precond;
+    if (ip == 1 && !pl->symmetric) return EXPMV_EINVAL;
+    if (o.preconditioned && pl->symmetric && (ip == 1 || (ip == -1 && n >= 4096))) {
+      st = build_amg(pl.get());
+      if (st != EXPMV_OK && ip == 1) return st;
+    }
     *out = pl.release();
     return EXPMV_OK;
   });
@@ -1494,6 +1757,109 @@ expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X
     return r.hit_cap ? EXPMV_EINNER : EXPMV_OK;
   });
 }
+
+expmv_status expmv_apply_preconditioner(expmv_plan plan, int transpose, const double* X,
+                                        int64_t p, double* Y) {
+  if (!plan || !X || !Y || p < 1 || p > kMaxP || p > plan->n || plan->kind != 0)
+    return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    ensure_workspace(plan, int(p));
+    hipStream_t s = plan->stream;
+    const int64_t cnt = plan->n * p;
+    auto apply = [&](auto tag, const auto* x, auto* y) {
+      using T = decltype(tag);
+      if (plan->amg) {
+        amg_vcycle<T>(plan, int(p), x, y, 0, nullptr, nullptr);
+      } else {
+        Csr<T> A = csr_of<T>(plan, transpose);
+        hipLaunchKernelGGL((k_scale_rows<T>), dim3(grid_for(plan->n, 1, 4096)), dim3(kThreads), 0,
+                           s, plan->n, int(p), A.dinv, x, y);
+      }
+    };
+    if (plan->mixed) {
+      float* xf = reinterpret_cast<float*>(plan->ws.W.p);
+      float* yf = reinterpret_cast<float*>(plan->ws.Wt.p);
+      hipLaunchKernelGGL((k_convert<double, float>), dim3(512), dim3(kThreads), 0, s, cnt, X, xf,
+                         1.0);
+      apply(float(), xf, yf);
+      hipLaunchKernelGGL((k_convert<float, double>), dim3(512), dim3(kThreads), 0, s, cnt, yf, Y,
+                         1.0);
+    } else {
+      apply(double(), X, Y);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return EXPMV_OK;
+  });
+}
+
+expmv_status expmv_host_amg_build(int64_t n, const int32_t* rowptr, const int32_t* colind,
+                                  const double* val, int symmetric, double theta, int max_coarse,
+                                  expmv_amg* out) {
+  if (!out) return EXPMV_EINVAL;
+  *out = nullptr;
+  if (n < 1 || n > INT32_MAX - 1 || !rowptr || !colind || !val || !(theta >= 0.0) ||
+      max_coarse < 1 || max_coarse > 4096)
+    return EXPMV_EINVAL;
+  if (rowptr[0] != 0) return EXPMV_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return EXPMV_EINVAL;
+  const int64_t nnz = rowptr[n];
+  for (int64_t e = 0; e < nnz; ++e)
+    if (colind[e] < 0 || colind[e] >= n || !std::isfinite(val[e])) return EXPMV_EINVAL;
+  try {
+    std::unique_ptr<expmv_amg_s> h(new expmv_amg_s());
+    HostCsr A;
+    A.nrows = A.ncols = n;
+    A.rp.assign(rowptr, rowptr + n + 1);
+    A.ci.assign(colind, colind + nnz);
+    A.v.assign(val, val + nnz);
+    AmgParams prm;
+    prm.symmetric = symmetric != 0;
+    prm.theta = theta;
+    prm.max_coarse = max_coarse;
+    if (amg_build(A, prm, h->h) != 0) return EXPMV_EINVAL;
+    *out = h.release();
+    return EXPMV_OK;
+  } catch (const std::bad_alloc&) {
+    return EXPMV_ENOMEM;
+  }
+}
+
+int expmv_host_amg_levels(expmv_amg h) { return h ? int(h->h.lv.size()) : 0; }
+
+expmv_status expmv_host_amg_level(expmv_amg h, int level, int64_t* dims, double* lmax,
+                                  int32_t* a_rowptr, int32_t* a_colind, double* a_val,
+                                  int32_t* p_rowptr, int32_t* p_colind, double* p_val,
+                                  int32_t* agg) {
+  if (!h || level < 0 || level >= int(h->h.lv.size())) return EXPMV_EINVAL;
+  const AmgLevelHost& L = h->h.lv[level];
+  const bool coarsest = level + 1 == int(h->h.lv.size());
+  if (dims) {
+    dims[0] = L.A.nrows;
+    dims[1] = L.A.nnz();
+    dims[2] = coarsest ? 0 : L.P.ncols;
+    dims[3] = coarsest ? 0 : L.P.nnz();
+  }
+  if (lmax) *lmax = L.lmax;
+  if (a_rowptr) std::copy(L.A.rp.begin(), L.A.rp.end(), a_rowptr);
+  if (a_colind) std::copy(L.A.ci.begin(), L.A.ci.end(), a_colind);
+  if (a_val) std::copy(L.A.v.begin(), L.A.v.end(), a_val);
+  if (!coarsest) {
+    if (p_rowptr) std::copy(L.P.rp.begin(), L.P.rp.end(), p_rowptr);
+    if (p_colind) std::copy(L.P.ci.begin(), L.P.ci.end(), p_colind);
+    if (p_val) std::copy(L.P.v.begin(), L.P.v.end(), p_val);
+    if (agg) std::copy(L.agg.begin(), L.agg.end(), agg);
+  }
+  return EXPMV_OK;
+}
+
+expmv_status expmv_host_amg_coarse_inverse(expmv_amg h, double* inv) {
+  if (!h || !inv) return EXPMV_EINVAL;
+  std::copy(h->h.coarse_inv.begin(), h->h.coarse_inv.end(), inv);
+  return EXPMV_OK;
+}
+
+void expmv_host_amg_destroy(expmv_amg h) { delete h; }
 
 expmv_status expmv_cf_table(double* tau_re, double* tau_im, double* c_re, double* c_im,
                             double* omega0) {

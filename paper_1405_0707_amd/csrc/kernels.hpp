@@ -108,7 +108,9 @@ __device__ inline void xcd_rows(int64_t n, int64_t& r0, int64_t& r1) {
 }
 
 // acc (+)= sum_e val[e] * x[colind[e] * ld + c] over one CSR row, in order,
-// with four independent gathers in flight per step.
+// eight nonzeros per step with every load of a step issued before the first
+// product (predicated, no serial tail): a stencil row costs one round trip
+// for its indices and one for its gathers.
 // The operator's values are FP64 for every working type T: in the mixed
 // form the FP32 inner solver thus works with the exact operator (rounding
 // its entries to FP32 would move the eigenvalues of a non-normal operator
@@ -116,18 +118,22 @@ __device__ inline void xcd_rows(int64_t n, int64_t& r0, int64_t& r1) {
 template <typename T>
 __device__ inline T csr_row_dot(const int32_t* __restrict__ colind, const double* __restrict__ val,
                                 const T* __restrict__ x, int e0, int e1, int ld, int c) {
+  constexpr int U = 8;
   double acc = 0.0;
-  int e = e0;
-  for (; e + 4 <= e1; e += 4) {
-    const int64_t j0 = colind[e], j1 = colind[e + 1], j2 = colind[e + 2], j3 = colind[e + 3];
-    const double v0 = val[e], v1 = val[e + 1], v2 = val[e + 2], v3 = val[e + 3];
-    const T x0 = x[j0 * ld + c], x1 = x[j1 * ld + c], x2 = x[j2 * ld + c], x3 = x[j3 * ld + c];
-    acc += v0 * double(x0);
-    acc += v1 * double(x1);
-    acc += v2 * double(x2);
-    acc += v3 * double(x3);
+  for (int e = e0; e < e1; e += U) {
+    int32_t j[U];
+    double v[U], w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e + u < e1;
+      j[u] = ok ? colind[e + u] : -1;
+      v[u] = ok ? val[e + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) w[u] = j[u] >= 0 ? double(x[int64_t(j[u]) * ld + c]) : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u] * w[u];
   }
-  for (; e < e1; ++e) acc += val[e] * double(x[int64_t(colind[e]) * ld + c]);
   return T(acc);
 }
 
@@ -157,7 +163,9 @@ k_spmm(int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restri
 // Workgroup 0 records the scalars later kernels need in a two-slot table
 // indexed by the iteration's parity.
 //
-// Iteration k (z = D^{-1} r), three streaming kernels:
+// Iteration k (z = D^{-1} r, or z = the AMG V-cycle applied to r, computed
+// between B_{k-1} and C_k together with the (r, z) partials), three
+// streaming kernels:
 //   C_k: rho_k = (r_k, z_k), |r_k|^2 from B_{k-1}'s partials (init's for k=0);
 //        beta = rho_k / rho_{k-1}; convergence test;
 //        x += alpha_{k-1} p_{k-1};  p_k = z_k + beta p_{k-1}.
@@ -254,8 +262,9 @@ k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __rest
 template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
-       const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x, CgState* st,
-       KrylovCtl* ctl, const double* __restrict__ part_rr, double tol2, int maxit) {
+       const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
+       T* __restrict__ x, CgState* st, KrylovCtl* ctl, const double* __restrict__ part_rr,
+       double tol2, int maxit) {
   if (finished_before(ctl, k)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
@@ -320,7 +329,7 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
       const int64_t i = row * p + c;
       const T po = pold[i];
       x[i] += aprev * po;
-      if (any) pnew[i] = dinv[row] * r[i] + beta * po;
+      if (any) pnew[i] = (z ? z[i] : dinv[row] * r[i]) + beta * po;
     }
   }
 }
@@ -351,7 +360,7 @@ template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const T* __restrict__ q,
        CgState* st, const KrylovCtl* ctl, const double* __restrict__ part_sig,
-       double* __restrict__ part_rr) {
+       double* __restrict__ part_rr, int jacobi) {
   if (finished_by(ctl, k)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[PP];
@@ -379,11 +388,11 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
       const T rn = r[i] - alpha * q[i];
       r[i] = rn;
       const double rd = double(rn);
-      rz += rd * double(dinv[row]) * rd;
+      if (jacobi) rz += rd * double(dinv[row]) * rd;
       rr += rd * rd;
     }
   }
-  write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
+  if (jacobi) write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
   write_col_partial<PP>(rr, red, part_rr, 2 * PP, PP);
 }
 

@@ -1,0 +1,127 @@
+"""GPU checks of the AMG-preconditioned inner solver (through the C ABI):
+the device V-cycle against the numpy V-cycle over the same host hierarchy
+(element by element), the inner solve against a sparse LU solve, and whole
+solves against the closed form, with AMG and with Jacobi."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import inverses
+from oracle.cf import r_eval
+from paper_1405_0707_amd import HostAmg, Plan, _lib
+from paper_1405_0707_amd._lib import ExpmvError
+
+from amg_reference import VCycle
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def announce(name):
+    print(f"[gpu-test] {name}", flush=True)
+
+
+def _workload(name):
+    if name == "lap3d20":
+        A, t = wl.laplacian_3d(20), 5.842338 / (3 * (2 - 2 * np.cos(np.pi / 21)))
+    elif name == "vardiff96":
+        A, t = wl.vardiff_2d(96, 205), 0.1
+    else:
+        A, t = wl.laplacian_2d(70), 30.0
+    return A, t
+
+
+def _host_vcycle(A, t, degree):
+    K = A.val * (-t)   # the plan's K = -tA, rounded the same way
+    return VCycle(HostAmg(A.rowptr, A.colind, K).levels(), degree)
+
+
+@pytest.mark.parametrize("name,p,degree", [("lap3d20", 8, 2), ("lap3d20", 3, 1),
+                                           ("vardiff96", 32, 2), ("lap2d70", 1, 3),
+                                           ("vardiff96", 16, 4)])
+def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
+    announce(f"V-cycle {name} p={p} degree={degree}")
+    A, t = _workload(name)
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
+                  amg_degree=degree)
+    X = np.random.default_rng(p).standard_normal((A.n, p))
+    Y = pl.apply_preconditioner(torch.from_numpy(X)).cpu().numpy()
+    ref = _host_vcycle(A, t, degree).apply(X)
+    assert rel(Y, ref) < 1e-12
+    # the preconditioner is symmetric: <P x, y> = <x, P y>
+    Xs = X[:, :1]
+    Ys = np.random.default_rng(99).standard_normal((A.n, 1))
+    Px = pl.apply_preconditioner(torch.from_numpy(Xs)).cpu().numpy()
+    Py = pl.apply_preconditioner(torch.from_numpy(Ys)).cpu().numpy()
+    a, b = float(Px[:, 0] @ Ys[:, 0]), float(Xs[:, 0] @ Py[:, 0])
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_device_vcycle_mixed_form():
+    announce("V-cycle mixed")
+    A, t = _workload("vardiff96")
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
+                  precision="mixed")
+    X = np.random.default_rng(4).standard_normal((A.n, 8))
+    Y = pl.apply_preconditioner(torch.from_numpy(X)).cpu().numpy()
+    assert rel(Y, _host_vcycle(A, t, 2).apply(X)) < 1e-5
+
+
+@pytest.mark.parametrize("name,p", [("lap3d20", 8), ("vardiff96", 5)])
+def test_amg_inverse_matches_splu_in_few_iterations(name, p):
+    announce(f"AMG inverse {name} p={p}")
+    A, t = _workload(name)
+    X = np.random.default_rng(3).standard_normal((A.n, p))
+    M = (t * A.to_scipy()).tocsr()
+    ref = inverses.splu_inverse(M)(X)
+    amg = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
+                   inner_tol=1e-13)
+    jac = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="jacobi",
+                   inner_tol=1e-13)
+    Ya, ita = amg.apply_inverse(torch.from_numpy(X))
+    Yj, itj = jac.apply_inverse(torch.from_numpy(X))
+    assert rel(Ya.cpu().numpy(), ref) < 1e-10
+    assert rel(Yj.cpu().numpy(), ref) < 1e-10
+    assert 0 < ita <= 40 and itj >= 5 * ita, (ita, itj)
+
+
+@pytest.mark.parametrize("precond", ["amg", "jacobi"])
+def test_solve_with_each_preconditioner_matches_closed_form(precond):
+    announce(f"execute 3D N=24 p=8 m=15 inner={precond}")
+    N = 24
+    W = wl.c2(N=N)
+    W.t = 5.842338 / (3 * (2 - 2 * np.cos(np.pi / (N + 1))))
+    pl = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=DEV, m=W.m, k=W.k,
+                  inner_precond=precond)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=W.tol)
+    rB = inverses.dst_laplacian_function(N, 3, W.t, lambda x: r_eval(np.asarray(x)), W.B)
+    assert rel(Z.cpu().numpy(), rB) < 1e-10
+    assert (info.amg_levels > 1) == (precond == "amg")
+
+
+def test_amg_vardiff_matches_direct_rational():
+    """Variable coefficients (log-normal, sigma = 1), 64^2, p = 4: AMG-PCG
+    inner solves inside the whole method against per-pole sparse solves."""
+    announce("execute vardiff 64^2 AMG")
+    A = wl.vardiff_2d(64, 205)
+    t = 0.1
+    B = np.random.default_rng(5).standard_normal((A.n, 4))
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, m=10, inner_precond="amg")
+    Z, info = pl.execute(torch.from_numpy(B), tol=1e-11)
+    from oracle import exact
+    ref = exact.rational_sparse((t * A.to_scipy()).tocsc(), B)
+    assert rel(Z.cpu().numpy(), ref) < 1e-10
+    assert info.amg_levels >= 2
+
+
+def test_amg_rejected_for_nonsymmetric():
+    announce("AMG nonsymmetric -> EINVAL")
+    A = wl.convdiff_3d(8, 50.0)
+    with pytest.raises(ExpmvError) as e:
+        Plan.csr(A.rowptr, A.colind, A.val, 1e-3, device=DEV, inner_precond="amg")
+    assert e.value.status == _lib.EINVAL
