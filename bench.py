@@ -9,11 +9,14 @@ solve, update and the final combination) with A's plan and B already in
 HBM.  Prints one JSON line.
 
 Also reported:
-  roofline      the dominant kernel of the inner CG (the one with the
-                largest mean launch time among SpMM, residual update and
-                direction update), timed with HIP events on the solver's
-                stream during the timed steps (every 16th iteration);
-                achieved = algorithmic bytes per launch / mean duration.
+  roofline      the dominant kernel of the inner solve (largest device time
+                per inner iteration among the CG's SpMM, residual update,
+                direction update and, with AMG, the finest level's
+                smoothing-step kernel), timed with HIP events on the
+                solver's stream during the timed steps (every 4th
+                iteration); achieved = algorithmic bytes per launch / mean
+                duration; traffic = counter bytes per launch when the
+                kernel sources are the ones the counters were taken on.
   cpu_baseline  the oracle (plain numpy FP64, one thread) on a bounded
                 sample of the same workload, scaled to one solve.
 """
@@ -31,6 +34,35 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernels from two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a 256 MiB device copy;
+# early-exit launches excluded), valid while the kernel sources hash to the
+# recorded value; any change to them makes `traffic` null until re-measured.
+MEASURED_TRAFFIC = {
+    "S": {"bytes": 91.0e6, "sources": ("amg.hpp", "kernels.hpp"),
+          "sha256": "0319c17888c36927f847859f476058ef0917b482f6678ccabf8a3bd383b2284e"},
+}
+
+
+def sources_hash(names) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_1405_0707_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    rec = MEASURED_TRAFFIC.get(key)
+    if rec is None:
+        return None
+    try:
+        ok = sources_hash(rec["sources"]) == rec["sha256"]
+    except OSError:
+        ok = False
+    return rec["bytes"] if ok else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -47,8 +79,10 @@ def parse():
                          "'suite'")
     ap.add_argument("--vardiff-n", type=int, default=256,
                     help="grid side of the variable-coefficient workload in --suite")
-    ap.add_argument("--profile-every", type=int, default=16,
+    ap.add_argument("--profile-every", type=int, default=4,
                     help="sample every N-th inner iteration with HIP events (0 = off)")
+    ap.add_argument("--inner", choices=["auto", "amg", "jacobi"], default="auto",
+                    help="preconditioner of the inner CG (auto = AMG at this size)")
     return ap.parse_args()
 
 
@@ -63,6 +97,30 @@ def cg_kernel_bytes(n: int, nnz: int, p: int) -> dict:
     return {"A": 4 * (n + 1) + 12 * nnz + 16 * n * p,
             "B": 8 * n + 24 * n * p,
             "C": 8 * n + 40 * n * p}
+
+
+def smooth_kernel_bytes(n: int, nnz: int, p: int, degree: int) -> float:
+    """Mean algorithmic HBM bytes per launch of the finest AMG level's
+    smoothing-step kernel k_amg_step over the 2 * degree launches of one
+    V-cycle (FP64, int32 indices; A = 4(n+1) + 12 nnz for the CSR operator):
+      first pre-step (iterate s0 D^{-1} b implicit): A + 8n + 24np
+      later pre-steps: A + 8n + 40np
+      residual: A + 24np (A + 8n + 16np when degree = 1)
+      post-steps: A + 8n + 24np (+ 8np for the direction d unless the step is
+      the last one, + 8np for reading d after the first)."""
+    A = 4 * (n + 1) + 12 * nnz
+    launches = []
+    for st in range(1, degree):
+        launches.append(A + 8 * n + (24 if st == 1 else 40) * n * p)
+    launches.append(A + 24 * n * p if degree > 1 else A + 8 * n + 16 * n * p)
+    for st in range(degree):
+        b = A + 8 * n + 24 * n * p
+        if st > 0:
+            b += 8 * n * p
+        if st + 1 < degree:
+            b += 8 * n * p
+        launches.append(b)
+    return sum(launches) / len(launches)
 
 
 def cpu_baseline(W):
@@ -183,7 +241,7 @@ def main():
     W = wl.c2()
     t0 = time.perf_counter()
     plan = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=dev, m=W.m, k=W.k,
-                    profile=max(0, args.profile_every))
+                    profile=max(0, args.profile_every), inner_precond=args.inner)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     B = torch.from_numpy(W.B).to(dev)
@@ -218,16 +276,27 @@ def main():
         names = {"A": "k_cg_a (CSR SpMM q = K p of the inner CG)",
                  "B": "k_cg_b (inner CG residual update)",
                  "C": "k_cg_c (inner CG direction and iterate update)"}
+        per_iter = dict(mean)          # device time per inner iteration
+        sm_launches = sum(i.kern_smooth_launches for i in infos)
+        if sm_launches:
+            degree = 2
+            mean["S"] = sum(i.kern_ms_smooth * i.kern_smooth_launches for i in infos) / sm_launches
+            byt["S"] = smooth_kernel_bytes(W.n, W.A.nnz, W.p, degree)
+            names["S"] = ("k_amg_step, finest level (AMG V-cycle smoothing steps and residual, "
+                          "CSR SpMM fused with the Chebyshev update)")
+            per_iter["S"] = mean["S"] * sm_launches / samples
         kernels = {key: {"kernel": names[key], "mean_launch_ms": round(mean[key], 5),
-                         "bytes_per_launch": byt[key],
-                         "achieved_GBs": round(byt[key] / (mean[key] * 1e-3) / 1e9, 1)}
+                         "bytes_per_launch": int(byt[key]),
+                         "achieved_GBs": round(byt[key] / (mean[key] * 1e-3) / 1e9, 1),
+                         "ms_per_inner_iteration": round(per_iter[key], 5)}
                    for key in mean}
-        dom = max(mean, key=lambda key: mean[key])
+        dom = max(per_iter, key=lambda key: per_iter[key])
         ach = byt[dom] / (mean[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": names[dom], "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": byt[dom],
-                "mean_launch_ms": round(mean[dom], 5), "samples": samples}
+                "traffic": measured_traffic(dom), "bytes_per_launch": int(byt[dom]),
+                "mean_launch_ms": round(mean[dom], 5),
+                "samples": sm_launches if dom == "S" else samples}
 
     if args.copy_calibration:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -252,6 +321,8 @@ def main():
                                "||tA||_2=1e4, B n x 8 Gaussian seed 2, m=15, k=40, tol=1e-10",
                    "n": W.n, "p": W.p, "m": W.m, "k": W.k, "tol": W.tol},
         "rel_err_vs_rational_closed_form": rel_err,
+        "inner_preconditioner": (f"AMG ({info.amg_levels} levels)" if info.amg_levels
+                                 else "Jacobi"),
         "cycles": info.cycles, "block_apps": info.block_apps,
         "inner_iters": int(info.inner_iters), "err_bound": info.err_bound,
         "phase_ms": {"apply": round(info.ms_apply, 2), "orth": round(info.ms_orth, 2),

@@ -115,6 +115,9 @@ typedef struct {                  /* host struct, filled by expmv_execute */
                                      C = search-direction and iterate update          */
   int amg_levels;                 /* levels of the AMG hierarchy of the inner solver
                                      (0: Jacobi preconditioning)                      */
+  int kern_smooth_launches;       /* sampled launches of the finest AMG level's
+                                     smoothing-step kernel (pre, residual, post)      */
+  double kern_ms_smooth;          /* their mean device time, ms                       */
 } expmv_info;
 
 typedef struct expmv_plan_s* expmv_plan;

@@ -29,7 +29,8 @@ class Info(C.Structure):
                 ("ms_apply", C.c_double), ("ms_orth", C.c_double), ("ms_small", C.c_double),
                 ("ms_update", C.c_double), ("breakdown", C.c_int), ("kern_samples", C.c_int),
                 ("kern_ms_a", C.c_double), ("kern_ms_b", C.c_double),
-                ("kern_ms_c", C.c_double), ("amg_levels", C.c_int)]
+                ("kern_ms_c", C.c_double), ("amg_levels", C.c_int),
+                ("kern_smooth_launches", C.c_int), ("kern_ms_smooth", C.c_double)]
 
     def as_dict(self):
         d = {}

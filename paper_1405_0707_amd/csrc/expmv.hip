@@ -103,6 +103,8 @@ struct Workspace {
 
 constexpr int kAmgMaxDeg = 4;
 constexpr double kAmgEigRatio = 20.0;   // Chebyshev interval [lmax / ratio, lmax]
+constexpr int kSmoothEv = 4 * kAmgMaxDeg;   // events around the finest level's smoothing steps
+constexpr int kSampleEv = 6 + kSmoothEv;    // events of one profiled inner iteration
 
 // One level of the AMG hierarchy on the device.  Level 0 borrows the plan's
 // CSR operator and Jacobi scaling; coarser levels own their Galerkin
@@ -173,11 +175,15 @@ struct expmv_plan_s {
   hipEvent_t ev[2]{};
   int ldh = 0;
   // profiling (opts.profile > 0): event pairs around sampled inner iterations
+  // (per sample: C, A, B start/stop, then up to kSmoothEv events around the
+  // finest level's smoothing steps of the sample's V-cycle)
   std::vector<hipEvent_t> pev;
   std::vector<int> pev_iter;      // inner iteration index of each sample
-  int pev_used = 0;
-  double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0;
-  int prof_samples = 0;
+  std::vector<int> pev_nsm;       // smoothing launches timed in each sample
+  int pev_used = 0;               // samples in use
+  double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0, prof_ms_sm = 0.0;
+  int prof_samples = 0, prof_sm_launches = 0;
+  int last_inner_iters = 0;       // iterations of the previous inner solve
   // AMG preconditioner of the CSR inner solver (symmetric K)
   std::unique_ptr<AmgDev> amg;
 };
@@ -316,18 +322,25 @@ void apply_K(expmv_plan_s* pl, int transpose, const T* X, T* Y, int p) {
 // sampled iteration).  Only iterations the solve actually ran count (kexec
 // = iterations executed); the ones issued after convergence return at once.
 void collect_profile(expmv_plan_s* pl, int kexec) {
-  if (pl->pev_used == 0) return;
-  for (int i = 0; i + 6 <= pl->pev_used; i += 6) {
+  for (int sidx = 0; sidx < pl->pev_used; ++sidx) {
+    const hipEvent_t* e = &pl->pev[size_t(sidx) * kSampleEv];
+    const int nsm = pl->pev_nsm[sidx];
     float tc = 0.f, ta = 0.f, tb = 0.f;
-    HIPCHK(hipEventSynchronize(pl->pev[i + 5]));
-    HIPCHK(hipEventElapsedTime(&tc, pl->pev[i], pl->pev[i + 1]));
-    HIPCHK(hipEventElapsedTime(&ta, pl->pev[i + 2], pl->pev[i + 3]));
-    HIPCHK(hipEventElapsedTime(&tb, pl->pev[i + 4], pl->pev[i + 5]));
-    if (pl->pev_iter[i / 6] < kexec) {
+    HIPCHK(hipEventSynchronize(nsm > 0 ? e[6 + 2 * nsm - 1] : e[5]));
+    HIPCHK(hipEventElapsedTime(&tc, e[0], e[1]));
+    HIPCHK(hipEventElapsedTime(&ta, e[2], e[3]));
+    HIPCHK(hipEventElapsedTime(&tb, e[4], e[5]));
+    if (pl->pev_iter[sidx] < kexec) {
       pl->prof_ms_a += ta;
       pl->prof_ms_b += tb;
       pl->prof_ms_c += tc;
       pl->prof_samples += 1;
+      for (int q = 0; q < nsm; ++q) {
+        float ts = 0.f;
+        HIPCHK(hipEventElapsedTime(&ts, e[6 + 2 * q], e[6 + 2 * q + 1]));
+        pl->prof_ms_sm += ts;
+        pl->prof_sm_launches += 1;
+      }
     }
   }
   pl->pev_used = 0;
@@ -350,17 +363,20 @@ double inner_tol_of(expmv_plan_s* pl) {
 
 // Poll the inner solver's control word every `chunk` iterations, one chunk
 // ahead of the device; returns when a chunk has seen every column stop.
+// The first chunk may be larger (first_chunk, e.g. a few iterations short
+// of what the previous inner solve needed).
 template <typename LaunchChunk>
 InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chunk,
-                           int chunk = 16) {
+                           int chunk = 16, int first_chunk = 0) {
   Workspace& w = pl->ws;
   hipStream_t s = pl->stream;
   int launched = 0;
   int pending = -1, slot = 0;
   bool done = false;
   while (!done) {
-    launch_chunk(launched, chunk);
-    launched += chunk;
+    const int c = (launched == 0 && first_chunk > chunk) ? std::min(first_chunk, maxit) : chunk;
+    launch_chunk(launched, c);
+    launched += c;
     HIPCHK(hipMemcpyAsync(pl->host_flags + 4 * slot, w.ctl.p, sizeof(KrylovCtl),
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(pl->ev[slot], s));
@@ -412,7 +428,7 @@ void amg_vectors(AmgDev& H, int p, size_t el) {
 // and with part_rz the (b, out) partials of the last smoothing step).
 template <typename T, int PP>
 void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
-               const KrylovCtl* ctl, double* part_rz) {
+               const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
   AmgDevLevel& L = *H.lv[l];
   hipStream_t s = pl->stream;
   const int n = int(L.n);
@@ -429,11 +445,17 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   const int gcoarse_a = grid_for(n, PP * GA, 4096), gcoarse_p = grid_for(n, PP * GP, 4096);
   auto step = [&](int mode, const T* x, T* o, double cd, double ad, double* part) {
     T* d = reinterpret_cast<T*>(L.vd.p);
-    if (fine)
-      hipLaunchKernelGGL((k_amg_step<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads), 0,
-                         s, k, ctl, n, p, GA, L.arp, L.aci, L.av, dinv, b, x, d, o, L.ad[0], cd,
-                         ad, mode, part);
-    else
+    if (fine) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (sev && *nsev < kSmoothEv / 2) {
+        e0 = sev[2 * *nsev];
+        e1 = sev[2 * *nsev + 1];
+        *nsev += 1;
+      }
+      hipExtLaunchKernelGGL((k_amg_step<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads),
+                            0, s, e0, e1, 0, k, ctl, n, p, GA, L.arp, L.aci, L.av, dinv, b, x, d,
+                            o, L.ad[0], cd, ad, mode, part);
+    } else
       hipLaunchKernelGGL((k_amg_step<T, PP, kThreads, false>), dim3(gcoarse_a), dim3(kThreads), 0,
                          s, k, ctl, n, p, GA, L.arp, L.aci, L.av, dinv, b, x, d, o, L.ad[0], cd,
                          ad, mode, part);
@@ -456,7 +478,7 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   hipLaunchKernelGGL((k_amg_restrict<T, PP, kThreads, false>), dim3(grid_for(nc, PP * GR, 4096)),
                      dim3(kThreads), 0, s, k, ctl, nc, p, GR, L.Rrp.p, L.Rci.p, L.Rv.p, r, bc);
   T* xc = reinterpret_cast<T*>(C.vo.p);
-  amg_level<T, PP>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr);
+  amg_level<T, PP>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
   const int pmode = implicit ? kAmgX0 : 0;
   if (fine)
     hipLaunchKernelGGL((k_amg_prolong<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads), 0,
@@ -477,13 +499,15 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   }
 }
 
+// One V-cycle; sev (may be NULL) receives start/stop events of the finest
+// level's smoothing-step launches, *nsev their number.
 template <typename T>
 void amg_vcycle(expmv_plan_s* pl, int p, const T* b, T* out, int k, const KrylovCtl* ctl,
-                double* part_rz) {
+                double* part_rz, hipEvent_t* sev = nullptr, int* nsev = nullptr) {
   AmgDev& H = *pl->amg;
   amg_vectors(H, p, sizeof(T));
   const int PP = pow2_lanes(p);
-  DISPATCH_PP(PP, amg_level<T, P_>(pl, H, 0, p, b, out, k, ctl, part_rz));
+  DISPATCH_PP(PP, amg_level<T, P_>(pl, H, 0, p, b, out, k, ctl, part_rz, sev, nsev));
 }
 
 // out = K^{-1} (sign * src) by batched Jacobi-PCG (K SPD); out is the iterate.
@@ -513,12 +537,14 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
       T* pold = P[k & 1];
       T* pnew = P[(k + 1) & 1];
       const bool sample = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0 &&
-                          pl->pev_used + 6 <= int(pl->pev.size());
-      hipEvent_t* e = sample ? &pl->pev[pl->pev_used] : nullptr;
+                          pl->pev_used < int(pl->pev_iter.size());
+      hipEvent_t* e = sample ? &pl->pev[size_t(pl->pev_used) * kSampleEv] : nullptr;
+      int* nsm = sample ? &pl->pev_nsm[pl->pev_used] : nullptr;
       hipEvent_t ez = nullptr;
       if (sample) {
-        pl->pev_iter[pl->pev_used / 6] = k;
-        pl->pev_used += 6;
+        pl->pev_iter[pl->pev_used] = k;
+        *nsm = 0;
+        pl->pev_used += 1;
       }
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
                                             sample ? e[0] : ez, sample ? e[1] : ez, 0, k, int(n),
@@ -532,10 +558,11 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
                                             sample ? e[4] : ez, sample ? e[5] : ez, 0, k, int(n),
                                             p, A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
                                             w.part_rr.p, amg ? 0 : 1));
-      if (amg) amg_vcycle<T>(pl, p, r, z, k, w.ctl.p, w.part_rr.p);
+      if (amg) amg_vcycle<T>(pl, p, r, z, k, w.ctl.p, w.part_rr.p, sample ? e + 6 : nullptr, nsm);
     }
-  }, amg ? 2 : 16);
+  }, amg ? 1 : 16, amg ? pl->last_inner_iters - 2 : 0);
   collect_profile(pl, res.iters);
+  pl->last_inner_iters = res.iters;
   return res;
 }
 
@@ -989,8 +1016,8 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   const double t_start = host_now_ms();
   expmv_info inf{};
   double ms_apply = 0, ms_orth = 0, ms_small = 0, ms_update = 0;
-  pl->prof_ms_a = pl->prof_ms_b = pl->prof_ms_c = 0.0;
-  pl->prof_samples = 0;
+  pl->prof_ms_a = pl->prof_ms_b = pl->prof_ms_c = pl->prof_ms_sm = 0.0;
+  pl->prof_samples = pl->prof_sm_launches = 0;
   pl->pev_used = 0;
 
   double c_re[kNShift], c_im[kNShift], delta[kNShift];
@@ -1223,6 +1250,8 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   inf.kern_ms_a = pl->prof_samples ? pl->prof_ms_a / pl->prof_samples : 0.0;
   inf.kern_ms_b = pl->prof_samples ? pl->prof_ms_b / pl->prof_samples : 0.0;
   inf.kern_ms_c = pl->prof_samples ? pl->prof_ms_c / pl->prof_samples : 0.0;
+  inf.kern_smooth_launches = pl->prof_sm_launches;
+  inf.kern_ms_smooth = pl->prof_sm_launches ? pl->prof_ms_sm / pl->prof_sm_launches : 0.0;
   inf.amg_levels = pl->amg ? int(pl->amg->lv.size()) : 0;
   if (info) *info = inf;
   return status;
@@ -1292,8 +1321,9 @@ void init_plan_common(expmv_plan_s* pl) {
   HIPCHK(hipEventCreateWithFlags(&pl->ev[0], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pl->ev[1], hipEventDisableTiming));
   if (pl->opts.profile > 0) {
-    pl->pev.resize(6 * 128);
+    pl->pev.resize(size_t(kSampleEv) * 128);
     pl->pev_iter.resize(128);
+    pl->pev_nsm.resize(128);
     for (auto& e : pl->pev) HIPCHK(hipEventCreate(&e));
   }
   upload_cf(pl);
