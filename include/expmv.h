@@ -91,11 +91,12 @@ typedef struct {
                           correction solve); -1 = 1 for nonsymmetric A, 0 otherwise      */
   int inner_precond;   /* preconditioner of the CSR inner solver (the solve that applies
                           (tA)^{-1}, Section 4.1): 0 Jacobi (diagonal scaling),
-                          1 smoothed-aggregation AMG V-cycle (symmetric A only; A with
-                          n <= 500 has no coarse level and keeps Jacobi),
-                          -1 auto = AMG for symmetric A with n >= 4096, else Jacobi     */
+                          1 smoothed-aggregation AMG V-cycle (CG for symmetric A,
+                          BiCGStab for general A with a second hierarchy for A^T; A
+                          with n <= 500 has no coarse level and keeps Jacobi),
+                          -1 auto = AMG for n >= 4096, else Jacobi                       */
   int amg_degree;      /* Chebyshev smoothing steps before and after each coarse
-                          correction (1..4; 0 = 2)                                       */
+                          correction (1..4; 0 = 2 for symmetric A, 1 otherwise)          */
 } expmv_opts;
 
 typedef struct {                  /* host struct, filled by expmv_execute */
@@ -134,8 +135,8 @@ expmv_status expmv_default_opts(expmv_opts* o);
  * with the AMG inner preconditioner, the hierarchy built on the host from K
  * (levels, prolongators, Galerkin operators, dense inverse of the coarsest
  * operator).  opts may be NULL (defaults).  *out receives the plan.
- * Errors: EINVAL (also: inner_precond = 1 with a nonsymmetric A, or an AMG
- * hierarchy that cannot be built), ENOTNEG (a diagonal entry of tA >= 0, or
+ * Errors: EINVAL (also: inner_precond = 1 and an AMG hierarchy that cannot
+ * be built), ENOTNEG (a diagonal entry of tA >= 0, or
  * missing), ENOMEM, EHIP. */
 expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
                             const int32_t* colind, const double* val, double t,

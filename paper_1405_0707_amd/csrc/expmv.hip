@@ -86,7 +86,7 @@ struct Workspace {
   DevBuf<char> Win, Wout;       // n x p (inner-solver type, when it differs)
   DevBuf<char> Rin, Din;        // n x p (inner-solver type, refinement)
   DevBuf<char> kr, kpa, kpb, kq, kv, ks, kt, krh;   // inner-solver vectors, n x p
-  DevBuf<char> kz;                                  // preconditioned residual (AMG)
+  DevBuf<char> kz, kph, ksh;                        // AMG-preconditioned vectors
   DevBuf<double> X;             // n x 14p
   DevBuf<double> partial;       // reductions of the dense kernels
   DevBuf<double> hcoef, gram, R1, R2, Rinv, w0;   // small orth buffers
@@ -184,8 +184,9 @@ struct expmv_plan_s {
   double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0, prof_ms_sm = 0.0;
   int prof_samples = 0, prof_sm_launches = 0;
   int last_inner_iters = 0;       // iterations of the previous inner solve
-  // AMG preconditioner of the CSR inner solver (symmetric K)
-  std::unique_ptr<AmgDev> amg;
+  // AMG preconditioner of the CSR inner solver: hierarchy of K and, for a
+  // nonsymmetric K, of K^T (transposed solves)
+  std::unique_ptr<AmgDev> amg, amgT;
 };
 
 namespace expmv {
@@ -234,6 +235,10 @@ void ensure_workspace(expmv_plan_s* pl, int p) {
   w.kpb.alloc(blk * el);
   w.kq.alloc(blk * el);
   if (pl->amg) w.kz.alloc(blk * el);
+  if (pl->amg && !pl->symmetric) {
+    w.kph.alloc(blk * el);
+    w.ksh.alloc(blk * el);
+  }
   if (!pl->symmetric) {
     w.kv.alloc(blk * el);
     w.ks.alloc(blk * el);
@@ -499,12 +504,18 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   }
 }
 
-// One V-cycle; sev (may be NULL) receives start/stop events of the finest
-// level's smoothing-step launches, *nsev their number.
+// The hierarchy for K (transpose = 0) or K^T; NULL without AMG.
+AmgDev* amg_for(expmv_plan_s* pl, int transpose) {
+  if (transpose && !pl->symmetric) return pl->amgT.get();
+  return pl->amg.get();
+}
+
+// One V-cycle of hierarchy H; sev (may be NULL) receives start/stop events
+// of the finest level's smoothing-step launches, *nsev their number.
 template <typename T>
-void amg_vcycle(expmv_plan_s* pl, int p, const T* b, T* out, int k, const KrylovCtl* ctl,
-                double* part_rz, hipEvent_t* sev = nullptr, int* nsev = nullptr) {
-  AmgDev& H = *pl->amg;
+void amg_vcycle(expmv_plan_s* pl, AmgDev& H, int p, const T* b, T* out, int k,
+                const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev = nullptr,
+                int* nsev = nullptr) {
   amg_vectors(H, p, sizeof(T));
   const int PP = pow2_lanes(p);
   DISPATCH_PP(PP, amg_level<T, P_>(pl, H, 0, p, b, out, k, ctl, part_rz, sev, nsev));
@@ -525,12 +536,13 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
   T* r = reinterpret_cast<T*>(w.kr.p);
   T* q = reinterpret_cast<T*>(w.kq.p);
   T* P[2] = {reinterpret_cast<T*>(w.kpa.p), reinterpret_cast<T*>(w.kpb.p)};
-  const bool amg = pl->amg != nullptr;
+  AmgDev* H = amg_for(pl, 0);
+  const bool amg = H != nullptr;
   T* z = amg ? reinterpret_cast<T*>(w.kz.p) : nullptr;
   DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
                                      int(n), p, sign, src, A.dinv, out, r, P[0], w.ctl.p,
                                      w.part_rr.p));
-  if (amg) amg_vcycle<T>(pl, p, r, z, 0, w.ctl.p, w.part_rr.p);
+  if (amg) amg_vcycle<T>(pl, *H, p, r, z, 0, w.ctl.p, w.part_rr.p);
   InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
     for (int it = 0; it < chunk; ++it) {
       const int k = launched + it;
@@ -558,7 +570,8 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
                                             sample ? e[4] : ez, sample ? e[5] : ez, 0, k, int(n),
                                             p, A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
                                             w.part_rr.p, amg ? 0 : 1));
-      if (amg) amg_vcycle<T>(pl, p, r, z, k, w.ctl.p, w.part_rr.p, sample ? e + 6 : nullptr, nsm);
+      if (amg)
+        amg_vcycle<T>(pl, *H, p, r, z, k, w.ctl.p, w.part_rr.p, sample ? e + 6 : nullptr, nsm);
     }
   }, amg ? 1 : 16, amg ? pl->last_inner_iters - 2 : 0);
   collect_profile(pl, res.iters);
@@ -586,6 +599,10 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
   T* sv = reinterpret_cast<T*>(w.ks.p);
   T* tv = reinterpret_cast<T*>(w.kt.p);
   T* rh = reinterpret_cast<T*>(w.krh.p);
+  AmgDev* H = amg_for(pl, transpose);
+  T* ph = H ? reinterpret_cast<T*>(w.kph.p) : nullptr;   // M^{-1} p
+  T* sh = H ? reinterpret_cast<T*>(w.ksh.p) : nullptr;   // M^{-1} s
+  const T* dscale = H ? nullptr : A.dinv;
   DISPATCH_PP(PP, hipLaunchKernelGGL((k_bcg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
                                      int(n), p, sign, src, out, r, rh, pv, v, w.ctl.p,
                                      w.part_rr.p));
@@ -595,18 +612,23 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
       DISPATCH_PP(PP, {
         hipLaunchKernelGGL((k_bcg_u1<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
                            r, pv, v, w.bcgst.p, w.ctl.p, w.part_rr.p, tol2, maxit);
+        if (H) amg_vcycle<T>(pl, *H, p, pv, ph, i, w.ctl.p, nullptr);
         hipLaunchKernelGGL((k_bcg_s<T, P_, 1>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
-                           A.rowptr, A.colind, A.val, A.dinv, pv, rh, v, w.ctl.p, w.part_sig.p);
+                           A.rowptr, A.colind, A.val, dscale, H ? ph : pv, rh, v, w.ctl.p,
+                           w.part_sig.p);
         hipLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p, r,
                            v, sv, w.bcgst.p, w.ctl.p, w.part_sig.p);
+        if (H) amg_vcycle<T>(pl, *H, p, sv, sh, i, w.ctl.p, nullptr);
         hipLaunchKernelGGL((k_bcg_s<T, P_, 2>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
-                           A.rowptr, A.colind, A.val, A.dinv, sv, sv, tv, w.ctl.p, w.part_sig.p);
+                           A.rowptr, A.colind, A.val, dscale, H ? sh : sv, sv, tv, w.ctl.p,
+                           w.part_sig.p);
         hipLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
-                           A.dinv, pv, sv, tv, rh, out, r, w.bcgst.p, w.ctl.p, w.part_sig.p,
-                           w.part_rr.p);
+                           A.dinv, pv, sv, tv, rh, ph, sh, out, r, w.bcgst.p, w.ctl.p,
+                           w.part_sig.p, w.part_rr.p);
       });
     }
-  });
+  }, H ? 1 : 16, H ? pl->last_inner_iters - 2 : 0);
+  pl->last_inner_iters = res.iters;
   return res;
 }
 
@@ -1459,37 +1481,42 @@ void chebyshev_coefficients(double lmax, int degree, double* cd, double* ad) {
   }
 }
 
-// Build the AMG hierarchy of K on the host and upload it (symmetric K).
-expmv_status build_amg(expmv_plan_s* pl) {
+// Build the AMG hierarchy of K (tr = 0) or K^T (tr = 1) on the host and
+// upload it.  Default smoothing degree: 2 for symmetric K (Chebyshev), 1 for
+// nonsymmetric K (damped Jacobi: higher Chebyshev degrees amplify the
+// complex part of a convection operator's spectrum).
+expmv_status build_amg(expmv_plan_s* pl, int tr) {
   const int64_t n = pl->n, nnz = pl->nnz;
+  const Csr<double> A = csr_of<double>(pl, tr);
   HostCsr K;
   K.nrows = K.ncols = n;
   {
     std::vector<int32_t> rp(n + 1);
-    HIPCHK(hipMemcpy(rp.data(), pl->rowptr.p, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(rp.data(), A.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
     K.rp.assign(rp.begin(), rp.end());
     K.ci.resize(nnz);
     K.v.resize(nnz);
-    HIPCHK(hipMemcpy(K.ci.data(), pl->colind.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(K.v.data(), pl->val.p, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(K.ci.data(), A.colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(K.v.data(), A.val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
   }
   AmgParams prm;
-  prm.symmetric = true;
+  prm.symmetric = pl->symmetric;
   AmgHost h;
   if (amg_build(K, prm, h) != 0) return EXPMV_EINVAL;
   if (h.lv.size() < 2) return EXPMV_OK;   // n <= max_coarse: no coarse level, Jacobi
   std::unique_ptr<AmgDev> H(new AmgDev());
-  H->degree = pl->opts.amg_degree > 0 ? pl->opts.amg_degree : 2;
+  H->degree = pl->opts.amg_degree > 0 ? pl->opts.amg_degree : (pl->symmetric ? 2 : 1);
   for (size_t l = 0; l < h.lv.size(); ++l) {
     const AmgLevelHost& Lh = h.lv[l];
     std::unique_ptr<AmgDevLevel> L(new AmgDevLevel());
     L->n = Lh.A.nrows;
     if (l == 0) {
-      L->arp = pl->rowptr.p;
-      L->aci = pl->colind.p;
-      L->av = pl->val.p;
-      L->dinv64 = pl->dinv.p;
-      L->dinv32 = pl->dinvf.p;
+      const bool t = tr && !pl->symmetric;
+      L->arp = A.rowptr;
+      L->aci = A.colind;
+      L->av = A.val;
+      L->dinv64 = t ? pl->dinvT.p : pl->dinv.p;
+      L->dinv32 = t ? pl->dinvTf.p : pl->dinvf.p;
     } else {
       upload_csr(Lh.A, L->Arp, L->Aci, L->Av);
       upload_vec(L->dinv, Lh.dinv);
@@ -1513,7 +1540,7 @@ expmv_status build_amg(expmv_plan_s* pl) {
     H->lv.push_back(std::move(L));
   }
   upload_vec(H->cinv, h.coarse_inv);
-  pl->amg = std::move(H);
+  (tr && !pl->symmetric ? pl->amgT : pl->amg) = std::move(H);
   pl->ws.p = 0;   // workspace re-sized with the AMG vectors on the next call
   return EXPMV_OK;
 }
@@ -1570,9 +1597,12 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const
     expmv_status st = build_csr(pl.get(), rowptr, colind, val);
     if (st != EXPMV_OK) return st;
     const int ip = o.inner_precond;
-    if (ip == 1 && !pl->symmetric) return EXPMV_EINVAL;
-    if (o.preconditioned && pl->symmetric && (ip == 1 || (ip == -1 && n >= 4096))) {
-      st = build_amg(pl.get());
+    if (o.preconditioned && (ip == 1 || (ip == -1 && n >= 4096))) {
+      st = build_amg(pl.get(), 0);
+      if (st == EXPMV_OK && !pl->symmetric && pl->amg) {
+        st = build_amg(pl.get(), 1);
+        if (st != EXPMV_OK) pl->amg.reset();   // both or neither
+      }
       if (st != EXPMV_OK && ip == 1) return st;
     }
     *out = pl.release();
@@ -1798,8 +1828,8 @@ expmv_status expmv_apply_preconditioner(expmv_plan plan, int transpose, const do
     const int64_t cnt = plan->n * p;
     auto apply = [&](auto tag, const auto* x, auto* y) {
       using T = decltype(tag);
-      if (plan->amg) {
-        amg_vcycle<T>(plan, int(p), x, y, 0, nullptr, nullptr);
+      if (AmgDev* H = amg_for(plan, transpose)) {
+        amg_vcycle<T>(plan, *H, int(p), x, y, 0, nullptr, nullptr);
       } else {
         Csr<T> A = csr_of<T>(plan, transpose);
         hipLaunchKernelGGL((k_scale_rows<T>), dim3(grid_for(plan->n, 1, 4096)), dim3(kThreads), 0,

@@ -397,9 +397,11 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
 }
 
 // ---------------------------------------------------------------------------
-// Batched BiCGStab (right Jacobi preconditioning, y = D^{-1} p, z = D^{-1} s)
-// on K x = b for nonsymmetric K, column-wise, b = sign * src, r^ = b.  Same
-// scheme as the CG: every kernel re-sums the previous kernel's partials.
+// Batched BiCGStab (right preconditioning, y = M^{-1} p, z = M^{-1} s, with
+// M^{-1} = D^{-1} fused into the kernels below, or one AMG V-cycle whose
+// results y, z the kernels read) on K x = b for nonsymmetric K, column-wise,
+// b = sign * src, r^ = b.  Same scheme as the CG: every kernel re-sums the
+// previous kernel's partials.
 // Iteration i:
 //   U1: rho_i = (r^, r), |r|^2 (partials of U3_{i-1} or init); convergence;
 //       beta = (rho_i / rho_{i-1}) (alpha / omega); p = r + beta (p - omega v)
@@ -532,7 +534,8 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
   }
 }
 
-// out = K D^{-1} in, partials (a, out) [NV = 1] or (out, a), (out, out) [NV = 2]
+// out = K D^{-1} in (out = K in when dinv is NULL: the input is already
+// preconditioned), partials (a, out) [NV = 1] or (out, a), (out, out) [NV = 2]
 template <typename T, int PP, int NV>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
@@ -549,9 +552,13 @@ k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* 
     if (c < p) {
       const int e0 = rowptr[row], e1 = rowptr[row + 1];
       double accd = 0.0;
-      for (int e = e0; e < e1; ++e) {
-        const int64_t j = colind[e];
-        accd += val[e] * double(dinv[j] * in[j * p + c]);
+      if (dinv) {
+        for (int e = e0; e < e1; ++e) {
+          const int64_t j = colind[e];
+          accd += val[e] * double(dinv[j] * in[j * p + c]);
+        }
+      } else {
+        accd = double(csr_row_dot(colind, val, in, e0, e1, p, c));
       }
       const T acc = T(accd);
       const int64_t idx = row * p + c;
@@ -599,8 +606,9 @@ template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_u3(int i, int n, int p, const T* __restrict__ dinv, const T* __restrict__ pv,
          const T* __restrict__ sv, const T* __restrict__ tv, const T* __restrict__ rhat,
-         T* __restrict__ x, T* __restrict__ r, BcgState* st, const KrylovCtl* ctl,
-         const double* __restrict__ part, double* __restrict__ part_rr) {
+         const T* __restrict__ ph, const T* __restrict__ sh, T* __restrict__ x,
+         T* __restrict__ r, BcgState* st, const KrylovCtl* ctl, const double* __restrict__ part,
+         double* __restrict__ part_rr) {
   if (finished_by(ctl, i)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
@@ -627,9 +635,13 @@ k_bcg_u3(int i, int n, int p, const T* __restrict__ dinv, const T* __restrict__ 
   for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
     if (c < p) {
       const int64_t idx = row * p + c;
-      const T dv = dinv[row];
       const T sval = sv[idx];
-      x[idx] += a * (dv * pv[idx]) + om * (dv * sval);
+      if (ph) {
+        x[idx] += a * ph[idx] + om * sh[idx];
+      } else {
+        const T dv = dinv[row];
+        x[idx] += a * (dv * pv[idx]) + om * (dv * sval);
+      }
       const T rn = sval - om * tv[idx];
       r[idx] = rn;
       rr_hat += double(rhat[idx]) * double(rn);

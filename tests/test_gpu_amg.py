@@ -9,8 +9,7 @@ import torch
 import workloads as wl
 from oracle import inverses
 from oracle.cf import r_eval
-from paper_1405_0707_amd import HostAmg, Plan, _lib
-from paper_1405_0707_amd._lib import ExpmvError
+from paper_1405_0707_amd import HostAmg, Plan
 
 from amg_reference import VCycle
 
@@ -119,9 +118,59 @@ def test_amg_vardiff_matches_direct_rational():
     assert info.amg_levels >= 2
 
 
-def test_amg_rejected_for_nonsymmetric():
-    announce("AMG nonsymmetric -> EINVAL")
-    A = wl.convdiff_3d(8, 50.0)
-    with pytest.raises(ExpmvError) as e:
-        Plan.csr(A.rowptr, A.colind, A.val, 1e-3, device=DEV, inner_precond="amg")
-    assert e.value.status == _lib.EINVAL
+# ---------------------------------------------------------------------------
+# nonsymmetric operator: AMG-preconditioned BiCGStab, hierarchies of K and K^T
+
+def _convdiff(N):
+    """Upwind convection-diffusion on N^3 with t lambda_min = 3.33, as on 128^3."""
+    import scipy.sparse.linalg as spla
+    A = wl.convdiff_3d(N, 50.0)
+    lam = spla.eigs((-A.to_scipy()).tocsc(), k=1, sigma=0, return_eigenvectors=False)
+    return A, 3.33 / float(lam.real.min())
+
+
+@pytest.mark.parametrize("p,transpose", [(4, False), (4, True), (16, False)])
+def test_device_vcycle_nonsymmetric_matches_numpy(p, transpose):
+    announce(f"V-cycle convdiff 20^3 p={p} transpose={transpose}")
+    A, t = _convdiff(20)
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg")
+    X = np.random.default_rng(p).standard_normal((A.n, p))
+    Y = pl.apply_preconditioner(torch.from_numpy(X), transpose=transpose).cpu().numpy()
+    K = (A.to_scipy() * (-t)).tocsr()
+    if transpose:
+        K = K.T.tocsr()
+        K.sort_indices()
+    V = VCycle(HostAmg(K.indptr, K.indices, K.data, symmetric=False).levels(), 1)
+    assert rel(Y, V.apply(X)) < 1e-12
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_amg_bicgstab_inverse_matches_splu(transpose):
+    announce(f"AMG BiCGStab inverse convdiff 24^3 transpose={transpose}")
+    A, t = _convdiff(24)
+    X = np.random.default_rng(8).standard_normal((A.n, 4))
+    M = (t * A.to_scipy()).tocsr()
+    ref = inverses.splu_inverse(M.T.tocsr() if transpose else M)(X)
+    amg = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
+                   inner_tol=1e-13)
+    jac = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="jacobi",
+                   inner_tol=1e-13)
+    Ya, ita = amg.apply_inverse(torch.from_numpy(X), transpose=transpose)
+    Yj, itj = jac.apply_inverse(torch.from_numpy(X), transpose=transpose)
+    assert rel(Ya.cpu().numpy(), ref) < 1e-10
+    assert rel(Yj.cpu().numpy(), ref) < 1e-10
+    assert 0 < ita <= 40 and itj > 2 * ita, (ita, itj)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_amg_convdiff_solve_matches_direct_rational(precision, bar):
+    announce(f"execute convdiff 16^3 AMG {precision}")
+    A, t = _convdiff(16)
+    B = np.random.default_rng(6).standard_normal((A.n, 4))
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, m=10, k=12, inner_precond="amg",
+                  precision=precision)
+    Z, info = pl.execute(torch.from_numpy(B), tol=1e-11 if precision == "fp64" else 1e-6)
+    from oracle import exact
+    ref = exact.rational_sparse((t * A.to_scipy()).tocsc(), B)
+    assert rel(Z.cpu().numpy(), ref) < bar
+    assert info.amg_levels >= 2

@@ -319,14 +319,17 @@ def test_toeplitz_full_size_properties():
     assert abs(lhs - rhs) <= 1e-9 * abs(lhs)
 
 
-@pytest.mark.parametrize("precision,bar", [("fp64", 1e-11), ("mixed", 1e-5)])
-def test_bicgstab_wide_block_full_grid(precision, bar):
+@pytest.mark.parametrize("precision,bar,inner", [("fp64", 1e-11, "jacobi"),
+                                                 ("mixed", 1e-5, "jacobi"),
+                                                 ("fp64", 1e-11, "amg"),
+                                                 ("mixed", 1e-5, "amg")])
+def test_bicgstab_wide_block_full_grid(precision, bar, inner):
     """p = 16 on 32^3 launches the inner solver's full 512-workgroup grid;
     regression test for the scalars of one iteration being overwritten while
     other workgroups of the same kernel still read them."""
-    announce(f"BiCGStab 32^3 p=16 {precision}")
+    announce(f"BiCGStab 32^3 p=16 {precision} {inner}")
     W = wl.c4(N=32, p=16, precision="fp64")
-    pl = plan_for(W, precision=precision, inner_maxit=2000)
+    pl = plan_for(W, precision=precision, inner_maxit=2000, inner_precond=inner)
     Y, iters = pl.apply_inverse(torch.from_numpy(W.B))
     M = (W.t * W.A.to_scipy()).tocsr()
     res = np.linalg.norm(M @ Y.cpu().numpy() - W.B) / np.linalg.norm(W.B)
