@@ -226,24 +226,35 @@ bool hess_eigenvalues(int n, const std::vector<double>& Hr, std::vector<cd>& ev)
   return true;
 }
 
-// Solve (A - mu I) x = b for dense complex A by LU with partial pivoting.
-void complex_solve(int n, std::vector<cd> M, std::vector<cd>& x) {
+// LU factorisation with partial pivoting of a dense complex matrix, in
+// place: M = P^T L U, L unit lower (below the diagonal), U upper; piv[c] is
+// the row swapped into position c.
+void complex_lu(int n, std::vector<cd>& M, std::vector<int>& piv) {
   auto at = [&](int i, int j) -> cd& { return M[size_t(i) * n + j]; };
+  piv.resize(n);
   for (int c = 0; c < n; ++c) {
     int pv = c;
     for (int r = c + 1; r < n; ++r)
       if (std::abs(at(r, c)) > std::abs(at(pv, c))) pv = r;
-    if (pv != c) {
+    piv[c] = pv;
+    if (pv != c)
       for (int j = 0; j < n; ++j) std::swap(at(c, j), at(pv, j));
-      std::swap(x[c], x[pv]);
-    }
     if (at(c, c) == cd(0.0)) at(c, c) = cd(1e-300);
     for (int r = c + 1; r < n; ++r) {
       const cd l = at(r, c) / at(c, c);
+      at(r, c) = l;
       if (l == cd(0.0)) continue;
       for (int j = c + 1; j < n; ++j) at(r, j) -= l * at(c, j);
-      x[r] -= l * x[c];
     }
+  }
+}
+
+void complex_lu_solve(int n, const std::vector<cd>& M, const std::vector<int>& piv,
+                      std::vector<cd>& x) {
+  auto at = [&](int i, int j) { return M[size_t(i) * n + j]; };
+  for (int c = 0; c < n; ++c) {
+    if (piv[c] != c) std::swap(x[c], x[piv[c]]);
+    for (int r = c + 1; r < n; ++r) x[r] -= at(r, c) * x[c];
   }
   for (int c = n - 1; c >= 0; --c) {
     cd s = x[c];
@@ -253,9 +264,8 @@ void complex_solve(int n, std::vector<cd> M, std::vector<cd>& x) {
 }
 }  // namespace
 
-bool general_eig(int n, const double* Ain, double* wr, double* wi, double* Vr, double* Vi) {
-  std::vector<double> A(Ain, Ain + size_t(n) * n);
-  std::vector<double> Hh = A;
+bool general_eigvals(int n, const double* Ain, double* wr, double* wi) {
+  std::vector<double> Hh(Ain, Ain + size_t(n) * n);
   hessenberg(n, Hh);
   std::vector<cd> ev;
   if (!hess_eigenvalues(n, Hh, ev)) return false;
@@ -292,17 +302,35 @@ bool general_eig(int n, const double* Ain, double* wr, double* wi, double* Vr, d
       used[best] = 1;
     }
   }
-  // eigenvectors by inverse iteration on the original matrix
-  std::vector<cd> M(size_t(n) * n);
   for (int i = 0; i < n; ++i) {
-    const cd lam = ev2[i];
+    wr[i] = ev2[i].real();
+    wi[i] = ev2[i].imag();
+  }
+  return true;
+}
+
+void general_eigvecs(int n, const double* A, const double* wr, const double* wi,
+                     const char* want, double* Vr, double* Vi) {
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, std::hypot(wr[i], wi[i]));
+  // eigenvectors by inverse iteration on the original matrix: one LU of
+  // A - (lambda + pert) I, two solves
+  std::vector<cd> M(size_t(n) * n);
+  std::vector<int> piv;
+  for (int i = 0; i < n; ++i) {
+    if (want && !want[i]) {
+      for (int r = 0; r < n; ++r) Vr[size_t(r) * n + i] = Vi[size_t(r) * n + i] = 0.0;
+      continue;
+    }
+    const cd lam(wr[i], wi[i]);
     const double pert = 1e-13 * (scale == 0.0 ? 1.0 : scale);
     for (int r = 0; r < n; ++r)
       for (int c = 0; c < n; ++c) M[size_t(r) * n + c] = A[size_t(r) * n + c] - ((r == c) ? lam + pert : 0.0);
+    complex_lu(n, M, piv);
     std::vector<cd> x(n);
     for (int r = 0; r < n; ++r) x[r] = cd(1.0 / std::sqrt(double(n)), 0.37 / (r + 1.0));
     for (int it = 0; it < 2; ++it) {
-      complex_solve(n, M, x);
+      complex_lu_solve(n, M, piv, x);
       double nr = 0.0;
       for (auto& e : x) nr += std::norm(e);
       nr = std::sqrt(nr);
@@ -318,9 +346,12 @@ bool general_eig(int n, const double* Ain, double* wr, double* wi, double* Vr, d
       Vr[size_t(r) * n + i] = e.real();
       Vi[size_t(r) * n + i] = e.imag();
     }
-    wr[i] = lam.real();
-    wi[i] = lam.imag();
   }
+}
+
+bool general_eig(int n, const double* A, double* wr, double* wi, double* Vr, double* Vi) {
+  if (!general_eigvals(n, A, wr, wi)) return false;
+  general_eigvecs(n, A, wr, wi, nullptr, Vr, Vi);
   return true;
 }
 

@@ -12,4 +12,11 @@ void sym_eig(int n, const double* A, double* w, double* Q);
 // conjugate pairs.  Returns false if the QR iteration did not converge.
 bool general_eig(int n, const double* A, double* wr, double* wi, double* Vr, double* Vi);
 
+// The two halves of general_eig: eigenvalues (exact conjugate pairs), then
+// eigenvectors only for the indices with want[i] != 0 (want NULL: all; the
+// other columns are zero).
+bool general_eigvals(int n, const double* A, double* wr, double* wi);
+void general_eigvecs(int n, const double* A, const double* wr, const double* wi,
+                     const char* want, double* Vr, double* Vi);
+
 }  // namespace expmv

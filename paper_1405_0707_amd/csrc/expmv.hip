@@ -24,6 +24,7 @@
 #include "expmv.h"
 #include "kernels.hpp"
 #include "kernels_dense.hpp"
+#include "orth_mfma.hpp"
 #include "toeplitz.hpp"
 
 #include "cf_nu14.inc"
@@ -193,6 +194,7 @@ namespace expmv {
 namespace {
 
 constexpr int kCgGrid = 512;   // workgroups of the inner-solver kernels
+constexpr int kOrthGrid = 512; // most workgroups (partial sums) of an orthogonalisation pass
 
 int grid_for(int64_t rows, int PP, int cap = 1024) {
   const int64_t wgs = (rows * PP + kThreads - 1) / kThreads;
@@ -247,7 +249,7 @@ void ensure_workspace(expmv_plan_s* pl, int p) {
   }
   w.X.alloc(blk * 2 * kNShift);
   const size_t O = size_t(npan_max) * p * p + p;
-  w.partial.alloc(std::max<size_t>(O * 256, size_t(512) * kNShift));
+  w.partial.alloc(std::max<size_t>(O * kOrthGrid, size_t(512) * kNShift));
   w.hcoef.alloc(O);
   w.gram.alloc(size_t(p) * p);
   w.R1.alloc(size_t(p) * p);
@@ -795,6 +797,28 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
   const bool use_v = (mode == kProj || mode == kUpdProj || mode == kUpdGram);
   const int npv = use_v ? npan : 0;
   const int O = proj ? npv * p * p + (mode == kProj ? p : 0) : (gram ? p * p : 0);
+  // matrix-core path: up to 24 column blocks of 16 (4 waves x MBW)
+  const int nmb = (npv * p + 15) / 16;
+  if (p <= 32 && nmb <= 24) {
+    const int64_t steps = (pl->n + 63) / 64;
+    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(kOrthGrid, steps)));
+    const int NB = (p + 15) / 16;
+    const int MBW = nmb <= 8 ? 2 : (nmb <= 16 ? 4 : 6);
+#define ORTH_MMA(NB_, MBW_)                                                                     \
+  hipLaunchKernelGGL((k_orth_mma<T, NB_, MBW_>), dim3(grid), dim3(kThreads), 0, pl->stream, mode, \
+                     pl->n, p, V, npv, Win, Wout, C, pl->ws.partial.p)
+    if (NB == 1) {
+      if (MBW == 2) ORTH_MMA(1, 2);
+      else if (MBW == 4) ORTH_MMA(1, 4);
+      else ORTH_MMA(1, 6);
+    } else {
+      if (MBW == 2) ORTH_MMA(2, 2);
+      else if (MBW == 4) ORTH_MMA(2, 4);
+      else ORTH_MMA(2, 6);
+    }
+#undef ORTH_MMA
+    return (proj || gram) ? grid : 0;
+  }
   OrthLaunch L = orth_config(pl->n, p, npv, O, sizeof(T));
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth<T>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)));
@@ -855,6 +879,24 @@ template <typename T, typename TO>
 void panel_gemm(expmv_plan_s* pl, int p, const T* V, int npan, const double* C, int ldc,
                 int nchunks, TO* out, int64_t chunk_stride, int64_t ldo, int accumulate) {
   const int np_cols = npan * p;
+  // matrix-core path: output columns in 16-wide blocks spread over 4 waves
+  const int nout = nchunks * p;
+  const int nnb = (nout + 15) / 16;
+  if (nnb <= 32) {
+    const int NBW = (nnb + 3) / 4;
+    const int RB = NBW <= 2 ? 4 : (NBW <= 4 ? 2 : 1);
+    const int64_t steps = (pl->n + 16 * RB - 1) / (16 * RB);
+    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(2048, steps)));
+#define PG_MMA(NBW_, RB_)                                                                         \
+  hipLaunchKernelGGL((k_panel_gemm_mma<T, TO, NBW_, RB_>), dim3(grid), dim3(kThreads), 0,          \
+                     pl->stream, pl->n, p, V, npan, C, ldc, nout, out, chunk_stride, ldo, accumulate)
+    if (NBW <= 1) PG_MMA(1, 4);
+    else if (NBW <= 2) PG_MMA(2, 4);
+    else if (NBW <= 4) PG_MMA(4, 2);
+    else PG_MMA(8, 1);
+#undef PG_MMA
+    return;
+  }
   int TR = 32;
   auto lds_for = [&](int tr) {
     return size_t(np_cols) * p * 8 + size_t(tr) * np_cols * sizeof(T);
@@ -934,11 +976,31 @@ RitzBasis ritz_basis(bool symmetric, bool precond, int dl, const std::vector<dou
     return rb;
   }
   std::vector<double> wr(dl), wi(dl), Vr(size_t(dl) * dl), Vi(size_t(dl) * dl);
-  if (!general_eig(dl, Hd.data(), wr.data(), wi.data(), Vr.data(), Vi.data()))
-    throw StatusError{EXPMV_EBREAKDOWN};
+  if (!general_eigvals(dl, Hd.data(), wr.data(), wi.data())) throw StatusError{EXPMV_EBREAKDOWN};
   auto mag = [&](int a) { return std::hypot(wr[a], wi[a]); };
   if (precond) std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return mag(a) > mag(b); });
   else std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return mag(a) < mag(b); });
+  {
+    // eigenvectors only of the Ritz values kept (one per conjugate pair)
+    std::vector<char> want(dl, 0), seen(dl, 0);
+    int chosen = 0;
+    for (int idx : ord) {
+      if (chosen >= k) break;
+      if (seen[idx]) continue;
+      seen[idx] = 1;
+      want[idx] = 1;
+      ++chosen;
+      if (wi[idx] != 0.0) {
+        for (int j = 0; j < dl; ++j)
+          if (!seen[j] && wr[j] == wr[idx] && wi[j] == -wi[idx]) {
+            seen[j] = 1;
+            break;
+          }
+        ++chosen;
+      }
+    }
+    general_eigvecs(dl, Hd.data(), wr.data(), wi.data(), want.data(), Vr.data(), Vi.data());
+  }
   std::vector<char> taken(dl, 0);
   std::vector<std::vector<double>> cols;
   int chosen = 0;

@@ -1,0 +1,305 @@
+// Block Gram-Schmidt and CholQR passes on matrix cores (MFMA 16x16x4, FP64
+// or FP32): the same five modes as k_orth (kernels_dense.hpp), as tall-skinny
+// contractions over the n rows.
+//
+// One workgroup = 4 wavefronts handles 64 rows per step; wave w owns the
+// 16-row block w of the step:
+//   1. the block's updated rows W' (in the MFMA result layout):
+//        kProj                 W' = W
+//        kUpdProj / kUpdGram   W' = W - V C     (C: (npan p) x p, K = npan p)
+//        kScaleGram / kScale   W' = W C         (C: p x p, K = p)
+//      written to Wout (all modes but kProj) and to LDS;
+//   2. after a barrier the contractions over the step's 64 rows, the B
+//      operands read from LDS:
+//        projection V^T W' (kProj, kUpdProj): wave w owns the 16-column
+//        blocks mb = w, w + 4, ...; the A operand is read from V;
+//        Gram W'^T W' (kUpdGram, kScaleGram): wave w owns block pair w.
+// Every K-step of 4 rows is exact in the MFMA's own precision; each 16-row
+// block's sums are added to FP64 accumulators, so an FP32 basis accumulates
+// in FP32 only within 16 rows.  Partial sums per workgroup, layout as k_orth.
+// W and Wout may be the same array (each row is read by the wave that
+// rewrites it, before it does).
+//
+// Lane layout of the 16x16x4 builtins (checked on gfx950): lane l supplies
+// A(l % 16, l / 16) and B(l / 16, l % 16); D(i, j) comes back in lane
+// j + 16 (i / 4) (FP32) or j + 16 (i % 4) (FP64), register i % 4 (FP32) or
+// i / 4 (FP64).  So lane l's register s holds row drow(l, s) of the result,
+// and register s of all lanes is exactly the B operand of the K-step whose
+// 4 rows are {drow(16 k, s)}.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels_dense.hpp"
+
+namespace expmv {
+
+template <typename T>
+struct Mma;
+
+template <>
+struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int drow(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+template <>
+struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int drow(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+// element (row, col) of the basis: column col = panel * p + a
+template <typename T>
+__device__ inline T basis_at(const T* __restrict__ V, int64_t n, int p, int64_t row, int col) {
+  const int pan = col / p;
+  return V[int64_t(pan) * n * p + row * p + (col - pan * p)];
+}
+
+// NB = 16-column blocks of W (p <= 16 NB); MBW = projection column blocks
+// per wave (npan p <= 64 MBW).
+template <typename T, int NB, int MBW>
+__global__ void __launch_bounds__(kThreads)
+k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const T* W, T* Wout,
+           const double* __restrict__ C, double* __restrict__ partial) {
+  using M = Mma<T>;
+  using v4 = typename M::v4;
+  __shared__ T sW[64 * 16 * NB];        // W' of the step, row-major, ld 16 NB
+  __shared__ double sN[4][16 * NB];     // per-wave column norms (kProj)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ldw = 16 * NB;
+  const int np_cols = npan * p;
+  const int nmb = (np_cols + 15) / 16;
+  const bool upd = (mode == kUpdProj || mode == kUpdGram);
+  const bool scl = (mode == kScaleGram || mode == kScale);
+  const bool proj = (mode == kProj || mode == kUpdProj);
+  const bool gram = (mode == kUpdGram || mode == kScaleGram);
+
+  double acc[MBW][NB][4];
+#pragma unroll
+  for (int a = 0; a < MBW; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0.0;
+  double nrm[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) nrm[b] = 0.0;
+  // Gram block pair of this wave (pairs (b1, b2) with b1, b2 < NB)
+  const int g1 = wave / NB, g2 = wave % NB;
+  const bool gram_owner = gram && wave < NB * NB;
+
+  const int64_t steps = (n + 63) / 64;
+  for (int64_t st = blockIdx.x; st < steps; st += gridDim.x) {
+    const int64_t r0 = st * 64 + 16 * wave;   // this wave's 16-row block
+    // ---- 1. updated rows of the wave's block
+    v4 d[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) d[b] = v4{0, 0, 0, 0};
+    if (upd || scl) {
+      const int K = upd ? np_cols : p;
+      const int64_t row = r0 + li;   // A operand row of this lane
+      // four K-steps per iteration, every load issued before the products
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        T a[4], bv[4][NB];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kc = k0 + 4 * u + lk;
+          a[u] = T(0);
+          if (kc < K && row < n) a[u] = upd ? basis_at(V, n, p, row, kc) : W[row * p + kc];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const int j = 16 * b + li;
+            bv[u][b] = (kc < K && j < p) ? T(C[int64_t(kc) * p + j]) : T(0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) d[b] = M::mma(a[u], bv[u][b], d[b]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = 16 * b + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = M::drow(lane, r);
+        const int64_t row = r0 + i;
+        T w = T(0);
+        if (row < n && j < p) {
+          if (upd) w = T(double(W[row * p + j]) - double(d[b][r]));
+          else if (scl) w = d[b][r];
+          else w = W[row * p + j];
+          if (mode != kProj) Wout[row * p + j] = w;
+        }
+        sW[(16 * wave + i) * ldw + j] = w;
+        if (mode == kProj) nrm[b] += double(w) * double(w);
+      }
+    }
+    __syncthreads();
+    // ---- 2. contractions over the step's 64 rows
+    if (proj) {
+      for (int u = 0; u < MBW; ++u) {
+        const int mb = wave + 4 * u;
+        if (mb >= nmb) break;
+        const int col = 16 * mb + li;
+        v4 t[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) t[b] = v4{0, 0, 0, 0};
+        // the 16 K-steps of the step's 64 rows: all 16 loads first
+        T a[16];
+#pragma unroll
+        for (int qs = 0; qs < 16; ++qs) {
+          const int64_t row = st * 64 + 16 * (qs >> 2) + M::drow(lane, qs & 3);
+          a[qs] = (col < np_cols && row < n) ? basis_at(V, n, p, row, col) : T(0);
+        }
+#pragma unroll
+        for (int qs = 0; qs < 16; ++qs) {
+          const int i = 16 * (qs >> 2) + M::drow(lane, qs & 3);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) t[b] = M::mma(a[qs], sW[i * ldw + 16 * b + li], t[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[u][b][r] += double(t[b][r]);
+      }
+    }
+    if (gram_owner) {
+      v4 t = v4{0, 0, 0, 0};
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int i = M::drow(lane, s);
+          const T* rw = sW + (16 * q + i) * ldw;
+          t = M::mma(rw[16 * g1 + li], rw[16 * g2 + li], t);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[0][0][r] += double(t[r]);
+    }
+    __syncthreads();
+  }
+
+  // ---- partial sums of this workgroup
+  const int O = proj ? np_cols * p + (mode == kProj ? p : 0) : (gram ? p * p : 0);
+  double* out = partial + size_t(blockIdx.x) * O;
+  if (proj) {
+#pragma unroll
+    for (int u = 0; u < MBW; ++u) {
+      const int mb = wave + 4 * u;
+      if (mb >= nmb) break;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = 16 * mb + M::drow(lane, r), j = 16 * b + li;
+          if (col < np_cols && j < p) out[col * p + j] = acc[u][b][r];
+        }
+    }
+  }
+  if (mode == kProj) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      double v = nrm[b];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      if (lk == 0) sN[wave][16 * b + li] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < p)
+      out[np_cols * p + threadIdx.x] = ((sN[0][threadIdx.x] + sN[1][threadIdx.x]) +
+                                        sN[2][threadIdx.x]) + sN[3][threadIdx.x];
+  }
+  if (gram_owner) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 16 * g1 + M::drow(lane, r), j = 16 * g2 + li;
+      if (a < p && j < p) out[a * p + j] = acc[0][0][r];
+    }
+  }
+}
+
+// out (+)= V C on matrix cores in FP64 (an FP32 basis is widened on load):
+// V = npan basis panels (n x p each, columns k < npan p), C FP64
+// (npan p) x nout with leading dimension ldc; output column oc = q p + b goes
+// to out[q chunk_stride + row ldo + b].  The X update (out = X, chunk_stride
+// = p, ldo = 14 p) and the restart rotation (out = new panels, chunk_stride =
+// n p, ldo = p).  A workgroup handles 16 RB rows per step; wave w computes
+// the 16-column output blocks w, w + 4, ... (NBW of them) for all RB row
+// blocks, so V is read from memory once and C once per step.
+template <typename T, typename TO, int NBW, int RB>
+__global__ void __launch_bounds__(kThreads)
+k_panel_gemm_mma(int64_t n, int p, const T* __restrict__ V, int npan, const double* __restrict__ C,
+                 int ldc, int nout, TO* __restrict__ out, int64_t chunk_stride, int64_t ldo,
+                 int accumulate) {
+  using M = Mma<double>;
+  using v4 = M::v4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int np_cols = npan * p;
+  const int nnb = (nout + 15) / 16;
+  const int64_t steps = (n + 16 * RB - 1) / (16 * RB);
+  for (int64_t st = blockIdx.x; st < steps; st += gridDim.x) {
+    const int64_t r0 = st * 16 * RB;
+    v4 acc[RB][NBW];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int u = 0; u < NBW; ++u) acc[rb][u] = v4{0, 0, 0, 0};
+    // two K-steps per iteration, every load issued before the products
+    for (int k0 = 0; k0 < np_cols; k0 += 8) {
+      double a[2][RB], bv[2][NBW];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int kc = k0 + 4 * h + lk;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int64_t row = r0 + 16 * rb + li;
+          a[h][rb] = (kc < np_cols && row < n) ? double(basis_at(V, n, p, row, kc)) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NBW; ++u) {
+          const int oc = 16 * (wave + 4 * u) + li;
+          bv[h][u] = (kc < np_cols && oc < nout) ? C[int64_t(kc) * ldc + oc] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int u = 0; u < NBW; ++u) {
+          if (wave + 4 * u >= nnb) break;
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) acc[rb][u] = M::mma(a[h][rb], bv[h][u], acc[rb][u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NBW; ++u) {
+      const int nb = wave + 4 * u;
+      if (nb >= nnb) break;
+      const int oc = 16 * nb + li;
+      if (oc >= nout) continue;
+      const int q = oc / p, b = oc - q * p;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = r0 + 16 * rb + M::drow(lane, r);
+          if (row >= n) continue;
+          TO* dst = out + q * chunk_stride + row * ldo + b;
+          *dst = accumulate ? TO(double(*dst) + acc[rb][u][r]) : TO(acc[rb][u][r]);
+        }
+    }
+  }
+}
+
+}  // namespace expmv
