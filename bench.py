@@ -292,6 +292,15 @@ def main():
                    for key in mean}
         dom = max(per_iter, key=lambda key: per_iter[key])
         ach = byt[dom] / (mean[dom] * 1e-3) / 1e9
+        ol = sum(i.kern_orth_launches for i in infos)
+        if ol:
+            oms = sum(i.kern_ms_orth * i.kern_orth_launches for i in infos) / ol
+            oby = sum(i.kern_orth_bytes * i.kern_orth_launches for i in infos) / ol
+            kernels["orth"] = {
+                "kernel": "k_orth_mma (block Gram-Schmidt / CholQR passes, FP64 MFMA)",
+                "mean_launch_ms": round(oms, 5), "bytes_per_launch": int(oby),
+                "achieved_GBs": round(oby / (oms * 1e-3) / 1e9, 1),
+                "launches": ol}
         roof = {"bound": "hbm", "kernel": names[dom], "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(dom), "bytes_per_launch": int(byt[dom]),

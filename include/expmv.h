@@ -119,6 +119,10 @@ typedef struct {                  /* host struct, filled by expmv_execute */
   int kern_smooth_launches;       /* sampled launches of the finest AMG level's
                                      smoothing-step kernel (pre, residual, post)      */
   double kern_ms_smooth;          /* their mean device time, ms                       */
+  int kern_orth_launches;         /* timed block Gram-Schmidt / CholQR passes (matrix-
+                                     core kernel; profile > 0)                        */
+  double kern_ms_orth;            /* their mean device time, ms                       */
+  double kern_orth_bytes;         /* their mean algorithmic HBM bytes per launch      */
 } expmv_info;
 
 typedef struct expmv_plan_s* expmv_plan;
@@ -157,6 +161,21 @@ expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t,
  * after ENOCONV, EBREAKDOWN and EINNER Z holds the last iterate. */
 expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int64_t p,
                            double tol, double* Z, expmv_info* info);
+
+/* Several times at once: Z_q = e^{t_q A} B for q = 0..nt-1 (times: host
+ * array, 1 <= nt <= 32; Z: device, nt consecutive n x p blocks, block q at
+ * Z + q n p).  A is the plan's matrix (the plan holds t_0 A for its own t_0);
+ * every t_q must have the sign of t_0 so that t_q A is negative definite
+ * (ENOTNEG otherwise).  Since t_q A = s_q (t_0 A) with s_q = t_q / t_0 and
+ * r(s M) B = omega_0 B + Re sum_j (c_j / s)(M - (tau_j / s) I)^{-1} B, all 7 nt
+ * shifted systems are solved on one Krylov basis of (t_0 A)^{-1}: the inner
+ * solves, Gram-Schmidt passes and restarts are shared, and the stopping rule
+ * must hold for every time.  info as expmv_execute (err_bound: the largest
+ * over the times; true_res[j]: the largest over the times; znorm, est: time
+ * 0).  Statuses as expmv_execute. */
+expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* times, int nt,
+                                 const double* B, int64_t p, double tol, double* Z,
+                                 expmv_info* info);
 
 /* *out (host) = <G, A Z> = sum_ij G_ij (A Z)_ij: the derivative of
  * <G, e^{tA}B> with respect to t when Z = e^{tA}B (d/dt e^{tA}B = A e^{tA}B).
@@ -238,6 +257,11 @@ void expmv_host_amg_destroy(expmv_amg h);
 void expmv_plan_destroy(expmv_plan plan);
 
 const char* expmv_status_string(expmv_status s);
+
+/* Detail of the last EHIP / ENOMEM returned on this host thread (the failing
+ * runtime call's source line and message), "" if none.  Host string owned by
+ * the library. */
+const char* expmv_last_error_detail(void);
 
 /* One-shot forms of the problem statement: plan, execute, destroy, with the
  * default options and a given tol. */

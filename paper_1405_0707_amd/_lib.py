@@ -30,7 +30,9 @@ class Info(C.Structure):
                 ("ms_update", C.c_double), ("breakdown", C.c_int), ("kern_samples", C.c_int),
                 ("kern_ms_a", C.c_double), ("kern_ms_b", C.c_double),
                 ("kern_ms_c", C.c_double), ("amg_levels", C.c_int),
-                ("kern_smooth_launches", C.c_int), ("kern_ms_smooth", C.c_double)]
+                ("kern_smooth_launches", C.c_int), ("kern_ms_smooth", C.c_double),
+                ("kern_orth_launches", C.c_int), ("kern_ms_orth", C.c_double),
+                ("kern_orth_bytes", C.c_double)]
 
     def as_dict(self):
         d = {}
@@ -47,6 +49,7 @@ EXPORTS = [
     "expmv_status_string", "expmv_block_csr", "expmv_block_toeplitz",
     "expmv_apply_preconditioner", "expmv_host_amg_build", "expmv_host_amg_levels",
     "expmv_host_amg_level", "expmv_host_amg_coarse_inverse", "expmv_host_amg_destroy",
+    "expmv_execute_times", "expmv_last_error_detail",
 ]
 
 _lib = None
@@ -77,9 +80,12 @@ def lib():
     L.expmv_plan_destroy.restype = None
     L.expmv_status_string.argtypes = [i32]
     L.expmv_status_string.restype = C.c_char_p
+    L.expmv_last_error_detail.argtypes = []
+    L.expmv_last_error_detail.restype = C.c_char_p
     L.expmv_block_csr.argtypes = [i64, i64, vp, vp, vp, vp, i64, dbl, dbl, vp, vp]
     L.expmv_block_toeplitz.argtypes = [i64, vp, vp, i64, dbl, dbl, vp, vp]
     L.expmv_apply_preconditioner.argtypes = [vp, i32, vp, i64, vp]
+    L.expmv_execute_times.argtypes = [vp, i32, vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
     L.expmv_host_amg_build.argtypes = [i64, vp, vp, vp, i32, dbl, i32, C.POINTER(vp)]
     L.expmv_host_amg_levels.argtypes = [vp]
     L.expmv_host_amg_level.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -87,7 +93,8 @@ def lib():
     L.expmv_host_amg_destroy.argtypes = [vp]
     L.expmv_host_amg_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("expmv_plan_destroy", "expmv_status_string", "expmv_host_amg_destroy"):
+        if name not in ("expmv_plan_destroy", "expmv_status_string", "expmv_host_amg_destroy",
+                        "expmv_last_error_detail"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -96,7 +103,8 @@ def lib():
 class ExpmvError(RuntimeError):
     def __init__(self, status: int, where: str):
         msg = lib().expmv_status_string(status).decode()
-        super().__init__(f"{where}: {msg} (status {status})")
+        detail = lib().expmv_last_error_detail().decode()
+        super().__init__(f"{where}: {msg} (status {status})" + (f" [{detail}]" if detail else ""))
         self.status = status
 
 

@@ -108,6 +108,21 @@ class Plan:
         check(st, "expmv_execute", allow)
         return Z, info
 
+    def execute_times(self, times, B: torch.Tensor, tol: float = 1e-10, transpose: bool = False,
+                      allow=()):
+        """Z[q] = e^{t_q A} B for every t_q in `times` on one shared Krylov
+        basis (A = the plan's matrix); returns (Z of shape (nt, n, p), info)."""
+        B = _dev_f64(B, self.device)
+        if B.dim() == 1:
+            B = B[:, None]
+        ts = (C.c_double * len(times))(*[float(x) for x in times])
+        Z = torch.empty((len(times),) + tuple(B.shape), dtype=torch.float64, device=self.device)
+        info = Info()
+        st = lib().expmv_execute_times(self._h, int(transpose), ts, len(times), B.data_ptr(),
+                                       B.shape[1], float(tol), Z.data_ptr(), C.byref(info))
+        check(st, "expmv_execute_times", allow)
+        return Z, info
+
     def grad_t(self, G: torch.Tensor, Z: torch.Tensor) -> float:
         G = _dev_f64(G, self.device)
         Z = _dev_f64(Z, self.device)

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -99,6 +100,7 @@ struct Workspace {
   DevBuf<CgState> cgst;
   DevBuf<BcgState> bcgst;
   DevBuf<double> part_rr, part_sig;   // inner-solver partials
+  DevBuf<double> taus, coefs;         // poles and coefficients of all shifts (re | im)
   DevBuf<KrylovCtl> ctl;
 };
 
@@ -185,6 +187,11 @@ struct expmv_plan_s {
   double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0, prof_ms_sm = 0.0;
   int prof_samples = 0, prof_sm_launches = 0;
   int last_inner_iters = 0;       // iterations of the previous inner solve
+  // (profile > 0) start/stop events of the orthogonalisation passes of one
+  // execute and their algorithmic bytes
+  std::vector<hipEvent_t> oev;
+  std::vector<double> oev_bytes;
+  int oev_used = 0;
   // AMG preconditioner of the CSR inner solver: hierarchy of K and, for a
   // nonsymmetric K, of K^T (transposed solves)
   std::unique_ptr<AmgDev> amg, amgT;
@@ -195,6 +202,7 @@ namespace {
 
 constexpr int kCgGrid = 512;   // workgroups of the inner-solver kernels
 constexpr int kOrthGrid = 512; // most workgroups (partial sums) of an orthogonalisation pass
+constexpr int kMaxTimes = 32;  // times of one expmv_execute_times call
 
 int grid_for(int64_t rows, int PP, int cap = 1024) {
   const int64_t wgs = (rows * PP + kThreads - 1) / kThreads;
@@ -804,9 +812,18 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
     const int grid = int(std::max<int64_t>(1, std::min<int64_t>(kOrthGrid, steps)));
     const int NB = (p + 15) / 16;
     const int MBW = nmb <= 8 ? 2 : (nmb <= 16 ? 4 : 6);
+    const bool upd = (mode == kUpdProj || mode == kUpdGram);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pl->opts.profile > 0 && pl->oev_used + 2 <= int(pl->oev.size())) {
+      e0 = pl->oev[pl->oev_used];
+      e1 = pl->oev[pl->oev_used + 1];
+      pl->oev_used += 2;
+      const double el = double(sizeof(T)) * double(pl->n) * p;
+      pl->oev_bytes.push_back(el * (mode == kProj ? npv + 1 : (upd ? npv + 2 : 2)));
+    }
 #define ORTH_MMA(NB_, MBW_)                                                                     \
-  hipLaunchKernelGGL((k_orth_mma<T, NB_, MBW_>), dim3(grid), dim3(kThreads), 0, pl->stream, mode, \
-                     pl->n, p, V, npv, Win, Wout, C, pl->ws.partial.p)
+  hipExtLaunchKernelGGL((k_orth_mma<T, NB_, MBW_>), dim3(grid), dim3(kThreads), 0, pl->stream,     \
+                        e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C, pl->ws.partial.p)
     if (NB == 1) {
       if (MBW == 2) ORTH_MMA(1, 2);
       else if (MBW == 4) ORTH_MMA(1, 4);
@@ -1083,9 +1100,15 @@ InnerResult apply_inverse_mixed(expmv_plan_s* pl, int transpose, const T* V, T* 
   return total;
 }
 
+// Z_q = r(s_q M) B for the scale factors s_q > 0 of `scales` (M = tA of the
+// plan; Z_q is the q-th n x p block of Z).  Since r(s M) B = omega_0 B +
+// Re sum_j (c_j / s)(M - (tau_j / s) I)^{-1} B, every time adds 7 shifted
+// systems with poles tau_j / s_q on the one Krylov basis of M^{-1}: the
+// basis, the inner solves and the restarts are shared, the projected solves
+// and the solution updates run over all 7 nt shifts.
 template <typename T, typename TI>
 expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
-                          double* Z, expmv_info* info) {
+                          double* Z, expmv_info* info, const std::vector<double>& scales) {
   hipStream_t s = pl->stream;
   ensure_workspace(pl, p);
   Workspace& w = pl->ws;
@@ -1096,13 +1119,49 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   const int k = std::max(p, std::min(kk_opt, (m - 2) * p) / p * p);
   const bool precond = pl->opts.preconditioned != 0;
   const size_t blk = size_t(n) * p;
-  const int ldx = 2 * kNShift * p;
+  const int nt = int(scales.size());
+  const int ns = kNShift * nt;   // shifted systems
+  const int ldx = 2 * ns * p;
+  {
+    // shift-dependent buffers (grow only)
+    const int dmax = m * p;
+    w.X.alloc(blk * 2 * ns);
+    w.G.alloc(size_t(ns) * dmax * p);
+    w.Zs.alloc(size_t(ns) * dmax * p);
+    w.Ascr.alloc(size_t(ns) * dmax * dmax);
+    w.S.alloc(size_t(ns) * p * p);
+    w.Cr.alloc(size_t(ldh) * 2 * ns * p);
+    w.rho.alloc(ns);
+    w.singular.alloc(ns);
+    w.taus.alloc(2 * size_t(ns));
+    w.coefs.alloc(2 * size_t(ns));
+    w.partial.alloc(size_t(512) * std::max(nt, kNShift));
+  }
+  // poles tau_j / s_q and coefficients c_j / s_q, shift index q * 7 + j
+  std::vector<double> tau_h(2 * size_t(ns)), coef_h(2 * size_t(ns));
+  for (int q = 0; q < nt; ++q)
+    for (int j = 0; j < kNShift; ++j) {
+      tau_h[q * kNShift + j] = CF_TAU_RE[j] / scales[q];
+      tau_h[ns + q * kNShift + j] = CF_TAU_IM[j] / scales[q];
+      coef_h[q * kNShift + j] = CF_C_RE[j] / scales[q];
+      coef_h[ns + q * kNShift + j] = CF_C_IM[j] / scales[q];
+    }
+  HIPCHK(hipMemcpyAsync(w.taus.p, tau_h.data(), sizeof(double) * tau_h.size(),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.coefs.p, coef_h.data(), sizeof(double) * coef_h.size(),
+                        hipMemcpyHostToDevice, s));
+  const double* tau_re_d = w.taus.p;
+  const double* tau_im_d = w.taus.p + ns;
+  const double* c_re_d = w.coefs.p;
+  const double* c_im_d = w.coefs.p + ns;
   const double t_start = host_now_ms();
   expmv_info inf{};
   double ms_apply = 0, ms_orth = 0, ms_small = 0, ms_update = 0;
   pl->prof_ms_a = pl->prof_ms_b = pl->prof_ms_c = pl->prof_ms_sm = 0.0;
   pl->prof_samples = pl->prof_sm_launches = 0;
   pl->pev_used = 0;
+  pl->oev_used = 0;
+  pl->oev_bytes.clear();
 
   double c_re[kNShift], c_im[kNShift], delta[kNShift];
   for (int j = 0; j < kNShift; ++j) {
@@ -1114,18 +1173,18 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   HIPCHK(hipMemsetAsync(w.X.p, 0, sizeof(double) * size_t(n) * ldx, s));
   HIPCHK(hipMemsetAsync(w.H.p, 0, sizeof(double) * size_t(ldh) * ldh, s));
   HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int) * 4, s));
-  HIPCHK(hipMemsetAsync(w.singular.p, 0, sizeof(int) * kNShift, s));
+  HIPCHK(hipMemsetAsync(w.singular.p, 0, sizeof(int) * ns, s));
 
   const int cgrid = 512;
-  std::vector<double> part(cgrid);
+  std::vector<double> part(size_t(cgrid) * nt);
   // ||B||_F (k_combine with X = 0 and omega0 = 1 writes B to Z and its norm)
-  hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, 1.0, pl->c_re.p,
-                     pl->c_im.p, Z, w.partial.p);
+  hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, ldx, 1.0,
+                     c_re_d, c_im_d, Z, w.partial.p);
   HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   {
     double bb = 0.0;
-    for (double v : part) bb += v;
+    for (int i = 0; i < cgrid; ++i) bb += part[i];
     inf.bnorm = std::sqrt(bb);
   }
   if (!(inf.bnorm > 0.0) || !std::isfinite(inf.bnorm)) {
@@ -1147,7 +1206,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   int first_block = 0;    // first panel to expand in this cycle
   expmv_status status = EXPMV_OK;
   std::vector<double> Hh(size_t(ldh) * ldh);
-  std::vector<double> rho(kNShift);
+  std::vector<double> rho(ns);
   bool rhs_from_S = false;
   int cycle = 0;
   for (;;) {
@@ -1175,37 +1234,51 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     }
     double t0 = host_now_ms();
     {
-      dim3 g(std::max(1, (d * p + kThreads - 1) / kThreads), kNShift);
+      dim3 g(std::max(1, (d * p + kThreads - 1) / kThreads), ns);
       hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, d, p, rhs_from_S ? kp : 0,
                          rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
     }
     // Step 4: projected shifted systems, residual estimates, update coefficients
-    hipLaunchKernelGGL(k_proj_solve, dim3(kNShift), dim3(1024), 0, s, d, p, precond ? 1 : 0, w.H.p,
-                       ldh, pl->tau_re.p, pl->tau_im.p, w.G.p, w.Ascr.p, w.Zs.p, w.Cr.p, w.S.p,
+    hipLaunchKernelGGL(k_proj_solve, dim3(ns), dim3(1024), 0, s, d, p, precond ? 1 : 0, w.H.p,
+                       ldh, tau_re_d, tau_im_d, w.G.p, w.Ascr.p, w.Zs.p, w.Cr.p, ldx, w.S.p,
                        w.rho.p, w.singular.p);
     double t1 = host_now_ms();
     // X_j += V_{d+p} (H~ Z_j)  [Algorithm 1: V_d Z_j]
-    panel_gemm<T, double>(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * kNShift, w.X.p, p, ldx, 1);
-    hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p,
-                       double(CF_OMEGA0), pl->c_re.p, pl->c_im.p, Z, w.partial.p);
-    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * kNShift, hipMemcpyDeviceToHost, s));
+    panel_gemm<T, double>(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * ns, w.X.p, p, ldx, 1);
+    for (int q = 0; q < nt; ++q)
+      hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B,
+                         w.X.p + size_t(2 * kNShift * p) * q, ldx, double(CF_OMEGA0),
+                         c_re_d + kNShift * q, c_im_d + kNShift * q, Z + blk * q,
+                         w.partial.p + size_t(cgrid) * q);
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid * nt,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
     int flags_h[4];
     HIPCHK(hipMemcpyAsync(flags_h, w.flags.p, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double t2 = host_now_ms();
     ms_small += t1 - t0;
     ms_update += t2 - t1;
-    double zz = 0.0;
-    for (int i = 0; i < cgrid; ++i) zz += part[i];
-    inf.znorm = std::sqrt(zz);
-    double bound = 0.0, rmax = 0.0;
-    for (int j = 0; j < kNShift; ++j) {
-      inf.est[j] = rho[j];
-      bound += std::hypot(c_re[j], c_im[j]) * rho[j] / delta[j];
-      rmax = std::max(rmax, rho[j]);
+    // per time: ||Z~_q|| and the bound sum_j |c_j / s| rho / (delta_j / s)
+    bool conv_bound = true;
+    double rmax = 0.0, worst = 0.0;
+    for (int q = 0; q < nt; ++q) {
+      double zz = 0.0;
+      for (int i = 0; i < cgrid; ++i) zz += part[size_t(cgrid) * q + i];
+      const double zn = std::sqrt(zz);
+      double bound = 0.0;
+      for (int j = 0; j < kNShift; ++j) {
+        const double r = rho[q * kNShift + j];
+        bound += std::hypot(c_re[j], c_im[j]) * r / delta[j];
+        rmax = std::max(rmax, r);
+      }
+      if (!(bound <= tol * zn)) conv_bound = false;
+      const double rel_b = zn > 0.0 ? bound / zn : bound;
+      if (q == 0) inf.znorm = zn;
+      worst = std::max(worst, rel_b);
     }
-    inf.err_bound = inf.znorm > 0.0 ? bound / inf.znorm : bound;
+    for (int j = 0; j < kNShift; ++j) inf.est[j] = rho[j];
+    inf.err_bound = worst;
     inf.cycles = cycle;
     inf.breakdown = flags_h[0];
     if (flags_h[1]) {
@@ -1214,7 +1287,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     }
     bool conv;
     if (pl->opts.stop_rule == EXPMV_STOP_PAPER) conv = rmax <= tol * inf.bnorm;
-    else conv = bound <= tol * inf.znorm;
+    else conv = conv_bound;
     if (!(rmax > 0.0)) conv = true;   // invariant space or exact
     if (!std::isfinite(rmax)) {
       status = EXPMV_EBREAKDOWN;
@@ -1289,39 +1362,36 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     rhs_from_S = true;
     ms_small += host_now_ms() - t3;
   }
-  // true residuals of the shifted systems (FP64 operator, once at the end)
-  if (pl->kind == 0) {
-    Csr<double> A = csr_of<double>(pl, transpose);
-    const int PP = pow2_lanes(p);
-    const int grid = grid_for(n, PP, 512);
-    DISPATCH_PP(PP, hipLaunchKernelGGL((k_true_residual<P_>), dim3(grid), dim3(kThreads), 0, s, n,
-                                       p, A.rowptr, A.colind, A.val, B, w.X.p, pl->tau_re.p,
-                                       pl->tau_im.p, w.partial.p));
+  // true residuals of the shifted systems (FP64 operator, once at the end);
+  // true_res[j] is the largest over the times
+  for (int q = 0; q < nt; ++q) {
+    const double* Xq = w.X.p + size_t(2 * kNShift * p) * q;
+    int grid = 512;
+    if (pl->kind == 0) {
+      Csr<double> A = csr_of<double>(pl, transpose);
+      const int PP = pow2_lanes(p);
+      grid = grid_for(n, PP, 512);
+      DISPATCH_PP(PP, hipLaunchKernelGGL((k_true_residual<P_>), dim3(grid), dim3(kThreads), 0, s,
+                                         n, p, A.rowptr, A.colind, A.val, B, Xq, ldx,
+                                         tau_re_d + kNShift * q, tau_im_d + kNShift * q,
+                                         w.partial.p));
+    } else {
+      pl->kx.alloc(size_t(n) * 2 * kNShift * p);
+      const int64_t ldk = 2 * kNShift * p;
+      for (int j = 0; j < kNShift; ++j)
+        toeplitz_apply<double>(pl, Xq + 2 * p * j, ldx, pl->kx.p + 2 * p * j, ldk, 2 * p, pl->t,
+                               0);
+      hipLaunchKernelGGL(k_residual_from_kx, dim3(grid), dim3(kThreads), 0, s, n, p, B, Xq, ldx,
+                         pl->kx.p, int(ldk), tau_re_d + kNShift * q, tau_im_d + kNShift * q,
+                         w.partial.p);
+    }
     std::vector<double> tp(size_t(grid) * kNShift);
     HIPCHK(hipMemcpyAsync(tp.data(), w.partial.p, sizeof(double) * tp.size(), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (int j = 0; j < kNShift; ++j) {
       double acc = 0.0;
       for (int g = 0; g < grid; ++g) acc += tp[size_t(g) * kNShift + j];
-      inf.true_res[j] = std::sqrt(acc);
-    }
-  }
-  if (pl->kind == 1) {
-    const int64_t ldxr = 2 * kNShift * p;
-    pl->kx.alloc(size_t(n) * ldxr);
-    for (int j = 0; j < kNShift; ++j)
-      toeplitz_apply<double>(pl, w.X.p + 2 * p * j, ldxr, pl->kx.p + 2 * p * j, ldxr, 2 * p, pl->t,
-                             0);
-    const int grid = 512;
-    hipLaunchKernelGGL(k_residual_from_kx, dim3(grid), dim3(kThreads), 0, s, n, p, B, w.X.p,
-                       pl->kx.p, pl->tau_re.p, pl->tau_im.p, w.partial.p);
-    std::vector<double> tp(size_t(grid) * kNShift);
-    HIPCHK(hipMemcpyAsync(tp.data(), w.partial.p, sizeof(double) * tp.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int j = 0; j < kNShift; ++j) {
-      double acc = 0.0;
-      for (int g2 = 0; g2 < grid; ++g2) acc += tp[size_t(g2) * kNShift + j];
-      inf.true_res[j] = std::sqrt(acc);
+      inf.true_res[j] = std::max(inf.true_res[j], std::sqrt(acc));
     }
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -1334,6 +1404,22 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   inf.kern_ms_a = pl->prof_samples ? pl->prof_ms_a / pl->prof_samples : 0.0;
   inf.kern_ms_b = pl->prof_samples ? pl->prof_ms_b / pl->prof_samples : 0.0;
   inf.kern_ms_c = pl->prof_samples ? pl->prof_ms_c / pl->prof_samples : 0.0;
+  inf.kern_orth_launches = 0;
+  inf.kern_ms_orth = inf.kern_orth_bytes = 0.0;
+  if (pl->oev_used > 0) {
+    HIPCHK(hipEventSynchronize(pl->oev[pl->oev_used - 1]));
+    double ms = 0.0, by = 0.0;
+    for (int q = 0; q + 1 < pl->oev_used; q += 2) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, pl->oev[q], pl->oev[q + 1]));
+      ms += t;
+      by += pl->oev_bytes[q / 2];
+    }
+    const int nl = pl->oev_used / 2;
+    inf.kern_orth_launches = nl;
+    inf.kern_ms_orth = ms / nl;
+    inf.kern_orth_bytes = by / nl;
+  }
   inf.kern_smooth_launches = pl->prof_sm_launches;
   inf.kern_ms_smooth = pl->prof_sm_launches ? pl->prof_ms_sm / pl->prof_sm_launches : 0.0;
   inf.amg_levels = pl->amg ? int(pl->amg->lv.size()) : 0;
@@ -1342,10 +1428,11 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
 }
 
 expmv_status dispatch_execute(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
-                              double* Z, expmv_info* info) {
-  if (pl->basis32) return execute_impl<float, float>(pl, transpose, B, p, tol, Z, info);
-  if (pl->mixed) return execute_impl<double, float>(pl, transpose, B, p, tol, Z, info);
-  return execute_impl<double, double>(pl, transpose, B, p, tol, Z, info);
+                              double* Z, expmv_info* info,
+                              const std::vector<double>& scales = std::vector<double>{1.0}) {
+  if (pl->basis32) return execute_impl<float, float>(pl, transpose, B, p, tol, Z, info, scales);
+  if (pl->mixed) return execute_impl<double, float>(pl, transpose, B, p, tol, Z, info, scales);
+  return execute_impl<double, double>(pl, transpose, B, p, tol, Z, info, scales);
 }
 
 }  // namespace
@@ -1356,17 +1443,27 @@ expmv_status dispatch_execute(expmv_plan_s* pl, int transpose, const double* B, 
 
 namespace {
 
+thread_local char g_error_detail[256] = "";
+
 template <typename F>
 expmv_status guarded(F&& f) {
+  g_error_detail[0] = '\0';
   try {
     return f();
-  } catch (const expmv::HipError&) {
+  } catch (const expmv::HipError& e) {
+    std::snprintf(g_error_detail, sizeof(g_error_detail), "HIP call at expmv.hip:%d: %s", e.line,
+                  hipGetErrorString(e.err));
     return EXPMV_EHIP;
   } catch (const expmv::StatusError& e) {
     return e.st;
   } catch (const std::bad_alloc&) {
+    std::snprintf(g_error_detail, sizeof(g_error_detail), "host allocation failed");
     return EXPMV_ENOMEM;
+  } catch (const std::exception& e) {
+    std::snprintf(g_error_detail, sizeof(g_error_detail), "C++ exception: %s", e.what());
+    return EXPMV_EHIP;
   } catch (...) {
+    std::snprintf(g_error_detail, sizeof(g_error_detail), "unknown C++ exception");
     return EXPMV_EHIP;
   }
 }
@@ -1408,6 +1505,8 @@ void init_plan_common(expmv_plan_s* pl) {
     pl->pev.resize(size_t(kSampleEv) * 128);
     pl->pev_iter.resize(128);
     pl->pev_nsm.resize(128);
+    pl->oev.resize(2 * 2048);
+    for (auto& e : pl->oev) HIPCHK(hipEventCreate(&e));
     for (auto& e : pl->pev) HIPCHK(hipEventCreate(&e));
   }
   upload_cf(pl);
@@ -1775,6 +1874,22 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
   return guarded([&]() { return dispatch_execute(plan, transpose, B, int(p), tol, Z, info); });
 }
 
+expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* times, int nt,
+                                 const double* B, int64_t p, double tol, double* Z,
+                                 expmv_info* info) {
+  if (!plan || !times || !B || !Z || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
+  if (nt < 1 || nt > kMaxTimes) return EXPMV_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
+  std::vector<double> scales(nt);
+  for (int q = 0; q < nt; ++q) {
+    if (!std::isfinite(times[q])) return EXPMV_EINVAL;
+    scales[q] = times[q] / plan->t;
+    if (!(scales[q] > 0.0)) return EXPMV_ENOTNEG;   // t_q A must stay negative definite
+  }
+  return guarded(
+      [&]() { return dispatch_execute(plan, transpose, B, int(p), tol, Z, info, scales); });
+}
+
 expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, int64_t p,
                            double tol, double* gradB, double* grad_t, expmv_info* info) {
   if (!plan || !G || !B || !gradB || !grad_t || p < 1 || p > kMaxP || p > plan->n)
@@ -2019,8 +2134,11 @@ void expmv_plan_destroy(expmv_plan plan) {
   if (plan->ev[0]) (void)hipEventDestroy(plan->ev[0]);
   if (plan->ev[1]) (void)hipEventDestroy(plan->ev[1]);
   for (auto& e : plan->pev) (void)hipEventDestroy(e);
+  for (auto& e : plan->oev) (void)hipEventDestroy(e);
   delete plan;
 }
+
+const char* expmv_last_error_detail(void) { return g_error_detail; }
 
 const char* expmv_status_string(expmv_status s) {
   switch (s) {

@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(1024)
 k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
              const double* __restrict__ tau_re, const double* __restrict__ tau_im,
              const cplx* __restrict__ G, cplx* __restrict__ Ascr, cplx* __restrict__ Zs,
-             double* __restrict__ Cr, cplx* __restrict__ S, double* __restrict__ rho,
+             double* __restrict__ Cr, int ldc, cplx* __restrict__ S, double* __restrict__ rho,
              int* __restrict__ singular) {
   const int j = blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -336,8 +336,8 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
     __syncthreads();
   }
   if (tid == 0 && sing) singular[j] = 1;
-  // update coefficients Cr (rows d+p, ld 14p): real part then imaginary part
-  const int ldc = 2 * kNShift * p;
+  // update coefficients Cr (rows d+p, ld ldc = 2 p x shifts): real part then
+  // imaginary part
   for (int idx = tid; idx < (d + p) * p; idx += nt) {
     const int r = idx / p, b = idx % p;
     cplx s{0.0, 0.0};
@@ -440,11 +440,10 @@ k_panel_gemm(int64_t n, int p, const T* __restrict__ V, int npan, const double* 
 // Z = omega0 B + sum_j Re(c_j X_j), X row-major n x 14p (shift j: real part
 // in columns 2pj..2pj+p-1, imaginary part in 2pj+p..2pj+2p-1); partial ||Z||^2.
 __global__ void __launch_bounds__(kThreads)
-k_combine(int64_t n, int p, const double* __restrict__ B, const double* __restrict__ X,
+k_combine(int64_t n, int p, const double* __restrict__ B, const double* __restrict__ X, int ldx,
           double omega0, const double* __restrict__ c_re, const double* __restrict__ c_im,
           double* __restrict__ Z, double* __restrict__ partial) {
   __shared__ double red[kThreads];
-  const int ldx = 2 * kNShift * p;
   double zz = 0.0;
   for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < n * p;
        idx += int64_t(gridDim.x) * kThreads) {
@@ -466,17 +465,17 @@ k_combine(int64_t n, int p, const double* __restrict__ B, const double* __restri
 }
 
 // True residuals R_j = B - (M - tau_j I) X_j = B + K X_j + tau_j X_j with
-// K = -M in CSR; partial[wg * 7 + j] = sum of |R_j|^2 over the workgroup.
+// K = -M in CSR, for the 7 shifts whose X_j start at X (row stride ldx);
+// partial[wg * 7 + j] = sum of |R_j|^2 over the workgroup.
 template <int PP>
 __global__ void __launch_bounds__(kThreads)
 k_true_residual(int64_t n, int p, const int32_t* __restrict__ rowptr,
                 const int32_t* __restrict__ colind, const double* __restrict__ val,
-                const double* __restrict__ B, const double* __restrict__ X,
+                const double* __restrict__ B, const double* __restrict__ X, int ldx,
                 const double* __restrict__ tau_re, const double* __restrict__ tau_im,
                 double* __restrict__ partial) {
   __shared__ double red[kThreads];
   const int c = threadIdx.x % PP;
-  const int ldx = 2 * kNShift * p;
   double nr[kNShift];
   for (int j = 0; j < kNShift; ++j) nr[j] = 0.0;
   const int64_t rows_per_grid = int64_t(gridDim.x) * (kThreads / PP);
