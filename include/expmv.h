@@ -97,6 +97,12 @@ typedef struct {
                           -1 auto = AMG for n >= 4096, else Jacobi                       */
   int amg_degree;      /* Chebyshev smoothing steps before and after each coarse
                           correction (1..4; 0 = 2 for symmetric A, 1 otherwise)          */
+  int inner_relax;     /* c in 0..10, relaxed inner solves (CSR plans, Algorithm 2):
+                          the inner tolerance of block j is inner_tol * min(cap,
+                          ||B||_F / rho_{j-1}), rho_{j-1} the largest residual estimate
+                          (eq. 4.9) over the shifts after block j-1, cap = 10^c (at
+                          most 10^2 in the mixed forms); the estimates cost one
+                          projected solve per block.  0: fixed inner tolerance        */
 } expmv_opts;
 
 typedef struct {                  /* host struct, filled by expmv_execute */
@@ -130,7 +136,7 @@ typedef struct expmv_plan_s* expmv_plan;
 /* Fill *o with the defaults: m = 10, k = 0 (auto), max_cycles = 50, FP64,
  * EXPMV_STOP_BOUND, inner_tol = 0 (auto), inner_maxit = 50000, symmetric = -1,
  * preconditioned = 1, profile = 0, inner_refine = -1, inner_precond = -1,
- * amg_degree = 0.  o is a host pointer. */
+ * amg_degree = 0, inner_relax = 8.  o is a host pointer. */
 expmv_status expmv_default_opts(expmv_opts* o);
 
 /* Plan for Z = e^{tA} B with A in CSR (device arrays, see conventions).

@@ -101,6 +101,9 @@ struct Workspace {
   DevBuf<BcgState> bcgst;
   DevBuf<double> part_rr, part_sig;   // inner-solver partials
   DevBuf<double> taus, coefs;         // poles and coefficients of all shifts (re | im)
+  DevBuf<double> Cr2;                 // scratch of the per-block residual estimates
+  DevBuf<cplx> S2;
+  DevBuf<int> singular2;
   DevBuf<KrylovCtl> ctl;
 };
 
@@ -187,6 +190,7 @@ struct expmv_plan_s {
   double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0, prof_ms_sm = 0.0;
   int prof_samples = 0, prof_sm_launches = 0;
   int last_inner_iters = 0;       // iterations of the previous inner solve
+  double relax_scale = 1.0;       // inner tolerance factor (opts.inner_relax)
   // (profile > 0) start/stop events of the orthogonalisation passes of one
   // execute and their algorithmic bytes
   std::vector<hipEvent_t> oev;
@@ -372,8 +376,8 @@ int cg_grid(int64_t n, int PP) {
 }
 
 double inner_tol_of(expmv_plan_s* pl) {
-  if (pl->opts.inner_tol > 0.0) return pl->opts.inner_tol;
-  return pl->mixed ? 1e-6 : 1e-12;
+  const double base = pl->opts.inner_tol > 0.0 ? pl->opts.inner_tol : (pl->mixed ? 1e-6 : 1e-12);
+  return base * pl->relax_scale;
 }
 
 // Poll the inner solver's control word every `chunk` iterations, one chunk
@@ -1135,6 +1139,11 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     w.singular.alloc(ns);
     w.taus.alloc(2 * size_t(ns));
     w.coefs.alloc(2 * size_t(ns));
+    if (pl->opts.inner_relax) {
+      w.Cr2.alloc(size_t(ldh) * 2 * ns * p);
+      w.S2.alloc(size_t(ns) * p * p);
+      w.singular2.alloc(ns);
+    }
     w.partial.alloc(size_t(512) * std::max(nt, kNShift));
   }
   // poles tau_j / s_q and coefficients c_j / s_q, shift index q * 7 + j
@@ -1207,6 +1216,13 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   expmv_status status = EXPMV_OK;
   std::vector<double> Hh(size_t(ldh) * ldh);
   std::vector<double> rho(ns);
+  // relaxed inner solves (opts.inner_relax = c > 0): the inner tolerance of
+  // block j grows like rho_0 / rho_{j-1}, capped at 10^c (10^2 in the mixed
+  // forms) times the base value
+  const bool relax = pl->opts.inner_relax != 0 && precond && pl->kind == 0;
+  const double relax_cap =
+      std::min(std::pow(10.0, double(pl->opts.inner_relax)), pl->mixed ? 1e2 : 1e12);
+  double rho_prev = 0.0;
   bool rhs_from_S = false;
   int cycle = 0;
   for (;;) {
@@ -1216,7 +1232,13 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       double t0 = host_now_ms();
       const T* Vj = Vb + size_t(jb) * blk;
       if (precond) {
+        // relaxed inner tolerance: factor rho_0 / rho_{j-1} (capped), rho the
+        // largest residual estimate over the shifts after the previous block
+        pl->relax_scale = 1.0;
+        if (relax && rho_prev > 0.0)
+          pl->relax_scale = std::min(relax_cap, std::max(1.0, inf.bnorm / rho_prev));
         InnerResult r = apply_inverse_mixed<T, TI>(pl, transpose, Vj, Wk, p);
+        pl->relax_scale = 1.0;
         inf.inner_iters += r.iters;
         inf.inner_maxit_hit += r.hit_cap;
       } else {
@@ -1231,7 +1253,24 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       orthonormalize<T>(pl, p, Vb, jb + 1, Wk, Vb + size_t(jb + 1) * blk, w.H.p, ldh, jb * p,
                         nullptr);
       ms_orth += host_now_ms() - t1;
+      if (relax && jb + 1 < m) {
+        // residual estimates of the projected systems on the first jb + 1
+        // blocks (scratch outputs: the cycle's own S and Cr stay intact)
+        const int dj = (jb + 1) * p;
+        dim3 g(std::max(1, (dj * p + kThreads - 1) / kThreads), ns);
+        hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, dj, p, rhs_from_S ? kp : 0,
+                           rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
+        hipLaunchKernelGGL(k_proj_solve, dim3(ns), dim3(1024), 0, s, dj, p, 1, w.H.p, ldh,
+                           tau_re_d, tau_im_d, w.G.p, w.Ascr.p, w.Zs.p, w.Cr2.p, ldx, w.S2.p,
+                           w.rho.p, w.singular2.p);
+        HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        rho_prev = 0.0;
+        for (int q = 0; q < ns; ++q) rho_prev = std::max(rho_prev, rho[q]);
+        if (!std::isfinite(rho_prev)) rho_prev = 0.0;
+      }
     }
+    rho_prev = 0.0;
     double t0 = host_now_ms();
     {
       dim3 g(std::max(1, (d * p + kThreads - 1) / kThreads), ns);
@@ -1481,6 +1520,7 @@ bool valid_opts(const expmv_opts& o) {
   if (o.inner_refine < -1 || o.inner_refine > 8) return false;
   if (o.inner_precond < -1 || o.inner_precond > 1) return false;
   if (o.amg_degree < 0 || o.amg_degree > kAmgMaxDeg) return false;
+  if (o.inner_relax < 0 || o.inner_relax > 10) return false;
   return true;
 }
 
@@ -1729,6 +1769,7 @@ expmv_status expmv_default_opts(expmv_opts* o) {
   o->inner_refine = -1;
   o->inner_precond = -1;
   o->amg_degree = 0;
+  o->inner_relax = 8;
   return EXPMV_OK;
 }
 

@@ -174,3 +174,23 @@ def test_amg_convdiff_solve_matches_direct_rational(precision, bar):
     ref = exact.rational_sparse((t * A.to_scipy()).tocsc(), B)
     assert rel(Z.cpu().numpy(), ref) < bar
     assert info.amg_levels >= 2
+
+
+# ---------------------------------------------------------------------------
+# relaxed inner solves (inner_relax): inner tolerance grows like ||B|| / rho
+
+@pytest.mark.parametrize("inner", ["amg", "jacobi"])
+def test_relaxed_inner_solves_keep_accuracy(inner):
+    announce(f"relaxed inner solves 3D 24^3 {inner}")
+    N = 24
+    W = wl.c2(N=N)
+    W.t = 5.842338 / (3 * (2 - 2 * np.cos(np.pi / (N + 1))))
+    rB = inverses.dst_laplacian_function(N, 3, W.t, lambda x: r_eval(np.asarray(x)), W.B)
+    its = {}
+    for relax in (0, 8):
+        pl = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=DEV, m=6, k=16,
+                      inner_precond=inner, inner_relax=relax)
+        Z, info = pl.execute(torch.from_numpy(W.B), tol=1e-10)
+        assert rel(Z.cpu().numpy(), rB) < 1e-10
+        its[relax] = info.inner_iters
+    assert its[8] < 0.9 * its[0], its
