@@ -1253,9 +1253,11 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       orthonormalize<T>(pl, p, Vb, jb + 1, Wk, Vb + size_t(jb + 1) * blk, w.H.p, ldh, jb * p,
                         nullptr);
       ms_orth += host_now_ms() - t1;
-      if (relax && jb + 1 < m) {
+      if (relax && jb + 1 < m && (jb - first_block) % 2 == 1) {
         // residual estimates of the projected systems on the first jb + 1
-        // blocks (scratch outputs: the cycle's own S and Cr stay intact)
+        // blocks, after every second block (each is a latency-bound dense
+        // solve per shift); scratch outputs: the cycle's own S and Cr stay
+        // intact
         const int dj = (jb + 1) * p;
         dim3 g(std::max(1, (dj * p + kThreads - 1) / kThreads), ns);
         hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, dj, p, rhs_from_S ? kp : 0,
