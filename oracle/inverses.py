@@ -103,6 +103,48 @@ def gohberg_semencul_inverse(col: np.ndarray, scale: float):
     return apply
 
 
+def toeplitz_matvec_general(col: np.ndarray, row: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """T V for Toeplitz T with first column col and first row row (row[0] =
+    col[0]) via the circulant of size 2n whose first column is
+    [col, 0, row[n-1], ..., row[1]]."""
+    n = len(col)
+    emb = np.concatenate([col, [0.0], row[1:][::-1]])
+    F = sfft.fft(emb)
+    W = sfft.ifft(F[:, None] * sfft.fft(np.asarray(V, np.float64), n=2 * n, axis=0), axis=0)
+    return W[:n].real
+
+
+def gohberg_semencul_general(col: np.ndarray, row: np.ndarray, scale: float):
+    """(scale*T)^{-1} V for a nonsymmetric Toeplitz T (first column col, first
+    row row) by the Gohberg-Semencul formula (Section 4.1 and the Toeplitz
+    experiment of Section 5): with x = T^{-1} e_1, y = T^{-1} e_n (Levinson
+    solves, scipy) and x_0 = x[0] != 0,
+        T^{-1} = (1/x_0) (L(x) L(J y)^T - L(Z y) L(Z J x)^T),
+    L(v) lower-triangular Toeplitz with first column v, J the reversal, Z the
+    down-shift; for symmetric T (y = J x) this is the symmetric formula."""
+    n = len(col)
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    en = np.zeros(n)
+    en[-1] = 1.0
+    x = sla.solve_toeplitz((col, row), e1)
+    y = sla.solve_toeplitz((col, row), en)
+    shift = lambda v: np.concatenate([[0.0], v[:-1]])   # Z v
+
+    def lower(vec_col, V):                    # L(vec) V
+        F = sfft.rfft(vec_col, n=2 * n)
+        return sfft.irfft(F[:, None] * sfft.rfft(V, n=2 * n, axis=0), n=2 * n, axis=0)[:n]
+
+    def upper(vec_col, V):                    # L(vec)^T V = J L(vec) J V
+        return lower(vec_col, V[::-1])[::-1]
+
+    def apply(V):
+        V = np.asarray(V, np.float64)
+        W = lower(x, upper(y[::-1], V)) - lower(shift(y), upper(shift(x[::-1]), V))
+        return W / (x[0] * scale)
+    return apply
+
+
 # ---- iterative ----------------------------------------------------------------
 
 def krylov_inverse(M: sp.spmatrix, rtol: float = 1e-14, symmetric: bool = True, maxiter=100000):

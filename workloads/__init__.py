@@ -146,6 +146,36 @@ def toeplitz_symbol_max(c: np.ndarray) -> float:
     return float(np.max(np.fft.rfft(v).real))
 
 
+def grunwald_weights(beta: float, count: int) -> np.ndarray:
+    """g_k = (-1)^k binom(beta, k), k = 0..count-1, by g_k = g_{k-1} (1 - (beta+1)/k)."""
+    g = np.empty(count)
+    g[0] = 1.0
+    for k in range(1, count):
+        g[k] = g[k - 1] * (1.0 - (beta + 1.0) / k)
+    return g
+
+
+def fractional_toeplitz(n: int, beta: float = 1.8, d1: float = 1.0, d2: float = 3.0):
+    """Two-sided space-fractional diffusion d1 D_+^beta + d2 D_-^beta on (0, 1),
+    zero Dirichlet data, shifted Gruenwald formula, h = 1/(n+1):
+    A = h^{-beta} (d1 G + d2 G^T), G the lower Hessenberg Toeplitz matrix with
+    G_ij = g_{i-j+1} (j <= i + 1).  A is a nonsymmetric Toeplitz matrix with a
+    negative definite symmetric part.  Returns (col, row): first column and
+    first row of T = -A (the exponent matrix is t * (-T))."""
+    g = grunwald_weights(beta, n + 2)
+    col = np.zeros(n)
+    row = np.zeros(n)
+    col[0] = row[0] = (d1 + d2) * g[1]
+    if n > 1:
+        col[1] = d1 * g[2] + d2 * g[0]
+        row[1] = d1 * g[0] + d2 * g[2]
+    if n > 2:
+        col[2:] = d1 * g[3:n + 1]
+        row[2:] = d2 * g[3:n + 1]
+    scale = (n + 1.0) ** beta
+    return -col * scale, -row * scale
+
+
 def gaussian_block(n: int, p: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((n, p))
 
@@ -163,6 +193,7 @@ class Workload:
     B: np.ndarray
     A: CSR | None = None      # A (not tA) for kind == "csr"
     col: np.ndarray | None = None   # first column of T for kind == "toeplitz" (A = -T)
+    row: np.ndarray | None = None   # first row of T when T is not symmetric
     symmetric: bool = True
     precision: str = "fp64"
     note: str = ""
@@ -190,6 +221,16 @@ def c3(n: int = 1 << 20, p: int = 16, m: int = 10) -> Workload:
     t = 1e3 / toeplitz_symbol_max(col)
     return Workload("toeplitz", "toeplitz", n, p, t, m, p * (m // 3), 1e-10,
                     gaussian_block(n, p, 3), col=col, note=f"SPD Toeplitz n={n}")
+
+
+def c6(n: int = 1 << 17, p: int = 2, m: int = 30, t: float = 0.1) -> Workload:
+    """Nonsymmetric Toeplitz: fractional diffusion, beta = 1.8, d1 = 1, d2 = 3
+    (the large-n Toeplitz experiment of Section 5), A = -T, B Gaussian n x 2.
+    t = 0.1 puts t lambda_min at 2.76 (lambda_min(-A) = 27.6 for every n)."""
+    col, row = fractional_toeplitz(n)
+    return Workload("fractional", "toeplitz", n, p, t, m, p * (m // 3), 1e-10,
+                    gaussian_block(n, p, 6), col=col, row=row, symmetric=False,
+                    note=f"fractional diffusion Toeplitz n={n}, beta=1.8, d1=1, d2=3")
 
 
 def c4(N: int = 128, p: int = 16, m: int = 10, precision: str = "mixed") -> Workload:
