@@ -160,6 +160,20 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
 expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t,
                                  const expmv_opts* opts, hipStream_t stream, expmv_plan* out);
 
+/* Plan for A = -T with T a general (nonsymmetric) Toeplitz matrix given by
+ * its first column col0 and first row row0 (device, n values each; row0[0]
+ * is ignored, row0 = NULL means T symmetric), tA = -t T with t > 0; T's
+ * symmetric part should be positive definite (e.g. the space-fractional
+ * diffusion matrices of Section 5).  Products with T and T^T use length-2n
+ * circulant embeddings; (tA)^{-1} and its transpose use the Gohberg-Semencul
+ * formula with x = T^{-1} e_1 and y = T^{-1} e_n, solved once at plan
+ * creation (BiCGStab with the FFT product, preconditioned by T's Strang
+ * circulant when n is a power of two).  Errors as expmv_plan_csr; ENOCONV if
+ * those set-up solves do not reach a relative residual of 1e-10. */
+expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const double* row0,
+                                         double t, const expmv_opts* opts, hipStream_t stream,
+                                         expmv_plan* out);
+
 /* Z = e^{tA} B (transpose = 0) or Z = e^{tA^T} B (transpose = 1), p = block
  * width (1 <= p <= 32, p <= n), tol = stopping tolerance of opts.stop_rule.
  * B and Z are device n x p blocks and may not overlap.  info (host) may be

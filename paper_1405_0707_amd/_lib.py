@@ -49,7 +49,7 @@ EXPORTS = [
     "expmv_status_string", "expmv_block_csr", "expmv_block_toeplitz",
     "expmv_apply_preconditioner", "expmv_host_amg_build", "expmv_host_amg_levels",
     "expmv_host_amg_level", "expmv_host_amg_coarse_inverse", "expmv_host_amg_destroy",
-    "expmv_execute_times", "expmv_last_error_detail",
+    "expmv_execute_times", "expmv_last_error_detail", "expmv_plan_toeplitz_general",
 ]
 
 _lib = None
@@ -68,6 +68,8 @@ def lib():
     L.expmv_default_opts.argtypes = [C.POINTER(Opts)]
     L.expmv_plan_csr.argtypes = [i64, i64, vp, vp, vp, dbl, C.POINTER(Opts), vp, C.POINTER(vp)]
     L.expmv_plan_toeplitz.argtypes = [i64, vp, dbl, C.POINTER(Opts), vp, C.POINTER(vp)]
+    L.expmv_plan_toeplitz_general.argtypes = [i64, vp, vp, dbl, C.POINTER(Opts), vp,
+                                              C.POINTER(vp)]
     L.expmv_execute.argtypes = [vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
     L.expmv_grad_t.argtypes = [vp, vp, vp, i64, C.POINTER(dbl)]
     L.expmv_adjoint.argtypes = [vp, vp, vp, i64, dbl, vp, C.POINTER(dbl), C.POINTER(Info)]

@@ -48,9 +48,10 @@ def _dev_f64(x, device) -> torch.Tensor:
 
 @dataclasses.dataclass
 class Toeplitz:
-    """Symmetric positive definite Toeplitz T given by its first column;
-    the exponent is t * (-T)."""
+    """Toeplitz T given by its first column (and first row when T is not
+    symmetric); the exponent is t * (-T)."""
     col0: torch.Tensor
+    row0: torch.Tensor | None = None
 
 
 class Plan:
@@ -78,14 +79,23 @@ class Plan:
         return cls(h, n, rowptr.device, float(t))
 
     @classmethod
-    def toeplitz(cls, col0, t: float, device="cuda", **opts):
+    def toeplitz(cls, col0, t: float, device="cuda", row0=None, **opts):
+        """A = -T with T Toeplitz: first column col0, first row row0 (None:
+        T symmetric)."""
         col0 = _dev_f64(col0, device)
         o = default_opts(**opts)
         h = C.c_void_p()
-        st = lib().expmv_plan_toeplitz(col0.numel(), col0.data_ptr(), float(t), C.byref(o),
-                                       _stream_ptr(col0.device), C.byref(h))
-        check(st, "expmv_plan_toeplitz")
-        return cls(h, col0.numel(), col0.device, float(t))
+        if row0 is None:
+            st = lib().expmv_plan_toeplitz(col0.numel(), col0.data_ptr(), float(t), C.byref(o),
+                                           _stream_ptr(col0.device), C.byref(h))
+            check(st, "expmv_plan_toeplitz")
+            return cls(h, col0.numel(), col0.device, float(t))
+        row0 = _dev_f64(row0, device)
+        st = lib().expmv_plan_toeplitz_general(col0.numel(), col0.data_ptr(), row0.data_ptr(),
+                                               float(t), C.byref(o), _stream_ptr(col0.device),
+                                               C.byref(h))
+        check(st, "expmv_plan_toeplitz_general")
+        return cls(h, col0.numel(), col0.device, float(t), keepalive=(row0,))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -243,7 +253,7 @@ def cf_table():
 
 def _make_plan(A, t, device, opts):
     if isinstance(A, Toeplitz):
-        return Plan.toeplitz(A.col0, t, device=device, **opts)
+        return Plan.toeplitz(A.col0, t, device=device, row0=A.row0, **opts)
     if isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr:
         return Plan.csr(A.crow_indices(), A.col_indices(), A.values(), t, device=device, **opts)
     rowptr, colind, val = A

@@ -171,6 +171,9 @@ struct expmv_plan_s {
   double x0 = 0.0;
   std::vector<int> radices;
   DevBuf<cplx> chat, xhat, yhat;
+  // nonsymmetric T: spectrum of the embedding of T^T, and of the generators
+  // J y, Z y (y = T^{-1} e_n) beside x and Z J x (xhat, yhat)
+  DevBuf<cplx> chatT, jyhat, zyhat;
   DevBuf<cplx> fb[4];            // L x q work arrays
   int fq = 0;                    // complex columns the work arrays hold
   DevBuf<double> kx;             // n x 14p (Toeplitz true residual)
@@ -320,14 +323,14 @@ Csr<float> csr_of<float>(expmv_plan_s* pl, int transpose) {
 // Y = K X (K = -tA, or its transpose) for n x p blocks of type T.
 template <typename T>
 void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy, int p,
-                    double scale, int accumulate);
+                    double scale, int accumulate, int transpose = 0);
 template <typename T>
-void toeplitz_gsf(expmv_plan_s* pl, const T* V, T* W, int p, double scale);
+void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, double scale);
 
 template <typename T>
 void apply_K(expmv_plan_s* pl, int transpose, const T* X, T* Y, int p) {
-  if (pl->kind == 1) {   // K = t T, T symmetric
-    toeplitz_apply<T>(pl, X, p, Y, p, p, pl->t, 0);
+  if (pl->kind == 1) {   // K = t T (or t T^T)
+    toeplitz_apply<T>(pl, X, p, Y, p, p, pl->t, 0, transpose);
     return;
   }
   Csr<T> A = csr_of<T>(pl, transpose);
@@ -649,8 +652,8 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
 // W ~= M^{-1} V = -(K^{-1} V), M = tA.
 template <typename T>
 InnerResult apply_inverse(expmv_plan_s* pl, int transpose, const T* V, T* Wout, int p) {
-  if (pl->kind == 1) {   // M^{-1} = -(1/t) T^{-1}, Gohberg-Semencul
-    toeplitz_gsf<T>(pl, V, Wout, p, -1.0 / pl->t);
+  if (pl->kind == 1) {   // M^{-1} = -(1/t) T^{-1} (or T^{-T}), Gohberg-Semencul
+    toeplitz_gsf<T>(pl, transpose, V, Wout, p, -1.0 / pl->t);
     return {0, 0};
   }
   if (pl->symmetric) return inner_cg<T>(pl, V, -1.0, Wout, p);
@@ -683,15 +686,15 @@ int stream_grid(int64_t items) {
 }
 
 // out = DFT(in) over L rows for q columns (sign -1 forward, +1 inverse,
-// unnormalised); in, out and tmp distinct.
-void fft(expmv_plan_s* pl, const cplx* in, cplx* out, cplx* tmp, int q, double sign) {
-  const int np = int(pl->radices.size());
-  const int64_t L = pl->L;
+// unnormalised); in, out and tmp distinct; L = the product of radices.
+void fft_len(expmv_plan_s* pl, int64_t L, const std::vector<int>& radices, const cplx* in,
+             cplx* out, cplx* tmp, int q, double sign) {
+  const int np = int(radices.size());
   const cplx* src = in;
   int64_t Ns = 1;
   for (int i = 0; i < np; ++i) {
     cplx* dst = ((np - 1 - i) % 2 == 0) ? out : tmp;
-    const int R = pl->radices[i];
+    const int R = radices[i];
     const int grid = stream_grid((L / R) * q);
     if (R == 8)
       hipLaunchKernelGGL(k_fft_pass<8>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
@@ -704,6 +707,11 @@ void fft(expmv_plan_s* pl, const cplx* in, cplx* out, cplx* tmp, int q, double s
   }
 }
 
+// the embedding's transform, length pl->L
+void fft(expmv_plan_s* pl, const cplx* in, cplx* out, cplx* tmp, int q, double sign) {
+  fft_len(pl, pl->L, pl->radices, in, out, tmp, q, sign);
+}
+
 void ensure_fft_buffers(expmv_plan_s* pl, int q) {
   if (pl->fq >= q) return;
   for (auto& b : pl->fb) b.alloc(size_t(pl->L) * q);
@@ -713,7 +721,8 @@ void ensure_fft_buffers(expmv_plan_s* pl, int q) {
 // Y (n x p, ld) = scale * T X (X n x p, ld) through the circulant embedding
 template <typename T>
 void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy, int p,
-                    double scale, int accumulate) {
+                    double scale, int accumulate, int transpose) {
+  const cplx* sym = (transpose && !pl->symmetric) ? pl->chatT.p : pl->chat.p;
   const int q = (p + 1) / 2;
   ensure_fft_buffers(pl, q);
   const int64_t L = pl->L, n = pl->n;
@@ -722,18 +731,31 @@ void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy
   hipLaunchKernelGGL((k_pack<T>), dim3(stream_grid(L * q)), dim3(kThreads), 0, s, n, p, ldx, q, L,
                      X, A, 0, 1.0);
   fft(pl, A, Bf, C, q, -1.0);
-  hipLaunchKernelGGL(k_spec_mul, dim3(stream_grid(L * q)), dim3(kThreads), 0, s, L, q, Bf,
-                     pl->chat.p, scale / double(L));
+  hipLaunchKernelGGL(k_spec_mul, dim3(stream_grid(L * q)), dim3(kThreads), 0, s, L, q, Bf, sym,
+                     scale / double(L));
   fft(pl, Bf, A, C, q, +1.0);
   hipLaunchKernelGGL((k_unpack<T>), dim3(stream_grid(n * p)), dim3(kThreads), 0, s, n, p, ldy, q, A,
                      Y, 0, 1.0, accumulate);
 }
 
-// W = scale * T^{-1} V by the Gohberg-Semencul formula
-//   T^{-1} = (1/x0) (L(x) L(x)^T - L(y) L(y)^T),  x = T^{-1} e_1, y = Z x~,
-// L(h)^T v = rev(L(h) rev(v)); six length-L FFTs per block.
+// W = scale * T^{-1} V (or T^{-T} V) by the Gohberg-Semencul formula
+//   T^{-1} = (1/x0) (L(x) L(Jy)^T - L(Zy) L(ZJx)^T),
+//   T^{-T} = (1/x0) (L(Jy) L(x)^T - L(ZJx) L(Zy)^T),
+// x = T^{-1} e_1, y = T^{-1} e_n (symmetric T: y = J x), L(h)^T v =
+// rev(L(h) rev(v)); with spectra a1, a2 for the two transposed factors and
+// b1, b2 for the lower ones: W = (L(b1) L(a1)^T - L(b2) L(a2)^T) V / x0.
+// Six length-L FFTs per block.
 template <typename T>
-void toeplitz_gsf(expmv_plan_s* pl, const T* V, T* W, int p, double scale) {
+void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, double scale) {
+  const bool tr = transpose && !pl->symmetric;
+  const cplx* gx = pl->xhat.p;                                // x
+  const cplx* gzjx = pl->yhat.p;                              // Z J x
+  const cplx* gjy = pl->symmetric ? pl->xhat.p : pl->jyhat.p;  // J y
+  const cplx* gzy = pl->symmetric ? pl->yhat.p : pl->zyhat.p;  // Z y
+  const cplx* a1 = tr ? gx : gjy;
+  const cplx* a2 = tr ? gzy : gzjx;
+  const cplx* b1 = tr ? gjy : gx;
+  const cplx* b2 = tr ? gzjx : gzy;
   const int q = (p + 1) / 2;
   ensure_fft_buffers(pl, q);
   const int64_t L = pl->L, n = pl->n;
@@ -744,16 +766,15 @@ void toeplitz_gsf(expmv_plan_s* pl, const T* V, T* W, int p, double scale) {
   hipLaunchKernelGGL((k_pack<T>), dim3(g), dim3(kThreads), 0, s, n, p, int64_t(p), q, L, V, A, 1,
                      1.0);
   fft(pl, A, Bf, C, q, -1.0);                                   // B = F rev(V)
-  hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, pl->xhat.p, C, inv);
-  hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, pl->yhat.p, D, inv);
-  fft(pl, C, A, Bf, q, +1.0);                                   // A = L(x) rev(V)
-  hipLaunchKernelGGL(k_rev_trunc, dim3(g), dim3(kThreads), 0, s, L, n, q, A, C, 1.0);  // C = L(x)^T V
-  fft(pl, D, A, Bf, q, +1.0);                                   // A = L(y) rev(V)
-  hipLaunchKernelGGL(k_rev_trunc, dim3(g), dim3(kThreads), 0, s, L, n, q, A, D, 1.0);  // D = L(y)^T V
+  hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, a1, C, inv);
+  hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, a2, D, inv);
+  fft(pl, C, A, Bf, q, +1.0);                                   // A = L(a1) rev(V)
+  hipLaunchKernelGGL(k_rev_trunc, dim3(g), dim3(kThreads), 0, s, L, n, q, A, C, 1.0);  // C = L(a1)^T V
+  fft(pl, D, A, Bf, q, +1.0);                                   // A = L(a2) rev(V)
+  hipLaunchKernelGGL(k_rev_trunc, dim3(g), dim3(kThreads), 0, s, L, n, q, A, D, 1.0);  // D = L(a2)^T V
   fft(pl, C, A, Bf, q, -1.0);                                   // A = F C
   fft(pl, D, C, Bf, q, -1.0);                                   // C = F D
-  hipLaunchKernelGGL(k_spec_mul2, dim3(g), dim3(kThreads), 0, s, L, q, A, pl->xhat.p, C,
-                     pl->yhat.p, Bf, inv);
+  hipLaunchKernelGGL(k_spec_mul2, dim3(g), dim3(kThreads), 0, s, L, q, A, b1, C, b2, Bf, inv);
   fft(pl, Bf, A, C, q, +1.0);
   hipLaunchKernelGGL((k_unpack<T>), dim3(stream_grid(n * p)), dim3(kThreads), 0, s, n, p,
                      int64_t(p), q, A, W, 0, scale / pl->x0, 0);
@@ -1421,7 +1442,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       const int64_t ldk = 2 * kNShift * p;
       for (int j = 0; j < kNShift; ++j)
         toeplitz_apply<double>(pl, Xq + 2 * p * j, ldx, pl->kx.p + 2 * p * j, ldk, 2 * p, pl->t,
-                               0);
+                               0, transpose);
       hipLaunchKernelGGL(k_residual_from_kx, dim3(grid), dim3(kThreads), 0, s, n, p, B, Xq, ldx,
                          pl->kx.p, int(ldk), tau_re_d + kNShift * q, tau_im_d + kNShift * q,
                          w.partial.p);
@@ -1748,6 +1769,197 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
   return EXPMV_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Toeplitz plan set-up: spectra of the circulant embeddings of T (and T^T)
+// and of the Gohberg-Semencul generators x = T^{-1} e_1 (and y = T^{-1} e_n)
+
+// Host-driven Krylov solve T z = e_k with the FFT product: CG for symmetric
+// T; for general T BiCGStab, right-preconditioned by the inverse of T's
+// Strang circulant (first column c_0..c_{n/2}, r_{n/2-1}..r_1) when n is a
+// power of two (a length-n FFT), unpreconditioned otherwise.  Returns the
+// true relative residual ||e_k - T z|| (z on the device).
+double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
+                            const std::vector<double>& r, int64_t k, double* z) {
+  const int64_t n = pl->n;
+  hipStream_t s = pl->stream;
+  const int g = stream_grid(n);
+  std::vector<DevBuf<double>> v(9);
+  for (auto& b : v) b.alloc(n);
+  double *x = z, *res = v[0].p, *rh = v[1].p, *pv = v[2].p, *vv = v[3].p, *sv = v[4].p,
+         *tv = v[5].p, *ph = v[6].p, *sh = v[7].p, *tmp = v[8].p;
+  HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+  HIPCHK(hipMemsetAsync(res, 0, sizeof(double) * n, s));
+  const double one = 1.0;
+  HIPCHK(hipMemcpyAsync(res + k, &one, sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto Tapply = [&](const double* in, double* outp) {
+    toeplitz_apply<double>(pl, in, 1, outp, 1, 1, 1.0, 0, 0);
+  };
+  auto axpby = [&](double a, const double* xx, double b, double* yy) {
+    hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, a, xx, b, yy);
+  };
+  auto copy = [&](const double* from, double* to) {
+    HIPCHK(hipMemcpyAsync(to, from, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  };
+  if (pl->symmetric) {
+    copy(res, pv);
+    double rr = 1.0;
+    for (int it = 0; it < 20000; ++it) {
+      Tapply(pv, vv);
+      const double pq = device_dot(pl, n, pv, vv);
+      if (!(pq > 0.0)) throw StatusError{EXPMV_ENOTNEG};   // T not positive definite
+      const double alpha = rr / pq;
+      axpby(alpha, pv, 1.0, x);
+      axpby(-alpha, vv, 1.0, res);
+      const double rr2 = device_dot(pl, n, res, res);
+      if (std::sqrt(rr2) <= 1e-14) break;
+      axpby(1.0, res, rr2 / rr, pv);
+      rr = rr2;
+    }
+  } else {
+    // Strang circulant preconditioner (n a power of two)
+    const bool pow2 = (n & (n - 1)) == 0 && n >= 4;
+    DevBuf<cplx> inv_eig;
+    std::vector<int> rad_n;
+    if (pow2) {
+      rad_n = fft_radices(n);
+      std::vector<double> sc(n, 0.0);
+      for (int64_t i = 0; i <= n / 2; ++i) sc[i] = c[i];
+      for (int64_t i = n / 2 + 1; i < n; ++i) sc[i] = r[n - i];
+      DevBuf<double> scd;
+      scd.alloc(n);
+      HIPCHK(hipMemcpyAsync(scd.p, sc.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
+                         int64_t(1), 1, n, scd.p, pl->fb[0].p, 0, 1.0);
+      fft_len(pl, n, rad_n, pl->fb[0].p, pl->fb[1].p, pl->fb[2].p, 1, -1.0);
+      std::vector<cplx> ev(n);
+      HIPCHK(hipMemcpyAsync(ev.data(), pl->fb[1].p, sizeof(cplx) * n, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (auto& e : ev) {
+        const double d = e.x * e.x + e.y * e.y;
+        e = d > 0.0 ? cplx{e.x / d, -e.y / d} : cplx{0.0, 0.0};
+      }
+      inv_eig.alloc(n);
+      HIPCHK(hipMemcpyAsync(inv_eig.p, ev.data(), sizeof(cplx) * n, hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    auto Papply = [&](const double* in, double* outp) {
+      if (!pow2) {
+        copy(in, outp);
+        return;
+      }
+      hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
+                         int64_t(1), 1, n, in, pl->fb[0].p, 0, 1.0);
+      fft_len(pl, n, rad_n, pl->fb[0].p, pl->fb[1].p, pl->fb[2].p, 1, -1.0);
+      hipLaunchKernelGGL(k_spec_mul, dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
+                         pl->fb[1].p, inv_eig.p, 1.0 / double(n));
+      fft_len(pl, n, rad_n, pl->fb[1].p, pl->fb[0].p, pl->fb[2].p, 1, +1.0);
+      hipLaunchKernelGGL((k_unpack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
+                         int64_t(1), 1, pl->fb[0].p, outp, 0, 1.0, 0);
+    };
+    copy(res, rh);
+    HIPCHK(hipMemsetAsync(pv, 0, sizeof(double) * n, s));
+    HIPCHK(hipMemsetAsync(vv, 0, sizeof(double) * n, s));
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    for (int it = 0; it < 20000; ++it) {
+      const double rho = device_dot(pl, n, rh, res);
+      if (rho == 0.0 || omega == 0.0) break;
+      const double beta = (rho / rho_prev) * (alpha / omega);
+      // p = r + beta (p - omega v)
+      axpby(-omega, vv, 1.0, pv);
+      axpby(1.0, res, beta, pv);
+      Papply(pv, ph);
+      Tapply(ph, vv);
+      const double rv = device_dot(pl, n, rh, vv);
+      if (rv == 0.0) break;
+      alpha = rho / rv;
+      copy(res, sv);
+      axpby(-alpha, vv, 1.0, sv);                      // s = r - alpha v
+      Papply(sv, sh);
+      Tapply(sh, tv);
+      const double tt = device_dot(pl, n, tv, tv);
+      omega = tt > 0.0 ? device_dot(pl, n, tv, sv) / tt : 0.0;
+      axpby(alpha, ph, 1.0, x);
+      axpby(omega, sh, 1.0, x);                        // x += alpha p^ + omega s^
+      copy(sv, res);
+      axpby(-omega, tv, 1.0, res);                     // r = s - omega t
+      rho_prev = rho;
+      if (std::sqrt(device_dot(pl, n, res, res)) <= 1e-14) break;
+    }
+  }
+  // true residual e_k - T z
+  Tapply(x, tmp);
+  HIPCHK(hipMemsetAsync(res, 0, sizeof(double) * n, s));
+  HIPCHK(hipMemcpyAsync(res + k, &one, sizeof(double), hipMemcpyHostToDevice, s));
+  axpby(-1.0, tmp, 1.0, res);
+  const double rn = std::sqrt(device_dot(pl, n, res, res));
+  HIPCHK(hipStreamSynchronize(s));
+  return rn;
+}
+
+expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
+                            const std::vector<double>& r) {
+  const int64_t n = pl->n;
+  hipStream_t s = pl->stream;
+  int64_t L = 1;
+  while (L < 2 * n) L <<= 1;
+  pl->L = L;
+  pl->radices = fft_radices(L);
+  pl->ws.partial.alloc(4096);
+  ensure_fft_buffers(pl, 1);
+  DevBuf<double> tmp;
+  tmp.alloc(L);
+  auto spectrum = [&](const std::vector<double>& h, DevBuf<cplx>& dst) {
+    dst.alloc(L);
+    HIPCHK(hipMemcpyAsync(tmp.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(L)), dim3(kThreads), 0, s,
+                       int64_t(h.size()), 1, int64_t(1), 1, L, tmp.p, pl->fb[0].p, 0, 1.0);
+    fft(pl, pl->fb[0].p, dst.p, pl->fb[1].p, 1, -1.0);
+    HIPCHK(hipStreamSynchronize(s));
+  };
+  // circulant embeddings [c_0 .. c_{n-1}, 0 .., r_{n-1} .. r_1] of T and
+  // [r_0 .. r_{n-1}, 0 .., c_{n-1} .. c_1] of T^T
+  std::vector<double> emb(L, 0.0);
+  for (int64_t i = 0; i < n; ++i) emb[i] = c[i];
+  for (int64_t i = 1; i < n; ++i) emb[L - i] = r[i];
+  spectrum(emb, pl->chat);
+  if (!pl->symmetric) {
+    std::fill(emb.begin(), emb.end(), 0.0);
+    for (int64_t i = 0; i < n; ++i) emb[i] = r[i];
+    for (int64_t i = 1; i < n; ++i) emb[L - i] = c[i];
+    spectrum(emb, pl->chatT);
+  }
+  // generators (once per plan)
+  DevBuf<double> xd, yd;
+  xd.alloc(n);
+  if (toeplitz_setup_solve(pl, c, r, 0, xd.p) > 1e-10) return EXPMV_ENOCONV;
+  std::vector<double> xh(n), yh;
+  HIPCHK(hipMemcpy(xh.data(), xd.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+  pl->x0 = xh[0];
+  if (!(pl->x0 > 0.0)) return EXPMV_ENOTNEG;
+  if (pl->symmetric) {
+    yh.assign(xh.rbegin(), xh.rend());   // y = J x
+  } else {
+    yd.alloc(n);
+    if (toeplitz_setup_solve(pl, c, r, n - 1, yd.p) > 1e-10) return EXPMV_ENOCONV;
+    yh.resize(n);
+    HIPCHK(hipMemcpy(yh.data(), yd.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+  }
+  std::vector<double> e(L, 0.0);
+  auto gen = [&](auto f, DevBuf<cplx>& dst) {
+    std::fill(e.begin(), e.end(), 0.0);
+    for (int64_t i = 0; i < n; ++i) e[i] = f(i);
+    spectrum(e, dst);
+  };
+  gen([&](int64_t i) { return xh[i]; }, pl->xhat);                            // x
+  gen([&](int64_t i) { return i ? xh[n - i] : 0.0; }, pl->yhat);             // Z J x
+  if (!pl->symmetric) {
+    gen([&](int64_t i) { return yh[n - 1 - i]; }, pl->jyhat);                 // J y
+    gen([&](int64_t i) { return i ? yh[i - 1] : 0.0; }, pl->zyhat);          // Z y
+  }
+  return EXPMV_OK;
+}
+
 }  // namespace
 
 struct expmv_amg_s {
@@ -1816,16 +2028,30 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const
 
 expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t, const expmv_opts* opts,
                                  hipStream_t stream, expmv_plan* out) {
+  return expmv_plan_toeplitz_general(n, col0, nullptr, t, opts, stream, out);
+}
+
+expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const double* row0,
+                                         double t, const expmv_opts* opts, hipStream_t stream,
+                                         expmv_plan* out) {
   if (!out) return EXPMV_EINVAL;
   *out = nullptr;
   if (n < 2 || n > (int64_t(1) << 28) || !col0) return EXPMV_EINVAL;
   if (!(t != 0.0) || !std::isfinite(t)) return EXPMV_EINVAL;
-  if (t < 0.0) return EXPMV_ENOTNEG;   // tA = -t T with T SPD needs t > 0
+  if (t < 0.0) return EXPMV_ENOTNEG;   // tA = -t T needs t > 0
   expmv_opts o;
   expmv_default_opts(&o);
   if (opts) o = *opts;
   if (!valid_opts(o)) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
+    std::vector<double> c(n), r(n);
+    HIPCHK(hipMemcpy(c.data(), col0, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (row0) HIPCHK(hipMemcpy(r.data(), row0, sizeof(double) * n, hipMemcpyDeviceToHost));
+    else r = c;
+    r[0] = c[0];
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(c[i]) || !std::isfinite(r[i])) return EXPMV_EINVAL;
+    if (!(c[0] > 0.0)) return EXPMV_ENOTNEG;
     std::unique_ptr<expmv_plan_s> pl(new expmv_plan_s());
     pl->kind = 1;
     pl->n = n;
@@ -1835,76 +2061,10 @@ expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t, const 
     pl->stream = stream;
     pl->mixed = (o.precision != EXPMV_FP64);
     pl->basis32 = (o.precision == EXPMV_MIXED);
-    pl->symmetric = true;
+    pl->symmetric = (c == r);
     init_plan_common(pl.get());
-    hipStream_t s = stream;
-    std::vector<double> c(n);
-    HIPCHK(hipMemcpy(c.data(), col0, sizeof(double) * n, hipMemcpyDeviceToHost));
-    for (double v : c)
-      if (!std::isfinite(v)) return EXPMV_EINVAL;
-    if (!(c[0] > 0.0)) return EXPMV_ENOTNEG;
-    int64_t L = 1;
-    while (L < 2 * n) L <<= 1;
-    pl->L = L;
-    pl->radices = fft_radices(L);
-    pl->ws.partial.alloc(4096);
-    ensure_fft_buffers(pl.get(), 1);
-    // spectrum of the circulant embedding [c_0 .. c_{n-1}, 0 .., c_{n-1} .. c_1]
-    std::vector<double> emb(L, 0.0);
-    for (int64_t i = 0; i < n; ++i) emb[i] = c[i];
-    for (int64_t i = 1; i < n; ++i) emb[L - i] = c[i];
-    DevBuf<double> tmp;
-    tmp.alloc(L);
-    pl->chat.alloc(L);
-    pl->xhat.alloc(L);
-    pl->yhat.alloc(L);
-    auto spectrum = [&](const std::vector<double>& h, cplx* dst) {
-      HIPCHK(hipMemcpyAsync(tmp.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(L)), dim3(kThreads), 0, s, int64_t(h.size()),
-                         1, int64_t(1), 1, L, tmp.p, pl->fb[0].p, 0, 1.0);
-      fft(pl.get(), pl->fb[0].p, dst, pl->fb[1].p, 1, -1.0);
-      HIPCHK(hipStreamSynchronize(s));
-    };
-    spectrum(emb, pl->chat.p);
-    // x = T^{-1} e_1 by CG with the FFT product (once per plan)
-    DevBuf<double> x, r, pv, q;
-    x.alloc(n);
-    r.alloc(n);
-    pv.alloc(n);
-    q.alloc(n);
-    HIPCHK(hipMemsetAsync(x.p, 0, sizeof(double) * n, s));
-    HIPCHK(hipMemsetAsync(r.p, 0, sizeof(double) * n, s));
-    const double one = 1.0;
-    HIPCHK(hipMemcpyAsync(r.p, &one, sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(pv.p, r.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    double rr = 1.0;
-    bool ok = false;
-    const int g = stream_grid(n);
-    for (int it = 0; it < 20000; ++it) {
-      toeplitz_apply<double>(pl.get(), pv.p, 1, q.p, 1, 1, 1.0, 0);
-      const double pq = device_dot(pl.get(), n, pv.p, q.p);
-      if (!(pq > 0.0)) return EXPMV_ENOTNEG;   // T not positive definite
-      const double alpha = rr / pq;
-      hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, alpha, pv.p, 1.0, x.p);
-      hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, -alpha, q.p, 1.0, r.p);
-      const double rr2 = device_dot(pl.get(), n, r.p, r.p);
-      if (std::sqrt(rr2) <= 1e-14) {
-        ok = true;
-        break;
-      }
-      hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, 1.0, r.p, rr2 / rr, pv.p);
-      rr = rr2;
-    }
-    if (!ok) return EXPMV_ENOCONV;
-    std::vector<double> xh(n);
-    HIPCHK(hipMemcpy(xh.data(), x.p, sizeof(double) * n, hipMemcpyDeviceToHost));
-    pl->x0 = xh[0];
-    if (!(pl->x0 > 0.0)) return EXPMV_ENOTNEG;
-    std::vector<double> xe(L, 0.0), ye(L, 0.0);
-    for (int64_t i = 0; i < n; ++i) xe[i] = xh[i];
-    for (int64_t i = 1; i < n; ++i) ye[i] = xh[n - i];   // Z x~ = [0, x_{n-1}, .., x_1]
-    spectrum(xe, pl->xhat.p);
-    spectrum(ye, pl->yhat.p);
+    expmv_status st = build_toeplitz(pl.get(), c, r);
+    if (st != EXPMV_OK) return st;
     *out = pl.release();
     return EXPMV_OK;
   });

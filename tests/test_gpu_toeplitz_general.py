@@ -1,0 +1,121 @@
+"""GPU parity of the nonsymmetric Toeplitz path (expmv_plan_toeplitz_general):
+the space-fractional diffusion matrix of the paper's large-n Toeplitz
+experiment (Section 5; beta = 1.8, d1 = 1, d2 = 3), products with T and T^T,
+the general Gohberg-Semencul inverse in both directions, whole solves against
+dense rational solves, and properties at the full workload size."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+import workloads as wl
+from oracle import exact, inverses
+from paper_1405_0707_amd import Plan, _lib
+from paper_1405_0707_amd._lib import ExpmvError
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def announce(name):
+    print(f"[gpu-test] {name}", flush=True)
+
+
+def plan(col, row, t, **opts):
+    return Plan.toeplitz(torch.from_numpy(col), t, device=DEV, row0=torch.from_numpy(row), **opts)
+
+
+@pytest.mark.parametrize("n,p", [(1000, 3), (1024, 2)])   # 1024: Strang-preconditioned set-up
+def test_operator_and_inverse_both_directions(n, p):
+    announce(f"fractional toeplitz operator/inverse n={n} p={p}")
+    col, row = wl.fractional_toeplitz(n)
+    T = sla.toeplitz(col, row)
+    t = 0.1
+    pl = plan(col, row, t)
+    X = np.random.default_rng(n).standard_normal((n, p))
+    for tr, Tm in ((False, T), (True, T.T)):
+        Y = pl.apply_operator(torch.from_numpy(X), transpose=tr).cpu().numpy()
+        ref = -t * (Tm @ X)
+        assert np.abs(Y - ref).max() <= 1e-12 * np.abs(ref).max()
+        Yi, _ = pl.apply_inverse(torch.from_numpy(X), transpose=tr)
+        refi = np.linalg.solve(-t * Tm, X)
+        assert rel(Yi.cpu().numpy(), refi) < 1e-9
+    # the GPU inverse agrees with the oracle's general Gohberg-Semencul form
+    Yo = inverses.gohberg_semencul_general(col, row, -t)(X)
+    Yi, _ = pl.apply_inverse(torch.from_numpy(X))
+    assert rel(Yi.cpu().numpy(), Yo) < 1e-9
+
+
+@pytest.mark.parametrize("n,p,m", [(500, 2, 10), (512, 2, 30)])   # 512: Strang set-up
+def test_execute_matches_dense_rational(n, p, m):
+    announce(f"fractional toeplitz execute n={n} p={p} m={m}")
+    col, row = wl.fractional_toeplitz(n)
+    T = sla.toeplitz(col, row)
+    t = 0.1
+    B = np.random.default_rng(6).standard_normal((n, p))
+    pl = plan(col, row, t, m=m, k=p * (m // 3))
+    Z, info = pl.execute(torch.from_numpy(B), tol=1e-11)
+    assert rel(Z.cpu().numpy(), exact.rational_dense(-t * T, B)) < 1e-10
+    Zt, _ = pl.execute(torch.from_numpy(B), tol=1e-11, transpose=True)
+    assert rel(Zt.cpu().numpy(), exact.rational_dense(-t * T.T, B)) < 1e-10
+    assert max(info.true_res) < 1e-8 * np.linalg.norm(B)
+
+
+def test_execute_at_1024_within_the_conditioning_floor():
+    """n = 1024: kappa(T) = 1.3e5 and e^{tA} keeps ~1e-3 of a random B, so
+    any FP64 evaluation of r(tA)B (the dense per-pole reference included) is
+    only determined to ~kappa eps |B|/|Z| ~ 1e-8 relative to |Z|; the GPU
+    result must agree with the reference to a tenth of that floor and to
+    1e-12 |B| absolutely."""
+    announce("fractional toeplitz execute n=1024 (conditioning floor)")
+    n = 1024
+    col, row = wl.fractional_toeplitz(n)
+    T = sla.toeplitz(col, row)
+    t = 0.1
+    B = np.random.default_rng(6).standard_normal((n, 2))
+    pl = plan(col, row, t, m=30, k=20)
+    Z, _ = pl.execute(torch.from_numpy(B), tol=1e-11)
+    ref = exact.rational_dense(-t * T, B)
+    Zh = Z.cpu().numpy()
+    floor = np.linalg.cond(T) * np.finfo(float).eps * np.linalg.norm(B) / np.linalg.norm(ref)
+    assert rel(Zh, ref) < 0.1 * floor
+    assert np.linalg.norm(Zh - ref) < 1e-12 * np.linalg.norm(B)
+
+
+def test_full_size_properties():
+    """n = 2^17, p = 2, m = 30 (the nonsymmetric Toeplitz workload): no dense
+    reference at this size; check what holds at any size: contraction (the
+    symmetric part of tA is negative definite, so ||e^{tA}||_2 <= 1), the
+    duality <W, e^{tA} B> = <e^{tA^T} W, B>, and a sampled residual of the
+    Gohberg-Semencul inverse (T (T^{-1} V) = V)."""
+    W6 = wl.c6()
+    announce(f"fractional toeplitz full n={W6.n}")
+    pl = plan(W6.col, W6.row, W6.t, m=W6.m, k=W6.k)
+    B = torch.from_numpy(W6.B).to(DEV)
+    Z, info = pl.execute(B, tol=W6.tol)
+    print(f"fractional full: cycles {info.cycles} err_bound {info.err_bound:.2e} "
+          f"ms {info.ms_total:.1f}", flush=True)
+    assert bool(torch.all(torch.linalg.norm(Z, dim=0) <= torch.linalg.norm(B, dim=0)))
+    G = torch.from_numpy(np.random.default_rng(66).standard_normal((W6.n, W6.p))).to(DEV)
+    ZG, _ = pl.execute(G, tol=W6.tol, transpose=True)
+    lhs, rhs = float(torch.sum(G * Z)), float(torch.sum(ZG * B))
+    assert abs(lhs - rhs) <= 1e-9 * abs(lhs)
+    V = torch.from_numpy(np.random.default_rng(67).standard_normal((W6.n, 2))).to(DEV)
+    Y, _ = pl.apply_inverse(V)
+    R = pl.apply_operator(Y) - V
+    assert float(torch.linalg.norm(R) / torch.linalg.norm(V)) < 1e-8
+
+
+def test_general_toeplitz_errors():
+    announce("fractional toeplitz errors")
+    col, row = wl.fractional_toeplitz(64)
+    with pytest.raises(ExpmvError) as e:
+        plan(-col, -row, 0.1)
+    assert e.value.status == _lib.ENOTNEG
+    with pytest.raises(ExpmvError) as e:
+        plan(col, row, -0.1)
+    assert e.value.status == _lib.ENOTNEG
