@@ -179,6 +179,22 @@ def run_suite(dev, vardiff_n):
     res["toeplitz_2^20_p16_fp64"] = {"s": round(el, 4), "cycles": info.cycles,
                                      "err_bound": info.err_bound}
     del pl, B, Z
+    # nonsymmetric fractional-diffusion Toeplitz 2^17, p = 2, m = 30: forward
+    # and adjoint (e^{tA^T} G and grad_t), FP64
+    W = wl.c6()
+    pl = Plan.toeplitz(torch.from_numpy(W.col), W.t, device=dev, row0=torch.from_numpy(W.row),
+                       m=W.m, k=W.k)
+    B = torch.from_numpy(W.B).to(dev)
+    G = torch.from_numpy(wl.gaussian_block(W.n, W.p, 106)).to(dev)
+    el_f, (Z, info_f) = timed(lambda: pl.execute(B, tol=W.tol), "fractional toeplitz fwd")
+    el_b, (gB, gt, info_b) = timed(lambda: pl.adjoint(G, B, tol=W.tol),
+                                   "fractional toeplitz adjoint")
+    res["fractional_toeplitz_2^17_p2_fp64"] = {"forward_s": round(el_f, 4),
+                                               "adjoint_s": round(el_b, 4),
+                                               "cycles_fwd": info_f.cycles,
+                                               "cycles_adj": info_b.cycles,
+                                               "err_bound": info_f.err_bound}
+    del pl, B, G, Z, gB
     # convection-diffusion 128^3, p = 16: FP64 (tol 1e-10) and mixed (tol 1e-6)
     W = wl.c4()
     print("[suite] convection-diffusion 128^3 built", file=sys.stderr, flush=True)
