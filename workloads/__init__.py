@@ -176,6 +176,52 @@ def fractional_toeplitz(n: int, beta: float = 1.8, d1: float = 1.0, d2: float = 
     return -col * scale, -row * scale
 
 
+@dataclasses.dataclass
+class SourceProblem:
+    """u'(s) = A u(s) + e^{gamma s} b, u(0) = u0, with A = -diag(d) T and T
+    the Toeplitz matrix given by its first column and first row."""
+    n: int
+    col: np.ndarray
+    row: np.ndarray
+    d: np.ndarray
+    u0: np.ndarray       # n x p
+    b: np.ndarray        # n x p
+    gamma: float
+    t: float
+    x: np.ndarray        # interior nodes
+
+    def dense_A(self) -> np.ndarray:
+        import scipy.linalg as sla
+        return -self.d[:, None] * sla.toeplitz(self.col, self.row)
+
+
+def fractional_source(n: int, beta: float = 1.7, t: float = 1.0) -> SourceProblem:
+    """One-sided fractional diffusion with a source (Section 5, Example 5.3):
+    u_t = d(x) D_+^beta u + q(x, t) on (0, 1), u(0, t) = 0, u(1, t) = e^{-t},
+    u(x, 0) = x^3, d(x) = Gamma(4 - beta)/6 x^{1+beta},
+    q(x, t) = -(1 + x) e^{-t} x^3 (exact solution e^{-t} x^3).
+    Shifted Gruenwald formula on the nodes x_i = i h, h = 1/(n+1):
+    (D_+^beta u)(x_i) ~ h^{-beta} sum_{k=0}^{i+1} g_k u_{i-k+1}, so
+    A = h^{-beta} diag(d) G with G_ij = g_{i-j+1} (lower Hessenberg), and the
+    source is e^{-s} b with b_i = -(1 + x_i) x_i^3, plus the boundary value
+    u_{n+1} = e^{-s} entering row n as d(x_n) h^{-beta} g_0.
+    Returned as A = -diag(d) T with T = -h^{-beta} G (col, row: T's first
+    column and row), gamma = -1."""
+    g = grunwald_weights(beta, n + 1)
+    h = 1.0 / (n + 1)
+    hb = h ** (-beta)
+    x = h * np.arange(1, n + 1)
+    d = math.gamma(4.0 - beta) / 6.0 * x ** (1.0 + beta)
+    col = -hb * g[1:n + 1]
+    row = np.zeros(n)
+    row[0] = -hb * g[1]
+    if n > 1:
+        row[1] = -hb * g[0]
+    b = -(1.0 + x) * x ** 3
+    b[-1] += d[-1] * hb * g[0]
+    return SourceProblem(n, col, row, d, (x ** 3)[:, None].copy(), b[:, None].copy(), -1.0, t, x)
+
+
 def gaussian_block(n: int, p: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((n, p))
 
