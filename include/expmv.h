@@ -160,19 +160,24 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr,
 expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t,
                                  const expmv_opts* opts, hipStream_t stream, expmv_plan* out);
 
-/* Plan for A = -T with T a general (nonsymmetric) Toeplitz matrix given by
- * its first column col0 and first row row0 (device, n values each; row0[0]
- * is ignored, row0 = NULL means T symmetric), tA = -t T with t > 0; T's
- * symmetric part should be positive definite (e.g. the space-fractional
- * diffusion matrices of Section 5).  Products with T and T^T use length-2n
- * circulant embeddings; (tA)^{-1} and its transpose use the Gohberg-Semencul
- * formula with x = T^{-1} e_1 and y = T^{-1} e_n, solved once at plan
- * creation (BiCGStab with the FFT product, preconditioned by T's Strang
- * circulant when n is a power of two).  Errors as expmv_plan_csr; ENOCONV if
- * those set-up solves do not reach a relative residual of 1e-10. */
+/* Plan for A = -diag(d) T with T a general (nonsymmetric) Toeplitz matrix
+ * given by its first column col0 and first row row0 (device, n values each;
+ * row0[0] is ignored, row0 = NULL means T symmetric) and d = diag (device, n
+ * positive values; NULL means d = 1), tA = -t diag(d) T with t > 0.  T's
+ * symmetric part should be positive definite: the space-fractional diffusion
+ * matrices of Section 5 (Example 5.4: d = 1; Example 5.3: a variable
+ * diffusion coefficient d(x) times a one-sided Gruenwald matrix).  Products
+ * with T and T^T use length-2n circulant embeddings, scaled by d on the
+ * output (input, transposed); (tA)^{-1} = -(1/t) T^{-1} diag(1/d) and its
+ * transpose use the Gohberg-Semencul formula with x = T^{-1} e_1 and
+ * y = T^{-1} e_n, solved once at plan creation (CG for symmetric T, else
+ * BiCGStab with the FFT product, preconditioned by T's Strang circulant when
+ * n is a power of two).  The plan copies col0, row0 and diag.  Errors as
+ * expmv_plan_csr (ENOTNEG also for a d_i <= 0); ENOCONV if those set-up
+ * solves do not reach a relative residual of 1e-10. */
 expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const double* row0,
-                                         double t, const expmv_opts* opts, hipStream_t stream,
-                                         expmv_plan* out);
+                                         const double* diag, double t, const expmv_opts* opts,
+                                         hipStream_t stream, expmv_plan* out);
 
 /* Z = e^{tA} B (transpose = 0) or Z = e^{tA^T} B (transpose = 1), p = block
  * width (1 <= p <= 32, p <= n), tol = stopping tolerance of opts.stop_rule.
@@ -196,6 +201,29 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
 expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* times, int nt,
                                  const double* B, int64_t p, double tol, double* Z,
                                  expmv_info* info);
+
+/* Linear ODE with an exponential source (Section 5, Example 5.3, gamma = -1):
+ * U = the solution at time t (the plan's t) of u' = A u + e^{gamma s} S,
+ * u(0) = U0, with both exponentials of its variation-of-constants form
+ * e^{tA}(U0 + W) - e^{gamma t} W, W = (A - gamma I)^{-1} S, taken in the CF
+ * form r of eq. 2.5:
+ *   U = r(tA) U0 + (r(tA) - r(gamma t) I) (A - gamma I)^{-1} S
+ *     = omega_0 U0 + Re sum_j c_j (tA - tau_j I)^{-1} (U0 + t / (tau_j - gamma t) S)
+ * (partial fractions of r), so no solve with A - gamma I is made and
+ * A - gamma I need not be invertible.  One run of the method on the joined
+ * n x 2p block [U0 | S] (the 7 shifted systems share one Krylov basis),
+ * which must have full column rank unless U0 or S is entirely zero (S = 0:
+ * the plain e^{tA} U0; U0 = 0: one run on S alone; otherwise rank loss ends
+ * in EBREAKDOWN); opts.k counts columns of the block the method runs on.  transpose = 1 uses A^T.  U0, S, U:
+ * device n x p blocks, 1 <= p <= 16, 2p <= n; U may not overlap U0 or S.
+ * tol bounds the estimated error of U relative to ||U||_F (opts.stop_rule
+ * as in expmv_execute, the paper rule on the joined block).  info as
+ * expmv_execute (znorm = ||U||_F; est and true_res refer to the joined
+ * block).  EINVAL for a non-finite gamma, U0 = S = 0 or bad sizes; other
+ * statuses as expmv_execute. */
+expmv_status expmv_execute_source(expmv_plan plan, int transpose, const double* U0,
+                                  const double* S, int64_t p, double gamma, double tol, double* U,
+                                  expmv_info* info);
 
 /* *out (host) = <G, A Z> = sum_ij G_ij (A Z)_ij: the derivative of
  * <G, e^{tA}B> with respect to t when Z = e^{tA}B (d/dt e^{tA}B = A e^{tA}B).

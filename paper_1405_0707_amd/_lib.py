@@ -50,6 +50,7 @@ EXPORTS = [
     "expmv_apply_preconditioner", "expmv_host_amg_build", "expmv_host_amg_levels",
     "expmv_host_amg_level", "expmv_host_amg_coarse_inverse", "expmv_host_amg_destroy",
     "expmv_execute_times", "expmv_last_error_detail", "expmv_plan_toeplitz_general",
+    "expmv_execute_source",
 ]
 
 _lib = None
@@ -68,7 +69,7 @@ def lib():
     L.expmv_default_opts.argtypes = [C.POINTER(Opts)]
     L.expmv_plan_csr.argtypes = [i64, i64, vp, vp, vp, dbl, C.POINTER(Opts), vp, C.POINTER(vp)]
     L.expmv_plan_toeplitz.argtypes = [i64, vp, dbl, C.POINTER(Opts), vp, C.POINTER(vp)]
-    L.expmv_plan_toeplitz_general.argtypes = [i64, vp, vp, dbl, C.POINTER(Opts), vp,
+    L.expmv_plan_toeplitz_general.argtypes = [i64, vp, vp, vp, dbl, C.POINTER(Opts), vp,
                                               C.POINTER(vp)]
     L.expmv_execute.argtypes = [vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
     L.expmv_grad_t.argtypes = [vp, vp, vp, i64, C.POINTER(dbl)]
@@ -88,6 +89,7 @@ def lib():
     L.expmv_block_toeplitz.argtypes = [i64, vp, vp, i64, dbl, dbl, vp, vp]
     L.expmv_apply_preconditioner.argtypes = [vp, i32, vp, i64, vp]
     L.expmv_execute_times.argtypes = [vp, i32, vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
+    L.expmv_execute_source.argtypes = [vp, i32, vp, vp, i64, dbl, dbl, vp, C.POINTER(Info)]
     L.expmv_host_amg_build.argtypes = [i64, vp, vp, vp, i32, dbl, i32, C.POINTER(vp)]
     L.expmv_host_amg_levels.argtypes = [vp]
     L.expmv_host_amg_level.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]

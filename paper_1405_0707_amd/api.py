@@ -49,9 +49,11 @@ def _dev_f64(x, device) -> torch.Tensor:
 @dataclasses.dataclass
 class Toeplitz:
     """Toeplitz T given by its first column (and first row when T is not
-    symmetric); the exponent is t * (-T)."""
+    symmetric), optionally with a positive row scaling d; the exponent is
+    t * (-diag(d) T)."""
     col0: torch.Tensor
     row0: torch.Tensor | None = None
+    diag: torch.Tensor | None = None
 
 
 class Plan:
@@ -79,23 +81,26 @@ class Plan:
         return cls(h, n, rowptr.device, float(t))
 
     @classmethod
-    def toeplitz(cls, col0, t: float, device="cuda", row0=None, **opts):
-        """A = -T with T Toeplitz: first column col0, first row row0 (None:
-        T symmetric)."""
+    def toeplitz(cls, col0, t: float, device="cuda", row0=None, diag=None, **opts):
+        """A = -diag(d) T with T Toeplitz: first column col0, first row row0
+        (None: T symmetric), d = diag (None: d = 1)."""
         col0 = _dev_f64(col0, device)
         o = default_opts(**opts)
         h = C.c_void_p()
-        if row0 is None:
+        if row0 is None and diag is None:
             st = lib().expmv_plan_toeplitz(col0.numel(), col0.data_ptr(), float(t), C.byref(o),
                                            _stream_ptr(col0.device), C.byref(h))
             check(st, "expmv_plan_toeplitz")
             return cls(h, col0.numel(), col0.device, float(t))
-        row0 = _dev_f64(row0, device)
-        st = lib().expmv_plan_toeplitz_general(col0.numel(), col0.data_ptr(), row0.data_ptr(),
+        row0 = None if row0 is None else _dev_f64(row0, device)
+        diag = None if diag is None else _dev_f64(diag, device)
+        st = lib().expmv_plan_toeplitz_general(col0.numel(), col0.data_ptr(),
+                                               None if row0 is None else row0.data_ptr(),
+                                               None if diag is None else diag.data_ptr(),
                                                float(t), C.byref(o), _stream_ptr(col0.device),
                                                C.byref(h))
         check(st, "expmv_plan_toeplitz_general")
-        return cls(h, col0.numel(), col0.device, float(t), keepalive=(row0,))
+        return cls(h, col0.numel(), col0.device, float(t))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -132,6 +137,24 @@ class Plan:
                                        B.shape[1], float(tol), Z.data_ptr(), C.byref(info))
         check(st, "expmv_execute_times", allow)
         return Z, info
+
+    def execute_source(self, U0: torch.Tensor, S: torch.Tensor, gamma: float,
+                       tol: float = 1e-10, transpose: bool = False, allow=()):
+        """U = solution at the plan's t of u' = A u + e^{gamma s} S, u(0) = U0,
+        with both exponentials in the CF form (one solve on [U0 | S])."""
+        U0 = _dev_f64(U0, self.device)
+        S = _dev_f64(S, self.device)
+        if U0.dim() == 1:
+            U0, S = U0[:, None], S[:, None]
+        if U0.shape != S.shape:
+            raise ValueError("U0 and S must have the same shape")
+        U = torch.empty_like(U0)
+        info = Info()
+        st = lib().expmv_execute_source(self._h, int(transpose), U0.data_ptr(), S.data_ptr(),
+                                        U0.shape[1], float(gamma), float(tol), U.data_ptr(),
+                                        C.byref(info))
+        check(st, "expmv_execute_source", allow)
+        return U, info
 
     def grad_t(self, G: torch.Tensor, Z: torch.Tensor) -> float:
         G = _dev_f64(G, self.device)
@@ -253,7 +276,7 @@ def cf_table():
 
 def _make_plan(A, t, device, opts):
     if isinstance(A, Toeplitz):
-        return Plan.toeplitz(A.col0, t, device=device, row0=A.row0, **opts)
+        return Plan.toeplitz(A.col0, t, device=device, row0=A.row0, diag=A.diag, **opts)
     if isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr:
         return Plan.csr(A.crow_indices(), A.col_indices(), A.values(), t, device=device, **opts)
     rowptr, colind, val = A

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -174,9 +175,12 @@ struct expmv_plan_s {
   // nonsymmetric T: spectrum of the embedding of T^T, and of the generators
   // J y, Z y (y = T^{-1} e_n) beside x and Z J x (xhat, yhat)
   DevBuf<cplx> chatT, jyhat, zyhat;
+  bool tsym = true;              // T symmetric (A = -diag(d) T symmetric needs d = 1 too)
+  DevBuf<double> tdiag, tdinv;   // d and 1/d of A = -diag(d) T (empty: d = 1)
   DevBuf<cplx> fb[4];            // L x q work arrays
   int fq = 0;                    // complex columns the work arrays hold
   DevBuf<double> kx;             // n x 14p (Toeplitz true residual)
+  DevBuf<double> srcB;           // n x 2p joined block [U0 | S] (source-term solves)
   // CF table on the device
   DevBuf<double> tau_re, tau_im, c_re, c_im;
   Workspace ws;
@@ -323,7 +327,7 @@ Csr<float> csr_of<float>(expmv_plan_s* pl, int transpose) {
 // Y = K X (K = -tA, or its transpose) for n x p blocks of type T.
 template <typename T>
 void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy, int p,
-                    double scale, int accumulate, int transpose = 0);
+                    double scale, int accumulate, int transpose = 0, bool with_diag = true);
 template <typename T>
 void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, double scale);
 
@@ -663,21 +667,16 @@ InnerResult apply_inverse(expmv_plan_s* pl, int transpose, const T* V, T* Wout, 
 // -------------------------------------------------------------------------
 // Toeplitz operator (FFT circulant embedding) and Gohberg-Semencul inverse
 
+// Radices of a length-L transform: 8s, then 4 or 2 for the rest of the
+// power of two, then 5s and 3s; empty when L has another prime factor.
 std::vector<int> fft_radices(int64_t L) {
   std::vector<int> r;
-  while (L % 8 == 0 && L > 4) {
-    r.push_back(8);
-    L /= 8;
-  }
-  while (L > 1) {
-    if (L % 4 == 0) {
-      r.push_back(4);
-      L /= 4;
-    } else {
-      r.push_back(2);
-      L /= 2;
+  for (int R : {8, 4, 2, 5, 3})
+    while (L % R == 0) {
+      r.push_back(R);
+      L /= R;
     }
-  }
+  if (L != 1) r.clear();
   return r;
 }
 
@@ -700,6 +699,10 @@ void fft_len(expmv_plan_s* pl, int64_t L, const std::vector<int>& radices, const
       hipLaunchKernelGGL(k_fft_pass<8>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
     else if (R == 4)
       hipLaunchKernelGGL(k_fft_pass<4>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
+    else if (R == 5)
+      hipLaunchKernelGGL(k_fft_pass<5>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
+    else if (R == 3)
+      hipLaunchKernelGGL(k_fft_pass<3>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
     else
       hipLaunchKernelGGL(k_fft_pass<2>, dim3(grid), dim3(kThreads), 0, pl->stream, L, q, Ns, src, dst, sign);
     src = dst;
@@ -718,24 +721,26 @@ void ensure_fft_buffers(expmv_plan_s* pl, int q) {
   pl->fq = q;
 }
 
-// Y (n x p, ld) = scale * T X (X n x p, ld) through the circulant embedding
+// Y (n x p, ld) (+)= scale * (K / t) X through the circulant embedding, K / t
+// = diag(d) T, or T^T diag(d) when transposed (with_diag = false: T, T^T)
 template <typename T>
 void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy, int p,
-                    double scale, int accumulate, int transpose) {
-  const cplx* sym = (transpose && !pl->symmetric) ? pl->chatT.p : pl->chat.p;
+                    double scale, int accumulate, int transpose, bool with_diag) {
+  const cplx* sym = (transpose && !pl->tsym) ? pl->chatT.p : pl->chat.p;
+  const double* dg = with_diag ? pl->tdiag.p : nullptr;
   const int q = (p + 1) / 2;
   ensure_fft_buffers(pl, q);
   const int64_t L = pl->L, n = pl->n;
   cplx *A = pl->fb[0].p, *Bf = pl->fb[1].p, *C = pl->fb[2].p;
   hipStream_t s = pl->stream;
   hipLaunchKernelGGL((k_pack<T>), dim3(stream_grid(L * q)), dim3(kThreads), 0, s, n, p, ldx, q, L,
-                     X, A, 0, 1.0);
+                     X, A, 0, 1.0, transpose ? dg : nullptr);
   fft(pl, A, Bf, C, q, -1.0);
   hipLaunchKernelGGL(k_spec_mul, dim3(stream_grid(L * q)), dim3(kThreads), 0, s, L, q, Bf, sym,
                      scale / double(L));
   fft(pl, Bf, A, C, q, +1.0);
   hipLaunchKernelGGL((k_unpack<T>), dim3(stream_grid(n * p)), dim3(kThreads), 0, s, n, p, ldy, q, A,
-                     Y, 0, 1.0, accumulate);
+                     Y, 0, 1.0, accumulate, transpose ? nullptr : dg);
 }
 
 // W = scale * T^{-1} V (or T^{-T} V) by the Gohberg-Semencul formula
@@ -744,14 +749,17 @@ void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy
 // x = T^{-1} e_1, y = T^{-1} e_n (symmetric T: y = J x), L(h)^T v =
 // rev(L(h) rev(v)); with spectra a1, a2 for the two transposed factors and
 // b1, b2 for the lower ones: W = (L(b1) L(a1)^T - L(b2) L(a2)^T) V / x0.
-// Six length-L FFTs per block.
+// Six length-L FFTs per block.  With A = -diag(d) T the inverse of K / t is
+// T^{-1} diag(1/d) (1/d scales V's rows on packing), transposed
+// diag(1/d) T^{-T} (1/d scales W's rows on unpacking).
 template <typename T>
 void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, double scale) {
-  const bool tr = transpose && !pl->symmetric;
+  const bool tr = transpose && !pl->tsym;
   const cplx* gx = pl->xhat.p;                                // x
   const cplx* gzjx = pl->yhat.p;                              // Z J x
-  const cplx* gjy = pl->symmetric ? pl->xhat.p : pl->jyhat.p;  // J y
-  const cplx* gzy = pl->symmetric ? pl->yhat.p : pl->zyhat.p;  // Z y
+  const cplx* gjy = pl->tsym ? pl->xhat.p : pl->jyhat.p;       // J y
+  const cplx* gzy = pl->tsym ? pl->yhat.p : pl->zyhat.p;       // Z y
+  const double* di = pl->tdinv.p;
   const cplx* a1 = tr ? gx : gjy;
   const cplx* a2 = tr ? gzy : gzjx;
   const cplx* b1 = tr ? gjy : gx;
@@ -764,7 +772,7 @@ void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, doub
   const int g = stream_grid(L * q);
   const double inv = 1.0 / double(L);
   hipLaunchKernelGGL((k_pack<T>), dim3(g), dim3(kThreads), 0, s, n, p, int64_t(p), q, L, V, A, 1,
-                     1.0);
+                     1.0, transpose ? nullptr : di);
   fft(pl, A, Bf, C, q, -1.0);                                   // B = F rev(V)
   hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, a1, C, inv);
   hipLaunchKernelGGL(k_spec_mul_to, dim3(g), dim3(kThreads), 0, s, L, q, Bf, a2, D, inv);
@@ -777,7 +785,7 @@ void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, doub
   hipLaunchKernelGGL(k_spec_mul2, dim3(g), dim3(kThreads), 0, s, L, q, A, b1, C, b2, Bf, inv);
   fft(pl, Bf, A, C, q, +1.0);
   hipLaunchKernelGGL((k_unpack<T>), dim3(stream_grid(n * p)), dim3(kThreads), 0, s, n, p,
-                     int64_t(p), q, A, W, 0, scale / pl->x0, 0);
+                     int64_t(p), q, A, W, 0, scale / pl->x0, 0, transpose ? di : nullptr);
 }
 
 double device_dot(expmv_plan_s* pl, int64_t len, const double* x, const double* y) {
@@ -824,7 +832,7 @@ OrthLaunch orth_config(int64_t n, int p, int npan, int O, size_t elem) {
 // in ws.partial (0 when the mode writes no partials).
 template <typename T>
 int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* Win, T* Wout,
-              const double* C) {
+              const double* C, const int* gate = nullptr) {
   const bool proj = (mode == kProj || mode == kUpdProj);
   const bool gram = (mode == kUpdGram || mode == kScaleGram);
   const bool use_v = (mode == kProj || mode == kUpdProj || mode == kUpdGram);
@@ -839,7 +847,7 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
     const int MBW = nmb <= 8 ? 2 : (nmb <= 16 ? 4 : 6);
     const bool upd = (mode == kUpdProj || mode == kUpdGram);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (pl->opts.profile > 0 && pl->oev_used + 2 <= int(pl->oev.size())) {
+    if (pl->opts.profile > 0 && !gate && pl->oev_used + 2 <= int(pl->oev.size())) {
       e0 = pl->oev[pl->oev_used];
       e1 = pl->oev[pl->oev_used + 1];
       pl->oev_used += 2;
@@ -848,7 +856,7 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
     }
 #define ORTH_MMA(NB_, MBW_)                                                                     \
   hipExtLaunchKernelGGL((k_orth_mma<T, NB_, MBW_>), dim3(grid), dim3(kThreads), 0, pl->stream,     \
-                        e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C, pl->ws.partial.p)
+                        e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C, pl->ws.partial.p, gate)
     if (NB == 1) {
       if (MBW == 2) ORTH_MMA(1, 2);
       else if (MBW == 4) ORTH_MMA(1, 4);
@@ -865,7 +873,7 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth<T>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)));
   hipLaunchKernelGGL(k_orth<T>, dim3(L.nwg), dim3(kThreads), L.lds, pl->stream, mode, pl->n, p, V,
-                     npv, Win, Wout, C, pl->ws.partial.p, L.TR, L.rows_per_wg);
+                     npv, Win, Wout, C, pl->ws.partial.p, L.TR, L.rows_per_wg, gate);
   return (proj || gram) ? L.nwg : 0;
 }
 
@@ -902,18 +910,26 @@ void orthonormalize(expmv_plan_s* pl, int p, const T* Vb, int npan, T* W, T* Vou
     int nwg = orth_pass<T>(pl, kUpdGram, p, static_cast<const T*>(nullptr), 0, W, Wt, nullptr);
     reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
   }
+  // shift of the fallback (shifted Cholesky QR): 11 (n p + p (p + 1)) u
+  // times trace(G), u = 2^-53 (the Gram matrices are FP64)
+  const double shift_rel = 11.0 * (double(pl->n) * p + double(p) * (p + 1)) * 0x1p-53;
   hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R1.p, w.Rinv.p,
-                     npan > 0 ? w.w0.p : nullptr, npan > 0 ? 1 : 0, nullptr, nullptr, 0, 0, 0,
+                     npan > 0 ? w.w0.p : nullptr, 1, nullptr, nullptr, 0, 0, 0, shift_rel,
                      w.flags.p);
   int nwg = orth_pass<T>(pl, kScaleGram, p, static_cast<const T*>(nullptr), 0, Wt, Wt, w.Rinv.p);
   reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
-  if (H != nullptr) {
-    hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
-                       nullptr, 2, w.R1.p, H, ldh, npan * p, col0, w.flags.p);
-  } else {
-    hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
-                       nullptr, 2, w.R1.p, Rhat, p, 0, 0, w.flags.p);
-  }
+  double* Hb = H != nullptr ? H : Rhat;
+  const int ldb = H != nullptr ? ldh : p;
+  const int hr = H != nullptr ? npan * p : 0, hc = H != nullptr ? col0 : 0;
+  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
+                     nullptr, 2, w.R1.p, Hb, ldb, hr, hc, 0.0, w.flags.p);
+  // third pass, only after a shifted first factor (flags[2]; the kernels
+  // return at once otherwise)
+  const int* gate = w.flags.p + 2;
+  nwg = orth_pass<T>(pl, kScaleGram, p, static_cast<const T*>(nullptr), 0, Wt, Wt, w.Rinv.p, gate);
+  reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
+  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R1.p, w.Rinv.p,
+                     nullptr, 3, nullptr, Hb, ldb, hr, hc, 0.0, w.flags.p);
   orth_pass<T>(pl, kScale, p, static_cast<const T*>(nullptr), 0, Wt, Vout, w.Rinv.p);
 }
 
@@ -1125,6 +1141,19 @@ InnerResult apply_inverse_mixed(expmv_plan_s* pl, int transpose, const T* V, T* 
   return total;
 }
 
+// Source-term mode: a single time; Z receives
+//   U = r(M) U0 + (r(M) - r(sigma)) t (M - sigma I)^{-1} S
+//     = omega_0 U0 + Re sum_j c_j (M - tau_j I)^{-1} (U0 + t / (tau_j - sigma) S),
+// the solution at time t of u' = A u + e^{gamma s} S, u(0) = U0, with both
+// exponentials in the CF form (sigma = gamma t; partial fractions of r).
+// B is the joined n x 2p' block [U0 | S] (p = 2p', Z n x p'), or S alone
+// when U0 = 0 (s_only: Z = Re sum_j s_j X_j, no omega_0 term).
+struct SourceMode {
+  double sigma;
+  double t;
+  bool s_only;
+};
+
 // Z_q = r(s_q M) B for the scale factors s_q > 0 of `scales` (M = tA of the
 // plan; Z_q is the q-th n x p block of Z).  Since r(s M) B = omega_0 B +
 // Re sum_j (c_j / s)(M - (tau_j / s) I)^{-1} B, every time adds 7 shifted
@@ -1133,7 +1162,8 @@ InnerResult apply_inverse_mixed(expmv_plan_s* pl, int transpose, const T* V, T* 
 // and the solution updates run over all 7 nt shifts.
 template <typename T, typename TI>
 expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
-                          double* Z, expmv_info* info, const std::vector<double>& scales) {
+                          double* Z, expmv_info* info, const std::vector<double>& scales,
+                          const SourceMode* src) {
   hipStream_t s = pl->stream;
   ensure_workspace(pl, p);
   Workspace& w = pl->ws;
@@ -1159,7 +1189,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     w.rho.alloc(ns);
     w.singular.alloc(ns);
     w.taus.alloc(2 * size_t(ns));
-    w.coefs.alloc(2 * size_t(ns));
+    w.coefs.alloc(4 * size_t(ns));
     if (pl->opts.inner_relax) {
       w.Cr2.alloc(size_t(ldh) * 2 * ns * p);
       w.S2.alloc(size_t(ns) * p * p);
@@ -1178,12 +1208,25 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     }
   HIPCHK(hipMemcpyAsync(w.taus.p, tau_h.data(), sizeof(double) * tau_h.size(),
                         hipMemcpyHostToDevice, s));
+  // source mode: s_j = c_j t / (tau_j - sigma), the coefficients of the S part
+  double s_re[kNShift] = {0}, s_im[kNShift] = {0};
+  if (src) {
+    coef_h.resize(4 * size_t(ns));
+    for (int j = 0; j < kNShift; ++j) {
+      const std::complex<double> cj(CF_C_RE[j], CF_C_IM[j]), tj(CF_TAU_RE[j], CF_TAU_IM[j]);
+      const std::complex<double> sj = cj * src->t / (tj - src->sigma);
+      s_re[j] = coef_h[2 * ns + j] = sj.real();
+      s_im[j] = coef_h[3 * ns + j] = sj.imag();
+    }
+  }
   HIPCHK(hipMemcpyAsync(w.coefs.p, coef_h.data(), sizeof(double) * coef_h.size(),
                         hipMemcpyHostToDevice, s));
   const double* tau_re_d = w.taus.p;
   const double* tau_im_d = w.taus.p + ns;
   const double* c_re_d = w.coefs.p;
   const double* c_im_d = w.coefs.p + ns;
+  const double* s_re_d = w.coefs.p + 2 * ns;
+  const double* s_im_d = w.coefs.p + 3 * ns;
   const double t_start = host_now_ms();
   expmv_info inf{};
   double ms_apply = 0, ms_orth = 0, ms_small = 0, ms_update = 0;
@@ -1193,10 +1236,14 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   pl->oev_used = 0;
   pl->oev_bytes.clear();
 
-  double c_re[kNShift], c_im[kNShift], delta[kNShift];
+  // bound weights: |c_j| (source mode: |(c_j, s_j)|, since the two parts'
+  // errors E, E' give |c_j E + s_j E'| <= |(c_j, s_j)| ||(E, E')||_F; S
+  // alone: |s_j|)
+  double cw[kNShift], delta[kNShift];
   for (int j = 0; j < kNShift; ++j) {
-    c_re[j] = CF_C_RE[j];
-    c_im[j] = CF_C_IM[j];
+    cw[j] = std::hypot(CF_C_RE[j], CF_C_IM[j]);
+    if (src && src->s_only) cw[j] = std::hypot(s_re[j], s_im[j]);
+    else if (src) cw[j] = std::hypot(cw[j], std::hypot(s_re[j], s_im[j]));
     delta[j] = CF_TAU_RE[j] >= 0.0 ? std::hypot(CF_TAU_RE[j], CF_TAU_IM[j]) : std::fabs(CF_TAU_IM[j]);
   }
 
@@ -1207,12 +1254,16 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
 
   const int cgrid = 512;
   std::vector<double> part(size_t(cgrid) * nt);
-  // ||B||_F (k_combine with X = 0 and omega0 = 1 writes B to Z and its norm)
-  hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, ldx, 1.0,
-                     c_re_d, c_im_d, Z, w.partial.p);
-  HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  {
+  // ||B||_F (k_combine with X = 0 and omega0 = 1 writes B to Z and its norm;
+  // in source mode Z is narrower than B)
+  if (src) {
+    inf.bnorm = std::sqrt(device_dot(pl, int64_t(blk), B, B));
+  } else {
+    hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, ldx, 1.0,
+                       c_re_d, c_im_d, Z, w.partial.p);
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
     double bb = 0.0;
     for (int i = 0; i < cgrid; ++i) bb += part[i];
     inf.bnorm = std::sqrt(bb);
@@ -1307,11 +1358,18 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     double t1 = host_now_ms();
     // X_j += V_{d+p} (H~ Z_j)  [Algorithm 1: V_d Z_j]
     panel_gemm<T, double>(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * ns, w.X.p, p, ldx, 1);
-    for (int q = 0; q < nt; ++q)
-      hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B,
-                         w.X.p + size_t(2 * kNShift * p) * q, ldx, double(CF_OMEGA0),
-                         c_re_d + kNShift * q, c_im_d + kNShift * q, Z + blk * q,
-                         w.partial.p + size_t(cgrid) * q);
+    if (src && src->s_only)
+      hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, ldx, 0.0,
+                         s_re_d, s_im_d, Z, w.partial.p);
+    else if (src)
+      hipLaunchKernelGGL(k_combine_source, dim3(cgrid), dim3(kThreads), 0, s, n, p / 2, B, w.X.p,
+                         ldx, double(CF_OMEGA0), c_re_d, c_im_d, s_re_d, s_im_d, Z, w.partial.p);
+    else
+      for (int q = 0; q < nt; ++q)
+        hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B,
+                           w.X.p + size_t(2 * kNShift * p) * q, ldx, double(CF_OMEGA0),
+                           c_re_d + kNShift * q, c_im_d + kNShift * q, Z + blk * q,
+                           w.partial.p + size_t(cgrid) * q);
     HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid * nt,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
@@ -1331,7 +1389,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       double bound = 0.0;
       for (int j = 0; j < kNShift; ++j) {
         const double r = rho[q * kNShift + j];
-        bound += std::hypot(c_re[j], c_im[j]) * r / delta[j];
+        bound += cw[j] * r / delta[j];
         rmax = std::max(rmax, r);
       }
       if (!(bound <= tol * zn)) conv_bound = false;
@@ -1491,10 +1549,13 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
 
 expmv_status dispatch_execute(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
                               double* Z, expmv_info* info,
-                              const std::vector<double>& scales = std::vector<double>{1.0}) {
-  if (pl->basis32) return execute_impl<float, float>(pl, transpose, B, p, tol, Z, info, scales);
-  if (pl->mixed) return execute_impl<double, float>(pl, transpose, B, p, tol, Z, info, scales);
-  return execute_impl<double, double>(pl, transpose, B, p, tol, Z, info, scales);
+                              const std::vector<double>& scales = std::vector<double>{1.0},
+                              const SourceMode* src = nullptr) {
+  if (pl->basis32)
+    return execute_impl<float, float>(pl, transpose, B, p, tol, Z, info, scales, src);
+  if (pl->mixed)
+    return execute_impl<double, float>(pl, transpose, B, p, tol, Z, info, scales, src);
+  return execute_impl<double, double>(pl, transpose, B, p, tol, Z, info, scales, src);
 }
 
 }  // namespace
@@ -1775,8 +1836,8 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
 
 // Host-driven Krylov solve T z = e_k with the FFT product: CG for symmetric
 // T; for general T BiCGStab, right-preconditioned by the inverse of T's
-// Strang circulant (first column c_0..c_{n/2}, r_{n/2-1}..r_1) when n is a
-// power of two (a length-n FFT), unpreconditioned otherwise.  Returns the
+// Strang circulant (first column c_0..c_{n/2}, r_{n/2-1}..r_1) when n has no
+// prime factor above 5 (a length-n FFT), unpreconditioned otherwise.  Returns the
 // true relative residual ||e_k - T z|| (z on the device).
 double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
                             const std::vector<double>& r, int64_t k, double* z) {
@@ -1793,7 +1854,7 @@ double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
   HIPCHK(hipMemcpyAsync(res + k, &one, sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   auto Tapply = [&](const double* in, double* outp) {
-    toeplitz_apply<double>(pl, in, 1, outp, 1, 1, 1.0, 0, 0);
+    toeplitz_apply<double>(pl, in, 1, outp, 1, 1, 1.0, 0, 0, false);
   };
   auto axpby = [&](double a, const double* xx, double b, double* yy) {
     hipLaunchKernelGGL(k_axpby, dim3(g), dim3(kThreads), 0, s, n, a, xx, b, yy);
@@ -1801,7 +1862,7 @@ double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
   auto copy = [&](const double* from, double* to) {
     HIPCHK(hipMemcpyAsync(to, from, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   };
-  if (pl->symmetric) {
+  if (pl->tsym) {
     copy(res, pv);
     double rr = 1.0;
     for (int it = 0; it < 20000; ++it) {
@@ -1817,12 +1878,11 @@ double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
       rr = rr2;
     }
   } else {
-    // Strang circulant preconditioner (n a power of two)
-    const bool pow2 = (n & (n - 1)) == 0 && n >= 4;
+    // Strang circulant preconditioner (n 2,3,5-smooth)
+    std::vector<int> rad_n = fft_radices(n);
+    const bool strang = !rad_n.empty() && n >= 4;
     DevBuf<cplx> inv_eig;
-    std::vector<int> rad_n;
-    if (pow2) {
-      rad_n = fft_radices(n);
+    if (strang) {
       std::vector<double> sc(n, 0.0);
       for (int64_t i = 0; i <= n / 2; ++i) sc[i] = c[i];
       for (int64_t i = n / 2 + 1; i < n; ++i) sc[i] = r[n - i];
@@ -1830,7 +1890,7 @@ double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
       scd.alloc(n);
       HIPCHK(hipMemcpyAsync(scd.p, sc.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
-                         int64_t(1), 1, n, scd.p, pl->fb[0].p, 0, 1.0);
+                         int64_t(1), 1, n, scd.p, pl->fb[0].p, 0, 1.0, nullptr);
       fft_len(pl, n, rad_n, pl->fb[0].p, pl->fb[1].p, pl->fb[2].p, 1, -1.0);
       std::vector<cplx> ev(n);
       HIPCHK(hipMemcpyAsync(ev.data(), pl->fb[1].p, sizeof(cplx) * n, hipMemcpyDeviceToHost, s));
@@ -1844,18 +1904,18 @@ double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
       HIPCHK(hipStreamSynchronize(s));
     }
     auto Papply = [&](const double* in, double* outp) {
-      if (!pow2) {
+      if (!strang) {
         copy(in, outp);
         return;
       }
       hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
-                         int64_t(1), 1, n, in, pl->fb[0].p, 0, 1.0);
+                         int64_t(1), 1, n, in, pl->fb[0].p, 0, 1.0, nullptr);
       fft_len(pl, n, rad_n, pl->fb[0].p, pl->fb[1].p, pl->fb[2].p, 1, -1.0);
       hipLaunchKernelGGL(k_spec_mul, dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
                          pl->fb[1].p, inv_eig.p, 1.0 / double(n));
       fft_len(pl, n, rad_n, pl->fb[1].p, pl->fb[0].p, pl->fb[2].p, 1, +1.0);
       hipLaunchKernelGGL((k_unpack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
-                         int64_t(1), 1, pl->fb[0].p, outp, 0, 1.0, 0);
+                         int64_t(1), 1, pl->fb[0].p, outp, 0, 1.0, 0, nullptr);
     };
     copy(res, rh);
     HIPCHK(hipMemsetAsync(pv, 0, sizeof(double) * n, s));
@@ -1913,7 +1973,8 @@ expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
     dst.alloc(L);
     HIPCHK(hipMemcpyAsync(tmp.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(L)), dim3(kThreads), 0, s,
-                       int64_t(h.size()), 1, int64_t(1), 1, L, tmp.p, pl->fb[0].p, 0, 1.0);
+                       int64_t(h.size()), 1, int64_t(1), 1, L, tmp.p, pl->fb[0].p, 0, 1.0,
+                       nullptr);
     fft(pl, pl->fb[0].p, dst.p, pl->fb[1].p, 1, -1.0);
     HIPCHK(hipStreamSynchronize(s));
   };
@@ -1923,7 +1984,7 @@ expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
   for (int64_t i = 0; i < n; ++i) emb[i] = c[i];
   for (int64_t i = 1; i < n; ++i) emb[L - i] = r[i];
   spectrum(emb, pl->chat);
-  if (!pl->symmetric) {
+  if (!pl->tsym) {
     std::fill(emb.begin(), emb.end(), 0.0);
     for (int64_t i = 0; i < n; ++i) emb[i] = r[i];
     for (int64_t i = 1; i < n; ++i) emb[L - i] = c[i];
@@ -1937,7 +1998,7 @@ expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
   HIPCHK(hipMemcpy(xh.data(), xd.p, sizeof(double) * n, hipMemcpyDeviceToHost));
   pl->x0 = xh[0];
   if (!(pl->x0 > 0.0)) return EXPMV_ENOTNEG;
-  if (pl->symmetric) {
+  if (pl->tsym) {
     yh.assign(xh.rbegin(), xh.rend());   // y = J x
   } else {
     yd.alloc(n);
@@ -1953,7 +2014,7 @@ expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
   };
   gen([&](int64_t i) { return xh[i]; }, pl->xhat);                            // x
   gen([&](int64_t i) { return i ? xh[n - i] : 0.0; }, pl->yhat);             // Z J x
-  if (!pl->symmetric) {
+  if (!pl->tsym) {
     gen([&](int64_t i) { return yh[n - 1 - i]; }, pl->jyhat);                 // J y
     gen([&](int64_t i) { return i ? yh[i - 1] : 0.0; }, pl->zyhat);          // Z y
   }
@@ -2028,12 +2089,12 @@ expmv_status expmv_plan_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const
 
 expmv_status expmv_plan_toeplitz(int64_t n, const double* col0, double t, const expmv_opts* opts,
                                  hipStream_t stream, expmv_plan* out) {
-  return expmv_plan_toeplitz_general(n, col0, nullptr, t, opts, stream, out);
+  return expmv_plan_toeplitz_general(n, col0, nullptr, nullptr, t, opts, stream, out);
 }
 
 expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const double* row0,
-                                         double t, const expmv_opts* opts, hipStream_t stream,
-                                         expmv_plan* out) {
+                                         const double* diag, double t, const expmv_opts* opts,
+                                         hipStream_t stream, expmv_plan* out) {
   if (!out) return EXPMV_EINVAL;
   *out = nullptr;
   if (n < 2 || n > (int64_t(1) << 28) || !col0) return EXPMV_EINVAL;
@@ -2052,6 +2113,15 @@ expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const do
     for (int64_t i = 0; i < n; ++i)
       if (!std::isfinite(c[i]) || !std::isfinite(r[i])) return EXPMV_EINVAL;
     if (!(c[0] > 0.0)) return EXPMV_ENOTNEG;
+    std::vector<double> dg;
+    if (diag) {
+      dg.resize(n);
+      HIPCHK(hipMemcpy(dg.data(), diag, sizeof(double) * n, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(dg[i])) return EXPMV_EINVAL;
+        if (!(dg[i] > 0.0)) return EXPMV_ENOTNEG;   // diag(tA) = -t d_i c_0 must be < 0
+      }
+    }
     std::unique_ptr<expmv_plan_s> pl(new expmv_plan_s());
     pl->kind = 1;
     pl->n = n;
@@ -2061,10 +2131,19 @@ expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const do
     pl->stream = stream;
     pl->mixed = (o.precision != EXPMV_FP64);
     pl->basis32 = (o.precision == EXPMV_MIXED);
-    pl->symmetric = (c == r);
+    pl->tsym = (c == r);
+    pl->symmetric = pl->tsym && !diag;
     init_plan_common(pl.get());
     expmv_status st = build_toeplitz(pl.get(), c, r);
     if (st != EXPMV_OK) return st;
+    if (diag) {
+      std::vector<double> di(n);
+      for (int64_t i = 0; i < n; ++i) di[i] = 1.0 / dg[i];
+      pl->tdiag.alloc(n);
+      pl->tdinv.alloc(n);
+      HIPCHK(hipMemcpy(pl->tdiag.p, dg.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(pl->tdinv.p, di.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    }
     *out = pl.release();
     return EXPMV_OK;
   });
@@ -2091,6 +2170,34 @@ expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* t
   }
   return guarded(
       [&]() { return dispatch_execute(plan, transpose, B, int(p), tol, Z, info, scales); });
+}
+
+expmv_status expmv_execute_source(expmv_plan plan, int transpose, const double* U0,
+                                  const double* S, int64_t p, double gamma, double tol, double* U,
+                                  expmv_info* info) {
+  if (!plan || !U0 || !S || !U || p < 1 || 2 * p > kMaxP || 2 * p > plan->n) return EXPMV_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0) || !std::isfinite(gamma)) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    const int64_t n = plan->n;
+    plan->ws.partial.alloc(4096);   // device_dot's partial sums
+    // an all-zero part would make the joined block rank deficient: S = 0 is
+    // the plain exponential, U0 = 0 runs on S alone
+    const double uu = device_dot(plan, n * p, U0, U0), ss = device_dot(plan, n * p, S, S);
+    if (!std::isfinite(uu) || !std::isfinite(ss) || !(uu + ss > 0.0)) return EXPMV_EINVAL;
+    if (ss == 0.0) return dispatch_execute(plan, transpose, U0, int(p), tol, U, info);
+    const SourceMode sm{gamma * plan->t, plan->t, uu == 0.0};
+    if (sm.s_only)
+      return dispatch_execute(plan, transpose, S, int(p), tol, U, info, std::vector<double>{1.0},
+                              &sm);
+    plan->srcB.alloc(size_t(n) * 2 * p);
+    // joined block [U0 | S]: row i holds U0's row i, then S's row i
+    HIPCHK(hipMemcpy2DAsync(plan->srcB.p, sizeof(double) * 2 * p, U0, sizeof(double) * p,
+                            sizeof(double) * p, n, hipMemcpyDeviceToDevice, plan->stream));
+    HIPCHK(hipMemcpy2DAsync(plan->srcB.p + p, sizeof(double) * 2 * p, S, sizeof(double) * p,
+                            sizeof(double) * p, n, hipMemcpyDeviceToDevice, plan->stream));
+    return dispatch_execute(plan, transpose, plan->srcB.p, int(2 * p), tol, U, info,
+                            std::vector<double>{1.0}, &sm);
+  });
 }
 
 expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, int64_t p,

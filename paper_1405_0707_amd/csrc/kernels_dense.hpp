@@ -26,7 +26,8 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_orth(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const T* __restrict__ W,
        T* __restrict__ Wout, const double* __restrict__ C, double* __restrict__ partial,
-       int TR, int64_t rows_per_wg) {
+       int TR, int64_t rows_per_wg, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // conditional pass not requested
   extern __shared__ double lds_d[];
   const int tid = threadIdx.x;
   const int np_cols = npan * p;
@@ -132,43 +133,72 @@ k_reduce_partials(const double* __restrict__ partial, int nwg, int O, double* __
   }
 }
 
+// Upper Cholesky factor of G + shift I into R (p x p, row-major): 0 = done,
+// 1 = done but some pivot is at most 1e-14 of its diagonal entry (a column
+// within an angle of about 1e-7 of the span of the earlier ones), 2 = a
+// pivot not above 1e-28 trace (or NaN).
+__device__ inline int chol_upper(int p, const double* __restrict__ G, double shift, double tr,
+                                 double* __restrict__ R) {
+  int st = 0;
+  for (int j = 0; j < p; ++j) {
+    const double gjj = G[j * p + j] + shift;
+    double djj = gjj;
+    for (int k = 0; k < j; ++k) djj -= R[k * p + j] * R[k * p + j];
+    if (!(djj > 1e-28 * tr)) return 2;
+    if (djj <= 1e-14 * gjj) st = 1;
+    const double rjj = sqrt(djj);
+    R[j * p + j] = rjj;
+    for (int i = j + 1; i < p; ++i) {
+      double s = G[j * p + i];
+      for (int k = 0; k < j; ++k) s -= R[k * p + j] * R[k * p + i];
+      R[j * p + i] = s / rjj;
+    }
+    for (int i = 0; i < j; ++i) R[j * p + i] = 0.0;
+  }
+  return st;
+}
+
 // Cholesky of the p x p Gram matrix G = R^T R (R upper) and R^{-1}.
 // stage 1 (after Gram-Schmidt): w0norm2 = ||W||_F^2 before projection; a
 //   trace(G) <= (1e-12)^2 * w0norm2 is an invariant subspace (happy
-//   breakdown): R = R^{-1} = 0 and flags[0] = 1; a non-positive pivot
-//   otherwise sets flags[1] (rank-deficient block).
-// stage 2: H(jrow.., jcol..) = R2 * R1 (R1 from stage 1 in Rprev).
+//   breakdown): R = R^{-1} = 0 and flags[0] = 1 (w0norm2 = NULL: the
+//   initial QR, no such test).  A block that plain
+//   Cholesky QR cannot resolve (a nearly collinear column, chol_upper 1 or
+//   2) is factored as G + shift trace(G) I instead (shifted Cholesky QR,
+//   Fukaya, Kannan, Nakatsukasa, Yamamoto and Yanagisawa, SIAM J. Sci.
+//   Comput. 42 (2020)) and flags[2] = 1 requests a third pass; flags[2] = 0
+//   otherwise; a failure even then sets flags[1] (rank-deficient block).
+// stage 2: H(hrow.., hcol..) = R2 * R1 (R1 from stage 1 in Rprev).
+// stage 3 (runs only when flags[2] = 1): the third pass's factor; the H
+//   block becomes R3 * (H block).
 __global__ void k_cholqr_factor(int p, const double* __restrict__ G, double* __restrict__ R,
                                 double* __restrict__ Rinv, const double* __restrict__ w0norm2,
                                 int stage, const double* __restrict__ Rprev,
                                 double* __restrict__ H, int ldh, int hrow, int hcol,
-                                int* __restrict__ flags) {
+                                double shift_rel, int* __restrict__ flags) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (stage == 3 && flags[2] == 0) return;
   double tr = 0.0;
   for (int i = 0; i < p; ++i) tr += G[i * p + i];
+  // stage 1 of the initial QR (w0norm2 = NULL) has no invariant-subspace test
   double wn = 0.0;
-  if (stage == 1)
+  if (stage == 1 && w0norm2)
     for (int b = 0; b < p; ++b) wn += w0norm2[b];
-  bool zero = (stage == 1) ? (tr <= 1e-24 * wn) : (tr == 0.0);
+  bool zero = (stage == 1 && w0norm2) ? (tr <= 1e-24 * wn) : (tr == 0.0);
+  if (stage == 1) flags[2] = 0;
   if (!zero) {
-    for (int j = 0; j < p; ++j) {
-      double djj = G[j * p + j];
-      for (int k = 0; k < j; ++k) djj -= R[k * p + j] * R[k * p + j];
-      if (!(djj > 1e-28 * tr)) {   // rank deficient (or NaN)
-        flags[1] = 1;
-        zero = true;
-        break;
-      }
-      const double rjj = sqrt(djj);
-      R[j * p + j] = rjj;
-      for (int i = j + 1; i < p; ++i) {
-        double s = G[j * p + i];
-        for (int k = 0; k < j; ++k) s -= R[k * p + j] * R[k * p + i];
-        R[j * p + i] = s / rjj;
-      }
-      for (int i = 0; i < j; ++i) R[j * p + i] = 0.0;
+    int st = chol_upper(p, G, 0.0, tr, R);
+    if (stage == 1 && st != 0) {
+      st = chol_upper(p, G, shift_rel * tr, tr, R);
+      if (st != 2) flags[2] = 1;
+    } else if (st == 1) {
+      st = 0;   // passes 2 and 3 work on blocks already close to orthonormal
     }
-  } else if (stage == 1) {
+    if (st == 2) {   // rank deficient (or NaN)
+      flags[1] = 1;
+      zero = true;
+    }
+  } else if (stage == 1 && w0norm2) {
     flags[0] = 1;
   }
   if (zero) {
@@ -193,6 +223,15 @@ __global__ void k_cholqr_factor(int p, const double* __restrict__ G, double* __r
       for (int j = 0; j < p; ++j) {
         double s = 0.0;
         for (int k = 0; k < p; ++k) s += R[i * p + k] * Rprev[k * p + j];
+        H[int64_t(hrow + i) * ldh + hcol + j] = s;
+      }
+  }
+  if (stage == 3 && H != nullptr) {
+    // H block <- R3 * H block, column by column (R3 upper: row i uses rows >= i)
+    for (int j = 0; j < p; ++j)
+      for (int i = 0; i < p; ++i) {
+        double s = 0.0;
+        for (int k = i; k < p; ++k) s += R[i * p + k] * H[int64_t(hrow + k) * ldh + hcol + j];
         H[int64_t(hrow + i) * ldh + hcol + j] = s;
       }
   }
@@ -456,6 +495,41 @@ k_combine(int64_t n, int p, const double* __restrict__ B, const double* __restri
     zz += s * s;
   }
   red[threadIdx.x] = zz;
+  __syncthreads();
+  for (int st = kThreads / 2; st >= 1; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Source-term combination over the joined block [U0 | S] (width 2 pu):
+// U = omega0 U0 + sum_j Re(c_j X_j[U0 part]) + Re(s_j X_j[S part]), X_j's real
+// part in columns 4 pu j .. 4 pu j + 2 pu - 1 (the U0 part first, then the S
+// part), its imaginary part in the next 2 pu columns; partial ||U||^2.
+__global__ void __launch_bounds__(kThreads)
+k_combine_source(int64_t n, int pu, const double* __restrict__ B, const double* __restrict__ X,
+                 int ldx, double omega0, const double* __restrict__ c_re,
+                 const double* __restrict__ c_im, const double* __restrict__ s_re,
+                 const double* __restrict__ s_im, double* __restrict__ U,
+                 double* __restrict__ partial) {
+  __shared__ double red[kThreads];
+  double uu = 0.0;
+  for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < n * pu;
+       idx += int64_t(gridDim.x) * kThreads) {
+    const int64_t r = idx / pu;
+    const int b = int(idx % pu);
+    double u = omega0 * B[r * 2 * pu + b];
+    const double* xr = X + r * ldx;
+    for (int j = 0; j < kNShift; ++j) {
+      const double* xj = xr + 4 * pu * j;
+      u += c_re[j] * xj[b] - c_im[j] * xj[2 * pu + b] + s_re[j] * xj[pu + b] -
+           s_im[j] * xj[3 * pu + b];
+    }
+    U[idx] = u;
+    uu += u * u;
+  }
+  red[threadIdx.x] = uu;
   __syncthreads();
   for (int st = kThreads / 2; st >= 1; st >>= 1) {
     if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];

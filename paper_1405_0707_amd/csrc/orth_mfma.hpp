@@ -68,7 +68,9 @@ __device__ inline T basis_at(const T* __restrict__ V, int64_t n, int p, int64_t 
 template <typename T, int NB, int MBW>
 __global__ void __launch_bounds__(kThreads)
 k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const T* W, T* Wout,
-           const double* __restrict__ C, double* __restrict__ partial) {
+           const double* __restrict__ C, double* __restrict__ partial,
+           const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // conditional pass not requested
   using M = Mma<T>;
   using v4 = typename M::v4;
   __shared__ T sW[64 * 16 * NB];        // W' of the step, row-major, ld 16 NB

@@ -1,5 +1,5 @@
 // Toeplitz operator kernels: a batched complex FFT (Stockham autosort,
-// mixed radix 8/4/2, q interleaved columns), real <-> complex packing of
+// mixed radix 8/4/2/5/3, q interleaved columns), real <-> complex packing of
 // two real columns per complex column, and the pointwise spectral products
 // of the circulant-embedding product T v and of the Gohberg-Semencul
 // formula for T^{-1} v (paper, Section 4.1 and the fast Toeplitz products of
@@ -55,16 +55,36 @@ k_fft_pass(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __re
       V[1] = {b.x + di.x, b.y + di.y};
       V[3] = {b.x - di.x, b.y - di.y};
     } else {
-      // R == 8: V_m = sum_r v_r exp(sign 2 pi i r m / 8)
+      // R = 8, 5, 3: V_m = sum_r v_r exp(sign 2 pi i r m / R), with the
+      // cosines and sines of 2 pi e / R, e = 0 .. R-1
+      static_assert(R == 8 || R == 5 || R == 3, "radix");
       constexpr double h = 0.70710678118654752440;
-      const double cs[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
-      const double sn[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
+      constexpr double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+      constexpr double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+      constexpr double s3 = 0.86602540378443864676;
+      double cs[R], sn[R];
+      if constexpr (R == 8) {
+        const double c8[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
+        const double s8[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cs[e] = c8[e], sn[e] = s8[e];
+      } else if constexpr (R == 5) {
+        const double c5[5] = {1.0, c1, c2, c2, c1};
+        const double s5[5] = {0.0, s1, s2, -s2, -s1};
+#pragma unroll
+        for (int e = 0; e < 5; ++e) cs[e] = c5[e], sn[e] = s5[e];
+      } else {
+        const double c3[3] = {1.0, -0.5, -0.5};
+        const double s3v[3] = {0.0, s3, -s3};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) cs[e] = c3[e], sn[e] = s3v[e];
+      }
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         double xr = 0.0, xi = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const int e = (r * m) & 7;
+          const int e = (r * m) % R;
           const double wr = cs[e], wi = sign * sn[e];
           xr += v[r].x * wr - v[r].y * wi;
           xi += v[r].x * wi + v[r].y * wr;
@@ -80,11 +100,12 @@ k_fft_pass(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __re
 
 // out (L x q complex) = rows of src (n x p real, row-major), two real
 // columns per complex column (2c -> real part, 2c+1 -> imaginary part),
-// rows reversed if `reverse`, zero for rows >= n, times scale.
+// rows reversed if `reverse`, zero for rows >= n, times scale and, when rs
+// is not null, times rs[source row] (a diagonal applied before the product).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_pack(int64_t n, int p, int64_t ld, int q, int64_t L, const T* __restrict__ src,
-       cplx* __restrict__ out, int reverse, double scale) {
+       cplx* __restrict__ out, int reverse, double scale, const double* __restrict__ rs) {
   for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < L * q;
        gid += int64_t(gridDim.x) * kThreads) {
     const int64_t i = gid / q;
@@ -92,26 +113,29 @@ k_pack(int64_t n, int p, int64_t ld, int q, int64_t L, const T* __restrict__ src
     cplx v{0.0, 0.0};
     if (i < n) {
       const int64_t row = reverse ? (n - 1 - i) : i;
-      v.x = scale * double(src[row * ld + 2 * c]);
-      if (2 * c + 1 < p) v.y = scale * double(src[row * ld + 2 * c + 1]);
+      const double sc = rs ? scale * rs[row] : scale;
+      v.x = sc * double(src[row * ld + 2 * c]);
+      if (2 * c + 1 < p) v.y = sc * double(src[row * ld + 2 * c + 1]);
     }
     out[gid] = v;
   }
 }
 
 // dst (n x p real) (+)= scale * the first n rows of in (reversed if
-// `reverse`), unpacking the two real columns of each complex column.
+// `reverse`), unpacking the two real columns of each complex column; when
+// rs is not null each destination row i is also scaled by rs[i] (a diagonal
+// applied after the product).
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_unpack(int64_t n, int p, int64_t ld, int q, const cplx* __restrict__ in, T* __restrict__ dst,
-         int reverse, double scale, int accumulate) {
+         int reverse, double scale, int accumulate, const double* __restrict__ rs) {
   for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < n * p;
        gid += int64_t(gridDim.x) * kThreads) {
     const int64_t i = gid / p;
     const int col = int(gid % p);
     const int64_t src_row = reverse ? (n - 1 - i) : i;
     const cplx v = in[src_row * q + col / 2];
-    const double x = scale * ((col & 1) ? v.y : v.x);
+    const double x = (rs ? scale * rs[i] : scale) * ((col & 1) ? v.y : v.x);
     T* d = dst + i * ld + col;
     *d = accumulate ? T(double(*d) + x) : T(x);
   }

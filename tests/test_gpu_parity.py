@@ -126,6 +126,26 @@ def test_sine_modes_happy_breakdown():
     assert np.linalg.norm(Z.cpu().numpy() - expect) < 1e-12 * np.linalg.norm(B)
 
 
+@pytest.mark.parametrize("eps", [1e-9, 1e-11])
+def test_nearly_collinear_block_uses_shifted_cholesky_qr(eps):
+    """B = [v, v + eps w]: its Gram matrix is singular to rounding, so plain
+    Cholesky QR cannot factor the first block; the shifted factor and a
+    third pass must give a basis on which the solve still converges to the
+    closed form (before the fallback this block ended in EBREAKDOWN)."""
+    announce(f"nearly collinear block eps={eps}")
+    N = 24
+    W = wl.c1(N=N, p=2)
+    W.t = 2.2692 / (2 * (2 - 2 * np.cos(np.pi / (N + 1))))
+    rng = np.random.default_rng(24)
+    v, w = rng.standard_normal(N * N), rng.standard_normal(N * N)
+    B = np.stack([v, v + eps * w], 1)
+    pl = plan_for(W, m=10, k=12)
+    Z, info = pl.execute(torch.from_numpy(B), tol=1e-11)
+    Z = Z.cpu().numpy()
+    ref = inverses.dst_laplacian_function(N, 2, W.t, rfun, B)
+    assert rel(Z, ref) < 1e-10
+
+
 def test_algorithm_1_unpreconditioned():
     announce("SBFOM-DR")
     W = wl.c1(N=16, p=3)
