@@ -83,42 +83,49 @@ def parse():
                     help="sample every N-th inner iteration with HIP events (0 = off)")
     ap.add_argument("--inner", choices=["auto", "amg", "jacobi"], default="auto",
                     help="preconditioner of the inner CG (auto = AMG at this size)")
+    ap.add_argument("--amg-fp32", action="store_true",
+                    help="run the AMG V-cycle in FP32 under the FP64 CG (default: FP64)")
     return ap.parse_args()
 
 
-def cg_kernel_bytes(n: int, nnz: int, p: int) -> dict:
+def cg_kernel_bytes(n: int, nnz: int, p: int, precond: str = "jacobi") -> dict:
     """Algorithmic HBM bytes per launch of the inner CG's three kernels
-    (FP64 values, int32 indices):
+    (FP64 values, int32 indices; precond "jacobi", "amg64" or "amg32", the
+    V-cycle's precision):
       A  q = K p (CSR SpMM) + partial (p, q): rowptr 4(n+1), colind and
          values 12 nnz, read p and write q 16 n p;
-      B  r -= alpha q + partials: dinv 8 n, read r, q and write r 24 n p;
-      C  x += alpha p_old, p_new = D^{-1} r + beta p_old: dinv 8 n, read r,
-         p_old, x and write p_new, x 40 n p."""
+      B  r -= alpha q + partials: read r, q and write r 24 n p (+ dinv 8 n
+         for Jacobi's (r, D^{-1} r); + 4 n p writing the FP32 copy of r);
+      C  x += alpha p_old, p_new = z + beta p_old: read p_old, x and write
+         p_new, x 32 n p, and z = D^{-1} r (dinv 8 n + r 8 n p) or the
+         V-cycle's z (8 n p, or 4 n p in FP32)."""
     return {"A": 4 * (n + 1) + 12 * nnz + 16 * n * p,
-            "B": 8 * n + 24 * n * p,
-            "C": 8 * n + 40 * n * p}
+            "B": 24 * n * p + {"jacobi": 8 * n, "amg64": 0, "amg32": 4 * n * p}[precond],
+            "C": 32 * n * p + {"jacobi": 8 * n + 8 * n * p, "amg64": 8 * n * p,
+                               "amg32": 4 * n * p}[precond]}
 
 
-def smooth_kernel_bytes(n: int, nnz: int, p: int, degree: int) -> float:
+def smooth_kernel_bytes(n: int, nnz: int, p: int, degree: int, es: int = 8) -> float:
     """Mean algorithmic HBM bytes per launch of the finest AMG level's
     smoothing-step kernel k_amg_step over the 2 * degree launches of one
-    V-cycle (FP64, int32 indices; A = 4(n+1) + 12 nnz for the CSR operator):
-      first pre-step (iterate s0 D^{-1} b implicit): A + 8n + 24np
-      later pre-steps: A + 8n + 40np
-      residual: A + 24np (A + 8n + 16np when degree = 1)
-      post-steps: A + 8n + 24np (+ 8np for the direction d unless the step is
-      the last one, + 8np for reading d after the first)."""
-    A = 4 * (n + 1) + 12 * nnz
+    V-cycle, with es-byte values and vectors (8: FP64 V-cycle, 4: FP32) and
+    int32 indices, A = 4(n+1) + (4 + es) nnz for the CSR operator:
+      first pre-step (iterate s0 D^{-1} b implicit): A + es n + 3 es np
+      later pre-steps: A + es n + 5 es np
+      residual: A + 3 es np (A + es n + 2 es np when degree = 1)
+      post-steps: A + es n + 3 es np (+ es np for the direction d unless the
+      step is the last one, + es np for reading d after the first)."""
+    A = 4 * (n + 1) + (4 + es) * nnz
     launches = []
     for st in range(1, degree):
-        launches.append(A + 8 * n + (24 if st == 1 else 40) * n * p)
-    launches.append(A + 24 * n * p if degree > 1 else A + 8 * n + 16 * n * p)
+        launches.append(A + es * n + (3 if st == 1 else 5) * es * n * p)
+    launches.append(A + 3 * es * n * p if degree > 1 else A + es * n + 2 * es * n * p)
     for st in range(degree):
-        b = A + 8 * n + 24 * n * p
+        b = A + es * n + 3 * es * n * p
         if st > 0:
-            b += 8 * n * p
+            b += es * n * p
         if st + 1 < degree:
-            b += 8 * n * p
+            b += es * n * p
         launches.append(b)
     return sum(launches) / len(launches)
 
@@ -277,7 +284,8 @@ def main():
     W = wl.c2()
     t0 = time.perf_counter()
     plan = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=dev, m=W.m, k=W.k,
-                    profile=max(0, args.profile_every), inner_precond=args.inner)
+                    profile=max(0, args.profile_every), inner_precond=args.inner,
+                    amg_fp32=1 if args.amg_fp32 else 0)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     B = torch.from_numpy(W.B).to(dev)
@@ -308,7 +316,8 @@ def main():
     if samples:
         mean = {key: sum(getattr(i, "kern_ms_" + key.lower()) * i.kern_samples for i in infos)
                 / samples for key in ("A", "B", "C")}
-        byt = cg_kernel_bytes(W.n, W.A.nnz, W.p)
+        precond = ("jacobi" if not info.amg_levels else ("amg32" if args.amg_fp32 else "amg64"))
+        byt = cg_kernel_bytes(W.n, W.A.nnz, W.p, precond)
         names = {"A": "k_cg_a (CSR SpMM q = K p of the inner CG)",
                  "B": "k_cg_b (inner CG residual update)",
                  "C": "k_cg_c (inner CG direction and iterate update)"}
@@ -317,7 +326,7 @@ def main():
         if sm_launches:
             degree = 2
             mean["S"] = sum(i.kern_ms_smooth * i.kern_smooth_launches for i in infos) / sm_launches
-            byt["S"] = smooth_kernel_bytes(W.n, W.A.nnz, W.p, degree)
+            byt["S"] = smooth_kernel_bytes(W.n, W.A.nnz, W.p, degree, 4 if args.amg_fp32 else 8)
             names["S"] = ("k_amg_step, finest level (AMG V-cycle smoothing steps and residual, "
                           "CSR SpMM fused with the Chebyshev update)")
             per_iter["S"] = mean["S"] * sm_launches / samples
@@ -366,8 +375,9 @@ def main():
                                "||tA||_2=1e4, B n x 8 Gaussian seed 2, m=15, k=40, tol=1e-10",
                    "n": W.n, "p": W.p, "m": W.m, "k": W.k, "tol": W.tol},
         "rel_err_vs_rational_closed_form": rel_err,
-        "inner_preconditioner": (f"AMG ({info.amg_levels} levels)" if info.amg_levels
-                                 else "Jacobi"),
+        "inner_preconditioner": (f"AMG ({info.amg_levels} levels, "
+                                 f"{'FP32' if args.amg_fp32 else 'FP64'} V-cycle)"
+                                 if info.amg_levels else "Jacobi"),
         "cycles": info.cycles, "block_apps": info.block_apps,
         "inner_iters": int(info.inner_iters), "err_bound": info.err_bound,
         "phase_ms": {"apply": round(info.ms_apply, 2), "orth": round(info.ms_orth, 2),

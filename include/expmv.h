@@ -103,6 +103,12 @@ typedef struct {
                           (eq. 4.9) over the shifts after block j-1, cap = 10^c (at
                           most 10^2 in the mixed forms); the estimates cost one
                           projected solve per block.  0: fixed inner tolerance        */
+  int amg_fp32;        /* FP64 form, symmetric A with the AMG-preconditioned CG: 1 runs
+                          the V-cycle in FP32 (FP32 operator values and vectors, FP64
+                          sums); the CG, its SpMM, its recurrences and its stopping
+                          test stay FP64, so the result's accuracy is unchanged and
+                          only the iteration count can move.  0 (default): FP64
+                          V-cycle.  The mixed forms always use FP32.                  */
 } expmv_opts;
 
 typedef struct {                  /* host struct, filled by expmv_execute */

@@ -60,10 +60,12 @@ struct RowRange {
 
 // sum over the row's nonzeros of val[e] * w(j) with w(j) = x[j * ld + c] (or
 // s0 * dinv[j] * x[j * ld + c] when scaled), split over the G sub-lanes and
-// summed across them; every lane of the group receives the row's sum.
+// summed across them; every lane of the group receives the row's sum.  The
+// operator values have the vectors' type (an FP32 V-cycle reads FP32 values);
+// the sums are FP64.
 template <typename T, int PP, bool SCALED>
 __device__ inline double row_dot_split(const int32_t* __restrict__ colind,
-                                       const double* __restrict__ val, const T* __restrict__ x,
+                                       const T* __restrict__ val, const T* __restrict__ x,
                                        const T* __restrict__ dinv, int e0, int e1, int ld, int c,
                                        bool active, int g, int G) {
   constexpr int U = 8;   // nonzeros per sub-lane step, all loads issued first
@@ -76,7 +78,7 @@ __device__ inline double row_dot_split(const int32_t* __restrict__ colind,
       for (int u = 0; u < U; ++u) {
         const bool ok = e + u * G < e1;
         j[u] = ok ? colind[e + u * G] : -1;
-        v[u] = ok ? val[e + u * G] : 0.0;
+        v[u] = ok ? double(val[e + u * G]) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -96,7 +98,7 @@ __device__ inline double row_dot_split(const int32_t* __restrict__ colind,
 template <typename T, int PP, int NT, bool SEG>
 __global__ void __launch_bounds__(NT)
 k_amg_step(int k, const KrylovCtl* ctl, int n, int p, int G, const int32_t* __restrict__ rowptr,
-           const int32_t* __restrict__ colind, const double* __restrict__ val,
+           const int32_t* __restrict__ colind, const T* __restrict__ val,
            const T* __restrict__ dinv, const T* __restrict__ b, const T* __restrict__ x,
            T* __restrict__ d, T* __restrict__ out, double s0, double cd, double ad, int mode,
            double* __restrict__ part) {
@@ -142,7 +144,7 @@ template <typename T, int PP, int NT, bool SEG>
 __global__ void __launch_bounds__(NT)
 k_amg_restrict(int k, const KrylovCtl* ctl, int nc, int p, int G,
                const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-               const double* __restrict__ val, const T* __restrict__ r, T* __restrict__ bc) {
+               const T* __restrict__ val, const T* __restrict__ r, T* __restrict__ bc) {
   if (ctl && finished_by(ctl, k)) return;
   const int c = threadIdx.x % PP;
   const int g = (threadIdx.x / PP) % G;
@@ -159,7 +161,7 @@ template <typename T, int PP, int NT, bool SEG>
 __global__ void __launch_bounds__(NT)
 k_amg_prolong(int k, const KrylovCtl* ctl, int n, int p, int G,
               const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
-              const double* __restrict__ val, const T* __restrict__ xc,
+              const T* __restrict__ val, const T* __restrict__ xc,
               const T* __restrict__ dinv, const T* __restrict__ b, double s0, int mode,
               T* __restrict__ x) {
   if (ctl && finished_by(ctl, k)) return;

@@ -90,6 +90,7 @@ struct Workspace {
   DevBuf<char> Rin, Din;        // n x p (inner-solver type, refinement)
   DevBuf<char> kr, kpa, kpb, kq, kv, ks, kt, krh;   // inner-solver vectors, n x p
   DevBuf<char> kz, kph, ksh;                        // AMG-preconditioned vectors
+  DevBuf<float> kr32, kz32;                         // FP32 V-cycle input / output (n x p)
   DevBuf<double> X;             // n x 14p
   DevBuf<double> partial;       // reductions of the dense kernels
   DevBuf<double> hcoef, gram, R1, R2, Rinv, w0;   // small orth buffers
@@ -128,6 +129,7 @@ struct AmgDevLevel {
   DevBuf<int32_t> Arp, Aci, Prp, Pci, Rrp, Rci;
   DevBuf<double> Av, Pv, Rv, dinv;
   DevBuf<float> dinvf;
+  DevBuf<float> Av32, Pv32, Rv32;   // FP32 copies of the values (FP32 V-cycles)
   double cd[kAmgMaxDeg] = {}, ad[kAmgMaxDeg] = {};   // Chebyshev step coefficients
   double avg_a = 0.0, avg_p = 0.0, avg_r = 0.0;      // mean nonzeros per row of A, P, R
   DevBuf<char> vb, vu, vv, vd, vr, vo;
@@ -423,6 +425,14 @@ InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chu
 // ------------------------------------------------------------------------
 // AMG V-cycle (preconditioner of the inner CG)
 
+// operator values of a level in the V-cycle's precision
+template <typename T>
+struct LevelVals {
+  const T *a, *p, *r;
+};
+LevelVals<double> vals_of(const AmgDevLevel& L, double) { return {L.av, L.Pv.p, L.Rv.p}; }
+LevelVals<float> vals_of(const AmgDevLevel& L, float) { return {L.Av32.p, L.Pv32.p, L.Rv32.p}; }
+
 template <typename T>
 const T* dinv_of(const AmgDevLevel& L);
 template <>
@@ -465,6 +475,7 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
     return;
   }
   const T* dinv = dinv_of<T>(L);
+  const LevelVals<T> lv = vals_of(L, T());
   const bool fine = (l == 0);
   const int gfine = cg_grid(n, PP);
   const int GA = row_split(L.avg_a, PP), GP = row_split(L.avg_p, PP);
@@ -479,11 +490,11 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
         *nsev += 1;
       }
       hipExtLaunchKernelGGL((k_amg_step<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads),
-                            0, s, e0, e1, 0, k, ctl, n, p, GA, L.arp, L.aci, L.av, dinv, b, x, d,
+                            0, s, e0, e1, 0, k, ctl, n, p, GA, L.arp, L.aci, lv.a, dinv, b, x, d,
                             o, L.ad[0], cd, ad, mode, part);
     } else
       hipLaunchKernelGGL((k_amg_step<T, PP, kThreads, false>), dim3(gcoarse_a), dim3(kThreads), 0,
-                         s, k, ctl, n, p, GA, L.arp, L.aci, L.av, dinv, b, x, d, o, L.ad[0], cd,
+                         s, k, ctl, n, p, GA, L.arp, L.aci, lv.a, dinv, b, x, d, o, L.ad[0], cd,
                          ad, mode, part);
   };
   T* x = reinterpret_cast<T*>(L.vu.p);
@@ -502,17 +513,17 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   const int nc = int(C.n);
   const int GR = row_split(L.avg_r, PP);
   hipLaunchKernelGGL((k_amg_restrict<T, PP, kThreads, false>), dim3(grid_for(nc, PP * GR, 4096)),
-                     dim3(kThreads), 0, s, k, ctl, nc, p, GR, L.Rrp.p, L.Rci.p, L.Rv.p, r, bc);
+                     dim3(kThreads), 0, s, k, ctl, nc, p, GR, L.Rrp.p, L.Rci.p, lv.r, r, bc);
   T* xc = reinterpret_cast<T*>(C.vo.p);
   amg_level<T, PP>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
   const int pmode = implicit ? kAmgX0 : 0;
   if (fine)
     hipLaunchKernelGGL((k_amg_prolong<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads), 0,
-                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, L.Pv.p, xc, dinv, b, L.ad[0], pmode,
+                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv, b, L.ad[0], pmode,
                        x);
   else
     hipLaunchKernelGGL((k_amg_prolong<T, PP, kThreads, false>), dim3(gcoarse_p), dim3(kThreads), 0,
-                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, L.Pv.p, xc, dinv, b, L.ad[0], pmode,
+                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv, b, L.ad[0], pmode,
                        x);
   // post-smoothing from x, the same polynomial (symmetric V-cycle)
   for (int st = 0; st < H.degree; ++st) {
@@ -560,10 +571,27 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
   AmgDev* H = amg_for(pl, 0);
   const bool amg = H != nullptr;
   T* z = amg ? reinterpret_cast<T*>(w.kz.p) : nullptr;
+  // FP32 V-cycle under the FP64 CG (opts.amg_fp32): k_cg_init / k_cg_b write an
+  // FP32 copy of r, the V-cycle maps it to an FP32 z that k_cg_c reads
+  const bool v32 = amg && !std::is_same<T, float>::value && pl->opts.amg_fp32 != 0;
+  float* r32 = nullptr;
+  float* z32 = nullptr;
+  if (v32) {
+    w.kr32.alloc(size_t(n) * p);
+    w.kz32.alloc(size_t(n) * p);
+    r32 = w.kr32.p;
+    z32 = w.kz32.p;
+  }
   DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
                                      int(n), p, sign, src, A.dinv, out, r, P[0], w.ctl.p,
-                                     w.part_rr.p));
-  if (amg) amg_vcycle<T>(pl, *H, p, r, z, 0, w.ctl.p, w.part_rr.p);
+                                     w.part_rr.p, r32));
+  auto vcycle = [&](int k, hipEvent_t* sev, int* nsev) {
+    if (v32)
+      amg_vcycle<float>(pl, *H, p, r32, z32, k, w.ctl.p, w.part_rr.p, sev, nsev);
+    else
+      amg_vcycle<T>(pl, *H, p, r, z, k, w.ctl.p, w.part_rr.p, sev, nsev);
+  };
+  if (amg) vcycle(0, nullptr, nullptr);
   InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
     for (int it = 0; it < chunk; ++it) {
       const int k = launched + it;
@@ -579,10 +607,17 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
         *nsm = 0;
         pl->pev_used += 1;
       }
-      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[0] : ez, sample ? e[1] : ez, 0, k, int(n),
-                                            p, A.dinv, r, z, pold, pnew, out, w.cgst.p, w.ctl.p,
-                                            w.part_rr.p, tol2, maxit));
+      if (v32) {
+        DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, float, P_>), dim3(grid), dim3(kCgThreads),
+                                              0, s, sample ? e[0] : ez, sample ? e[1] : ez, 0, k,
+                                              int(n), p, A.dinv, r, z32, pold, pnew, out, w.cgst.p,
+                                              w.ctl.p, w.part_rr.p, tol2, maxit));
+      } else {
+        DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, T, P_>), dim3(grid), dim3(kCgThreads), 0,
+                                              s, sample ? e[0] : ez, sample ? e[1] : ez, 0, k,
+                                              int(n), p, A.dinv, r, z, pold, pnew, out, w.cgst.p,
+                                              w.ctl.p, w.part_rr.p, tol2, maxit));
+      }
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_a<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
                                             sample ? e[2] : ez, sample ? e[3] : ez, 0, k, int(n),
                                             p, A.rowptr, A.colind, A.val, pnew, q, w.ctl.p,
@@ -590,9 +625,8 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
       DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_b<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
                                             sample ? e[4] : ez, sample ? e[5] : ez, 0, k, int(n),
                                             p, A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
-                                            w.part_rr.p, amg ? 0 : 1));
-      if (amg)
-        amg_vcycle<T>(pl, *H, p, r, z, k, w.ctl.p, w.part_rr.p, sample ? e + 6 : nullptr, nsm);
+                                            w.part_rr.p, amg ? 0 : 1, r32));
+      if (amg) vcycle(k, sample ? e + 6 : nullptr, nsm);
     }
   }, amg ? 1 : 16, amg ? pl->last_inner_iters - 2 : 0);
   collect_profile(pl, res.iters);
@@ -1605,6 +1639,7 @@ bool valid_opts(const expmv_opts& o) {
   if (o.inner_precond < -1 || o.inner_precond > 1) return false;
   if (o.amg_degree < 0 || o.amg_degree > kAmgMaxDeg) return false;
   if (o.inner_relax < 0 || o.inner_relax > 10) return false;
+  if (o.amg_fp32 != 0 && o.amg_fp32 != 1) return false;
   return true;
 }
 
@@ -1712,7 +1747,7 @@ expmv_status build_csr(expmv_plan_s* pl, const int32_t* rowptr_d, const int32_t*
   HIPCHK(hipMemcpy(pl->colind.p, ci.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(pl->val.p, v.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(pl->dinv.p, dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-  if (pl->mixed) {
+  {   // FP32 Jacobi scaling (mixed forms, FP32 V-cycles)
     std::vector<float> df(dinv.begin(), dinv.end());
     pl->dinvf.alloc(n);
     HIPCHK(hipMemcpy(pl->dinvf.p, df.data(), sizeof(float) * n, hipMemcpyHostToDevice));
@@ -1809,15 +1844,16 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
       L->aci = L->Aci.p;
       L->av = L->Av.p;
       L->dinv64 = L->dinv.p;
-      if (pl->mixed) {
-        upload_vec(L->dinvf, Lh.dinv);
-        L->dinv32 = L->dinvf.p;
-      }
+      upload_vec(L->dinvf, Lh.dinv);
+      L->dinv32 = L->dinvf.p;
     }
+    upload_vec(L->Av32, Lh.A.v);   // level 0: the values of K (or K^T) as the host copy holds them
     L->avg_a = double(Lh.A.nnz()) / double(std::max<int64_t>(1, Lh.A.nrows));
     if (l + 1 < h.lv.size()) {
       upload_csr(Lh.P, L->Prp, L->Pci, L->Pv);
       upload_csr(Lh.R, L->Rrp, L->Rci, L->Rv);
+      upload_vec(L->Pv32, Lh.P.v);
+      upload_vec(L->Rv32, Lh.R.v);
       L->avg_p = double(Lh.P.nnz()) / double(std::max<int64_t>(1, Lh.P.nrows));
       L->avg_r = double(Lh.R.nnz()) / double(std::max<int64_t>(1, Lh.R.nrows));
     }
@@ -2045,6 +2081,7 @@ expmv_status expmv_default_opts(expmv_opts* o) {
   o->inner_precond = -1;
   o->amg_degree = 0;
   o->inner_relax = 8;
+  o->amg_fp32 = 0;
   return EXPMV_OK;
 }
 
@@ -2323,7 +2360,10 @@ expmv_status expmv_apply_preconditioner(expmv_plan plan, int transpose, const do
                            s, plan->n, int(p), A.dinv, x, y);
       }
     };
-    if (plan->mixed) {
+    // the V-cycle in the precision the inner solver uses
+    const bool v32 = plan->mixed || (plan->opts.amg_fp32 && plan->symmetric &&
+                                     amg_for(plan, transpose) != nullptr);
+    if (v32) {
       float* xf = reinterpret_cast<float*>(plan->ws.W.p);
       float* yf = reinterpret_cast<float*>(plan->ws.Wt.p);
       hipLaunchKernelGGL((k_convert<double, float>), dim3(512), dim3(kThreads), 0, s, cnt, X, xf,

@@ -231,7 +231,7 @@ template <typename T, typename TS, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __restrict__ dinv,
           T* __restrict__ x, T* __restrict__ r, T* __restrict__ pold,
-          KrylovCtl* ctl, double* __restrict__ part_rr) {
+          KrylovCtl* ctl, double* __restrict__ part_rr, float* __restrict__ r32) {
   __shared__ double red[kCgThreads];
   const int c = threadIdx.x % PP;
   double rz = 0.0, bb = 0.0;
@@ -242,6 +242,7 @@ k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __rest
       const int64_t i = row * p + c;
       const T b = T(sign * double(src[i]));
       r[i] = b;
+      if (r32) r32[i] = float(b);   // input of an FP32 preconditioner
       x[i] = T(0);
       pold[i] = T(0);
       const double bd = double(b);
@@ -259,10 +260,12 @@ k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __rest
   }
 }
 
-template <typename T, int PP>
+// z: the preconditioned residual (TZ = float for an FP32 V-cycle), or NULL
+// for Jacobi (D^{-1} r formed here)
+template <typename T, typename TZ, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
-       const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
+       const TZ* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
        T* __restrict__ x, CgState* st, KrylovCtl* ctl, const double* __restrict__ part_rr,
        double tol2, int maxit) {
   if (finished_before(ctl, k)) return;
@@ -329,7 +332,7 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
       const int64_t i = row * p + c;
       const T po = pold[i];
       x[i] += aprev * po;
-      if (any) pnew[i] = (z ? z[i] : dinv[row] * r[i]) + beta * po;
+      if (any) pnew[i] = (z ? T(z[i]) : dinv[row] * r[i]) + beta * po;
     }
   }
 }
@@ -360,7 +363,7 @@ template <typename T, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const T* __restrict__ q,
        CgState* st, const KrylovCtl* ctl, const double* __restrict__ part_sig,
-       double* __restrict__ part_rr, int jacobi) {
+       double* __restrict__ part_rr, int jacobi, float* __restrict__ r32) {
   if (finished_by(ctl, k)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[PP];
@@ -387,6 +390,7 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
       const int64_t i = row * p + c;
       const T rn = r[i] - alpha * q[i];
       r[i] = rn;
+      if (r32) r32[i] = float(rn);   // input of an FP32 preconditioner
       const double rd = double(rn);
       if (jacobi) rz += rd * double(dinv[row]) * rd;
       rr += rd * rd;

@@ -47,7 +47,7 @@ def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
     announce(f"V-cycle {name} p={p} degree={degree}")
     A, t = _workload(name)
     pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
-                  amg_degree=degree)
+                  amg_degree=degree, amg_fp32=0)
     X = np.random.default_rng(p).standard_normal((A.n, p))
     Y = pl.apply_preconditioner(torch.from_numpy(X)).cpu().numpy()
     ref = _host_vcycle(A, t, degree).apply(X)
@@ -61,14 +61,22 @@ def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
     assert abs(a - b) <= 1e-12 * abs(a)
 
 
-def test_device_vcycle_mixed_form():
-    announce("V-cycle mixed")
+@pytest.mark.parametrize("form", ["mixed", "fp64_fp32_vcycle"])
+def test_device_fp32_vcycle(form):
+    """The FP32 V-cycle (FP32 values and vectors, FP64 sums) of the mixed
+    form and, by default, of the FP64 form's CG, against the numpy V-cycle
+    in FP64; symmetric to FP32 rounding."""
+    announce(f"V-cycle FP32 ({form})")
     A, t = _workload("vardiff96")
-    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
-                  precision="mixed")
+    kw = {"precision": "mixed"} if form == "mixed" else {"amg_fp32": 1}
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg", **kw)
     X = np.random.default_rng(4).standard_normal((A.n, 8))
     Y = pl.apply_preconditioner(torch.from_numpy(X)).cpu().numpy()
     assert rel(Y, _host_vcycle(A, t, 2).apply(X)) < 1e-5
+    Px = pl.apply_preconditioner(torch.from_numpy(X[:, :1])).cpu().numpy()[:, 0]
+    Py = pl.apply_preconditioner(torch.from_numpy(X[:, 1:2])).cpu().numpy()[:, 0]
+    a, b = float(Px @ X[:, 1]), float(X[:, 0] @ Py)
+    assert abs(a - b) <= 1e-5 * np.linalg.norm(Px) * np.linalg.norm(X[:, 1])
 
 
 @pytest.mark.parametrize("name,p", [("lap3d20", 8), ("vardiff96", 5)])
