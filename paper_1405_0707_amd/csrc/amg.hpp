@@ -178,23 +178,39 @@ k_amg_prolong(int k, const KrylovCtl* ctl, int n, int p, int G,
   }
 }
 
-// x = Inv b on the coarsest level (Inv dense nc x nc, row-major, FP64); one
-// row per workgroup step, the nc products split over the NT / PP lane groups.
+// x = M b with M dense nr x ncols (row-major, FP64): the coarsest solve
+// (M = the inverse of the coarsest operator, ncols = nr), or the restriction
+// and coarsest solve in one (M = Inv R, b the finer level's residual).  One
+// row per workgroup step; its ncols products are split over the 1024 / PP
+// lane groups, four loads issued before their products, then summed per
+// column with wavefront shuffles.
 template <typename T, int PP>
-__global__ void __launch_bounds__(kThreads)
-k_amg_coarse(int k, const KrylovCtl* ctl, int nc, int p, const double* __restrict__ inv,
-             const T* __restrict__ b, T* __restrict__ x) {
+__global__ void __launch_bounds__(1024)
+k_amg_dense(int k, const KrylovCtl* ctl, int nr, int ncols, int p, const double* __restrict__ M,
+            const T* __restrict__ b, T* __restrict__ x) {
   if (ctl && finished_by(ctl, k)) return;
-  __shared__ double red[kThreads];
+  constexpr int NT = 1024, groups = NT / PP, U = 4;
+  __shared__ double red[NT / 64 * PP + PP];
   const int c = threadIdx.x % PP;
-  const int lane = threadIdx.x / PP;
-  constexpr int groups = kThreads / PP;
-  for (int row = blockIdx.x; row < nc; row += gridDim.x) {
+  const int g = threadIdx.x / PP;
+  for (int row = blockIdx.x; row < nr; row += gridDim.x) {
     double acc = 0.0;
-    if (c < p)
-      for (int q = lane; q < nc; q += groups)
-        acc += inv[int64_t(row) * nc + q] * double(b[int64_t(q) * p + c]);
-    block_col_reduce<PP>(acc, red);
+    if (c < p) {
+      const double* mr = M + int64_t(row) * ncols;
+      int q = g;
+      for (; q + (U - 1) * groups < ncols; q += U * groups) {
+        double a[U], v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a[u] = mr[q + u * groups];
+          v[u] = double(b[int64_t(q + u * groups) * p + c]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += a[u] * v[u];
+      }
+      for (; q < ncols; q += groups) acc += mr[q] * double(b[int64_t(q) * p + c]);
+    }
+    wave_col_reduce<PP, NT>(acc, red);
     if (threadIdx.x < p) x[int64_t(row) * p + threadIdx.x] = T(red[threadIdx.x]);
     __syncthreads();
   }

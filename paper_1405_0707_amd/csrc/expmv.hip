@@ -146,6 +146,9 @@ inline int row_split(double avg, int PP) {
 struct AmgDev {
   std::vector<std::unique_ptr<AmgDevLevel>> lv;
   DevBuf<double> cinv;   // dense inverse of the coarsest operator
+  // Inv R of the level above the coarsest (restriction and coarsest solve as
+  // one dense product), when it is small enough (kAmgFusedMax entries)
+  DevBuf<double> cinvR;
   int degree = 2;
   int p = 0;
   size_t el = 0;
@@ -215,6 +218,7 @@ namespace {
 
 constexpr int kCgGrid = 512;   // workgroups of the inner-solver kernels
 constexpr int kOrthGrid = 512; // most workgroups (partial sums) of an orthogonalisation pass
+constexpr int64_t kAmgFusedMax = int64_t(1) << 21;   // entries of the fused Inv R (16 MB)
 constexpr int kMaxTimes = 32;  // times of one expmv_execute_times call
 
 int grid_for(int64_t rows, int PP, int cap = 1024) {
@@ -470,7 +474,7 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   const int n = int(L.n);
   if (l + 1 == int(H.lv.size())) {
     const int grid = std::max(1, std::min(n, 1024));
-    hipLaunchKernelGGL((k_amg_coarse<T, PP>), dim3(grid), dim3(kThreads), 0, s, k, ctl, n, p,
+    hipLaunchKernelGGL((k_amg_dense<T, PP>), dim3(grid), dim3(1024), 0, s, k, ctl, n, n, p,
                        H.cinv.p, b, out);
     return;
   }
@@ -511,11 +515,18 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   AmgDevLevel& C = *H.lv[l + 1];
   T* bc = reinterpret_cast<T*>(C.vb.p);
   const int nc = int(C.n);
-  const int GR = row_split(L.avg_r, PP);
-  hipLaunchKernelGGL((k_amg_restrict<T, PP, kThreads, false>), dim3(grid_for(nc, PP * GR, 4096)),
-                     dim3(kThreads), 0, s, k, ctl, nc, p, GR, L.Rrp.p, L.Rci.p, lv.r, r, bc);
   T* xc = reinterpret_cast<T*>(C.vo.p);
-  amg_level<T, PP>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+  if (l + 2 == int(H.lv.size()) && H.cinvR.p) {
+    // coarsest correction in one dense product: xc = (Inv R) r
+    hipLaunchKernelGGL((k_amg_dense<T, PP>), dim3(std::max(1, std::min(nc, 1024))), dim3(1024),
+                       0, s, k, ctl, nc, n, p, H.cinvR.p, r, xc);
+  } else {
+    const int GR = row_split(L.avg_r, PP);
+    hipLaunchKernelGGL((k_amg_restrict<T, PP, kThreads, false>),
+                       dim3(grid_for(nc, PP * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p, GR,
+                       L.Rrp.p, L.Rci.p, lv.r, r, bc);
+    amg_level<T, PP>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+  }
   const int pmode = implicit ? kAmgX0 : 0;
   if (fine)
     hipLaunchKernelGGL((k_amg_prolong<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads), 0,
@@ -1861,6 +1872,22 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
     H->lv.push_back(std::move(L));
   }
   upload_vec(H->cinv, h.coarse_inv);
+  {
+    // Inv R for the level above the coarsest: nc x n_l dense, built from the
+    // sparse R row by row (same sums as R then Inv, another order)
+    const AmgLevelHost& Lp = h.lv[h.lv.size() - 2];
+    const int64_t nc = h.lv.back().A.nrows, nl = Lp.A.nrows;
+    if (nc * nl <= kAmgFusedMax) {
+      std::vector<double> IR(size_t(nc) * nl, 0.0);
+      for (int64_t i = 0; i < nc; ++i)
+        for (int64_t q = 0; q < nc; ++q) {
+          const double a = h.coarse_inv[size_t(i) * nc + q];
+          for (int64_t e = Lp.R.rp[q]; e < Lp.R.rp[q + 1]; ++e)
+            IR[size_t(i) * nl + Lp.R.ci[e]] += a * Lp.R.v[e];
+        }
+      upload_vec(H->cinvR, IR);
+    }
+  }
   (tr && !pl->symmetric ? pl->amgT : pl->amg) = std::move(H);
   pl->ws.p = 0;   // workspace re-sized with the AMG vectors on the next call
   return EXPMV_OK;

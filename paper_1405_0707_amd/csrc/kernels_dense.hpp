@@ -171,69 +171,81 @@ __device__ inline int chol_upper(int p, const double* __restrict__ G, double shi
 // stage 2: H(hrow.., hcol..) = R2 * R1 (R1 from stage 1 in Rprev).
 // stage 3 (runs only when flags[2] = 1): the third pass's factor; the H
 //   block becomes R3 * (H block).
-__global__ void k_cholqr_factor(int p, const double* __restrict__ G, double* __restrict__ R,
-                                double* __restrict__ Rinv, const double* __restrict__ w0norm2,
-                                int stage, const double* __restrict__ Rprev,
-                                double* __restrict__ H, int ldh, int hrow, int hcol,
-                                double shift_rel, int* __restrict__ flags) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(64)
+k_cholqr_factor(int p, const double* __restrict__ G, double* __restrict__ R,
+                double* __restrict__ Rinv, const double* __restrict__ w0norm2, int stage,
+                const double* __restrict__ Rprev, double* __restrict__ H, int ldh, int hrow,
+                int hcol, double shift_rel, int* __restrict__ flags) {
+  // one wavefront: G, R, R^{-1} and the H block in LDS; the p^3/6 Cholesky on
+  // one lane, R^{-1} one column per lane, the products one entry per lane
+  __shared__ double sG[kMaxP * kMaxP], sR[kMaxP * kMaxP], sRi[kMaxP * kMaxP],
+      sX[kMaxP * kMaxP];
+  __shared__ int s_zero;
+  const int tid = threadIdx.x;
+  if (blockIdx.x != 0) return;
   if (stage == 3 && flags[2] == 0) return;
-  double tr = 0.0;
-  for (int i = 0; i < p; ++i) tr += G[i * p + i];
-  // stage 1 of the initial QR (w0norm2 = NULL) has no invariant-subspace test
-  double wn = 0.0;
-  if (stage == 1 && w0norm2)
-    for (int b = 0; b < p; ++b) wn += w0norm2[b];
-  bool zero = (stage == 1 && w0norm2) ? (tr <= 1e-24 * wn) : (tr == 0.0);
-  if (stage == 1) flags[2] = 0;
-  if (!zero) {
-    int st = chol_upper(p, G, 0.0, tr, R);
-    if (stage == 1 && st != 0) {
-      st = chol_upper(p, G, shift_rel * tr, tr, R);
-      if (st != 2) flags[2] = 1;
-    } else if (st == 1) {
-      st = 0;   // passes 2 and 3 work on blocks already close to orthonormal
-    }
-    if (st == 2) {   // rank deficient (or NaN)
-      flags[1] = 1;
-      zero = true;
-    }
-  } else if (stage == 1 && w0norm2) {
-    flags[0] = 1;
+  const int pp = p * p;
+  for (int i = tid; i < pp; i += 64) {
+    sG[i] = G[i];
+    sR[i] = 0.0;
+    sRi[i] = 0.0;
   }
+  __syncthreads();
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < p; ++i) tr += sG[i * p + i];
+    // stage 1 of the initial QR (w0norm2 = NULL) has no invariant-subspace test
+    double wn = 0.0;
+    if (stage == 1 && w0norm2)
+      for (int b = 0; b < p; ++b) wn += w0norm2[b];
+    bool zero = (stage == 1 && w0norm2) ? (tr <= 1e-24 * wn) : (tr == 0.0);
+    if (stage == 1) flags[2] = 0;
+    if (!zero) {
+      int st = chol_upper(p, sG, 0.0, tr, sR);
+      if (stage == 1 && st != 0) {
+        st = chol_upper(p, sG, shift_rel * tr, tr, sR);
+        if (st != 2) flags[2] = 1;
+      } else if (st == 1) {
+        st = 0;   // passes 2 and 3 work on blocks already close to orthonormal
+      }
+      if (st == 2) {   // rank deficient (or NaN)
+        flags[1] = 1;
+        zero = true;
+      }
+    } else if (stage == 1 && w0norm2) {
+      flags[0] = 1;
+    }
+    s_zero = zero ? 1 : 0;
+  }
+  __syncthreads();
+  const bool zero = s_zero != 0;
   if (zero) {
-    for (int i = 0; i < p * p; ++i) {
-      R[i] = 0.0;
-      Rinv[i] = 0.0;
-    }
-  } else {
-    // Rinv = R^{-1}, upper triangular, column by column
-    for (int j = 0; j < p; ++j) {
-      for (int i = j + 1; i < p; ++i) Rinv[i * p + j] = 0.0;
-      Rinv[j * p + j] = 1.0 / R[j * p + j];
-      for (int i = j - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int k = i + 1; k <= j; ++k) s += R[i * p + k] * Rinv[k * p + j];
-        Rinv[i * p + j] = -s / R[i * p + i];
-      }
+    for (int i = tid; i < pp; i += 64) sR[i] = 0.0;
+  } else if (tid < p) {
+    // column j of R^{-1} (upper triangular) by back substitution
+    const int j = tid;
+    sRi[j * p + j] = 1.0 / sR[j * p + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int k = i + 1; k <= j; ++k) acc += sR[i * p + k] * sRi[k * p + j];
+      sRi[i * p + j] = -acc / sR[i * p + i];
     }
   }
-  if (stage == 2 && H != nullptr) {
-    for (int i = 0; i < p; ++i)
-      for (int j = 0; j < p; ++j) {
-        double s = 0.0;
-        for (int k = 0; k < p; ++k) s += R[i * p + k] * Rprev[k * p + j];
-        H[int64_t(hrow + i) * ldh + hcol + j] = s;
-      }
+  __syncthreads();
+  for (int i = tid; i < pp; i += 64) {
+    R[i] = sR[i];
+    Rinv[i] = sRi[i];
   }
-  if (stage == 3 && H != nullptr) {
-    // H block <- R3 * H block, column by column (R3 upper: row i uses rows >= i)
-    for (int j = 0; j < p; ++j)
-      for (int i = 0; i < p; ++i) {
-        double s = 0.0;
-        for (int k = i; k < p; ++k) s += R[i * p + k] * H[int64_t(hrow + k) * ldh + hcol + j];
-        H[int64_t(hrow + i) * ldh + hcol + j] = s;
-      }
+  if (H == nullptr || (stage != 2 && stage != 3)) return;
+  // stage 2: H block = R2 * R1 (Rprev); stage 3: H block <- R3 * H block
+  for (int i = tid; i < pp; i += 64)
+    sX[i] = stage == 2 ? Rprev[i] : H[int64_t(hrow + i / p) * ldh + hcol + i % p];
+  __syncthreads();
+  for (int o = tid; o < pp; o += 64) {
+    const int i = o / p, j = o % p;
+    double acc = 0.0;
+    for (int k = stage == 2 ? 0 : i; k < p; ++k) acc += sR[i * p + k] * sX[k * p + j];
+    H[int64_t(hrow + i) * ldh + hcol + j] = acc;
   }
 }
 
