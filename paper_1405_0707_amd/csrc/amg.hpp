@@ -15,6 +15,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -29,21 +30,23 @@ enum : int {
                    // (finest level, inner-solver launch shape only)
 };
 
-// A row is handled by a group of PP * G lanes: lane (c, g) = c + PP g takes
-// column c and the nonzeros e0 + g, e0 + g + G, ... of the row, and the G
-// partial sums of a column are added with shuffles inside the group (G > 1
-// for the long rows of Galerkin operators and restrictions, whose serial
-// sums would otherwise set the kernel's latency).  PP * G <= 64, so a group
-// never straddles a wavefront.
+// A row is handled by a group of PPL * G lanes: lane (l, g) = l + PPL g takes
+// the VW columns c = VW l .. VW l + VW - 1 (VW = 2 for even p: two adjacent
+// columns in one 8- or 16-byte access, half the lanes and index loads of one
+// column per lane) and the nonzeros e0 + g, e0 + g + G, ... of the row, and
+// the G partial sums of a column are added with shuffles inside the group
+// (G > 1 for the long rows of Galerkin operators and restrictions, whose
+// serial sums would otherwise set the kernel's latency).  PPL * G <= 64, so a
+// group never straddles a wavefront.
 //
 // Rows of a group: SEG = one contiguous XCD-aware segment per workgroup (the
 // inner solver's layout), else a grid-stride loop.  Every lane of a group
 // runs the same rows, so the shuffles always see a whole group.
-template <int NT, int PP, bool SEG>
+template <int NT, int PPL, bool SEG>
 struct RowRange {
   int64_t r, end, step;
   __device__ RowRange(int64_t n, int G) {
-    const int lanes = PP * G;
+    const int lanes = PPL * G;
     if (SEG) {
       int64_t s0, s1;
       xcd_rows(n, s0, s1);
@@ -58,22 +61,50 @@ struct RowRange {
   }
 };
 
-// sum over the row's nonzeros of val[e] * w(j) with w(j) = x[j * ld + c] (or
-// s0 * dinv[j] * x[j * ld + c] when scaled), split over the G sub-lanes and
-// summed across them; every lane of the group receives the row's sum.  The
-// operator values have the vectors' type (an FP32 V-cycle reads FP32 values);
-// the sums are FP64.
-template <typename T, int PP, bool SCALED>
-__device__ inline double row_dot_split(const int32_t* __restrict__ colind,
-                                       const T* __restrict__ val, const T* __restrict__ x,
-                                       const T* __restrict__ dinv, int e0, int e1, int ld, int c,
-                                       bool active, int g, int G) {
+// VW consecutive entries of a row-major block (VW = 2: one 2-element access;
+// the offset is even, so it is aligned)
+template <int VW, typename T>
+__device__ inline void load_vw(const T* __restrict__ src, double (&o)[VW]) {
+  if constexpr (VW == 1) {
+    o[0] = double(src[0]);
+  } else if constexpr (std::is_same<T, double>::value) {
+    const double2 v = *reinterpret_cast<const double2*>(src);
+    o[0] = v.x;
+    o[1] = v.y;
+  } else {
+    const float2 v = *reinterpret_cast<const float2*>(src);
+    o[0] = double(v.x);
+    o[1] = double(v.y);
+  }
+}
+template <int VW, typename T>
+__device__ inline void store_vw(T* __restrict__ dst, const double (&o)[VW]) {
+  if constexpr (VW == 1) {
+    dst[0] = T(o[0]);
+  } else if constexpr (std::is_same<T, double>::value) {
+    *reinterpret_cast<double2*>(dst) = double2{o[0], o[1]};
+  } else {
+    *reinterpret_cast<float2*>(dst) = float2{float(o[0]), float(o[1])};
+  }
+}
+
+// acc[k] = sum over the row's nonzeros of val[e] * w_k(j) with w_k(j) =
+// x[j * ld + c0 + k] (or s0 * dinv[j] * x[j * ld + c0 + k] when scaled),
+// split over the G sub-lanes and summed across them; every lane of the
+// group receives the row's sums.  The operator values have the vectors'
+// type (an FP32 V-cycle reads FP32 values); the sums are FP64.
+template <typename T, int PPL, int VW, bool SCALED>
+__device__ inline void row_dot_split(const int32_t* __restrict__ colind,
+                                     const T* __restrict__ val, const T* __restrict__ x,
+                                     const T* __restrict__ dinv, int e0, int e1, int ld, int c0,
+                                     bool active, int g, int G, double (&acc)[VW]) {
   constexpr int U = 8;   // nonzeros per sub-lane step, all loads issued first
-  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) acc[k] = 0.0;
   if (active) {
     for (int e = e0 + g; e < e1; e += U * G) {
       int32_t j[U];
-      double v[U], w[U];
+      double v[U], w[U][VW];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = e + u * G < e1;
@@ -83,19 +114,31 @@ __device__ inline double row_dot_split(const int32_t* __restrict__ colind,
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t jj = j[u];
-        w[u] = jj < 0 ? 0.0
-                      : (SCALED ? double(dinv[jj]) * double(x[jj * ld + c]) : double(x[jj * ld + c]));
+        if (jj < 0) {
+#pragma unroll
+          for (int k = 0; k < VW; ++k) w[u][k] = 0.0;
+        } else {
+          load_vw<VW>(x + jj * ld + c0, w[u]);
+          if (SCALED) {
+            const double dj = double(dinv[jj]);
+#pragma unroll
+            for (int k = 0; k < VW; ++k) w[u][k] *= dj;
+          }
+        }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) acc += v[u] * w[u];
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < VW; ++k) acc[k] += v[u] * w[u][k];
     }
   }
-  for (int off = PP; off < PP * G; off <<= 1) acc += __shfl_xor(acc, off, 64);
-  return acc;
+#pragma unroll
+  for (int k = 0; k < VW; ++k)
+    for (int off = PPL; off < PPL * G; off <<= 1) acc[k] += __shfl_xor(acc[k], off, 64);
 }
 
 // One smoothing step or a residual on one level (see the mode bits).
-template <typename T, int PP, int NT, bool SEG>
+template <typename T, int PPL, int VW, int NT, bool SEG>
 __global__ void __launch_bounds__(NT)
 k_amg_step(int k, const KrylovCtl* ctl, int n, int p, int G, const int32_t* __restrict__ rowptr,
            const int32_t* __restrict__ colind, const T* __restrict__ val,
@@ -103,61 +146,89 @@ k_amg_step(int k, const KrylovCtl* ctl, int n, int p, int G, const int32_t* __re
            T* __restrict__ d, T* __restrict__ out, double s0, double cd, double ad, int mode,
            double* __restrict__ part) {
   if (ctl && finished_by(ctl, k)) return;
-  const int c = threadIdx.x % PP;
-  const int g = (threadIdx.x / PP) % G;
+  const int c0 = VW * (threadIdx.x % PPL);
+  const int g = (threadIdx.x / PPL) % G;
   const bool x0 = (mode & kAmgX0) != 0;
-  double rz = 0.0;
-  for (RowRange<NT, PP, SEG> rr(n, G); rr.r < rr.end; rr.r += rr.step) {
+  double rz[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) rz[q] = 0.0;
+  for (RowRange<NT, PPL, SEG> rr(n, G); rr.r < rr.end; rr.r += rr.step) {
     const int64_t row = rr.r;
     const int e0 = rowptr[row], e1 = rowptr[row + 1];
-    double acc;
-    if (x0)
-      acc = s0 * row_dot_split<T, PP, true>(colind, val, b, dinv, e0, e1, p, c, c < p, g, G);
-    else
-      acc = row_dot_split<T, PP, false>(colind, val, x, dinv, e0, e1, p, c, c < p, g, G);
-    if (c >= p || g != 0) continue;
-    const int64_t i = row * p + c;
-    const double bi = double(b[i]);
-    const double ri = bi - acc;
+    double acc[VW];
+    if (x0) {
+      row_dot_split<T, PPL, VW, true>(colind, val, b, dinv, e0, e1, p, c0, c0 < p, g, G, acc);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) acc[q] *= s0;
+    } else {
+      row_dot_split<T, PPL, VW, false>(colind, val, x, dinv, e0, e1, p, c0, c0 < p, g, G, acc);
+    }
+    if (c0 >= p || g != 0) continue;
+    const int64_t i = row * p + c0;
+    double bi[VW], o[VW];
+    load_vw<VW>(b + i, bi);
     if (mode & kAmgResid) {
-      out[i] = T(ri);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) o[q] = bi[q] - acc[q];
+      store_vw<VW>(out + i, o);
       continue;
     }
-    const double xi = x0 ? s0 * double(dinv[row]) * bi : double(x[i]);
-    double di = ad * double(dinv[row]) * ri;
-    if (mode & kAmgHasD) di += cd * (x0 ? xi : double(d[i]));
-    const T o = T(xi + di);
-    out[i] = o;
-    if (mode & kAmgWriteD) d[i] = T(di);
-    rz += bi * double(o);
+    const double dr = double(dinv[row]);
+    double xi[VW], di[VW], dold[VW];
+    if (x0) {
+#pragma unroll
+      for (int q = 0; q < VW; ++q) xi[q] = s0 * dr * bi[q];
+    } else {
+      load_vw<VW>(x + i, xi);
+    }
+    const bool hasd = (mode & kAmgHasD) != 0;
+    if (hasd && !x0) load_vw<VW>(d + i, dold);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      di[q] = ad * dr * (bi[q] - acc[q]);
+      if (hasd) di[q] += cd * (x0 ? xi[q] : dold[q]);
+      o[q] = double(T(xi[q] + di[q]));   // the value stored (and summed) in type T
+    }
+    store_vw<VW>(out + i, o);
+    if (mode & kAmgWriteD) store_vw<VW>(d + i, di);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) rz[q] += bi[q] * o[q];
   }
   if constexpr (NT == kCgThreads) {
     if (mode & kAmgRz) {
       __shared__ double red[kCgThreads];
-      write_col_partial<PP>(rz, red, part, 2 * PP, 0);
+      // column c0 + q of this lane into part[wg][0][c0 + q] (layout of PP = PPL VW)
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        wave_col_reduce<PPL, kCgThreads>(rz[q], red);
+        if (threadIdx.x < PPL)
+          part[size_t(blockIdx.x) * (2 * PPL * VW) + VW * threadIdx.x + q] = red[threadIdx.x];
+        __syncthreads();
+      }
     }
   }
 }
 
 // bc = R r (restriction to the next level; R = P^T in CSR)
-template <typename T, int PP, int NT, bool SEG>
+template <typename T, int PPL, int VW, int NT, bool SEG>
 __global__ void __launch_bounds__(NT)
 k_amg_restrict(int k, const KrylovCtl* ctl, int nc, int p, int G,
                const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
                const T* __restrict__ val, const T* __restrict__ r, T* __restrict__ bc) {
   if (ctl && finished_by(ctl, k)) return;
-  const int c = threadIdx.x % PP;
-  const int g = (threadIdx.x / PP) % G;
-  for (RowRange<NT, PP, SEG> rr(nc, G); rr.r < rr.end; rr.r += rr.step) {
+  const int c0 = VW * (threadIdx.x % PPL);
+  const int g = (threadIdx.x / PPL) % G;
+  for (RowRange<NT, PPL, SEG> rr(nc, G); rr.r < rr.end; rr.r += rr.step) {
     const int64_t row = rr.r;
-    const double acc = row_dot_split<T, PP, false>(colind, val, r, r, rowptr[row],
-                                                   rowptr[row + 1], p, c, c < p, g, G);
-    if (c < p && g == 0) bc[row * p + c] = T(acc);
+    double acc[VW];
+    row_dot_split<T, PPL, VW, false>(colind, val, r, r, rowptr[row], rowptr[row + 1], p, c0,
+                                     c0 < p, g, G, acc);
+    if (c0 < p && g == 0) store_vw<VW>(bc + row * p + c0, acc);
   }
 }
 
 // x = x_base + P xc with x_base = x, or s0 D^{-1} b (mode kAmgX0)
-template <typename T, int PP, int NT, bool SEG>
+template <typename T, int PPL, int VW, int NT, bool SEG>
 __global__ void __launch_bounds__(NT)
 k_amg_prolong(int k, const KrylovCtl* ctl, int n, int p, int G,
               const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
@@ -165,16 +236,27 @@ k_amg_prolong(int k, const KrylovCtl* ctl, int n, int p, int G,
               const T* __restrict__ dinv, const T* __restrict__ b, double s0, int mode,
               T* __restrict__ x) {
   if (ctl && finished_by(ctl, k)) return;
-  const int c = threadIdx.x % PP;
-  const int g = (threadIdx.x / PP) % G;
-  for (RowRange<NT, PP, SEG> rr(n, G); rr.r < rr.end; rr.r += rr.step) {
+  const int c0 = VW * (threadIdx.x % PPL);
+  const int g = (threadIdx.x / PPL) % G;
+  for (RowRange<NT, PPL, SEG> rr(n, G); rr.r < rr.end; rr.r += rr.step) {
     const int64_t row = rr.r;
-    const double corr = row_dot_split<T, PP, false>(colind, val, xc, xc, rowptr[row],
-                                                    rowptr[row + 1], p, c, c < p, g, G);
-    if (c >= p || g != 0) continue;
-    const int64_t i = row * p + c;
-    const double base = (mode & kAmgX0) ? s0 * double(dinv[row]) * double(b[i]) : double(x[i]);
-    x[i] = T(base + corr);
+    double corr[VW];
+    row_dot_split<T, PPL, VW, false>(colind, val, xc, xc, rowptr[row], rowptr[row + 1], p, c0,
+                                     c0 < p, g, G, corr);
+    if (c0 >= p || g != 0) continue;
+    const int64_t i = row * p + c0;
+    double base[VW];
+    if (mode & kAmgX0) {
+      load_vw<VW>(b + i, base);
+      const double sd = s0 * double(dinv[row]);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) base[q] *= sd;
+    } else {
+      load_vw<VW>(x + i, base);
+    }
+#pragma unroll
+    for (int q = 0; q < VW; ++q) base[q] += corr[q];
+    store_vw<VW>(x + i, base);
   }
 }
 

@@ -465,10 +465,14 @@ void amg_vectors(AmgDev& H, int p, size_t el) {
 }
 
 // out = V-cycle(b) on level l (level 0: the inner solver's launch shape,
-// and with part_rz the (b, out) partials of the last smoothing step).
-template <typename T, int PP>
-void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
-               const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
+// and with part_rz the (b, out) partials of the last smoothing step).  The
+// kernels take VW columns per lane and PPL = PP / VW lanes per row; the finest
+// level keeps the inner solver's grid (its partials are re-summed by the CG
+// kernels over that many workgroups).
+template <typename T, int PPL, int VW>
+void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
+                  const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
+  constexpr int PP = PPL * VW;
   AmgDevLevel& L = *H.lv[l];
   hipStream_t s = pl->stream;
   const int n = int(L.n);
@@ -482,8 +486,8 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
   const LevelVals<T> lv = vals_of(L, T());
   const bool fine = (l == 0);
   const int gfine = cg_grid(n, PP);
-  const int GA = row_split(L.avg_a, PP), GP = row_split(L.avg_p, PP);
-  const int gcoarse_a = grid_for(n, PP * GA, 4096), gcoarse_p = grid_for(n, PP * GP, 4096);
+  const int GA = row_split(L.avg_a, PPL), GP = row_split(L.avg_p, PPL);
+  const int gcoarse_a = grid_for(n, PPL * GA, 4096), gcoarse_p = grid_for(n, PPL * GP, 4096);
   auto step = [&](int mode, const T* x, T* o, double cd, double ad, double* part) {
     T* d = reinterpret_cast<T*>(L.vd.p);
     if (fine) {
@@ -493,13 +497,13 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
         e1 = sev[2 * *nsev + 1];
         *nsev += 1;
       }
-      hipExtLaunchKernelGGL((k_amg_step<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads),
-                            0, s, e0, e1, 0, k, ctl, n, p, GA, L.arp, L.aci, lv.a, dinv, b, x, d,
-                            o, L.ad[0], cd, ad, mode, part);
+      hipExtLaunchKernelGGL((k_amg_step<T, PPL, VW, kCgThreads, true>), dim3(gfine),
+                            dim3(kCgThreads), 0, s, e0, e1, 0, k, ctl, n, p, GA, L.arp, L.aci,
+                            lv.a, dinv, b, x, d, o, L.ad[0], cd, ad, mode, part);
     } else
-      hipLaunchKernelGGL((k_amg_step<T, PP, kThreads, false>), dim3(gcoarse_a), dim3(kThreads), 0,
-                         s, k, ctl, n, p, GA, L.arp, L.aci, lv.a, dinv, b, x, d, o, L.ad[0], cd,
-                         ad, mode, part);
+      hipLaunchKernelGGL((k_amg_step<T, PPL, VW, kThreads, false>), dim3(gcoarse_a),
+                         dim3(kThreads), 0, s, k, ctl, n, p, GA, L.arp, L.aci, lv.a, dinv, b, x,
+                         d, o, L.ad[0], cd, ad, mode, part);
   };
   T* x = reinterpret_cast<T*>(L.vu.p);
   T* y = reinterpret_cast<T*>(L.vv.p);
@@ -521,21 +525,21 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
     hipLaunchKernelGGL((k_amg_dense<T, PP>), dim3(std::max(1, std::min(nc, 1024))), dim3(1024),
                        0, s, k, ctl, nc, n, p, H.cinvR.p, r, xc);
   } else {
-    const int GR = row_split(L.avg_r, PP);
-    hipLaunchKernelGGL((k_amg_restrict<T, PP, kThreads, false>),
-                       dim3(grid_for(nc, PP * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p, GR,
-                       L.Rrp.p, L.Rci.p, lv.r, r, bc);
-    amg_level<T, PP>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+    const int GR = row_split(L.avg_r, PPL);
+    hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
+                       dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
+                       GR, L.Rrp.p, L.Rci.p, lv.r, r, bc);
+    amg_level_vw<T, PPL, VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
   }
   const int pmode = implicit ? kAmgX0 : 0;
   if (fine)
-    hipLaunchKernelGGL((k_amg_prolong<T, PP, kCgThreads, true>), dim3(gfine), dim3(kCgThreads), 0,
-                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv, b, L.ad[0], pmode,
-                       x);
+    hipLaunchKernelGGL((k_amg_prolong<T, PPL, VW, kCgThreads, true>), dim3(gfine),
+                       dim3(kCgThreads), 0, s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv,
+                       b, L.ad[0], pmode, x);
   else
-    hipLaunchKernelGGL((k_amg_prolong<T, PP, kThreads, false>), dim3(gcoarse_p), dim3(kThreads), 0,
-                       s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv, b, L.ad[0], pmode,
-                       x);
+    hipLaunchKernelGGL((k_amg_prolong<T, PPL, VW, kThreads, false>), dim3(gcoarse_p),
+                       dim3(kThreads), 0, s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv,
+                       b, L.ad[0], pmode, x);
   // post-smoothing from x, the same polynomial (symmetric V-cycle)
   for (int st = 0; st < H.degree; ++st) {
     const bool last = (st + 1 == H.degree);
@@ -545,6 +549,19 @@ void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, in
     step(mode, x, o, L.cd[st], L.ad[st], last ? part_rz : nullptr);
     if (!last) std::swap(x, y);
   }
+}
+
+// two adjacent columns per lane when p is even
+template <typename T, int PP>
+void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
+               const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
+  if constexpr (PP >= 2) {
+    if (p % 2 == 0) {
+      amg_level_vw<T, PP / 2, 2>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
+      return;
+    }
+  }
+  amg_level_vw<T, PP, 1>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
 }
 
 // The hierarchy for K (transpose = 0) or K^T; NULL without AMG.
