@@ -236,6 +236,24 @@ int grid_for(int64_t rows, int PP, int cap = 1024) {
     default: { constexpr int P_ = 32; __VA_ARGS__; } break; \
   }
 
+// CG kernels: PPL_ lanes per row with VW_ adjacent columns each (VW_ = 2 for
+// even p), PPL_ VW_ = PP
+#define CG_CASE(PPV, p, ...)                                                \
+  case PPV:                                                                 \
+    if (PPV >= 2 && (p) % 2 == 0) {                                         \
+      constexpr int PPL_ = (PPV >= 2 ? PPV / 2 : 1), VW_ = (PPV >= 2 ? 2 : 1); \
+      __VA_ARGS__;                                                          \
+    } else {                                                                \
+      constexpr int PPL_ = PPV, VW_ = 1;                                    \
+      __VA_ARGS__;                                                          \
+    }                                                                       \
+    break;
+#define DISPATCH_CG(PP, p, ...)                                                       \
+  switch (PP) {                                                                       \
+    CG_CASE(1, p, __VA_ARGS__) CG_CASE(2, p, __VA_ARGS__) CG_CASE(4, p, __VA_ARGS__)  \
+    CG_CASE(8, p, __VA_ARGS__) CG_CASE(16, p, __VA_ARGS__) CG_CASE(32, p, __VA_ARGS__) \
+  }
+
 void ensure_workspace(expmv_plan_s* pl, int p) {
   Workspace& w = pl->ws;
   const int64_t n = pl->n;
@@ -610,7 +628,7 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
     r32 = w.kr32.p;
     z32 = w.kz32.p;
   }
-  DISPATCH_PP(PP, hipLaunchKernelGGL((k_cg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+  DISPATCH_CG(PP, p, hipLaunchKernelGGL((k_cg_init<T, T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0, s,
                                      int(n), p, sign, src, A.dinv, out, r, P[0], w.ctl.p,
                                      w.part_rr.p, r32));
   auto vcycle = [&](int k, hipEvent_t* sev, int* nsev) {
@@ -636,21 +654,21 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
         pl->pev_used += 1;
       }
       if (v32) {
-        DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, float, P_>), dim3(grid), dim3(kCgThreads),
+        DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_c<T, float, PPL_, VW_>), dim3(grid), dim3(kCgThreads),
                                               0, s, sample ? e[0] : ez, sample ? e[1] : ez, 0, k,
                                               int(n), p, A.dinv, r, z32, pold, pnew, out, w.cgst.p,
                                               w.ctl.p, w.part_rr.p, tol2, maxit));
       } else {
-        DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_c<T, T, P_>), dim3(grid), dim3(kCgThreads), 0,
+        DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_c<T, T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0,
                                               s, sample ? e[0] : ez, sample ? e[1] : ez, 0, k,
                                               int(n), p, A.dinv, r, z, pold, pnew, out, w.cgst.p,
                                               w.ctl.p, w.part_rr.p, tol2, maxit));
       }
-      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_a<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+      DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_a<T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0, s,
                                             sample ? e[2] : ez, sample ? e[3] : ez, 0, k, int(n),
                                             p, A.rowptr, A.colind, A.val, pnew, q, w.ctl.p,
                                             w.part_sig.p));
-      DISPATCH_PP(PP, hipExtLaunchKernelGGL((k_cg_b<T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
+      DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_b<T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0, s,
                                             sample ? e[4] : ez, sample ? e[5] : ez, 0, k, int(n),
                                             p, A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
                                             w.part_rr.p, amg ? 0 : 1, r32));

@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace expmv {
 
@@ -227,31 +228,122 @@ __device__ inline void write_col_partial(double v, double* red, double* part, in
   __syncthreads();
 }
 
-template <typename T, typename TS, int PP>
+// The same layout when each lane holds VW adjacent columns: lane l's value q
+// is column VW l + q of the PPL VW columns.
+template <int PPL, int VW>
+__device__ inline void write_col_partial_vw(const double (&v)[VW], double* red, double* part,
+                                            int stride, int off) {
+#pragma unroll
+  for (int q = 0; q < VW; ++q) {
+    wave_col_reduce<PPL, kCgThreads>(v[q], red);
+    if (threadIdx.x < PPL)
+      part[size_t(blockIdx.x) * stride + off + VW * threadIdx.x + q] = red[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// VW adjacent entries of a row-major block in the block's own type (VW = 2:
+// one 2-element access; the offset is even, so it is aligned)
+template <int VW, typename T>
+__device__ inline void ld_vw(const T* __restrict__ src, T (&o)[VW]) {
+  if constexpr (VW == 1) {
+    o[0] = src[0];
+  } else if constexpr (std::is_same<T, double>::value) {
+    const double2 v = *reinterpret_cast<const double2*>(src);
+    o[0] = v.x;
+    o[1] = v.y;
+  } else {
+    const float2 v = *reinterpret_cast<const float2*>(src);
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+}
+template <int VW, typename T>
+__device__ inline void st_vw(T* __restrict__ dst, const T (&o)[VW]) {
+  if constexpr (VW == 1) {
+    dst[0] = o[0];
+  } else if constexpr (std::is_same<T, double>::value) {
+    *reinterpret_cast<double2*>(dst) = double2{o[0], o[1]};
+  } else {
+    *reinterpret_cast<float2*>(dst) = float2{o[0], o[1]};
+  }
+}
+
+// csr_row_dot for the VW columns c0 .. c0 + VW - 1 (sums in FP64)
+template <int VW, typename T>
+__device__ inline void csr_row_dot_vw(const int32_t* __restrict__ colind,
+                                      const double* __restrict__ val, const T* __restrict__ x,
+                                      int e0, int e1, int ld, int c0, double (&acc)[VW]) {
+  constexpr int U = 8;
+#pragma unroll
+  for (int q = 0; q < VW; ++q) acc[q] = 0.0;
+  for (int e = e0; e < e1; e += U) {
+    int32_t j[U];
+    double v[U];
+    T w[U][VW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e + u < e1;
+      j[u] = ok ? colind[e + u] : -1;
+      v[u] = ok ? val[e + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j[u] >= 0) {
+        ld_vw<VW>(x + int64_t(j[u]) * ld + c0, w[u]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < VW; ++q) w[u][q] = T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < VW; ++q) acc[q] += v[u] * double(w[u][q]);
+  }
+}
+
+// The CG kernels take VW adjacent columns per lane (VW = 2 for even p) and
+// PPL = PP / VW lanes per row; per-column scalars and partials keep the layout
+// of PP columns.
+template <typename T, typename TS, int PPL, int VW>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __restrict__ dinv,
           T* __restrict__ x, T* __restrict__ r, T* __restrict__ pold,
           KrylovCtl* ctl, double* __restrict__ part_rr, float* __restrict__ r32) {
+  constexpr int PP = PPL * VW;
   __shared__ double red[kCgThreads];
-  const int c = threadIdx.x % PP;
-  double rz = 0.0, bb = 0.0;
+  const int c0 = VW * (threadIdx.x % PPL);
+  double rz[VW], bb[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) rz[q] = bb[q] = 0.0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
-      const int64_t i = row * p + c;
-      const T b = T(sign * double(src[i]));
-      r[i] = b;
-      if (r32) r32[i] = float(b);   // input of an FP32 preconditioner
-      x[i] = T(0);
-      pold[i] = T(0);
-      const double bd = double(b);
-      rz += bd * double(dinv[row]) * bd;
-      bb += bd * bd;
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
+      const int64_t i = row * p + c0;
+      TS sv[VW];
+      ld_vw<VW>(src + i, sv);
+      T b[VW], zero[VW];
+      float b32[VW];
+      const double dr = double(dinv[row]);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        b[q] = T(sign * double(sv[q]));
+        zero[q] = T(0);
+        b32[q] = float(b[q]);
+        const double bd = double(b[q]);
+        rz[q] += bd * dr * bd;
+        bb[q] += bd * bd;
+      }
+      st_vw<VW>(r + i, b);
+      if (r32) st_vw<VW>(r32 + i, b32);   // input of an FP32 preconditioner
+      st_vw<VW>(x + i, zero);
+      st_vw<VW>(pold + i, zero);
     }
   }
-  write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
-  write_col_partial<PP>(bb, red, part_rr, 2 * PP, PP);
+  write_col_partial_vw<PPL, VW>(rz, red, part_rr, 2 * PP, 0);
+  write_col_partial_vw<PPL, VW>(bb, red, part_rr, 2 * PP, PP);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->done = -1;
     ctl->iters_max = 0;
@@ -262,12 +354,13 @@ k_cg_init(int n, int p, double sign, const TS* __restrict__ src, const T* __rest
 
 // z: the preconditioned residual (TZ = float for an FP32 V-cycle), or NULL
 // for Jacobi (D^{-1} r formed here)
-template <typename T, typename TZ, int PP>
+template <typename T, typename TZ, int PPL, int VW>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
        const TZ* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
        T* __restrict__ x, CgState* st, KrylovCtl* ctl, const double* __restrict__ part_rr,
        double tol2, int maxit) {
+  constexpr int PP = PPL * VW;
   if (finished_before(ctl, k)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
@@ -322,48 +415,84 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
     }
   }
   __syncthreads();
-  const int c = threadIdx.x % PP;
-  const T beta = T(s_beta[c]), aprev = T(s_aprev[c]);
+  const int c0 = VW * (threadIdx.x % PPL);
+  T beta[VW], aprev[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) {
+    beta[q] = T(s_beta[(c0 + q) % PP]);
+    aprev[q] = T(s_aprev[(c0 + q) % PP]);
+  }
   const bool any = s_any != 0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
-      const int64_t i = row * p + c;
-      const T po = pold[i];
-      x[i] += aprev * po;
-      if (any) pnew[i] = (z ? T(z[i]) : dinv[row] * r[i]) + beta * po;
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
+      const int64_t i = row * p + c0;
+      T po[VW], xv[VW];
+      ld_vw<VW>(pold + i, po);
+      ld_vw<VW>(x + i, xv);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) xv[q] += aprev[q] * po[q];
+      st_vw<VW>(x + i, xv);
+      if (any) {
+        T zv[VW];
+        if (z) {
+          TZ zz[VW];
+          ld_vw<VW>(z + i, zz);
+#pragma unroll
+          for (int q = 0; q < VW; ++q) zv[q] = T(zz[q]);
+        } else {
+          T rv[VW];
+          ld_vw<VW>(r + i, rv);
+          const T dr = dinv[row];
+#pragma unroll
+          for (int q = 0; q < VW; ++q) zv[q] = dr * rv[q];
+        }
+#pragma unroll
+        for (int q = 0; q < VW; ++q) zv[q] = zv[q] + beta[q] * po[q];
+        st_vw<VW>(pnew + i, zv);
+      }
     }
   }
 }
 
-template <typename T, int PP>
+template <typename T, int PPL, int VW>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_a(int k, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
        const double* __restrict__ val, const T* __restrict__ pk, T* __restrict__ q,
        const KrylovCtl* ctl, double* __restrict__ part_sig) {
+  constexpr int PP = PPL * VW;
   if (finished_by(ctl, k)) return;
   __shared__ double red[kCgThreads];
-  const int c = threadIdx.x % PP;
-  double sig = 0.0;
+  const int c0 = VW * (threadIdx.x % PPL);
+  double sig[VW];
+#pragma unroll
+  for (int u = 0; u < VW; ++u) sig[u] = 0.0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
-      const T acc = csr_row_dot(colind, val, pk, rowptr[row], rowptr[row + 1], p, c);
-      const int64_t i = row * p + c;
-      q[i] = acc;
-      sig += double(pk[i]) * double(acc);
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
+      double acc[VW];
+      csr_row_dot_vw<VW>(colind, val, pk, rowptr[row], rowptr[row + 1], p, c0, acc);
+      const int64_t i = row * p + c0;
+      T qv[VW], pv[VW];
+#pragma unroll
+      for (int u = 0; u < VW; ++u) qv[u] = T(acc[u]);
+      st_vw<VW>(q + i, qv);
+      ld_vw<VW>(pk + i, pv);
+#pragma unroll
+      for (int u = 0; u < VW; ++u) sig[u] += double(pv[u]) * double(qv[u]);
     }
   }
-  write_col_partial<PP>(sig, red, part_sig, PP, 0);
+  write_col_partial_vw<PPL, VW>(sig, red, part_sig, PP, 0);
 }
 
-template <typename T, int PP>
+template <typename T, int PPL, int VW>
 __global__ void __launch_bounds__(kCgThreads)
 k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const T* __restrict__ q,
        CgState* st, const KrylovCtl* ctl, const double* __restrict__ part_sig,
        double* __restrict__ part_rr, int jacobi, float* __restrict__ r32) {
+  constexpr int PP = PPL * VW;
   if (finished_by(ctl, k)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[PP];
@@ -380,24 +509,37 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
     s_alpha[cc] = a;
   }
   __syncthreads();
-  const int c = threadIdx.x % PP;
-  const T alpha = T(s_alpha[c]);
-  double rz = 0.0, rr = 0.0;
+  const int c0 = VW * (threadIdx.x % PPL);
+  T alpha[VW];
+#pragma unroll
+  for (int u = 0; u < VW; ++u) alpha[u] = T(s_alpha[(c0 + u) % PP]);
+  double rz[VW], rr[VW];
+#pragma unroll
+  for (int u = 0; u < VW; ++u) rz[u] = rr[u] = 0.0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
-      const int64_t i = row * p + c;
-      const T rn = r[i] - alpha * q[i];
-      r[i] = rn;
-      if (r32) r32[i] = float(rn);   // input of an FP32 preconditioner
-      const double rd = double(rn);
-      if (jacobi) rz += rd * double(dinv[row]) * rd;
-      rr += rd * rd;
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
+      const int64_t i = row * p + c0;
+      T rv[VW], qv[VW];
+      float r32v[VW];
+      ld_vw<VW>(r + i, rv);
+      ld_vw<VW>(q + i, qv);
+      const double dr = jacobi ? double(dinv[row]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        rv[u] = rv[u] - alpha[u] * qv[u];
+        r32v[u] = float(rv[u]);
+        const double rd = double(rv[u]);
+        if (jacobi) rz[u] += rd * dr * rd;
+        rr[u] += rd * rd;
+      }
+      st_vw<VW>(r + i, rv);
+      if (r32) st_vw<VW>(r32 + i, r32v);   // input of an FP32 preconditioner
     }
   }
-  if (jacobi) write_col_partial<PP>(rz, red, part_rr, 2 * PP, 0);
-  write_col_partial<PP>(rr, red, part_rr, 2 * PP, PP);
+  if (jacobi) write_col_partial_vw<PPL, VW>(rz, red, part_rr, 2 * PP, 0);
+  write_col_partial_vw<PPL, VW>(rr, red, part_rr, 2 * PP, PP);
 }
 
 // ---------------------------------------------------------------------------
