@@ -109,6 +109,10 @@ typedef struct {
                           test stay FP64, so the result's accuracy is unchanged and
                           only the iteration count can move.  0 (default): FP64
                           V-cycle.  The mixed forms always use FP32.                  */
+  int amg_coarse_degree; /* Chebyshev smoothing steps on the levels below the finest
+                          (1..4; 0 = amg_degree's value).  Each level uses one
+                          polynomial before and after its coarse correction, so the
+                          V-cycle stays symmetric.                                     */
 } expmv_opts;
 
 typedef struct {                  /* host struct, filled by expmv_execute */

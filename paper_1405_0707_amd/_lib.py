@@ -18,7 +18,8 @@ class Opts(C.Structure):
                 ("precision", C.c_int), ("stop_rule", C.c_int), ("inner_tol", C.c_double),
                 ("inner_maxit", C.c_int), ("symmetric", C.c_int), ("preconditioned", C.c_int),
                 ("profile", C.c_int), ("inner_refine", C.c_int), ("inner_precond", C.c_int),
-                ("amg_degree", C.c_int), ("inner_relax", C.c_int), ("amg_fp32", C.c_int)]
+                ("amg_degree", C.c_int), ("inner_relax", C.c_int), ("amg_fp32", C.c_int),
+                ("amg_coarse_degree", C.c_int)]
 
 
 class Info(C.Structure):

@@ -131,6 +131,7 @@ struct AmgDevLevel {
   DevBuf<float> dinvf;
   DevBuf<float> Av32, Pv32, Rv32;   // FP32 copies of the values (FP32 V-cycles)
   double cd[kAmgMaxDeg] = {}, ad[kAmgMaxDeg] = {};   // Chebyshev step coefficients
+  int degree = 2;                                    // smoothing steps before / after
   double avg_a = 0.0, avg_p = 0.0, avg_r = 0.0;      // mean nonzeros per row of A, P, R
   DevBuf<char> vb, vu, vv, vd, vr, vo;
 };
@@ -527,7 +528,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
   T* y = reinterpret_cast<T*>(L.vv.p);
   // pre-smoothing from zero: the first step's iterate s0 D^{-1} b stays implicit
   bool implicit = true;
-  for (int st = 1; st < H.degree; ++st) {
+  for (int st = 1; st < L.degree; ++st) {
     step(kAmgHasD | kAmgWriteD | (implicit ? kAmgX0 : 0), x, y, L.cd[st], L.ad[st], nullptr);
     implicit = false;
     std::swap(x, y);
@@ -559,8 +560,8 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
                        dim3(kThreads), 0, s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv,
                        b, L.ad[0], pmode, x);
   // post-smoothing from x, the same polynomial (symmetric V-cycle)
-  for (int st = 0; st < H.degree; ++st) {
-    const bool last = (st + 1 == H.degree);
+  for (int st = 0; st < L.degree; ++st) {
+    const bool last = (st + 1 == L.degree);
     T* o = last ? out : y;
     const int mode = (st > 0 ? kAmgHasD : 0) | (last ? 0 : kAmgWriteD) |
                      (last && part_rz ? kAmgRz : 0);
@@ -1686,6 +1687,7 @@ bool valid_opts(const expmv_opts& o) {
   if (o.amg_degree < 0 || o.amg_degree > kAmgMaxDeg) return false;
   if (o.inner_relax < 0 || o.inner_relax > 10) return false;
   if (o.amg_fp32 != 0 && o.amg_fp32 != 1) return false;
+  if (o.amg_coarse_degree < 0 || o.amg_coarse_degree > kAmgMaxDeg) return false;
   return true;
 }
 
@@ -1903,7 +1905,8 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
       L->avg_p = double(Lh.P.nnz()) / double(std::max<int64_t>(1, Lh.P.nrows));
       L->avg_r = double(Lh.R.nnz()) / double(std::max<int64_t>(1, Lh.R.nrows));
     }
-    chebyshev_coefficients(Lh.lmax, H->degree, L->cd, L->ad);
+    L->degree = (l > 0 && pl->opts.amg_coarse_degree > 0) ? pl->opts.amg_coarse_degree : H->degree;
+    chebyshev_coefficients(Lh.lmax, L->degree, L->cd, L->ad);
     H->lv.push_back(std::move(L));
   }
   upload_vec(H->cinv, h.coarse_inv);
@@ -2144,6 +2147,7 @@ expmv_status expmv_default_opts(expmv_opts* o) {
   o->amg_degree = 0;
   o->inner_relax = 8;
   o->amg_fp32 = 0;
+  o->amg_coarse_degree = 0;
   return EXPMV_OK;
 }
 
