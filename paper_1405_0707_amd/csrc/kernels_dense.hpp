@@ -285,9 +285,7 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
   cplx* A = Ascr + size_t(j) * d * d;
   cplx* Z = Zs + size_t(j) * d * p;
   const cplx* Gj = G + size_t(j) * d * p;
-  __shared__ double sval[1024];
-  __shared__ int sidx[1024];
-  __shared__ int piv_s;
+  __shared__ int s_piv, s_zero;
   for (int idx = tid; idx < d * d; idx += nt) {
     const int r = idx / d, c = idx % d;
     const double h = H[int64_t(r) * ldh + c];
@@ -308,35 +306,38 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
   __syncthreads();
   int sing = 0;
   for (int c = 0; c < d; ++c) {
-    // pivot search
-    double best = -1.0;
-    int bi = c;
-    for (int r = c + tid; r < d; r += nt) {
-      const cplx a = A[r * d + c];
-      const double v = a.x * a.x + a.y * a.y;
-      if (v > best) {
-        best = v;
-        bi = r;
-      }
-    }
-    sval[tid] = best;
-    sidx[tid] = bi;
-    __syncthreads();
-    for (int st = nt / 2; st >= 1; st >>= 1) {
-      if (tid < st) {
-        const double o = sval[tid + st];
-        const int oi = sidx[tid + st];
-        if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
-          sval[tid] = o;
-          sidx[tid] = oi;
+    // pivot: the first row of largest |a|^2 in column c, by one wavefront
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = c;
+      for (int r = c + tid; r < d; r += 64) {
+        const cplx a = A[r * d + c];
+        const double v = a.x * a.x + a.y * a.y;
+        if (v > best) {
+          best = v;
+          bi = r;
         }
       }
-      __syncthreads();
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_piv = bi;
+        s_zero = !(best > 0.0);
+      }
     }
-    if (tid == 0) piv_s = sidx[0];
-    if (sval[0] <= 0.0) sing = 1;
     __syncthreads();
-    const int pv = piv_s;
+    const int pv = s_piv;
+    if (s_zero) {   // zero column: singular, nothing to eliminate
+      sing = 1;
+      __syncthreads();   // every thread has read s_piv, s_zero before the next pivot
+      continue;
+    }
     if (pv != c) {
       for (int cc = c + tid; cc < d; cc += nt) {
         const cplx t0 = A[c * d + cc];
@@ -350,20 +351,14 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
       }
     }
     __syncthreads();
+    // rows below: multiplier l_r = a_rc / a_cc formed where it is used
     const cplx diag = A[c * d + c];
-    if (diag.x == 0.0 && diag.y == 0.0) {
-      sing = 1;
-      __syncthreads();
-      continue;
-    }
-    for (int r = c + 1 + tid; r < d; r += nt) A[r * d + c] = cdiv(A[r * d + c], diag);
-    __syncthreads();
     const int m1 = d - c - 1;
     const int wide = m1 + p;
     for (int idx = tid; idx < m1 * wide; idx += nt) {
       const int r = c + 1 + idx / wide;
       const int cc = idx % wide;
-      const cplx l = A[r * d + c];
+      const cplx l = cdiv(A[r * d + c], diag);
       if (cc < m1) {
         const int col = c + 1 + cc;
         A[r * d + col] = csub(A[r * d + col], cmul(l, A[c * d + col]));
@@ -374,18 +369,26 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
     }
     __syncthreads();
   }
-  // back substitution
+  // back substitution, one barrier per column: every thread forms
+  // x_c = z_c / u_cc itself; row c of Z is overwritten by x_c one step
+  // later, when no thread reads it any more
+  auto xval = [&](int c, int b) -> cplx {
+    const cplx dg = A[c * d + c];
+    return (dg.x == 0.0 && dg.y == 0.0) ? cplx{0.0, 0.0} : cdiv(Z[c * p + b], dg);
+  };
   for (int c = d - 1; c >= 0; --c) {
-    const cplx diag = A[c * d + c];
-    if (tid < p) Z[c * p + tid] = (diag.x == 0.0 && diag.y == 0.0) ? cplx{0.0, 0.0}
-                                                                   : cdiv(Z[c * p + tid], diag);
-    __syncthreads();
+    cplx xn{0.0, 0.0};
+    const bool wr = c + 1 < d && tid < p;
+    if (wr) xn = xval(c + 1, tid);
     for (int idx = tid; idx < c * p; idx += nt) {
       const int r = idx / p, b = idx % p;
-      Z[r * p + b] = csub(Z[r * p + b], cmul(A[r * d + c], Z[c * p + b]));
+      Z[r * p + b] = csub(Z[r * p + b], cmul(A[r * d + c], xval(c, b)));
     }
+    if (wr) Z[(c + 1) * p + tid] = xn;
     __syncthreads();
   }
+  if (tid < p) Z[tid] = xval(0, tid);   // row 0: each thread its own entry
+  __syncthreads();
   if (tid == 0 && sing) singular[j] = 1;
   // update coefficients Cr (rows d+p, ld ldc = 2 p x shifts): real part then
   // imaginary part

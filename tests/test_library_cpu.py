@@ -75,3 +75,29 @@ def test_host_general_eig(n):
     V = Vr + 1j * Vi
     res = np.abs(A @ V - V * ev[None, :]).max()
     assert res < 1e-9 * np.abs(ref).max()
+
+
+def test_default_options_and_range_checks():
+    """expmv_default_opts fills the documented defaults; expmv_plan_csr
+    rejects an out-of-range option with EINVAL before it touches a device
+    (the pointers below are never dereferenced)."""
+    import ctypes as C
+
+    import numpy as np
+
+    from paper_1405_0707_amd import _lib
+    o = _lib.Opts()
+    assert _lib.lib().expmv_default_opts(C.byref(o)) == 0
+    assert (o.m, o.inner_relax, o.amg_fp32, o.amg_coarse_degree, o.inner_precond) == (10, 8, 0, 0, -1)
+    dummy = np.zeros(4)
+    ptr = dummy.ctypes.data
+    bad = [("amg_fp32", 2), ("amg_coarse_degree", 5), ("amg_coarse_degree", -1), ("amg_degree", -1),
+           ("inner_relax", 11), ("m", 1), ("m", 65), ("inner_precond", 2), ("precision", 7)]
+    for field, value in bad:
+        q = _lib.Opts()
+        _lib.lib().expmv_default_opts(C.byref(q))
+        setattr(q, field, value)
+        h = C.c_void_p()
+        st = _lib.lib().expmv_plan_csr(2, 2, ptr, ptr, ptr, 1.0, C.byref(q), None, C.byref(h))
+        assert st == _lib.EINVAL, (field, value, st)
+        assert not h.value
