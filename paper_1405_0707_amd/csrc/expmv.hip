@@ -681,6 +681,22 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
   return res;
 }
 
+// BiCGStab's SpMM (k_bcg_s) with two adjacent columns per lane for even p
+template <typename T, int PP, int NV>
+void bcg_spmm(hipStream_t s, int grid, int i, int n, int p, const int32_t* rowptr,
+              const int32_t* colind, const double* val, const T* dinv, const T* in, const T* a,
+              T* out, const KrylovCtl* ctl, double* part) {
+  if constexpr (PP >= 2) {
+    if (p % 2 == 0) {
+      hipLaunchKernelGGL((k_bcg_s<T, PP / 2, 2, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,
+                         rowptr, colind, val, dinv, in, a, out, ctl, part);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_bcg_s<T, PP, 1, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p, rowptr,
+                     colind, val, dinv, in, a, out, ctl, part);
+}
+
 // out = K^{-1} (sign * src) (or K^{-T}) by batched BiCGStab with right
 // Jacobi preconditioning (K nonsymmetric).
 template <typename T>
@@ -715,15 +731,13 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
         hipLaunchKernelGGL((k_bcg_u1<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
                            r, pv, v, w.bcgst.p, w.ctl.p, w.part_rr.p, tol2, maxit);
         if (H) amg_vcycle<T>(pl, *H, p, pv, ph, i, w.ctl.p, nullptr);
-        hipLaunchKernelGGL((k_bcg_s<T, P_, 1>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
-                           A.rowptr, A.colind, A.val, dscale, H ? ph : pv, rh, v, w.ctl.p,
-                           w.part_sig.p);
+        bcg_spmm<T, P_, 1>(s, grid, i, int(n), p, A.rowptr, A.colind, A.val, dscale, H ? ph : pv,
+                           rh, v, w.ctl.p, w.part_sig.p);
         hipLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p, r,
                            v, sv, w.bcgst.p, w.ctl.p, w.part_sig.p);
         if (H) amg_vcycle<T>(pl, *H, p, sv, sh, i, w.ctl.p, nullptr);
-        hipLaunchKernelGGL((k_bcg_s<T, P_, 2>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
-                           A.rowptr, A.colind, A.val, dscale, H ? sh : sv, sv, tv, w.ctl.p,
-                           w.part_sig.p);
+        bcg_spmm<T, P_, 2>(s, grid, i, int(n), p, A.rowptr, A.colind, A.val, dscale, H ? sh : sv,
+                           sv, tv, w.ctl.p, w.part_sig.p);
         hipLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
                            A.dinv, pv, sv, tv, rh, ph, sh, out, r, w.bcgst.p, w.ctl.p,
                            w.part_sig.p, w.part_rr.p);

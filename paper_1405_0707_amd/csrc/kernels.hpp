@@ -682,40 +682,55 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
 
 // out = K D^{-1} in (out = K in when dinv is NULL: the input is already
 // preconditioned), partials (a, out) [NV = 1] or (out, a), (out, out) [NV = 2]
-template <typename T, int PP, int NV>
+template <typename T, int PPL, int VW, int NV>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
         const double* __restrict__ val, const T* __restrict__ dinv, const T* __restrict__ in,
         const T* __restrict__ a, T* __restrict__ out, const KrylovCtl* ctl,
         double* __restrict__ part) {
+  constexpr int PP = PPL * VW;
   if (finished_by(ctl, i)) return;
   __shared__ double red[kCgThreads];
-  const int c = threadIdx.x % PP;
-  double d0 = 0.0, d1 = 0.0;
+  const int c0 = VW * (threadIdx.x % PPL);
+  double d0[VW], d1[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) d0[q] = d1[q] = 0.0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
       const int e0 = rowptr[row], e1 = rowptr[row + 1];
-      double accd = 0.0;
+      double accd[VW];
       if (dinv) {
+#pragma unroll
+        for (int q = 0; q < VW; ++q) accd[q] = 0.0;
         for (int e = e0; e < e1; ++e) {
           const int64_t j = colind[e];
-          accd += val[e] * double(dinv[j] * in[j * p + c]);
+          T xv[VW];
+          ld_vw<VW>(in + j * p + c0, xv);
+          const T dj = dinv[j];
+#pragma unroll
+          for (int q = 0; q < VW; ++q) accd[q] += val[e] * double(dj * xv[q]);
         }
       } else {
-        accd = double(csr_row_dot(colind, val, in, e0, e1, p, c));
+        csr_row_dot_vw<VW>(colind, val, in, e0, e1, p, c0, accd);
       }
-      const T acc = T(accd);
-      const int64_t idx = row * p + c;
-      out[idx] = acc;
-      const double o = double(acc), av = double(a[idx]);
-      d0 += av * o;
-      if (NV == 2) d1 += o * o;
+      const int64_t idx = row * p + c0;
+      T acc[VW], av[VW];
+#pragma unroll
+      for (int q = 0; q < VW; ++q) acc[q] = T(accd[q]);
+      st_vw<VW>(out + idx, acc);
+      ld_vw<VW>(a + idx, av);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        const double o = double(acc[q]);
+        d0[q] += double(av[q]) * o;
+        if (NV == 2) d1[q] += o * o;
+      }
     }
   }
-  write_col_partial<PP>(d0, red, part, NV * PP, 0);
-  if (NV == 2) write_col_partial<PP>(d1, red, part, NV * PP, PP);
+  write_col_partial_vw<PPL, VW>(d0, red, part, NV * PP, 0);
+  if (NV == 2) write_col_partial_vw<PPL, VW>(d1, red, part, NV * PP, PP);
 }
 
 template <typename T, int PP>
