@@ -110,9 +110,9 @@ typedef struct {
                           only the iteration count can move.  0 (default): FP64
                           V-cycle.  The mixed forms always use FP32.                  */
   int amg_coarse_degree; /* Chebyshev smoothing steps on the levels below the finest
-                          (1..4; 0 = amg_degree's value).  Each level uses one
-                          polynomial before and after its coarse correction, so the
-                          V-cycle stays symmetric.                                     */
+                          (1..4; 0 = one less than the finest level's, at least 1).
+                          Every level uses one polynomial before and after its coarse
+                          correction, so the V-cycle stays symmetric.                 */
 } expmv_opts;
 
 typedef struct {                  /* host struct, filled by expmv_execute */

@@ -103,7 +103,6 @@ struct Workspace {
   DevBuf<BcgState> bcgst;
   DevBuf<double> part_rr, part_sig;   // inner-solver partials
   DevBuf<double> taus, coefs;         // poles and coefficients of all shifts (re | im)
-  DevBuf<double> Cr2;                 // scratch of the per-block residual estimates
   DevBuf<cplx> S2;
   DevBuf<int> singular2;
   DevBuf<KrylovCtl> ctl;
@@ -1236,6 +1235,14 @@ InnerResult apply_inverse_mixed(expmv_plan_s* pl, int transpose, const T* V, T* 
   return total;
 }
 
+// The projected shifted solves (k_proj_solve), one workgroup per shift
+void proj_solve(hipStream_t s, int ns, int d, int p, int precond, const double* H, int ldh,
+                const double* tau_re, const double* tau_im, const cplx* G, cplx* Ascr, cplx* Zs,
+                double* Cr, int ldc, cplx* S, double* rho, int* singular) {
+  hipLaunchKernelGGL(k_proj_solve, dim3(ns), dim3(1024), 0, s, d, p, precond, H, ldh, tau_re,
+                     tau_im, G, Ascr, Zs, Cr, ldc, S, rho, singular);
+}
+
 // Source-term mode: a single time; Z receives
 //   U = r(M) U0 + (r(M) - r(sigma)) t (M - sigma I)^{-1} S
 //     = omega_0 U0 + Re sum_j c_j (M - tau_j I)^{-1} (U0 + t / (tau_j - sigma) S),
@@ -1286,7 +1293,6 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     w.taus.alloc(2 * size_t(ns));
     w.coefs.alloc(4 * size_t(ns));
     if (pl->opts.inner_relax) {
-      w.Cr2.alloc(size_t(ldh) * 2 * ns * p);
       w.S2.alloc(size_t(ns) * p * p);
       w.singular2.alloc(ns);
     }
@@ -1429,9 +1435,8 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
         dim3 g(std::max(1, (dj * p + kThreads - 1) / kThreads), ns);
         hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, dj, p, rhs_from_S ? kp : 0,
                            rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
-        hipLaunchKernelGGL(k_proj_solve, dim3(ns), dim3(1024), 0, s, dj, p, 1, w.H.p, ldh,
-                           tau_re_d, tau_im_d, w.G.p, w.Ascr.p, w.Zs.p, w.Cr2.p, ldx, w.S2.p,
-                           w.rho.p, w.singular2.p);
+        proj_solve(s, ns, dj, p, 1, w.H.p, ldh, tau_re_d, tau_im_d, w.G.p, w.Ascr.p, w.Zs.p,
+                   nullptr, ldx, w.S2.p, w.rho.p, w.singular2.p);
         HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         rho_prev = 0.0;
@@ -1447,9 +1452,8 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
                          rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
     }
     // Step 4: projected shifted systems, residual estimates, update coefficients
-    hipLaunchKernelGGL(k_proj_solve, dim3(ns), dim3(1024), 0, s, d, p, precond ? 1 : 0, w.H.p,
-                       ldh, tau_re_d, tau_im_d, w.G.p, w.Ascr.p, w.Zs.p, w.Cr.p, ldx, w.S.p,
-                       w.rho.p, w.singular.p);
+    proj_solve(s, ns, d, p, precond ? 1 : 0, w.H.p, ldh, tau_re_d, tau_im_d, w.G.p, w.Ascr.p,
+               w.Zs.p, w.Cr.p, ldx, w.S.p, w.rho.p, w.singular.p);
     double t1 = host_now_ms();
     // X_j += V_{d+p} (H~ Z_j)  [Algorithm 1: V_d Z_j]
     panel_gemm<T, double>(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * ns, w.X.p, p, ldx, 1);
@@ -1919,7 +1923,9 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
       L->avg_p = double(Lh.P.nnz()) / double(std::max<int64_t>(1, Lh.P.nrows));
       L->avg_r = double(Lh.R.nnz()) / double(std::max<int64_t>(1, Lh.R.nrows));
     }
-    L->degree = (l > 0 && pl->opts.amg_coarse_degree > 0) ? pl->opts.amg_coarse_degree : H->degree;
+    L->degree = l == 0 ? H->degree
+                       : (pl->opts.amg_coarse_degree > 0 ? pl->opts.amg_coarse_degree
+                                                         : std::max(1, H->degree - 1));
     chebyshev_coefficients(Lh.lmax, L->degree, L->cd, L->ad);
     H->lv.push_back(std::move(L));
   }

@@ -268,10 +268,13 @@ __device__ inline cplx cdiv(cplx a, cplx b) {
 
 // Projected shifted systems, one workgroup per pole j (Section 4.1, eq. 4.7):
 //   precond: (I - tau_j H_d) Z_j = G_j,  S_j = tau_j H(d:d+p, 0:d) Z_j,
-//            Cr(:, shift j) = H~ Z_j  ((d+p) x p, real and imaginary parts)
+//            Cr(:, shift j) = H~ Z_j  ((d+p) x p, real and imaginary parts;
+//            skipped when Cr is NULL)
 //   plain:   (H_d - tau_j I) Z_j = G_j,  S_j = -H(d:d+p, 0:d) Z_j,
 //            Cr(:, shift j) = [Z_j; 0]
-// Dense LU with partial pivoting on a d x d complex matrix in global scratch.
+// Dense LU with partial pivoting on a d x d complex matrix in global scratch
+// (in LDS its column accesses, at a stride of d entries, hit one bank: it
+// measured slower).
 // rho_j = ||S_j||_F (eq. 4.9 / eq. 3.6).
 __global__ void __launch_bounds__(1024)
 k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
@@ -391,8 +394,8 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
   __syncthreads();
   if (tid == 0 && sing) singular[j] = 1;
   // update coefficients Cr (rows d+p, ld ldc = 2 p x shifts): real part then
-  // imaginary part
-  for (int idx = tid; idx < (d + p) * p; idx += nt) {
+  // imaginary part (Cr = NULL: only the residual estimates are wanted)
+  for (int idx = tid; Cr && idx < (d + p) * p; idx += nt) {
     const int r = idx / p, b = idx % p;
     cplx s{0.0, 0.0};
     if (precond) {

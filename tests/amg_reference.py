@@ -36,8 +36,11 @@ def chebyshev_coefficients(lmax: float, degree: int, ratio: float = EIG_RATIO):
 
 
 class VCycle:
-    def __init__(self, levels, degree: int = 2):
-        self.degree = degree
+    def __init__(self, levels, degree: int = 2, coarse_degree=None):
+        # `degree` Chebyshev steps on the finest level, `coarse_degree` (default:
+        # the same) on the levels below it
+        cdeg = degree if coarse_degree is None else coarse_degree
+        self.deg = [degree if l == 0 else cdeg for l in range(len(levels))]
         self.A, self.P, self.dinv, self.coef = [], [], [], []
         for lv in levels:
             rp, ci, v = lv["A"]
@@ -47,14 +50,14 @@ class VCycle:
             if lv["P"] is not None:
                 prp, pci, pv, nc = lv["P"]
                 self.P.append(sp.csr_matrix((pv, pci, prp), shape=(lv["n"], nc)))
-            self.coef.append(chebyshev_coefficients(lv["lmax"], degree))
+            self.coef.append(chebyshev_coefficients(lv["lmax"], self.deg[len(self.coef)]))
         self.coarse = np.linalg.inv(self.A[-1].toarray())
 
     def smooth(self, l, b, x):
         cd, ad = self.coef[l]
         A, dinv = self.A[l], self.dinv[l][:, None]
         d = None
-        for k in range(self.degree):
+        for k in range(self.deg[l]):
             r = b - A @ x
             dn = ad[k] * dinv * r
             if k > 0:

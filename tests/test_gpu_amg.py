@@ -36,8 +36,10 @@ def _workload(name):
 
 
 def _host_vcycle(A, t, degree):
+    """The numpy V-cycle with the library's default coarse degree,
+    max(1, degree - 1)."""
     K = A.val * (-t)   # the plan's K = -tA, rounded the same way
-    return VCycle(HostAmg(A.rowptr, A.colind, K).levels(), degree)
+    return VCycle(HostAmg(A.rowptr, A.colind, K).levels(), degree, max(1, degree - 1))
 
 
 @pytest.mark.parametrize("name,p,degree", [("lap3d20", 8, 2), ("lap3d20", 3, 1),
