@@ -366,6 +366,27 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
   __shared__ double tot[2 * PP];
   __shared__ double s_beta[PP], s_aprev[PP];
   __shared__ int s_any;
+  // the operands of this thread's first row are loaded before the scalar
+  // reduction, so their latency overlaps it (they are final at kernel start)
+  const int c0 = VW * (threadIdx.x % PPL);
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  const int64_t row0 = seg0 + threadIdx.x / PPL;
+  const bool pre = row0 < seg1 && c0 < p;
+  T po0[VW], xv0[VW], zr0[VW];
+  if (pre) {
+    const int64_t i = row0 * p + c0;
+    ld_vw<VW>(pold + i, po0);
+    ld_vw<VW>(x + i, xv0);
+    if (z) {
+      TZ zz[VW];
+      ld_vw<VW>(z + i, zz);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) zr0[q] = T(zz[q]);
+    } else {
+      ld_vw<VW>(r + i, zr0);
+    }
+  }
   reduce_parts<PP, 2>(part_rr, gridDim.x, red, tot);   // tot[c] = rho_k, tot[PP + c] = |r_k|^2
   if (threadIdx.x == 0) {
     int any = 0, itmax = 0, hit = 0;
@@ -415,7 +436,6 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
     }
   }
   __syncthreads();
-  const int c0 = VW * (threadIdx.x % PPL);
   T beta[VW], aprev[VW];
 #pragma unroll
   for (int q = 0; q < VW; ++q) {
@@ -423,27 +443,41 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
     aprev[q] = T(s_aprev[(c0 + q) % PP]);
   }
   const bool any = s_any != 0;
-  int64_t seg0, seg1;
-  xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+  for (int64_t row = row0; row < seg1; row += kCgThreads / PPL) {
     if (c0 < p) {
       const int64_t i = row * p + c0;
+      const bool first = row == row0;
       T po[VW], xv[VW];
-      ld_vw<VW>(pold + i, po);
-      ld_vw<VW>(x + i, xv);
+      if (first) {
+#pragma unroll
+        for (int q = 0; q < VW; ++q) po[q] = po0[q], xv[q] = xv0[q];
+      } else {
+        ld_vw<VW>(pold + i, po);
+        ld_vw<VW>(x + i, xv);
+      }
 #pragma unroll
       for (int q = 0; q < VW; ++q) xv[q] += aprev[q] * po[q];
       st_vw<VW>(x + i, xv);
       if (any) {
         T zv[VW];
         if (z) {
-          TZ zz[VW];
-          ld_vw<VW>(z + i, zz);
+          if (first) {
 #pragma unroll
-          for (int q = 0; q < VW; ++q) zv[q] = T(zz[q]);
+            for (int q = 0; q < VW; ++q) zv[q] = zr0[q];
+          } else {
+            TZ zz[VW];
+            ld_vw<VW>(z + i, zz);
+#pragma unroll
+            for (int q = 0; q < VW; ++q) zv[q] = T(zz[q]);
+          }
         } else {
           T rv[VW];
-          ld_vw<VW>(r + i, rv);
+          if (first) {
+#pragma unroll
+            for (int q = 0; q < VW; ++q) rv[q] = zr0[q];
+          } else {
+            ld_vw<VW>(r + i, rv);
+          }
           const T dr = dinv[row];
 #pragma unroll
           for (int q = 0; q < VW; ++q) zv[q] = dr * rv[q];
@@ -497,6 +531,17 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
   __shared__ double red[kCgThreads];
   __shared__ double tot[PP];
   __shared__ double s_alpha[PP];
+  // the first row's r and q are loaded before the scalar reduction
+  const int c0 = VW * (threadIdx.x % PPL);
+  int64_t seg0, seg1;
+  xcd_rows(n, seg0, seg1);
+  const int64_t row0 = seg0 + threadIdx.x / PPL;
+  const bool pre = row0 < seg1 && c0 < p;
+  T rv0[VW], qv0[VW];
+  if (pre) {
+    ld_vw<VW>(r + row0 * p + c0, rv0);
+    ld_vw<VW>(q + row0 * p + c0, qv0);
+  }
   reduce_parts<PP, 1>(part_sig, gridDim.x, red, tot);
   if (threadIdx.x < PP) {
     const int cc = threadIdx.x;
@@ -509,22 +554,24 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
     s_alpha[cc] = a;
   }
   __syncthreads();
-  const int c0 = VW * (threadIdx.x % PPL);
   T alpha[VW];
 #pragma unroll
   for (int u = 0; u < VW; ++u) alpha[u] = T(s_alpha[(c0 + u) % PP]);
   double rz[VW], rr[VW];
 #pragma unroll
   for (int u = 0; u < VW; ++u) rz[u] = rr[u] = 0.0;
-  int64_t seg0, seg1;
-  xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+  for (int64_t row = row0; row < seg1; row += kCgThreads / PPL) {
     if (c0 < p) {
       const int64_t i = row * p + c0;
       T rv[VW], qv[VW];
       float r32v[VW];
-      ld_vw<VW>(r + i, rv);
-      ld_vw<VW>(q + i, qv);
+      if (row == row0) {
+#pragma unroll
+        for (int u = 0; u < VW; ++u) rv[u] = rv0[u], qv[u] = qv0[u];
+      } else {
+        ld_vw<VW>(r + i, rv);
+        ld_vw<VW>(q + i, qv);
+      }
       const double dr = jacobi ? double(dinv[row]) : 0.0;
 #pragma unroll
       for (int u = 0; u < VW; ++u) {
