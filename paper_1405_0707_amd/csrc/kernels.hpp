@@ -3,7 +3,10 @@
 // Blocks are n x p row-major (ld = p).  Streaming kernels use 256-thread
 // workgroups and a grid-stride loop over rows; a group of PP lanes (PP = p
 // rounded up to a power of two, PP | 64) owns one row, so every row's p
-// values are one contiguous, coalesced segment.  Reductions are
+// values are one contiguous, coalesced segment.  The inner-solver kernels
+// (1024-thread workgroups) give each lane VW = 2 adjacent columns when p is
+// even, so PPL = PP / 2 lanes own a row and loads are 16 bytes wide; for odd
+// p, VW = 1 and PPL = PP.  Reductions are
 // deterministic: per-workgroup partial sums in a fixed tree order, then a
 // fixed-order sum over workgroups (no floating-point atomics).
 #pragma once
