@@ -65,6 +65,23 @@ class Plan:
         self.device = device
         self.t = t
         self._keep = keepalive
+        # the stream the library runs this plan's work on (torch's current
+        # stream when the plan was made)
+        self._stream = (torch.cuda.current_stream(device)
+                        if torch.device(device).type == "cuda" else None)
+
+    def _run(self, call):
+        """Run a library call on the plan's stream, ordered after the work
+        queued on the caller's current stream (which produced the inputs) and
+        before what the caller queues next (which reads the outputs)."""
+        cur = torch.cuda.current_stream(self.device) if self._stream is not None else None
+        other = cur is not None and cur != self._stream
+        if other:
+            self._stream.wait_stream(cur)
+        st = call()
+        if other:
+            cur.wait_stream(self._stream)
+        return st
 
     @classmethod
     def csr(cls, rowptr, colind, val, t: float, device="cuda", **opts):
@@ -102,6 +119,30 @@ class Plan:
         check(st, "expmv_plan_toeplitz_general")
         return cls(h, col0.numel(), col0.device, float(t))
 
+    def _block(self, x, name: str) -> torch.Tensor:
+        """x as a contiguous FP64 n x p block on the plan's device (a vector
+        becomes one column).  The library reads n rows through the pointer,
+        so a block of any other height is refused here."""
+        x = _dev_f64(x, self.device)
+        if x.dim() == 1:
+            x = x[:, None]
+        if x.dim() != 2 or x.shape[0] != self.n or x.shape[1] < 1:
+            raise ValueError(f"{name} must be an n x p block with n = {self.n}, "
+                             f"got shape {tuple(x.shape)}")
+        return x
+
+    def _out(self, out, like: torch.Tensor, name: str) -> torch.Tensor:
+        if out is None:
+            return torch.empty_like(like)
+        if (out.dtype != torch.float64 or out.device != like.device or not out.is_contiguous()
+                or tuple(out.shape) != tuple(like.shape)):
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape "
+                             f"{tuple(like.shape)} on {like.device}")
+        nb = like.numel() * 8
+        if out.data_ptr() < like.data_ptr() + nb and like.data_ptr() < out.data_ptr() + nb:
+            raise ValueError(f"{name} may not overlap the input block")
+        return out
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -113,13 +154,12 @@ class Plan:
 
     def execute(self, B: torch.Tensor, tol: float = 1e-10, transpose: bool = False,
                 out: torch.Tensor | None = None, allow=()):
-        B = _dev_f64(B, self.device)
-        if B.dim() == 1:
-            B = B[:, None]
-        Z = torch.empty_like(B) if out is None else out
+        B = self._block(B, "B")
+        Z = self._out(out, B, "out")
         info = Info()
-        st = lib().expmv_execute(self._h, int(transpose), B.data_ptr(), B.shape[1], float(tol),
-                                 Z.data_ptr(), C.byref(info))
+        st = self._run(lambda: lib().expmv_execute(
+            self._h, int(transpose), B.data_ptr(), B.shape[1], float(tol), Z.data_ptr(),
+            C.byref(info)))
         check(st, "expmv_execute", allow)
         return Z, info
 
@@ -127,14 +167,13 @@ class Plan:
                       allow=()):
         """Z[q] = e^{t_q A} B for every t_q in `times` on one shared Krylov
         basis (A = the plan's matrix); returns (Z of shape (nt, n, p), info)."""
-        B = _dev_f64(B, self.device)
-        if B.dim() == 1:
-            B = B[:, None]
+        B = self._block(B, "B")
         ts = (C.c_double * len(times))(*[float(x) for x in times])
         Z = torch.empty((len(times),) + tuple(B.shape), dtype=torch.float64, device=self.device)
         info = Info()
-        st = lib().expmv_execute_times(self._h, int(transpose), ts, len(times), B.data_ptr(),
-                                       B.shape[1], float(tol), Z.data_ptr(), C.byref(info))
+        st = self._run(lambda: lib().expmv_execute_times(
+            self._h, int(transpose), ts, len(times), B.data_ptr(), B.shape[1], float(tol),
+            Z.data_ptr(), C.byref(info)))
         check(st, "expmv_execute_times", allow)
         return Z, info
 
@@ -142,64 +181,68 @@ class Plan:
                        tol: float = 1e-10, transpose: bool = False, allow=()):
         """U = solution at the plan's t of u' = A u + e^{gamma s} S, u(0) = U0,
         with both exponentials in the CF form (one solve on [U0 | S])."""
-        U0 = _dev_f64(U0, self.device)
-        S = _dev_f64(S, self.device)
-        if U0.dim() == 1:
-            U0, S = U0[:, None], S[:, None]
+        U0 = self._block(U0, "U0")
+        S = self._block(S, "S")
         if U0.shape != S.shape:
             raise ValueError("U0 and S must have the same shape")
         U = torch.empty_like(U0)
         info = Info()
-        st = lib().expmv_execute_source(self._h, int(transpose), U0.data_ptr(), S.data_ptr(),
-                                        U0.shape[1], float(gamma), float(tol), U.data_ptr(),
-                                        C.byref(info))
+        st = self._run(lambda: lib().expmv_execute_source(
+            self._h, int(transpose), U0.data_ptr(), S.data_ptr(), U0.shape[1], float(gamma),
+            float(tol), U.data_ptr(), C.byref(info)))
         check(st, "expmv_execute_source", allow)
         return U, info
 
     def grad_t(self, G: torch.Tensor, Z: torch.Tensor) -> float:
-        G = _dev_f64(G, self.device)
-        Z = _dev_f64(Z, self.device)
+        G = self._block(G, "G")
+        Z = self._block(Z, "Z")
+        if G.shape != Z.shape:
+            raise ValueError("G and Z must have the same shape")
         out = C.c_double()
-        check(lib().expmv_grad_t(self._h, G.data_ptr(), Z.data_ptr(), G.shape[1], C.byref(out)),
-              "expmv_grad_t")
+        check(self._run(lambda: lib().expmv_grad_t(
+            self._h, G.data_ptr(), Z.data_ptr(), G.shape[1], C.byref(out))), "expmv_grad_t")
         return out.value
 
     def adjoint(self, G: torch.Tensor, B: torch.Tensor, tol: float = 1e-10, allow=()):
         """(e^{tA^T} G, <G, A r(tA) B>, info) from one transposed solve."""
-        G = _dev_f64(G, self.device)
-        B = _dev_f64(B, self.device)
+        G = self._block(G, "G")
+        B = self._block(B, "B")
+        if G.shape != B.shape:
+            raise ValueError("G and B must have the same shape")
         gB = torch.empty_like(G)
         gt = C.c_double()
         info = Info()
-        st = lib().expmv_adjoint(self._h, G.data_ptr(), B.data_ptr(), G.shape[1], float(tol),
-                                 gB.data_ptr(), C.byref(gt), C.byref(info))
+        st = self._run(lambda: lib().expmv_adjoint(
+            self._h, G.data_ptr(), B.data_ptr(), G.shape[1], float(tol), gB.data_ptr(),
+            C.byref(gt), C.byref(info)))
         check(st, "expmv_adjoint", allow)
         return gB, gt.value, info
 
     def apply_operator(self, X: torch.Tensor, transpose: bool = False) -> torch.Tensor:
-        X = _dev_f64(X, self.device)
+        X = self._block(X, "X")
         Y = torch.empty_like(X)
-        check(lib().expmv_apply_operator(self._h, int(transpose), X.data_ptr(), X.shape[1],
-                                         Y.data_ptr()), "expmv_apply_operator")
+        check(self._run(lambda: lib().expmv_apply_operator(
+            self._h, int(transpose), X.data_ptr(), X.shape[1], Y.data_ptr())),
+            "expmv_apply_operator")
         return Y
 
     def apply_preconditioner(self, X: torch.Tensor, transpose: bool = False) -> torch.Tensor:
         """One application of the inner solver's preconditioner for K = -tA
         (Jacobi D^{-1}, or one AMG V-cycle): Y ~= K^{-1} X."""
-        X = _dev_f64(X, self.device)
-        if X.dim() == 1:
-            X = X[:, None]
+        X = self._block(X, "X")
         Y = torch.empty_like(X)
-        check(lib().expmv_apply_preconditioner(self._h, int(transpose), X.data_ptr(), X.shape[1],
-                                               Y.data_ptr()), "expmv_apply_preconditioner")
+        check(self._run(lambda: lib().expmv_apply_preconditioner(
+            self._h, int(transpose), X.data_ptr(), X.shape[1], Y.data_ptr())),
+            "expmv_apply_preconditioner")
         return Y
 
     def apply_inverse(self, X: torch.Tensor, transpose: bool = False):
-        X = _dev_f64(X, self.device)
+        X = self._block(X, "X")
         Y = torch.empty_like(X)
         it = C.c_longlong()
-        check(lib().expmv_apply_inverse(self._h, int(transpose), X.data_ptr(), X.shape[1],
-                                        Y.data_ptr(), C.byref(it)), "expmv_apply_inverse")
+        check(self._run(lambda: lib().expmv_apply_inverse(
+            self._h, int(transpose), X.data_ptr(), X.shape[1], Y.data_ptr(), C.byref(it))),
+            "expmv_apply_inverse")
         return Y, it.value
 
 
@@ -292,12 +335,13 @@ class _ExpmvFn(torch.autograd.Function):
         ctx.tol = tol
         ctx.save_for_backward(Bd)
         ctx.info = info
-        return Z
+        return Z.view(B.shape)   # a vector B gives a vector Z
 
     @staticmethod
     def backward(ctx, G):
         (B,) = ctx.saved_tensors
         gB, gt, _ = ctx.plan.adjoint(G.contiguous(), B, tol=ctx.tol)
+        gB = gB.view(B.shape)
         gt_t = torch.tensor(gt, dtype=torch.float64, device=gB.device)
         return (gB if ctx.needs_input_grad[0] else None,
                 gt_t if ctx.needs_input_grad[1] else None, None, None, None)
@@ -311,4 +355,6 @@ def expmv(A, B: torch.Tensor, t, tol: float = 1e-10, plan: Plan | None = None, *
     t_float = float(t_t.detach())
     if plan is None:
         plan = _make_plan(A, t_float, B.device, opts)
+    elif plan.t != t_float:
+        raise ValueError(f"the plan was made for t = {plan.t}, not t = {t_float}")
     return _ExpmvFn.apply(B, t_t, plan, tol, t_float)

@@ -2336,8 +2336,9 @@ expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, in
     // K B (K = -tA = -M), for the omega_0 <G, M B> term
     plan->kx.alloc(size_t(plan->n) * p * 2 * kNShift);
     double* KB = plan->kx.p;
-    apply_K<double>(plan, 0, B, KB, int(p));
     const int grid = 512;
+    w.partial.alloc(size_t(grid) * 16);   // 16 sums per workgroup (the solve has finished)
+    apply_K<double>(plan, 0, B, KB, int(p));
     hipLaunchKernelGGL(k_adjoint_dots, dim3(grid), dim3(kThreads), 0, s, plan->n, int(p), w.X.p,
                        B, G, KB, w.partial.p);
     std::vector<double> part(size_t(grid) * 16);

@@ -98,3 +98,50 @@ def test_nonsymmetric_grad_b_uses_transpose():
     torch.sum(torch.from_numpy(G).to(DEV) * Z).backward()
     M = (Wc.t * Wc.A.to_scipy()).tocsr()
     assert rel(B.grad.cpu().numpy(), exact.rational_sparse(M.T.tocsr(), G)) < 1e-9
+
+
+def test_vector_input_and_reused_plan():
+    """A vector B gives a vector Z and a vector grad_B; a plan made once is
+    reused for another B; a plan for another t is refused."""
+    announce("autograd vector B, reused plan")
+    from paper_1405_0707_amd import Plan
+    W = vardiff_small(N=24, p=1)
+    A = csr_tuple(W)
+    pl = Plan.csr(*A, W.t, device=DEV)
+    g = np.random.default_rng(11).standard_normal(W.A.n)
+    b = torch.from_numpy(W.B[:, 0].copy()).to(DEV).requires_grad_(True)
+    z = expmv(A, b, W.t, tol=1e-11, plan=pl)
+    assert z.shape == b.shape
+    torch.sum(torch.from_numpy(g).to(DEV) * z).backward()
+    assert b.grad.shape == b.shape
+    M = (W.t * W.A.to_scipy()).tocsr()
+    assert rel(z.detach().cpu().numpy(), exact.rational_sparse(M, W.B[:, :1])[:, 0]) < 1e-9
+    assert rel(b.grad.cpu().numpy(), exact.rational_sparse(M.T.tocsr(), g[:, None])[:, 0]) < 1e-9
+    z2 = expmv(A, 2.0 * b.detach(), W.t, tol=1e-11, plan=pl)
+    assert rel(z2.cpu().numpy(), 2.0 * z.detach().cpu().numpy()) < 1e-9
+    with pytest.raises(ValueError):
+        expmv(A, b, 2.0 * W.t, plan=pl)
+
+
+def test_calls_from_another_stream_are_ordered():
+    """A plan made on the default stream, used from a side stream whose
+    pending work produces the input and whose next work reads the output:
+    the binding orders the library's stream after and before it."""
+    announce("side stream ordering")
+    from paper_1405_0707_amd import Plan
+    W = vardiff_small(N=32, p=2)
+    A = csr_tuple(W)
+    pl = Plan.csr(*A, W.t, device=DEV)
+    ref, _ = pl.execute(torch.from_numpy(W.B).to(DEV), tol=1e-11)
+    side = torch.cuda.Stream(device=DEV)
+    base = torch.from_numpy(W.B).to(DEV)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        big = torch.ones(4096, 4096, dtype=torch.float64, device=DEV)
+        for _ in range(4):
+            big = big @ big * (1.0 / 4096)       # keeps the side stream busy
+        B = base * big[0, 0]                     # = base, ready only after the products
+        Z, _ = pl.execute(B, tol=1e-11)
+        Z2 = Z * 1.0                             # read on the side stream
+    torch.cuda.synchronize()
+    assert rel(Z2.cpu().numpy(), ref.cpu().numpy()) < 1e-12

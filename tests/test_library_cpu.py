@@ -101,3 +101,41 @@ def test_default_options_and_range_checks():
         st = _lib.lib().expmv_plan_csr(2, 2, ptr, ptr, ptr, 1.0, C.byref(q), None, C.byref(h))
         assert st == _lib.EINVAL, (field, value, st)
         assert not h.value
+
+
+def test_binding_refuses_blocks_of_the_wrong_height():
+    """The C entry points read n rows through each block pointer, so the
+    binding checks every block's shape before it calls them.  A plan object
+    with no library handle on the CPU shows that the checks come first."""
+    import torch
+
+    from paper_1405_0707_amd.api import Plan, expmv
+    pl = Plan(None, 10, torch.device("cpu"), 0.5)
+    good = torch.zeros(10, 2, dtype=torch.float64)
+    for bad in (torch.zeros(9, 2), torch.zeros(11), torch.zeros(10, 0), torch.zeros(2, 10, 1)):
+        with pytest.raises(ValueError):
+            pl.execute(bad)
+        with pytest.raises(ValueError):
+            pl.apply_operator(bad)
+        with pytest.raises(ValueError):
+            pl.apply_inverse(bad)
+        with pytest.raises(ValueError):
+            pl.apply_preconditioner(bad)
+        with pytest.raises(ValueError):
+            pl.execute_times([1.0], bad)
+        with pytest.raises(ValueError):
+            pl.execute_source(good, bad, -1.0)
+        with pytest.raises(ValueError):
+            pl.adjoint(good, bad)
+        with pytest.raises(ValueError):
+            pl.grad_t(bad, good)
+    with pytest.raises(ValueError):
+        pl.adjoint(good, torch.zeros(10, 3))
+    for out in (torch.zeros(10, 3, dtype=torch.float64), torch.zeros(10, 2, dtype=torch.float32),
+                torch.zeros(2, 10, dtype=torch.float64).t()):
+        with pytest.raises(ValueError):
+            pl.execute(good, out=out)
+    with pytest.raises(ValueError):   # output aliasing the input
+        pl.execute(good, out=good)
+    with pytest.raises(ValueError):   # a plan made for another t
+        expmv(None, good, 0.25, plan=pl)
