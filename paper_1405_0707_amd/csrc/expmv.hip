@@ -973,8 +973,8 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
 
 void reduce_partials(expmv_plan_s* pl, int nwg, int O, double* out, double* H, int ldh, int col0,
                      int p, int O_h) {
-  const int grid = (O + (kThreads / 8) - 1) / (kThreads / 8);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(grid), dim3(kThreads), 0, pl->stream,
+  const int grid = (O + kRedOut - 1) / kRedOut;
+  hipLaunchKernelGGL(k_reduce_partials, dim3(grid), dim3(kRedOut * kRedLanes), 0, pl->stream,
                      pl->ws.partial.p, nwg, O, out, H, ldh, col0, p, O_h);
 }
 

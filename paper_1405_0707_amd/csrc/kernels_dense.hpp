@@ -104,27 +104,42 @@ k_orth(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const T* _
   for (int o = tid; o < O; o += kThreads) partial[size_t(blockIdx.x) * O + o] = acc[o];
 }
 
-// out[o] = sum_w partial[w*O + o], fixed order; 8 lanes per output.
+// out[o] = sum_w partial[w*O + o], fixed order.  A workgroup takes 16
+// adjacent outputs (one 128-byte line of every partial row) with 64 lanes
+// each: lane l sums the rows w = l, l + 64, ..., and the 64 sums of an
+// output are added in a fixed tree in LDS.  A wavefront reads four whole
+// lines per load.
 // If H != nullptr the first O_h outputs (rows of C = (npan*p) x p) are also
 // added to H[(row) * ldh + col0 + b].
-__global__ void __launch_bounds__(kThreads)
+constexpr int kRedOut = 16;     // outputs per workgroup
+constexpr int kRedLanes = 64;   // lanes per output
+__global__ void __launch_bounds__(kRedOut * kRedLanes)
 k_reduce_partials(const double* __restrict__ partial, int nwg, int O, double* __restrict__ out,
                   double* __restrict__ H, int ldh, int col0, int p, int O_h) {
-  __shared__ double red[kThreads];
-  constexpr int L = 8;
-  const int o = blockIdx.x * (kThreads / L) + threadIdx.x / L;
-  const int l = threadIdx.x % L;
+  __shared__ double red[kRedLanes][kRedOut];
+  const int oo = threadIdx.x % kRedOut, l = threadIdx.x / kRedOut;
+  const int o = blockIdx.x * kRedOut + oo;
   double s = 0.0;
-  if (o < O)
-    for (int w = l; w < nwg; w += L) s += partial[size_t(w) * O + o];
-  red[threadIdx.x] = s;
+  if (o < O) {
+    constexpr int U = 4;
+    int w = l;
+    for (; w + (U - 1) * kRedLanes < nwg; w += U * kRedLanes) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = partial[size_t(w + u * kRedLanes) * O + o];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; w < nwg; w += kRedLanes) s += partial[size_t(w) * O + o];
+  }
+  red[l][oo] = s;
   __syncthreads();
-  for (int st = L / 2; st >= 1; st >>= 1) {
-    if (l < st) red[threadIdx.x] += red[threadIdx.x + st];
+  for (int st = kRedLanes / 2; st >= 1; st >>= 1) {
+    if (l < st) red[l][oo] += red[l + st][oo];
     __syncthreads();
   }
   if (l == 0 && o < O) {
-    const double v = red[threadIdx.x];
+    const double v = red[0][oo];
     out[o] = v;
     if (H != nullptr && o < O_h) {
       const int row = o / p, b = o % p;
@@ -266,15 +281,24 @@ __device__ inline cplx cdiv(cplx a, cplx b) {
   return {(a.x * r + a.y) / den, (a.y * r - a.x) / den};
 }
 
+constexpr int kProjMaxD = 64 * kMaxP;   // m <= 64 block steps of p <= kMaxP columns
+
 // Projected shifted systems, one workgroup per pole j (Section 4.1, eq. 4.7):
 //   precond: (I - tau_j H_d) Z_j = G_j,  S_j = tau_j H(d:d+p, 0:d) Z_j,
 //            Cr(:, shift j) = H~ Z_j  ((d+p) x p, real and imaginary parts;
 //            skipped when Cr is NULL)
 //   plain:   (H_d - tau_j I) Z_j = G_j,  S_j = -H(d:d+p, 0:d) Z_j,
 //            Cr(:, shift j) = [Z_j; 0]
-// Dense LU with partial pivoting on a d x d complex matrix in global scratch
+// LU with partial pivoting on a d x d complex matrix in global scratch
 // (in LDS its column accesses, at a stride of d entries, hit one bank: it
-// measured slower).
+// measured slower), limited to the matrix's lower band: L(c), the last row
+// that can be nonzero in column c during the elimination, is the running
+// maximum over columns c' <= c of the last nonzero row of H in column c'.
+// Rows below L(c) are zero in every column up to c, are never chosen as a
+// pivot and receive zero updates, so they are skipped: the same arithmetic
+// as the dense elimination, with p to 2p - 1 rows per column instead of
+// d - c on the block Hessenberg H_d of one cycle (a dense leading block
+// after a restart widens the band there).
 // rho_j = ||S_j||_F (eq. 4.9 / eq. 3.6).
 __global__ void __launch_bounds__(1024)
 k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
@@ -289,9 +313,13 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
   cplx* Z = Zs + size_t(j) * d * p;
   const cplx* Gj = G + size_t(j) * d * p;
   __shared__ int s_piv, s_zero;
+  __shared__ int s_lim[kProjMaxD];   // L(c)
+  for (int c = tid; c < d; c += nt) s_lim[c] = c;
+  __syncthreads();
   for (int idx = tid; idx < d * d; idx += nt) {
     const int r = idx / d, c = idx % d;
     const double h = H[int64_t(r) * ldh + c];
+    if (r > c && h != 0.0) atomicMax(&s_lim[c], r);
     cplx a;
     if (precond) {
       a = {-tau.x * h, -tau.y * h};
@@ -307,13 +335,28 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
   }
   for (int idx = tid; idx < d * p; idx += nt) Z[idx] = Gj[idx];
   __syncthreads();
+  if (tid < 64) {   // running maximum, one wavefront, 64 columns per step
+    int carry = 0;
+    for (int c0 = 0; c0 < d; c0 += 64) {
+      int v = c0 + tid < d ? s_lim[c0 + tid] : 0;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(v, off, 64);
+        if (tid >= off) v = max(v, o);
+      }
+      v = max(v, carry);
+      if (c0 + tid < d) s_lim[c0 + tid] = v;
+      carry = __shfl(v, 63, 64);
+    }
+  }
+  __syncthreads();
   int sing = 0;
   for (int c = 0; c < d; ++c) {
+    const int last = s_lim[c];
     // pivot: the first row of largest |a|^2 in column c, by one wavefront
     if (tid < 64) {
       double best = -1.0;
       int bi = c;
-      for (int r = c + tid; r < d; r += 64) {
+      for (int r = c + tid; r <= last; r += 64) {
         const cplx a = A[r * d + c];
         const double v = a.x * a.x + a.y * a.y;
         if (v > best) {
@@ -354,11 +397,12 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
       }
     }
     __syncthreads();
-    // rows below: multiplier l_r = a_rc / a_cc formed where it is used
+    // rows c+1..L(c): multiplier l_r = a_rc / a_cc formed where it is used
     const cplx diag = A[c * d + c];
     const int m1 = d - c - 1;
     const int wide = m1 + p;
-    for (int idx = tid; idx < m1 * wide; idx += nt) {
+    const int rows = last - c;
+    for (int idx = tid; idx < rows * wide; idx += nt) {
       const int r = c + 1 + idx / wide;
       const int cc = idx % wide;
       const cplx l = cdiv(A[r * d + c], diag);
