@@ -105,11 +105,14 @@ def cg_kernel_bytes(n: int, nnz: int, p: int, precond: str = "jacobi") -> dict:
                                "amg32": 4 * n * p}[precond]}
 
 
-def smooth_kernel_bytes(n: int, nnz: int, p: int, degree: int, es: int = 8) -> float:
+def smooth_kernel_bytes(n: int, nnz: int, p: int, degree: int, es: int = 8,
+                        fused: bool = False) -> float:
     """Mean algorithmic HBM bytes per launch of the finest AMG level's
-    smoothing-step kernel k_amg_step over the 2 * degree launches of one
-    V-cycle, with es-byte values and vectors (8: FP64 V-cycle, 4: FP32) and
-    int32 indices, A = 4(n+1) + (4 + es) nnz for the CSR operator:
+    smoothing-step kernel k_amg_step over its launches in one V-cycle (2 *
+    degree; the degree post-steps alone when the level is fused, i.e. its
+    pre-smoothing, residual and restriction run as one restriction of b),
+    with es-byte values and vectors (8: FP64 V-cycle, 4: FP32) and int32
+    indices, A = 4(n+1) + (4 + es) nnz for the CSR operator:
       first pre-step (iterate s0 D^{-1} b implicit): A + es n + 3 es np
       later pre-steps: A + es n + 5 es np
       residual: A + 3 es np (A + es n + 2 es np when degree = 1)
@@ -117,9 +120,10 @@ def smooth_kernel_bytes(n: int, nnz: int, p: int, degree: int, es: int = 8) -> f
       step is the last one, + es np for reading d after the first)."""
     A = 4 * (n + 1) + (4 + es) * nnz
     launches = []
-    for st in range(1, degree):
-        launches.append(A + es * n + (3 if st == 1 else 5) * es * n * p)
-    launches.append(A + 3 * es * n * p if degree > 1 else A + es * n + 2 * es * n * p)
+    if not fused:
+        for st in range(1, degree):
+            launches.append(A + es * n + (3 if st == 1 else 5) * es * n * p)
+        launches.append(A + 3 * es * n * p if degree > 1 else A + es * n + 2 * es * n * p)
     for st in range(degree):
         b = A + es * n + 3 * es * n * p
         if st > 0:
@@ -324,10 +328,16 @@ def main():
         per_iter = dict(mean)          # device time per inner iteration
         sm_launches = sum(i.kern_smooth_launches for i in infos)
         if sm_launches:
+            # default degree 2 on the finest level; with more than two levels
+            # the library fuses its pre-smoothing, residual and restriction
             degree = 2
+            fused = info.amg_levels > 2
             mean["S"] = sum(i.kern_ms_smooth * i.kern_smooth_launches for i in infos) / sm_launches
-            byt["S"] = smooth_kernel_bytes(W.n, W.A.nnz, W.p, degree, 4 if args.amg_fp32 else 8)
-            names["S"] = ("k_amg_step, finest level (AMG V-cycle smoothing steps and residual, "
+            byt["S"] = smooth_kernel_bytes(W.n, W.A.nnz, W.p, degree, 4 if args.amg_fp32 else 8,
+                                           fused)
+            names["S"] = ("k_amg_step, finest level (AMG V-cycle post-smoothing steps, "
+                          "CSR SpMM fused with the Chebyshev update)" if fused else
+                          "k_amg_step, finest level (AMG V-cycle smoothing steps and residual, "
                           "CSR SpMM fused with the Chebyshev update)")
             per_iter["S"] = mean["S"] * sm_launches / samples
         kernels = {key: {"kernel": names[key], "mean_launch_ms": round(mean[key], 5),

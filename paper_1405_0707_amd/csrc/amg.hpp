@@ -137,6 +137,67 @@ __device__ inline void row_dot_split(const int32_t* __restrict__ colind,
     for (int off = PPL; off < PPL * G; off <<= 1) acc[k] += __shfl_xor(acc[k], off, 64);
 }
 
+// Both sums of k_amg_affine_pair in one loop, so that their loads are in flight
+// together: accA over row ea0..ea1 of the operator with the scaled vector
+// s_j = dinv[j] * b[j], accP over row ep0..ep1 of Pf with xc.  Same split
+// over the G sub-lanes and the same order within each sum as row_dot_split.
+template <typename T, int PPL, int VW>
+__device__ inline void row_dot_pair(const int32_t* __restrict__ aci, const T* __restrict__ av,
+                                    const T* __restrict__ b, const T* __restrict__ dinv, int ea0,
+                                    int ea1, const int32_t* __restrict__ pci,
+                                    const T* __restrict__ pv, const T* __restrict__ xc, int ep0,
+                                    int ep1, int ld, int c0, bool active, int g, int G,
+                                    double (&accA)[VW], double (&accP)[VW]) {
+  constexpr int U = 8;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) accA[k] = accP[k] = 0.0;
+  if (active) {
+    for (int ea = ea0 + g, ep = ep0 + g; ea < ea1 || ep < ep1; ea += U * G, ep += U * G) {
+      int32_t ja[U], jp[U];
+      double va[U], vp[U], wa[U][VW], wp[U][VW];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool oa = ea + u * G < ea1, op = ep + u * G < ep1;
+        ja[u] = oa ? aci[ea + u * G] : -1;
+        va[u] = oa ? double(av[ea + u * G]) : 0.0;
+        jp[u] = op ? pci[ep + u * G] : -1;
+        vp[u] = op ? double(pv[ep + u * G]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ja[u] < 0) {
+#pragma unroll
+          for (int k = 0; k < VW; ++k) wa[u][k] = 0.0;
+        } else {
+          load_vw<VW>(b + int64_t(ja[u]) * ld + c0, wa[u]);
+          const double dj = double(dinv[ja[u]]);
+#pragma unroll
+          for (int k = 0; k < VW; ++k) wa[u][k] *= dj;
+        }
+        if (jp[u] < 0) {
+#pragma unroll
+          for (int k = 0; k < VW; ++k) wp[u][k] = 0.0;
+        } else {
+          load_vw<VW>(xc + int64_t(jp[u]) * ld + c0, wp[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+          accA[k] += va[u] * wa[u][k];
+          accP[k] += vp[u] * wp[u][k];
+        }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < VW; ++k)
+    for (int off = PPL; off < PPL * G; off <<= 1) {
+      accA[k] += __shfl_xor(accA[k], off, 64);
+      accP[k] += __shfl_xor(accP[k], off, 64);
+    }
+}
+
 // One smoothing step or a residual on one level (see the mode bits).
 template <typename T, int PPL, int VW, int NT, bool SEG>
 __global__ void __launch_bounds__(NT)
@@ -257,6 +318,42 @@ k_amg_prolong(int k, const KrylovCtl* ctl, int n, int p, int G,
 #pragma unroll
     for (int q = 0; q < VW; ++q) base[q] += corr[q];
     store_vw<VW>(x + i, base);
+  }
+}
+
+// x = D^{-1} (alpha b - beta A D^{-1} b) + P' xc in one pass (G sub-lanes
+// per row serve both sums):
+//  * a level below the finest smoothed by one step from x0 = s0 D^{-1} b,
+//    prolongation and post-smoothing step together:
+//      x1 = x0 + P xc,  out = x1 + s0 D^{-1} (b - A x1)
+//         = D^{-1} (2 s0 b - s0^2 A D^{-1} b) + Pf xc,  Pf = (I - s0 D^{-1} A) P
+//  * the finest level at degree 2, whose pre-smoothed iterate
+//      x1 = (1 + c1) x0 + a1 D^{-1} (b - A x0) = D^{-1} ((s0 + c1 s0 + a1) b - a1 s0 A D^{-1} b)
+//    is not stored: the prolongation x1 + P xc recomputes it.
+template <typename T, int PPL, int VW, int NT, bool SEG>
+__global__ void __launch_bounds__(NT)
+k_amg_affine_pair(int k, const KrylovCtl* ctl, int n, int p, int G,
+                  const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                  const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
+                  const int32_t* __restrict__ prp, const int32_t* __restrict__ pci,
+                  const T* __restrict__ pv, const T* __restrict__ xc, double alpha, double beta,
+                  T* __restrict__ out) {
+  if (ctl && finished_by(ctl, k)) return;
+  const int c0 = VW * (threadIdx.x % PPL);
+  const int g = (threadIdx.x / PPL) % G;
+  for (RowRange<NT, PPL, SEG> rr(n, G); rr.r < rr.end; rr.r += rr.step) {
+    const int64_t row = rr.r;
+    double ab[VW], corr[VW];
+    row_dot_pair<T, PPL, VW>(aci, av, b, dinv, arp[row], arp[row + 1], pci, pv, xc, prp[row],
+                             prp[row + 1], p, c0, c0 < p, g, G, ab, corr);
+    if (c0 >= p || g != 0) continue;
+    const int64_t i = row * p + c0;
+    double bi[VW], o[VW];
+    load_vw<VW>(b + i, bi);
+    const double dr = double(dinv[row]);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) o[q] = dr * (alpha * bi[q] - beta * ab[q]) + corr[q];
+    store_vw<VW>(out + i, o);
   }
 }
 

@@ -31,6 +31,59 @@ HostCsr csr_transpose(const HostCsr& A) {
   return T;
 }
 
+HostCsr csr_add(const HostCsr& A, const HostCsr& B, double a, double b) {
+  HostCsr C;
+  C.nrows = A.nrows;
+  C.ncols = A.ncols;
+  C.rp.assign(C.nrows + 1, 0);
+  std::vector<int64_t> pos(A.ncols, -1);
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    const int64_t start = int64_t(C.ci.size());
+    auto put = [&](int32_t j, double v) {
+      if (pos[j] < start) {
+        pos[j] = int64_t(C.ci.size());
+        C.ci.push_back(j);
+        C.v.push_back(v);
+      } else {
+        C.v[pos[j]] += v;
+      }
+    };
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) put(A.ci[e], a * A.v[e]);
+    for (int64_t e = B.rp[i]; e < B.rp[i + 1]; ++e) put(B.ci[e], b * B.v[e]);
+    C.rp[i + 1] = int64_t(C.ci.size());
+  }
+  return C;
+}
+
+HostCsr jacobi_step_operator(const HostCsr& A, const std::vector<double>& dinv, double s,
+                             bool left) {
+  HostCsr M;
+  M.nrows = A.nrows;
+  M.ncols = A.ncols;
+  M.rp.assign(M.nrows + 1, 0);
+  M.ci.reserve(A.nnz() + M.nrows);
+  M.v.reserve(A.nnz() + M.nrows);
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    bool diag = false;
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      const int32_t j = A.ci[e];
+      double v = -s * A.v[e] * (left ? dinv[i] : dinv[j]);
+      if (j == i) {
+        v += 1.0;
+        diag = true;
+      }
+      M.ci.push_back(j);
+      M.v.push_back(v);
+    }
+    if (!diag) {
+      M.ci.push_back(int32_t(i));
+      M.v.push_back(1.0);
+    }
+    M.rp[i + 1] = int64_t(M.ci.size());
+  }
+  return M;
+}
+
 // C = A B (Gustavson, row by row; entries of a row in first-touch order, so
 // the result and its summation order are deterministic).
 HostCsr csr_matmul(const HostCsr& A, const HostCsr& B) {

@@ -55,4 +55,13 @@ int amg_build(const HostCsr& A, const AmgParams& prm, AmgHost& out);
 HostCsr csr_transpose(const HostCsr& A);
 HostCsr csr_matmul(const HostCsr& A, const HostCsr& B);
 
+// I - s A D^{-1} (left = false) or I - s D^{-1} A (left = true) with
+// D^{-1} = diag(dinv), on A's pattern plus the diagonal: the residual map
+// b - A x and the error map of one Jacobi step x = s D^{-1} b.
+// a A + b B (union of the patterns)
+HostCsr csr_add(const HostCsr& A, const HostCsr& B, double a, double b);
+
+HostCsr jacobi_step_operator(const HostCsr& A, const std::vector<double>& dinv, double s,
+                             bool left);
+
 }  // namespace expmv

@@ -132,6 +132,22 @@ struct AmgDevLevel {
   double cd[kAmgMaxDeg] = {}, ad[kAmgMaxDeg] = {};   // Chebyshev step coefficients
   int degree = 2;                                    // smoothing steps before / after
   double avg_a = 0.0, avg_p = 0.0, avg_r = 0.0;      // mean nonzeros per row of A, P, R
+  // A level below the finest smoothed by one step (degree 1, x0 = s0 D^{-1} b):
+  // the pre-smoothing step, the residual and the restriction are one operator
+  // Rf = R (I - s0 A D^{-1}), and the prolongation and the post-smoothing step
+  // give out = s0 D^{-1} (2 b - s0 A D^{-1} b) + Pf xc with
+  // Pf = (I - s0 D^{-1} A) P: two launches per level instead of four, the
+  // same linear map up to rounding.
+  // The finest level at degree 2 (fused likewise): its pre-smoothed iterate
+  // x1 = D^{-1} (alpha b - beta A D^{-1} b) is recomputed where the
+  // prolongation needs it, and the two pre-smoothing steps, the residual and
+  // the restriction are one operator Rf = R (I - A D^{-1} (alpha I - beta A D^{-1})).
+  double alpha = 0.0, beta = 0.0;
+  bool fused = false;
+  DevBuf<int32_t> Rfrp, Rfci, Pfrp, Pfci;
+  DevBuf<double> Rfv, Pfv;
+  DevBuf<float> Rfv32, Pfv32;
+  double avg_rf = 0.0, avg_pf = 0.0;
   DevBuf<char> vb, vu, vv, vd, vr, vo;
 };
 
@@ -147,7 +163,9 @@ struct AmgDev {
   std::vector<std::unique_ptr<AmgDevLevel>> lv;
   DevBuf<double> cinv;   // dense inverse of the coarsest operator
   // Inv R of the level above the coarsest (restriction and coarsest solve as
-  // one dense product), when it is small enough (kAmgFusedMax entries)
+  // one dense product), when it is small enough (kAmgFusedMax entries); on a
+  // fused level (AmgDevLevel::fused) Inv Rf, which also takes in the level's
+  // pre-smoothing step and residual
   DevBuf<double> cinvR;
   int degree = 2;
   int p = 0;
@@ -450,10 +468,14 @@ InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chu
 // operator values of a level in the V-cycle's precision
 template <typename T>
 struct LevelVals {
-  const T *a, *p, *r;
+  const T *a, *p, *r, *pf, *rf;
 };
-LevelVals<double> vals_of(const AmgDevLevel& L, double) { return {L.av, L.Pv.p, L.Rv.p}; }
-LevelVals<float> vals_of(const AmgDevLevel& L, float) { return {L.Av32.p, L.Pv32.p, L.Rv32.p}; }
+LevelVals<double> vals_of(const AmgDevLevel& L, double) {
+  return {L.av, L.Pv.p, L.Rv.p, L.Pfv.p, L.Rfv.p};
+}
+LevelVals<float> vals_of(const AmgDevLevel& L, float) {
+  return {L.Av32.p, L.Pv32.p, L.Rv32.p, L.Pfv32.p, L.Rfv32.p};
+}
 
 template <typename T>
 const T* dinv_of(const AmgDevLevel& L);
@@ -503,6 +525,29 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
   const T* dinv = dinv_of<T>(L);
   const LevelVals<T> lv = vals_of(L, T());
   const bool fine = (l == 0);
+  if (!fine && L.fused) {
+    AmgDevLevel& C = *H.lv[l + 1];
+    const int nc = int(C.n);
+    T* xc = reinterpret_cast<T*>(C.vo.p);
+    if (l + 2 == int(H.lv.size()) && H.cinvR.p) {
+      // xc = (Inv Rf) b: smoothing step, residual, restriction and coarsest solve
+      hipLaunchKernelGGL((k_amg_dense<T, PP>), dim3(std::max(1, std::min(nc, 1024))), dim3(1024),
+                         0, s, k, ctl, nc, n, p, H.cinvR.p, b, xc);
+    } else {
+      T* bc = reinterpret_cast<T*>(C.vb.p);
+      const int GR = row_split(L.avg_rf, PPL);
+      hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
+                         dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
+                         GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
+      amg_level_vw<T, PPL, VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+    }
+    const int G = std::max(row_split(L.avg_a, PPL), row_split(L.avg_pf, PPL));
+    hipLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
+                       dim3(grid_for(n, PPL * G, 4096)), dim3(kThreads), 0, s, k, ctl, n, p, G,
+                       L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf, xc, L.alpha,
+                       L.beta, out);
+    return;
+  }
   const int gfine = cg_grid(n, PP);
   const int GA = row_split(L.avg_a, PPL), GP = row_split(L.avg_p, PPL);
   const int gcoarse_a = grid_for(n, PPL * GA, 4096), gcoarse_p = grid_for(n, PPL * GP, 4096);
@@ -525,6 +570,21 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
   };
   T* x = reinterpret_cast<T*>(L.vu.p);
   T* y = reinterpret_cast<T*>(L.vv.p);
+  if (fine && L.fused) {
+    // bc = Rf b, the coarse correction, then x = x1 + P xc
+    AmgDevLevel& C = *H.lv[l + 1];
+    const int nc = int(C.n);
+    T* bc = reinterpret_cast<T*>(C.vb.p);
+    T* xc = reinterpret_cast<T*>(C.vo.p);
+    const int GR = row_split(L.avg_rf, PPL);
+    hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
+                       dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
+                       GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
+    amg_level_vw<T, PPL, VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kCgThreads, true>), dim3(gfine),
+                       dim3(kCgThreads), 0, s, k, ctl, n, p, std::max(GA, GP), L.arp, L.aci,
+                       lv.a, dinv, b, L.Prp.p, L.Pci.p, lv.p, xc, L.alpha, L.beta, x);
+  } else {
   // pre-smoothing from zero: the first step's iterate s0 D^{-1} b stays implicit
   bool implicit = true;
   for (int st = 1; st < L.degree; ++st) {
@@ -558,6 +618,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     hipLaunchKernelGGL((k_amg_prolong<T, PPL, VW, kThreads, false>), dim3(gcoarse_p),
                        dim3(kThreads), 0, s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv,
                        b, L.ad[0], pmode, x);
+  }
   // post-smoothing from x, the same polynomial (symmetric V-cycle)
   for (int st = 0; st < L.degree; ++st) {
     const bool last = (st + 1 == L.degree);
@@ -1930,21 +1991,80 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
     H->lv.push_back(std::move(L));
   }
   upload_vec(H->cinv, h.coarse_inv);
+  const int nlev = int(h.lv.size());
+  const int64_t nc_last = h.lv.back().A.nrows, nl_last = h.lv[nlev - 2].A.nrows;
+  const bool dense_last = nc_last * nl_last <= kAmgFusedMax;
+  // fused levels: below the finest, above the coarsest, one smoothing step
+  for (int l = 1; l + 1 < nlev; ++l) {
+    AmgDevLevel& L = *H->lv[l];
+    if (L.degree != 1) continue;
+    const AmgLevelHost& Lh = h.lv[l];
+    const double s0 = L.ad[0];
+    L.fused = true;
+    L.alpha = 2.0 * s0;
+    L.beta = s0 * s0;
+    const HostCsr Pf = csr_matmul(jacobi_step_operator(Lh.A, Lh.dinv, s0, true), Lh.P);
+    upload_csr(Pf, L.Pfrp, L.Pfci, L.Pfv);
+    upload_vec(L.Pfv32, Pf.v);
+    L.avg_pf = double(Pf.nnz()) / double(std::max<int64_t>(1, Pf.nrows));
+    if (l + 2 == nlev && dense_last) continue;   // Inv Rf below
+    const HostCsr Rf = csr_matmul(Lh.R, jacobi_step_operator(Lh.A, Lh.dinv, s0, false));
+    upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
+    upload_vec(L.Rfv32, Rf.v);
+    L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
+  }
   {
-    // Inv R for the level above the coarsest: nc x n_l dense, built from the
-    // sparse R row by row (same sums as R then Inv, another order)
-    const AmgLevelHost& Lp = h.lv[h.lv.size() - 2];
-    const int64_t nc = h.lv.back().A.nrows, nl = Lp.A.nrows;
-    if (nc * nl <= kAmgFusedMax) {
-      std::vector<double> IR(size_t(nc) * nl, 0.0);
-      for (int64_t i = 0; i < nc; ++i)
-        for (int64_t q = 0; q < nc; ++q) {
-          const double a = h.coarse_inv[size_t(i) * nc + q];
-          for (int64_t e = Lp.R.rp[q]; e < Lp.R.rp[q + 1]; ++e)
-            IR[size_t(i) * nl + Lp.R.ci[e]] += a * Lp.R.v[e];
-        }
-      upload_vec(H->cinvR, IR);
+    // the finest level at degree 2, when it restricts to a sparse level:
+    // x1 = D^{-1} (alpha b - beta A D^{-1} b), b - A x1 = (I - A D^{-1} S) b
+    // with S = alpha I - beta A D^{-1}
+    AmgDevLevel& L = *H->lv[0];
+    if (L.degree == 2 && !(nlev == 2 && dense_last)) {
+      const AmgLevelHost& Lh = h.lv[0];
+      L.alpha = (1.0 + L.cd[1]) * L.ad[0] + L.ad[1];
+      L.beta = L.ad[1] * L.ad[0];
+      HostCsr M = Lh.A;   // A D^{-1}
+      for (int64_t e = 0; e < M.nnz(); ++e) M.v[e] *= Lh.dinv[M.ci[e]];
+      HostCsr I;
+      I.nrows = I.ncols = M.nrows;
+      I.rp.resize(I.nrows + 1);
+      I.ci.resize(I.nrows);
+      I.v.assign(I.nrows, 1.0);
+      for (int64_t i = 0; i <= I.nrows; ++i) I.rp[i] = i;
+      for (int64_t i = 0; i < I.nrows; ++i) I.ci[i] = int32_t(i);
+      const HostCsr S = csr_add(I, M, L.alpha, -L.beta);
+      const HostCsr E = csr_add(I, csr_matmul(M, S), 1.0, -1.0);
+      const HostCsr Rf = csr_matmul(Lh.R, E);
+      upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
+      upload_vec(L.Rfv32, Rf.v);
+      L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
+      L.fused = true;
     }
+  }
+  if (dense_last) {
+    // Inv R for the level above the coarsest: nc x n_l dense, built from the
+    // sparse R row by row (same sums as R then Inv, another order); on a
+    // fused level Inv Rf = (Inv R)(I - s0 A D^{-1}), built from it the same way
+    const AmgLevelHost& Lp = h.lv[nlev - 2];
+    const int64_t nc = nc_last, nl = nl_last;
+    std::vector<double> IR(size_t(nc) * nl, 0.0);
+    for (int64_t i = 0; i < nc; ++i)
+      for (int64_t q = 0; q < nc; ++q) {
+        const double a = h.coarse_inv[size_t(i) * nc + q];
+        for (int64_t e = Lp.R.rp[q]; e < Lp.R.rp[q + 1]; ++e)
+          IR[size_t(i) * nl + Lp.R.ci[e]] += a * Lp.R.v[e];
+      }
+    if (H->lv[nlev - 2]->fused) {
+      const HostCsr M = jacobi_step_operator(Lp.A, Lp.dinv, H->lv[nlev - 2]->ad[0], false);
+      std::vector<double> IRf(size_t(nc) * nl, 0.0);
+      for (int64_t i = 0; i < nc; ++i)
+        for (int64_t q = 0; q < nl; ++q) {
+          const double a = IR[size_t(i) * nl + q];
+          for (int64_t e = M.rp[q]; e < M.rp[q + 1]; ++e)
+            IRf[size_t(i) * nl + M.ci[e]] += a * M.v[e];
+        }
+      IR.swap(IRf);
+    }
+    upload_vec(H->cinvR, IR);
   }
   (tr && !pl->symmetric ? pl->amgT : pl->amg) = std::move(H);
   pl->ws.p = 0;   // workspace re-sized with the AMG vectors on the next call

@@ -28,6 +28,8 @@ def announce(name):
 def _workload(name):
     if name == "lap3d20":
         A, t = wl.laplacian_3d(20), 5.842338 / (3 * (2 - 2 * np.cos(np.pi / 21)))
+    elif name == "lap3d40":   # four levels: a sparse fused restriction on level 1
+        A, t = wl.laplacian_3d(40), 5.842338 / (3 * (2 - 2 * np.cos(np.pi / 41)))
     elif name == "vardiff96":
         A, t = wl.vardiff_2d(96, 205), 0.1
     else:
@@ -44,7 +46,8 @@ def _host_vcycle(A, t, degree):
 
 @pytest.mark.parametrize("name,p,degree", [("lap3d20", 8, 2), ("lap3d20", 3, 1),
                                            ("vardiff96", 32, 2), ("lap2d70", 1, 3),
-                                           ("vardiff96", 16, 4)])
+                                           ("vardiff96", 16, 4), ("lap3d40", 8, 2),
+                                           ("lap3d40", 5, 1)])
 def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
     announce(f"V-cycle {name} p={p} degree={degree}")
     A, t = _workload(name)
@@ -139,10 +142,11 @@ def _convdiff(N):
     return A, 3.33 / float(lam.real.min())
 
 
-@pytest.mark.parametrize("p,transpose", [(4, False), (4, True), (16, False)])
-def test_device_vcycle_nonsymmetric_matches_numpy(p, transpose):
-    announce(f"V-cycle convdiff 20^3 p={p} transpose={transpose}")
-    A, t = _convdiff(20)
+@pytest.mark.parametrize("N,p,transpose", [(20, 4, False), (20, 4, True), (20, 16, False),
+                                           (40, 4, True)])
+def test_device_vcycle_nonsymmetric_matches_numpy(N, p, transpose):
+    announce(f"V-cycle convdiff {N}^3 p={p} transpose={transpose}")
+    A, t = _convdiff(N)
     pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg")
     X = np.random.default_rng(p).standard_normal((A.n, p))
     Y = pl.apply_preconditioner(torch.from_numpy(X), transpose=transpose).cpu().numpy()
