@@ -391,51 +391,59 @@ k_cg_c(int k, int n, int p, const T* __restrict__ dinv, const T* __restrict__ r,
     }
   }
   reduce_parts<PP, 2>(part_rr, gridDim.x, red, tot);   // tot[c] = rho_k, tot[PP + c] = |r_k|^2
-  if (threadIdx.x == 0) {
-    int any = 0, itmax = 0, hit = 0;
+  if (threadIdx.x < 64) {
+    // one lane per column (PP <= 64), the control word from the wavefront's
+    // reductions: the scalar loads of all columns are in flight together
+    const int cc = threadIdx.x;
     const CgSlot& prev = st->slot[(k + 1) & 1];
-    for (int cc = 0; cc < PP; ++cc) {
-      double beta = 0.0, aprev = 0.0;
-      int act = 0, it = 0;
-      if (cc < p) {
-        const double rho = tot[cc], rn = tot[PP + cc];
-        double bn;
-        int act_prev;
-        if (k == 0) {
-          bn = rn;
-          act_prev = bn > 0.0;
-        } else {
-          bn = st->bnorm2[cc];
-          act_prev = prev.active[cc];
-          it = prev.iters[cc];
-          aprev = prev.alpha[cc];
-          beta = (act_prev && prev.rho[cc] != 0.0) ? rho / prev.rho[cc] : 0.0;
-        }
-        act = act_prev && !(rn <= tol2 * bn);
-        if (act && it >= maxit) {
-          act = 0;
-          hit = 1;
-        }
-        if (!act) beta = 0.0;
-        if (blockIdx.x == 0) {
-          CgSlot& cur = st->slot[k & 1];
-          cur.rho[cc] = rho;
-          cur.active[cc] = act;
-          cur.iters[cc] = it + act;
-          if (k == 0) st->bnorm2[cc] = bn;
-        }
-        if (it > itmax) itmax = it;
+    double beta = 0.0, aprev = 0.0;
+    int act = 0, it = 0, hit = 0;
+    if (cc < p) {
+      const double rho = tot[cc], rn = tot[PP + cc];
+      double bn;
+      int act_prev;
+      if (k == 0) {
+        bn = rn;
+        act_prev = bn > 0.0;
+      } else {
+        bn = st->bnorm2[cc];
+        act_prev = prev.active[cc];
+        it = prev.iters[cc];
+        aprev = prev.alpha[cc];
+        beta = (act_prev && prev.rho[cc] != 0.0) ? rho / prev.rho[cc] : 0.0;
       }
+      act = act_prev && !(rn <= tol2 * bn);
+      if (act && it >= maxit) {
+        act = 0;
+        hit = 1;
+      }
+      if (!act) beta = 0.0;
+      if (blockIdx.x == 0) {
+        CgSlot& cur = st->slot[k & 1];
+        cur.rho[cc] = rho;
+        cur.active[cc] = act;
+        cur.iters[cc] = it + act;
+        if (k == 0) st->bnorm2[cc] = bn;
+      }
+    }
+    if (cc < PP) {
       s_beta[cc] = beta;
       s_aprev[cc] = aprev;
-      any |= act;
     }
-    s_any = any;
-    if (blockIdx.x == 0 && !any) {
-      ctl->iters_max = itmax;
-      ctl->hit_cap = hit;
-      __threadfence();
-      ctl->done = k;
+    int any = act, itmax = it;
+    for (int off = 32; off >= 1; off >>= 1) {
+      any |= __shfl_xor(any, off, 64);
+      hit |= __shfl_xor(hit, off, 64);
+      itmax = max(itmax, __shfl_xor(itmax, off, 64));
+    }
+    if (cc == 0) {
+      s_any = any;
+      if (blockIdx.x == 0 && !any) {
+        ctl->iters_max = itmax;
+        ctl->hit_cap = hit;
+        __threadfence();
+        ctl->done = k;
+      }
     }
   }
   __syncthreads();
@@ -663,57 +671,63 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
   __shared__ double s_beta[PP], s_om[PP];
   __shared__ int s_any;
   reduce_parts<PP, 2>(part_rr, gridDim.x, red, tot);
-  if (threadIdx.x == 0) {
-    int any = 0, itmax = 0, hit = 0;
-    for (int cc = 0; cc < PP; ++cc) {
-      double beta = 0.0, om = 0.0;
-      int act = 0;
-      if (cc < p) {
-        const double rho = tot[cc], rn = tot[PP + cc];
-        double bn, rho_prev, a_prev, om_prev;
-        int act_prev, it;
-        const BcgSlot& prev = st->slot[(i + 1) & 1];
-        if (i == 0) {
-          bn = rn;
-          act_prev = bn > 0.0;
-          it = 0;
-          rho_prev = a_prev = om_prev = 1.0;
-        } else {
-          bn = st->bnorm2[cc];
-          act_prev = prev.active[cc];
-          it = prev.iters[cc];
-          rho_prev = prev.rho[cc];
-          a_prev = prev.alpha[cc];
-          om_prev = prev.omega[cc];
-        }
-        act = act_prev && !(rn <= tol2 * bn);
-        if (act && (it >= maxit || rho == 0.0 || om_prev == 0.0 || rho_prev == 0.0)) {
-          act = 0;
-          hit = 1;
-        }
-        if (act) {
-          beta = (rho / rho_prev) * (a_prev / om_prev);
-          om = om_prev;
-        }
-        if (blockIdx.x == 0) {
-          BcgSlot& cur = st->slot[i & 1];
-          cur.rho[cc] = rho;
-          cur.active[cc] = act;
-          cur.iters[cc] = it + act;
-          if (i == 0) st->bnorm2[cc] = bn;
-        }
-        if (it > itmax) itmax = it;
+  if (threadIdx.x < 64) {
+    // one lane per column, as in k_cg_c
+    const int cc = threadIdx.x;
+    double beta = 0.0, om = 0.0;
+    int act = 0, it = 0, hit = 0;
+    if (cc < p) {
+      const double rho = tot[cc], rn = tot[PP + cc];
+      double bn, rho_prev, a_prev, om_prev;
+      int act_prev;
+      const BcgSlot& prev = st->slot[(i + 1) & 1];
+      if (i == 0) {
+        bn = rn;
+        act_prev = bn > 0.0;
+        rho_prev = a_prev = om_prev = 1.0;
+      } else {
+        bn = st->bnorm2[cc];
+        act_prev = prev.active[cc];
+        it = prev.iters[cc];
+        rho_prev = prev.rho[cc];
+        a_prev = prev.alpha[cc];
+        om_prev = prev.omega[cc];
       }
+      act = act_prev && !(rn <= tol2 * bn);
+      if (act && (it >= maxit || rho == 0.0 || om_prev == 0.0 || rho_prev == 0.0)) {
+        act = 0;
+        hit = 1;
+      }
+      if (act) {
+        beta = (rho / rho_prev) * (a_prev / om_prev);
+        om = om_prev;
+      }
+      if (blockIdx.x == 0) {
+        BcgSlot& cur = st->slot[i & 1];
+        cur.rho[cc] = rho;
+        cur.active[cc] = act;
+        cur.iters[cc] = it + act;
+        if (i == 0) st->bnorm2[cc] = bn;
+      }
+    }
+    if (cc < PP) {
       s_beta[cc] = beta;
       s_om[cc] = om;
-      any |= act;
     }
-    s_any = any;
-    if (blockIdx.x == 0 && !any) {
-      ctl->iters_max = itmax;
-      ctl->hit_cap = hit;
-      __threadfence();
-      ctl->done = i;
+    int any = act, itmax = it;
+    for (int off = 32; off >= 1; off >>= 1) {
+      any |= __shfl_xor(any, off, 64);
+      hit |= __shfl_xor(hit, off, 64);
+      itmax = max(itmax, __shfl_xor(itmax, off, 64));
+    }
+    if (cc == 0) {
+      s_any = any;
+      if (blockIdx.x == 0 && !any) {
+        ctl->iters_max = itmax;
+        ctl->hit_cap = hit;
+        __threadfence();
+        ctl->done = i;
+      }
     }
   }
   __syncthreads();
