@@ -31,6 +31,12 @@ HostCsr csr_transpose(const HostCsr& A) {
   return T;
 }
 
+int64_t csr_product_nnz_bound(const HostCsr& A, const HostCsr& B) {
+  int64_t s = 0;
+  for (int64_t e = 0; e < A.nnz(); ++e) s += B.rp[A.ci[e] + 1] - B.rp[A.ci[e]];
+  return s;
+}
+
 HostCsr csr_add(const HostCsr& A, const HostCsr& B, double a, double b) {
   HostCsr C;
   C.nrows = A.nrows;

@@ -58,6 +58,10 @@ HostCsr csr_matmul(const HostCsr& A, const HostCsr& B);
 // I - s A D^{-1} (left = false) or I - s D^{-1} A (left = true) with
 // D^{-1} = diag(dinv), on A's pattern plus the diagonal: the residual map
 // b - A x and the error map of one Jacobi step x = s D^{-1} b.
+// sum over the entries a_ik of A of the length of row k of B: an upper
+// bound of nnz(A B) that costs one pass over A
+int64_t csr_product_nnz_bound(const HostCsr& A, const HostCsr& B);
+
 // a A + b B (union of the patterns)
 HostCsr csr_add(const HostCsr& A, const HostCsr& B, double a, double b);
 

@@ -110,6 +110,7 @@ struct Workspace {
 
 constexpr int kAmgMaxDeg = 4;
 constexpr double kAmgEigRatio = 20.0;   // Chebyshev interval [lmax / ratio, lmax]
+constexpr int64_t kAmgFuseGrowth = 16;  // fused operators: at most this many times nnz(A) + nnz(P)
 constexpr int kSmoothEv = 4 * kAmgMaxDeg;   // events around the finest level's smoothing steps
 constexpr int kSampleEv = 6 + kSmoothEv;    // events of one profiled inner iteration
 
@@ -1994,21 +1995,27 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
   const int nlev = int(h.lv.size());
   const int64_t nc_last = h.lv.back().A.nrows, nl_last = h.lv[nlev - 2].A.nrows;
   const bool dense_last = nc_last * nl_last <= kAmgFusedMax;
-  // fused levels: below the finest, above the coarsest, one smoothing step
+  // fused levels: below the finest, above the coarsest, one smoothing step;
+  // a level whose fused operators could outgrow kAmgFuseGrowth times its own
+  // operator and prolongator (a bound on the product patterns) stays unfused
   for (int l = 1; l + 1 < nlev; ++l) {
     AmgDevLevel& L = *H->lv[l];
     if (L.degree != 1) continue;
     const AmgLevelHost& Lh = h.lv[l];
     const double s0 = L.ad[0];
+    const HostCsr N = jacobi_step_operator(Lh.A, Lh.dinv, s0, true);
+    const HostCsr Mr = jacobi_step_operator(Lh.A, Lh.dinv, s0, false);
+    const int64_t cap = kAmgFuseGrowth * (Lh.A.nnz() + Lh.P.nnz());
+    if (csr_product_nnz_bound(N, Lh.P) > cap || csr_product_nnz_bound(Lh.R, Mr) > cap) continue;
     L.fused = true;
     L.alpha = 2.0 * s0;
     L.beta = s0 * s0;
-    const HostCsr Pf = csr_matmul(jacobi_step_operator(Lh.A, Lh.dinv, s0, true), Lh.P);
+    const HostCsr Pf = csr_matmul(N, Lh.P);
     upload_csr(Pf, L.Pfrp, L.Pfci, L.Pfv);
     upload_vec(L.Pfv32, Pf.v);
     L.avg_pf = double(Pf.nnz()) / double(std::max<int64_t>(1, Pf.nrows));
     if (l + 2 == nlev && dense_last) continue;   // Inv Rf below
-    const HostCsr Rf = csr_matmul(Lh.R, jacobi_step_operator(Lh.A, Lh.dinv, s0, false));
+    const HostCsr Rf = csr_matmul(Lh.R, Mr);
     upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
     upload_vec(L.Rfv32, Rf.v);
     L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
@@ -2022,22 +2029,31 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
       const AmgLevelHost& Lh = h.lv[0];
       L.alpha = (1.0 + L.cd[1]) * L.ad[0] + L.ad[1];
       L.beta = L.ad[1] * L.ad[0];
+      const double alpha = (1.0 + L.cd[1]) * L.ad[0] + L.ad[1];
+      const double beta = L.ad[1] * L.ad[0];
+      const int64_t cap = kAmgFuseGrowth * (Lh.A.nnz() + Lh.P.nnz());
       HostCsr M = Lh.A;   // A D^{-1}
       for (int64_t e = 0; e < M.nnz(); ++e) M.v[e] *= Lh.dinv[M.ci[e]];
-      HostCsr I;
-      I.nrows = I.ncols = M.nrows;
-      I.rp.resize(I.nrows + 1);
-      I.ci.resize(I.nrows);
-      I.v.assign(I.nrows, 1.0);
-      for (int64_t i = 0; i <= I.nrows; ++i) I.rp[i] = i;
-      for (int64_t i = 0; i < I.nrows; ++i) I.ci[i] = int32_t(i);
-      const HostCsr S = csr_add(I, M, L.alpha, -L.beta);
-      const HostCsr E = csr_add(I, csr_matmul(M, S), 1.0, -1.0);
-      const HostCsr Rf = csr_matmul(Lh.R, E);
-      upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
-      upload_vec(L.Rfv32, Rf.v);
-      L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
-      L.fused = true;
+      if (csr_product_nnz_bound(M, M) + M.nrows <= cap) {
+        HostCsr I;
+        I.nrows = I.ncols = M.nrows;
+        I.rp.resize(I.nrows + 1);
+        I.ci.resize(I.nrows);
+        I.v.assign(I.nrows, 1.0);
+        for (int64_t i = 0; i <= I.nrows; ++i) I.rp[i] = i;
+        for (int64_t i = 0; i < I.nrows; ++i) I.ci[i] = int32_t(i);
+        const HostCsr S = csr_add(I, M, alpha, -beta);
+        const HostCsr E = csr_add(I, csr_matmul(M, S), 1.0, -1.0);
+        if (csr_product_nnz_bound(Lh.R, E) <= cap) {
+          const HostCsr Rf = csr_matmul(Lh.R, E);
+          upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
+          upload_vec(L.Rfv32, Rf.v);
+          L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
+          L.alpha = alpha;
+          L.beta = beta;
+          L.fused = true;
+        }
+      }
     }
   }
   if (dense_last) {

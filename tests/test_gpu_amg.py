@@ -30,6 +30,8 @@ def _workload(name):
         A, t = wl.laplacian_3d(20), 5.842338 / (3 * (2 - 2 * np.cos(np.pi / 21)))
     elif name == "lap3d40":   # four levels: a sparse fused restriction on level 1
         A, t = wl.laplacian_3d(40), 5.842338 / (3 * (2 - 2 * np.cos(np.pi / 41)))
+    elif name == "lap2d40":   # two levels: the finest level restricts into the dense solve
+        A, t = wl.laplacian_2d(40), 30.0
     elif name == "vardiff96":
         A, t = wl.vardiff_2d(96, 205), 0.1
     else:
@@ -47,7 +49,7 @@ def _host_vcycle(A, t, degree):
 @pytest.mark.parametrize("name,p,degree", [("lap3d20", 8, 2), ("lap3d20", 3, 1),
                                            ("vardiff96", 32, 2), ("lap2d70", 1, 3),
                                            ("vardiff96", 16, 4), ("lap3d40", 8, 2),
-                                           ("lap3d40", 5, 1)])
+                                           ("lap3d40", 5, 1), ("lap2d40", 4, 2)])
 def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
     announce(f"V-cycle {name} p={p} degree={degree}")
     A, t = _workload(name)
