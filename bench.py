@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # recorded value; any change to them makes `traffic` null until re-measured.
 MEASURED_TRAFFIC = {
     "S": {"bytes": 100.8e6, "sources": ("amg.hpp", "kernels.hpp"),
-          "sha256": "5681fd094b1b4213f09ca76ce245c258ca99146734d28ecf04cd363f3908efad"},
+          "sha256": "60ee44af6d9aa05c6c8a853892e494e258d5fd5308ff28ad51eacdb4ad1b917b"},
 }
 
 
@@ -79,6 +79,8 @@ def parse():
                          "'suite'")
     ap.add_argument("--vardiff-n", type=int, default=256,
                     help="grid side of the variable-coefficient workload in --suite")
+    ap.add_argument("--suite-parts", default=",".join(SUITE_PARTS),
+                    help="comma-separated parts of --suite: " + ", ".join(SUITE_PARTS))
     ap.add_argument("--profile-every", type=int, default=4,
                     help="sample every N-th inner iteration with HIP events (0 = off)")
     ap.add_argument("--inner", choices=["auto", "amg", "jacobi"], default="auto",
@@ -158,9 +160,13 @@ def cpu_baseline(W):
                        "MGS cost grows faster than linearly, so this underestimates")}
 
 
-def run_suite(dev, vardiff_n):
+SUITE_PARTS = ("toeplitz", "fractional", "example53", "convdiff", "vardiff")
+
+
+def run_suite(dev, vardiff_n, parts=SUITE_PARTS):
     """Secondary measurements: one timed solve each (the Toeplitz one after a
-    warm-up; the large ones cold, their first-call setup being negligible)."""
+    warm-up; the large ones cold, their first-call setup being negligible);
+    `parts` selects among SUITE_PARTS."""
     import numpy as np
     import torch
 
@@ -182,6 +188,24 @@ def run_suite(dev, vardiff_n):
         return el, out
 
     res = {}
+    if "toeplitz" in parts:
+        _suite_toeplitz(dev, timed, res)
+    if "fractional" in parts:
+        _suite_fractional(dev, timed, res)
+    if "example53" in parts:
+        _suite_example53(dev, timed, res)
+    if "convdiff" in parts:
+        _suite_convdiff(dev, timed, res)
+    if "vardiff" in parts:
+        _suite_vardiff(dev, timed, res, vardiff_n)
+    return res
+
+
+def _suite_toeplitz(dev, timed, res):
+    import torch
+
+    import workloads as wl
+    from paper_1405_0707_amd import Plan
     # Toeplitz 2^20, p = 16, FP64
     W = wl.c3()
     pl = Plan.toeplitz(torch.from_numpy(W.col), W.t, device=dev, m=W.m, k=W.k)
@@ -190,6 +214,13 @@ def run_suite(dev, vardiff_n):
     res["toeplitz_2^20_p16_fp64"] = {"s": round(el, 4), "cycles": info.cycles,
                                      "err_bound": info.err_bound}
     del pl, B, Z
+
+
+def _suite_fractional(dev, timed, res):
+    import torch
+
+    import workloads as wl
+    from paper_1405_0707_amd import Plan
     # nonsymmetric fractional-diffusion Toeplitz 2^17, p = 2, m = 30: forward
     # and adjoint (e^{tA^T} G and grad_t), FP64
     W = wl.c6()
@@ -206,6 +237,14 @@ def run_suite(dev, vardiff_n):
                                                "cycles_adj": info_b.cycles,
                                                "err_bound": info_f.err_bound}
     del pl, B, G, Z, gB
+
+
+def _suite_example53(dev, timed, res):
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1405_0707_amd import Plan
     # Example 5.3: one-sided fractional diffusion with a source, A = -diag(d) T,
     # u(1) from the source-term driver on [u0 | b], m = 40, FP64
     for n in (1000, 2000, 3000):
@@ -226,6 +265,13 @@ def run_suite(dev, vardiff_n):
             "rel_err_vs_pde_solution": float(np.linalg.norm(U.cpu().numpy() - exact_pde)
                                              / np.linalg.norm(exact_pde))}
         del pl, U0, S, U
+
+
+def _suite_convdiff(dev, timed, res):
+    import torch
+
+    import workloads as wl
+    from paper_1405_0707_amd import Plan
     # convection-diffusion 128^3, p = 16: FP64 (tol 1e-10) and mixed (tol 1e-6)
     W = wl.c4()
     print("[suite] convection-diffusion 128^3 built", file=sys.stderr, flush=True)
@@ -244,6 +290,13 @@ def run_suite(dev, vardiff_n):
     res["convdiff_mixed_vs_fp64_rel_diff"] = float(torch.linalg.norm(Zs["mixed"] - Zs["fp64"])
                                                    / torch.linalg.norm(Zs["fp64"]))
     del Zs, B
+
+
+def _suite_vardiff(dev, timed, res, vardiff_n):
+    import torch
+
+    import workloads as wl
+    from paper_1405_0707_amd import Plan
     # variable-coefficient diffusion, forward + adjoint, mixed and FP64
     N = vardiff_n
     W = wl.c5(N=N)
@@ -269,7 +322,6 @@ def run_suite(dev, vardiff_n):
         "Z_rel_diff": float(torch.linalg.norm(zm - z64) / torch.linalg.norm(z64)),
         "gradB_rel_diff": float(torch.linalg.norm(gm - g64) / torch.linalg.norm(g64)),
         "gradt_rel_diff": abs(tm - t64) / abs(t64)}
-    return res
 
 
 def main():
@@ -369,7 +421,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
-    suite = run_suite(dev, args.vardiff_n) if args.suite else None
+    parts = tuple(x for x in args.suite_parts.split(",") if x)
+    suite = run_suite(dev, args.vardiff_n, parts) if args.suite else None
 
     cpu = None
     if not args.no_cpu_baseline:
