@@ -33,7 +33,9 @@ enum : int {
 // A row is handled by a group of PPL * G lanes: lane (l, g) = l + PPL g takes
 // the VW columns c = VW l .. VW l + VW - 1 (VW = 2 for even p: two adjacent
 // columns in one 8- or 16-byte access, half the lanes and index loads of one
-// column per lane) and the nonzeros e0 + g, e0 + g + G, ... of the row, and
+// column per lane; VW = 4 for FP32 blocks with p a multiple of 4: one 16-byte
+// access, with half the nonzeros per sub-lane step so that the registers stay
+// those of VW = 2) and the nonzeros e0 + g, e0 + g + G, ... of the row, and
 // the G partial sums of a column are added with shuffles inside the group
 // (G > 1 for the long rows of Galerkin operators and restrictions, whose
 // serial sums would otherwise set the kernel's latency).  PPL * G <= 64, so a
@@ -67,6 +69,11 @@ template <int VW, typename T>
 __device__ inline void load_vw(const T* __restrict__ src, double (&o)[VW]) {
   if constexpr (VW == 1) {
     o[0] = double(src[0]);
+  } else if constexpr (VW == 4) {   // FP32 only (see ld_vw)
+    T v[4];
+    ld_vw<4>(src, v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = double(v[q]);
   } else if constexpr (std::is_same<T, double>::value) {
     const double2 v = *reinterpret_cast<const double2*>(src);
     o[0] = v.x;
@@ -81,6 +88,11 @@ template <int VW, typename T>
 __device__ inline void store_vw(T* __restrict__ dst, const double (&o)[VW]) {
   if constexpr (VW == 1) {
     dst[0] = T(o[0]);
+  } else if constexpr (VW == 4) {
+    T v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = T(o[q]);
+    st_vw<4>(dst, v);
   } else if constexpr (std::is_same<T, double>::value) {
     *reinterpret_cast<double2*>(dst) = double2{o[0], o[1]};
   } else {
@@ -98,7 +110,7 @@ __device__ inline void row_dot_split(const int32_t* __restrict__ colind,
                                      const T* __restrict__ val, const T* __restrict__ x,
                                      const T* __restrict__ dinv, int e0, int e1, int ld, int c0,
                                      bool active, int g, int G, double (&acc)[VW]) {
-  constexpr int U = 8;   // nonzeros per sub-lane step, all loads issued first
+  constexpr int U = VW == 4 ? 4 : 8;   // nonzeros per sub-lane step, all loads issued first
 #pragma unroll
   for (int k = 0; k < VW; ++k) acc[k] = 0.0;
   if (active) {
@@ -148,7 +160,7 @@ __device__ inline void row_dot_pair(const int32_t* __restrict__ aci, const T* __
                                     const T* __restrict__ pv, const T* __restrict__ xc, int ep0,
                                     int ep1, int ld, int c0, bool active, int g, int G,
                                     double (&accA)[VW], double (&accP)[VW]) {
-  constexpr int U = 8;
+  constexpr int U = VW == 4 ? 4 : 8;
 #pragma unroll
   for (int k = 0; k < VW; ++k) accA[k] = accP[k] = 0.0;
   if (active) {

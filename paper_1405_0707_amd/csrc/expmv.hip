@@ -255,10 +255,17 @@ int grid_for(int64_t rows, int PP, int cap = 1024) {
     default: { constexpr int P_ = 32; __VA_ARGS__; } break; \
   }
 
-// CG kernels: PPL_ lanes per row with VW_ adjacent columns each (VW_ = 2 for
-// even p), PPL_ VW_ = PP
+// CG kernels (working type T): PPL_ lanes per row with VW_ adjacent columns
+// each (VW_ = 4 for FP32 and p a multiple of 4, else 2 for even p), PPL_ VW_ = PP
 #define CG_CASE(PPV, p, ...)                                                \
   case PPV:                                                                 \
+    if constexpr (sizeof(T) == 4 && PPV >= 4) {                             \
+      if ((p) % 4 == 0) {                                                   \
+        constexpr int PPL_ = PPV / 4, VW_ = 4;                              \
+        __VA_ARGS__;                                                        \
+        break;                                                              \
+      }                                                                     \
+    }                                                                       \
     if (PPV >= 2 && (p) % 2 == 0) {                                         \
       constexpr int PPL_ = (PPV >= 2 ? PPV / 2 : 1), VW_ = (PPV >= 2 ? 2 : 1); \
       __VA_ARGS__;                                                          \
@@ -631,10 +638,17 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
   }
 }
 
-// two adjacent columns per lane when p is even
+// two adjacent columns per lane when p is even, four for FP32 vectors when p
+// is a multiple of 4
 template <typename T, int PP>
 void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
                const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
+  if constexpr (sizeof(T) == 4 && PP >= 4) {
+    if (p % 4 == 0) {
+      amg_level_vw<T, PP / 4, 4>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
+      return;
+    }
+  }
   if constexpr (PP >= 2) {
     if (p % 2 == 0) {
       amg_level_vw<T, PP / 2, 2>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
@@ -743,10 +757,18 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
 }
 
 // BiCGStab's SpMM (k_bcg_s) with two adjacent columns per lane for even p
+// (four for FP32 when p is a multiple of 4)
 template <typename T, int PP, int NV>
 void bcg_spmm(hipStream_t s, int grid, int i, int n, int p, const int32_t* rowptr,
               const int32_t* colind, const double* val, const T* dinv, const T* in, const T* a,
               T* out, const KrylovCtl* ctl, double* part) {
+  if constexpr (sizeof(T) == 4 && PP >= 4) {
+    if (p % 4 == 0) {
+      hipLaunchKernelGGL((k_bcg_s<T, PP / 4, 4, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,
+                         rowptr, colind, val, dinv, in, a, out, ctl, part);
+      return;
+    }
+  }
   if constexpr (PP >= 2) {
     if (p % 2 == 0) {
       hipLaunchKernelGGL((k_bcg_s<T, PP / 2, 2, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,

@@ -245,12 +245,20 @@ __device__ inline void write_col_partial_vw(const double (&v)[VW], double* red, 
   }
 }
 
-// VW adjacent entries of a row-major block in the block's own type (VW = 2:
-// one 2-element access; the offset is even, so it is aligned)
+// VW adjacent entries of a row-major block in the block's own type, in one
+// access: VW = 2 (the offset is even, so it is aligned) or VW = 4 for FP32
+// (the offset and the row length are multiples of 4: a 16-byte access)
 template <int VW, typename T>
 __device__ inline void ld_vw(const T* __restrict__ src, T (&o)[VW]) {
+  static_assert(VW == 1 || VW == 2 || (VW == 4 && sizeof(T) == 4), "lane width");
   if constexpr (VW == 1) {
     o[0] = src[0];
+  } else if constexpr (VW == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(src);
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
   } else if constexpr (std::is_same<T, double>::value) {
     const double2 v = *reinterpret_cast<const double2*>(src);
     o[0] = v.x;
@@ -263,8 +271,11 @@ __device__ inline void ld_vw(const T* __restrict__ src, T (&o)[VW]) {
 }
 template <int VW, typename T>
 __device__ inline void st_vw(T* __restrict__ dst, const T (&o)[VW]) {
+  static_assert(VW == 1 || VW == 2 || (VW == 4 && sizeof(T) == 4), "lane width");
   if constexpr (VW == 1) {
     dst[0] = o[0];
+  } else if constexpr (VW == 4) {
+    *reinterpret_cast<float4*>(dst) = float4{o[0], o[1], o[2], o[3]};
   } else if constexpr (std::is_same<T, double>::value) {
     *reinterpret_cast<double2*>(dst) = double2{o[0], o[1]};
   } else {
@@ -277,7 +288,7 @@ template <int VW, typename T>
 __device__ inline void csr_row_dot_vw(const int32_t* __restrict__ colind,
                                       const double* __restrict__ val, const T* __restrict__ x,
                                       int e0, int e1, int ld, int c0, double (&acc)[VW]) {
-  constexpr int U = 8;
+  constexpr int U = VW == 4 ? 4 : 8;   // VW = 4: same registers as VW = 2
 #pragma unroll
   for (int q = 0; q < VW; ++q) acc[q] = 0.0;
   for (int e = e0; e < e1; e += U) {
