@@ -33,9 +33,9 @@ enum : int {
 // A row is handled by a group of PPL * G lanes: lane (l, g) = l + PPL g takes
 // the VW columns c = VW l .. VW l + VW - 1 (VW = 2 for even p: two adjacent
 // columns in one 8- or 16-byte access, half the lanes and index loads of one
-// column per lane; VW = 4 for FP32 blocks with p a multiple of 4: one 16-byte
-// access, with half the nonzeros per sub-lane step so that the registers stay
-// those of VW = 2) and the nonzeros e0 + g, e0 + g + G, ... of the row, and
+// column per lane; VW = 4 for p a multiple of 4 in FP32, or in FP64 from 16
+// columns: 16 or 32 bytes per lane, with half the nonzeros per sub-lane step
+// so that the registers stay those of VW = 2) and the nonzeros e0 + g, e0 + g + G, ... of the row, and
 // the G partial sums of a column are added with shuffles inside the group
 // (G > 1 for the long rows of Galerkin operators and restrictions, whose
 // serial sums would otherwise set the kernel's latency).  PPL * G <= 64, so a
@@ -69,7 +69,7 @@ template <int VW, typename T>
 __device__ inline void load_vw(const T* __restrict__ src, double (&o)[VW]) {
   if constexpr (VW == 1) {
     o[0] = double(src[0]);
-  } else if constexpr (VW == 4) {   // FP32 only (see ld_vw)
+  } else if constexpr (VW == 4) {
     T v[4];
     ld_vw<4>(src, v);
 #pragma unroll

@@ -255,11 +255,20 @@ int grid_for(int64_t rows, int PP, int cap = 1024) {
     default: { constexpr int P_ = 32; __VA_ARGS__; } break; \
   }
 
+// Four adjacent columns per lane (16-byte FP32 or 32-byte FP64 accesses per
+// lane) pay for FP32 blocks and for FP64 blocks of 16 or more columns; at
+// p = 8 in FP64, two lanes per row with two double2 loads each measured
+// slower than four lanes with one (59.4 against 57.7 ms per solve on the
+// 64^3 benchmark; 0.61 against 0.67 s at p = 32).
+template <typename T, int PP>
+constexpr bool kWide4 = PP >= 4 && (sizeof(T) == 4 || PP >= 16);
+
 // CG kernels (working type T): PPL_ lanes per row with VW_ adjacent columns
-// each (VW_ = 4 for FP32 and p a multiple of 4, else 2 for even p), PPL_ VW_ = PP
+// each, PPL_ VW_ = PP: VW_ = 4 when p is a multiple of 4 and the block is FP32
+// or at least 16 wide (kWide4), else 2 for even p
 #define CG_CASE(PPV, p, ...)                                                \
   case PPV:                                                                 \
-    if constexpr (sizeof(T) == 4 && PPV >= 4) {                             \
+    if constexpr (kWide4<T, PPV>) {                                         \
       if ((p) % 4 == 0) {                                                   \
         constexpr int PPL_ = PPV / 4, VW_ = 4;                              \
         __VA_ARGS__;                                                        \
@@ -638,12 +647,12 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
   }
 }
 
-// two adjacent columns per lane when p is even, four for FP32 vectors when p
-// is a multiple of 4
+// two adjacent columns per lane when p is even, four when p is a multiple of
+// 4 and kWide4
 template <typename T, int PP>
 void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
                const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
-  if constexpr (sizeof(T) == 4 && PP >= 4) {
+  if constexpr (kWide4<T, PP>) {
     if (p % 4 == 0) {
       amg_level_vw<T, PP / 4, 4>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
       return;
@@ -757,12 +766,12 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
 }
 
 // BiCGStab's SpMM (k_bcg_s) with two adjacent columns per lane for even p
-// (four for FP32 when p is a multiple of 4)
+// (four when p is a multiple of 4 and kWide4)
 template <typename T, int PP, int NV>
 void bcg_spmm(hipStream_t s, int grid, int i, int n, int p, const int32_t* rowptr,
               const int32_t* colind, const double* val, const T* dinv, const T* in, const T* a,
               T* out, const KrylovCtl* ctl, double* part) {
-  if constexpr (sizeof(T) == 4 && PP >= 4) {
+  if constexpr (kWide4<T, PP>) {
     if (p % 4 == 0) {
       hipLaunchKernelGGL((k_bcg_s<T, PP / 4, 4, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,
                          rowptr, colind, val, dinv, in, a, out, ctl, part);

@@ -245,14 +245,22 @@ __device__ inline void write_col_partial_vw(const double (&v)[VW], double* red, 
   }
 }
 
-// VW adjacent entries of a row-major block in the block's own type, in one
-// access: VW = 2 (the offset is even, so it is aligned) or VW = 4 for FP32
-// (the offset and the row length are multiples of 4: a 16-byte access)
+// VW adjacent entries of a row-major block in the block's own type: VW = 2
+// (the offset is even, so it is aligned: one access) or VW = 4 (the offset
+// and the row length are multiples of 4: one 16-byte FP32 access, or two
+// 16-byte FP64 ones)
 template <int VW, typename T>
 __device__ inline void ld_vw(const T* __restrict__ src, T (&o)[VW]) {
-  static_assert(VW == 1 || VW == 2 || (VW == 4 && sizeof(T) == 4), "lane width");
+  static_assert(VW == 1 || VW == 2 || VW == 4, "lane width");
   if constexpr (VW == 1) {
     o[0] = src[0];
+  } else if constexpr (VW == 4 && sizeof(T) == 8) {
+    const double2 v0 = *reinterpret_cast<const double2*>(src);
+    const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+    o[0] = v0.x;
+    o[1] = v0.y;
+    o[2] = v1.x;
+    o[3] = v1.y;
   } else if constexpr (VW == 4) {
     const float4 v = *reinterpret_cast<const float4*>(src);
     o[0] = v.x;
@@ -271,9 +279,12 @@ __device__ inline void ld_vw(const T* __restrict__ src, T (&o)[VW]) {
 }
 template <int VW, typename T>
 __device__ inline void st_vw(T* __restrict__ dst, const T (&o)[VW]) {
-  static_assert(VW == 1 || VW == 2 || (VW == 4 && sizeof(T) == 4), "lane width");
+  static_assert(VW == 1 || VW == 2 || VW == 4, "lane width");
   if constexpr (VW == 1) {
     dst[0] = o[0];
+  } else if constexpr (VW == 4 && sizeof(T) == 8) {
+    *reinterpret_cast<double2*>(dst) = double2{o[0], o[1]};
+    *reinterpret_cast<double2*>(dst + 2) = double2{o[2], o[3]};
   } else if constexpr (VW == 4) {
     *reinterpret_cast<float4*>(dst) = float4{o[0], o[1], o[2], o[3]};
   } else if constexpr (std::is_same<T, double>::value) {
