@@ -526,6 +526,10 @@ void amg_vectors(AmgDev& H, int p, size_t el) {
 // kernels take VW columns per lane and PPL = PP / VW lanes per row; the finest
 // level keeps the inner solver's grid (its partials are re-summed by the CG
 // kernels over that many workgroups).
+template <typename T, int PP>
+void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
+               const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev);
+
 template <typename T, int PPL, int VW>
 void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
                   const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
@@ -556,7 +560,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
       hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
                          dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
                          GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
-      amg_level_vw<T, PPL, VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+      amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
     }
     const int G = std::max(row_split(L.avg_a, PPL), row_split(L.avg_pf, PPL));
     hipLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
@@ -597,7 +601,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
                        dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
                        GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
-    amg_level_vw<T, PPL, VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+    amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
     hipLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kCgThreads, true>), dim3(gfine),
                        dim3(kCgThreads), 0, s, k, ctl, n, p, std::max(GA, GP), L.arp, L.aci,
                        lv.a, dinv, b, L.Prp.p, L.Pci.p, lv.p, xc, L.alpha, L.beta, x);
@@ -624,7 +628,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
                        dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
                        GR, L.Rrp.p, L.Rci.p, lv.r, r, bc);
-    amg_level_vw<T, PPL, VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+    amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
   }
   const int pmode = implicit ? kAmgX0 : 0;
   if (fine)
@@ -648,12 +652,13 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
 }
 
 // two adjacent columns per lane when p is even, four when p is a multiple of
-// 4 and kWide4
+// 4 and kWide4, and on the levels below the finest (their longer Galerkin
+// rows: 0.7% on the 64^3 benchmark); each level picks its own layout
 template <typename T, int PP>
 void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
                const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
-  if constexpr (kWide4<T, PP>) {
-    if (p % 4 == 0) {
+  if constexpr (PP >= 4) {
+    if (p % 4 == 0 && (kWide4<T, PP> || l > 0)) {
       amg_level_vw<T, PP / 4, 4>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
       return;
     }
