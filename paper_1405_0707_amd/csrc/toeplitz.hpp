@@ -13,6 +13,61 @@
 
 namespace expmv {
 
+// V = DFT_R(v): V_m = sum_r v_r exp(sign 2 pi i r m / R)
+template <int R>
+__device__ inline void dft_small(const cplx (&v)[R], cplx (&V)[R], double sign) {
+  if constexpr (R == 2) {
+    V[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
+    V[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
+  } else if constexpr (R == 4) {
+    const cplx a{v[0].x + v[2].x, v[0].y + v[2].y}, b{v[0].x - v[2].x, v[0].y - v[2].y};
+    const cplx c2{v[1].x + v[3].x, v[1].y + v[3].y}, d{v[1].x - v[3].x, v[1].y - v[3].y};
+    // d * (sign i)
+    const cplx di{-sign * d.y, sign * d.x};
+    V[0] = {a.x + c2.x, a.y + c2.y};
+    V[2] = {a.x - c2.x, a.y - c2.y};
+    V[1] = {b.x + di.x, b.y + di.y};
+    V[3] = {b.x - di.x, b.y - di.y};
+  } else {
+    // R = 8, 5, 3: V_m = sum_r v_r exp(sign 2 pi i r m / R), with the
+    // cosines and sines of 2 pi e / R, e = 0 .. R-1
+    static_assert(R == 8 || R == 5 || R == 3, "radix");
+    constexpr double h = 0.70710678118654752440;
+    constexpr double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+    constexpr double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+    constexpr double s3 = 0.86602540378443864676;
+    double cs[R], sn[R];
+    if constexpr (R == 8) {
+      const double c8[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
+      const double s8[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) cs[e] = c8[e], sn[e] = s8[e];
+    } else if constexpr (R == 5) {
+      const double c5[5] = {1.0, c1, c2, c2, c1};
+      const double s5[5] = {0.0, s1, s2, -s2, -s1};
+#pragma unroll
+      for (int e = 0; e < 5; ++e) cs[e] = c5[e], sn[e] = s5[e];
+    } else {
+      const double c3[3] = {1.0, -0.5, -0.5};
+      const double s3v[3] = {0.0, s3, -s3};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) cs[e] = c3[e], sn[e] = s3v[e];
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      double xr = 0.0, xi = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = (r * m) % R;
+        const double wr = cs[e], wi = sign * sn[e];
+        xr += v[r].x * wr - v[r].y * wi;
+        xi += v[r].x * wi + v[r].y * wr;
+      }
+      V[m] = {xr, xi};
+    }
+  }
+}
+
 // One Stockham pass of radix R over a length-L transform, q columns
 // interleaved (element i of column c at [i * q + c]).  Ns = product of the
 // radices of the earlier passes.  Thread (j, c), j < L / R:
@@ -42,59 +97,71 @@ k_fft_pass(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __re
       }
     }
     cplx V[R];
-    if constexpr (R == 2) {
-      V[0] = {v[0].x + v[1].x, v[0].y + v[1].y};
-      V[1] = {v[0].x - v[1].x, v[0].y - v[1].y};
-    } else if constexpr (R == 4) {
-      const cplx a{v[0].x + v[2].x, v[0].y + v[2].y}, b{v[0].x - v[2].x, v[0].y - v[2].y};
-      const cplx c2{v[1].x + v[3].x, v[1].y + v[3].y}, d{v[1].x - v[3].x, v[1].y - v[3].y};
-      // d * (sign i)
-      const cplx di{-sign * d.y, sign * d.x};
-      V[0] = {a.x + c2.x, a.y + c2.y};
-      V[2] = {a.x - c2.x, a.y - c2.y};
-      V[1] = {b.x + di.x, b.y + di.y};
-      V[3] = {b.x - di.x, b.y - di.y};
-    } else {
-      // R = 8, 5, 3: V_m = sum_r v_r exp(sign 2 pi i r m / R), with the
-      // cosines and sines of 2 pi e / R, e = 0 .. R-1
-      static_assert(R == 8 || R == 5 || R == 3, "radix");
-      constexpr double h = 0.70710678118654752440;
-      constexpr double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
-      constexpr double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
-      constexpr double s3 = 0.86602540378443864676;
-      double cs[R], sn[R];
-      if constexpr (R == 8) {
-        const double c8[8] = {1.0, h, 0.0, -h, -1.0, -h, 0.0, h};
-        const double s8[8] = {0.0, h, 1.0, h, 0.0, -h, -1.0, -h};
-#pragma unroll
-        for (int e = 0; e < 8; ++e) cs[e] = c8[e], sn[e] = s8[e];
-      } else if constexpr (R == 5) {
-        const double c5[5] = {1.0, c1, c2, c2, c1};
-        const double s5[5] = {0.0, s1, s2, -s2, -s1};
-#pragma unroll
-        for (int e = 0; e < 5; ++e) cs[e] = c5[e], sn[e] = s5[e];
-      } else {
-        const double c3[3] = {1.0, -0.5, -0.5};
-        const double s3v[3] = {0.0, s3, -s3};
-#pragma unroll
-        for (int e = 0; e < 3; ++e) cs[e] = c3[e], sn[e] = s3v[e];
-      }
-#pragma unroll
-      for (int m = 0; m < R; ++m) {
-        double xr = 0.0, xi = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int e = (r * m) % R;
-          const double wr = cs[e], wi = sign * sn[e];
-          xr += v[r].x * wr - v[r].y * wi;
-          xi += v[r].x * wi + v[r].y * wr;
-        }
-        V[m] = {xr, xi};
-      }
-    }
+    dft_small<R>(v, V, sign);
     const int64_t idxD = (j / Ns) * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[(idxD + r * Ns) * q + c] = V[r];
+  }
+}
+
+// One Stockham pass of radix 64 (same index map as k_fft_pass<64>), the
+// 64-point DFT as 8 x 8 in LDS: with r = r1 + 8 r2 and m = m2 + 8 m1,
+//   X_m = sum_r1 w8^(r1 m1) w64^(r1 m2) Y_r1(m2),  Y_r1(m2) = sum_r2 v_(r1+8 r2) w8^(r2 m2)
+// (w_N = exp(sign 2 pi i / N)).  A workgroup of 512 threads takes 64 (j, c)
+// pairs, eight threads t per pair: thread t loads v_(t + 8 s), s < 8, forms
+// Y_t, scales it by w64^(t m2) and writes it to LDS; after a barrier thread t
+// reads Y_r1(t) of its pair and writes X_(t + 8 m1), m1 < 8.  One pass over
+// the data instead of two radix-8 passes.
+constexpr int kFft64Threads = 512;
+__global__ void __launch_bounds__(kFft64Threads)
+k_fft_pass64(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __restrict__ out,
+             double sign) {
+  __shared__ cplx sY[8][8][64];   // [r1][m2][pair]
+  const int pc = threadIdx.x % 64, t = threadIdx.x / 64;
+  const int64_t pairs = (L / 64) * q;
+  const int64_t stride = L / 64;
+  for (int64_t base = int64_t(blockIdx.x) * 64; base < pairs; base += int64_t(gridDim.x) * 64) {
+    const int64_t gp = base + pc;
+    const bool ok = gp < pairs;
+    const int64_t j = ok ? gp / q : 0;
+    const int c = ok ? int(gp % q) : 0;
+    const int64_t k = j % Ns;
+    cplx v[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2)
+      v[s2] = ok ? in[(j + (t + 8 * s2) * stride) * q + c] : cplx{0.0, 0.0};
+    if (Ns > 1) {
+      // v_r *= w^(r k), w = exp(sign 2 pi i / (Ns 64)), r = t + 8 s2
+      double sb, cb, ss, cs;
+      sincospi(sign * 2.0 * double(t * k) / double(Ns * 64), &sb, &cb);
+      sincospi(sign * 2.0 * double(8 * k) / double(Ns * 64), &ss, &cs);
+      cplx wr{cb, sb};
+      const cplx w8{cs, ss};
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) {
+        v[s2] = cmul(v[s2], wr);
+        wr = cmul(wr, w8);
+      }
+    }
+    cplx Y[8];
+    dft_small<8>(v, Y, sign);
+#pragma unroll
+    for (int m2 = 0; m2 < 8; ++m2) {
+      double si, co;
+      sincospi(sign * 2.0 * double(t * m2) / 64.0, &si, &co);
+      sY[t][m2][pc] = cmul(Y[m2], cplx{co, si});
+    }
+    __syncthreads();
+    cplx Z[8], X[8];
+#pragma unroll
+    for (int r1 = 0; r1 < 8; ++r1) Z[r1] = sY[r1][t][pc];
+    __syncthreads();   // sY is rewritten by the next group of pairs
+    dft_small<8>(Z, X, sign);
+    if (ok) {
+      const int64_t idxD = (j / Ns) * Ns * 64 + k;
+#pragma unroll
+      for (int m1 = 0; m1 < 8; ++m1) out[(idxD + (t + 8 * m1) * Ns) * q + c] = X[m1];
+    }
   }
 }
 
