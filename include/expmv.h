@@ -310,6 +310,18 @@ expmv_status expmv_host_amg_level(expmv_amg h, int level, int64_t* dims, double*
                                   int32_t* agg);
 /* Dense row-major inverse of the coarsest operator (n_c x n_c doubles). */
 expmv_status expmv_host_amg_coarse_inverse(expmv_amg h, double* inv);
+/* The fused transfer operators the device V-cycle uses on level `level`
+ * (not the coarsest), host CSR.  which = 0: the restriction of the residual
+ * of the pre-smoothed iterate x1 = D^{-1}(alpha b - beta A D^{-1} b),
+ * Rf = R (I - A D^{-1} (alpha I - beta A D^{-1})), n_{l+1} x n_l (one smoothing
+ * step from zero: alpha = s0, beta = 0); which = 1: the prolongation followed
+ * by one smoothing step x += alpha D^{-1}(b - A x), Pf = (I - alpha D^{-1} A) P,
+ * n_l x n_{l+1} (beta ignored).  dims receives rows, columns, nnz; the
+ * arrays (rowptr rows + 1, colind and val nnz; NULL: sizes only) receive the
+ * matrix.  Errors: EINVAL (no such level, the coarsest, which not 0 or 1,
+ * alpha or beta not finite), ENOMEM. */
+expmv_status expmv_host_amg_fused(expmv_amg h, int level, int which, double alpha, double beta,
+                                  int64_t* dims, int32_t* rowptr, int32_t* colind, double* val);
 void expmv_host_amg_destroy(expmv_amg h);
 
 void expmv_plan_destroy(expmv_plan plan);

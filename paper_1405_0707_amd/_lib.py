@@ -50,6 +50,7 @@ EXPORTS = [
     "expmv_status_string", "expmv_block_csr", "expmv_block_toeplitz",
     "expmv_apply_preconditioner", "expmv_host_amg_build", "expmv_host_amg_levels",
     "expmv_host_amg_level", "expmv_host_amg_coarse_inverse", "expmv_host_amg_destroy",
+    "expmv_host_amg_fused",
     "expmv_execute_times", "expmv_last_error_detail", "expmv_plan_toeplitz_general",
     "expmv_execute_source",
 ]
@@ -94,6 +95,7 @@ def lib():
     L.expmv_host_amg_build.argtypes = [i64, vp, vp, vp, i32, dbl, i32, C.POINTER(vp)]
     L.expmv_host_amg_levels.argtypes = [vp]
     L.expmv_host_amg_level.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.expmv_host_amg_fused.argtypes = [vp, i32, i32, dbl, dbl, vp, vp, vp, vp]
     L.expmv_host_amg_coarse_inverse.argtypes = [vp, vp]
     L.expmv_host_amg_destroy.argtypes = [vp]
     L.expmv_host_amg_destroy.restype = None

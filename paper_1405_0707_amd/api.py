@@ -272,6 +272,25 @@ class HostAmg:
                 pass
             self._h = None
 
+    def fused(self, level: int, which: str, alpha: float, beta: float = 0.0):
+        """The device V-cycle's fused transfer operator of `level` as
+        (rowptr, colind, val, shape): which = "restriction" gives
+        R (I - A D^{-1}(alpha I - beta A D^{-1})), "prolongation" gives
+        (I - alpha D^{-1} A) P."""
+        np = self._np
+        w = {"restriction": 0, "prolongation": 1}[which]
+        dims = np.zeros(3, dtype=np.int64)
+        check(lib().expmv_host_amg_fused(self._h, level, w, float(alpha), float(beta),
+                                         dims.ctypes.data, None, None, None), "expmv_host_amg_fused")
+        rows, cols, nnz = (int(x) for x in dims)
+        rp = np.zeros(rows + 1, np.int32)
+        ci = np.zeros(nnz, np.int32)
+        v = np.zeros(nnz, np.float64)
+        check(lib().expmv_host_amg_fused(self._h, level, w, float(alpha), float(beta),
+                                         dims.ctypes.data, rp.ctypes.data, ci.ctypes.data,
+                                         v.ctypes.data), "expmv_host_amg_fused")
+        return rp, ci, v, (rows, cols)
+
     def levels(self):
         np = self._np
         out = []

@@ -90,6 +90,74 @@ HostCsr jacobi_step_operator(const HostCsr& A, const std::vector<double>& dinv, 
   return M;
 }
 
+namespace {
+HostCsr identity_csr(int64_t n) {
+  HostCsr I;
+  I.nrows = I.ncols = n;
+  I.rp.resize(n + 1);
+  I.ci.resize(n);
+  I.v.assign(n, 1.0);
+  for (int64_t i = 0; i <= n; ++i) I.rp[i] = i;
+  for (int64_t i = 0; i < n; ++i) I.ci[i] = int32_t(i);
+  return I;
+}
+
+HostCsr scaled_by_dinv_right(const AmgLevelHost& L) {   // A D^{-1}
+  HostCsr M = L.A;
+  for (int64_t e = 0; e < M.nnz(); ++e) M.v[e] *= L.dinv[M.ci[e]];
+  return M;
+}
+}  // namespace
+
+HostCsr fused_restriction(const AmgLevelHost& L, double alpha, double beta) {
+  if (beta == 0.0) return csr_matmul(L.R, jacobi_step_operator(L.A, L.dinv, alpha, false));
+  const HostCsr M = scaled_by_dinv_right(L);
+  const HostCsr I = identity_csr(M.nrows);
+  const HostCsr S = csr_add(I, M, alpha, -beta);
+  return csr_matmul(L.R, csr_add(I, csr_matmul(M, S), 1.0, -1.0));
+}
+
+HostCsr fused_prolongation(const AmgLevelHost& L, double s0) {
+  return csr_matmul(jacobi_step_operator(L.A, L.dinv, s0, true), L.P);
+}
+
+int64_t fused_restriction_nnz_bound(const AmgLevelHost& L, double beta) {
+  // exact row lengths of the pattern of E = I - A D^{-1} S (the pattern of
+  // I + A, or of I + A + A^2 for two steps), then R E bounded row by row
+  const HostCsr& A = L.A;
+  std::vector<int64_t> elen(A.nrows, 0);
+  std::vector<int64_t> mark(A.ncols, -1);
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    int64_t len = 0;
+    auto touch = [&](int32_t j) {
+      if (mark[j] != i) {
+        mark[j] = i;
+        ++len;
+      }
+    };
+    touch(int32_t(i));
+    for (int64_t e = A.rp[i]; e < A.rp[i + 1]; ++e) {
+      touch(A.ci[e]);
+      if (beta != 0.0)
+        for (int64_t f = A.rp[A.ci[e]]; f < A.rp[A.ci[e] + 1]; ++f) touch(A.ci[f]);
+    }
+    elen[i] = len;
+  }
+  int64_t s = 0;
+  for (int64_t e = 0; e < L.R.nnz(); ++e) s += elen[L.R.ci[e]];
+  return s;
+}
+
+int64_t fused_prolongation_nnz_bound(const AmgLevelHost& L) {
+  int64_t s = 0;
+  for (int64_t i = 0; i < L.A.nrows; ++i) {
+    s += L.P.rp[i + 1] - L.P.rp[i];   // the identity's term
+    for (int64_t e = L.A.rp[i]; e < L.A.rp[i + 1]; ++e)
+      s += L.P.rp[L.A.ci[e] + 1] - L.P.rp[L.A.ci[e]];
+  }
+  return s;
+}
+
 // C = A B (Gustavson, row by row; entries of a row in first-touch order, so
 // the result and its summation order are deterministic).
 HostCsr csr_matmul(const HostCsr& A, const HostCsr& B) {

@@ -68,4 +68,17 @@ HostCsr csr_add(const HostCsr& A, const HostCsr& B, double a, double b);
 HostCsr jacobi_step_operator(const HostCsr& A, const std::vector<double>& dinv, double s,
                              bool left);
 
+// Fused transfer operators of a V-cycle level whose pre-smoothed iterate is
+// x1 = D^{-1} (alpha b - beta A D^{-1} b) (one Jacobi/Chebyshev step from zero:
+// alpha = s0, beta = 0; two Chebyshev steps: see the device V-cycle):
+//   restriction of the residual b - A x1:  Rf = R (I - A D^{-1} S),
+//                                           S = alpha I - beta A D^{-1};
+//   prolongation followed by one step x += s0 D^{-1} (b - A x):
+//                                           Pf = (I - s0 D^{-1} A) P.
+HostCsr fused_restriction(const AmgLevelHost& L, double alpha, double beta);
+HostCsr fused_prolongation(const AmgLevelHost& L, double s0);
+// upper bounds of nnz(Rf) and nnz(Pf) from the product patterns (one pass)
+int64_t fused_restriction_nnz_bound(const AmgLevelHost& L, double beta);
+int64_t fused_prolongation_nnz_bound(const AmgLevelHost& L);
+
 }  // namespace expmv

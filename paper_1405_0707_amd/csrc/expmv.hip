@@ -2043,19 +2043,18 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
     if (L.degree != 1) continue;
     const AmgLevelHost& Lh = h.lv[l];
     const double s0 = L.ad[0];
-    const HostCsr N = jacobi_step_operator(Lh.A, Lh.dinv, s0, true);
-    const HostCsr Mr = jacobi_step_operator(Lh.A, Lh.dinv, s0, false);
     const int64_t cap = kAmgFuseGrowth * (Lh.A.nnz() + Lh.P.nnz());
-    if (csr_product_nnz_bound(N, Lh.P) > cap || csr_product_nnz_bound(Lh.R, Mr) > cap) continue;
+    if (fused_prolongation_nnz_bound(Lh) > cap || fused_restriction_nnz_bound(Lh, 0.0) > cap)
+      continue;
     L.fused = true;
-    L.alpha = 2.0 * s0;
+    L.alpha = 2.0 * s0;   // of the prolongation-plus-smoothing pass
     L.beta = s0 * s0;
-    const HostCsr Pf = csr_matmul(N, Lh.P);
+    const HostCsr Pf = fused_prolongation(Lh, s0);
     upload_csr(Pf, L.Pfrp, L.Pfci, L.Pfv);
     upload_vec(L.Pfv32, Pf.v);
     L.avg_pf = double(Pf.nnz()) / double(std::max<int64_t>(1, Pf.nrows));
     if (l + 2 == nlev && dense_last) continue;   // Inv Rf below
-    const HostCsr Rf = csr_matmul(Lh.R, Mr);
+    const HostCsr Rf = fused_restriction(Lh, s0, 0.0);
     upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
     upload_vec(L.Rfv32, Rf.v);
     L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
@@ -2072,27 +2071,14 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
       const double alpha = (1.0 + L.cd[1]) * L.ad[0] + L.ad[1];
       const double beta = L.ad[1] * L.ad[0];
       const int64_t cap = kAmgFuseGrowth * (Lh.A.nnz() + Lh.P.nnz());
-      HostCsr M = Lh.A;   // A D^{-1}
-      for (int64_t e = 0; e < M.nnz(); ++e) M.v[e] *= Lh.dinv[M.ci[e]];
-      if (csr_product_nnz_bound(M, M) + M.nrows <= cap) {
-        HostCsr I;
-        I.nrows = I.ncols = M.nrows;
-        I.rp.resize(I.nrows + 1);
-        I.ci.resize(I.nrows);
-        I.v.assign(I.nrows, 1.0);
-        for (int64_t i = 0; i <= I.nrows; ++i) I.rp[i] = i;
-        for (int64_t i = 0; i < I.nrows; ++i) I.ci[i] = int32_t(i);
-        const HostCsr S = csr_add(I, M, alpha, -beta);
-        const HostCsr E = csr_add(I, csr_matmul(M, S), 1.0, -1.0);
-        if (csr_product_nnz_bound(Lh.R, E) <= cap) {
-          const HostCsr Rf = csr_matmul(Lh.R, E);
-          upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
-          upload_vec(L.Rfv32, Rf.v);
-          L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
-          L.alpha = alpha;
-          L.beta = beta;
-          L.fused = true;
-        }
+      if (fused_restriction_nnz_bound(Lh, beta) <= cap) {
+        const HostCsr Rf = fused_restriction(Lh, alpha, beta);
+        upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
+        upload_vec(L.Rfv32, Rf.v);
+        L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
+        L.alpha = alpha;
+        L.beta = beta;
+        L.fused = true;
       }
     }
   }
@@ -2676,6 +2662,29 @@ expmv_status expmv_host_amg_build(int64_t n, const int32_t* rowptr, const int32_
 }
 
 int expmv_host_amg_levels(expmv_amg h) { return h ? int(h->h.lv.size()) : 0; }
+
+expmv_status expmv_host_amg_fused(expmv_amg h, int level, int which, double alpha, double beta,
+                                  int64_t* dims, int32_t* rowptr, int32_t* colind, double* val) {
+  if (!h || level < 0 || level + 1 >= int(h->h.lv.size()) || (which != 0 && which != 1) ||
+      !std::isfinite(alpha) || !std::isfinite(beta))
+    return EXPMV_EINVAL;
+  try {
+    const AmgLevelHost& L = h->h.lv[level];
+    const HostCsr F = which == 0 ? fused_restriction(L, alpha, beta) : fused_prolongation(L, alpha);
+    if (F.nnz() > INT32_MAX) return EXPMV_ENOMEM;
+    if (dims) {
+      dims[0] = F.nrows;
+      dims[1] = F.ncols;
+      dims[2] = F.nnz();
+    }
+    if (rowptr) std::copy(F.rp.begin(), F.rp.end(), rowptr);
+    if (colind) std::copy(F.ci.begin(), F.ci.end(), colind);
+    if (val) std::copy(F.v.begin(), F.v.end(), val);
+    return EXPMV_OK;
+  } catch (const std::bad_alloc&) {
+    return EXPMV_ENOMEM;
+  }
+}
 
 expmv_status expmv_host_amg_level(expmv_amg h, int level, int64_t* dims, double* lmax,
                                   int32_t* a_rowptr, int32_t* a_colind, double* a_val,

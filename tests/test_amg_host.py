@@ -130,3 +130,46 @@ def test_nonpositive_diagonal_is_rejected():
     K = K.tocsr()
     with pytest.raises(ExpmvError):
         HostAmg(K.indptr, K.indices, K.data)
+
+
+@pytest.mark.parametrize("name,symmetric", [("vardiff", True), ("convdiff", False)])
+def test_fused_transfer_operators(name, symmetric):
+    """The fused operators of the device V-cycle against their definition
+    with scipy products: the restriction of the pre-smoothed residual
+    R (I - A D^{-1}(alpha I - beta A D^{-1})) for one step (beta = 0) and for
+    two Chebyshev steps (beta != 0), and the prolongation followed by one
+    smoothing step (I - s D^{-1} A) P, on every level above the coarsest.
+    A planted mistake (the wrong side of D^{-1}) fails the comparison."""
+    # variable diagonals, so that D^{-1} A and A D^{-1} differ
+    A = wl.vardiff_2d(48, 205) if name == "vardiff" else wl.convdiff_3d(12, 50.0)
+    K = _pos(A)
+    h, lvs = _levels(K, symmetric=symmetric, max_coarse=60)
+    assert len(lvs) >= 3
+    planted = 0
+    for level, lv in enumerate(lvs[:-1]):
+        Al = _csr(lv)
+        # the planted mistake shows where the diagonal is not constant
+        varies = np.ptp(Al.diagonal()) > 1e-9 * abs(Al.diagonal()).max()
+        planted += int(varies)
+        P = _prolong(lv)
+        R = P.T.tocsr()
+        Dinv = sp.diags(1.0 / Al.diagonal())
+        I = sp.identity(Al.shape[0], format="csr")
+        s0 = 0.7 / lv["lmax"]
+        for alpha, beta in ((s0, 0.0), (1.9 * s0, 0.4 * s0 * s0)):
+            rp, ci, v, shape = h.fused(level, "restriction", alpha, beta)
+            F = sp.csr_matrix((v, ci, rp), shape=shape)
+            ref = R @ (I - Al @ Dinv @ (alpha * I - beta * Al @ Dinv))
+            assert shape == ref.shape
+            assert abs(F - ref).max() <= 1e-14 * abs(ref).max()
+            wrong = R @ (I - Dinv @ Al @ (alpha * I - beta * Dinv @ Al))
+            assert not varies or abs(F - wrong).max() > 1e-6 * abs(ref).max()
+        rp, ci, v, shape = h.fused(level, "prolongation", s0)
+        F = sp.csr_matrix((v, ci, rp), shape=shape)
+        ref = (I - s0 * Dinv @ Al) @ P
+        assert abs(F - ref).max() <= 1e-14 * abs(ref).max()
+        wrong = (I - s0 * Al @ Dinv) @ P
+        assert not varies or abs(F - wrong).max() > 1e-6 * abs(ref).max()
+    assert planted >= 1
+    with pytest.raises(ExpmvError):
+        h.fused(len(lvs) - 1, "restriction", 1.0)
