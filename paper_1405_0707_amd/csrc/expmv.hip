@@ -879,12 +879,12 @@ InnerResult apply_inverse(expmv_plan_s* pl, int transpose, const T* V, T* Wout, 
 // -------------------------------------------------------------------------
 // Toeplitz operator (FFT circulant embedding) and Gohberg-Semencul inverse
 
-// Radices of a length-L transform: 64s (one pass doing two radix-8 stages
-// in LDS), 8s, then 4 or 2 for the rest of the power of two, then 5s and
-// 3s; empty when L has another prime factor.
+// Radices of a length-L transform: 512s and 64s (one pass doing three or
+// two radix-8 stages in LDS), 8s, then 4 or 2 for the rest of the power of
+// two, then 5s and 3s; empty when L has another prime factor.
 std::vector<int> fft_radices(int64_t L) {
   std::vector<int> r;
-  for (int R : {64, 8, 4, 2, 5, 3})
+  for (int R : {512, 64, 8, 4, 2, 5, 3})
     while (L % R == 0) {
       r.push_back(R);
       L /= R;
@@ -908,7 +908,10 @@ void fft_len(expmv_plan_s* pl, int64_t L, const std::vector<int>& radices, const
     cplx* dst = ((np - 1 - i) % 2 == 0) ? out : tmp;
     const int R = radices[i];
     const int grid = stream_grid((L / R) * q);
-    if (R == 64)
+    if (R == 512)
+      hipLaunchKernelGGL(k_fft_pass512, dim3(int(std::min<int64_t>(16384, ((L / 512) * q + 7) / 8))),
+                         dim3(kFft512Threads), 0, pl->stream, L, q, Ns, src, dst, sign);
+    else if (R == 64)
       hipLaunchKernelGGL(k_fft_pass64, dim3(int(std::min<int64_t>(8192, ((L / 64) * q + 63) / 64))),
                          dim3(kFft64Threads), 0, pl->stream, L, q, Ns, src, dst, sign);
     else if (R == 8)

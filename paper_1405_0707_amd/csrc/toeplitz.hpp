@@ -165,6 +165,91 @@ k_fft_pass64(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __
   }
 }
 
+// One Stockham pass of radix 512 (same index map), the 512-point DFT as
+// 8 x 64 with the 64-point DFTs as 8 x 8, all in LDS: with r = a + 8 b,
+// b = b0 + 8 b1, m = c + 64 d, c = c2 + 8 c1 (w_N = exp(sign 2 pi i / N)),
+//   Y_a(c)  = sum_b0 w8^(b0 c1) w64^(b0 c2) sum_b1 v_(a + 8 b0 + 64 b1) w8^(b1 c2)
+//   X_m     = sum_a w8^(a d) w512^(a c) Y_a(c).
+// A workgroup of 512 threads takes 8 (j, c) pairs, 64 threads t per pair:
+// stage 1, t = a + 8 b0: loads v_(t + 64 s), s < 8, the inner 8-point DFT
+// over b1; stage 2, t = a + 8 c2: the 8-point DFT over b0; stage 3, t = c:
+// the 8-point DFT over a, writing X_(c + 64 d).  One pass over the data
+// instead of three radix-8 passes.
+constexpr int kFft512Threads = 512;
+__global__ void __launch_bounds__(kFft512Threads)
+k_fft_pass512(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __restrict__ out,
+              double sign) {
+  __shared__ cplx sb[8][64][8];   // stage 1: [a][b0 + 8 c2][pair]; stage 2: [a][c][pair]
+  const int pc = threadIdx.x % 8, t = threadIdx.x / 8;
+  const int64_t pairs = (L / 512) * q;
+  const int64_t stride = L / 512;
+  for (int64_t base = int64_t(blockIdx.x) * 8; base < pairs; base += int64_t(gridDim.x) * 8) {
+    const int64_t gp = base + pc;
+    const bool ok = gp < pairs;
+    const int64_t j = ok ? gp / q : 0;
+    const int c = ok ? int(gp % q) : 0;
+    const int64_t k = j % Ns;
+    // stage 1: thread t = a + 8 b0
+    cplx v[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2)
+      v[s2] = ok ? in[(j + (t + 64 * s2) * stride) * q + c] : cplx{0.0, 0.0};
+    if (Ns > 1) {
+      // v_r *= w^(r k), w = exp(sign 2 pi i / (Ns 512)), r = t + 64 s2
+      double sbv, cbv, ss, cs;
+      sincospi(sign * 2.0 * double(t * k) / double(Ns * 512), &sbv, &cbv);
+      sincospi(sign * 2.0 * double(64 * k) / double(Ns * 512), &ss, &cs);
+      cplx wr{cbv, sbv};
+      const cplx w64{cs, ss};
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) {
+        v[s2] = cmul(v[s2], wr);
+        wr = cmul(wr, w64);
+      }
+    }
+    {
+      const int a = t % 8, b0 = t / 8;
+      cplx Z[8];
+      dft_small<8>(v, Z, sign);
+#pragma unroll
+      for (int c2 = 0; c2 < 8; ++c2) {
+        double si, co;
+        sincospi(sign * 2.0 * double(b0 * c2) / 64.0, &si, &co);
+        sb[a][b0 + 8 * c2][pc] = cmul(Z[c2], cplx{co, si});
+      }
+    }
+    __syncthreads();
+    // stage 2: thread t = a + 8 c2
+    {
+      const int a = t % 8, c2 = t / 8;
+      cplx u[8], W[8];
+#pragma unroll
+      for (int b0 = 0; b0 < 8; ++b0) u[b0] = sb[a][b0 + 8 * c2][pc];
+      __syncthreads();   // every stage-1 value is read before stage 2 overwrites
+      dft_small<8>(u, W, sign);
+#pragma unroll
+      for (int c1 = 0; c1 < 8; ++c1) {
+        const int cc = c2 + 8 * c1;
+        double si, co;
+        sincospi(sign * 2.0 * double(a * cc) / 512.0, &si, &co);
+        sb[a][cc][pc] = cmul(W[c1], cplx{co, si});
+      }
+    }
+    __syncthreads();
+    // stage 3: thread t = c
+    cplx y[8], X[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) y[a] = sb[a][t][pc];
+    __syncthreads();   // sb is rewritten by the next group of pairs
+    dft_small<8>(y, X, sign);
+    if (ok) {
+      const int64_t idxD = (j / Ns) * Ns * 512 + k;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) out[(idxD + (t + 64 * d) * Ns) * q + c] = X[d];
+    }
+  }
+}
+
 // out (L x q complex) = rows of src (n x p real, row-major), two real
 // columns per complex column (2c -> real part, 2c+1 -> imaginary part),
 // rows reversed if `reverse`, zero for rows >= n, times scale and, when rs
