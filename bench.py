@@ -327,8 +327,8 @@ def _suite_vardiff(dev, timed, res, vardiff_n):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
+                          "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
