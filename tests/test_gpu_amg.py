@@ -49,7 +49,8 @@ def _host_vcycle(A, t, degree):
 @pytest.mark.parametrize("name,p,degree", [("lap3d20", 8, 2), ("lap3d20", 3, 1),
                                            ("vardiff96", 32, 2), ("lap2d70", 1, 3),
                                            ("vardiff96", 16, 4), ("lap3d40", 8, 2),
-                                           ("lap3d40", 5, 1), ("lap2d40", 4, 2)])
+                                           ("lap3d40", 5, 1), ("lap2d40", 4, 2),
+                                           ("vardiff96", 12, 2), ("lap3d20", 20, 2)])
 def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
     announce(f"V-cycle {name} p={p} degree={degree}")
     A, t = _workload(name)
@@ -68,16 +69,17 @@ def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
     assert abs(a - b) <= 1e-12 * abs(a)
 
 
-@pytest.mark.parametrize("form", ["mixed", "fp64_fp32_vcycle"])
-def test_device_fp32_vcycle(form):
+@pytest.mark.parametrize("form,p", [("mixed", 8), ("fp64_fp32_vcycle", 8), ("mixed", 12),
+                                    ("fp64_fp32_vcycle", 20)])
+def test_device_fp32_vcycle(form, p):
     """The FP32 V-cycle (FP32 values and vectors, FP64 sums) of the mixed
     form and, by default, of the FP64 form's CG, against the numpy V-cycle
     in FP64; symmetric to FP32 rounding."""
-    announce(f"V-cycle FP32 ({form})")
+    announce(f"V-cycle FP32 ({form}) p={p}")
     A, t = _workload("vardiff96")
     kw = {"precision": "mixed"} if form == "mixed" else {"amg_fp32": 1}
     pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg", **kw)
-    X = np.random.default_rng(4).standard_normal((A.n, 8))
+    X = np.random.default_rng(4).standard_normal((A.n, p))
     Y = pl.apply_preconditioner(torch.from_numpy(X)).cpu().numpy()
     assert rel(Y, _host_vcycle(A, t, 2).apply(X)) < 1e-5
     Px = pl.apply_preconditioner(torch.from_numpy(X[:, :1])).cpu().numpy()[:, 0]
@@ -86,7 +88,24 @@ def test_device_fp32_vcycle(form):
     assert abs(a - b) <= 1e-5 * np.linalg.norm(Px) * np.linalg.norm(X[:, 1])
 
 
-@pytest.mark.parametrize("name,p", [("lap3d20", 8), ("vardiff96", 5)])
+@pytest.mark.parametrize("p", [12, 20])
+def test_mixed_amg_inverse_wide_blocks(p):
+    """The FP32 inner CG and V-cycle of the mixed form with four columns per
+    lane and masked lanes (p = 12, 20) against a sparse LU solve."""
+    announce(f"mixed AMG inverse vardiff96 p={p}")
+    A, t = _workload("vardiff96")
+    X = np.random.default_rng(7).standard_normal((A.n, p))
+    M = (t * A.to_scipy()).tocsr()
+    ref = inverses.splu_inverse(M)(X)
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
+                  precision="mixed", inner_tol=1e-6)
+    Y, it = pl.apply_inverse(torch.from_numpy(X))
+    assert rel(Y.cpu().numpy(), ref) < 1e-5
+    assert 0 < it <= 40
+
+
+@pytest.mark.parametrize("name,p", [("lap3d20", 8), ("vardiff96", 5), ("lap3d20", 12),
+                                    ("vardiff96", 20)])
 def test_amg_inverse_matches_splu_in_few_iterations(name, p):
     announce(f"AMG inverse {name} p={p}")
     A, t = _workload(name)
