@@ -69,11 +69,11 @@ template <int VW, typename T>
 __device__ inline void load_vw(const T* __restrict__ src, double (&o)[VW]) {
   if constexpr (VW == 1) {
     o[0] = double(src[0]);
-  } else if constexpr (VW == 4) {
-    T v[4];
-    ld_vw<4>(src, v);
+  } else if constexpr (VW >= 4) {
+    T v[VW];
+    ld_vw<VW>(src, v);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = double(v[q]);
+    for (int q = 0; q < VW; ++q) o[q] = double(v[q]);
   } else if constexpr (std::is_same<T, double>::value) {
     const double2 v = *reinterpret_cast<const double2*>(src);
     o[0] = v.x;
@@ -88,11 +88,11 @@ template <int VW, typename T>
 __device__ inline void store_vw(T* __restrict__ dst, const double (&o)[VW]) {
   if constexpr (VW == 1) {
     dst[0] = T(o[0]);
-  } else if constexpr (VW == 4) {
-    T v[4];
+  } else if constexpr (VW >= 4) {
+    T v[VW];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = T(o[q]);
-    st_vw<4>(dst, v);
+    for (int q = 0; q < VW; ++q) v[q] = T(o[q]);
+    st_vw<VW>(dst, v);
   } else if constexpr (std::is_same<T, double>::value) {
     *reinterpret_cast<double2*>(dst) = double2{o[0], o[1]};
   } else {
@@ -110,7 +110,7 @@ __device__ inline void row_dot_split(const int32_t* __restrict__ colind,
                                      const T* __restrict__ val, const T* __restrict__ x,
                                      const T* __restrict__ dinv, int e0, int e1, int ld, int c0,
                                      bool active, int g, int G, double (&acc)[VW]) {
-  constexpr int U = VW == 4 ? 4 : 8;   // nonzeros per sub-lane step, all loads issued first
+  constexpr int U = 16 / (VW > 2 ? VW : 2);   // nonzeros per sub-lane step, all loads issued first
 #pragma unroll
   for (int k = 0; k < VW; ++k) acc[k] = 0.0;
   if (active) {
@@ -160,7 +160,7 @@ __device__ inline void row_dot_pair(const int32_t* __restrict__ aci, const T* __
                                     const T* __restrict__ pv, const T* __restrict__ xc, int ep0,
                                     int ep1, int ld, int c0, bool active, int g, int G,
                                     double (&accA)[VW], double (&accP)[VW]) {
-  constexpr int U = VW == 4 ? 4 : 8;
+  constexpr int U = 16 / (VW > 2 ? VW : 2);
 #pragma unroll
   for (int k = 0; k < VW; ++k) accA[k] = accP[k] = 0.0;
   if (active) {

@@ -262,12 +262,22 @@ int grid_for(int64_t rows, int PP, int cap = 1024) {
 // 64^3 benchmark; 0.61 against 0.67 s at p = 32).
 template <typename T, int PP>
 constexpr bool kWide4 = PP >= 4 && (sizeof(T) == 4 || PP >= 16);
+// eight FP32 columns per lane (two 16-byte accesses) from 32 columns
+template <typename T, int PP>
+constexpr bool kWide8 = sizeof(T) == 4 && PP >= 32;
 
 // CG kernels (working type T): PPL_ lanes per row with VW_ adjacent columns
 // each, PPL_ VW_ = PP: VW_ = 4 when p is a multiple of 4 and the block is FP32
 // or at least 16 wide (kWide4), else 2 for even p
 #define CG_CASE(PPV, p, ...)                                                \
   case PPV:                                                                 \
+    if constexpr (kWide8<T, PPV>) {                                         \
+      if ((p) % 8 == 0) {                                                   \
+        constexpr int PPL_ = PPV / 8, VW_ = 8;                              \
+        __VA_ARGS__;                                                        \
+        break;                                                              \
+      }                                                                     \
+    }                                                                       \
     if constexpr (kWide4<T, PPV>) {                                         \
       if ((p) % 4 == 0) {                                                   \
         constexpr int PPL_ = PPV / 4, VW_ = 4;                              \
@@ -677,6 +687,12 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
 template <typename T, int PP>
 void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
                const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
+  if constexpr (kWide8<T, PP>) {
+    if (p % 8 == 0) {
+      amg_level_vw<T, PP / 8, 8>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
+      return;
+    }
+  }
   if constexpr (PP >= 4) {
     if (p % 4 == 0 && (kWide4<T, PP> || l > 0)) {
       amg_level_vw<T, PP / 4, 4>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
@@ -796,6 +812,13 @@ template <typename T, int PP, int NV>
 void bcg_spmm(hipStream_t s, int grid, int i, int n, int p, const int32_t* rowptr,
               const int32_t* colind, const double* val, const T* dinv, const T* in, const T* a,
               T* out, const KrylovCtl* ctl, double* part) {
+  if constexpr (kWide8<T, PP>) {
+    if (p % 8 == 0) {
+      hipLaunchKernelGGL((k_bcg_s<T, PP / 8, 8, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,
+                         rowptr, colind, val, dinv, in, a, out, ctl, part);
+      return;
+    }
+  }
   if constexpr (kWide4<T, PP>) {
     if (p % 4 == 0) {
       hipLaunchKernelGGL((k_bcg_s<T, PP / 4, 4, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,

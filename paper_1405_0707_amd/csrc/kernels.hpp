@@ -251,9 +251,20 @@ __device__ inline void write_col_partial_vw(const double (&v)[VW], double* red, 
 // 16-byte FP64 ones)
 template <int VW, typename T>
 __device__ inline void ld_vw(const T* __restrict__ src, T (&o)[VW]) {
-  static_assert(VW == 1 || VW == 2 || VW == 4, "lane width");
+  static_assert(VW == 1 || VW == 2 || VW == 4 || (VW == 8 && sizeof(T) == 4), "lane width");
   if constexpr (VW == 1) {
     o[0] = src[0];
+  } else if constexpr (VW == 8) {
+    const float4 v0 = *reinterpret_cast<const float4*>(src);
+    const float4 v1 = *reinterpret_cast<const float4*>(src + 4);
+    o[0] = v0.x;
+    o[1] = v0.y;
+    o[2] = v0.z;
+    o[3] = v0.w;
+    o[4] = v1.x;
+    o[5] = v1.y;
+    o[6] = v1.z;
+    o[7] = v1.w;
   } else if constexpr (VW == 4 && sizeof(T) == 8) {
     const double2 v0 = *reinterpret_cast<const double2*>(src);
     const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
@@ -279,9 +290,12 @@ __device__ inline void ld_vw(const T* __restrict__ src, T (&o)[VW]) {
 }
 template <int VW, typename T>
 __device__ inline void st_vw(T* __restrict__ dst, const T (&o)[VW]) {
-  static_assert(VW == 1 || VW == 2 || VW == 4, "lane width");
+  static_assert(VW == 1 || VW == 2 || VW == 4 || (VW == 8 && sizeof(T) == 4), "lane width");
   if constexpr (VW == 1) {
     dst[0] = o[0];
+  } else if constexpr (VW == 8) {
+    *reinterpret_cast<float4*>(dst) = float4{o[0], o[1], o[2], o[3]};
+    *reinterpret_cast<float4*>(dst + 4) = float4{o[4], o[5], o[6], o[7]};
   } else if constexpr (VW == 4 && sizeof(T) == 8) {
     *reinterpret_cast<double2*>(dst) = double2{o[0], o[1]};
     *reinterpret_cast<double2*>(dst + 2) = double2{o[2], o[3]};
@@ -299,7 +313,7 @@ template <int VW, typename T>
 __device__ inline void csr_row_dot_vw(const int32_t* __restrict__ colind,
                                       const double* __restrict__ val, const T* __restrict__ x,
                                       int e0, int e1, int ld, int c0, double (&acc)[VW]) {
-  constexpr int U = VW == 4 ? 4 : 8;   // VW = 4: same registers as VW = 2
+  constexpr int U = 16 / (VW > 2 ? VW : 2);   // VW = 4, 8: same registers as VW = 2
 #pragma unroll
   for (int q = 0; q < VW; ++q) acc[q] = 0.0;
   for (int e = e0; e < e1; e += U) {
