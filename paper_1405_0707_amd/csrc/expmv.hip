@@ -264,7 +264,7 @@ template <typename T, int PP>
 constexpr bool kWide4 = PP >= 4 && (sizeof(T) == 4 || PP >= 16);
 // eight FP32 columns per lane (two 16-byte accesses) from 32 columns
 template <typename T, int PP>
-constexpr bool kWide8 = sizeof(T) == 4 && PP >= 32;
+constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
 
 // CG kernels (working type T): PPL_ lanes per row with VW_ adjacent columns
 // each, PPL_ VW_ = PP: VW_ = 4 when p is a multiple of 4 and the block is FP32
