@@ -262,7 +262,9 @@ int grid_for(int64_t rows, int PP, int cap = 1024) {
 // 64^3 benchmark; 0.61 against 0.67 s at p = 32).
 template <typename T, int PP>
 constexpr bool kWide4 = PP >= 4 && (sizeof(T) == 4 || PP >= 16);
-// eight FP32 columns per lane (two 16-byte accesses) from 32 columns
+// eight FP32 columns per lane (two 16-byte accesses) from 16 columns
+// (measured: 32 bytes per lane pays for FP32 at p = 16 and 32; at p = 8, one
+// lane per row, it changes nothing)
 template <typename T, int PP>
 constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
 
