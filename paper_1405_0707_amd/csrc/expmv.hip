@@ -269,8 +269,9 @@ template <typename T, int PP>
 constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
 
 // CG kernels (working type T): PPL_ lanes per row with VW_ adjacent columns
-// each, PPL_ VW_ = PP: VW_ = 4 when p is a multiple of 4 and the block is FP32
-// or at least 16 wide (kWide4), else 2 for even p
+// each, PPL_ VW_ = PP: VW_ = 8 for FP32 blocks of 16 or more columns with p a
+// multiple of 8 (kWide8), else 4 when p is a multiple of 4 and the block is
+// FP32 or at least 16 wide (kWide4), else 2 for even p
 #define CG_CASE(PPV, p, ...)                                                \
   case PPV:                                                                 \
     if constexpr (kWide8<T, PPV>) {                                         \
