@@ -34,8 +34,9 @@ enum : int {
 // the VW columns c = VW l .. VW l + VW - 1 (VW = 2 for even p: two adjacent
 // columns in one 8- or 16-byte access, half the lanes and index loads of one
 // column per lane; VW = 4 for p a multiple of 4 in FP32, or in FP64 from 16
-// columns: 16 or 32 bytes per lane, with half the nonzeros per sub-lane step
-// so that the registers stay those of VW = 2) and the nonzeros e0 + g, e0 + g + G, ... of the row, and
+// columns, and VW = 8 for FP32 from 16 columns: 16 or 32 bytes per lane, with
+// 16 / VW nonzeros per sub-lane step so that the registers stay those of
+// VW = 2) and the nonzeros e0 + g, e0 + g + G, ... of the row, and
 // the G partial sums of a column are added with shuffles inside the group
 // (G > 1 for the long rows of Galerkin operators and restrictions, whose
 // serial sums would otherwise set the kernel's latency).  PPL * G <= 64, so a
