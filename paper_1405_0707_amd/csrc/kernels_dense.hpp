@@ -282,6 +282,9 @@ __device__ inline cplx cdiv(cplx a, cplx b) {
 }
 
 constexpr int kProjMaxD = 64 * kMaxP;   // m <= 64 block steps of p <= kMaxP columns
+constexpr int kProjLdsZ = 4096;   // d * p of the back substitution through LDS
+constexpr int kProjLdsRows = 256; // and its largest d
+constexpr int kProjUCols = 8;     // columns of U per LDS chunk
 
 // Projected shifted systems, one workgroup per pole j (Section 4.1, eq. 4.7):
 //   precond: (I - tau_j H_d) Z_j = G_j,  S_j = tau_j H(d:d+p, 0:d) Z_j,
@@ -313,6 +316,7 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
   cplx* Z = Zs + size_t(j) * d * p;
   const cplx* Gj = G + size_t(j) * d * p;
   __shared__ int s_piv, s_zero;
+  __shared__ cplx s_inv;   // 1 / pivot
   __shared__ int s_lim[kProjMaxD];   // L(c)
   for (int c = tid; c < d; c += nt) s_lim[c] = c;
   __syncthreads();
@@ -352,29 +356,35 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
   int sing = 0;
   for (int c = 0; c < d; ++c) {
     const int last = s_lim[c];
-    // pivot: the first row of largest |a|^2 in column c, by one wavefront
+    // pivot: the first row of largest |a|^2 in column c, by one wavefront,
+    // and its reciprocal (one division per column instead of one per entry)
     if (tid < 64) {
       double best = -1.0;
       int bi = c;
+      cplx bv{0.0, 0.0};
       for (int r = c + tid; r <= last; r += 64) {
         const cplx a = A[r * d + c];
         const double v = a.x * a.x + a.y * a.y;
         if (v > best) {
           best = v;
           bi = r;
+          bv = a;
         }
       }
       for (int off = 32; off >= 1; off >>= 1) {
         const double ob = __shfl_xor(best, off, 64);
         const int oi = __shfl_xor(bi, off, 64);
+        const cplx ov{__shfl_xor(bv.x, off, 64), __shfl_xor(bv.y, off, 64)};
         if (ob > best || (ob == best && oi < bi)) {
           best = ob;
           bi = oi;
+          bv = ov;
         }
       }
       if (tid == 0) {
         s_piv = bi;
         s_zero = !(best > 0.0);
+        s_inv = best > 0.0 ? cdiv(cplx{1.0, 0.0}, bv) : cplx{0.0, 0.0};
       }
     }
     __syncthreads();
@@ -397,15 +407,15 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
       }
     }
     __syncthreads();
-    // rows c+1..L(c): multiplier l_r = a_rc / a_cc formed where it is used
-    const cplx diag = A[c * d + c];
+    // rows c+1..L(c): multiplier l_r = a_rc * (1 / a_cc) formed where it is used
+    const cplx inv = s_inv;
     const int m1 = d - c - 1;
     const int wide = m1 + p;
     const int rows = last - c;
     for (int idx = tid; idx < rows * wide; idx += nt) {
       const int r = c + 1 + idx / wide;
       const int cc = idx % wide;
-      const cplx l = cdiv(A[r * d + c], diag);
+      const cplx l = cmul(A[r * d + c], inv);
       if (cc < m1) {
         const int col = c + 1 + cc;
         A[r * d + col] = csub(A[r * d + col], cmul(l, A[c * d + col]));
@@ -416,26 +426,69 @@ k_proj_solve(int d, int p, int precond, const double* __restrict__ H, int ldh,
     }
     __syncthreads();
   }
-  // back substitution, one barrier per column: every thread forms
-  // x_c = z_c / u_cc itself; row c of Z is overwritten by x_c one step
-  // later, when no thread reads it any more
-  auto xval = [&](int c, int b) -> cplx {
-    const cplx dg = A[c * d + c];
-    return (dg.x == 0.0 && dg.y == 0.0) ? cplx{0.0, 0.0} : cdiv(Z[c * p + b], dg);
-  };
-  for (int c = d - 1; c >= 0; --c) {
-    cplx xn{0.0, 0.0};
-    const bool wr = c + 1 < d && tid < p;
-    if (wr) xn = xval(c + 1, tid);
-    for (int idx = tid; idx < c * p; idx += nt) {
-      const int r = idx / p, b = idx % p;
-      Z[r * p + b] = csub(Z[r * p + b], cmul(A[r * d + c], xval(c, b)));
+  if (d * p <= kProjLdsZ && d <= kProjLdsRows) {
+    // back substitution through LDS: Z, the reciprocals of the diagonal of
+    // U (formed once, in parallel) and U in chunks of kProjUCols columns
+    // (one global load pass and one extra barrier per chunk), so that a
+    // step costs two complex products and one barrier; x_c = z_c * (1/u_cc)
+    // rounds differently from z_c / u_cc by an ulp
+    __shared__ cplx sZ[kProjLdsZ];
+    __shared__ cplx sU[kProjUCols][kProjLdsRows];   // column c in slot c % kProjUCols
+    __shared__ cplx sInv[kProjLdsRows];
+    for (int idx = tid; idx < d * p; idx += nt) sZ[idx] = Z[idx];
+    for (int c = tid; c < d; c += nt) {
+      const cplx dg = A[c * d + c];
+      sInv[c] = (dg.x == 0.0 && dg.y == 0.0) ? cplx{0.0, 0.0} : cdiv(cplx{1.0, 0.0}, dg);
     }
-    if (wr) Z[(c + 1) * p + tid] = xn;
+    auto xval = [&](int c, int b) -> cplx { return cmul(sZ[c * p + b], sInv[c]); };
+    for (int c = d - 1; c >= 0; --c) {
+      if (c == d - 1 || c % kProjUCols == kProjUCols - 1) {
+        // columns lo..c, rows above the diagonal; readers of the previous
+        // chunk finished before the last barrier
+        const int lo = c - c % kProjUCols, nc = c - lo + 1;
+        for (int idx = tid; idx < c * nc; idx += nt) {
+          const int r = idx / nc, col = lo + idx % nc;
+          if (r < col) sU[col % kProjUCols][r] = A[r * d + col];
+        }
+        __syncthreads();
+      }
+      cplx xn{0.0, 0.0};
+      const bool wr = c + 1 < d && tid < p;
+      if (wr) xn = xval(c + 1, tid);
+      const cplx* u = sU[c % kProjUCols];
+      for (int idx = tid; idx < c * p; idx += nt) {
+        const int r = idx / p, b = idx % p;
+        sZ[r * p + b] = csub(sZ[r * p + b], cmul(u[r], xval(c, b)));
+      }
+      if (wr) sZ[(c + 1) * p + tid] = xn;
+      __syncthreads();
+    }
+    if (tid < p) sZ[tid] = xval(0, tid);
+    __syncthreads();
+    for (int idx = tid; idx < d * p; idx += nt) Z[idx] = sZ[idx];
+    __syncthreads();
+  } else {
+    // back substitution, one barrier per column: every thread forms
+    // x_c = z_c / u_cc itself; row c of Z is overwritten by x_c one step
+    // later, when no thread reads it any more
+    auto xval = [&](int c, int b) -> cplx {
+      const cplx dg = A[c * d + c];
+      return (dg.x == 0.0 && dg.y == 0.0) ? cplx{0.0, 0.0} : cdiv(Z[c * p + b], dg);
+    };
+    for (int c = d - 1; c >= 0; --c) {
+      cplx xn{0.0, 0.0};
+      const bool wr = c + 1 < d && tid < p;
+      if (wr) xn = xval(c + 1, tid);
+      for (int idx = tid; idx < c * p; idx += nt) {
+        const int r = idx / p, b = idx % p;
+        Z[r * p + b] = csub(Z[r * p + b], cmul(A[r * d + c], xval(c, b)));
+      }
+      if (wr) Z[(c + 1) * p + tid] = xn;
+      __syncthreads();
+    }
+    if (tid < p) Z[tid] = xval(0, tid);   // row 0: each thread its own entry
     __syncthreads();
   }
-  if (tid < p) Z[tid] = xval(0, tid);   // row 0: each thread its own entry
-  __syncthreads();
   if (tid == 0 && sing) singular[j] = 1;
   // update coefficients Cr (rows d+p, ld ldc = 2 p x shifts): real part then
   // imaginary part (Cr = NULL: only the residual estimates are wanted)
