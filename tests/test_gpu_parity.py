@@ -75,6 +75,18 @@ def test_c1_full_matches_oracle_and_closed_form():
     assert rel(Z, Zo) < 1e-10
 
 
+def test_wide_block_projected_solves_both_back_substitutions():
+    """p = 32, m = 6: the projected systems reach d = 192 (d p = 6144), past
+    the LDS back substitution of the projected solves (d p <= 4096), which
+    the residual estimates at d = 64 and 128 still take."""
+    announce("execute C1 32^2 p=32 m=6")
+    W = wl.c1(N=32, p=32, m=6)
+    pl = plan_for(W, m=W.m, k=W.k)
+    Z, info = pl.execute(torch.from_numpy(W.B), tol=1e-10)
+    rB = inverses.dst_laplacian_function(32, 2, W.t, rfun, W.B)
+    assert rel(Z.cpu().numpy(), rB) < 1e-10
+
+
 def test_ragged_sizes_match_dense_rational():
     announce("execute ragged 2D N=27 p=3")
     W = wl.c1(N=27, p=3, m=8)
