@@ -187,16 +187,13 @@ def cf_table():
 
 
 def r_eval(x, tau=None, c=None, omega0=None):
-    """Evaluate r(x) = omega0 + Re sum_j c_j/(x - tau_j) (the partial-fraction
-    form of Section 2 with the conjugate pairs folded) for real or complex x (numpy, FP64)."""
+    """Evaluate r(x) = omega0 + Re sum_j c_j/(x - tau_j) at real points x (the
+    partial-fraction form of Section 2 with the conjugate pairs folded, which
+    holds for real x only), numpy FP64."""
     if tau is None:
         tau, c, omega0 = cf_table()
     x = np.asarray(x)
-    terms = c[None, :] / (x.reshape(-1, 1) - tau[None, :])
     if np.iscomplexobj(x):
-        # r(x) = omega0 + sum over all 14 poles; fold pairs explicitly
-        conj = np.conj(c)[None, :] / (x.reshape(-1, 1) - np.conj(tau)[None, :])
-        val = omega0 + 0.5 * (terms.sum(1) + conj.sum(1))
-    else:
-        val = omega0 + terms.sum(1).real
-    return val.reshape(x.shape)
+        raise TypeError("r_eval takes real points: the folded pair form is real-only")
+    terms = c[None, :] / (x.reshape(-1, 1) - tau[None, :])
+    return (omega0 + terms.sum(1).real).reshape(x.shape)

@@ -1,8 +1,11 @@
-"""Plain definitions used to pin the oracle (test infrastructure).
+"""Plain definitions used to pin the oracle and as GPU references (test
+infrastructure).
 
 r(M)B = omega_0 B + Re sum_j c_j (M - tau_j I)^{-1} B is the exact quantity
 the iteration converges to (Section 2, eq. 2.5 with the conjugate pairs
-folded); e^{M}B differs from it by the CF error.
+folded); e^{M}B differs from it by the CF error.  Every function here forms
+that sum from direct solves, one per pole; they differ only in how each
+shifted system is solved.
 """
 from __future__ import annotations
 
@@ -38,12 +41,101 @@ def rational_sparse(M: sp.spmatrix, B: np.ndarray, table=None) -> np.ndarray:
     return out
 
 
+def rational_sparse_adjoint(M: sp.spmatrix, B: np.ndarray, G: np.ndarray, t: float,
+                            table=None):
+    """The forward result, the adjoint result and the t-derivative pairing of
+    L = <G, r(tA)B> from one sparse complex LU of M - tau_j I per pole (M = tA):
+
+        Z     = r(M) B      = omega_0 B + Re sum_j c_j X_j,   X_j = (M - tau_j I)^{-1} B
+        gradB = r(M^T) G    = omega_0 G + Re sum_j c_j Y_j,   Y_j = (M - tau_j I)^{-T} G
+        gt    = <G, A r(M) B> = (1/t) <G, M r(M) B>
+
+    with M r(M) expanded by the partial fractions of x r(x) (x/(x - tau) =
+    1 + tau/(x - tau)):  <G, M r(M) B> = omega_0 <G, M B> + Re(sum_j c_j) <G, B>
+    + Re sum_j c_j tau_j <G, X_j>, so no operator is applied to a computed
+    solution.  Y_j uses the transposed solve of the same factors (SuperLU
+    trans='T', a plain transpose for complex data)."""
+    tau, c, w0 = cf_table() if table is None else table
+    n = M.shape[0]
+    Mc = sp.csc_matrix(M, dtype=complex)
+    I = sp.identity(n, dtype=complex, format="csc")
+    Z = w0 * B.astype(np.float64)
+    gB = w0 * G.astype(np.float64)
+    pair = w0 * float(np.sum(G * (sp.csr_matrix(M) @ B))) + float(np.real(np.sum(c))) * float(
+        np.sum(G * B))
+    for tj, cj in zip(tau, c):
+        lu = spla.splu(Mc - tj * I)
+        Xj = lu.solve(B.astype(complex))
+        Z = Z + np.real(cj * Xj)
+        pair += float(np.real(cj * tj * np.sum(G * Xj)))
+        del Xj
+        Yj = lu.solve(G.astype(complex), trans="T")
+        gB = gB + np.real(cj * Yj)
+        del Yj, lu
+    return Z, gB, pair / t
+
+
+def _tridiag_modes(a: float, b: float, c: float, N: int):
+    """Eigen-decomposition of the N x N tridiagonal Toeplitz matrix with
+    sub-diagonal a, diagonal b, super-diagonal c, a c > 0: with
+    r = sqrt(a/c) and s_k(i) = sin((i+1)(k+1) pi/(N+1)),
+    (T v)_i = a v_{i-1} + b v_i + c v_{i+1} for v_i = r^i s_k(i) gives
+    r^i (sqrt(ac) sgn(a) (s_{i-1} + s_{i+1}) + b s_i), and
+    s_{i-1} + s_{i+1} = 2 cos((k+1) pi/(N+1)) s_i, so
+    lam_k = b + 2 sgn(a) sqrt(ac) cos((k+1) pi/(N+1)), V = diag(r^i) S with S the
+    orthonormal (symmetric, involutory) DST-I matrix and V^{-1} = S diag(r^{-i})."""
+    if not a * c > 0:
+        raise ValueError("closed-form modes need a c > 0")
+    i = np.arange(N)
+    theta = (i + 1) * np.pi / (N + 1)
+    lam = b + 2.0 * np.sign(a) * np.sqrt(a * c) * np.cos(theta)
+    S = np.sqrt(2.0 / (N + 1)) * np.sin(np.outer(i + 1, i + 1) * np.pi / (N + 1))
+    r = np.sqrt(a / c)
+    V = (r ** i)[:, None] * S
+    Vinv = S * (r ** (-i.astype(np.float64)))[None, :]
+    return lam, V, Vinv
+
+
+def rational_kron3_tridiag(N: int, coef, t: float, B: np.ndarray, table=None) -> np.ndarray:
+    """r(M)B for M = -t K with K = T_x (+) T_y (+) T_z the Kronecker sum of three
+    N x N tridiagonal Toeplitz matrices (coef[d] = (sub, diagonal, super) of
+    T_d, axis d = 0, 1, 2 = x, y, z), unknowns ordered x fastest
+    (index x + N y + N^2 z), B of shape (N^3, p).
+
+    T_z is diagonalised in closed form (_tridiag_modes), so in the z-mode
+    basis K splits into N two-dimensional operators K_xy + lam_k I.  Since V
+    is real, Re commutes with it, and
+        r(M) B = V_z [omega_0 Bh + Re sum_j c_j (-t (K_xy + lam_k I) - tau_j I)^{-1} Bh_k]
+    with Bh = V_z^{-1} B taken along z; each 2-D shifted system is solved by a
+    sparse complex LU (SuperLU), one per pole and z mode.  Only the z factor
+    is diagonalised: cond(V_z) = r^{N-1} stays near e^{Pe v_z / 2} for the
+    upwind operators used here (~5e2), where the x and y factors would be
+    far worse conditioned."""
+    tau, cc, w0 = cf_table() if table is None else table
+    n2 = N * N
+    p = B.shape[1]
+    ax, bx, cx = coef[0]
+    ay, by, cy = coef[1]
+    Tx = sp.diags([np.full(N - 1, ax), np.full(N, bx), np.full(N - 1, cx)], [-1, 0, 1])
+    Ty = sp.diags([np.full(N - 1, ay), np.full(N, by), np.full(N - 1, cy)], [-1, 0, 1])
+    Iy = sp.identity(N)
+    Kxy = (sp.kron(Iy, Tx) + sp.kron(Ty, sp.identity(N))).tocsc().astype(complex)
+    lam, V, Vinv = _tridiag_modes(*coef[2], N)
+    B3 = np.asarray(B, np.float64).reshape(N, n2, p)          # [z, xy, column]
+    Bh = np.einsum("kz,zmp->kmp", Vinv, B3)
+    Zh = w0 * Bh
+    I2 = sp.identity(n2, dtype=complex, format="csc")
+    base = (-t) * Kxy
+    for k in range(N):
+        rhs = Bh[k].astype(complex)
+        acc = np.zeros((n2, p))
+        for tj, cj in zip(tau, cc):
+            lu = spla.splu(base - (t * lam[k] + tj) * I2)
+            acc += np.real(cj * lu.solve(rhs))
+        Zh[k] += acc
+    return np.einsum("zk,kmp->zmp", V, Zh).reshape(N ** 3, p)
+
+
 def expm_dense(M: np.ndarray, B: np.ndarray) -> np.ndarray:
     """e^{M}B by scipy's Pade scaling-and-squaring expm (n <= a few thousand)."""
     return sla.expm(M) @ B
-
-
-def expm_eigh(M: np.ndarray, B: np.ndarray) -> np.ndarray:
-    """e^{M}B for symmetric M through its eigendecomposition."""
-    lam, Q = np.linalg.eigh(0.5 * (M + M.T))
-    return Q @ (np.exp(lam)[:, None] * (Q.T @ B))

@@ -1,8 +1,8 @@
 """Ways to apply M^{-1} (M = tA) for the oracle (test infrastructure).
 
 Section 4.1: for moderate n the paper factors A once by sparse LU and applies
-U \\ (L \\ w); for Toeplitz A it uses the Gohberg-Semencul formula; for very
-large n an iterative solve.  Each function returns a callable V -> M^{-1} V.
+U \\ (L \\ w); for Toeplitz A it uses the Gohberg-Semencul formula.  Each
+function returns a callable V -> M^{-1} V.
 """
 from __future__ import annotations
 
@@ -77,15 +77,56 @@ def levinson_first_column(col: np.ndarray) -> np.ndarray:
     return sla.solve_toeplitz(col, e1)
 
 
-def gohberg_semencul_inverse(col: np.ndarray, scale: float):
+def cg_first_column(col: np.ndarray, rtol: float = 1e-15, maxiter: int = 100000) -> np.ndarray:
+    """x = T^{-1} e_1 for symmetric positive definite Toeplitz T = toeplitz(col)
+    by plain conjugate gradients with the circulant-embedding product
+    (toeplitz_matvec): O(n log n) per step where Levinson's recursion costs
+    O(n^2).  Iterates until ||e_1 - T x||_2 <= rtol (||e_1|| = 1) or the
+    residual stops decreasing for 50 steps; the true residual is recomputed
+    every 50 steps so the recurrence cannot drift."""
+    n = len(col)
+    b = np.zeros(n)
+    b[0] = 1.0
+    T = lambda v: toeplitz_matvec(col, v[:, None])[:, 0]
+    x = np.zeros(n)
+    r = b.copy()
+    d = r.copy()
+    rr = r @ r
+    best, stall = np.inf, 0
+    for it in range(maxiter):
+        q = T(d)
+        alpha = rr / (d @ q)
+        x += alpha * d
+        if (it + 1) % 50 == 0:
+            r = b - T(x)
+        else:
+            r -= alpha * q
+        rr_new = r @ r
+        rn = np.sqrt(rr_new)
+        if rn <= rtol:
+            break
+        if rn < 0.5 * best:
+            best, stall = rn, 0
+        else:
+            stall += 1
+            if stall >= 50:
+                break
+        d = r + (rr_new / rr) * d
+        rr = rr_new
+    return x
+
+
+def gohberg_semencul_inverse(col: np.ndarray, scale: float, x: np.ndarray | None = None):
     """(scale*T)^{-1} V for symmetric positive definite Toeplitz T by the
     Gohberg-Semencul formula (Section 4.1): with x = T^{-1} e_1,
         T^{-1} = (1/x_0) (L(x) L(x)^T - L(Z x~) L(Z x~)^T),
     L(y) the lower-triangular Toeplitz matrix with first column y, x~ the
     reversal of x and Z the down-shift.  Each lower/upper triangular Toeplitz
-    product is a length-2n FFT convolution."""
+    product is a length-2n FFT convolution.  x defaults to Levinson's solve
+    (levinson_first_column); for large n pass cg_first_column(col)."""
     n = len(col)
-    x = levinson_first_column(col)
+    if x is None:
+        x = levinson_first_column(col)
     xr = x[::-1]
     y = np.concatenate([[0.0], xr[:-1]])      # Z x~
 
@@ -142,23 +183,4 @@ def gohberg_semencul_general(col: np.ndarray, row: np.ndarray, scale: float):
         V = np.asarray(V, np.float64)
         W = lower(x, upper(y[::-1], V)) - lower(shift(y), upper(shift(x[::-1]), V))
         return W / (x[0] * scale)
-    return apply
-
-
-# ---- iterative ----------------------------------------------------------------
-
-def krylov_inverse(M: sp.spmatrix, rtol: float = 1e-14, symmetric: bool = True, maxiter=100000):
-    """Column-by-column CG (on -M, SPD) or BiCGStab to relative residual rtol."""
-    Mneg = -sp.csr_matrix(M)
-    solver = spla.cg if symmetric else spla.bicgstab
-
-    def apply(V):
-        V = np.asarray(V, np.float64)
-        out = np.empty_like(V)
-        for j in range(V.shape[1]):
-            xj, infoj = solver(Mneg, -V[:, j], rtol=rtol, atol=0.0, maxiter=maxiter)
-            if infoj != 0:
-                raise RuntimeError(f"inner solve did not converge (info={infoj})")
-            out[:, j] = xj
-        return out
     return apply
