@@ -19,10 +19,17 @@
  *  - CSR matrices use int32 row pointers (n + 1 entries, rowptr[0] = 0) and
  *    int32 column indices (nnz entries), FP64 values; column indices in a row
  *    need not be sorted.
- *  - The caller owns every array it passes and keeps it alive for the call.
- *    A plan copies what it needs from A at creation (the caller may free A
- *    afterwards) and owns its own device workspace, released by
- *    expmv_plan_destroy.
+ *  - The caller owns every array it passes and keeps it alive for the call,
+ *    including the device workspace `work` (work_bytes bytes, 256-byte
+ *    aligned, contents ignored on entry) that every call doing device work
+ *    takes; expmv_workspace_size* give the bytes a call needs, and a smaller
+ *    or misaligned buffer is refused with EINVAL before any device work.  A
+ *    plan copies what it needs from A at creation (the caller may free A
+ *    afterwards) and owns only what its creation set up (K, its transpose,
+ *    the AMG hierarchy, the Toeplitz spectra, the CF table), released by
+ *    expmv_plan_destroy: the library allocates device memory at plan
+ *    creation only (and in the one-shot forms, which create a plan).  Two
+ *    calls must not share one workspace while both can be running.
  *  - All device work is ordered on the stream given at plan creation
  *    (NULL = the default stream).  Entry points that return host values
  *    synchronise that stream before returning.
@@ -113,7 +120,36 @@ typedef struct {
                           (1..4; 0 = one less than the finest level's, at least 1).
                           Every level uses one polynomial before and after its coarse
                           correction, so the V-cycle stays symmetric.                 */
+  int restart_refine;  /* after every cycle the true residuals R_j = B - (tA - tau_j I) X_j
+                          are recomputed in FP64 from X_j (reported in expmv_info).
+                          1: the next cycle's right-hand sides are their coordinates
+                          S_j = V_{d+1}^T R_j on the block after the basis (refinement
+                          of the collinear residuals of eq. 4.8); 0 (default): the
+                          coordinates tau_j H_{d+1,d} E^T Z_j of eq. 4.8 themselves  */
 } expmv_opts;
+
+/* Kernel classes timed when opts.profile = N > 0: the launches of every N-th
+ * iteration of each inner solve and every orthogonalisation pass get HIP
+ * start/stop events on the plan's stream (launches that return at once
+ * because their solve has finished are not counted).  Index into
+ * expmv_info.kern_launches / kern_ms / kern_bytes. */
+typedef enum {
+  EXPMV_KT_CG_SPMM = 0,    /* inner CG: q = K p and the (p, q) partials (k_cg_a)           */
+  EXPMV_KT_CG_RESID = 1,   /* inner CG: r -= alpha q (k_cg_b)                              */
+  EXPMV_KT_CG_DIR = 2,     /* inner CG: x, p updates (k_cg_c)                              */
+  EXPMV_KT_BCG_SPMM1 = 3,  /* inner BiCGStab: v = K (M^{-1} p) (k_bcg_s)                   */
+  EXPMV_KT_BCG_SPMM2 = 4,  /* inner BiCGStab: t = K (M^{-1} s) (k_bcg_s)                   */
+  EXPMV_KT_BCG_U1 = 5,     /* inner BiCGStab: p = r + beta (p - omega v) (k_bcg_u1)        */
+  EXPMV_KT_BCG_U2 = 6,     /* inner BiCGStab: s = r - alpha v (k_bcg_u2)                   */
+  EXPMV_KT_BCG_U3 = 7,     /* inner BiCGStab: x, r updates and partials (k_bcg_u3)         */
+  EXPMV_KT_AMG_SMOOTH = 8, /* AMG finest level: smoothing steps (k_amg_step)               */
+  EXPMV_KT_AMG_RESTRICT = 9,  /* AMG finest level: restriction (k_amg_restrict / dense)    */
+  EXPMV_KT_AMG_PROLONG = 10,  /* AMG finest level: prolongation (+ smoothing step)
+                                 (k_amg_affine_pair / k_amg_prolong)                      */
+  EXPMV_KT_AMG_COARSE = 11,   /* every launch of the AMG levels below the finest          */
+  EXPMV_KT_ORTH = 12,         /* block Gram-Schmidt / CholQR passes (k_orth_mma, k_orth)   */
+  EXPMV_KT_COUNT = 16
+} expmv_kernel_class;
 
 typedef struct {                  /* host struct, filled by expmv_execute */
   int cycles;                     /* restart cycles run                               */
@@ -121,24 +157,28 @@ typedef struct {                  /* host struct, filled by expmv_execute */
   long long inner_iters;          /* inner solver iterations, summed over blocks      */
   int inner_maxit_hit;            /* inner solves that stopped at inner_maxit         */
   double est[7];                  /* rho_j of the last cycle (eq. 4.9)                */
-  double true_res[7];             /* ||B - (tA - tau_j I) X_j||_F after the last cycle */
+  double true_res[7];             /* ||R_j||_F, R_j = B - (tA - tau_j I) X_j in FP64,
+                                     after the last cycle                             */
   double err_bound;               /* sum_j |c_j| rho_j / delta_j / ||Z~||_F           */
   double bnorm, znorm;            /* ||B||_F, ||Z~||_F                                 */
   double ms_total, ms_apply, ms_orth, ms_small, ms_update;  /* host wall times      */
   int breakdown;                  /* 1 when the Krylov space became invariant          */
-  int kern_samples;               /* sampled inner iterations (opts.profile > 0)       */
-  double kern_ms_a, kern_ms_b,    /* mean device time of the inner CG's kernels, ms:  */
-         kern_ms_c;               /* A = CSR SpMM q = K p, B = residual update,
-                                     C = search-direction and iterate update          */
   int amg_levels;                 /* levels of the AMG hierarchy of the inner solver
                                      (0: Jacobi preconditioning)                      */
-  int kern_smooth_launches;       /* sampled launches of the finest AMG level's
-                                     smoothing-step kernel (pre, residual, post)      */
-  double kern_ms_smooth;          /* their mean device time, ms                       */
-  int kern_orth_launches;         /* timed block Gram-Schmidt / CholQR passes (matrix-
-                                     core kernel; profile > 0)                        */
-  double kern_ms_orth;            /* their mean device time, ms                       */
-  double kern_orth_bytes;         /* their mean algorithmic HBM bytes per launch      */
+  int kern_launches[EXPMV_KT_COUNT];  /* timed launches of each kernel class
+                                         (expmv_kernel_class; opts.profile > 0)      */
+  double kern_ms[EXPMV_KT_COUNT];     /* their mean device time, ms                  */
+  double kern_bytes[EXPMV_KT_COUNT];  /* their mean algorithmic HBM bytes per launch:
+                                         operands each read or written once (CSR:
+                                         4 (rows + 1) + 12 nnz), 8 bytes per FP64
+                                         and 4 per FP32 value                        */
+  double noncollinear[7];         /* ||R_j - V_{d+1} V_{d+1}^T R_j||_F after the last
+                                     cycle: the part of the true residual outside the
+                                     block the restart carries (0 in exact arithmetic,
+                                     Section 3)                                       */
+  double true_bound;              /* sum_j |c_j| ||R_j||_F / delta_j / ||Z~||_F        */
+  double noncollinear_bound;      /* the same sum over the remainders                 */
+  int refined_restarts;           /* restarts whose right-hand sides were refined     */
 } expmv_info;
 
 typedef struct expmv_plan_s* expmv_plan;
@@ -146,7 +186,8 @@ typedef struct expmv_plan_s* expmv_plan;
 /* Fill *o with the defaults: m = 10, k = 0 (auto), max_cycles = 50, FP64,
  * EXPMV_STOP_BOUND, inner_tol = 0 (auto), inner_maxit = 50000, symmetric = -1,
  * preconditioned = 1, profile = 0, inner_refine = -1, inner_precond = -1,
- * amg_degree = 0, inner_relax = 8.  o is a host pointer. */
+ * amg_degree = 0, inner_relax = 8, amg_fp32 = 0, amg_coarse_degree = 0,
+ * restart_refine = 0.  o is a host pointer. */
 expmv_status expmv_default_opts(expmv_opts* o);
 
 /* Plan for Z = e^{tA} B with A in CSR (device arrays, see conventions).
@@ -189,13 +230,29 @@ expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const do
                                          const double* diag, double t, const expmv_opts* opts,
                                          hipStream_t stream, expmv_plan* out);
 
+/* *bytes (host) = the device workspace expmv_execute, expmv_adjoint,
+ * expmv_grad_t and the expmv_apply_* calls need for a block of p columns
+ * (1 <= p <= 32, p <= n): the Krylov basis (two copies of (m+1) n p values),
+ * the inner solver's and the V-cycle's vectors, X (n x 14p FP64), the true
+ * residuals (n x 14p FP64), the projected systems and the reductions (and,
+ * for Toeplitz plans, the FFT arrays).  Errors: EINVAL. */
+expmv_status expmv_workspace_size(expmv_plan plan, int64_t p, size_t* bytes);
+/* The same for expmv_execute_times with nt times (1 <= nt <= 32). */
+expmv_status expmv_workspace_size_times(expmv_plan plan, int64_t p, int nt, size_t* bytes);
+/* The same for expmv_execute_source with n x p blocks U0 and S (2p <= 32). */
+expmv_status expmv_workspace_size_source(expmv_plan plan, int64_t p, size_t* bytes);
+
 /* Z = e^{tA} B (transpose = 0) or Z = e^{tA^T} B (transpose = 1), p = block
- * width (1 <= p <= 32, p <= n), tol = stopping tolerance of opts.stop_rule.
- * B and Z are device n x p blocks and may not overlap.  info (host) may be
- * NULL.  Returns OK, EINVAL, ENOCONV, EBREAKDOWN, EINNER, ENOMEM or EHIP;
- * after ENOCONV, EBREAKDOWN and EINNER Z holds the last iterate. */
+ * width (1 <= p <= 32, p <= n), tol = stopping tolerance of opts.stop_rule,
+ * work = device workspace of work_bytes >= expmv_workspace_size(plan, p).
+ * B and Z are device n x p blocks and may not overlap (nor the workspace).
+ * info (host) may be NULL.  Returns OK, EINVAL (also: workspace missing, too
+ * small or not 256-byte aligned), ENOCONV, EBREAKDOWN (also: a singular
+ * projected system or a non-finite estimate), EINNER, ENOMEM or EHIP; after
+ * ENOCONV, EBREAKDOWN and EINNER Z holds the last iterate. */
 expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int64_t p,
-                           double tol, double* Z, expmv_info* info);
+                           double tol, void* work, size_t work_bytes, double* Z,
+                           expmv_info* info);
 
 /* Several times at once: Z_q = e^{t_q A} B for q = 0..nt-1 (times: host
  * array, 1 <= nt <= 32; Z: device, nt consecutive n x p blocks, block q at
@@ -209,8 +266,8 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
  * over the times; true_res[j]: the largest over the times; znorm, est: time
  * 0).  Statuses as expmv_execute. */
 expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* times, int nt,
-                                 const double* B, int64_t p, double tol, double* Z,
-                                 expmv_info* info);
+                                 const double* B, int64_t p, double tol, void* work,
+                                 size_t work_bytes, double* Z, expmv_info* info);
 
 /* Linear ODE with an exponential source (Section 5, Example 5.3, gamma = -1):
  * U = the solution at time t (the plan's t) of u' = A u + e^{gamma s} S,
@@ -232,14 +289,14 @@ expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* t
  * block).  EINVAL for a non-finite gamma, U0 = S = 0 or bad sizes; other
  * statuses as expmv_execute. */
 expmv_status expmv_execute_source(expmv_plan plan, int transpose, const double* U0,
-                                  const double* S, int64_t p, double gamma, double tol, double* U,
-                                  expmv_info* info);
+                                  const double* S, int64_t p, double gamma, double tol,
+                                  void* work, size_t work_bytes, double* U, expmv_info* info);
 
 /* *out (host) = <G, A Z> = sum_ij G_ij (A Z)_ij: the derivative of
  * <G, e^{tA}B> with respect to t when Z = e^{tA}B (d/dt e^{tA}B = A e^{tA}B).
- * G, Z device n x p. */
+ * G, Z device n x p; work as expmv_execute. */
 expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Z, int64_t p,
-                          double* out);
+                          void* work, size_t work_bytes, double* out);
 
 /* Adjoint of Z = e^{tA}B for a loss L with dL/dZ = G: one solve with A^T
  * gives gradB = e^{tA^T} G (n x p, device), and *grad_t (host) =
@@ -249,17 +306,20 @@ expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Z, int
  * (partial fractions of x r(x)), which applies no operator to a computed
  * iterate.  tol and info as in expmv_execute; returns its statuses. */
 expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, int64_t p,
-                           double tol, double* gradB, double* grad_t, expmv_info* info);
+                           double tol, void* work, size_t work_bytes, double* gradB,
+                           double* grad_t, expmv_info* info);
 
-/* Y = tA X (transpose = 0) or (tA)^T X (transpose = 1), X, Y device n x p. */
+/* Y = tA X (transpose = 0) or (tA)^T X (transpose = 1), X, Y device n x p;
+ * work as expmv_execute. */
 expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* X,
-                                  int64_t p, double* Y);
+                                  int64_t p, void* work, size_t work_bytes, double* Y);
 
 /* Y ~= (tA)^{-1} X by the plan's preconditioner application (inner solve to
  * relative residual inner_tol, or Gohberg-Semencul for Toeplitz plans);
  * *iters (host, may be NULL) receives the largest inner iteration count. */
 expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X,
-                                 int64_t p, double* Y, long long* iters);
+                                 int64_t p, void* work, size_t work_bytes, double* Y,
+                                 long long* iters);
 
 /* Y = P X, one application of the CSR inner solver's preconditioner P for
  * K = -tA (or K^T when transpose = 1): P = D^{-1} (Jacobi) or one AMG
@@ -267,7 +327,7 @@ expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X
  * (1 <= p <= 32), not overlapping.  Errors: EINVAL (Toeplitz plan, bad
  * arguments), EHIP. */
 expmv_status expmv_apply_preconditioner(expmv_plan plan, int transpose, const double* X,
-                                        int64_t p, double* Y);
+                                        int64_t p, void* work, size_t work_bytes, double* Y);
 
 /* Copy the library's CF table to host arrays of 7 entries (poles with
  * Im tau > 0, c_j = 2 omega_j) and *omega0.  Any pointer may be NULL. */

@@ -11,6 +11,10 @@ OK, EINVAL, ENOTNEG, ENOMEM, ENOCONV, EBREAKDOWN, EHIP, EINNER = range(8)
 JACOBI, AMG, AUTO = 0, 1, -1
 FP64, MIXED, MIXED_INNER = 0, 1, 2
 STOP_PAPER, STOP_BOUND = 0, 1
+# expmv_kernel_class (timed kernel classes, opts.profile > 0)
+KT_NAMES = ["cg_spmm", "cg_resid", "cg_dir", "bcg_spmm1", "bcg_spmm2", "bcg_u1", "bcg_u2",
+            "bcg_u3", "amg_smooth", "amg_restrict", "amg_prolong", "amg_coarse", "orth"]
+KT_COUNT = 16
 
 
 class Opts(C.Structure):
@@ -19,7 +23,7 @@ class Opts(C.Structure):
                 ("inner_maxit", C.c_int), ("symmetric", C.c_int), ("preconditioned", C.c_int),
                 ("profile", C.c_int), ("inner_refine", C.c_int), ("inner_precond", C.c_int),
                 ("amg_degree", C.c_int), ("inner_relax", C.c_int), ("amg_fp32", C.c_int),
-                ("amg_coarse_degree", C.c_int)]
+                ("amg_coarse_degree", C.c_int), ("restart_refine", C.c_int)]
 
 
 class Info(C.Structure):
@@ -28,12 +32,11 @@ class Info(C.Structure):
                 ("true_res", C.c_double * 7), ("err_bound", C.c_double),
                 ("bnorm", C.c_double), ("znorm", C.c_double), ("ms_total", C.c_double),
                 ("ms_apply", C.c_double), ("ms_orth", C.c_double), ("ms_small", C.c_double),
-                ("ms_update", C.c_double), ("breakdown", C.c_int), ("kern_samples", C.c_int),
-                ("kern_ms_a", C.c_double), ("kern_ms_b", C.c_double),
-                ("kern_ms_c", C.c_double), ("amg_levels", C.c_int),
-                ("kern_smooth_launches", C.c_int), ("kern_ms_smooth", C.c_double),
-                ("kern_orth_launches", C.c_int), ("kern_ms_orth", C.c_double),
-                ("kern_orth_bytes", C.c_double)]
+                ("ms_update", C.c_double), ("breakdown", C.c_int), ("amg_levels", C.c_int),
+                ("kern_launches", C.c_int * KT_COUNT), ("kern_ms", C.c_double * KT_COUNT),
+                ("kern_bytes", C.c_double * KT_COUNT), ("noncollinear", C.c_double * 7),
+                ("true_bound", C.c_double), ("noncollinear_bound", C.c_double),
+                ("refined_restarts", C.c_int)]
 
     def as_dict(self):
         d = {}
@@ -52,7 +55,8 @@ EXPORTS = [
     "expmv_host_amg_level", "expmv_host_amg_coarse_inverse", "expmv_host_amg_destroy",
     "expmv_host_amg_fused",
     "expmv_execute_times", "expmv_last_error_detail", "expmv_plan_toeplitz_general",
-    "expmv_execute_source",
+    "expmv_execute_source", "expmv_workspace_size", "expmv_workspace_size_times",
+    "expmv_workspace_size_source",
 ]
 
 _lib = None
@@ -73,11 +77,16 @@ def lib():
     L.expmv_plan_toeplitz.argtypes = [i64, vp, dbl, C.POINTER(Opts), vp, C.POINTER(vp)]
     L.expmv_plan_toeplitz_general.argtypes = [i64, vp, vp, vp, dbl, C.POINTER(Opts), vp,
                                               C.POINTER(vp)]
-    L.expmv_execute.argtypes = [vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
-    L.expmv_grad_t.argtypes = [vp, vp, vp, i64, C.POINTER(dbl)]
-    L.expmv_adjoint.argtypes = [vp, vp, vp, i64, dbl, vp, C.POINTER(dbl), C.POINTER(Info)]
-    L.expmv_apply_operator.argtypes = [vp, i32, vp, i64, vp]
-    L.expmv_apply_inverse.argtypes = [vp, i32, vp, i64, vp, C.POINTER(C.c_longlong)]
+    sz = C.c_size_t
+    L.expmv_workspace_size.argtypes = [vp, i64, C.POINTER(sz)]
+    L.expmv_workspace_size_times.argtypes = [vp, i64, i32, C.POINTER(sz)]
+    L.expmv_workspace_size_source.argtypes = [vp, i64, C.POINTER(sz)]
+    L.expmv_execute.argtypes = [vp, i32, vp, i64, dbl, vp, sz, vp, C.POINTER(Info)]
+    L.expmv_grad_t.argtypes = [vp, vp, vp, i64, vp, sz, C.POINTER(dbl)]
+    L.expmv_adjoint.argtypes = [vp, vp, vp, i64, dbl, vp, sz, vp, C.POINTER(dbl),
+                                C.POINTER(Info)]
+    L.expmv_apply_operator.argtypes = [vp, i32, vp, i64, vp, sz, vp]
+    L.expmv_apply_inverse.argtypes = [vp, i32, vp, i64, vp, sz, vp, C.POINTER(C.c_longlong)]
     L.expmv_cf_table.argtypes = [vp, vp, vp, vp, vp]
     L.expmv_host_eig_sym.argtypes = [i32, vp, vp, vp]
     L.expmv_host_eig_general.argtypes = [i32, vp, vp, vp, vp, vp]
@@ -89,9 +98,11 @@ def lib():
     L.expmv_last_error_detail.restype = C.c_char_p
     L.expmv_block_csr.argtypes = [i64, i64, vp, vp, vp, vp, i64, dbl, dbl, vp, vp]
     L.expmv_block_toeplitz.argtypes = [i64, vp, vp, i64, dbl, dbl, vp, vp]
-    L.expmv_apply_preconditioner.argtypes = [vp, i32, vp, i64, vp]
-    L.expmv_execute_times.argtypes = [vp, i32, vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
-    L.expmv_execute_source.argtypes = [vp, i32, vp, vp, i64, dbl, dbl, vp, C.POINTER(Info)]
+    L.expmv_apply_preconditioner.argtypes = [vp, i32, vp, i64, vp, sz, vp]
+    L.expmv_execute_times.argtypes = [vp, i32, vp, i32, vp, i64, dbl, vp, sz, vp,
+                                      C.POINTER(Info)]
+    L.expmv_execute_source.argtypes = [vp, i32, vp, vp, i64, dbl, dbl, vp, sz, vp,
+                                       C.POINTER(Info)]
     L.expmv_host_amg_build.argtypes = [i64, vp, vp, vp, i32, dbl, i32, C.POINTER(vp)]
     L.expmv_host_amg_levels.argtypes = [vp]
     L.expmv_host_amg_level.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]

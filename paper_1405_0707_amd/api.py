@@ -69,6 +69,32 @@ class Plan:
         # stream when the plan was made)
         self._stream = (torch.cuda.current_stream(device)
                         if torch.device(device).type == "cuda" else None)
+        self._work = {}   # (kind, p, nt) -> uint8 device tensor (the call's workspace)
+
+    def workspace_size(self, p: int, kind: str = "execute", nt: int = 1) -> int:
+        """Bytes of device workspace a call with block width p needs (kind:
+        "execute" for execute / adjoint / grad_t / apply_*, "times" for
+        execute_times with nt times, "source" for execute_source)."""
+        b = C.c_size_t()
+        if kind == "times":
+            st = lib().expmv_workspace_size_times(self._h, int(p), int(nt), C.byref(b))
+        elif kind == "source":
+            st = lib().expmv_workspace_size_source(self._h, int(p), C.byref(b))
+        else:
+            st = lib().expmv_workspace_size(self._h, int(p), C.byref(b))
+        check(st, "expmv_workspace_size")
+        return b.value
+
+    def _ws(self, p: int, kind: str = "execute", nt: int = 1):
+        """(pointer, bytes) of a workspace for the call, allocated by torch on
+        the plan's device and kept for later calls of the same shape."""
+        key = (kind, int(p), int(nt))
+        t = self._work.get(key)
+        if t is None:
+            nbytes = self.workspace_size(p, kind, nt)
+            t = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+            self._work[key] = t
+        return t.data_ptr(), t.numel()
 
     def _run(self, call):
         """Run a library call on the plan's stream, ordered after the work
@@ -143,6 +169,10 @@ class Plan:
             raise ValueError(f"{name} may not overlap the input block")
         return out
 
+    def release_workspaces(self):
+        """Drop the cached workspaces (torch frees them)."""
+        self._work = {}
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -157,8 +187,9 @@ class Plan:
         B = self._block(B, "B")
         Z = self._out(out, B, "out")
         info = Info()
+        wp, wb = self._ws(B.shape[1])
         st = self._run(lambda: lib().expmv_execute(
-            self._h, int(transpose), B.data_ptr(), B.shape[1], float(tol), Z.data_ptr(),
+            self._h, int(transpose), B.data_ptr(), B.shape[1], float(tol), wp, wb, Z.data_ptr(),
             C.byref(info)))
         check(st, "expmv_execute", allow)
         return Z, info
@@ -171,9 +202,10 @@ class Plan:
         ts = (C.c_double * len(times))(*[float(x) for x in times])
         Z = torch.empty((len(times),) + tuple(B.shape), dtype=torch.float64, device=self.device)
         info = Info()
+        wp, wb = self._ws(B.shape[1], "times", len(times))
         st = self._run(lambda: lib().expmv_execute_times(
             self._h, int(transpose), ts, len(times), B.data_ptr(), B.shape[1], float(tol),
-            Z.data_ptr(), C.byref(info)))
+            wp, wb, Z.data_ptr(), C.byref(info)))
         check(st, "expmv_execute_times", allow)
         return Z, info
 
@@ -187,9 +219,10 @@ class Plan:
             raise ValueError("U0 and S must have the same shape")
         U = torch.empty_like(U0)
         info = Info()
+        wp, wb = self._ws(U0.shape[1], "source")
         st = self._run(lambda: lib().expmv_execute_source(
             self._h, int(transpose), U0.data_ptr(), S.data_ptr(), U0.shape[1], float(gamma),
-            float(tol), U.data_ptr(), C.byref(info)))
+            float(tol), wp, wb, U.data_ptr(), C.byref(info)))
         check(st, "expmv_execute_source", allow)
         return U, info
 
@@ -199,8 +232,10 @@ class Plan:
         if G.shape != Z.shape:
             raise ValueError("G and Z must have the same shape")
         out = C.c_double()
+        wp, wb = self._ws(G.shape[1])
         check(self._run(lambda: lib().expmv_grad_t(
-            self._h, G.data_ptr(), Z.data_ptr(), G.shape[1], C.byref(out))), "expmv_grad_t")
+            self._h, G.data_ptr(), Z.data_ptr(), G.shape[1], wp, wb, C.byref(out))),
+            "expmv_grad_t")
         return out.value
 
     def adjoint(self, G: torch.Tensor, B: torch.Tensor, tol: float = 1e-10, allow=()):
@@ -212,8 +247,9 @@ class Plan:
         gB = torch.empty_like(G)
         gt = C.c_double()
         info = Info()
+        wp, wb = self._ws(G.shape[1])
         st = self._run(lambda: lib().expmv_adjoint(
-            self._h, G.data_ptr(), B.data_ptr(), G.shape[1], float(tol), gB.data_ptr(),
+            self._h, G.data_ptr(), B.data_ptr(), G.shape[1], float(tol), wp, wb, gB.data_ptr(),
             C.byref(gt), C.byref(info)))
         check(st, "expmv_adjoint", allow)
         return gB, gt.value, info
@@ -221,8 +257,9 @@ class Plan:
     def apply_operator(self, X: torch.Tensor, transpose: bool = False) -> torch.Tensor:
         X = self._block(X, "X")
         Y = torch.empty_like(X)
+        wp, wb = self._ws(X.shape[1])
         check(self._run(lambda: lib().expmv_apply_operator(
-            self._h, int(transpose), X.data_ptr(), X.shape[1], Y.data_ptr())),
+            self._h, int(transpose), X.data_ptr(), X.shape[1], wp, wb, Y.data_ptr())),
             "expmv_apply_operator")
         return Y
 
@@ -231,8 +268,9 @@ class Plan:
         (Jacobi D^{-1}, or one AMG V-cycle): Y ~= K^{-1} X."""
         X = self._block(X, "X")
         Y = torch.empty_like(X)
+        wp, wb = self._ws(X.shape[1])
         check(self._run(lambda: lib().expmv_apply_preconditioner(
-            self._h, int(transpose), X.data_ptr(), X.shape[1], Y.data_ptr())),
+            self._h, int(transpose), X.data_ptr(), X.shape[1], wp, wb, Y.data_ptr())),
             "expmv_apply_preconditioner")
         return Y
 
@@ -240,9 +278,10 @@ class Plan:
         X = self._block(X, "X")
         Y = torch.empty_like(X)
         it = C.c_longlong()
+        wp, wb = self._ws(X.shape[1])
         check(self._run(lambda: lib().expmv_apply_inverse(
-            self._h, int(transpose), X.data_ptr(), X.shape[1], Y.data_ptr(), C.byref(it))),
-            "expmv_apply_inverse")
+            self._h, int(transpose), X.data_ptr(), X.shape[1], wp, wb, Y.data_ptr(),
+            C.byref(it))), "expmv_apply_inverse")
         return Y, it.value
 
 

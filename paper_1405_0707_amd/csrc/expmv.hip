@@ -27,6 +27,7 @@
 #include "kernels.hpp"
 #include "kernels_dense.hpp"
 #include "orth_mfma.hpp"
+#include "residual.hpp"
 #include "toeplitz.hpp"
 
 #include "cf_nu14.inc"
@@ -40,6 +41,9 @@ struct HipError {
 struct StatusError {
   expmv_status st;
 };
+
+// Detail of the last EHIP / ENOMEM / EINVAL from a check inside a call.
+thread_local char g_error_detail[256] = "";
 
 #define HIPCHK(call)                                             \
   do {                                                           \
@@ -79,40 +83,77 @@ static int pow2_lanes(int p) {
   return pp;
 }
 
-// Work arrays that depend on the block width p, kept between calls.  The
-// basis, W and the inner solver's vectors hold the working type of the
-// plan (FP64, or FP32 in the mixed form); everything else is FP64.
+// Work arrays of one call, carved out of the caller's workspace buffer
+// (expmv_workspace_size gives its size).  The basis, W and the inner
+// solver's vectors hold the working type of the plan (FP64, or FP32 in the
+// mixed form); everything else is FP64.
 struct Workspace {
-  int p = 0;
-  DevBuf<char> V[2];            // basis panels, (m+1) * n * p elements each
-  DevBuf<char> W, Wt;           // n x p (basis type)
-  DevBuf<char> Win, Wout;       // n x p (inner-solver type, when it differs)
-  DevBuf<char> Rin, Din;        // n x p (inner-solver type, refinement)
-  DevBuf<char> kr, kpa, kpb, kq, kv, ks, kt, krh;   // inner-solver vectors, n x p
-  DevBuf<char> kz, kph, ksh;                        // AMG-preconditioned vectors
-  DevBuf<float> kr32, kz32;                         // FP32 V-cycle input / output (n x p)
-  DevBuf<double> X;             // n x 14p
-  DevBuf<double> partial;       // reductions of the dense kernels
-  DevBuf<double> hcoef, gram, R1, R2, Rinv, w0;   // small orth buffers
-  DevBuf<double> H;             // ldh x ldh
-  DevBuf<double> Rhat;          // p x p
-  DevBuf<cplx> G, Zs, Ascr, S;
-  DevBuf<double> Cr, Crot, rho;
-  DevBuf<int> flags, singular;
-  DevBuf<CgState> cgst;
-  DevBuf<BcgState> bcgst;
-  DevBuf<double> part_rr, part_sig;   // inner-solver partials
-  DevBuf<double> taus, coefs;         // poles and coefficients of all shifts (re | im)
-  DevBuf<cplx> S2;
-  DevBuf<int> singular2;
-  DevBuf<KrylovCtl> ctl;
+  char* V[2] = {};              // basis panels, (m+1) * n * p elements each
+  char *W = nullptr, *Wt = nullptr;          // n x p (basis type)
+  char *Win = nullptr, *Wout = nullptr;      // n x p (inner-solver type, when it differs)
+  char *Rin = nullptr, *Din = nullptr;       // n x p (inner-solver type, refinement)
+  char *kr = nullptr, *kpa = nullptr, *kpb = nullptr, *kq = nullptr, *kv = nullptr,
+       *ks = nullptr, *kt = nullptr, *krh = nullptr;   // inner-solver vectors, n x p
+  char *kz = nullptr, *kph = nullptr, *ksh = nullptr;  // AMG-preconditioned vectors
+  float *kr32 = nullptr, *kz32 = nullptr;   // FP32 V-cycle input / output (n x p)
+  double* X = nullptr;                      // n x 14p nt
+  double* partial = nullptr;                // reductions of the dense kernels
+  double *hcoef = nullptr, *gram = nullptr, *R1 = nullptr, *R2 = nullptr, *Rinv = nullptr,
+         *w0 = nullptr;                     // small orth buffers
+  double* H = nullptr;                      // ldh x ldh
+  double* Rhat = nullptr;                   // p x p
+  cplx *G = nullptr, *Zs = nullptr, *Ascr = nullptr, *S = nullptr;
+  double *Cr = nullptr, *Crot = nullptr, *rho = nullptr;
+  int *flags = nullptr, *singular = nullptr;
+  CgState* cgst = nullptr;
+  BcgState* bcgst = nullptr;
+  double *part_rr = nullptr, *part_sig = nullptr;   // inner-solver partials
+  double *taus = nullptr, *coefs = nullptr;         // poles and coefficients of all shifts
+  cplx* S2 = nullptr;
+  int* singular2 = nullptr;
+  KrylovCtl* ctl = nullptr;
+  double* Rres = nullptr;               // n x 14p: true residuals of one time block (also
+                                        // K X of a Toeplitz plan, K B of the adjoint)
+  double* projC = nullptr;              // p x 14p coordinates V_last^T R
+  double* rpart = nullptr;              // residual and remainder partial norms
+  cplx* Sref = nullptr;                 // restart coordinates when not refining
+  cplx* fb[4] = {};                     // Toeplitz FFT work arrays, L x fq complex
+  int fq = 0;
+  double* srcB = nullptr;               // n x 2p joined block [U0 | S] (source-term solves)
+};
+
+// Hands out 256-byte aligned pieces of one buffer in a fixed order; with
+// base == nullptr it only adds up the sizes.
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return ptr;
+  }
 };
 
 constexpr int kAmgMaxDeg = 4;
 constexpr double kAmgEigRatio = 20.0;   // Chebyshev interval [lmax / ratio, lmax]
 constexpr int64_t kAmgFuseGrowth = 16;  // fused operators: at most this many times nnz(A) + nnz(P)
-constexpr int kSmoothEv = 4 * kAmgMaxDeg;   // events around the finest level's smoothing steps
-constexpr int kSampleEv = 6 + kSmoothEv;    // events of one profiled inner iteration
+constexpr int kKtSlots = 4096;   // timed launches between two collections (opts.profile > 0)
+
+// Kernel timing (opts.profile > 0): event pairs from a pool, each with the
+// launch's kernel class, the inner iteration it belongs to (-1: none) and
+// its algorithmic bytes; summed per class by kt_collect.
+struct KernelTimer {
+  std::vector<hipEvent_t> ev;   // 2 per slot
+  std::vector<int> cls, iter;
+  std::vector<double> bytes;
+  int used = 0;
+  int cur_iter = -1;            // inner iteration being launched, -1 outside inner solves
+  bool sampling = false;        // that iteration is timed
+  double ms[EXPMV_KT_COUNT] = {}, by[EXPMV_KT_COUNT] = {};
+  int cnt[EXPMV_KT_COUNT] = {};
+};
 
 // One level of the AMG hierarchy on the device.  Level 0 borrows the plan's
 // CSR operator and Jacobi scaling; coarser levels own their Galerkin
@@ -133,6 +174,7 @@ struct AmgDevLevel {
   double cd[kAmgMaxDeg] = {}, ad[kAmgMaxDeg] = {};   // Chebyshev step coefficients
   int degree = 2;                                    // smoothing steps before / after
   double avg_a = 0.0, avg_p = 0.0, avg_r = 0.0;      // mean nonzeros per row of A, P, R
+  int64_t nnz_a = 0, nnz_p = 0, nnz_r = 0, nnz_rf = 0, nnz_pf = 0;   // (timing byte counts)
   // A level below the finest smoothed by one step (degree 1, x0 = s0 D^{-1} b):
   // the pre-smoothing step, the residual and the restriction are one operator
   // Rf = R (I - s0 A D^{-1}), and the prolongation and the post-smoothing step
@@ -149,7 +191,8 @@ struct AmgDevLevel {
   DevBuf<double> Rfv, Pfv;
   DevBuf<float> Rfv32, Pfv32;
   double avg_rf = 0.0, avg_pf = 0.0;
-  DevBuf<char> vb, vu, vv, vd, vr, vo;
+  char *vb = nullptr, *vu = nullptr, *vv = nullptr, *vd = nullptr, *vr = nullptr,
+       *vo = nullptr;   // carved from the call's workspace
 };
 
 // Sub-lanes per row for a matrix with `avg` nonzeros per row: the largest
@@ -169,8 +212,6 @@ struct AmgDev {
   // pre-smoothing step and residual
   DevBuf<double> cinvR;
   int degree = 2;
-  int p = 0;
-  size_t el = 0;
 };
 
 }  // namespace expmv
@@ -181,6 +222,7 @@ struct expmv_plan_s {
   int kind = 0;                 // 0 CSR, 1 Toeplitz
   int64_t n = 0, nnz = 0;
   double t = 0.0;
+  int device = 0;               // the device current when the plan was made
   expmv_opts opts{};
   hipStream_t stream = nullptr;
   bool symmetric = true;
@@ -201,32 +243,16 @@ struct expmv_plan_s {
   DevBuf<cplx> chatT, jyhat, zyhat;
   bool tsym = true;              // T symmetric (A = -diag(d) T symmetric needs d = 1 too)
   DevBuf<double> tdiag, tdinv;   // d and 1/d of A = -diag(d) T (empty: d = 1)
-  DevBuf<cplx> fb[4];            // L x q work arrays
-  int fq = 0;                    // complex columns the work arrays hold
-  DevBuf<double> kx;             // n x 14p (Toeplitz true residual)
-  DevBuf<double> srcB;           // n x 2p joined block [U0 | S] (source-term solves)
+  DevBuf<cplx> setup_fb[3];      // L x 1 work arrays of the plan's own set-up transforms
   // CF table on the device
   DevBuf<double> tau_re, tau_im, c_re, c_im;
   Workspace ws;
   int* host_flags = nullptr;    // pinned, 2 slots x 4 ints
   hipEvent_t ev[2]{};
   int ldh = 0;
-  // profiling (opts.profile > 0): event pairs around sampled inner iterations
-  // (per sample: C, A, B start/stop, then up to kSmoothEv events around the
-  // finest level's smoothing steps of the sample's V-cycle)
-  std::vector<hipEvent_t> pev;
-  std::vector<int> pev_iter;      // inner iteration index of each sample
-  std::vector<int> pev_nsm;       // smoothing launches timed in each sample
-  int pev_used = 0;               // samples in use
-  double prof_ms_a = 0.0, prof_ms_b = 0.0, prof_ms_c = 0.0, prof_ms_sm = 0.0;
-  int prof_samples = 0, prof_sm_launches = 0;
   int last_inner_iters = 0;       // iterations of the previous inner solve
   double relax_scale = 1.0;       // inner tolerance factor (opts.inner_relax)
-  // (profile > 0) start/stop events of the orthogonalisation passes of one
-  // execute and their algorithmic bytes
-  std::vector<hipEvent_t> oev;
-  std::vector<double> oev_bytes;
-  int oev_used = 0;
+  KernelTimer kt;                 // opts.profile > 0
   // AMG preconditioner of the CSR inner solver: hierarchy of K and, for a
   // nonsymmetric K, of K^T (transposed solves)
   std::unique_ptr<AmgDev> amg, amgT;
@@ -302,71 +328,143 @@ constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
     CG_CASE(8, p, __VA_ARGS__) CG_CASE(16, p, __VA_ARGS__) CG_CASE(32, p, __VA_ARGS__) \
   }
 
-void ensure_workspace(expmv_plan_s* pl, int p) {
-  Workspace& w = pl->ws;
+// Lay out the call's workspace in `work` (nullptr: size only) and return its
+// size in bytes.  p = width of the block the method runs on (the joined
+// block's in source mode), nt = times, joined = source mode (the joined
+// block itself is kept in the workspace).  All per-call device arrays come
+// from here: the basis, the inner solver's and the V-cycle's vectors, X,
+// the projected systems, the reductions and the Toeplitz FFT arrays.  The
+// plan holds only what its creation set up.
+size_t layout_workspace(expmv_plan_s* pl, int p, int nt, bool joined, char* work) {
+  Carver c{work};
+  Workspace w;
   const int64_t n = pl->n;
   const int m = pl->opts.m;
   const int npan_max = m + 1;
   const int ldh = (m + 1) * p;
-  pl->ldh = ldh;
-  if (w.p == p) return;
+  const int ns = kNShift * nt;
   const size_t elb = pl->basis32 ? sizeof(float) : sizeof(double);   // basis
   const size_t el = pl->mixed ? sizeof(float) : sizeof(double);      // inner solver
   const size_t blk = size_t(n) * p;
-  w.V[0].alloc(blk * npan_max * elb);
-  w.V[1].alloc(blk * npan_max * elb);
-  w.W.alloc(blk * std::max(elb, el));
-  w.Wt.alloc(blk * std::max(elb, el));
-  w.Win.alloc(blk * el);
-  w.Wout.alloc(blk * el);
-  if (pl->mixed) {
-    w.Rin.alloc(blk * el);
-    w.Din.alloc(blk * el);
+  const bool csr = pl->kind == 0;
+  w.V[0] = c.take<char>(blk * npan_max * elb);
+  w.V[1] = c.take<char>(blk * npan_max * elb);
+  w.W = c.take<char>(blk * std::max(elb, el));
+  w.Wt = c.take<char>(blk * std::max(elb, el));
+  w.Win = c.take<char>(blk * el);
+  w.Wout = c.take<char>(blk * el);
+  if (pl->mixed && csr) {
+    w.Rin = c.take<char>(blk * el);
+    w.Din = c.take<char>(blk * el);
   }
-  w.kr.alloc(blk * el);
-  w.kpa.alloc(blk * el);
-  w.kpb.alloc(blk * el);
-  w.kq.alloc(blk * el);
-  if (pl->amg) w.kz.alloc(blk * el);
-  if (pl->amg && !pl->symmetric) {
-    w.kph.alloc(blk * el);
-    w.ksh.alloc(blk * el);
+  if (csr) {
+    w.kr = c.take<char>(blk * el);
+    w.kpa = c.take<char>(blk * el);
+    w.kpb = c.take<char>(blk * el);
+    w.kq = c.take<char>(blk * el);
+    if (pl->amg) w.kz = c.take<char>(blk * el);
+    if (pl->amg && !pl->symmetric) {
+      w.kph = c.take<char>(blk * el);
+      w.ksh = c.take<char>(blk * el);
+    }
+    if (!pl->symmetric) {
+      w.kv = c.take<char>(blk * el);
+      w.ks = c.take<char>(blk * el);
+      w.kt = c.take<char>(blk * el);
+      w.krh = c.take<char>(blk * el);
+    }
+    if (pl->amg && !pl->mixed && pl->opts.amg_fp32) {
+      w.kr32 = c.take<float>(blk);
+      w.kz32 = c.take<float>(blk);
+    }
   }
-  if (!pl->symmetric) {
-    w.kv.alloc(blk * el);
-    w.ks.alloc(blk * el);
-    w.kt.alloc(blk * el);
-    w.krh.alloc(blk * el);
-  }
-  w.X.alloc(blk * 2 * kNShift);
+  w.X = c.take<double>(blk * 2 * ns);
   const size_t O = size_t(npan_max) * p * p + p;
-  w.partial.alloc(std::max<size_t>(O * kOrthGrid, size_t(512) * kNShift));
-  w.hcoef.alloc(O);
-  w.gram.alloc(size_t(p) * p);
-  w.R1.alloc(size_t(p) * p);
-  w.R2.alloc(size_t(p) * p);
-  w.Rinv.alloc(size_t(p) * p);
-  w.w0.alloc(O);
-  w.H.alloc(size_t(ldh) * ldh);
-  w.Rhat.alloc(size_t(p) * p);
+  const int Wres = 2 * kNShift * p;
+  w.partial = c.take<double>(std::max({O * kOrthGrid, size_t(512) * std::max(nt, 16),
+                                       size_t(kResGrid) * p * Wres, size_t(4096)}));
+  w.hcoef = c.take<double>(O);
+  w.gram = c.take<double>(size_t(p) * p);
+  w.R1 = c.take<double>(size_t(p) * p);
+  w.R2 = c.take<double>(size_t(p) * p);
+  w.Rinv = c.take<double>(size_t(p) * p);
+  w.w0 = c.take<double>(O);
+  w.H = c.take<double>(size_t(ldh) * ldh);
+  w.Rhat = c.take<double>(size_t(p) * p);
   const int dmax = m * p;
-  w.G.alloc(size_t(kNShift) * dmax * p);
-  w.Zs.alloc(size_t(kNShift) * dmax * p);
-  w.Ascr.alloc(size_t(kNShift) * dmax * dmax);
-  w.S.alloc(size_t(kNShift) * p * p);
-  w.Cr.alloc(size_t(ldh) * 2 * kNShift * p);
-  w.Crot.alloc(size_t(dmax) * dmax);
-  w.rho.alloc(kNShift);
-  w.flags.alloc(4);
-  w.singular.alloc(kNShift);
-  w.cgst.alloc(1);
-  w.bcgst.alloc(1);
-  w.part_rr.alloc(size_t(kCgGrid) * 2 * kMaxP);
-  w.part_sig.alloc(size_t(kCgGrid) * 2 * kMaxP);
-  w.ctl.alloc(1);
-  HIPCHK(hipMemsetAsync(w.ctl.p, 0, sizeof(KrylovCtl), pl->stream));
-  w.p = p;
+  w.G = c.take<cplx>(size_t(ns) * dmax * p);
+  w.Zs = c.take<cplx>(size_t(ns) * dmax * p);
+  w.Ascr = c.take<cplx>(size_t(ns) * dmax * dmax);
+  w.S = c.take<cplx>(size_t(ns) * p * p);
+  w.Cr = c.take<double>(size_t(ldh) * 2 * ns * p);
+  w.Crot = c.take<double>(size_t(dmax) * dmax);
+  w.rho = c.take<double>(ns);
+  w.flags = c.take<int>(4);
+  w.singular = c.take<int>(ns);
+  w.cgst = c.take<CgState>(1);
+  w.bcgst = c.take<BcgState>(1);
+  w.part_rr = c.take<double>(size_t(kCgGrid) * 2 * kMaxP);
+  w.part_sig = c.take<double>(size_t(kCgGrid) * 2 * kMaxP);
+  w.taus = c.take<double>(2 * size_t(ns));
+  w.coefs = c.take<double>(4 * size_t(ns));
+  w.S2 = c.take<cplx>(size_t(ns) * p * p);
+  w.singular2 = c.take<int>(ns);
+  w.ctl = c.take<KrylovCtl>(1);
+  w.Rres = c.take<double>(blk * 2 * kNShift);
+  w.projC = c.take<double>(size_t(p) * Wres);
+  w.rpart = c.take<double>(size_t(512 + kResGrid) * kNShift);
+  w.Sref = c.take<cplx>(size_t(ns) * p * p);
+  if (!csr) {
+    w.fq = p;   // the residual transforms 2p real columns as p complex ones
+    for (auto& b : w.fb) b = c.take<cplx>(size_t(pl->L) * w.fq);
+  }
+  if (joined) w.srcB = c.take<double>(blk);
+  // V-cycle vectors of the hierarchy of K and of K^T: one call uses one of
+  // them, so both share one region
+  size_t amg_base = 0, amg_end = 0;
+  for (AmgDev* Hd : {pl->amg.get(), pl->amgT.get()}) {
+    if (!Hd) continue;
+    Carver h{nullptr, 0};
+    const size_t start = (c.off + 255) & ~size_t(255);
+    if (amg_base == 0) amg_base = start;
+    h.off = amg_base;
+    h.base = work;
+    for (size_t l = 0; l < Hd->lv.size(); ++l) {
+      AmgDevLevel& L = *Hd->lv[l];
+      const size_t bytes = size_t(L.n) * p * sizeof(double);
+      char *vu = nullptr, *vv = nullptr, *vd = nullptr, *vr = nullptr, *vb = nullptr, *vo = nullptr;
+      if (l + 1 < Hd->lv.size()) {
+        vu = h.take<char>(bytes);
+        vv = h.take<char>(bytes);
+        vd = h.take<char>(bytes);
+        vr = h.take<char>(bytes);
+      }
+      if (l > 0) {
+        vb = h.take<char>(bytes);
+        vo = h.take<char>(bytes);
+      }
+      if (work) {
+        L.vu = vu;
+        L.vv = vv;
+        L.vd = vd;
+        L.vr = vr;
+        L.vb = vb;
+        L.vo = vo;
+      }
+    }
+    amg_end = std::max(amg_end, h.off);
+  }
+  if (amg_end > c.off) c.off = amg_end;
+  if (work) {
+    pl->ws = w;
+    pl->ldh = ldh;
+  }
+  return c.off;
 }
+
+// Bind the call's workspace; EINVAL (with a detail) when `work` is missing
+// or smaller than layout_workspace asks for.
+void bind_workspace(expmv_plan_s* pl, int p, int nt, bool joined, void* work, size_t bytes);
 
 // ------------------------------------------------------------------------
 // operator data of the working type
@@ -416,32 +514,46 @@ void apply_K(expmv_plan_s* pl, int transpose, const T* X, T* Y, int p) {
                                      int(pl->n), p, A.rowptr, A.colind, A.val, X, Y));
 }
 
-// Read the sampled start/stop events of the inner solver (three kernels per
-// sampled iteration).  Only iterations the solve actually ran count (kexec
-// = iterations executed); the ones issued after convergence return at once.
-void collect_profile(expmv_plan_s* pl, int kexec) {
-  for (int sidx = 0; sidx < pl->pev_used; ++sidx) {
-    const hipEvent_t* e = &pl->pev[size_t(sidx) * kSampleEv];
-    const int nsm = pl->pev_nsm[sidx];
-    float tc = 0.f, ta = 0.f, tb = 0.f;
-    HIPCHK(hipEventSynchronize(nsm > 0 ? e[6 + 2 * nsm - 1] : e[5]));
-    HIPCHK(hipEventElapsedTime(&tc, e[0], e[1]));
-    HIPCHK(hipEventElapsedTime(&ta, e[2], e[3]));
-    HIPCHK(hipEventElapsedTime(&tb, e[4], e[5]));
-    if (pl->pev_iter[sidx] < kexec) {
-      pl->prof_ms_a += ta;
-      pl->prof_ms_b += tb;
-      pl->prof_ms_c += tc;
-      pl->prof_samples += 1;
-      for (int q = 0; q < nsm; ++q) {
-        float ts = 0.f;
-        HIPCHK(hipEventElapsedTime(&ts, e[6 + 2 * q], e[6 + 2 * q + 1]));
-        pl->prof_ms_sm += ts;
-        pl->prof_sm_launches += 1;
-      }
-    }
+struct KtEv {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+// Start/stop events for one launch of kernel class `cls` moving `bytes`
+// algorithmic bytes, or none when it is not timed (profile off, an inner
+// iteration that is not sampled, or the pool is full until the next
+// collection).
+KtEv kt_take(expmv_plan_s* pl, int cls, double bytes) {
+  KernelTimer& k = pl->kt;
+  if (pl->opts.profile <= 0 || (k.cur_iter >= 0 && !k.sampling) || k.used >= kKtSlots) return {};
+  const int u = k.used++;
+  k.cls[u] = cls;
+  k.iter[u] = k.cur_iter;
+  k.bytes[u] = bytes;
+  return {k.ev[2 * u], k.ev[2 * u + 1]};
+}
+
+// Add the timed launches to the per-class sums.  Launches of inner
+// iterations at or after kexec (the iterations the solve ran) returned at
+// once and are dropped.
+void kt_collect(expmv_plan_s* pl, int kexec) {
+  KernelTimer& k = pl->kt;
+  if (k.used == 0) return;
+  HIPCHK(hipEventSynchronize(k.ev[2 * (k.used - 1) + 1]));
+  for (int u = 0; u < k.used; ++u) {
+    if (k.iter[u] >= 0 && k.iter[u] >= kexec) continue;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, k.ev[2 * u], k.ev[2 * u + 1]));
+    k.ms[k.cls[u]] += ms;
+    k.by[k.cls[u]] += k.bytes[u];
+    k.cnt[k.cls[u]] += 1;
   }
-  pl->pev_used = 0;
+  k.used = 0;
+}
+
+// CSR bytes of an operator with `rows` rows and `nnz` nonzeros (int32
+// indices, FP64 values)
+inline double csr_bytes(int64_t rows, int64_t nnz) {
+  return 4.0 * double(rows + 1) + 12.0 * double(nnz);
 }
 
 struct InnerResult {
@@ -475,7 +587,7 @@ InnerResult run_inner_loop(expmv_plan_s* pl, int maxit, LaunchChunk&& launch_chu
     const int c = (launched == 0 && first_chunk > chunk) ? std::min(first_chunk, maxit) : chunk;
     launch_chunk(launched, c);
     launched += c;
-    HIPCHK(hipMemcpyAsync(pl->host_flags + 4 * slot, w.ctl.p, sizeof(KrylovCtl),
+    HIPCHK(hipMemcpyAsync(pl->host_flags + 4 * slot, w.ctl, sizeof(KrylovCtl),
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipEventRecord(pl->ev[slot], s));
     if (pending >= 0) {
@@ -514,26 +626,6 @@ const double* dinv_of<double>(const AmgDevLevel& L) { return L.dinv64; }
 template <>
 const float* dinv_of<float>(const AmgDevLevel& L) { return L.dinv32; }
 
-void amg_vectors(AmgDev& H, int p, size_t el) {
-  if (H.p == p && H.el == el) return;
-  for (size_t l = 0; l < H.lv.size(); ++l) {
-    AmgDevLevel& L = *H.lv[l];
-    const size_t bytes = size_t(L.n) * p * el;
-    if (l + 1 < H.lv.size()) {
-      L.vu.alloc(bytes);
-      L.vv.alloc(bytes);
-      L.vd.alloc(bytes);
-      L.vr.alloc(bytes);
-    }
-    if (l > 0) {
-      L.vb.alloc(bytes);
-      L.vo.alloc(bytes);
-    }
-  }
-  H.p = p;
-  H.el = el;
-}
-
 // out = V-cycle(b) on level l (level 0: the inner solver's launch shape,
 // and with part_rz the (b, out) partials of the last smoothing step).  The
 // kernels take VW columns per lane and PPL = PP / VW lanes per row; the finest
@@ -541,137 +633,152 @@ void amg_vectors(AmgDev& H, int p, size_t el) {
 // kernels over that many workgroups).
 template <typename T, int PP>
 void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
-               const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev);
+               const KrylovCtl* ctl, double* part_rz);
 
 template <typename T, int PPL, int VW>
 void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
-                  const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
+                  const KrylovCtl* ctl, double* part_rz) {
   constexpr int PP = PPL * VW;
   AmgDevLevel& L = *H.lv[l];
   hipStream_t s = pl->stream;
   const int n = int(L.n);
+  const bool fine = (l == 0);
+  // timing: class of this level's launches and the bytes of their operands
+  const double es = double(sizeof(T));
+  const double blk = es * double(n) * p;
+  auto csr = [&](int64_t rows, int64_t nnz) {
+    return 4.0 * double(rows + 1) + (4.0 + es) * double(nnz);
+  };
+  const int c_smooth = fine ? EXPMV_KT_AMG_SMOOTH : EXPMV_KT_AMG_COARSE;
+  const int c_restr = fine ? EXPMV_KT_AMG_RESTRICT : EXPMV_KT_AMG_COARSE;
+  const int c_prol = fine ? EXPMV_KT_AMG_PROLONG : EXPMV_KT_AMG_COARSE;
   if (l + 1 == int(H.lv.size())) {
     const int grid = std::max(1, std::min(n, 1024));
-    hipLaunchKernelGGL((k_amg_dense<T, PP>), dim3(grid), dim3(1024), 0, s, k, ctl, n, n, p,
-                       H.cinv.p, b, out);
+    const KtEv e = kt_take(pl, EXPMV_KT_AMG_COARSE, 8.0 * double(n) * n + 2 * blk);
+    hipExtLaunchKernelGGL((k_amg_dense<T, PP>), dim3(grid), dim3(1024), 0, s, e.e0, e.e1, 0, k,
+                          ctl, n, n, p, H.cinv.p, b, out);
     return;
   }
   const T* dinv = dinv_of<T>(L);
   const LevelVals<T> lv = vals_of(L, T());
-  const bool fine = (l == 0);
-  if (!fine && L.fused) {
-    AmgDevLevel& C = *H.lv[l + 1];
-    const int nc = int(C.n);
-    T* xc = reinterpret_cast<T*>(C.vo.p);
-    if (l + 2 == int(H.lv.size()) && H.cinvR.p) {
-      // xc = (Inv Rf) b: smoothing step, residual, restriction and coarsest solve
-      hipLaunchKernelGGL((k_amg_dense<T, PP>), dim3(std::max(1, std::min(nc, 1024))), dim3(1024),
-                         0, s, k, ctl, nc, n, p, H.cinvR.p, b, xc);
-    } else {
-      T* bc = reinterpret_cast<T*>(C.vb.p);
-      const int GR = row_split(L.avg_rf, PPL);
-      hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
-                         dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
-                         GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
-      amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+  AmgDevLevel& C = *H.lv[l + 1];
+  const int nc = int(C.n);
+  const double cblk = es * double(nc) * p;
+  // restriction of b by a fused operator Rf (sparse), or Inv Rf (dense) into
+  // the coarsest level
+  auto restrict_fused = [&](T* bc, T* xc, bool dense) {
+    if (dense) {
+      const KtEv e = kt_take(pl, c_restr, 8.0 * double(nc) * n + blk + cblk);
+      hipExtLaunchKernelGGL((k_amg_dense<T, PP>), dim3(std::max(1, std::min(nc, 1024))),
+                            dim3(1024), 0, s, e.e0, e.e1, 0, k, ctl, nc, n, p, H.cinvR.p, b, xc);
+      return;
     }
+    const int GR = row_split(L.avg_rf, PPL);
+    const KtEv e = kt_take(pl, c_restr, csr(nc, L.nnz_rf) + blk + cblk);
+    hipExtLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
+                          dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, e.e0, e.e1, 0,
+                          k, ctl, nc, p, GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
+    amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr);
+  };
+  // prolongation plus the post-smoothing step in one pass (fused levels)
+  const double pair_bytes = csr(n, L.nnz_a) + es * n + blk + csr(n, L.nnz_pf) + cblk + blk;
+  if (!fine && L.fused) {
+    T* xc = reinterpret_cast<T*>(C.vo);
+    restrict_fused(reinterpret_cast<T*>(C.vb), xc, l + 2 == int(H.lv.size()) && H.cinvR.p);
     const int G = std::max(row_split(L.avg_a, PPL), row_split(L.avg_pf, PPL));
-    hipLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
-                       dim3(grid_for(n, PPL * G, 4096)), dim3(kThreads), 0, s, k, ctl, n, p, G,
-                       L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf, xc, L.alpha,
-                       L.beta, out);
+    const KtEv e = kt_take(pl, c_prol, pair_bytes);
+    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
+                          dim3(grid_for(n, PPL * G, 4096)), dim3(kThreads), 0, s, e.e0, e.e1, 0,
+                          k, ctl, n, p, G, L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf,
+                          xc, L.alpha, L.beta, out);
     return;
   }
   const int gfine = cg_grid(n, PP);
   const int GA = row_split(L.avg_a, PPL), GP = row_split(L.avg_p, PPL);
   const int gcoarse_a = grid_for(n, PPL * GA, 4096), gcoarse_p = grid_for(n, PPL * GP, 4096);
+  // one smoothing step: reads A, D^{-1}, b and the iterate (unless it is the
+  // implicit first one), the direction when HasD; writes the output and the
+  // direction when WriteD (the residual step writes r only)
   auto step = [&](int mode, const T* x, T* o, double cd, double ad, double* part) {
-    T* d = reinterpret_cast<T*>(L.vd.p);
-    if (fine) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (sev && *nsev < kSmoothEv / 2) {
-        e0 = sev[2 * *nsev];
-        e1 = sev[2 * *nsev + 1];
-        *nsev += 1;
-      }
+    T* d = reinterpret_cast<T*>(L.vd);
+    double bytes = csr(n, L.nnz_a) + es * n + 2 * blk;   // A, D^{-1}, b, output
+    if (!(mode & kAmgX0)) bytes += blk;
+    if (mode & kAmgHasD) bytes += blk;
+    if (mode & kAmgWriteD) bytes += blk;
+    const KtEv e = kt_take(pl, c_smooth, bytes);
+    if (fine)
       hipExtLaunchKernelGGL((k_amg_step<T, PPL, VW, kCgThreads, true>), dim3(gfine),
-                            dim3(kCgThreads), 0, s, e0, e1, 0, k, ctl, n, p, GA, L.arp, L.aci,
+                            dim3(kCgThreads), 0, s, e.e0, e.e1, 0, k, ctl, n, p, GA, L.arp, L.aci,
                             lv.a, dinv, b, x, d, o, L.ad[0], cd, ad, mode, part);
-    } else
-      hipLaunchKernelGGL((k_amg_step<T, PPL, VW, kThreads, false>), dim3(gcoarse_a),
-                         dim3(kThreads), 0, s, k, ctl, n, p, GA, L.arp, L.aci, lv.a, dinv, b, x,
-                         d, o, L.ad[0], cd, ad, mode, part);
+    else
+      hipExtLaunchKernelGGL((k_amg_step<T, PPL, VW, kThreads, false>), dim3(gcoarse_a),
+                            dim3(kThreads), 0, s, e.e0, e.e1, 0, k, ctl, n, p, GA, L.arp, L.aci,
+                            lv.a, dinv, b, x, d, o, L.ad[0], cd, ad, mode, part);
   };
-  T* x = reinterpret_cast<T*>(L.vu.p);
-  T* y = reinterpret_cast<T*>(L.vv.p);
+  T* x = reinterpret_cast<T*>(L.vu);
+  T* y = reinterpret_cast<T*>(L.vv);
   if (fine && L.fused && L.degree == 1 && part_rz == nullptr && sizeof(T) == 8) {
     // one step (nonsymmetric K): Rf b, the coarse correction, then the
     // prolongation and the post-smoothing step in one pass (FP64 V-cycles:
     // in FP32 the unfused launches measured faster, 4.45 against 4.77 s on
     // the 128^3 convection-diffusion workload)
-    AmgDevLevel& C = *H.lv[l + 1];
-    const int nc = int(C.n);
-    T* bc = reinterpret_cast<T*>(C.vb.p);
-    T* xc = reinterpret_cast<T*>(C.vo.p);
-    const int GR = row_split(L.avg_rf, PPL);
-    hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
-                       dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
-                       GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
-    amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
+    T* xc = reinterpret_cast<T*>(C.vo);
+    restrict_fused(reinterpret_cast<T*>(C.vb), xc, false);
     const int G = std::max(GA, row_split(L.avg_pf, PPL));
-    hipLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kCgThreads, true>), dim3(gfine),
-                       dim3(kCgThreads), 0, s, k, ctl, n, p, G, L.arp, L.aci, lv.a, dinv, b,
-                       L.Pfrp.p, L.Pfci.p, lv.pf, xc, L.alpha, L.beta, out);
+    const KtEv e = kt_take(pl, c_prol, pair_bytes);
+    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kCgThreads, true>), dim3(gfine),
+                          dim3(kCgThreads), 0, s, e.e0, e.e1, 0, k, ctl, n, p, G, L.arp, L.aci,
+                          lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf, xc, L.alpha, L.beta, out);
     return;
   }
   if (fine && L.fused && L.degree == 2) {
-    // bc = Rf b, the coarse correction, then x = x1 + P xc
-    AmgDevLevel& C = *H.lv[l + 1];
-    const int nc = int(C.n);
-    T* bc = reinterpret_cast<T*>(C.vb.p);
-    T* xc = reinterpret_cast<T*>(C.vo.p);
-    const int GR = row_split(L.avg_rf, PPL);
-    hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
-                       dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
-                       GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
-    amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
-    hipLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kCgThreads, true>), dim3(gfine),
-                       dim3(kCgThreads), 0, s, k, ctl, n, p, std::max(GA, GP), L.arp, L.aci,
-                       lv.a, dinv, b, L.Prp.p, L.Pci.p, lv.p, xc, L.alpha, L.beta, x);
+    // bc = Rf b, the coarse correction, then x = x1 + P xc (x1, the
+    // pre-smoothed iterate, recomputed from b)
+    T* xc = reinterpret_cast<T*>(C.vo);
+    restrict_fused(reinterpret_cast<T*>(C.vb), xc, false);
+    const KtEv e = kt_take(pl, c_prol, csr(n, L.nnz_a) + es * n + blk + csr(n, L.nnz_p) + cblk +
+                                           blk);
+    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kCgThreads, true>), dim3(gfine),
+                          dim3(kCgThreads), 0, s, e.e0, e.e1, 0, k, ctl, n, p, std::max(GA, GP),
+                          L.arp, L.aci, lv.a, dinv, b, L.Prp.p, L.Pci.p, lv.p, xc, L.alpha, L.beta,
+                          x);
   } else {
-  // pre-smoothing from zero: the first step's iterate s0 D^{-1} b stays implicit
-  bool implicit = true;
-  for (int st = 1; st < L.degree; ++st) {
-    step(kAmgHasD | kAmgWriteD | (implicit ? kAmgX0 : 0), x, y, L.cd[st], L.ad[st], nullptr);
-    implicit = false;
-    std::swap(x, y);
-  }
-  T* r = reinterpret_cast<T*>(L.vr.p);
-  step(kAmgResid | (implicit ? kAmgX0 : 0), x, r, 0.0, 0.0, nullptr);
-  AmgDevLevel& C = *H.lv[l + 1];
-  T* bc = reinterpret_cast<T*>(C.vb.p);
-  const int nc = int(C.n);
-  T* xc = reinterpret_cast<T*>(C.vo.p);
-  if (l + 2 == int(H.lv.size()) && H.cinvR.p) {
-    // coarsest correction in one dense product: xc = (Inv R) r
-    hipLaunchKernelGGL((k_amg_dense<T, PP>), dim3(std::max(1, std::min(nc, 1024))), dim3(1024),
-                       0, s, k, ctl, nc, n, p, H.cinvR.p, r, xc);
-  } else {
-    const int GR = row_split(L.avg_r, PPL);
-    hipLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
-                       dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, k, ctl, nc, p,
-                       GR, L.Rrp.p, L.Rci.p, lv.r, r, bc);
-    amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr, nullptr, nullptr);
-  }
-  const int pmode = implicit ? kAmgX0 : 0;
-  if (fine)
-    hipLaunchKernelGGL((k_amg_prolong<T, PPL, VW, kCgThreads, true>), dim3(gfine),
-                       dim3(kCgThreads), 0, s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv,
-                       b, L.ad[0], pmode, x);
-  else
-    hipLaunchKernelGGL((k_amg_prolong<T, PPL, VW, kThreads, false>), dim3(gcoarse_p),
-                       dim3(kThreads), 0, s, k, ctl, n, p, GP, L.Prp.p, L.Pci.p, lv.p, xc, dinv,
-                       b, L.ad[0], pmode, x);
+    // pre-smoothing from zero: the first step's iterate s0 D^{-1} b stays implicit
+    bool implicit = true;
+    for (int st = 1; st < L.degree; ++st) {
+      step(kAmgHasD | kAmgWriteD | (implicit ? kAmgX0 : 0), x, y, L.cd[st], L.ad[st], nullptr);
+      implicit = false;
+      std::swap(x, y);
+    }
+    T* r = reinterpret_cast<T*>(L.vr);
+    step(kAmgResid | (implicit ? kAmgX0 : 0), x, r, 0.0, 0.0, nullptr);
+    T* bc = reinterpret_cast<T*>(C.vb);
+    T* xc = reinterpret_cast<T*>(C.vo);
+    if (l + 2 == int(H.lv.size()) && H.cinvR.p) {
+      // coarsest correction in one dense product: xc = (Inv R) r
+      const KtEv e = kt_take(pl, c_restr, 8.0 * double(nc) * n + blk + cblk);
+      hipExtLaunchKernelGGL((k_amg_dense<T, PP>), dim3(std::max(1, std::min(nc, 1024))),
+                            dim3(1024), 0, s, e.e0, e.e1, 0, k, ctl, nc, n, p, H.cinvR.p, r, xc);
+    } else {
+      const int GR = row_split(L.avg_r, PPL);
+      const KtEv e = kt_take(pl, c_restr, csr(nc, L.nnz_r) + blk + cblk);
+      hipExtLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
+                            dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, e.e0, e.e1,
+                            0, k, ctl, nc, p, GR, L.Rrp.p, L.Rci.p, lv.r, r, bc);
+      amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr);
+    }
+    const int pmode = implicit ? kAmgX0 : 0;
+    // x (+)= P xc (with the implicit iterate from b and D^{-1} when pmode)
+    const double pb = csr(n, L.nnz_p) + cblk + blk + (implicit ? es * n + blk : blk);
+    const KtEv e = kt_take(pl, c_prol, pb);
+    if (fine)
+      hipExtLaunchKernelGGL((k_amg_prolong<T, PPL, VW, kCgThreads, true>), dim3(gfine),
+                            dim3(kCgThreads), 0, s, e.e0, e.e1, 0, k, ctl, n, p, GP, L.Prp.p,
+                            L.Pci.p, lv.p, xc, dinv, b, L.ad[0], pmode, x);
+    else
+      hipExtLaunchKernelGGL((k_amg_prolong<T, PPL, VW, kThreads, false>), dim3(gcoarse_p),
+                            dim3(kThreads), 0, s, e.e0, e.e1, 0, k, ctl, n, p, GP, L.Prp.p,
+                            L.Pci.p, lv.p, xc, dinv, b, L.ad[0], pmode, x);
   }
   // post-smoothing from x, the same polynomial (symmetric V-cycle)
   for (int st = 0; st < L.degree; ++st) {
@@ -689,26 +796,26 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
 // rows: 0.7% on the 64^3 benchmark); each level picks its own layout
 template <typename T, int PP>
 void amg_level(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out, int k,
-               const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev, int* nsev) {
+               const KrylovCtl* ctl, double* part_rz) {
   if constexpr (kWide8<T, PP>) {
     if (p % 8 == 0) {
-      amg_level_vw<T, PP / 8, 8>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
+      amg_level_vw<T, PP / 8, 8>(pl, H, l, p, b, out, k, ctl, part_rz);
       return;
     }
   }
   if constexpr (PP >= 4) {
     if (p % 4 == 0 && (kWide4<T, PP> || l > 0)) {
-      amg_level_vw<T, PP / 4, 4>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
+      amg_level_vw<T, PP / 4, 4>(pl, H, l, p, b, out, k, ctl, part_rz);
       return;
     }
   }
   if constexpr (PP >= 2) {
     if (p % 2 == 0) {
-      amg_level_vw<T, PP / 2, 2>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
+      amg_level_vw<T, PP / 2, 2>(pl, H, l, p, b, out, k, ctl, part_rz);
       return;
     }
   }
-  amg_level_vw<T, PP, 1>(pl, H, l, p, b, out, k, ctl, part_rz, sev, nsev);
+  amg_level_vw<T, PP, 1>(pl, H, l, p, b, out, k, ctl, part_rz);
 }
 
 // The hierarchy for K (transpose = 0) or K^T; NULL without AMG.
@@ -717,15 +824,12 @@ AmgDev* amg_for(expmv_plan_s* pl, int transpose) {
   return pl->amg.get();
 }
 
-// One V-cycle of hierarchy H; sev (may be NULL) receives start/stop events
-// of the finest level's smoothing-step launches, *nsev their number.
+// One V-cycle of hierarchy H.
 template <typename T>
 void amg_vcycle(expmv_plan_s* pl, AmgDev& H, int p, const T* b, T* out, int k,
-                const KrylovCtl* ctl, double* part_rz, hipEvent_t* sev = nullptr,
-                int* nsev = nullptr) {
-  amg_vectors(H, p, sizeof(T));
+                const KrylovCtl* ctl, double* part_rz) {
   const int PP = pow2_lanes(p);
-  DISPATCH_PP(PP, amg_level<T, P_>(pl, H, 0, p, b, out, k, ctl, part_rz, sev, nsev));
+  DISPATCH_PP(PP, amg_level<T, P_>(pl, H, 0, p, b, out, k, ctl, part_rz));
 }
 
 // out = K^{-1} (sign * src) by batched Jacobi-PCG (K SPD); out is the iterate.
@@ -740,71 +844,74 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
   const double tol2 = tol * tol;
   const int maxit = pl->opts.inner_maxit;
   Csr<T> A = csr_of<T>(pl, 0);
-  T* r = reinterpret_cast<T*>(w.kr.p);
-  T* q = reinterpret_cast<T*>(w.kq.p);
-  T* P[2] = {reinterpret_cast<T*>(w.kpa.p), reinterpret_cast<T*>(w.kpb.p)};
+  T* r = reinterpret_cast<T*>(w.kr);
+  T* q = reinterpret_cast<T*>(w.kq);
+  T* P[2] = {reinterpret_cast<T*>(w.kpa), reinterpret_cast<T*>(w.kpb)};
   AmgDev* H = amg_for(pl, 0);
   const bool amg = H != nullptr;
-  T* z = amg ? reinterpret_cast<T*>(w.kz.p) : nullptr;
+  T* z = amg ? reinterpret_cast<T*>(w.kz) : nullptr;
   // FP32 V-cycle under the FP64 CG (opts.amg_fp32): k_cg_init / k_cg_b write an
   // FP32 copy of r, the V-cycle maps it to an FP32 z that k_cg_c reads
   const bool v32 = amg && !std::is_same<T, float>::value && pl->opts.amg_fp32 != 0;
   float* r32 = nullptr;
   float* z32 = nullptr;
   if (v32) {
-    w.kr32.alloc(size_t(n) * p);
-    w.kz32.alloc(size_t(n) * p);
-    r32 = w.kr32.p;
-    z32 = w.kz32.p;
+    r32 = w.kr32;
+    z32 = w.kz32;
   }
   DISPATCH_CG(PP, p, hipLaunchKernelGGL((k_cg_init<T, T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                     int(n), p, sign, src, A.dinv, out, r, P[0], w.ctl.p,
-                                     w.part_rr.p, r32));
-  auto vcycle = [&](int k, hipEvent_t* sev, int* nsev) {
+                                     int(n), p, sign, src, A.dinv, out, r, P[0], w.ctl,
+                                     w.part_rr, r32));
+  auto vcycle = [&](int k) {
     if (v32)
-      amg_vcycle<float>(pl, *H, p, r32, z32, k, w.ctl.p, w.part_rr.p, sev, nsev);
+      amg_vcycle<float>(pl, *H, p, r32, z32, k, w.ctl, w.part_rr);
     else
-      amg_vcycle<T>(pl, *H, p, r, z, k, w.ctl.p, w.part_rr.p, sev, nsev);
+      amg_vcycle<T>(pl, *H, p, r, z, k, w.ctl, w.part_rr);
   };
-  if (amg) vcycle(0, nullptr, nullptr);
+  if (amg) vcycle(0);
+  // timed bytes per launch: A q = K p (CSR, p gathered, q written);
+  // B r -= alpha q (+ D^{-1} for Jacobi's (r, D^{-1} r), + the FP32 copy of r);
+  // C x += alpha p_old, p_new = z + beta p_old (z = D^{-1} r for Jacobi)
+  const double es = double(sizeof(T)), blk = es * double(n) * p;
+  const double by_a = csr_bytes(n, pl->nnz) + 2 * blk;
+  const double by_b = 3 * blk + (amg ? 0.0 : es * n) + (v32 ? 4.0 * n * p : 0.0);
+  const double by_c = 4 * blk + (amg ? (v32 ? 4.0 : es) * n * p : es * n + blk);
+  KernelTimer& kt = pl->kt;
   InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
     for (int it = 0; it < chunk; ++it) {
       const int k = launched + it;
       T* pold = P[k & 1];
       T* pnew = P[(k + 1) & 1];
-      const bool sample = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0 &&
-                          pl->pev_used < int(pl->pev_iter.size());
-      hipEvent_t* e = sample ? &pl->pev[size_t(pl->pev_used) * kSampleEv] : nullptr;
-      int* nsm = sample ? &pl->pev_nsm[pl->pev_used] : nullptr;
-      hipEvent_t ez = nullptr;
-      if (sample) {
-        pl->pev_iter[pl->pev_used] = k;
-        *nsm = 0;
-        pl->pev_used += 1;
-      }
+      kt.cur_iter = k;
+      kt.sampling = pl->opts.profile > 0 && ((k + 1) % pl->opts.profile) == 0;
+      const KtEv ec = kt_take(pl, EXPMV_KT_CG_DIR, by_c);
       if (v32) {
-        DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_c<T, float, PPL_, VW_>), dim3(grid), dim3(kCgThreads),
-                                              0, s, sample ? e[0] : ez, sample ? e[1] : ez, 0, k,
-                                              int(n), p, A.dinv, r, z32, pold, pnew, out, w.cgst.p,
-                                              w.ctl.p, w.part_rr.p, tol2, maxit));
+        DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_c<T, float, PPL_, VW_>), dim3(grid),
+                                                 dim3(kCgThreads), 0, s, ec.e0, ec.e1, 0, k,
+                                                 int(n), p, A.dinv, r, z32, pold, pnew, out,
+                                                 w.cgst, w.ctl, w.part_rr, tol2, maxit));
       } else {
-        DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_c<T, T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0,
-                                              s, sample ? e[0] : ez, sample ? e[1] : ez, 0, k,
-                                              int(n), p, A.dinv, r, z, pold, pnew, out, w.cgst.p,
-                                              w.ctl.p, w.part_rr.p, tol2, maxit));
+        DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_c<T, T, PPL_, VW_>), dim3(grid),
+                                                 dim3(kCgThreads), 0, s, ec.e0, ec.e1, 0, k,
+                                                 int(n), p, A.dinv, r, z, pold, pnew, out,
+                                                 w.cgst, w.ctl, w.part_rr, tol2, maxit));
       }
-      DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_a<T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[2] : ez, sample ? e[3] : ez, 0, k, int(n),
-                                            p, A.rowptr, A.colind, A.val, pnew, q, w.ctl.p,
-                                            w.part_sig.p));
-      DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_b<T, PPL_, VW_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                            sample ? e[4] : ez, sample ? e[5] : ez, 0, k, int(n),
-                                            p, A.dinv, r, q, w.cgst.p, w.ctl.p, w.part_sig.p,
-                                            w.part_rr.p, amg ? 0 : 1, r32));
-      if (amg) vcycle(k, sample ? e + 6 : nullptr, nsm);
+      const KtEv ea = kt_take(pl, EXPMV_KT_CG_SPMM, by_a);
+      DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_a<T, PPL_, VW_>), dim3(grid),
+                                               dim3(kCgThreads), 0, s, ea.e0, ea.e1, 0, k, int(n),
+                                               p, A.rowptr, A.colind, A.val, pnew, q, w.ctl,
+                                               w.part_sig));
+      const KtEv eb = kt_take(pl, EXPMV_KT_CG_RESID, by_b);
+      DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_b<T, PPL_, VW_>), dim3(grid),
+                                               dim3(kCgThreads), 0, s, eb.e0, eb.e1, 0, k, int(n),
+                                               p, A.dinv, r, q, w.cgst, w.ctl, w.part_sig,
+                                               w.part_rr, amg ? 0 : 1, r32));
+      if (amg) vcycle(k);
     }
+    kt.cur_iter = -1;
+    kt.sampling = false;
   }, amg ? 1 : 16, amg ? pl->last_inner_iters - 2 : 0);
-  collect_profile(pl, res.iters);
+  kt_collect(pl, res.iters);
   pl->last_inner_iters = res.iters;
   return res;
 }
@@ -812,32 +919,32 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
 // BiCGStab's SpMM (k_bcg_s) with two adjacent columns per lane for even p
 // (four when p is a multiple of 4 and kWide4)
 template <typename T, int PP, int NV>
-void bcg_spmm(hipStream_t s, int grid, int i, int n, int p, const int32_t* rowptr,
+void bcg_spmm(hipStream_t s, KtEv e, int grid, int i, int n, int p, const int32_t* rowptr,
               const int32_t* colind, const double* val, const T* dinv, const T* in, const T* a,
               T* out, const KrylovCtl* ctl, double* part) {
   if constexpr (kWide8<T, PP>) {
     if (p % 8 == 0) {
-      hipLaunchKernelGGL((k_bcg_s<T, PP / 8, 8, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,
-                         rowptr, colind, val, dinv, in, a, out, ctl, part);
+      hipExtLaunchKernelGGL((k_bcg_s<T, PP / 8, 8, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0,
+                            e.e1, 0, i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
       return;
     }
   }
   if constexpr (kWide4<T, PP>) {
     if (p % 4 == 0) {
-      hipLaunchKernelGGL((k_bcg_s<T, PP / 4, 4, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,
-                         rowptr, colind, val, dinv, in, a, out, ctl, part);
+      hipExtLaunchKernelGGL((k_bcg_s<T, PP / 4, 4, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0,
+                            e.e1, 0, i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
       return;
     }
   }
   if constexpr (PP >= 2) {
     if (p % 2 == 0) {
-      hipLaunchKernelGGL((k_bcg_s<T, PP / 2, 2, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p,
-                         rowptr, colind, val, dinv, in, a, out, ctl, part);
+      hipExtLaunchKernelGGL((k_bcg_s<T, PP / 2, 2, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0,
+                            e.e1, 0, i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
       return;
     }
   }
-  hipLaunchKernelGGL((k_bcg_s<T, PP, 1, NV>), dim3(grid), dim3(kCgThreads), 0, s, i, n, p, rowptr,
-                     colind, val, dinv, in, a, out, ctl, part);
+  hipExtLaunchKernelGGL((k_bcg_s<T, PP, 1, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0, e.e1, 0,
+                        i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
 }
 
 // out = K^{-1} (sign * src) (or K^{-T}) by batched BiCGStab with right
@@ -854,39 +961,55 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
   const double tol2 = tol * tol;
   const int maxit = pl->opts.inner_maxit;
   Csr<T> A = csr_of<T>(pl, transpose);
-  T* r = reinterpret_cast<T*>(w.kr.p);
-  T* pv = reinterpret_cast<T*>(w.kpa.p);
-  T* v = reinterpret_cast<T*>(w.kv.p);
-  T* sv = reinterpret_cast<T*>(w.ks.p);
-  T* tv = reinterpret_cast<T*>(w.kt.p);
-  T* rh = reinterpret_cast<T*>(w.krh.p);
+  T* r = reinterpret_cast<T*>(w.kr);
+  T* pv = reinterpret_cast<T*>(w.kpa);
+  T* v = reinterpret_cast<T*>(w.kv);
+  T* sv = reinterpret_cast<T*>(w.ks);
+  T* tv = reinterpret_cast<T*>(w.kt);
+  T* rh = reinterpret_cast<T*>(w.krh);
   AmgDev* H = amg_for(pl, transpose);
-  T* ph = H ? reinterpret_cast<T*>(w.kph.p) : nullptr;   // M^{-1} p
-  T* sh = H ? reinterpret_cast<T*>(w.ksh.p) : nullptr;   // M^{-1} s
+  T* ph = H ? reinterpret_cast<T*>(w.kph) : nullptr;   // M^{-1} p
+  T* sh = H ? reinterpret_cast<T*>(w.ksh) : nullptr;   // M^{-1} s
   const T* dscale = H ? nullptr : A.dinv;
   DISPATCH_PP(PP, hipLaunchKernelGGL((k_bcg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                     int(n), p, sign, src, out, r, rh, pv, v, w.ctl.p,
-                                     w.part_rr.p));
+                                     int(n), p, sign, src, out, r, rh, pv, v, w.ctl,
+                                     w.part_rr));
+  // timed bytes per launch: each SpMM reads K (CSR), its input (gathered)
+  // and the vector its partials pair with, and writes its output (+ D^{-1}
+  // for Jacobi); u1 reads r, p, v and writes p; u2 reads r, v, writes s; u3
+  // reads p^, s^ (or p, s and D^{-1}), s, t, r~ and x, writes x and r
+  const double es = double(sizeof(T)), blk = es * double(n) * p;
+  const double by_s = csr_bytes(n, pl->nnz) + 3 * blk + (H ? 0.0 : es * n);
+  const double by_u3 = 8 * blk + (H ? 0.0 : es * n);
+  KernelTimer& kt = pl->kt;
   InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
     for (int it = 0; it < chunk; ++it) {
       const int i = launched + it;
+      kt.cur_iter = i;
+      kt.sampling = pl->opts.profile > 0 && ((i + 1) % pl->opts.profile) == 0;
       DISPATCH_PP(PP, {
-        hipLaunchKernelGGL((k_bcg_u1<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
-                           r, pv, v, w.bcgst.p, w.ctl.p, w.part_rr.p, tol2, maxit);
-        if (H) amg_vcycle<T>(pl, *H, p, pv, ph, i, w.ctl.p, nullptr);
-        bcg_spmm<T, P_, 1>(s, grid, i, int(n), p, A.rowptr, A.colind, A.val, dscale, H ? ph : pv,
-                           rh, v, w.ctl.p, w.part_sig.p);
-        hipLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p, r,
-                           v, sv, w.bcgst.p, w.ctl.p, w.part_sig.p);
-        if (H) amg_vcycle<T>(pl, *H, p, sv, sh, i, w.ctl.p, nullptr);
-        bcg_spmm<T, P_, 2>(s, grid, i, int(n), p, A.rowptr, A.colind, A.val, dscale, H ? sh : sv,
-                           sv, tv, w.ctl.p, w.part_sig.p);
-        hipLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, i, int(n), p,
-                           A.dinv, pv, sv, tv, rh, ph, sh, out, r, w.bcgst.p, w.ctl.p,
-                           w.part_sig.p, w.part_rr.p);
+        const KtEv e1 = kt_take(pl, EXPMV_KT_BCG_U1, 4 * blk);
+        hipExtLaunchKernelGGL((k_bcg_u1<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, e1.e0, e1.e1,
+                              0, i, int(n), p, r, pv, v, w.bcgst, w.ctl, w.part_rr, tol2, maxit);
+        if (H) amg_vcycle<T>(pl, *H, p, pv, ph, i, w.ctl, nullptr);
+        bcg_spmm<T, P_, 1>(s, kt_take(pl, EXPMV_KT_BCG_SPMM1, by_s), grid, i, int(n), p, A.rowptr,
+                           A.colind, A.val, dscale, H ? ph : pv, rh, v, w.ctl, w.part_sig);
+        const KtEv e2 = kt_take(pl, EXPMV_KT_BCG_U2, 3 * blk);
+        hipExtLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, e2.e0, e2.e1,
+                              0, i, int(n), p, r, v, sv, w.bcgst, w.ctl, w.part_sig);
+        if (H) amg_vcycle<T>(pl, *H, p, sv, sh, i, w.ctl, nullptr);
+        bcg_spmm<T, P_, 2>(s, kt_take(pl, EXPMV_KT_BCG_SPMM2, by_s), grid, i, int(n), p, A.rowptr,
+                           A.colind, A.val, dscale, H ? sh : sv, sv, tv, w.ctl, w.part_sig);
+        const KtEv e3 = kt_take(pl, EXPMV_KT_BCG_U3, by_u3);
+        hipExtLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, e3.e0, e3.e1,
+                              0, i, int(n), p, A.dinv, pv, sv, tv, rh, ph, sh, out, r, w.bcgst,
+                              w.ctl, w.part_sig, w.part_rr);
       });
     }
+    kt.cur_iter = -1;
+    kt.sampling = false;
   }, H ? 1 : 16, H ? pl->last_inner_iters - 2 : 0);
+  kt_collect(pl, res.iters);
   pl->last_inner_iters = res.iters;
   return res;
 }
@@ -960,10 +1083,9 @@ void fft(expmv_plan_s* pl, const cplx* in, cplx* out, cplx* tmp, int q, double s
   fft_len(pl, pl->L, pl->radices, in, out, tmp, q, sign);
 }
 
-void ensure_fft_buffers(expmv_plan_s* pl, int q) {
-  if (pl->fq >= q) return;
-  for (auto& b : pl->fb) b.alloc(size_t(pl->L) * q);
-  pl->fq = q;
+// the call's FFT work arrays must hold q complex columns
+void check_fft_buffers(expmv_plan_s* pl, int q) {
+  if (q > pl->ws.fq) throw StatusError{EXPMV_EINVAL};
 }
 
 // Y (n x p, ld) (+)= scale * (K / t) X through the circulant embedding, K / t
@@ -974,9 +1096,9 @@ void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy
   const cplx* sym = (transpose && !pl->tsym) ? pl->chatT.p : pl->chat.p;
   const double* dg = with_diag ? pl->tdiag.p : nullptr;
   const int q = (p + 1) / 2;
-  ensure_fft_buffers(pl, q);
+  check_fft_buffers(pl, q);
   const int64_t L = pl->L, n = pl->n;
-  cplx *A = pl->fb[0].p, *Bf = pl->fb[1].p, *C = pl->fb[2].p;
+  cplx *A = pl->ws.fb[0], *Bf = pl->ws.fb[1], *C = pl->ws.fb[2];
   hipStream_t s = pl->stream;
   hipLaunchKernelGGL((k_pack<T>), dim3(stream_grid(L * q)), dim3(kThreads), 0, s, n, p, ldx, q, L,
                      X, A, 0, 1.0, transpose ? dg : nullptr);
@@ -1010,9 +1132,9 @@ void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, doub
   const cplx* b1 = tr ? gjy : gx;
   const cplx* b2 = tr ? gzjx : gzy;
   const int q = (p + 1) / 2;
-  ensure_fft_buffers(pl, q);
+  check_fft_buffers(pl, q);
   const int64_t L = pl->L, n = pl->n;
-  cplx *A = pl->fb[0].p, *Bf = pl->fb[1].p, *C = pl->fb[2].p, *D = pl->fb[3].p;
+  cplx *A = pl->ws.fb[0], *Bf = pl->ws.fb[1], *C = pl->ws.fb[2], *D = pl->ws.fb[3];
   hipStream_t s = pl->stream;
   const int g = stream_grid(L * q);
   const double inv = 1.0 / double(L);
@@ -1033,12 +1155,20 @@ void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, doub
                      int64_t(p), q, A, W, 0, scale / pl->x0, 0, transpose ? di : nullptr);
 }
 
+// zero `bytes` bytes (a multiple of 4) of device memory on the plan's stream
+void zero_device(expmv_plan_s* pl, void* ptr, size_t bytes) {
+  const int64_t words = int64_t(bytes / 4);
+  const int grid = int(std::max<int64_t>(1, std::min<int64_t>(2048, (words + kThreads - 1) / kThreads)));
+  hipLaunchKernelGGL(k_zero32, dim3(grid), dim3(kThreads), 0, pl->stream, words,
+                     reinterpret_cast<uint32_t*>(ptr));
+}
+
 double device_dot(expmv_plan_s* pl, int64_t len, const double* x, const double* y) {
   const int grid = 256;
   hipLaunchKernelGGL(k_dot_partial, dim3(grid), dim3(kThreads), 0, pl->stream, len, x, y,
-                     pl->ws.partial.p);
+                     pl->ws.partial);
   std::vector<double> part(grid);
-  HIPCHK(hipMemcpyAsync(part.data(), pl->ws.partial.p, sizeof(double) * grid,
+  HIPCHK(hipMemcpyAsync(part.data(), pl->ws.partial, sizeof(double) * grid,
                         hipMemcpyDeviceToHost, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
   double acc = 0.0;
@@ -1091,17 +1221,17 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
     const int NB = (p + 15) / 16;
     const int MBW = nmb <= 8 ? 2 : (nmb <= 16 ? 4 : 6);
     const bool upd = (mode == kUpdProj || mode == kUpdGram);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (pl->opts.profile > 0 && !gate && pl->oev_used + 2 <= int(pl->oev.size())) {
-      e0 = pl->oev[pl->oev_used];
-      e1 = pl->oev[pl->oev_used + 1];
-      pl->oev_used += 2;
+    // timed bytes: the panels of V used and W read once, W' written (all
+    // modes but the projection); the conditional third pass is not timed
+    KtEv ev;
+    if (!gate) {
       const double el = double(sizeof(T)) * double(pl->n) * p;
-      pl->oev_bytes.push_back(el * (mode == kProj ? npv + 1 : (upd ? npv + 2 : 2)));
+      ev = kt_take(pl, EXPMV_KT_ORTH, el * (mode == kProj ? npv + 1 : (upd ? npv + 2 : 2)));
     }
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
 #define ORTH_MMA(NB_, MBW_)                                                                     \
   hipExtLaunchKernelGGL((k_orth_mma<T, NB_, MBW_>), dim3(grid), dim3(kThreads), 0, pl->stream,     \
-                        e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C, pl->ws.partial.p, gate)
+                        e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C, pl->ws.partial, gate)
     if (NB == 1) {
       if (MBW == 2) ORTH_MMA(1, 2);
       else if (MBW == 4) ORTH_MMA(1, 4);
@@ -1118,7 +1248,7 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
   HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth<T>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(L.lds)));
   hipLaunchKernelGGL(k_orth<T>, dim3(L.nwg), dim3(kThreads), L.lds, pl->stream, mode, pl->n, p, V,
-                     npv, Win, Wout, C, pl->ws.partial.p, L.TR, L.rows_per_wg, gate);
+                     npv, Win, Wout, C, pl->ws.partial, L.TR, L.rows_per_wg, gate);
   return (proj || gram) ? L.nwg : 0;
 }
 
@@ -1126,7 +1256,59 @@ void reduce_partials(expmv_plan_s* pl, int nwg, int O, double* out, double* H, i
                      int p, int O_h) {
   const int grid = (O + kRedOut - 1) / kRedOut;
   hipLaunchKernelGGL(k_reduce_partials, dim3(grid), dim3(kRedOut * kRedLanes), 0, pl->stream,
-                     pl->ws.partial.p, nwg, O, out, H, ldh, col0, p, O_h);
+                     pl->ws.partial, nwg, O, out, H, ldh, col0, p, O_h);
+}
+
+// FP64 true residuals R_j = B - (M - tau_j I) X_j of the 7 shifted systems of
+// one time block (X block Xq, poles tau_re/tau_im), their coordinates
+// S_j = V_last^T R_j on the block that follows the basis (written to S,
+// p x p complex each: the refined restart right-hand sides), and the norms
+// res[j] = ||R_j||_F, rem[j] = ||R_j - V_last S_j||_F.  Algorithm 2, Step 4
+// with the residual of eq. 4.8 recomputed from X_j.
+template <typename T>
+void shift_residuals(expmv_plan_s* pl, int transpose, const double* B, int p, const double* Xq,
+                     int ldx, const double* tau_re, const double* tau_im, const T* Vlast, cplx* S,
+                     double* res, double* rem) {
+  Workspace& w = pl->ws;
+  hipStream_t s = pl->stream;
+  const int64_t n = pl->n;
+  const int W = 2 * kNShift * p;
+  double* R = w.Rres;
+  const int PP = pow2_lanes(p);
+  const int g1 = grid_for(n, PP, 512);
+  double* part1 = w.rpart;                     // g1 x 7
+  double* part3 = w.rpart + 512 * kNShift;     // kResGrid x 7
+  if (pl->kind == 0) {
+    Csr<double> A = csr_of<double>(pl, transpose);
+    DISPATCH_PP(PP, hipLaunchKernelGGL((k_shift_residual<P_>), dim3(g1), dim3(kThreads), 0, s, n,
+                                       p, A.rowptr, A.colind, A.val, nullptr, B, Xq, ldx, tau_re,
+                                       tau_im, R, part1));
+  } else {
+    // K X_j by the FFT product into R, then R = B + K X + tau X in place
+    for (int j = 0; j < kNShift; ++j)
+      toeplitz_apply<double>(pl, Xq + 2 * p * j, ldx, R + 2 * p * j, W, 2 * p, pl->t, 0, transpose);
+    DISPATCH_PP(PP, hipLaunchKernelGGL((k_shift_residual<P_>), dim3(g1), dim3(kThreads), 0, s, n,
+                                       p, nullptr, nullptr, nullptr, R, B, Xq, ldx, tau_re, tau_im,
+                                       R, part1));
+  }
+  const int g2 = int(std::max<int64_t>(1, std::min<int64_t>(kResGrid, n / 64)));
+  DISPATCH_PP(PP, hipLaunchKernelGGL((k_project_block<T, P_>), dim3(g2), dim3(kThreads), 0, s, n, p,
+                                     Vlast, R, W, w.partial));
+  reduce_partials(pl, g2, p * W, w.projC, nullptr, 0, 0, p, 0);
+  DISPATCH_PP(PP, hipLaunchKernelGGL((k_remainder_norms<T, P_>), dim3(g2), dim3(kThreads), 0, s, n,
+                                     p, Vlast, R, W, w.projC, part3));
+  hipLaunchKernelGGL(k_restart_rhs, dim3((kNShift * p * p + kThreads - 1) / kThreads),
+                     dim3(kThreads), 0, s, p, w.projC, W, S);
+  std::vector<double> h(size_t(512 + kResGrid) * kNShift);
+  HIPCHK(hipMemcpyAsync(h.data(), w.rpart, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int j = 0; j < kNShift; ++j) {
+    double a = 0.0, b = 0.0;
+    for (int g = 0; g < g1; ++g) a += h[size_t(g) * kNShift + j];
+    for (int g = 0; g < g2; ++g) b += h[size_t(512 + g) * kNShift + j];
+    res[j] = std::sqrt(a);
+    rem[j] = std::sqrt(b);
+  }
 }
 
 // Orthonormalise W (n x p) against panels 0..npan-1 of Vb (two block
@@ -1141,41 +1323,41 @@ void orthonormalize(expmv_plan_s* pl, int p, const T* Vb, int npan, T* W, T* Vou
   Workspace& w = pl->ws;
   hipStream_t s = pl->stream;
   const int Oc = npan * p * p;
-  T* Wt = reinterpret_cast<T*>(w.Wt.p);
+  T* Wt = reinterpret_cast<T*>(w.Wt);
   if (npan > 0) {
     int nwg = orth_pass<T>(pl, kProj, p, Vb, npan, W, nullptr, nullptr);
     // coefficients of pass 1, then ||W(:,b)||^2 in hcoef[Oc..Oc+p)
-    reduce_partials(pl, nwg, Oc + p, w.hcoef.p, H, ldh, col0, p, Oc);
-    nwg = orth_pass<T>(pl, kUpdProj, p, Vb, npan, W, Wt, w.hcoef.p);
-    reduce_partials(pl, nwg, Oc, w.w0.p + p, H, ldh, col0, p, Oc);
-    HIPCHK(hipMemcpyAsync(w.w0.p, w.hcoef.p + Oc, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
-    nwg = orth_pass<T>(pl, kUpdGram, p, Vb, npan, Wt, Wt, w.w0.p + p);
-    reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
+    reduce_partials(pl, nwg, Oc + p, w.hcoef, H, ldh, col0, p, Oc);
+    nwg = orth_pass<T>(pl, kUpdProj, p, Vb, npan, W, Wt, w.hcoef);
+    reduce_partials(pl, nwg, Oc, w.w0 + p, H, ldh, col0, p, Oc);
+    HIPCHK(hipMemcpyAsync(w.w0, w.hcoef + Oc, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    nwg = orth_pass<T>(pl, kUpdGram, p, Vb, npan, Wt, Wt, w.w0 + p);
+    reduce_partials(pl, nwg, p * p, w.gram, nullptr, 0, 0, p, 0);
   } else {
     int nwg = orth_pass<T>(pl, kUpdGram, p, static_cast<const T*>(nullptr), 0, W, Wt, nullptr);
-    reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
+    reduce_partials(pl, nwg, p * p, w.gram, nullptr, 0, 0, p, 0);
   }
   // shift of the fallback (shifted Cholesky QR): 11 (n p + p (p + 1)) u
   // times trace(G), u = 2^-53 (the Gram matrices are FP64)
   const double shift_rel = 11.0 * (double(pl->n) * p + double(p) * (p + 1)) * 0x1p-53;
-  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R1.p, w.Rinv.p,
-                     npan > 0 ? w.w0.p : nullptr, 1, nullptr, nullptr, 0, 0, 0, shift_rel,
-                     w.flags.p);
-  int nwg = orth_pass<T>(pl, kScaleGram, p, static_cast<const T*>(nullptr), 0, Wt, Wt, w.Rinv.p);
-  reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
+  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram, w.R1, w.Rinv,
+                     npan > 0 ? w.w0 : nullptr, 1, nullptr, nullptr, 0, 0, 0, shift_rel,
+                     w.flags);
+  int nwg = orth_pass<T>(pl, kScaleGram, p, static_cast<const T*>(nullptr), 0, Wt, Wt, w.Rinv);
+  reduce_partials(pl, nwg, p * p, w.gram, nullptr, 0, 0, p, 0);
   double* Hb = H != nullptr ? H : Rhat;
   const int ldb = H != nullptr ? ldh : p;
   const int hr = H != nullptr ? npan * p : 0, hc = H != nullptr ? col0 : 0;
-  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R2.p, w.Rinv.p,
-                     nullptr, 2, w.R1.p, Hb, ldb, hr, hc, 0.0, w.flags.p);
+  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram, w.R2, w.Rinv,
+                     nullptr, 2, w.R1, Hb, ldb, hr, hc, 0.0, w.flags);
   // third pass, only after a shifted first factor (flags[2]; the kernels
   // return at once otherwise)
-  const int* gate = w.flags.p + 2;
-  nwg = orth_pass<T>(pl, kScaleGram, p, static_cast<const T*>(nullptr), 0, Wt, Wt, w.Rinv.p, gate);
-  reduce_partials(pl, nwg, p * p, w.gram.p, nullptr, 0, 0, p, 0);
-  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram.p, w.R1.p, w.Rinv.p,
-                     nullptr, 3, nullptr, Hb, ldb, hr, hc, 0.0, w.flags.p);
-  orth_pass<T>(pl, kScale, p, static_cast<const T*>(nullptr), 0, Wt, Vout, w.Rinv.p);
+  const int* gate = w.flags + 2;
+  nwg = orth_pass<T>(pl, kScaleGram, p, static_cast<const T*>(nullptr), 0, Wt, Wt, w.Rinv, gate);
+  reduce_partials(pl, nwg, p * p, w.gram, nullptr, 0, 0, p, 0);
+  hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(64), 0, s, p, w.gram, w.R1, w.Rinv,
+                     nullptr, 3, nullptr, Hb, ldb, hr, hc, 0.0, w.flags);
+  orth_pass<T>(pl, kScale, p, static_cast<const T*>(nullptr), 0, Wt, Vout, w.Rinv);
 }
 
 template <typename T, typename TO>
@@ -1363,16 +1545,16 @@ InnerResult apply_inverse_mixed(expmv_plan_s* pl, int transpose, const T* V, T* 
   if constexpr (std::is_same<T, TI>::value) {
     accumulate(apply_inverse<T>(pl, transpose, V, Wout, p));
   } else {
-    TI* vi = reinterpret_cast<TI*>(pl->ws.Win.p);
-    TI* wi = reinterpret_cast<TI*>(pl->ws.Wout.p);
+    TI* vi = reinterpret_cast<TI*>(pl->ws.Win);
+    TI* wi = reinterpret_cast<TI*>(pl->ws.Wout);
     hipLaunchKernelGGL((k_convert<T, TI>), dim3(512), dim3(kThreads), 0, s, cnt, V, vi, 1.0);
     accumulate(apply_inverse<TI>(pl, transpose, vi, wi, p));
     hipLaunchKernelGGL((k_convert<TI, T>), dim3(512), dim3(kThreads), 0, s, cnt, wi, Wout, 1.0);
   }
   if (rounds > 0) {
     Csr<double> A = csr_of<double>(pl, transpose);
-    TI* ri = reinterpret_cast<TI*>(pl->ws.Rin.p);
-    TI* di = reinterpret_cast<TI*>(pl->ws.Din.p);
+    TI* ri = reinterpret_cast<TI*>(pl->ws.Rin);
+    TI* di = reinterpret_cast<TI*>(pl->ws.Din);
     const int PP = pow2_lanes(p);
     const int grid = grid_for(pl->n, PP, 4096);
     for (int r = 0; r < rounds; ++r) {
@@ -1418,8 +1600,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
                           double* Z, expmv_info* info, const std::vector<double>& scales,
                           const SourceMode* src) {
   hipStream_t s = pl->stream;
-  ensure_workspace(pl, p);
-  Workspace& w = pl->ws;
+  Workspace& w = pl->ws;   // bound by the caller for (p, nt)
   const int64_t n = pl->n;
   const int m = pl->opts.m;
   const int ldh = pl->ldh;
@@ -1430,25 +1611,6 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   const int nt = int(scales.size());
   const int ns = kNShift * nt;   // shifted systems
   const int ldx = 2 * ns * p;
-  {
-    // shift-dependent buffers (grow only)
-    const int dmax = m * p;
-    w.X.alloc(blk * 2 * ns);
-    w.G.alloc(size_t(ns) * dmax * p);
-    w.Zs.alloc(size_t(ns) * dmax * p);
-    w.Ascr.alloc(size_t(ns) * dmax * dmax);
-    w.S.alloc(size_t(ns) * p * p);
-    w.Cr.alloc(size_t(ldh) * 2 * ns * p);
-    w.rho.alloc(ns);
-    w.singular.alloc(ns);
-    w.taus.alloc(2 * size_t(ns));
-    w.coefs.alloc(4 * size_t(ns));
-    if (pl->opts.inner_relax) {
-      w.S2.alloc(size_t(ns) * p * p);
-      w.singular2.alloc(ns);
-    }
-    w.partial.alloc(size_t(512) * std::max(nt, kNShift));
-  }
   // poles tau_j / s_q and coefficients c_j / s_q, shift index q * 7 + j
   std::vector<double> tau_h(2 * size_t(ns)), coef_h(2 * size_t(ns));
   for (int q = 0; q < nt; ++q)
@@ -1458,7 +1620,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       coef_h[q * kNShift + j] = CF_C_RE[j] / scales[q];
       coef_h[ns + q * kNShift + j] = CF_C_IM[j] / scales[q];
     }
-  HIPCHK(hipMemcpyAsync(w.taus.p, tau_h.data(), sizeof(double) * tau_h.size(),
+  HIPCHK(hipMemcpyAsync(w.taus, tau_h.data(), sizeof(double) * tau_h.size(),
                         hipMemcpyHostToDevice, s));
   // source mode: s_j = c_j t / (tau_j - sigma), the coefficients of the S part
   double s_re[kNShift] = {0}, s_im[kNShift] = {0};
@@ -1471,22 +1633,27 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       s_im[j] = coef_h[3 * ns + j] = sj.imag();
     }
   }
-  HIPCHK(hipMemcpyAsync(w.coefs.p, coef_h.data(), sizeof(double) * coef_h.size(),
+  HIPCHK(hipMemcpyAsync(w.coefs, coef_h.data(), sizeof(double) * coef_h.size(),
                         hipMemcpyHostToDevice, s));
-  const double* tau_re_d = w.taus.p;
-  const double* tau_im_d = w.taus.p + ns;
-  const double* c_re_d = w.coefs.p;
-  const double* c_im_d = w.coefs.p + ns;
-  const double* s_re_d = w.coefs.p + 2 * ns;
-  const double* s_im_d = w.coefs.p + 3 * ns;
+  const double* tau_re_d = w.taus;
+  const double* tau_im_d = w.taus + ns;
+  const double* c_re_d = w.coefs;
+  const double* c_im_d = w.coefs + ns;
+  const double* s_re_d = w.coefs + 2 * ns;
+  const double* s_im_d = w.coefs + 3 * ns;
   const double t_start = host_now_ms();
   expmv_info inf{};
   double ms_apply = 0, ms_orth = 0, ms_small = 0, ms_update = 0;
-  pl->prof_ms_a = pl->prof_ms_b = pl->prof_ms_c = pl->prof_ms_sm = 0.0;
-  pl->prof_samples = pl->prof_sm_launches = 0;
-  pl->pev_used = 0;
-  pl->oev_used = 0;
-  pl->oev_bytes.clear();
+  {
+    KernelTimer& kt = pl->kt;
+    kt.used = 0;
+    kt.cur_iter = -1;
+    kt.sampling = false;
+    for (int c = 0; c < EXPMV_KT_COUNT; ++c) {
+      kt.ms[c] = kt.by[c] = 0.0;
+      kt.cnt[c] = 0;
+    }
+  }
 
   // bound weights: |c_j| (source mode: |(c_j, s_j)|, since the two parts'
   // errors E, E' give |c_j E + s_j E'| <= |(c_j, s_j)| ||(E, E')||_F; S
@@ -1499,10 +1666,11 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     delta[j] = CF_TAU_RE[j] >= 0.0 ? std::hypot(CF_TAU_RE[j], CF_TAU_IM[j]) : std::fabs(CF_TAU_IM[j]);
   }
 
-  HIPCHK(hipMemsetAsync(w.X.p, 0, sizeof(double) * size_t(n) * ldx, s));
-  HIPCHK(hipMemsetAsync(w.H.p, 0, sizeof(double) * size_t(ldh) * ldh, s));
-  HIPCHK(hipMemsetAsync(w.flags.p, 0, sizeof(int) * 4, s));
-  HIPCHK(hipMemsetAsync(w.singular.p, 0, sizeof(int) * ns, s));
+  zero_device(pl, w.X, sizeof(double) * size_t(n) * ldx);
+  zero_device(pl, w.H, sizeof(double) * size_t(ldh) * ldh);
+  zero_device(pl, w.flags, sizeof(int) * 4);
+  zero_device(pl, w.singular, sizeof(int) * ns);
+  if (pl->opts.inner_relax) zero_device(pl, w.singular2, sizeof(int) * ns);
 
   const int cgrid = 512;
   std::vector<double> part(size_t(cgrid) * nt);
@@ -1511,9 +1679,9 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   if (src) {
     inf.bnorm = std::sqrt(device_dot(pl, int64_t(blk), B, B));
   } else {
-    hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, ldx, 1.0,
-                       c_re_d, c_im_d, Z, w.partial.p);
-    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid, hipMemcpyDeviceToHost,
+    hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X, ldx, 1.0,
+                       c_re_d, c_im_d, Z, w.partial);
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial, sizeof(double) * cgrid, hipMemcpyDeviceToHost,
                           s));
     HIPCHK(hipStreamSynchronize(s));
     double bb = 0.0;
@@ -1526,12 +1694,12 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
   }
 
   int cur = 0;
-  T* Vb = reinterpret_cast<T*>(w.V[cur].p);
-  T* Wk = reinterpret_cast<T*>(w.W.p);
+  T* Vb = reinterpret_cast<T*>(w.V[cur]);
+  T* Wk = reinterpret_cast<T*>(w.W);
   // Steps 1-2: V_1 R^ = B
   hipLaunchKernelGGL((k_convert<double, T>), dim3(512), dim3(kThreads), 0, s, int64_t(blk), B, Wk,
                      1.0);
-  orthonormalize<T>(pl, p, nullptr, 0, Wk, Vb, nullptr, 0, 0, w.Rhat.p);
+  orthonormalize<T>(pl, p, nullptr, 0, Wk, Vb, nullptr, 0, 0, w.Rhat);
 
   int d = m * p;          // projected dimension (padded coordinates)
   int kp = 0;             // columns taken by the Ritz block (k_eff rounded up to p)
@@ -1574,7 +1742,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       inf.block_apps += 1;
       double t1 = host_now_ms();
       ms_apply += t1 - t0;
-      orthonormalize<T>(pl, p, Vb, jb + 1, Wk, Vb + size_t(jb + 1) * blk, w.H.p, ldh, jb * p,
+      orthonormalize<T>(pl, p, Vb, jb + 1, Wk, Vb + size_t(jb + 1) * blk, w.H, ldh, jb * p,
                         nullptr);
       ms_orth += host_now_ms() - t1;
       if (relax && jb + 1 < m && (jb - first_block) % 2 == 1) {
@@ -1585,10 +1753,10 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
         const int dj = (jb + 1) * p;
         dim3 g(std::max(1, (dj * p + kThreads - 1) / kThreads), ns);
         hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, dj, p, rhs_from_S ? kp : 0,
-                           rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
-        proj_solve(s, ns, dj, p, 1, w.H.p, ldh, tau_re_d, tau_im_d, w.G.p, w.Ascr.p, w.Zs.p,
-                   nullptr, ldx, w.S2.p, w.rho.p, w.singular2.p);
-        HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+                           rhs_from_S ? 1 : 0, w.Rhat, w.S, w.G);
+        proj_solve(s, ns, dj, p, 1, w.H, ldh, tau_re_d, tau_im_d, w.G, w.Ascr, w.Zs,
+                   nullptr, ldx, w.S2, w.rho, w.singular2);
+        HIPCHK(hipMemcpyAsync(rho.data(), w.rho, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         rho_prev = 0.0;
         for (int q = 0; q < ns; ++q) rho_prev = std::max(rho_prev, rho[q]);
@@ -1600,45 +1768,79 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     {
       dim3 g(std::max(1, (d * p + kThreads - 1) / kThreads), ns);
       hipLaunchKernelGGL(k_build_rhs, g, dim3(kThreads), 0, s, d, p, rhs_from_S ? kp : 0,
-                         rhs_from_S ? 1 : 0, w.Rhat.p, w.S.p, w.G.p);
+                         rhs_from_S ? 1 : 0, w.Rhat, w.S, w.G);
     }
     // Step 4: projected shifted systems, residual estimates, update coefficients
-    proj_solve(s, ns, d, p, precond ? 1 : 0, w.H.p, ldh, tau_re_d, tau_im_d, w.G.p, w.Ascr.p,
-               w.Zs.p, w.Cr.p, ldx, w.S.p, w.rho.p, w.singular.p);
+    proj_solve(s, ns, d, p, precond ? 1 : 0, w.H, ldh, tau_re_d, tau_im_d, w.G, w.Ascr,
+               w.Zs, w.Cr, ldx, w.S, w.rho, w.singular);
     double t1 = host_now_ms();
     // X_j += V_{d+p} (H~ Z_j)  [Algorithm 1: V_d Z_j]
-    panel_gemm<T, double>(pl, p, Vb, d / p + 1, w.Cr.p, ldx, 2 * ns, w.X.p, p, ldx, 1);
+    panel_gemm<T, double>(pl, p, Vb, d / p + 1, w.Cr, ldx, 2 * ns, w.X, p, ldx, 1);
     if (src && src->s_only)
-      hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X.p, ldx, 0.0,
-                         s_re_d, s_im_d, Z, w.partial.p);
+      hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B, w.X, ldx, 0.0,
+                         s_re_d, s_im_d, Z, w.partial);
     else if (src)
-      hipLaunchKernelGGL(k_combine_source, dim3(cgrid), dim3(kThreads), 0, s, n, p / 2, B, w.X.p,
-                         ldx, double(CF_OMEGA0), c_re_d, c_im_d, s_re_d, s_im_d, Z, w.partial.p);
+      hipLaunchKernelGGL(k_combine_source, dim3(cgrid), dim3(kThreads), 0, s, n, p / 2, B, w.X,
+                         ldx, double(CF_OMEGA0), c_re_d, c_im_d, s_re_d, s_im_d, Z, w.partial);
     else
       for (int q = 0; q < nt; ++q)
         hipLaunchKernelGGL(k_combine, dim3(cgrid), dim3(kThreads), 0, s, n, p, B,
-                           w.X.p + size_t(2 * kNShift * p) * q, ldx, double(CF_OMEGA0),
+                           w.X + size_t(2 * kNShift * p) * q, ldx, double(CF_OMEGA0),
                            c_re_d + kNShift * q, c_im_d + kNShift * q, Z + blk * q,
-                           w.partial.p + size_t(cgrid) * q);
-    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * cgrid * nt,
+                           w.partial + size_t(cgrid) * q);
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial, sizeof(double) * cgrid * nt,
                           hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(rho.data(), w.rho.p, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(rho.data(), w.rho, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
     int flags_h[4];
-    HIPCHK(hipMemcpyAsync(flags_h, w.flags.p, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(flags_h, w.flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    std::vector<int> sing_h(ns);
+    HIPCHK(hipMemcpyAsync(sing_h.data(), w.singular, sizeof(int) * ns, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double t2 = host_now_ms();
     ms_small += t1 - t0;
     ms_update += t2 - t1;
-    // per time: ||Z~_q|| and the bound sum_j |c_j / s| rho / (delta_j / s)
-    bool conv_bound = true;
-    double rmax = 0.0, worst = 0.0;
+    // Step 4 in FP64: the true residuals of the shifted systems, recomputed
+    // from X_j; with opts.restart_refine their coordinates on the block after
+    // the basis are the next cycle's right-hand sides (refinement)
+    const T* Vlast = Vb + size_t(d / p) * blk;
+    cplx* Sdst = pl->opts.restart_refine ? w.S : w.Sref;
+    std::vector<double> zn_q(nt);
     for (int q = 0; q < nt; ++q) {
       double zz = 0.0;
       for (int i = 0; i < cgrid; ++i) zz += part[size_t(cgrid) * q + i];
-      const double zn = std::sqrt(zz);
+      zn_q[q] = std::sqrt(zz);
+    }
+    double res_bound = 0.0, rem_bound = 0.0;
+    for (int j = 0; j < kNShift; ++j) inf.true_res[j] = inf.noncollinear[j] = 0.0;
+    for (int q = 0; q < nt; ++q) {
+      double res[kNShift], rem[kNShift];
+      shift_residuals<T>(pl, transpose, B, p, w.X + size_t(2 * kNShift * p) * q, ldx,
+                         tau_re_d + kNShift * q, tau_im_d + kNShift * q, Vlast,
+                         Sdst + size_t(kNShift) * p * p * q, res, rem);
+      double rb = 0.0, nb = 0.0;
+      for (int j = 0; j < kNShift; ++j) {
+        inf.true_res[j] = std::max(inf.true_res[j], res[j]);
+        inf.noncollinear[j] = std::max(inf.noncollinear[j], rem[j]);
+        rb += cw[j] * res[j] / delta[j];
+        nb += cw[j] * rem[j] / delta[j];
+      }
+      const double zn = zn_q[q] > 0.0 ? zn_q[q] : 1.0;
+      res_bound = std::max(res_bound, rb / zn);
+      rem_bound = std::max(rem_bound, nb / zn);
+    }
+    inf.true_bound = res_bound;
+    inf.noncollinear_bound = rem_bound;
+    ms_update += host_now_ms() - t2;
+    // per time: ||Z~_q|| and the bound sum_j |c_j / s| rho / (delta_j / s)
+    bool conv_bound = true, finite = true;
+    double rmax = 0.0, worst = 0.0;
+    for (int q = 0; q < nt; ++q) {
+      const double zn = zn_q[q];
+      if (!std::isfinite(zn)) finite = false;
       double bound = 0.0;
       for (int j = 0; j < kNShift; ++j) {
         const double r = rho[q * kNShift + j];
+        if (!std::isfinite(r)) finite = false;
         bound += cw[j] * r / delta[j];
         rmax = std::max(rmax, r);
       }
@@ -1651,30 +1853,33 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     inf.err_bound = worst;
     inf.cycles = cycle;
     inf.breakdown = flags_h[0];
-    if (flags_h[1]) {
+    bool singular = false;
+    for (int v : sing_h) singular = singular || v != 0;
+    // a rank-deficient block, a singular projected system (eq. 4.7) or a
+    // non-finite estimate or norm: the iterate cannot be trusted
+    if (flags_h[1] || singular || !finite) {
       status = EXPMV_EBREAKDOWN;
+      break;
+    }
+    // an inner solve that stopped at its cap leaves the Arnoldi relation
+    // (eq. 4.5) inexact, whatever the estimates say
+    if (inf.inner_maxit_hit) {
+      status = EXPMV_EINNER;
       break;
     }
     bool conv;
     if (pl->opts.stop_rule == EXPMV_STOP_PAPER) conv = rmax <= tol * inf.bnorm;
     else conv = conv_bound;
     if (!(rmax > 0.0)) conv = true;   // invariant space or exact
-    if (!std::isfinite(rmax)) {
-      status = EXPMV_EBREAKDOWN;
-      break;
-    }
     if (conv) break;
-    if (inf.inner_maxit_hit) {
-      status = EXPMV_EINNER;
-      break;
-    }
     if (cycle >= pl->opts.max_cycles) {
       status = EXPMV_ENOCONV;
       break;
     }
+    if (pl->opts.restart_refine) inf.refined_restarts += 1;
     // Steps 5-8: deflated restart (host eigensolve of the live part of H_d)
     double t3 = host_now_ms();
-    HIPCHK(hipMemcpyAsync(Hh.data(), w.H.p, sizeof(double) * size_t(ldh) * ldh,
+    HIPCHK(hipMemcpyAsync(Hh.data(), w.H, sizeof(double) * size_t(ldh) * ldh,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     // live padded coordinates: everything but the padding after the Ritz block
@@ -1714,17 +1919,17 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       }
     for (int r = 0; r < p; ++r)
       for (int c = 0; c < kn; ++c) Hh[size_t(kpn + r) * ldh + c] = HP[size_t(d + r) * kn + c];
-    HIPCHK(hipMemcpyAsync(w.Crot.p, Pk.data(), sizeof(double) * Pk.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(w.H.p, Hh.data(), sizeof(double) * Hh.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w.Crot, Pk.data(), sizeof(double) * Pk.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(w.H, Hh.data(), sizeof(double) * Hh.size(), hipMemcpyHostToDevice, s));
     // V_new = V_{d+p} P_{k+p}: the Ritz panels by a panel GEMM, then the last panel
-    T* Vn = reinterpret_cast<T*>(w.V[cur ^ 1].p);
-    panel_gemm<T, T>(pl, p, Vb, d / p, w.Crot.p, kpn, kpn / p, Vn, int64_t(blk), p, 0);
+    T* Vn = reinterpret_cast<T*>(w.V[cur ^ 1]);
+    panel_gemm<T, T>(pl, p, Vb, d / p, w.Crot, kpn, kpn / p, Vn, int64_t(blk), p, 0);
     HIPCHK(hipMemcpyAsync(Vn + size_t(kpn / p) * blk, Vb + size_t(d / p) * blk, sizeof(T) * blk,
                           hipMemcpyDeviceToDevice, s));
     // Pk's constant header (host copy) must stay alive until the copies ran
     HIPCHK(hipStreamSynchronize(s));
     cur ^= 1;
-    Vb = reinterpret_cast<T*>(w.V[cur].p);
+    Vb = reinterpret_cast<T*>(w.V[cur]);
     keff = kn;
     kp = kpn;
     d = m * p;   // kp + (m - kp/p) p
@@ -1732,69 +1937,33 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     rhs_from_S = true;
     ms_small += host_now_ms() - t3;
   }
-  // true residuals of the shifted systems (FP64 operator, once at the end);
-  // true_res[j] is the largest over the times
-  for (int q = 0; q < nt; ++q) {
-    const double* Xq = w.X.p + size_t(2 * kNShift * p) * q;
-    int grid = 512;
-    if (pl->kind == 0) {
-      Csr<double> A = csr_of<double>(pl, transpose);
-      const int PP = pow2_lanes(p);
-      grid = grid_for(n, PP, 512);
-      DISPATCH_PP(PP, hipLaunchKernelGGL((k_true_residual<P_>), dim3(grid), dim3(kThreads), 0, s,
-                                         n, p, A.rowptr, A.colind, A.val, B, Xq, ldx,
-                                         tau_re_d + kNShift * q, tau_im_d + kNShift * q,
-                                         w.partial.p));
-    } else {
-      pl->kx.alloc(size_t(n) * 2 * kNShift * p);
-      const int64_t ldk = 2 * kNShift * p;
-      for (int j = 0; j < kNShift; ++j)
-        toeplitz_apply<double>(pl, Xq + 2 * p * j, ldx, pl->kx.p + 2 * p * j, ldk, 2 * p, pl->t,
-                               0, transpose);
-      hipLaunchKernelGGL(k_residual_from_kx, dim3(grid), dim3(kThreads), 0, s, n, p, B, Xq, ldx,
-                         pl->kx.p, int(ldk), tau_re_d + kNShift * q, tau_im_d + kNShift * q,
-                         w.partial.p);
-    }
-    std::vector<double> tp(size_t(grid) * kNShift);
-    HIPCHK(hipMemcpyAsync(tp.data(), w.partial.p, sizeof(double) * tp.size(), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int j = 0; j < kNShift; ++j) {
-      double acc = 0.0;
-      for (int g = 0; g < grid; ++g) acc += tp[size_t(g) * kNShift + j];
-      inf.true_res[j] = std::max(inf.true_res[j], std::sqrt(acc));
-    }
-  }
   HIPCHK(hipStreamSynchronize(s));
   inf.ms_total = host_now_ms() - t_start;
   inf.ms_apply = ms_apply;
   inf.ms_orth = ms_orth;
   inf.ms_small = ms_small;
   inf.ms_update = ms_update;
-  inf.kern_samples = pl->prof_samples;
-  inf.kern_ms_a = pl->prof_samples ? pl->prof_ms_a / pl->prof_samples : 0.0;
-  inf.kern_ms_b = pl->prof_samples ? pl->prof_ms_b / pl->prof_samples : 0.0;
-  inf.kern_ms_c = pl->prof_samples ? pl->prof_ms_c / pl->prof_samples : 0.0;
-  inf.kern_orth_launches = 0;
-  inf.kern_ms_orth = inf.kern_orth_bytes = 0.0;
-  if (pl->oev_used > 0) {
-    HIPCHK(hipEventSynchronize(pl->oev[pl->oev_used - 1]));
-    double ms = 0.0, by = 0.0;
-    for (int q = 0; q + 1 < pl->oev_used; q += 2) {
-      float t = 0.f;
-      HIPCHK(hipEventElapsedTime(&t, pl->oev[q], pl->oev[q + 1]));
-      ms += t;
-      by += pl->oev_bytes[q / 2];
-    }
-    const int nl = pl->oev_used / 2;
-    inf.kern_orth_launches = nl;
-    inf.kern_ms_orth = ms / nl;
-    inf.kern_orth_bytes = by / nl;
+  kt_collect(pl, 0);
+  for (int c = 0; c < EXPMV_KT_COUNT; ++c) {
+    const int cnt = pl->kt.cnt[c];
+    inf.kern_launches[c] = cnt;
+    inf.kern_ms[c] = cnt ? pl->kt.ms[c] / cnt : 0.0;
+    inf.kern_bytes[c] = cnt ? pl->kt.by[c] / cnt : 0.0;
   }
-  inf.kern_smooth_launches = pl->prof_sm_launches;
-  inf.kern_ms_smooth = pl->prof_sm_launches ? pl->prof_ms_sm / pl->prof_sm_launches : 0.0;
   inf.amg_levels = pl->amg ? int(pl->amg->lv.size()) : 0;
   if (info) *info = inf;
   return status;
+}
+
+void bind_workspace(expmv_plan_s* pl, int p, int nt, bool joined, void* work, size_t bytes) {
+  const size_t need = layout_workspace(pl, p, nt, joined, nullptr);
+  if (!work || bytes < need || reinterpret_cast<uintptr_t>(work) % 256 != 0) {
+    std::snprintf(g_error_detail, sizeof(g_error_detail),
+                  "workspace %p of %zu bytes: this call needs %zu bytes, 256-byte aligned",
+                  work, bytes, need);
+    throw StatusError{EXPMV_EINVAL};
+  }
+  layout_workspace(pl, p, nt, joined, static_cast<char*>(work));
 }
 
 expmv_status dispatch_execute(expmv_plan_s* pl, int transpose, const double* B, int p, double tol,
@@ -1815,8 +1984,6 @@ expmv_status dispatch_execute(expmv_plan_s* pl, int transpose, const double* B, 
 // C ABI
 
 namespace {
-
-thread_local char g_error_detail[256] = "";
 
 template <typename F>
 expmv_status guarded(F&& f) {
@@ -1857,6 +2024,7 @@ bool valid_opts(const expmv_opts& o) {
   if (o.inner_relax < 0 || o.inner_relax > 10) return false;
   if (o.amg_fp32 != 0 && o.amg_fp32 != 1) return false;
   if (o.amg_coarse_degree < 0 || o.amg_coarse_degree > kAmgMaxDeg) return false;
+  if (o.restart_refine != 0 && o.restart_refine != 1) return false;
   return true;
 }
 
@@ -1872,18 +2040,19 @@ void upload_cf(expmv_plan_s* pl) {
 }
 
 void init_plan_common(expmv_plan_s* pl) {
+  HIPCHK(hipGetDevice(&pl->device));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pl->host_flags), sizeof(int) * 8,
                        hipHostMallocDefault));
   std::memset(pl->host_flags, 0, sizeof(int) * 8);
   HIPCHK(hipEventCreateWithFlags(&pl->ev[0], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&pl->ev[1], hipEventDisableTiming));
   if (pl->opts.profile > 0) {
-    pl->pev.resize(size_t(kSampleEv) * 128);
-    pl->pev_iter.resize(128);
-    pl->pev_nsm.resize(128);
-    pl->oev.resize(2 * 2048);
-    for (auto& e : pl->oev) HIPCHK(hipEventCreate(&e));
-    for (auto& e : pl->pev) HIPCHK(hipEventCreate(&e));
+    KernelTimer& kt = pl->kt;
+    kt.ev.assign(2 * size_t(kKtSlots), nullptr);
+    kt.cls.assign(kKtSlots, 0);
+    kt.iter.assign(kKtSlots, -1);
+    kt.bytes.assign(kKtSlots, 0.0);
+    for (auto& e : kt.ev) HIPCHK(hipEventCreate(&e));
   }
   upload_cf(pl);
 }
@@ -2066,6 +2235,7 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
     }
     upload_vec(L->Av32, Lh.A.v);   // level 0: the values of K (or K^T) as the host copy holds them
     L->avg_a = double(Lh.A.nnz()) / double(std::max<int64_t>(1, Lh.A.nrows));
+    L->nnz_a = Lh.A.nnz();
     if (l + 1 < h.lv.size()) {
       upload_csr(Lh.P, L->Prp, L->Pci, L->Pv);
       upload_csr(Lh.R, L->Rrp, L->Rci, L->Rv);
@@ -2073,6 +2243,8 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
       upload_vec(L->Rv32, Lh.R.v);
       L->avg_p = double(Lh.P.nnz()) / double(std::max<int64_t>(1, Lh.P.nrows));
       L->avg_r = double(Lh.R.nnz()) / double(std::max<int64_t>(1, Lh.R.nrows));
+      L->nnz_p = Lh.P.nnz();
+      L->nnz_r = Lh.R.nnz();
     }
     L->degree = l == 0 ? H->degree
                        : (pl->opts.amg_coarse_degree > 0 ? pl->opts.amg_coarse_degree
@@ -2102,11 +2274,13 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
     upload_csr(Pf, L.Pfrp, L.Pfci, L.Pfv);
     upload_vec(L.Pfv32, Pf.v);
     L.avg_pf = double(Pf.nnz()) / double(std::max<int64_t>(1, Pf.nrows));
+    L.nnz_pf = Pf.nnz();
     if (l + 2 == nlev && dense_last) continue;   // Inv Rf below
     const HostCsr Rf = fused_restriction(Lh, s0, 0.0);
     upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
     upload_vec(L.Rfv32, Rf.v);
     L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
+    L.nnz_rf = Rf.nnz();
   }
   {
     // the finest level at degree 2, when it restricts to a sparse level:
@@ -2123,6 +2297,7 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
         upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
         upload_vec(L.Rfv32, Rf.v);
         L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
+        L.nnz_rf = Rf.nnz();
         L.alpha = alpha;
         L.beta = beta;
         L.fused = true;
@@ -2137,10 +2312,12 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
         upload_csr(Rf, L.Rfrp, L.Rfci, L.Rfv);
         upload_vec(L.Rfv32, Rf.v);
         L.avg_rf = double(Rf.nnz()) / double(std::max<int64_t>(1, Rf.nrows));
+        L.nnz_rf = Rf.nnz();
         const HostCsr Pf = fused_prolongation(Lh, s0);
         upload_csr(Pf, L.Pfrp, L.Pfci, L.Pfv);
         upload_vec(L.Pfv32, Pf.v);
         L.avg_pf = double(Pf.nnz()) / double(std::max<int64_t>(1, Pf.nrows));
+        L.nnz_pf = Pf.nnz();
         L.alpha = 2.0 * s0;
         L.beta = s0 * s0;
         L.fused = true;
@@ -2174,7 +2351,6 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
     upload_vec(H->cinvR, IR);
   }
   (tr && !pl->symmetric ? pl->amgT : pl->amg) = std::move(H);
-  pl->ws.p = 0;   // workspace re-sized with the AMG vectors on the next call
   return EXPMV_OK;
 }
 
@@ -2238,10 +2414,10 @@ double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
       scd.alloc(n);
       HIPCHK(hipMemcpyAsync(scd.p, sc.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
-                         int64_t(1), 1, n, scd.p, pl->fb[0].p, 0, 1.0, nullptr);
-      fft_len(pl, n, rad_n, pl->fb[0].p, pl->fb[1].p, pl->fb[2].p, 1, -1.0);
+                         int64_t(1), 1, n, scd.p, pl->setup_fb[0].p, 0, 1.0, nullptr);
+      fft_len(pl, n, rad_n, pl->setup_fb[0].p, pl->setup_fb[1].p, pl->setup_fb[2].p, 1, -1.0);
       std::vector<cplx> ev(n);
-      HIPCHK(hipMemcpyAsync(ev.data(), pl->fb[1].p, sizeof(cplx) * n, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(ev.data(), pl->setup_fb[1].p, sizeof(cplx) * n, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       for (auto& e : ev) {
         const double d = e.x * e.x + e.y * e.y;
@@ -2257,13 +2433,13 @@ double toeplitz_setup_solve(expmv_plan_s* pl, const std::vector<double>& c,
         return;
       }
       hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
-                         int64_t(1), 1, n, in, pl->fb[0].p, 0, 1.0, nullptr);
-      fft_len(pl, n, rad_n, pl->fb[0].p, pl->fb[1].p, pl->fb[2].p, 1, -1.0);
+                         int64_t(1), 1, n, in, pl->setup_fb[0].p, 0, 1.0, nullptr);
+      fft_len(pl, n, rad_n, pl->setup_fb[0].p, pl->setup_fb[1].p, pl->setup_fb[2].p, 1, -1.0);
       hipLaunchKernelGGL(k_spec_mul, dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
-                         pl->fb[1].p, inv_eig.p, 1.0 / double(n));
-      fft_len(pl, n, rad_n, pl->fb[1].p, pl->fb[0].p, pl->fb[2].p, 1, +1.0);
+                         pl->setup_fb[1].p, inv_eig.p, 1.0 / double(n));
+      fft_len(pl, n, rad_n, pl->setup_fb[1].p, pl->setup_fb[0].p, pl->setup_fb[2].p, 1, +1.0);
       hipLaunchKernelGGL((k_unpack<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
-                         int64_t(1), 1, pl->fb[0].p, outp, 0, 1.0, 0, nullptr);
+                         int64_t(1), 1, pl->setup_fb[0].p, outp, 0, 1.0, 0, nullptr);
     };
     copy(res, rh);
     HIPCHK(hipMemsetAsync(pv, 0, sizeof(double) * n, s));
@@ -2313,17 +2489,24 @@ expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
   while (L < 2 * n) L <<= 1;
   pl->L = L;
   pl->radices = fft_radices(L);
-  pl->ws.partial.alloc(4096);
-  ensure_fft_buffers(pl, 1);
+  // set-up buffers (plan-owned, released below): the FFT work arrays for
+  // one complex column and the partial sums of the set-up solves' dots
+  for (auto& b : pl->setup_fb) b.alloc(size_t(L));
+  DevBuf<double> part;
+  part.alloc(4096);
+  pl->ws = Workspace();
+  for (int i = 0; i < 3; ++i) pl->ws.fb[i] = pl->setup_fb[i].p;
+  pl->ws.fq = 1;
+  pl->ws.partial = part.p;
   DevBuf<double> tmp;
   tmp.alloc(L);
   auto spectrum = [&](const std::vector<double>& h, DevBuf<cplx>& dst) {
     dst.alloc(L);
     HIPCHK(hipMemcpyAsync(tmp.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL((k_pack<double>), dim3(stream_grid(L)), dim3(kThreads), 0, s,
-                       int64_t(h.size()), 1, int64_t(1), 1, L, tmp.p, pl->fb[0].p, 0, 1.0,
+                       int64_t(h.size()), 1, int64_t(1), 1, L, tmp.p, pl->setup_fb[0].p, 0, 1.0,
                        nullptr);
-    fft(pl, pl->fb[0].p, dst.p, pl->fb[1].p, 1, -1.0);
+    fft(pl, pl->setup_fb[0].p, dst.p, pl->setup_fb[1].p, 1, -1.0);
     HIPCHK(hipStreamSynchronize(s));
   };
   // circulant embeddings [c_0 .. c_{n-1}, 0 .., r_{n-1} .. r_1] of T and
@@ -2366,6 +2549,9 @@ expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
     gen([&](int64_t i) { return yh[n - 1 - i]; }, pl->jyhat);                 // J y
     gen([&](int64_t i) { return i ? yh[i - 1] : 0.0; }, pl->zyhat);          // Z y
   }
+  HIPCHK(hipStreamSynchronize(s));
+  for (auto& b : pl->setup_fb) b.release();
+  pl->ws = Workspace();
   return EXPMV_OK;
 }
 
@@ -2395,6 +2581,7 @@ expmv_status expmv_default_opts(expmv_opts* o) {
   o->inner_relax = 8;
   o->amg_fp32 = 0;
   o->amg_coarse_degree = 0;
+  o->restart_refine = 0;
   return EXPMV_OK;
 }
 
@@ -2499,16 +2686,46 @@ expmv_status expmv_plan_toeplitz_general(int64_t n, const double* col0, const do
   });
 }
 
+expmv_status expmv_workspace_size(expmv_plan plan, int64_t p, size_t* bytes) {
+  if (!plan || !bytes || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    *bytes = layout_workspace(plan, int(p), 1, false, nullptr);
+    return EXPMV_OK;
+  });
+}
+
+expmv_status expmv_workspace_size_times(expmv_plan plan, int64_t p, int nt, size_t* bytes) {
+  if (!plan || !bytes || p < 1 || p > kMaxP || p > plan->n || nt < 1 || nt > kMaxTimes)
+    return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    *bytes = layout_workspace(plan, int(p), nt, false, nullptr);
+    return EXPMV_OK;
+  });
+}
+
+expmv_status expmv_workspace_size_source(expmv_plan plan, int64_t p, size_t* bytes) {
+  if (!plan || !bytes || p < 1 || 2 * p > kMaxP || 2 * p > plan->n) return EXPMV_EINVAL;
+  return guarded([&]() -> expmv_status {
+    // the joined block [U0 | S] (2p columns) or one of its halves alone
+    *bytes = std::max(layout_workspace(plan, int(2 * p), 1, true, nullptr),
+                      layout_workspace(plan, int(p), 1, false, nullptr));
+    return EXPMV_OK;
+  });
+}
+
 expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int64_t p, double tol,
-                           double* Z, expmv_info* info) {
+                           void* work, size_t work_bytes, double* Z, expmv_info* info) {
   if (!plan || !B || !Z || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
-  return guarded([&]() { return dispatch_execute(plan, transpose, B, int(p), tol, Z, info); });
+  return guarded([&]() {
+    bind_workspace(plan, int(p), 1, false, work, work_bytes);
+    return dispatch_execute(plan, transpose, B, int(p), tol, Z, info);
+  });
 }
 
 expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* times, int nt,
-                                 const double* B, int64_t p, double tol, double* Z,
-                                 expmv_info* info) {
+                                 const double* B, int64_t p, double tol, void* work,
+                                 size_t work_bytes, double* Z, expmv_info* info) {
   if (!plan || !times || !B || !Z || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   if (nt < 1 || nt > kMaxTimes) return EXPMV_EINVAL;
   if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
@@ -2518,20 +2735,22 @@ expmv_status expmv_execute_times(expmv_plan plan, int transpose, const double* t
     scales[q] = times[q] / plan->t;
     if (!(scales[q] > 0.0)) return EXPMV_ENOTNEG;   // t_q A must stay negative definite
   }
-  return guarded(
-      [&]() { return dispatch_execute(plan, transpose, B, int(p), tol, Z, info, scales); });
+  return guarded([&]() {
+    bind_workspace(plan, int(p), nt, false, work, work_bytes);
+    return dispatch_execute(plan, transpose, B, int(p), tol, Z, info, scales);
+  });
 }
 
 expmv_status expmv_execute_source(expmv_plan plan, int transpose, const double* U0,
-                                  const double* S, int64_t p, double gamma, double tol, double* U,
-                                  expmv_info* info) {
+                                  const double* S, int64_t p, double gamma, double tol, void* work,
+                                  size_t work_bytes, double* U, expmv_info* info) {
   if (!plan || !U0 || !S || !U || p < 1 || 2 * p > kMaxP || 2 * p > plan->n) return EXPMV_EINVAL;
   if (!(tol > 0.0 && tol < 1.0) || !std::isfinite(gamma)) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
     const int64_t n = plan->n;
-    plan->ws.partial.alloc(4096);   // device_dot's partial sums
     // an all-zero part would make the joined block rank deficient: S = 0 is
     // the plain exponential, U0 = 0 runs on S alone
+    bind_workspace(plan, int(p), 1, false, work, work_bytes);
     const double uu = device_dot(plan, n * p, U0, U0), ss = device_dot(plan, n * p, S, S);
     if (!std::isfinite(uu) || !std::isfinite(ss) || !(uu + ss > 0.0)) return EXPMV_EINVAL;
     if (ss == 0.0) return dispatch_execute(plan, transpose, U0, int(p), tol, U, info);
@@ -2539,37 +2758,38 @@ expmv_status expmv_execute_source(expmv_plan plan, int transpose, const double* 
     if (sm.s_only)
       return dispatch_execute(plan, transpose, S, int(p), tol, U, info, std::vector<double>{1.0},
                               &sm);
-    plan->srcB.alloc(size_t(n) * 2 * p);
+    bind_workspace(plan, int(2 * p), 1, true, work, work_bytes);
+    double* J = plan->ws.srcB;
     // joined block [U0 | S]: row i holds U0's row i, then S's row i
-    HIPCHK(hipMemcpy2DAsync(plan->srcB.p, sizeof(double) * 2 * p, U0, sizeof(double) * p,
+    HIPCHK(hipMemcpy2DAsync(J, sizeof(double) * 2 * p, U0, sizeof(double) * p,
                             sizeof(double) * p, n, hipMemcpyDeviceToDevice, plan->stream));
-    HIPCHK(hipMemcpy2DAsync(plan->srcB.p + p, sizeof(double) * 2 * p, S, sizeof(double) * p,
+    HIPCHK(hipMemcpy2DAsync(J + p, sizeof(double) * 2 * p, S, sizeof(double) * p,
                             sizeof(double) * p, n, hipMemcpyDeviceToDevice, plan->stream));
-    return dispatch_execute(plan, transpose, plan->srcB.p, int(2 * p), tol, U, info,
-                            std::vector<double>{1.0}, &sm);
+    return dispatch_execute(plan, transpose, J, int(2 * p), tol, U, info, std::vector<double>{1.0},
+                            &sm);
   });
 }
 
 expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, int64_t p,
-                           double tol, double* gradB, double* grad_t, expmv_info* info) {
+                           double tol, void* work, size_t work_bytes, double* gradB,
+                           double* grad_t, expmv_info* info) {
   if (!plan || !G || !B || !gradB || !grad_t || p < 1 || p > kMaxP || p > plan->n)
     return EXPMV_EINVAL;
   if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
+    bind_workspace(plan, int(p), 1, false, work, work_bytes);
     expmv_status st = dispatch_execute(plan, 1, G, int(p), tol, gradB, info);
     if (st != EXPMV_OK && st != EXPMV_ENOCONV) return st;
     hipStream_t s = plan->stream;
     Workspace& w = plan->ws;
     // K B (K = -tA = -M), for the omega_0 <G, M B> term
-    plan->kx.alloc(size_t(plan->n) * p * 2 * kNShift);
-    double* KB = plan->kx.p;
+    double* KB = w.Rres;
     const int grid = 512;
-    w.partial.alloc(size_t(grid) * 16);   // 16 sums per workgroup (the solve has finished)
     apply_K<double>(plan, 0, B, KB, int(p));
-    hipLaunchKernelGGL(k_adjoint_dots, dim3(grid), dim3(kThreads), 0, s, plan->n, int(p), w.X.p,
-                       B, G, KB, w.partial.p);
+    hipLaunchKernelGGL(k_adjoint_dots, dim3(grid), dim3(kThreads), 0, s, plan->n, int(p), w.X,
+                       B, G, KB, w.partial);
     std::vector<double> part(size_t(grid) * 16);
-    HIPCHK(hipMemcpyAsync(part.data(), w.partial.p, sizeof(double) * part.size(),
+    HIPCHK(hipMemcpyAsync(part.data(), w.partial, sizeof(double) * part.size(),
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double d[16] = {0};
@@ -2590,25 +2810,25 @@ expmv_status expmv_adjoint(expmv_plan plan, const double* G, const double* B, in
 }
 
 expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Zm, int64_t p,
-                          double* out) {
-  if (!plan || !G || !Zm || !out || p < 1 || p > kMaxP) return EXPMV_EINVAL;
+                          void* work, size_t work_bytes, double* out) {
+  if (!plan || !G || !Zm || !out || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
-    ensure_workspace(plan, int(p));
+    bind_workspace(plan, int(p), 1, false, work, work_bytes);
     hipStream_t s = plan->stream;
     if (plan->kind == 1) {
       // <G, A Z> = -<G, T Z>
-      plan->kx.alloc(size_t(plan->n) * p);
-      toeplitz_apply<double>(plan, Zm, p, plan->kx.p, p, int(p), 1.0, 0);
-      *out = -device_dot(plan, plan->n * p, G, plan->kx.p);
+      double* TZ = plan->ws.Rres;
+      toeplitz_apply<double>(plan, Zm, p, TZ, p, int(p), 1.0, 0);
+      *out = -device_dot(plan, plan->n * p, G, TZ);
       return EXPMV_OK;
     }
     const int PP = pow2_lanes(int(p));
     const int grid = grid_for(plan->n, PP, 512);
     DISPATCH_PP(PP, hipLaunchKernelGGL((k_dot_spmm<P_>), dim3(grid), dim3(kThreads), 0, s,
                                        plan->n, int(p), plan->rowptr.p, plan->colind.p,
-                                       plan->val.p, G, Zm, plan->ws.partial.p));
+                                       plan->val.p, G, Zm, plan->ws.partial));
     std::vector<double> part(grid);
-    HIPCHK(hipMemcpyAsync(part.data(), plan->ws.partial.p, sizeof(double) * grid,
+    HIPCHK(hipMemcpyAsync(part.data(), plan->ws.partial, sizeof(double) * grid,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double acc = 0.0;
@@ -2620,9 +2840,10 @@ expmv_status expmv_grad_t(expmv_plan plan, const double* G, const double* Zm, in
 }
 
 expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* X, int64_t p,
-                                  double* Y) {
-  if (!plan || !X || !Y || p < 1 || p > kMaxP) return EXPMV_EINVAL;
+                                  void* work, size_t work_bytes, double* Y) {
+  if (!plan || !X || !Y || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
+    bind_workspace(plan, int(p), 1, false, work, work_bytes);
     apply_K<double>(plan, transpose, X, Y, int(p));
     const int64_t cnt = plan->n * p;
     hipLaunchKernelGGL((k_convert<double, double>), dim3(512), dim3(kThreads), 0, plan->stream, cnt,
@@ -2633,14 +2854,14 @@ expmv_status expmv_apply_operator(expmv_plan plan, int transpose, const double* 
 }
 
 expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X, int64_t p,
-                                 double* Y, long long* iters) {
+                                 void* work, size_t work_bytes, double* Y, long long* iters) {
   if (!plan || !X || !Y || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
-    ensure_workspace(plan, int(p));
+    bind_workspace(plan, int(p), 1, false, work, work_bytes);
     InnerResult r;
     if (plan->mixed) {
-      float* xf = reinterpret_cast<float*>(plan->ws.W.p);
-      float* yf = reinterpret_cast<float*>(plan->ws.Wt.p);
+      float* xf = reinterpret_cast<float*>(plan->ws.W);
+      float* yf = reinterpret_cast<float*>(plan->ws.Wt);
       const int64_t cnt = plan->n * p;
       hipLaunchKernelGGL((k_convert<double, float>), dim3(512), dim3(kThreads), 0, plan->stream,
                          cnt, X, xf, 1.0);
@@ -2657,11 +2878,11 @@ expmv_status expmv_apply_inverse(expmv_plan plan, int transpose, const double* X
 }
 
 expmv_status expmv_apply_preconditioner(expmv_plan plan, int transpose, const double* X,
-                                        int64_t p, double* Y) {
+                                        int64_t p, void* work, size_t work_bytes, double* Y) {
   if (!plan || !X || !Y || p < 1 || p > kMaxP || p > plan->n || plan->kind != 0)
     return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
-    ensure_workspace(plan, int(p));
+    bind_workspace(plan, int(p), 1, false, work, work_bytes);
     hipStream_t s = plan->stream;
     const int64_t cnt = plan->n * p;
     auto apply = [&](auto tag, const auto* x, auto* y) {
@@ -2678,8 +2899,8 @@ expmv_status expmv_apply_preconditioner(expmv_plan plan, int transpose, const do
     const bool v32 = plan->mixed || (plan->opts.amg_fp32 && plan->symmetric &&
                                      amg_for(plan, transpose) != nullptr);
     if (v32) {
-      float* xf = reinterpret_cast<float*>(plan->ws.W.p);
-      float* yf = reinterpret_cast<float*>(plan->ws.Wt.p);
+      float* xf = reinterpret_cast<float*>(plan->ws.W);
+      float* yf = reinterpret_cast<float*>(plan->ws.Wt);
       hipLaunchKernelGGL((k_convert<double, float>), dim3(512), dim3(kThreads), 0, s, cnt, X, xf,
                          1.0);
       apply(float(), xf, yf);
@@ -2820,8 +3041,8 @@ void expmv_plan_destroy(expmv_plan plan) {
   if (plan->host_flags) (void)hipHostFree(plan->host_flags);
   if (plan->ev[0]) (void)hipEventDestroy(plan->ev[0]);
   if (plan->ev[1]) (void)hipEventDestroy(plan->ev[1]);
-  for (auto& e : plan->pev) (void)hipEventDestroy(e);
-  for (auto& e : plan->oev) (void)hipEventDestroy(e);
+  for (auto& e : plan->kt.ev)
+    if (e) (void)hipEventDestroy(e);
   delete plan;
 }
 
@@ -2841,13 +3062,28 @@ const char* expmv_status_string(expmv_status s) {
   return "unknown status";
 }
 
+// one-shot forms: plan, a workspace of their own (allocated like the plan's
+// set-up buffers), execute, destroy
+static expmv_status one_shot(expmv_plan pl, const double* B, int64_t p, double tol, double* Z) {
+  size_t bytes = 0;
+  expmv_status st = expmv_workspace_size(pl, p, &bytes);
+  if (st != EXPMV_OK) return st;
+  return guarded([&]() -> expmv_status {
+    DevBuf<char> work;
+    work.alloc(bytes);
+    const expmv_status r = expmv_execute(pl, 0, B, p, tol, work.p, bytes, Z, nullptr);
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    return r;
+  });
+}
+
 expmv_status expmv_block_csr(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
                              const double* val, const double* B, int64_t p, double t, double tol,
                              double* Z, hipStream_t stream) {
   expmv_plan pl = nullptr;
   expmv_status st = expmv_plan_csr(n, nnz, rowptr, colind, val, t, nullptr, stream, &pl);
   if (st != EXPMV_OK) return st;
-  st = expmv_execute(pl, 0, B, p, tol, Z, nullptr);
+  st = one_shot(pl, B, p, tol, Z);
   expmv_plan_destroy(pl);
   return st;
 }
@@ -2857,7 +3093,7 @@ expmv_status expmv_block_toeplitz(int64_t n, const double* col0, const double* B
   expmv_plan pl = nullptr;
   expmv_status st = expmv_plan_toeplitz(n, col0, t, nullptr, stream, &pl);
   if (st != EXPMV_OK) return st;
-  st = expmv_execute(pl, 0, B, p, tol, Z, nullptr);
+  st = one_shot(pl, B, p, tol, Z);
   expmv_plan_destroy(pl);
   return st;
 }

@@ -653,51 +653,12 @@ k_combine_source(int64_t n, int pu, const double* __restrict__ B, const double* 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// True residuals R_j = B - (M - tau_j I) X_j = B + K X_j + tau_j X_j with
-// K = -M in CSR, for the 7 shifts whose X_j start at X (row stride ldx);
-// partial[wg * 7 + j] = sum of |R_j|^2 over the workgroup.
-template <int PP>
-__global__ void __launch_bounds__(kThreads)
-k_true_residual(int64_t n, int p, const int32_t* __restrict__ rowptr,
-                const int32_t* __restrict__ colind, const double* __restrict__ val,
-                const double* __restrict__ B, const double* __restrict__ X, int ldx,
-                const double* __restrict__ tau_re, const double* __restrict__ tau_im,
-                double* __restrict__ partial) {
-  __shared__ double red[kThreads];
-  const int c = threadIdx.x % PP;
-  double nr[kNShift];
-  for (int j = 0; j < kNShift; ++j) nr[j] = 0.0;
-  const int64_t rows_per_grid = int64_t(gridDim.x) * (kThreads / PP);
-  for (int64_t row = int64_t(blockIdx.x) * (kThreads / PP) + threadIdx.x / PP; row < n;
-       row += rows_per_grid) {
-    if (c < p) {
-      const int e0 = rowptr[row], e1 = rowptr[row + 1];
-      const double bv = B[row * p + c];
-      for (int j = 0; j < kNShift; ++j) {
-        double kr = 0.0, ki = 0.0;
-        for (int e = e0; e < e1; ++e) {
-          const double* xc = X + int64_t(colind[e]) * ldx + 2 * p * j;
-          kr += val[e] * xc[c];
-          ki += val[e] * xc[p + c];
-        }
-        const double* xs = X + row * ldx + 2 * p * j;
-        const double xr = xs[c], xi = xs[p + c];
-        const double rr = bv + kr + tau_re[j] * xr - tau_im[j] * xi;
-        const double ri = ki + tau_re[j] * xi + tau_im[j] * xr;
-        nr[j] += rr * rr + ri * ri;
-      }
-    }
-  }
-  for (int j = 0; j < kNShift; ++j) {
-    red[threadIdx.x] = nr[j];
-    __syncthreads();
-    for (int st = kThreads / 2; st >= 1; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[size_t(blockIdx.x) * kNShift + j] = red[0];
-    __syncthreads();
-  }
+// words 32-bit words of p set to zero (a kernel rather than a memset, so the
+// clearing is an ordinary launch on the stream)
+__global__ void __launch_bounds__(kThreads) k_zero32(int64_t words, uint32_t* __restrict__ p) {
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < words;
+       i += int64_t(gridDim.x) * kThreads)
+    p[i] = 0u;
 }
 
 // partial dot <G, K Z> per workgroup (K in CSR)

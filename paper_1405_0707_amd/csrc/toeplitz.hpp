@@ -372,40 +372,4 @@ k_axpby(int64_t len, double a, const double* __restrict__ x, double b, double* _
     y[i] = a * x[i] + b * y[i];
 }
 
-// Z = omega0 B + sum_j Re(c_j X_j) is k_combine; the Toeplitz true residual
-// needs K X: R_j = B + K X_j + tau_j X_j for the 7 shifts whose X_j start at
-// X (row stride ldx), with KX (n x 14p, row stride ldk) precomputed.
-__global__ void __launch_bounds__(kThreads)
-k_residual_from_kx(int64_t n, int p, const double* __restrict__ B, const double* __restrict__ X,
-                   int ldx, const double* __restrict__ KX, int ldk,
-                   const double* __restrict__ tau_re, const double* __restrict__ tau_im,
-                   double* __restrict__ partial) {
-  __shared__ double red[kThreads];
-  double nr[kNShift];
-  for (int j = 0; j < kNShift; ++j) nr[j] = 0.0;
-  for (int64_t idx = int64_t(blockIdx.x) * kThreads + threadIdx.x; idx < n * p;
-       idx += int64_t(gridDim.x) * kThreads) {
-    const int64_t r = idx / p;
-    const int b = int(idx % p);
-    const double bv = B[idx];
-    for (int j = 0; j < kNShift; ++j) {
-      const double xr = X[r * ldx + 2 * p * j + b], xi = X[r * ldx + 2 * p * j + p + b];
-      const double kr = KX[r * ldk + 2 * p * j + b], ki = KX[r * ldk + 2 * p * j + p + b];
-      const double rr = bv + kr + tau_re[j] * xr - tau_im[j] * xi;
-      const double ri = ki + tau_re[j] * xi + tau_im[j] * xr;
-      nr[j] += rr * rr + ri * ri;
-    }
-  }
-  for (int j = 0; j < kNShift; ++j) {
-    red[threadIdx.x] = nr[j];
-    __syncthreads();
-    for (int st = kThreads / 2; st >= 1; st >>= 1) {
-      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[size_t(blockIdx.x) * kNShift + j] = red[0];
-    __syncthreads();
-  }
-}
-
 }  // namespace expmv

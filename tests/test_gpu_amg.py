@@ -70,7 +70,8 @@ def test_device_vcycle_matches_numpy_vcycle(name, p, degree):
 
 
 @pytest.mark.parametrize("form,p", [("mixed", 8), ("fp64_fp32_vcycle", 8), ("mixed", 12),
-                                    ("fp64_fp32_vcycle", 20)])
+                                    ("fp64_fp32_vcycle", 20), ("mixed", 16), ("mixed", 24),
+                                    ("mixed", 32), ("fp64_fp32_vcycle", 32)])
 def test_device_fp32_vcycle(form, p):
     """The FP32 V-cycle (FP32 values and vectors, FP64 sums) of the mixed
     form and, by default, of the FP64 form's CG, against the numpy V-cycle
@@ -88,10 +89,12 @@ def test_device_fp32_vcycle(form, p):
     assert abs(a - b) <= 1e-5 * np.linalg.norm(Px) * np.linalg.norm(X[:, 1])
 
 
-@pytest.mark.parametrize("p", [12, 20])
+@pytest.mark.parametrize("p", [12, 16, 20, 24, 32])
 def test_mixed_amg_inverse_wide_blocks(p):
-    """The FP32 inner CG and V-cycle of the mixed form with four columns per
-    lane and masked lanes (p = 12, 20) against a sparse LU solve."""
+    """The FP32 inner CG and V-cycle of the mixed form against a sparse LU
+    solve: four columns per lane with masked lanes (p = 12, 20), eight
+    columns per lane (p = 16, 32, the 128^3 and 1024^2 workloads' widths) and
+    eight with one of four lanes masked (p = 24)."""
     announce(f"mixed AMG inverse vardiff96 p={p}")
     A, t = _workload("vardiff96")
     X = np.random.default_rng(7).standard_normal((A.n, p))

@@ -1,0 +1,132 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times, against references the oracle computed once
+(tests/golden/make_full_size_references.py): a seeded sample of rows of the
+result plus the norms of the whole result.
+
+Bars (relative to the reference, written in each test):
+  FP64 form: the sampled rows within 1e-10 in the Frobenius norm, every
+    sampled entry within 1e-10 ||ref||_max, ||Z||_F within 1e-10;
+  mixed form: the same at 1e-5.
+The 3D convection-diffusion operator (128^3) also gets the invariants of an
+M-matrix exponential at full size (positivity for B >= 0 within the CF
+floor, 1-norm contraction) and linearity in B.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from paper_1405_0707_amd import Plan
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def announce(name):
+    print(f"[gpu-test] {name}", flush=True)
+
+
+def load(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing reference {path}: run tests/golden/make_full_size_references.py")
+    return np.load(path)
+
+
+def check_sample(Z, g, bar, key="Z", fro="fro", maxabs="maxabs", what="Z"):
+    rows = torch.from_numpy(g["rows"]).to(Z.device)
+    Zs = Z[rows].cpu().numpy()
+    ref = g[key]
+    e_f = float(np.linalg.norm(Zs - ref) / np.linalg.norm(ref))
+    e_m = float(np.abs(Zs - ref).max() / float(g[maxabs]))
+    e_n = abs(float(torch.linalg.norm(Z)) / float(g[fro]) - 1.0)
+    print(f"{what}: sampled rel {e_f:.2e}, max-abs {e_m:.2e}, norm {e_n:.2e}", flush=True)
+    assert e_f < bar, e_f
+    assert e_m < bar, e_m
+    assert e_n < bar, e_n
+
+
+# --------------------------------------------------------------------------- 128^3
+
+@pytest.fixture(scope="module")
+def convdiff128():
+    W = wl.c4(precision="fp64")
+    return W, torch.from_numpy(W.B).to(DEV)
+
+
+def convdiff_plan(W, precision):
+    return Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=DEV, m=W.m, k=W.k,
+                    precision=precision)
+
+
+@pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-11, 1e-10), ("mixed", 1e-6, 1e-5)])
+def test_convdiff128_matches_oracle(convdiff128, precision, tol, bar):
+    """The FP64 run stops at an error bound of 1e-11: at 1e-10 the Frobenius
+    error is 4e-11 but single entries reach 1.3e-10 of ||ref||_max."""
+    announce(f"convdiff 128^3 p=16 {precision} vs oracle")
+    W, B = convdiff128
+    pl = convdiff_plan(W, precision)
+    Z, info = pl.execute(B, tol=tol)
+    print(f"cycles {info.cycles} inner {info.inner_iters} true_res {max(info.true_res):.2e} "
+          f"noncollinear {max(info.noncollinear):.2e}", flush=True)
+    check_sample(Z, load("convdiff128.npz"), bar)
+
+
+def test_convdiff128_m_matrix_invariants_and_linearity(convdiff128):
+    """-K is an M-matrix with zero interior column sums, so e^{tA} >= 0
+    entrywise and ||e^{tA}||_1 <= 1: Z >= 0 for B >= 0 (to the CF floor and
+    the tolerance) and every column's 1-norm shrinks.  Linearity in B is
+    checked on the mixed form (to its tolerance)."""
+    announce("convdiff 128^3 invariants")
+    W, B = convdiff128
+    pl = convdiff_plan(W, "fp64")
+    Bp = torch.abs(B)
+    Z, _ = pl.execute(Bp, tol=1e-10)
+    floor = 1e-10 * float(Z.abs().max()) + 3e-14 * float(Bp.abs().max())
+    assert float(Z.min()) >= -floor, (float(Z.min()), floor)
+    n1 = Z.abs().sum(0)
+    assert bool(torch.all(n1 <= Bp.abs().sum(0) * (1 + 1e-10)))
+    pm = convdiff_plan(W, "mixed")
+    B2 = torch.from_numpy(wl.gaussian_block(W.n, W.p, 44)).to(DEV)
+    Z1, _ = pm.execute(B, tol=1e-7)
+    Z2, _ = pm.execute(B2, tol=1e-7)
+    Z3, _ = pm.execute(2.0 * B - 3.0 * B2, tol=1e-7)
+    e = float(torch.linalg.norm(Z3 - (2.0 * Z1 - 3.0 * Z2)) / torch.linalg.norm(Z3))
+    print(f"linearity {e:.2e}", flush=True)
+    assert e < 1e-5
+
+
+# --------------------------------------------------------------------------- 1024^2
+
+@pytest.mark.parametrize("precision,tol,bar", [("fp64", 1e-10, 1e-10), ("mixed", 1e-6, 1e-5)])
+def test_vardiff1024_forward_and_adjoint_match_oracle(precision, tol, bar):
+    announce(f"vardiff 1024^2 p=32 {precision} forward + adjoint vs oracle")
+    W = wl.c5(precision="fp64")
+    g = load("vardiff1024.npz")
+    pl = Plan.csr(W.A.rowptr, W.A.colind, W.A.val, W.t, device=DEV, m=W.m, k=W.k,
+                  precision=precision, inner_maxit=200000)
+    B = torch.from_numpy(W.B).to(DEV)
+    G = torch.from_numpy(wl.c5_weights()).to(DEV)
+    Z, info = pl.execute(B, tol=tol)
+    check_sample(Z, g, bar)
+    gB, gt, info_b = pl.adjoint(G, B, tol=tol)
+    check_sample(gB, g, bar, key="G", fro="gfro", maxabs="gmaxabs", what="grad_B")
+    ref_t = float(g["grad_t"])
+    e_t = abs(gt - ref_t) / abs(ref_t)
+    print(f"grad_t {gt:.12e} ref {ref_t:.12e} rel {e_t:.2e}", flush=True)
+    assert e_t < bar
+
+
+# --------------------------------------------------------------------------- Toeplitz 2^20
+
+def test_toeplitz2p20_matches_oracle():
+    announce("toeplitz 2^20 p=16 vs oracle")
+    W = wl.c3()
+    g = load("toeplitz2p20.npz")
+    pl = Plan.toeplitz(torch.from_numpy(W.col), W.t, device=DEV, m=W.m, k=W.k)
+    Z, info = pl.execute(torch.from_numpy(W.B).to(DEV), tol=W.tol)
+    print(f"cycles {info.cycles} true_res {max(info.true_res):.2e}", flush=True)
+    check_sample(Z, g, 1e-10)
