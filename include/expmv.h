@@ -254,6 +254,23 @@ expmv_status expmv_execute(expmv_plan plan, int transpose, const double* B, int6
                            double tol, void* work, size_t work_bytes, double* Z,
                            expmv_info* info);
 
+/* expmv_execute for callers that cannot allocate device memory or bring a
+ * workspace (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  It allocates nothing: its workspace is a static
+ * device array of EXPMV_STATIC_WORKSPACE_BYTES, one copy on every GPU the
+ * library runs on, held until the process ends.  A call whose
+ * expmv_workspace_size(plan, p) exceeds that size returns EINVAL (with a
+ * detail); so does a call made while another device than the plan's is
+ * current.  All such calls on one GPU share the array and it keeps the last
+ * call's contents (every array the method needs zeroed is cleared by the
+ * call itself): calls from one process are serialised by a host lock, and
+ * each call has finished its device work when it returns, so calls must not
+ * overlap in any other way (e.g. the same array used from device work that
+ * is still queued).  Arguments, results and statuses as expmv_execute. */
+#define EXPMV_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+expmv_status expmv_execute_noalloc(expmv_plan plan, int transpose, const double* B, int64_t p,
+                                   double tol, double* Z, expmv_info* info);
+
 /* Several times at once: Z_q = e^{t_q A} B for q = 0..nt-1 (times: host
  * array, 1 <= nt <= 32; Z: device, nt consecutive n x p blocks, block q at
  * Z + q n p).  A is the plan's matrix (the plan holds t_0 A for its own t_0);

@@ -56,7 +56,7 @@ EXPORTS = [
     "expmv_host_amg_fused",
     "expmv_execute_times", "expmv_last_error_detail", "expmv_plan_toeplitz_general",
     "expmv_execute_source", "expmv_workspace_size", "expmv_workspace_size_times",
-    "expmv_workspace_size_source",
+    "expmv_workspace_size_source", "expmv_execute_noalloc",
 ]
 
 _lib = None
@@ -82,6 +82,7 @@ def lib():
     L.expmv_workspace_size_times.argtypes = [vp, i64, i32, C.POINTER(sz)]
     L.expmv_workspace_size_source.argtypes = [vp, i64, C.POINTER(sz)]
     L.expmv_execute.argtypes = [vp, i32, vp, i64, dbl, vp, sz, vp, C.POINTER(Info)]
+    L.expmv_execute_noalloc.argtypes = [vp, i32, vp, i64, dbl, vp, C.POINTER(Info)]
     L.expmv_grad_t.argtypes = [vp, vp, vp, i64, vp, sz, C.POINTER(dbl)]
     L.expmv_adjoint.argtypes = [vp, vp, vp, i64, dbl, vp, sz, vp, C.POINTER(dbl),
                                 C.POINTER(Info)]

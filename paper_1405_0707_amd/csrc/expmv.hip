@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <type_traits>
@@ -3060,6 +3061,60 @@ const char* expmv_status_string(expmv_status s) {
     case EXPMV_EINNER: return "inner solve reached its iteration cap";
   }
   return "unknown status";
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Workspace of expmv_execute_noalloc: a static device array, one copy per GPU
+// (the runtime places it when the library's code object is loaded on a
+// device), so that call allocates nothing.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in); it asks the
+// runtime once per device for that device's address and uses that.
+
+namespace {
+
+constexpr size_t kStaticWorkBytes = EXPMV_STATIC_WORKSPACE_BYTES;
+__device__ __align__(256) char scratch[kStaticWorkBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;                   // one no-allocation call at a time per process
+void* g_scratch_ptr[kMaxDevices] = {};    // device address of `scratch` on each device
+
+// address of this device's copy of `scratch`; the device must be current
+void* scratch_of_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw StatusError{EXPMV_EINVAL};
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw StatusError{EXPMV_EHIP};
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+expmv_status expmv_execute_noalloc(expmv_plan plan, int transpose, const double* B, int64_t p,
+                                   double tol, double* Z, expmv_info* info) {
+  if (!plan || !B || !Z || p < 1 || p > kMaxP || p > plan->n) return EXPMV_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0)) return EXPMV_EINVAL;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  return guarded([&]() {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != plan->device) {
+      std::snprintf(g_error_detail, sizeof(g_error_detail),
+                    "current device %d is not the plan's device %d", dev, plan->device);
+      throw StatusError{EXPMV_EINVAL};
+    }
+    void* work = scratch_of_device(dev);
+    // bind_workspace refuses a call whose workspace exceeds the array (EINVAL)
+    bind_workspace(plan, int(p), 1, false, work, kStaticWorkBytes);
+    return dispatch_execute(plan, transpose, B, int(p), tol, Z, info);
+  });
 }
 
 // one-shot forms: plan, a workspace of their own (allocated like the plan's
