@@ -356,7 +356,8 @@ expmv_status expmv_cf_table(double* tau_re, double* tau_im, double* c_re, double
  * sym: eigenvalues w (n) and orthonormal eigenvectors in the columns of Q
  * (n x n row-major) of (A + A^T)/2.  general: eigenvalues wr + i wi and unit
  * eigenvectors Vr + i Vi (columns), complex ones in exact conjugate pairs.
- * Return EINVAL on bad arguments, ENOCONV if the QR iteration fails. */
+ * Return EINVAL on bad arguments, ENOCONV if the QR iteration does not
+ * converge or the input or result is not finite. */
 expmv_status expmv_host_eig_sym(int n, const double* A, double* w, double* Q);
 expmv_status expmv_host_eig_general(int n, const double* A, double* wr, double* wi, double* Vr,
                                     double* Vi);

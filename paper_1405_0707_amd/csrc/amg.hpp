@@ -43,8 +43,14 @@ enum : int {
 // group never straddles a wavefront.
 //
 // Rows of a group: SEG = one contiguous XCD-aware segment per workgroup (the
-// inner solver's layout), else a grid-stride loop.  Every lane of a group
-// runs the same rows, so the shuffles always see a whole group.
+// inner solver's layout), else a grid-stride loop that stays inside one XCD:
+// the workgroups are handed to the 8 XCDs round-robin, so XCD b % 8 takes
+// the (b % 8)-th contiguous eighth of the rows and its workgroups b / 8
+// stride through it together.  A gather by a restriction or prolongation
+// then reads the fine (or coarse) rows near its own from its own XCD's L2;
+// striding over the whole range instead made every XCD fetch every source
+// row (the 128^3 restriction read 4.5x its algorithmic bytes).  Every lane
+// of a group runs the same rows, so the shuffles always see a whole group.
 template <int NT, int PPL, bool SEG>
 struct RowRange {
   int64_t r, end, step;
@@ -56,6 +62,12 @@ struct RowRange {
       r = s0 + threadIdx.x / lanes;
       end = s1;
       step = NT / lanes;
+    } else if (gridDim.x % 8 == 0) {
+      const int64_t per = (n + 7) / 8;
+      const int64_t s0 = min<int64_t>(n, int64_t(blockIdx.x % 8) * per);
+      r = s0 + int64_t(blockIdx.x / 8) * (NT / lanes) + threadIdx.x / lanes;
+      end = min<int64_t>(n, s0 + per);
+      step = int64_t(gridDim.x / 8) * (NT / lanes);
     } else {
       r = int64_t(blockIdx.x) * (NT / lanes) + threadIdx.x / lanes;
       end = n;

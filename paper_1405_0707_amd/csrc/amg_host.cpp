@@ -271,8 +271,11 @@ double estimate_lmax(const HostCsr& A, const std::vector<double>& dinv, bool sym
       Tm[size_t(i) * m + i] = alpha[i];
       if (i + 1 < m) Tm[size_t(i) * m + i + 1] = Tm[size_t(i + 1) * m + i] = beta[i];
     }
-    sym_eig(m, Tm.data(), ev.data(), Q.data());
-    for (double x : ev) est = std::max(est, x);
+    // unconverged: the Gershgorin bound below stands in for the estimate
+    if (sym_eig(m, Tm.data(), ev.data(), Q.data()))
+      for (double x : ev) est = std::max(est, x);
+    else
+      est = gersh;
   } else {
     for (int k = 0; k < 30; ++k) {
       const double b = nrm(v);

@@ -16,7 +16,7 @@
 
 namespace expmv {
 
-void sym_eig(int n, const double* Ain, double* w, double* Q) {
+bool sym_eig(int n, const double* Ain, double* w, double* Q) {
   std::vector<double> A(Ain, Ain + size_t(n) * n);
   auto at = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
   auto q = [&](int i, int j) -> double& { return Q[size_t(i) * n + j]; };
@@ -111,7 +111,13 @@ void sym_eig(int n, const double* Ain, double* w, double* Q) {
       }
     }
   }
-  for (int i = 0; i < n; ++i) w[i] = a[i];
+  bool finite = true;
+  for (int i = 0; i < n; ++i) {
+    w[i] = a[i];
+    finite = finite && std::isfinite(a[i]);
+  }
+  for (size_t i = 0; i < size_t(n) * n; ++i) finite = finite && std::isfinite(Q[i]);
+  return hi == 0 && finite;
 }
 
 // ---------------------------------------------------------------------------

@@ -5,7 +5,10 @@ namespace expmv {
 
 // A (n x n, row-major) symmetric part -> eigenvalues w (n) and orthonormal
 // eigenvectors in the columns of Q (n x n row-major): A = Q diag(w) Q^T.
-void sym_eig(int n, const double* A, double* w, double* Q);
+// Returns false if the QR iteration did not deflate every off-diagonal
+// entry within 60 n sweeps, or if the input or the result is not finite (w
+// and Q then hold the unconverged iterate).
+bool sym_eig(int n, const double* A, double* w, double* Q);
 
 // General real A (n x n row-major) -> eigenvalues wr + i wi and eigenvectors
 // (column i of Vr + i Vi, unit 2-norm).  Complex eigenvalues come as exact

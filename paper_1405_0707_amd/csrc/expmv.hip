@@ -272,6 +272,14 @@ int grid_for(int64_t rows, int PP, int cap = 1024) {
   return int(std::max<int64_t>(1, std::min<int64_t>(cap, wgs)));
 }
 
+// Grid of an AMG gather kernel (256 threads, `lanes` per row): up to 4096
+// workgroups, a multiple of 8 from 8 on, so that RowRange keeps each
+// workgroup's rows inside the eighth of the level its XCD works on.
+int grid_amg(int64_t rows, int lanes) {
+  const int g = grid_for(rows, lanes, 4096);
+  return g < 8 ? g : (g + 7) / 8 * 8;
+}
+
 #define DISPATCH_PP(PP, ...)                         \
   switch (PP) {                                      \
     case 1: { constexpr int P_ = 1; __VA_ARGS__; } break;   \
@@ -677,7 +685,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     const int GR = row_split(L.avg_rf, PPL);
     const KtEv e = kt_take(pl, c_restr, csr(nc, L.nnz_rf) + blk + cblk);
     hipExtLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
-                          dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, e.e0, e.e1, 0,
+                          dim3(grid_amg(nc, PPL * GR)), dim3(kThreads), 0, s, e.e0, e.e1, 0,
                           k, ctl, nc, p, GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
     amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr);
   };
@@ -689,14 +697,14 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     const int G = std::max(row_split(L.avg_a, PPL), row_split(L.avg_pf, PPL));
     const KtEv e = kt_take(pl, c_prol, pair_bytes);
     hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
-                          dim3(grid_for(n, PPL * G, 4096)), dim3(kThreads), 0, s, e.e0, e.e1, 0,
+                          dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0,
                           k, ctl, n, p, G, L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf,
                           xc, L.alpha, L.beta, out);
     return;
   }
   const int gfine = cg_grid(n, PP);
   const int GA = row_split(L.avg_a, PPL), GP = row_split(L.avg_p, PPL);
-  const int gcoarse_a = grid_for(n, PPL * GA, 4096), gcoarse_p = grid_for(n, PPL * GP, 4096);
+  const int gcoarse_a = grid_amg(n, PPL * GA), gcoarse_p = grid_amg(n, PPL * GP);
   // one smoothing step: reads A, D^{-1}, b and the iterate (unless it is the
   // implicit first one), the direction when HasD; writes the output and the
   // direction when WriteD (the residual step writes r only)
@@ -764,7 +772,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
       const int GR = row_split(L.avg_r, PPL);
       const KtEv e = kt_take(pl, c_restr, csr(nc, L.nnz_r) + blk + cblk);
       hipExtLaunchKernelGGL((k_amg_restrict<T, PPL, VW, kThreads, false>),
-                            dim3(grid_for(nc, PPL * GR, 4096)), dim3(kThreads), 0, s, e.e0, e.e1,
+                            dim3(grid_amg(nc, PPL * GR)), dim3(kThreads), 0, s, e.e0, e.e1,
                             0, k, ctl, nc, p, GR, L.Rrp.p, L.Rci.p, lv.r, r, bc);
       amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr);
     }
@@ -1451,7 +1459,9 @@ RitzBasis ritz_basis(bool symmetric, bool precond, int dl, const std::vector<dou
   std::iota(ord.begin(), ord.end(), 0);
   if (symmetric) {
     std::vector<double> wv(dl), Q(size_t(dl) * dl);
-    sym_eig(dl, Hd.data(), wv.data(), Q.data());
+    // an unconverged eigen-decomposition would give a restart basis that is
+    // not the Ritz basis of Step 5: the solve stops with a breakdown
+    if (!sym_eig(dl, Hd.data(), wv.data(), Q.data())) throw StatusError{EXPMV_EBREAKDOWN};
     auto key = [&](int a) { return std::fabs(wv[a]); };
     if (precond) std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) > key(b); });
     else std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
@@ -3022,8 +3032,7 @@ expmv_status expmv_cf_table(double* tau_re, double* tau_im, double* c_re, double
 expmv_status expmv_host_eig_sym(int n, const double* A, double* w, double* Q) {
   if (n < 1 || !A || !w || !Q) return EXPMV_EINVAL;
   return guarded([&]() -> expmv_status {
-    sym_eig(n, A, w, Q);
-    return EXPMV_OK;
+    return sym_eig(n, A, w, Q) ? EXPMV_OK : EXPMV_ENOCONV;
   });
 }
 

@@ -77,6 +77,21 @@ def test_host_general_eig(n):
     assert res < 1e-9 * np.abs(ref).max()
 
 
+def test_host_eig_reports_non_finite_input():
+    """A NaN entry cannot converge: both eigensolvers return EXPMV_ENOCONV
+    (the restart step turns that into EXPMV_EBREAKDOWN)."""
+    n = 6
+    A = _sym(n, 3)
+    A[2, 4] = A[4, 2] = np.nan
+    w, Q = np.zeros(n), np.zeros((n, n))
+    assert _lib.lib().expmv_host_eig_sym(n, A.ctypes.data, w.ctypes.data,
+                                         Q.ctypes.data) == _lib.ENOCONV
+    wr, wi = np.zeros(n), np.zeros(n)
+    Vr, Vi = np.zeros((n, n)), np.zeros((n, n))
+    assert _lib.lib().expmv_host_eig_general(n, A.ctypes.data, wr.ctypes.data, wi.ctypes.data,
+                                             Vr.ctypes.data, Vi.ctypes.data) == _lib.ENOCONV
+
+
 def test_default_options_and_range_checks():
     """expmv_default_opts fills the documented defaults; expmv_plan_csr
     rejects an out-of-range option with EINVAL before it touches a device
