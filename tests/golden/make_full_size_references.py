@@ -7,9 +7,11 @@ is stored with the norms of the whole result:
 
   convdiff128.npz  3D upwind convection-diffusion 128^3, p = 16, ||tA||_1 = 1e3:
                    r(tA)B by the oracle's z-mode semi-direct solve
-                   (exact.rational_kron3_tridiag), a direct solve per pole.
+                   (exact.rational_kron3_tridiag), a direct solve per pole
+                   and z mode with one refinement step.
   vardiff1024.npz  2D log-normal diffusion 1024^2, p = 32, t = 0.1, weights W:
                    r(tA)B, r(tA^T)W and <W, A r(tA)B> by one sparse LU per pole
+                   with one refinement step per solve
                    (exact.rational_sparse_adjoint).
   toeplitz2p20.npz SPD Toeplitz n = 2^20, p = 16, ||tA||_2 ~= 1e3: the oracle's
                    PSBFOM-DR (Algorithm 2) with the Gohberg-Semencul inverse
@@ -62,7 +64,8 @@ def convdiff(N=128, pe=50.0, vel=(1.0, 0.5, 0.25)):
     el = time.perf_counter() - t0
     rows = sample_rows(W.n, 2048, 4)
     meta = {"workload": f"convdiff3d N={N} Pe={pe} v={vel}", "n": W.n, "p": W.p, "t": W.t,
-            "seed_B": 4, "reference": "r(tA)B, z-mode semi-direct solve per pole",
+            "seed_B": 4,
+            "reference": "r(tA)B, z-mode semi-direct solve per pole, one refinement step",
             "oracle_s": round(el, 1)}
     np.savez(os.path.join(HERE, "convdiff128.npz"), rows=rows, Z=Z[rows],
              fro=np.linalg.norm(Z), maxabs=np.abs(Z).max(), bfro=np.linalg.norm(W.B),
@@ -80,7 +83,8 @@ def vardiff(N=1024):
     rows = sample_rows(W.n, 1024, 5)
     meta = {"workload": f"vardiff2d N={N} seed 205", "n": W.n, "p": W.p, "t": W.t,
             "seed_B": 5, "seed_W": 105,
-            "reference": "r(tA)B, r(tA^T)W, <W, A r(tA)B> from one sparse LU per pole",
+            "reference": "r(tA)B, r(tA^T)W, <W, A r(tA)B> from one sparse LU per pole, "
+                         "one refinement step per solve",
             "oracle_s": round(el, 1)}
     np.savez(os.path.join(HERE, "vardiff1024.npz"), rows=rows, Z=Z[rows], fro=np.linalg.norm(Z),
              maxabs=np.abs(Z).max(), G=gB[rows], gfro=np.linalg.norm(gB),
