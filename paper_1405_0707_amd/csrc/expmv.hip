@@ -303,6 +303,27 @@ constexpr bool kWide4 = PP >= 4 && (sizeof(T) == 4 || PP >= 16);
 template <typename T, int PP>
 constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
 
+// Lane width of the inner solvers' SpMMs (k_cg_a, k_bcg_s): two adjacent
+// columns per lane for even p (one otherwise), so that the eight gathers of a
+// pipelined row step (spmm_unroll) fit in the registers of a 1024-thread
+// workgroup with FP32 and FP64 blocks alike (four FP32 columns spilled).
+// Only the columns a lane owns change with the width: the rows of each
+// workgroup, and so the partial sums, do not.
+#define SPMM_DISPATCH(T, PP, p, ...)                                         \
+  do {                                                                       \
+    if constexpr (PP >= 2) {                                                 \
+      if ((p) % 2 == 0) {                                                    \
+        constexpr int PPL_ = PP / 2, VW_ = 2;                                \
+        __VA_ARGS__;                                                         \
+        break;                                                               \
+      }                                                                      \
+    }                                                                        \
+    {                                                                        \
+      constexpr int PPL_ = PP, VW_ = 1;                                      \
+      __VA_ARGS__;                                                           \
+    }                                                                        \
+  } while (0)
+
 // CG kernels (working type T): PPL_ lanes per row with VW_ adjacent columns
 // each, PPL_ VW_ = PP: VW_ = 8 for FP32 blocks of 16 or more columns with p a
 // multiple of 8 (kWide8), else 4 when p is a multiple of 4 and the block is
@@ -344,6 +365,16 @@ constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
 // from here: the basis, the inner solver's and the V-cycle's vectors, X,
 // the projected systems, the reductions and the Toeplitz FFT arrays.  The
 // plan holds only what its creation set up.
+// Whether the block Gram-Schmidt passes (orth_pass) can project a block of
+// p columns against npan panels: the matrix-core path takes up to 24 column
+// blocks of 16 for p <= 32; the other path keeps a workgroup's npan p x p
+// projection partials and one row of the panels in LDS (150 KB).
+bool basis_fits(int npan, int p, size_t elem) {
+  if (p <= 32 && (npan * p + 15) / 16 <= 24) return true;
+  const size_t O = size_t(npan) * p * p + p;
+  return O * 8 + (size_t(npan) * p + 2 * size_t(p)) * elem <= 150 * 1024;
+}
+
 size_t layout_workspace(expmv_plan_s* pl, int p, int nt, bool joined, char* work) {
   Carver c{work};
   Workspace w;
@@ -353,6 +384,13 @@ size_t layout_workspace(expmv_plan_s* pl, int p, int nt, bool joined, char* work
   const int ldh = (m + 1) * p;
   const int ns = kNShift * nt;
   const size_t elb = pl->basis32 ? sizeof(float) : sizeof(double);   // basis
+  if (!basis_fits(npan_max, p, elb)) {
+    std::snprintf(g_error_detail, sizeof(g_error_detail),
+                  "a basis of m + 1 = %d blocks of %d columns is wider than the block "
+                  "Gram-Schmidt passes take: lower m or p",
+                  npan_max, p);
+    throw StatusError{EXPMV_EINVAL};
+  }
   const size_t el = pl->mixed ? sizeof(float) : sizeof(double);      // inner solver
   const size_t blk = size_t(n) * p;
   const bool csr = pl->kind == 0;
@@ -906,10 +944,11 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
                                                  w.cgst, w.ctl, w.part_rr, tol2, maxit));
       }
       const KtEv ea = kt_take(pl, EXPMV_KT_CG_SPMM, by_a);
-      DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_a<T, PPL_, VW_>), dim3(grid),
-                                               dim3(kCgThreads), 0, s, ea.e0, ea.e1, 0, k, int(n),
-                                               p, A.rowptr, A.colind, A.val, pnew, q, w.ctl,
-                                               w.part_sig));
+      DISPATCH_PP(PP, SPMM_DISPATCH(T, P_, p,
+                                    hipExtLaunchKernelGGL((k_cg_a<T, PPL_, VW_>), dim3(grid),
+                                                          dim3(kCgThreads), 0, s, ea.e0, ea.e1, 0,
+                                                          k, int(n), p, A.rowptr, A.colind, A.val,
+                                                          pnew, q, w.ctl, w.part_sig)));
       const KtEv eb = kt_take(pl, EXPMV_KT_CG_RESID, by_b);
       DISPATCH_CG(PP, p, hipExtLaunchKernelGGL((k_cg_b<T, PPL_, VW_>), dim3(grid),
                                                dim3(kCgThreads), 0, s, eb.e0, eb.e1, 0, k, int(n),
@@ -925,35 +964,14 @@ InnerResult inner_cg(expmv_plan_s* pl, const T* src, double sign, T* out, int p)
   return res;
 }
 
-// BiCGStab's SpMM (k_bcg_s) with two adjacent columns per lane for even p
-// (four when p is a multiple of 4 and kWide4)
 template <typename T, int PP, int NV>
 void bcg_spmm(hipStream_t s, KtEv e, int grid, int i, int n, int p, const int32_t* rowptr,
               const int32_t* colind, const double* val, const T* dinv, const T* in, const T* a,
               T* out, const KrylovCtl* ctl, double* part) {
-  if constexpr (kWide8<T, PP>) {
-    if (p % 8 == 0) {
-      hipExtLaunchKernelGGL((k_bcg_s<T, PP / 8, 8, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0,
-                            e.e1, 0, i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
-      return;
-    }
-  }
-  if constexpr (kWide4<T, PP>) {
-    if (p % 4 == 0) {
-      hipExtLaunchKernelGGL((k_bcg_s<T, PP / 4, 4, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0,
-                            e.e1, 0, i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
-      return;
-    }
-  }
-  if constexpr (PP >= 2) {
-    if (p % 2 == 0) {
-      hipExtLaunchKernelGGL((k_bcg_s<T, PP / 2, 2, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0,
-                            e.e1, 0, i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
-      return;
-    }
-  }
-  hipExtLaunchKernelGGL((k_bcg_s<T, PP, 1, NV>), dim3(grid), dim3(kCgThreads), 0, s, e.e0, e.e1, 0,
-                        i, n, p, rowptr, colind, val, dinv, in, a, out, ctl, part);
+  SPMM_DISPATCH(T, PP, p,
+                hipExtLaunchKernelGGL((k_bcg_s<T, PPL_, VW_, NV>), dim3(grid), dim3(kCgThreads),
+                                      0, s, e.e0, e.e1, 0, i, n, p, rowptr, colind, val, dinv,
+                                      in, a, out, ctl, part));
 }
 
 // out = K^{-1} (sign * src) (or K^{-T}) by batched BiCGStab with right

@@ -342,6 +342,122 @@ __device__ inline void csr_row_dot_vw(const int32_t* __restrict__ colind,
   }
 }
 
+// Entries a0 .. a0 + U - 1 of a CSR row ending at a1 (j = -1, v = 0 past it).
+template <int U>
+__device__ inline void csr_entries(const int32_t* __restrict__ colind,
+                                   const double* __restrict__ val, int a0, int a1,
+                                   int32_t (&j)[U], double (&v)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool ok = a0 + u < a1;
+    j[u] = ok ? colind[a0 + u] : -1;
+    v[u] = ok ? val[a0 + u] : 0.0;
+  }
+}
+
+// For the rows row, row + st, ... < end of a CSR operator K:
+//   acc = K[row, :] y[:, c0 .. c0 + VW),  y = x (dinv NULL) or D^{-1} x,
+// then body(row, acc).  The loop is software-pipelined so that one row costs
+// one memory round trip instead of three: while the gathers of a row are in
+// flight, the first U entries of the next row and the extents of the row
+// after it are already being loaded.  Entries past the first U of a row
+// (rows longer than U) follow without prefetch.  The sum runs over the row's
+// entries in order, as csr_row_dot_vw does; inactive lanes (masked columns)
+// issue no gathers and get zero sums.
+template <int U, int VW, typename T, typename Body>
+__device__ inline void csr_rows_pipelined(const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ colind,
+                                          const double* __restrict__ val, const T* __restrict__ x,
+                                          const T* __restrict__ dinv, int ld, int c0, bool active,
+                                          int64_t row, int64_t st, int64_t end, Body&& body) {
+  int e0 = 0, e1 = 0, ne0 = 0, ne1 = 0;
+  if (row < end) {
+    e0 = rowptr[row];
+    e1 = rowptr[row + 1];
+  }
+  if (row + st < end) {
+    ne0 = rowptr[row + st];
+    ne1 = rowptr[row + st + 1];
+  }
+  int32_t j[U];
+  double v[U];
+  csr_entries<U>(colind, val, e0, e1, j, v);
+  for (; row < end; row += st) {
+    T w[U][VW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (active && j[u] >= 0) {
+        ld_vw<VW>(x + int64_t(j[u]) * ld + c0, w[u]);
+        if (dinv) {
+          const T dj = dinv[j[u]];
+#pragma unroll
+          for (int q = 0; q < VW; ++q) w[u][q] = dj * w[u][q];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < VW; ++q) w[u][q] = T(0);
+      }
+    }
+    int32_t nj[U];
+    double nv[U];
+    csr_entries<U>(colind, val, ne0, ne1, nj, nv);
+    int n2e0 = 0, n2e1 = 0;
+    if (row + 2 * st < end) {
+      n2e0 = rowptr[row + 2 * st];
+      n2e1 = rowptr[row + 2 * st + 1];
+    }
+    double acc[VW];
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < VW; ++q) acc[q] += v[u] * double(w[u][q]);
+    for (int e = e0 + U; e < e1; e += U) {
+      int32_t tj[U];
+      double tv[U];
+      csr_entries<U>(colind, val, e, e1, tj, tv);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (active && tj[u] >= 0) {
+          ld_vw<VW>(x + int64_t(tj[u]) * ld + c0, w[u]);
+          if (dinv) {
+            const T dj = dinv[tj[u]];
+#pragma unroll
+            for (int q = 0; q < VW; ++q) w[u][q] = dj * w[u][q];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < VW; ++q) w[u][q] = T(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < VW; ++q) acc[q] += tv[u] * double(w[u][q]);
+    }
+    body(row, acc);
+    e0 = ne0;
+    e1 = ne1;
+    ne0 = n2e0;
+    ne1 = n2e1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      j[u] = nj[u];
+      v[u] = nv[u];
+    }
+  }
+}
+
+// Entries per pipelined row step of the inner solver's SpMM: 8 (a 7-point
+// stencil row in one step) for up to 16 bytes of columns per lane; wider
+// lanes take 4, as 8 would spill past the 128 VGPRs a wave of a 1024-thread
+// workgroup may hold.
+template <typename T, int VW>
+constexpr int spmm_unroll() {
+  return (VW * sizeof(T) <= 16) ? 8 : 4;
+}
+
 // The CG kernels take VW adjacent columns per lane (VW = 2 for even p) and
 // PPL = PP / VW lanes per row; per-column scalars and partials keep the layout
 // of PP columns.
@@ -551,20 +667,20 @@ k_cg_a(int k, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* _
   for (int u = 0; u < VW; ++u) sig[u] = 0.0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
-    if (c0 < p) {
-      double acc[VW];
-      csr_row_dot_vw<VW>(colind, val, pk, rowptr[row], rowptr[row + 1], p, c0, acc);
-      const int64_t i = row * p + c0;
-      T qv[VW], pv[VW];
+  const bool active = c0 < p;
+  csr_rows_pipelined<spmm_unroll<T, VW>(), VW>(
+      rowptr, colind, val, pk, static_cast<const T*>(nullptr), p, c0, active,
+      seg0 + threadIdx.x / PPL, kCgThreads / PPL, seg1, [&](int64_t row, const double(&acc)[VW]) {
+        if (!active) return;
+        const int64_t i = row * p + c0;
+        T qv[VW], pv[VW];
 #pragma unroll
-      for (int u = 0; u < VW; ++u) qv[u] = T(acc[u]);
-      st_vw<VW>(q + i, qv);
-      ld_vw<VW>(pk + i, pv);
+        for (int u = 0; u < VW; ++u) qv[u] = T(acc[u]);
+        st_vw<VW>(q + i, qv);
+        ld_vw<VW>(pk + i, pv);
 #pragma unroll
-      for (int u = 0; u < VW; ++u) sig[u] += double(pv[u]) * double(qv[u]);
-    }
-  }
+        for (int u = 0; u < VW; ++u) sig[u] += double(pv[u]) * double(qv[u]);
+      });
   write_col_partial_vw<PPL, VW>(sig, red, part_sig, PP, 0);
 }
 
@@ -797,38 +913,24 @@ k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* 
   for (int q = 0; q < VW; ++q) d0[q] = d1[q] = 0.0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
-    if (c0 < p) {
-      const int e0 = rowptr[row], e1 = rowptr[row + 1];
-      double accd[VW];
-      if (dinv) {
+  const bool active = c0 < p;
+  csr_rows_pipelined<spmm_unroll<T, VW>(), VW>(
+      rowptr, colind, val, in, dinv, p, c0, active, seg0 + threadIdx.x / PPL, kCgThreads / PPL,
+      seg1, [&](int64_t row, const double(&accd)[VW]) {
+        if (!active) return;
+        const int64_t idx = row * p + c0;
+        T acc[VW], av[VW];
 #pragma unroll
-        for (int q = 0; q < VW; ++q) accd[q] = 0.0;
-        for (int e = e0; e < e1; ++e) {
-          const int64_t j = colind[e];
-          T xv[VW];
-          ld_vw<VW>(in + j * p + c0, xv);
-          const T dj = dinv[j];
+        for (int q = 0; q < VW; ++q) acc[q] = T(accd[q]);
+        st_vw<VW>(out + idx, acc);
+        ld_vw<VW>(a + idx, av);
 #pragma unroll
-          for (int q = 0; q < VW; ++q) accd[q] += val[e] * double(dj * xv[q]);
+        for (int q = 0; q < VW; ++q) {
+          const double o = double(acc[q]);
+          d0[q] += double(av[q]) * o;
+          if (NV == 2) d1[q] += o * o;
         }
-      } else {
-        csr_row_dot_vw<VW>(colind, val, in, e0, e1, p, c0, accd);
-      }
-      const int64_t idx = row * p + c0;
-      T acc[VW], av[VW];
-#pragma unroll
-      for (int q = 0; q < VW; ++q) acc[q] = T(accd[q]);
-      st_vw<VW>(out + idx, acc);
-      ld_vw<VW>(a + idx, av);
-#pragma unroll
-      for (int q = 0; q < VW; ++q) {
-        const double o = double(acc[q]);
-        d0[q] += double(av[q]) * o;
-        if (NV == 2) d1[q] += o * o;
-      }
-    }
-  }
+      });
   write_col_partial_vw<PPL, VW>(d0, red, part, NV * PP, 0);
   if (NV == 2) write_col_partial_vw<PPL, VW>(d1, red, part, NV * PP, PP);
 }

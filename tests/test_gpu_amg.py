@@ -182,6 +182,43 @@ def test_device_vcycle_nonsymmetric_matches_numpy(N, p, transpose):
     assert rel(Y, V.apply(X)) < 1e-12
 
 
+def _convdiff27(N):
+    """The upwind operator plus a symmetric M-matrix part with 27-point rows,
+    0.2 mean(diag K) (I - S (x) S (x) S), S = tridiag(1, 1, 1) / 3: operator
+    rows longer than one pipelined step of the inner SpMM (8 entries), and
+    fused transfer operators whose rows outgrow one step of the V-cycle
+    kernels (restriction rows of 200 to 335 entries)."""
+    import scipy.sparse as sp
+    A, t = _convdiff(N)
+    S = sp.diags([1.0, 1.0, 1.0], [-1, 0, 1], shape=(N, N)) / 3.0
+    K7 = -A.to_scipy()
+    K = (K7 + 0.2 * K7.diagonal().mean() * (sp.identity(A.n) - sp.kron(S, sp.kron(S, S)))).tocsr()
+    K.sort_indices()
+    return wl.CSR.from_scipy(-K), t
+
+
+@pytest.mark.parametrize("p,transpose", [(16, False), (6, True)])
+def test_long_rows_vcycle_and_inverse(p, transpose):
+    announce(f"27-point convdiff 16^3 p={p} transpose={transpose}: V-cycle and inverse")
+    A, t = _convdiff27(16)
+    pl = Plan.csr(A.rowptr, A.colind, A.val, t, device=DEV, inner_precond="amg",
+                  inner_tol=1e-13)
+    X = np.random.default_rng(p).standard_normal((A.n, p))
+    Y = pl.apply_preconditioner(torch.from_numpy(X), transpose=transpose).cpu().numpy()
+    K = (A.to_scipy() * (-t)).tocsr()
+    if transpose:
+        K = K.T.tocsr()
+        K.sort_indices()
+    H = HostAmg(K.indptr, K.indices, K.data, symmetric=False)
+    rf = np.diff(H.fused(0, "restriction", 0.5, 0.0)[0])
+    assert rf.mean() >= 32 and rf.max() > 80
+    assert rel(Y, VCycle(H.levels(), 1).apply(X)) < 1e-12
+    M = (t * A.to_scipy()).tocsr()
+    ref = inverses.splu_inverse(M.T.tocsr() if transpose else M)(X)
+    Yi, its = pl.apply_inverse(torch.from_numpy(X), transpose=transpose)
+    assert rel(Yi.cpu().numpy(), ref) < 1e-10, its
+
+
 @pytest.mark.parametrize("transpose", [False, True])
 def test_amg_bicgstab_inverse_matches_splu(transpose):
     announce(f"AMG BiCGStab inverse convdiff 24^3 transpose={transpose}")

@@ -202,6 +202,18 @@ def test_error_statuses():
     with pytest.raises(_lib.ExpmvError) as e:
         Plan.csr(W.A.rowptr, W.A.colind, -W.A.val, W.t, device=DEV)
     assert e.value.status == _lib.ENOTNEG
+    # a basis too wide for the block Gram-Schmidt (m = 20 at p = 32) is
+    # refused by the call and by the workspace size; m = 17 runs
+    W32 = wl.c1(N=32, p=32)
+    wide = plan_for(W32, m=20, k=32)
+    with pytest.raises(_lib.ExpmvError) as e:
+        wide.workspace_size(32)
+    assert e.value.status == _lib.EINVAL
+    with pytest.raises(_lib.ExpmvError) as e:
+        wide.execute(torch.from_numpy(W32.B), tol=1e-8)
+    assert e.value.status == _lib.EINVAL
+    Z32, _ = plan_for(W32, m=17, k=32).execute(torch.from_numpy(W32.B), tol=1e-8)
+    assert bool(torch.isfinite(Z32).all())
     # max_cycles = 1 on a problem that needs two cycles
     W1 = wl.c1()
     pl1 = plan_for(W1, m=4, k=4, max_cycles=1)
