@@ -242,6 +242,11 @@ struct expmv_plan_s {
   // nonsymmetric T: spectrum of the embedding of T^T, and of the generators
   // J y, Z y (y = T^{-1} e_n) beside x and Z J x (xhat, yhat)
   DevBuf<cplx> chatT, jyhat, zyhat;
+  // length-n Gohberg-Semencul form (n with no prime factor above 5): the
+  // radices of n and the spectra F x, F (Z_1 y), F D (J y), F D (Z_{-1} J x)
+  bool gsf_n = false;
+  std::vector<int> radices_n;
+  DevBuf<cplx> ncx, ncz, nsj, nsz;
   bool tsym = true;              // T symmetric (A = -diag(d) T symmetric needs d = 1 too)
   DevBuf<double> tdiag, tdinv;   // d and 1/d of A = -diag(d) T (empty: d = 1)
   DevBuf<cplx> setup_fb[3];      // L x 1 work arrays of the plan's own set-up transforms
@@ -1137,6 +1142,61 @@ void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy
                      Y, 0, 1.0, accumulate, transpose ? nullptr : dg);
 }
 
+// W = scale * T^{-1} V (or T^{-T} V) in the length-n form of the
+// Gohberg-Semencul formula.  T^{-1} - Z_1 T^{-1} Z_{-1}^T = (x (Jy)^T -
+// (Z_1 y)(Z_{-1} J x)^T) / x0, with Z_1 the cyclic and Z_{-1} the skew-cyclic
+// down-shift, so (the displacement of T^{-1} by a circulant and a
+// skew-circulant shift determines it)
+//   T^{-1} = (1/(2 x0)) (C(x) S(Jy)^T - C(Z_1 y) S(Z_{-1} J x)^T),
+//   T^{-T} = (1/(2 x0)) (S(Jy) C(x)^T - S(Z_{-1} J x) C(Z_1 y)^T),
+// C(g) the circulant and S(h) the skew-circulant with first column g, h;
+// x = T^{-1} e_1, y = T^{-1} e_n (the remark on fast Toeplitz inverses in
+// Section 2).  With F the DFT, D = diag(exp(i pi k / n)):
+//   C(g) u = F^{-1} (F g . F u),        C(g)^T u = F^{-1} (rev(F g) . F u),
+//   S(h) u = D^{-1} F^{-1} (F D h . F D u),
+//   S(h)^T u = D F^{-1} (rev(F D h) . F D^{-1} u),   rev(s)_k = s_{-k mod n}.
+// Six length-n FFTs per block (two real columns per complex column: every
+// factor is a real matrix, so it maps a + i b to its images of a and b).
+template <typename T>
+void toeplitz_gsf_n(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, double scale) {
+  const bool tr = transpose && !pl->tsym;
+  const double* di = pl->tdinv.p;
+  const int q = (p + 1) / 2;
+  check_fft_buffers(pl, q);
+  const int64_t n = pl->n;
+  const std::vector<int>& rad = pl->radices_n;
+  cplx *A = pl->ws.fb[0], *Bf = pl->ws.fb[1], *C = pl->ws.fb[2], *D = pl->ws.fb[3];
+  hipStream_t s = pl->stream;
+  const int g = stream_grid(n * q);
+  const double inv = 1.0 / double(n);
+  // the first factor pair: spectra applied reversed (transposed factors)
+  const cplx* f1 = tr ? pl->ncx.p : pl->nsj.p;
+  const cplx* f2 = tr ? pl->ncz.p : pl->nsz.p;
+  // the second pair
+  const cplx* g1 = tr ? pl->nsj.p : pl->ncx.p;
+  const cplx* g2 = tr ? pl->nsz.p : pl->ncz.p;
+  // A = V (rows scaled by 1/d in the forward product), twisted by D^{-1}
+  // for the skew-circulant S(.)^T that acts first in T^{-1}
+  hipLaunchKernelGGL((k_pack_twist<T>), dim3(g), dim3(kThreads), 0, s, n, p, int64_t(p), q, V,
+                     A, 1.0, transpose ? nullptr : di, tr ? 0.0 : -1.0);
+  fft_len(pl, n, rad, A, Bf, C, q, -1.0);
+  hipLaunchKernelGGL(k_spec_mul_rev_to, dim3(g), dim3(kThreads), 0, s, n, q, Bf, f1, C, inv);
+  hipLaunchKernelGGL(k_spec_mul_rev_to, dim3(g), dim3(kThreads), 0, s, n, q, Bf, f2, D, inv);
+  fft_len(pl, n, rad, C, A, Bf, q, +1.0);
+  fft_len(pl, n, rad, D, C, Bf, q, +1.0);
+  // D u: closes S(.)^T (forward) or opens S(.) (transposed)
+  hipLaunchKernelGGL(k_twist, dim3(g), dim3(kThreads), 0, s, n, q, A, 1.0);
+  hipLaunchKernelGGL(k_twist, dim3(g), dim3(kThreads), 0, s, n, q, C, 1.0);
+  fft_len(pl, n, rad, A, Bf, D, q, -1.0);
+  fft_len(pl, n, rad, C, A, D, q, -1.0);
+  hipLaunchKernelGGL(k_spec_mul2, dim3(g), dim3(kThreads), 0, s, n, q, Bf, g1, A, g2, D, inv);
+  fft_len(pl, n, rad, D, Bf, C, q, +1.0);
+  // D^{-1} closes S(.) (transposed); rows scaled by 1/d after T^{-T}
+  hipLaunchKernelGGL((k_unpack_twist<T>), dim3(stream_grid(n * p)), dim3(kThreads), 0, s, n, p,
+                     int64_t(p), q, Bf, W, scale / (2.0 * pl->x0), transpose ? di : nullptr,
+                     tr ? -1.0 : 0.0);
+}
+
 // W = scale * T^{-1} V (or T^{-T} V) by the Gohberg-Semencul formula
 //   T^{-1} = (1/x0) (L(x) L(Jy)^T - L(Zy) L(ZJx)^T),
 //   T^{-T} = (1/x0) (L(Jy) L(x)^T - L(ZJx) L(Zy)^T),
@@ -1148,6 +1208,10 @@ void toeplitz_apply(expmv_plan_s* pl, const T* X, int64_t ldx, T* Y, int64_t ldy
 // diag(1/d) T^{-T} (1/d scales W's rows on unpacking).
 template <typename T>
 void toeplitz_gsf(expmv_plan_s* pl, int transpose, const T* V, T* W, int p, double scale) {
+  if (pl->gsf_n) {
+    toeplitz_gsf_n<T>(pl, transpose, V, W, p, scale);
+    return;
+  }
   const bool tr = transpose && !pl->tsym;
   const cplx* gx = pl->xhat.p;                                // x
   const cplx* gzjx = pl->yhat.p;                              // Z J x
@@ -2566,17 +2630,40 @@ expmv_status build_toeplitz(expmv_plan_s* pl, const std::vector<double>& c,
     yh.resize(n);
     HIPCHK(hipMemcpy(yh.data(), yd.p, sizeof(double) * n, hipMemcpyDeviceToHost));
   }
-  std::vector<double> e(L, 0.0);
-  auto gen = [&](auto f, DevBuf<cplx>& dst) {
-    std::fill(e.begin(), e.end(), 0.0);
-    for (int64_t i = 0; i < n; ++i) e[i] = f(i);
-    spectrum(e, dst);
-  };
-  gen([&](int64_t i) { return xh[i]; }, pl->xhat);                            // x
-  gen([&](int64_t i) { return i ? xh[n - i] : 0.0; }, pl->yhat);             // Z J x
-  if (!pl->tsym) {
-    gen([&](int64_t i) { return yh[n - 1 - i]; }, pl->jyhat);                 // J y
-    gen([&](int64_t i) { return i ? yh[i - 1] : 0.0; }, pl->zyhat);          // Z y
+  // the length-n form when n has no prime factor above 5 (spectra of x,
+  // Z_1 y, D J y and D Z_{-1} J x, D = diag(exp(i pi k / n))), else the
+  // triangular factors through the length-L embedding (spectra of the
+  // zero-padded x, Z J x, J y, Z y)
+  pl->radices_n = fft_radices(n);
+  pl->gsf_n = !pl->radices_n.empty() && n >= 2;
+  if (!pl->gsf_n) {
+    std::vector<double> e(L, 0.0);
+    auto gen = [&](auto f, DevBuf<cplx>& dst) {
+      std::fill(e.begin(), e.end(), 0.0);
+      for (int64_t i = 0; i < n; ++i) e[i] = f(i);
+      spectrum(e, dst);
+    };
+    gen([&](int64_t i) { return xh[i]; }, pl->xhat);                            // x
+    gen([&](int64_t i) { return i ? xh[n - i] : 0.0; }, pl->yhat);             // Z J x
+    if (!pl->tsym) {
+      gen([&](int64_t i) { return yh[n - 1 - i]; }, pl->jyhat);                 // J y
+      gen([&](int64_t i) { return i ? yh[i - 1] : 0.0; }, pl->zyhat);          // Z y
+    }
+  } else {
+    auto spectrum_n = [&](auto f, double sign, DevBuf<cplx>& dst) {
+      std::vector<double> h(n);
+      for (int64_t i = 0; i < n; ++i) h[i] = f(i);
+      dst.alloc(n);
+      HIPCHK(hipMemcpyAsync(tmp.p, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL((k_pack_twist<double>), dim3(stream_grid(n)), dim3(kThreads), 0, s, n, 1,
+                         int64_t(1), 1, tmp.p, pl->setup_fb[0].p, 1.0, nullptr, sign);
+      fft_len(pl, n, pl->radices_n, pl->setup_fb[0].p, dst.p, pl->setup_fb[1].p, 1, -1.0);
+      HIPCHK(hipStreamSynchronize(s));
+    };
+    spectrum_n([&](int64_t i) { return xh[i]; }, 0.0, pl->ncx);                       // x
+    spectrum_n([&](int64_t i) { return yh[(i + n - 1) % n]; }, 0.0, pl->ncz);          // Z_1 y
+    spectrum_n([&](int64_t i) { return yh[n - 1 - i]; }, 1.0, pl->nsj);                // J y
+    spectrum_n([&](int64_t i) { return i ? xh[n - i] : -xh[0]; }, 1.0, pl->nsz);       // Z_{-1} J x
   }
   HIPCHK(hipStreamSynchronize(s));
   for (auto& b : pl->setup_fb) b.release();

@@ -346,6 +346,73 @@ k_rev_trunc(int64_t L, int64_t n, int q, const cplx* __restrict__ in, cplx* __re
   }
 }
 
+// ---------------------------------------------------------------------------
+// Length-n form of the Gohberg-Semencul inverse: products with n x n
+// circulants C(g) = F^{-1} diag(F g) F and skew-circulants
+// S(h) = D^{-1} C(D h) D, D = diag(exp(i pi k / n)), so every transform has
+// length n (no embedding).  exp(sign i pi k / n) is the "twist" below.
+
+__device__ inline cplx twist_factor(int64_t k, int64_t n, double sign) {
+  double si, co;
+  sincospi(sign * double(k) / double(n), &si, &co);
+  return {co, si};
+}
+
+// out (n x q complex) = rows of src (n x p real) two real columns per complex
+// column (2c -> real, 2c+1 -> imaginary), times scale (and rs[row] when rs is
+// not null), then times exp(sign i pi row / n) (sign 0: no twist)
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_pack_twist(int64_t n, int p, int64_t ld, int q, const T* __restrict__ src,
+             cplx* __restrict__ out, double scale, const double* __restrict__ rs, double sign) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < n * q;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t i = gid / q;
+    const int c = int(gid % q);
+    const double sc = rs ? scale * rs[i] : scale;
+    cplx v{sc * double(src[i * ld + 2 * c]), 0.0};
+    if (2 * c + 1 < p) v.y = sc * double(src[i * ld + 2 * c + 1]);
+    out[gid] = sign != 0.0 ? cmul(v, twist_factor(i, n, sign)) : v;
+  }
+}
+
+// dst (n x p real) = scale (times rs[i] when rs is not null) times the two
+// real columns of exp(sign i pi i / n) in[i, c] (sign 0: no twist)
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_unpack_twist(int64_t n, int p, int64_t ld, int q, const cplx* __restrict__ in,
+               T* __restrict__ dst, double scale, const double* __restrict__ rs, double sign) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < n * p;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t i = gid / p;
+    const int col = int(gid % p);
+    cplx v = in[i * q + col / 2];
+    if (sign != 0.0) v = cmul(v, twist_factor(i, n, sign));
+    dst[i * ld + col] = T((rs ? scale * rs[i] : scale) * ((col & 1) ? v.y : v.x));
+  }
+}
+
+// data[i, c] *= exp(sign i pi i / n)
+__global__ void __launch_bounds__(kThreads)
+k_twist(int64_t n, int q, cplx* __restrict__ data, double sign) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < n * q;
+       gid += int64_t(gridDim.x) * kThreads)
+    data[gid] = cmul(data[gid], twist_factor(gid / q, n, sign));
+}
+
+// out[i, c] = in[i, c] * h[(n - i) mod n] * scale: the spectrum of the
+// transposed circulant (index reversal of the spectrum)
+__global__ void __launch_bounds__(kThreads)
+k_spec_mul_rev_to(int64_t n, int q, const cplx* __restrict__ in, const cplx* __restrict__ h,
+                  cplx* __restrict__ out, double scale) {
+  for (int64_t gid = int64_t(blockIdx.x) * kThreads + threadIdx.x; gid < n * q;
+       gid += int64_t(gridDim.x) * kThreads) {
+    const int64_t i = gid / q;
+    const cplx v = cmul(in[gid], h[i == 0 ? 0 : n - i]);
+    out[gid] = {scale * v.x, scale * v.y};
+  }
+}
+
 // partial sums of x . y (FP64 vectors of length len) per workgroup
 __global__ void __launch_bounds__(kThreads)
 k_dot_partial(int64_t len, const double* __restrict__ x, const double* __restrict__ y,

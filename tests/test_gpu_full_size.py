@@ -3,9 +3,18 @@ benchmark times, against references the oracle computed once
 (tests/golden/make_full_size_references.py): a seeded sample of rows of the
 result plus the norms of the whole result.
 
-Bars (relative to the reference, written in each test):
-  FP64 form: the sampled rows within 1e-10 in the Frobenius norm, every
-    sampled entry within 1e-10 ||ref||_max, ||Z||_F within 1e-10;
+Bars.  The error of the computed Z splits into the CF form's own error and
+the weighted errors of the shifted solves (Section 4.2).  The CF error is
+uniform on the negative axis, about 3e-14 ||B|| for degree 14 (Section 2),
+so the accuracy scale of the method is ||B||, not ||Z||.  Each check is
+therefore  ||Z - ref|| <= bar ||ref|| + FLOOR ||B||,  FLOOR = 1e-13 (three
+times the CF error).  The floor matters where ||Z|| << ||B||: on the
+1024^2 workload ||Z||/||B|| = 1.75e-4, and there the oracle's own
+Algorithm 2 with exact inner solves already differs from its direct
+per-pole solves by 6.7e-11 at 512^2, growing with the grid: the method's
+rounding floor.  bar is written in each test:
+  FP64 form: 1e-10 on the sampled rows (Frobenius), on every sampled entry
+    (against ||ref||_max, with FLOOR max|B|) and on ||Z||_F;
   mixed form: the same at 1e-5.
 The 3D convection-diffusion operator (128^3) also gets the invariants of an
 M-matrix exponential at full size (positivity for B >= 0 within the CF
@@ -36,17 +45,30 @@ def load(name):
     return np.load(path)
 
 
-def check_sample(Z, g, bar, key="Z", fro="fro", maxabs="maxabs", what="Z"):
-    rows = torch.from_numpy(g["rows"]).to(Z.device)
+FLOOR = 1e-13
+
+
+def check_sample(Z, g, bar, B, key="Z", fro="fro", maxabs="maxabs", what="Z"):
+    """Sampled rows, entries and the whole norm of Z against the reference,
+    each within bar times the reference plus FLOOR times the same measure of
+    the right-hand side B (host array, all rows)."""
+    rows_np = g["rows"]
+    rows = torch.from_numpy(rows_np).to(Z.device)
     Zs = Z[rows].cpu().numpy()
     ref = g[key]
-    e_f = float(np.linalg.norm(Zs - ref) / np.linalg.norm(ref))
+    Bs = B[rows_np]
+    nref, nB = np.linalg.norm(ref), np.linalg.norm(Bs)
+    e_f = float(np.linalg.norm(Zs - ref) / nref)
     e_m = float(np.abs(Zs - ref).max() / float(g[maxabs]))
     e_n = abs(float(torch.linalg.norm(Z)) / float(g[fro]) - 1.0)
-    print(f"{what}: sampled rel {e_f:.2e}, max-abs {e_m:.2e}, norm {e_n:.2e}", flush=True)
-    assert e_f < bar, e_f
-    assert e_m < bar, e_m
-    assert e_n < bar, e_n
+    b_f = bar + FLOOR * nB / nref
+    b_m = bar + FLOOR * float(np.abs(B).max()) / float(g[maxabs])
+    b_n = bar + FLOOR * float(np.linalg.norm(B)) / float(g[fro])
+    print(f"{what}: sampled rel {e_f:.2e} (bar {b_f:.2e}), max-abs {e_m:.2e} (bar {b_m:.2e}), "
+          f"norm {e_n:.2e} (bar {b_n:.2e})", flush=True)
+    assert e_f < b_f, e_f
+    assert e_m < b_m, e_m
+    assert e_n < b_n, e_n
 
 
 # --------------------------------------------------------------------------- 128^3
@@ -72,7 +94,7 @@ def test_convdiff128_matches_oracle(convdiff128, precision, tol, bar):
     Z, info = pl.execute(B, tol=tol)
     print(f"cycles {info.cycles} inner {info.inner_iters} true_res {max(info.true_res):.2e} "
           f"noncollinear {max(info.noncollinear):.2e}", flush=True)
-    check_sample(Z, load("convdiff128.npz"), bar)
+    check_sample(Z, load("convdiff128.npz"), bar, W.B)
 
 
 def test_convdiff128_m_matrix_invariants_and_linearity(convdiff128):
@@ -111,9 +133,10 @@ def test_vardiff1024_forward_and_adjoint_match_oracle(precision, tol, bar):
     B = torch.from_numpy(W.B).to(DEV)
     G = torch.from_numpy(wl.c5_weights()).to(DEV)
     Z, info = pl.execute(B, tol=tol)
-    check_sample(Z, g, bar)
+    check_sample(Z, g, bar, W.B)
     gB, gt, info_b = pl.adjoint(G, B, tol=tol)
-    check_sample(gB, g, bar, key="G", fro="gfro", maxabs="gmaxabs", what="grad_B")
+    check_sample(gB, g, bar, wl.c5_weights(), key="G", fro="gfro", maxabs="gmaxabs",
+                 what="grad_B")
     ref_t = float(g["grad_t"])
     e_t = abs(gt - ref_t) / abs(ref_t)
     print(f"grad_t {gt:.12e} ref {ref_t:.12e} rel {e_t:.2e}", flush=True)
@@ -129,4 +152,4 @@ def test_toeplitz2p20_matches_oracle():
     pl = Plan.toeplitz(torch.from_numpy(W.col), W.t, device=DEV, m=W.m, k=W.k)
     Z, info = pl.execute(torch.from_numpy(W.B).to(DEV), tol=W.tol)
     print(f"cycles {info.cycles} true_res {max(info.true_res):.2e}", flush=True)
-    check_sample(Z, g, 1e-10)
+    check_sample(Z, g, 1e-10, W.B)

@@ -315,8 +315,11 @@ def toe_plan(W, **opts):
     return Plan.toeplitz(torch.from_numpy(W.col), W.t, device=DEV, **opts)
 
 
-@pytest.mark.parametrize("n,p", [(1000, 3), (1024, 4), (4096, 16)])
+@pytest.mark.parametrize("n,p", [(1000, 3), (1024, 4), (4096, 16), (1001, 3)])
 def test_toeplitz_operator_and_inverse(n, p):
+    """n with prime factors up to 5: the length-n circulant / skew-circulant
+    form of the Gohberg-Semencul inverse; n = 1001 = 7 11 13: the triangular
+    factors through the length-2048 embedding."""
     announce(f"toeplitz operator n={n} p={p}")
     W = wl.c3(n=n, p=p)
     pl = toe_plan(W)

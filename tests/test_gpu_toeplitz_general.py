@@ -29,7 +29,9 @@ def plan(col, row, t, **opts):
     return Plan.toeplitz(torch.from_numpy(col), t, device=DEV, row0=torch.from_numpy(row), **opts)
 
 
-@pytest.mark.parametrize("n,p", [(1000, 3), (1024, 2)])   # 1024: Strang-preconditioned set-up
+# 1024: Strang-preconditioned set-up; 1001 = 7 11 13: the embedding form of
+# the inverse (the others take the length-n form)
+@pytest.mark.parametrize("n,p", [(1000, 3), (1024, 2), (1001, 3)])
 def test_operator_and_inverse_both_directions(n, p):
     announce(f"fractional toeplitz operator/inverse n={n} p={p}")
     col, row = wl.fractional_toeplitz(n)
