@@ -16,6 +16,9 @@ Also measured, after the timed region and with fewer repetitions:
   c5            2D log-normal diffusion 1024^2, p = 32, t = 0.1: forward,
                 adjoint (grad_B, grad_t) and forward + adjoint times, FP64
                 and mixed, with errors against the oracle's references;
+  toeplitz2p20  symmetric Toeplitz n = 2^20, p = 16, FP64 (length-n
+                Gohberg-Semencul inverse): time per solve (five solves after
+                a warm-up) and error against the oracle's reference;
   roofline      one more FP64 solve with kernel timing on (every 4th inner
                 iteration's launches timed with HIP events on the solver's
                 stream): the kernel class with the largest device time per
@@ -42,7 +45,14 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # HBM bytes per launch of a kernel class on the timed workload from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a
 # 256 MiB device copy), valid while the sources hash to the recorded value.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # profiles/psbfom_amg_bicgstab_convdiff128_p16_fp64_traffic.md:
+    # k_amg_affine_pair<double, 4, 4, 1024, true>, 601,348.4 KiB fetched and
+    # 262,145.0 KiB written per dispatch
+    "amg_prolong": {"bytes": 1499998003,
+                    "sources": ["amg.hpp", "kernels.hpp", "expmv.hip"],
+                    "sha256": "b75bc6ac3b79e6ed427fc511d26f2d8363b6961b0b572ad4cc68b33dc4a7c93f"},
+}
 
 
 def sources_hash(names) -> str:
@@ -259,6 +269,16 @@ def main():
             del pl5, Z5, gB
         extras["c5_vardiff1024_p32"] = c5
         print("[bench] 1024^2 forward + adjoint done", file=sys.stderr, flush=True)
+        T3 = wl.c3()
+        pl3 = Plan.toeplitz(torch.from_numpy(T3.col), T3.t, device=dev, m=T3.m, k=T3.k)
+        B3 = torch.from_numpy(T3.B).to(dev)
+        s3, (Z3, i3) = timed(lambda: pl3.execute(B3, tol=T3.tol), max(5, args.extra_reps))
+        extras["toeplitz2p20"] = {
+            "s_per_solve": round(s3, 5), "tol": T3.tol, "cycles": i3.cycles,
+            "block_apps": i3.block_apps,
+            "vs_oracle": sampled_error(Z3, "toeplitz2p20.npz")}
+        del pl3, Z3
+        print("[bench] Toeplitz 2^20 done", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
