@@ -1021,21 +1021,27 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
       kt.sampling = pl->opts.profile > 0 && ((i + 1) % pl->opts.profile) == 0;
       DISPATCH_PP(PP, {
         const KtEv e1 = kt_take(pl, EXPMV_KT_BCG_U1, 4 * blk);
-        hipExtLaunchKernelGGL((k_bcg_u1<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, e1.e0, e1.e1,
-                              0, i, int(n), p, r, pv, v, w.bcgst, w.ctl, w.part_rr, tol2, maxit);
+        SPMM_DISPATCH(T, P_, p,
+                      hipExtLaunchKernelGGL((k_bcg_u1<T, PPL_, VW_>), dim3(grid),
+                                            dim3(kCgThreads), 0, s, e1.e0, e1.e1, 0, i, int(n),
+                                            p, r, pv, v, w.bcgst, w.ctl, w.part_rr, tol2, maxit));
         if (H) amg_vcycle<T>(pl, *H, p, pv, ph, i, w.ctl, nullptr);
         bcg_spmm<T, P_, 1>(s, kt_take(pl, EXPMV_KT_BCG_SPMM1, by_s), grid, i, int(n), p, A.rowptr,
                            A.colind, A.val, dscale, H ? ph : pv, rh, v, w.ctl, w.part_sig);
         const KtEv e2 = kt_take(pl, EXPMV_KT_BCG_U2, 3 * blk);
-        hipExtLaunchKernelGGL((k_bcg_u2<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, e2.e0, e2.e1,
-                              0, i, int(n), p, r, v, sv, w.bcgst, w.ctl, w.part_sig);
+        SPMM_DISPATCH(T, P_, p,
+                      hipExtLaunchKernelGGL((k_bcg_u2<T, PPL_, VW_>), dim3(grid),
+                                            dim3(kCgThreads), 0, s, e2.e0, e2.e1, 0, i, int(n),
+                                            p, r, v, sv, w.bcgst, w.ctl, w.part_sig));
         if (H) amg_vcycle<T>(pl, *H, p, sv, sh, i, w.ctl, nullptr);
         bcg_spmm<T, P_, 2>(s, kt_take(pl, EXPMV_KT_BCG_SPMM2, by_s), grid, i, int(n), p, A.rowptr,
                            A.colind, A.val, dscale, H ? sh : sv, sv, tv, w.ctl, w.part_sig);
         const KtEv e3 = kt_take(pl, EXPMV_KT_BCG_U3, by_u3);
-        hipExtLaunchKernelGGL((k_bcg_u3<T, P_>), dim3(grid), dim3(kCgThreads), 0, s, e3.e0, e3.e1,
-                              0, i, int(n), p, A.dinv, pv, sv, tv, rh, ph, sh, out, r, w.bcgst,
-                              w.ctl, w.part_sig, w.part_rr);
+        SPMM_DISPATCH(T, P_, p,
+                      hipExtLaunchKernelGGL((k_bcg_u3<T, PPL_, VW_>), dim3(grid),
+                                            dim3(kCgThreads), 0, s, e3.e0, e3.e1, 0, i, int(n),
+                                            p, A.dinv, pv, sv, tv, rh, ph, sh, out, r, w.bcgst,
+                                            w.ctl, w.part_sig, w.part_rr));
       });
     }
     kt.cur_iter = -1;

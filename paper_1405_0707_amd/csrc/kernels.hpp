@@ -813,10 +813,13 @@ k_bcg_init(int n, int p, double sign, const TS* __restrict__ src, T* __restrict_
   }
 }
 
-template <typename T, int PP>
+// The three BiCGStab updates take VW adjacent columns per lane (PPL = PP / VW
+// lanes per row; VW = 2 for even p: 16-byte FP64 accesses) like the SpMM.
+template <typename T, int PPL, int VW>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const T* __restrict__ v,
          BcgState* st, KrylovCtl* ctl, const double* __restrict__ part_rr, double tol2, int maxit) {
+  constexpr int PP = PPL * VW;
   if (finished_before(ctl, i)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
@@ -884,14 +887,25 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
   }
   __syncthreads();
   if (!s_any) return;
-  const int c = threadIdx.x % PP;
-  const T beta = T(s_beta[c]), om = T(s_om[c]);
+  const int c0 = VW * (threadIdx.x % PPL);
+  T beta[VW], om[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) {
+    beta[q] = T(s_beta[(c0 + q) % PP]);
+    om[q] = T(s_om[(c0 + q) % PP]);
+  }
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
-      const int64_t idx = row * p + c;
-      pv[idx] = r[idx] + beta * (pv[idx] - om * v[idx]);
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
+      const int64_t idx = row * p + c0;
+      T rv[VW], pw[VW], vv[VW];
+      ld_vw<VW>(r + idx, rv);
+      ld_vw<VW>(pv + idx, pw);
+      ld_vw<VW>(v + idx, vv);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) pw[q] = rv[q] + beta[q] * (pw[q] - om[q] * vv[q]);
+      st_vw<VW>(pv + idx, pw);
     }
   }
 }
@@ -935,10 +949,11 @@ k_bcg_s(int i, int n, int p, const int32_t* __restrict__ rowptr, const int32_t* 
   if (NV == 2) write_col_partial_vw<PPL, VW>(d1, red, part, NV * PP, PP);
 }
 
-template <typename T, int PP>
+template <typename T, int PPL, int VW>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_u2(int i, int n, int p, const T* __restrict__ r, const T* __restrict__ v, T* __restrict__ sv,
          BcgState* st, const KrylovCtl* ctl, const double* __restrict__ part) {
+  constexpr int PP = PPL * VW;
   if (finished_by(ctl, i)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[PP];
@@ -953,25 +968,33 @@ k_bcg_u2(int i, int n, int p, const T* __restrict__ r, const T* __restrict__ v, 
     s_a[cc] = a;
   }
   __syncthreads();
-  const int c = threadIdx.x % PP;
-  const T a = T(s_a[c]);
+  const int c0 = VW * (threadIdx.x % PPL);
+  T a[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) a[q] = T(s_a[(c0 + q) % PP]);
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
-      const int64_t idx = row * p + c;
-      sv[idx] = r[idx] - a * v[idx];
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
+      const int64_t idx = row * p + c0;
+      T rv[VW], vv[VW];
+      ld_vw<VW>(r + idx, rv);
+      ld_vw<VW>(v + idx, vv);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) rv[q] = rv[q] - a[q] * vv[q];
+      st_vw<VW>(sv + idx, rv);
     }
   }
 }
 
-template <typename T, int PP>
+template <typename T, int PPL, int VW>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_u3(int i, int n, int p, const T* __restrict__ dinv, const T* __restrict__ pv,
          const T* __restrict__ sv, const T* __restrict__ tv, const T* __restrict__ rhat,
          const T* __restrict__ ph, const T* __restrict__ sh, T* __restrict__ x,
          T* __restrict__ r, BcgState* st, const KrylovCtl* ctl, const double* __restrict__ part,
          double* __restrict__ part_rr) {
+  constexpr int PP = PPL * VW;
   if (finished_by(ctl, i)) return;
   __shared__ double red[kCgThreads];
   __shared__ double tot[2 * PP];
@@ -990,29 +1013,50 @@ k_bcg_u3(int i, int n, int p, const T* __restrict__ dinv, const T* __restrict__ 
     s_om[cc] = om;
   }
   __syncthreads();
-  const int c = threadIdx.x % PP;
-  const T a = T(s_a[c]), om = T(s_om[c]);
-  double rr_hat = 0.0, rr = 0.0;
+  const int c0 = VW * (threadIdx.x % PPL);
+  T a[VW], om[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) {
+    a[q] = T(s_a[(c0 + q) % PP]);
+    om[q] = T(s_om[(c0 + q) % PP]);
+  }
+  double rr_hat[VW], rr[VW];
+#pragma unroll
+  for (int q = 0; q < VW; ++q) rr_hat[q] = rr[q] = 0.0;
   int64_t seg0, seg1;
   xcd_rows(n, seg0, seg1);
-  for (int64_t row = seg0 + threadIdx.x / PP; row < seg1; row += kCgThreads / PP) {
-    if (c < p) {
-      const int64_t idx = row * p + c;
-      const T sval = sv[idx];
+  for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
+    if (c0 < p) {
+      const int64_t idx = row * p + c0;
+      T sval[VW], xv[VW], tw[VW], rh[VW], u[VW], w[VW];
+      ld_vw<VW>(sv + idx, sval);
+      ld_vw<VW>(x + idx, xv);
+      ld_vw<VW>(tv + idx, tw);
+      ld_vw<VW>(rhat + idx, rh);
       if (ph) {
-        x[idx] += a * ph[idx] + om * sh[idx];
+        ld_vw<VW>(ph + idx, u);
+        ld_vw<VW>(sh + idx, w);
+#pragma unroll
+        for (int q = 0; q < VW; ++q) xv[q] += a[q] * u[q] + om[q] * w[q];
       } else {
         const T dv = dinv[row];
-        x[idx] += a * (dv * pv[idx]) + om * (dv * sval);
+        ld_vw<VW>(pv + idx, u);
+#pragma unroll
+        for (int q = 0; q < VW; ++q) xv[q] += a[q] * (dv * u[q]) + om[q] * (dv * sval[q]);
       }
-      const T rn = sval - om * tv[idx];
-      r[idx] = rn;
-      rr_hat += double(rhat[idx]) * double(rn);
-      rr += double(rn) * double(rn);
+      st_vw<VW>(x + idx, xv);
+      T rn[VW];
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        rn[q] = sval[q] - om[q] * tw[q];
+        rr_hat[q] += double(rh[q]) * double(rn[q]);
+        rr[q] += double(rn[q]) * double(rn[q]);
+      }
+      st_vw<VW>(r + idx, rn);
     }
   }
-  write_col_partial<PP>(rr_hat, red, part_rr, 2 * PP, 0);
-  write_col_partial<PP>(rr, red, part_rr, 2 * PP, PP);
+  write_col_partial_vw<PPL, VW>(rr_hat, red, part_rr, 2 * PP, 0);
+  write_col_partial_vw<PPL, VW>(rr, red, part_rr, 2 * PP, PP);
 }
 
 // R = V + K W (the residual of M W = V, M = -K) in FP64 from blocks of type
