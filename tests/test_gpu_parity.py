@@ -345,10 +345,10 @@ def test_toeplitz_execute_matches_direct_rational(n, p):
 
 
 def test_toeplitz_full_size_properties():
-    """n = 2^20, p = 16, m = 10 (the full Toeplitz workload): no direct
-    reference exists at this size, so check properties that hold at any size:
-    contraction, the symmetric adjoint identity, and agreement of the FP64
-    and mixed forms."""
+    """n = 2^20, p = 16, m = 10 (the full Toeplitz workload): properties that
+    hold at any size, contraction and the symmetric adjoint identity (the
+    oracle parity at this size is test_gpu_full_size.py's
+    test_toeplitz2p20_matches_oracle)."""
     announce("toeplitz 2^20 p=16")
     W = wl.c3()
     pl = toe_plan(W, m=W.m, k=W.k)
