@@ -50,15 +50,42 @@ k_shift_residual(int64_t n, int p, const int32_t* __restrict__ rowptr,
     if (c < p) {
       const double bv = B[row * p + c];
       int e0 = 0, e1 = 0;
+      // the row's first kRU entries, loaded once for all seven poles
+      constexpr int kRU = 8;
+      int32_t jj[kRU];
+      double vv[kRU];
       if (rowptr) {
         e0 = rowptr[row];
         e1 = rowptr[row + 1];
+#pragma unroll
+        for (int u = 0; u < kRU; ++u) {
+          const bool ok = e0 + u < e1;
+          jj[u] = ok ? colind[e0 + u] : -1;
+          vv[u] = ok ? val[e0 + u] : 0.0;
+        }
       }
 #pragma unroll 1
       for (int j = 0; j < kNShift; ++j) {
         double kr = 0.0, ki = 0.0;
         if (rowptr) {
-          for (int e = e0; e < e1; ++e) {
+          // the gathers of one pole all in flight, in the row's order
+          double xr[kRU], xi[kRU];
+#pragma unroll
+          for (int u = 0; u < kRU; ++u) {
+            if (jj[u] >= 0) {
+              const double* xc = X + int64_t(jj[u]) * ldx + 2 * p * j;
+              xr[u] = xc[c];
+              xi[u] = xc[p + c];
+            } else {
+              xr[u] = xi[u] = 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kRU; ++u) {
+            kr += vv[u] * xr[u];
+            ki += vv[u] * xi[u];
+          }
+          for (int e = e0 + kRU; e < e1; ++e) {
             const double* xc = X + int64_t(colind[e]) * ldx + 2 * p * j;
             kr += val[e] * xc[c];
             ki += val[e] * xc[p + c];
@@ -100,10 +127,25 @@ __device__ inline void res_rows(int64_t n, int64_t& r0, int64_t& r1) {
 // (V: the last basis block, n x p in the basis type; R: n x W FP64, W = 14p
 // <= 2 kThreads).  Thread t owns columns t and t + kThreads; every thread of
 // a row reads the same p entries of V.
+// The workgroup's rows go in chunks of kResChunk: the chunk's rows of V are
+// staged in LDS (one coalesced load), then every thread walks them kResU
+// rows at a time with all of those rows' R loads issued together.
+constexpr int kResChunk = 64, kResU = 8;
+
+template <typename T, int PP>
+__device__ inline void stage_v_chunk(const T* __restrict__ V, int p, int64_t i0, int rows,
+                                     double (*sv)[PP]) {
+  for (int e = threadIdx.x; e < rows * PP; e += kThreads) {
+    const int r = e / PP, a = e % PP;
+    sv[r][a] = a < p ? double(V[(i0 + r) * p + a]) : 0.0;
+  }
+}
+
 template <typename T, int PP>
 __global__ void __launch_bounds__(kThreads)
 k_project_block(int64_t n, int p, const T* __restrict__ V, const double* __restrict__ R, int W,
                 double* __restrict__ partial) {
+  __shared__ double sv[kResChunk][PP];
   const int col0 = threadIdx.x, col1 = threadIdx.x + kThreads;
   const bool has0 = col0 < W, has1 = col1 < W;
   double a0[PP], a1[PP];
@@ -111,15 +153,29 @@ k_project_block(int64_t n, int p, const T* __restrict__ V, const double* __restr
   for (int a = 0; a < PP; ++a) a0[a] = a1[a] = 0.0;
   int64_t r0, r1;
   res_rows(n, r0, r1);
-  for (int64_t i = r0; i < r1; ++i) {
-    const double x0 = has0 ? R[i * W + col0] : 0.0;
-    const double x1 = has1 ? R[i * W + col1] : 0.0;
+  for (int64_t i0 = r0; i0 < r1; i0 += kResChunk) {
+    const int rows = int(min<int64_t>(kResChunk, r1 - i0));
+    __syncthreads();   // the previous chunk is consumed
+    stage_v_chunk<T, PP>(V, p, i0, rows, sv);
+    __syncthreads();
+    for (int r = 0; r < rows; r += kResU) {
+      double x0[kResU], x1[kResU];
 #pragma unroll
-    for (int a = 0; a < PP; ++a) {
-      if (a < p) {
-        const double v = double(V[i * p + a]);
-        a0[a] += v * x0;
-        a1[a] += v * x1;
+      for (int u = 0; u < kResU; ++u) {
+        const bool ok = r + u < rows;
+        const int64_t i = i0 + r + u;
+        x0[u] = (ok && has0) ? R[i * W + col0] : 0.0;
+        x1[u] = (ok && has1) ? R[i * W + col1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kResU; ++u) {
+        if (r + u >= rows) continue;   // past the chunk (sv there is stale)
+#pragma unroll
+        for (int a = 0; a < PP; ++a) {
+          const double v = sv[r + u][a];
+          a0[a] += v * x0[u];
+          a1[a] += v * x1[u];
+        }
       }
     }
   }
@@ -149,22 +205,37 @@ k_remainder_norms(int64_t n, int p, const T* __restrict__ V, const double* __res
     c0[a] = (a < p && has0) ? C[a * W + col0] : 0.0;
     c1[a] = (a < p && has1) ? C[a * W + col1] : 0.0;
   }
+  __shared__ double sv[kResChunk][PP];
   double s0 = 0.0, s1 = 0.0;
   int64_t r0, r1;
   res_rows(n, r0, r1);
-  for (int64_t i = r0; i < r1; ++i) {
-    double e0 = has0 ? R[i * W + col0] : 0.0;
-    double e1 = has1 ? R[i * W + col1] : 0.0;
+  for (int64_t i0 = r0; i0 < r1; i0 += kResChunk) {
+    const int rows = int(min<int64_t>(kResChunk, r1 - i0));
+    __syncthreads();
+    stage_v_chunk<T, PP>(V, p, i0, rows, sv);
+    __syncthreads();
+    for (int r = 0; r < rows; r += kResU) {
+      double e0[kResU], e1[kResU];
 #pragma unroll
-    for (int a = 0; a < PP; ++a) {
-      if (a < p) {
-        const double v = double(V[i * p + a]);
-        e0 -= v * c0[a];
-        e1 -= v * c1[a];
+      for (int u = 0; u < kResU; ++u) {
+        const bool ok = r + u < rows;
+        const int64_t i = i0 + r + u;
+        e0[u] = (ok && has0) ? R[i * W + col0] : 0.0;
+        e1[u] = (ok && has1) ? R[i * W + col1] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kResU; ++u) {
+        if (r + u >= rows) continue;
+#pragma unroll
+        for (int a = 0; a < PP; ++a) {
+          const double v = sv[r + u][a];
+          e0[u] -= v * c0[a];
+          e1[u] -= v * c1[a];
+        }
+        s0 += e0[u] * e0[u];
+        s1 += e1[u] * e1[u];
       }
     }
-    s0 += e0 * e0;
-    s1 += e1 * e1;
   }
   scol[col0] = s0;
   scol[col1] = s1;

@@ -180,6 +180,16 @@ __global__ void __launch_bounds__(kFft512Threads)
 k_fft_pass512(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* __restrict__ out,
               double sign) {
   __shared__ cplx sb[8][64][8];   // stage 1: [a][b0 + 8 c2][pair]; stage 2: [a][c][pair]
+  // the fixed twiddles of the two inner transposes, exp(sign 2 pi i e / 512)
+  // for e = 0..511 (stage 1 uses e = 8 b0 c2), formed once per workgroup
+  // rather than by sincospi per element
+  __shared__ cplx tw[512];
+  for (int e = threadIdx.x; e < 512; e += kFft512Threads) {
+    double si, co;
+    sincospi(sign * 2.0 * double(e) / 512.0, &si, &co);
+    tw[e] = {co, si};
+  }
+  __syncthreads();
   const int pc = threadIdx.x % 8, t = threadIdx.x / 8;
   const int64_t pairs = (L / 512) * q;
   const int64_t stride = L / 512;
@@ -212,11 +222,7 @@ k_fft_pass512(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* _
       cplx Z[8];
       dft_small<8>(v, Z, sign);
 #pragma unroll
-      for (int c2 = 0; c2 < 8; ++c2) {
-        double si, co;
-        sincospi(sign * 2.0 * double(b0 * c2) / 64.0, &si, &co);
-        sb[a][b0 + 8 * c2][pc] = cmul(Z[c2], cplx{co, si});
-      }
+      for (int c2 = 0; c2 < 8; ++c2) sb[a][b0 + 8 * c2][pc] = cmul(Z[c2], tw[8 * b0 * c2]);
     }
     __syncthreads();
     // stage 2: thread t = a + 8 c2
@@ -230,9 +236,7 @@ k_fft_pass512(int64_t L, int q, int64_t Ns, const cplx* __restrict__ in, cplx* _
 #pragma unroll
       for (int c1 = 0; c1 < 8; ++c1) {
         const int cc = c2 + 8 * c1;
-        double si, co;
-        sincospi(sign * 2.0 * double(a * cc) / 512.0, &si, &co);
-        sb[a][cc][pc] = cmul(W[c1], cplx{co, si});
+        sb[a][cc][pc] = cmul(W[c1], tw[a * cc]);
       }
     }
     __syncthreads();
