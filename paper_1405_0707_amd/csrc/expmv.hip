@@ -778,9 +778,14 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     restrict_fused(reinterpret_cast<T*>(C.vb), xc, false);
     const int G = std::max(GA, row_split(L.avg_pf, PPL));
     const KtEv e = kt_take(pl, c_prol, pair_bytes);
-    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kCgThreads, true>), dim3(gfine),
-                          dim3(kCgThreads), 0, s, e.e0, e.e1, 0, k, ctl, n, p, G, L.arp, L.aci,
-                          lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf, xc, L.alpha, L.beta, out);
+    // 256-thread workgroups over the XCD's eighth of the rows, as on the
+    // coarse levels (this kernel writes no partial sums, so it need not
+    // keep the inner solver's launch shape): 0.467 against 0.493 ms per
+    // launch on the 128^3 workload in 1024-thread row segments
+    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
+                          dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0, k, ctl,
+                          n, p, G, L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf, xc,
+                          L.alpha, L.beta, out);
     return;
   }
   if (fine && L.fused && L.degree == 2) {
