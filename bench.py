@@ -52,11 +52,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # 256 MiB device copy), valid while the sources hash to the recorded value.
 MEASURED_TRAFFIC = {
     # profiles/psbfom_amg_bicgstab_convdiff128_p16_fp64_traffic.md:
-    # k_amg_affine_pair<double, 4, 4, 1024, true>, 601,348.4 KiB fetched and
-    # 262,145.0 KiB written per dispatch
-    "amg_prolong": {"bytes": 1499998003,
+    # k_amg_affine_pair<double, 4, 4, 256, false> on the finest level,
+    # 409,094.6 KiB fetched and 262,144.2 KiB written per dispatch
+    "amg_prolong": {"bytes": 1106261402,
                     "sources": ["amg.hpp", "kernels.hpp", "expmv.hip"],
-                    "sha256": "b75bc6ac3b79e6ed427fc511d26f2d8363b6961b0b572ad4cc68b33dc4a7c93f"},
+                    "sha256": "f2adf42c590f305038e84e3fae233872716a0f6b2835d8e57da7687695428d3a"},
 }
 
 
