@@ -1565,7 +1565,8 @@ RitzBasis ritz_basis(bool symmetric, bool precond, int dl, const std::vector<dou
     return rb;
   }
   std::vector<double> wr(dl), wi(dl), Vr(size_t(dl) * dl), Vi(size_t(dl) * dl);
-  if (!general_eigvals(dl, Hd.data(), wr.data(), wi.data())) throw StatusError{EXPMV_EBREAKDOWN};
+  HessForm hf;
+  if (!general_eigvals(dl, Hd.data(), wr.data(), wi.data(), &hf)) throw StatusError{EXPMV_EBREAKDOWN};
   auto mag = [&](int a) { return std::hypot(wr[a], wi[a]); };
   if (precond) std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return mag(a) > mag(b); });
   else std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return mag(a) < mag(b); });
@@ -1588,7 +1589,7 @@ RitzBasis ritz_basis(bool symmetric, bool precond, int dl, const std::vector<dou
         ++chosen;
       }
     }
-    general_eigvecs(dl, Hd.data(), wr.data(), wi.data(), want.data(), Vr.data(), Vi.data());
+    general_eigvecs(dl, Hd.data(), wr.data(), wi.data(), want.data(), Vr.data(), Vi.data(), &hf);
   }
   std::vector<char> taken(dl, 0);
   std::vector<std::vector<double>> cols;
@@ -2007,20 +2008,28 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     for (int i = 0; i < dl; ++i)
       for (int c = 0; c < kn; ++c) Pk[size_t(live[i]) * kpn + c] = rb.Pk[size_t(i) * kn + c];
     // H~_new = P_{k+p}^T H~ P_k: top kn x kn block and the p rows below
+    // (both products row by row, inner loops along rows)
     std::vector<double> HP(size_t(d + p) * kn, 0.0);
-    for (int i = 0; i < d + p; ++i)
-      for (int c = 0; c < kn; ++c) {
-        double acc = 0.0;
-        for (int j = 0; j < d; ++j) acc += Hh[size_t(i) * ldh + j] * Pk[size_t(j) * kpn + c];
-        HP[size_t(i) * kn + c] = acc;
+    for (int i = 0; i < d + p; ++i) {
+      double* hp = &HP[size_t(i) * kn];
+      for (int j = 0; j < d; ++j) {
+        const double h = Hh[size_t(i) * ldh + j];
+        if (h == 0.0) continue;
+        const double* pk = &Pk[size_t(j) * kpn];
+        for (int c = 0; c < kn; ++c) hp[c] += h * pk[c];
       }
+    }
     std::fill(Hh.begin(), Hh.end(), 0.0);
-    for (int r = 0; r < kn; ++r)
-      for (int c = 0; c < kn; ++c) {
-        double acc = 0.0;
-        for (int i = 0; i < d; ++i) acc += Pk[size_t(i) * kpn + r] * HP[size_t(i) * kn + c];
-        Hh[size_t(r) * ldh + c] = acc;
+    for (int i = 0; i < d; ++i) {
+      const double* pk = &Pk[size_t(i) * kpn];
+      const double* hp = &HP[size_t(i) * kn];
+      for (int r = 0; r < kn; ++r) {
+        const double pr = pk[r];
+        if (pr == 0.0) continue;
+        double* hr = &Hh[size_t(r) * ldh];
+        for (int c = 0; c < kn; ++c) hr[c] += pr * hp[c];
       }
+    }
     for (int r = 0; r < p; ++r)
       for (int c = 0; c < kn; ++c) Hh[size_t(kpn + r) * ldh + c] = HP[size_t(d + r) * kn + c];
     HIPCHK(hipMemcpyAsync(w.Crot, Pk.data(), sizeof(double) * Pk.size(), hipMemcpyHostToDevice, s));

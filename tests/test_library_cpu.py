@@ -57,9 +57,26 @@ def test_host_symmetric_eig(n):
     assert np.max(np.abs(A @ Q - Q * w[None, :])) < 1e-11 * max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("n", [3, 10, 60])
-def test_host_general_eig(n):
-    A = np.random.default_rng(100 + n).standard_normal((n, n))
+def _general_case(kind, n):
+    rng = np.random.default_rng(100 + n)
+    if kind == "gauss":
+        return rng.standard_normal((n, n))
+    if kind == "graded":       # the restart's shape: a spread spectrum, weak coupling
+        return np.diag(1.0 / (1.0 + np.arange(n))) + 0.3 * rng.standard_normal((n, n)) / np.sqrt(n)
+    if kind == "cyclic":       # roots of unity: the unshifted QR iteration stalls on it
+        return np.roll(np.eye(n), 1, axis=0)
+    if kind == "companion":
+        return np.ascontiguousarray(np.vstack([np.eye(n)[1:], -rng.standard_normal(n)]).T)
+    if kind == "upper":        # already triangular: every step deflates at once
+        return np.triu(rng.standard_normal((n, n)))
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind,n", [("gauss", 3), ("gauss", 10), ("gauss", 60), ("gauss", 320),
+                                    ("graded", 320), ("cyclic", 9), ("companion", 12),
+                                    ("upper", 15)])
+def test_host_general_eig(kind, n):
+    A = _general_case(kind, n)
     wr, wi = np.zeros(n), np.zeros(n)
     Vr, Vi = np.zeros((n, n)), np.zeros((n, n))
     st = _lib.lib().expmv_host_eig_general(n, A.ctypes.data, wr.ctypes.data, wi.ctypes.data,
