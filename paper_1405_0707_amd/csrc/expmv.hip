@@ -14,6 +14,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -1628,6 +1629,64 @@ RitzBasis ritz_basis(bool symmetric, bool precond, int dl, const std::vector<dou
   return rb;
 }
 
+// Steps 5-8 in the projected coordinates, on the host: from H~ (ldh x ldh,
+// row-major, the first d + p rows live) the Ritz basis P_k of its live part
+// (every padded coordinate but those after the kept Ritz vectors, keff..kp),
+// then H~ is overwritten by P_{k+p}^T H~ P_k (top kn x kn block and the p
+// rows of the last block below it, from row kpn).  Pk comes back as d x kpn
+// in padded coordinates (zero rows at the padding, zero columns after kn).
+struct RestartCoords {
+  std::vector<double> Pk;
+  int kn = 0, kpn = 0;
+};
+
+RestartCoords restart_coordinates(bool symmetric, bool precond, int d, int p, int k, int ldh,
+                                  int keff, int kp, std::vector<double>& Hh) {
+  std::vector<int> live;
+  for (int i = 0; i < d; ++i)
+    if (!(i >= keff && i < kp)) live.push_back(i);
+  const int dl = int(live.size());
+  std::vector<double> Hd(size_t(dl) * dl);
+  for (int i = 0; i < dl; ++i)
+    for (int j = 0; j < dl; ++j) Hd[size_t(i) * dl + j] = Hh[size_t(live[i]) * ldh + live[j]];
+  RitzBasis rb = ritz_basis(symmetric, precond, dl, Hd, k);
+  RestartCoords rc;
+  const int kn = rb.keff;
+  const int kpn = (kn + p - 1) / p * p;
+  rc.kn = kn;
+  rc.kpn = kpn;
+  if (kn < 1) return rc;
+  std::vector<double>& Pk = rc.Pk;
+  Pk.assign(size_t(d) * kpn, 0.0);
+  for (int i = 0; i < dl; ++i)
+    for (int c = 0; c < kn; ++c) Pk[size_t(live[i]) * kpn + c] = rb.Pk[size_t(i) * kn + c];
+  // H~_new = P_{k+p}^T H~ P_k (both products row by row, inner loops along rows)
+  std::vector<double> HP(size_t(d + p) * kn, 0.0);
+  for (int i = 0; i < d + p; ++i) {
+    double* hp = &HP[size_t(i) * kn];
+    for (int j = 0; j < d; ++j) {
+      const double h = Hh[size_t(i) * ldh + j];
+      if (h == 0.0) continue;
+      const double* pk = &Pk[size_t(j) * kpn];
+      for (int c = 0; c < kn; ++c) hp[c] += h * pk[c];
+    }
+  }
+  std::fill(Hh.begin(), Hh.end(), 0.0);
+  for (int i = 0; i < d; ++i) {
+    const double* pk = &Pk[size_t(i) * kpn];
+    const double* hp = &HP[size_t(i) * kn];
+    for (int r = 0; r < kn; ++r) {
+      const double pr = pk[r];
+      if (pr == 0.0) continue;
+      double* hr = &Hh[size_t(r) * ldh];
+      for (int c = 0; c < kn; ++c) hr[c] += pr * hp[c];
+    }
+  }
+  for (int r = 0; r < p; ++r)
+    for (int c = 0; c < kn; ++c) Hh[size_t(kpn + r) * ldh + c] = HP[size_t(d + r) * kn + c];
+  return rc;
+}
+
 // -------------------------------------------------------------------------
 // the method
 
@@ -1821,6 +1880,27 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       std::min(std::pow(10.0, double(pl->opts.inner_relax)), pl->mixed ? 1e2 : 1e12);
   double rho_prev = 0.0;
   bool rhs_from_S = false;
+  // Wk = M^{-1} Vj (Algorithm 2; Algorithm 1: M Vj)
+  auto apply_block = [&](const T* Vj) {
+    if (precond) {
+      // relaxed inner tolerance: factor rho_0 / rho_{j-1} (capped), rho the
+      // largest residual estimate over the shifts after the previous block
+      pl->relax_scale = 1.0;
+      if (relax && rho_prev > 0.0)
+        pl->relax_scale = std::min(relax_cap, std::max(1.0, inf.bnorm / rho_prev));
+      InnerResult r = apply_inverse_mixed<T, TI>(pl, transpose, Vj, Wk, p);
+      pl->relax_scale = 1.0;
+      inf.inner_iters += r.iters;
+      inf.inner_maxit_hit += r.hit_cap;
+    } else {
+      apply_K<T>(pl, transpose, Vj, Wk, p);
+      // M V = -K V
+      hipLaunchKernelGGL((k_convert<T, T>), dim3(512), dim3(kThreads), 0, s, int64_t(blk), Wk, Wk,
+                         -1.0);
+    }
+    inf.block_apps += 1;
+  };
+  bool first_applied = false;   // Wk already holds the first block's product
   int cycle = 0;
   for (;;) {
     ++cycle;
@@ -1828,23 +1908,8 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     for (int jb = first_block; jb < m; ++jb) {
       double t0 = host_now_ms();
       const T* Vj = Vb + size_t(jb) * blk;
-      if (precond) {
-        // relaxed inner tolerance: factor rho_0 / rho_{j-1} (capped), rho the
-        // largest residual estimate over the shifts after the previous block
-        pl->relax_scale = 1.0;
-        if (relax && rho_prev > 0.0)
-          pl->relax_scale = std::min(relax_cap, std::max(1.0, inf.bnorm / rho_prev));
-        InnerResult r = apply_inverse_mixed<T, TI>(pl, transpose, Vj, Wk, p);
-        pl->relax_scale = 1.0;
-        inf.inner_iters += r.iters;
-        inf.inner_maxit_hit += r.hit_cap;
-      } else {
-        apply_K<T>(pl, transpose, Vj, Wk, p);
-        // M V = -K V
-        hipLaunchKernelGGL((k_convert<T, T>), dim3(512), dim3(kThreads), 0, s, int64_t(blk), Wk, Wk,
-                           -1.0);
-      }
-      inf.block_apps += 1;
+      if (!(first_applied && jb == first_block)) apply_block(Vj);
+      first_applied = false;
       double t1 = host_now_ms();
       ms_apply += t1 - t0;
       orthonormalize<T>(pl, p, Vb, jb + 1, Wk, Vb + size_t(jb + 1) * blk, w.H, ldh, jb * p,
@@ -1982,56 +2047,30 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
       break;
     }
     if (pl->opts.restart_refine) inf.refined_restarts += 1;
-    // Steps 5-8: deflated restart (host eigensolve of the live part of H_d)
+    // Steps 5-8: deflated restart (host eigensolve of the live part of H_d).
+    // The restart keeps the basis's last block as the block after the Ritz
+    // panels, so the next cycle's first product M^{-1} V_{m+1} needs nothing
+    // from the eigensolve: it runs on the GPU while a host thread computes
+    // the Ritz basis and the rotated H~.
     double t3 = host_now_ms();
     HIPCHK(hipMemcpyAsync(Hh.data(), w.H, sizeof(double) * size_t(ldh) * ldh,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    // live padded coordinates: everything but the padding after the Ritz block
-    std::vector<int> live;
-    for (int i = 0; i < d; ++i)
-      if (!(i >= keff && i < kp)) live.push_back(i);
-    const int dl = int(live.size());
-    std::vector<double> Hd(size_t(dl) * dl);
-    for (int i = 0; i < dl; ++i)
-      for (int j = 0; j < dl; ++j) Hd[size_t(i) * dl + j] = Hh[size_t(live[i]) * ldh + live[j]];
-    RitzBasis rb = ritz_basis(pl->symmetric, precond, dl, Hd, k);
-    const int kn = rb.keff;
-    const int kpn = (kn + p - 1) / p * p;
+    auto coords = std::async(std::launch::async, restart_coordinates, bool(pl->symmetric), precond,
+                             d, p, k, ldh, keff, kp, std::ref(Hh));
+    const double ta = host_now_ms();
+    apply_block(Vb + size_t(d / p) * blk);
+    first_applied = true;
+    const double tb = host_now_ms();
+    ms_apply += tb - ta;
+    RestartCoords rcd = coords.get();
+    const int kn = rcd.kn;
+    const int kpn = rcd.kpn;
     if (kn < 1 || kpn / p + 1 > m) {
       status = EXPMV_EBREAKDOWN;
       break;
     }
-    // P_k in padded coordinates: d x kpn (zero rows at padding, zero columns
-    // after kn)
-    std::vector<double> Pk(size_t(d) * kpn, 0.0);
-    for (int i = 0; i < dl; ++i)
-      for (int c = 0; c < kn; ++c) Pk[size_t(live[i]) * kpn + c] = rb.Pk[size_t(i) * kn + c];
-    // H~_new = P_{k+p}^T H~ P_k: top kn x kn block and the p rows below
-    // (both products row by row, inner loops along rows)
-    std::vector<double> HP(size_t(d + p) * kn, 0.0);
-    for (int i = 0; i < d + p; ++i) {
-      double* hp = &HP[size_t(i) * kn];
-      for (int j = 0; j < d; ++j) {
-        const double h = Hh[size_t(i) * ldh + j];
-        if (h == 0.0) continue;
-        const double* pk = &Pk[size_t(j) * kpn];
-        for (int c = 0; c < kn; ++c) hp[c] += h * pk[c];
-      }
-    }
-    std::fill(Hh.begin(), Hh.end(), 0.0);
-    for (int i = 0; i < d; ++i) {
-      const double* pk = &Pk[size_t(i) * kpn];
-      const double* hp = &HP[size_t(i) * kn];
-      for (int r = 0; r < kn; ++r) {
-        const double pr = pk[r];
-        if (pr == 0.0) continue;
-        double* hr = &Hh[size_t(r) * ldh];
-        for (int c = 0; c < kn; ++c) hr[c] += pr * hp[c];
-      }
-    }
-    for (int r = 0; r < p; ++r)
-      for (int c = 0; c < kn; ++c) Hh[size_t(kpn + r) * ldh + c] = HP[size_t(d + r) * kn + c];
+    const std::vector<double>& Pk = rcd.Pk;
     HIPCHK(hipMemcpyAsync(w.Crot, Pk.data(), sizeof(double) * Pk.size(), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(w.H, Hh.data(), sizeof(double) * Hh.size(), hipMemcpyHostToDevice, s));
     // V_new = V_{d+p} P_{k+p}: the Ritz panels by a panel GEMM, then the last panel
@@ -2048,7 +2087,7 @@ expmv_status execute_impl(expmv_plan_s* pl, int transpose, const double* B, int 
     d = m * p;   // kp + (m - kp/p) p
     first_block = kp / p;
     rhs_from_S = true;
-    ms_small += host_now_ms() - t3;
+    ms_small += host_now_ms() - t3 - (tb - ta);
   }
   HIPCHK(hipStreamSynchronize(s));
   inf.ms_total = host_now_ms() - t_start;
