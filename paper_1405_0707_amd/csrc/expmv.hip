@@ -1333,8 +1333,16 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
     }
     hipEvent_t e0 = ev.e0, e1 = ev.e1;
 #define ORTH_MMA(NB_, MBW_)                                                                     \
-  hipExtLaunchKernelGGL((k_orth_mma<T, NB_, MBW_>), dim3(grid), dim3(kThreads), 0, pl->stream,     \
-                        e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C, pl->ws.partial, gate)
+  do {                                                                                          \
+    if (p == 16 * NB_)                                                                          \
+      hipExtLaunchKernelGGL((k_orth_mma<T, NB_, MBW_, 16 * NB_>), dim3(grid), dim3(kThreads), 0, \
+                            pl->stream, e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C,        \
+                            pl->ws.partial, gate);                                             \
+    else                                                                                        \
+      hipExtLaunchKernelGGL((k_orth_mma<T, NB_, MBW_, 0>), dim3(grid), dim3(kThreads), 0,        \
+                            pl->stream, e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C,        \
+                            pl->ws.partial, gate);                                             \
+  } while (0)
     if (NB == 1) {
       if (MBW == 2) ORTH_MMA(1, 2);
       else if (MBW == 4) ORTH_MMA(1, 4);

@@ -64,17 +64,26 @@ __device__ inline T basis_at(const T* __restrict__ V, int64_t n, int p, int64_t 
 }
 
 // NB = 16-column blocks of W (p <= 16 NB); MBW = projection column blocks
-// per wave (npan p <= 64 MBW).
-template <typename T, int NB, int MBW>
+// per wave (npan p <= 64 MBW); PC = p when it is known at compile time (16 NB:
+// panel and column offsets by shifts), else 0.  Basis and W loads clamp
+// their row and column to the array and zero what lies outside, so that
+// they need no branch and the compiler can issue a whole batch at once.
+template <typename T, int NB, int MBW, int PC>
 __global__ void __launch_bounds__(kThreads)
-k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const T* W, T* Wout,
-           const double* __restrict__ C, double* __restrict__ partial,
+k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, const T* W,
+           T* Wout, const double* __restrict__ C, double* __restrict__ partial,
            const int* __restrict__ gate) {
   if (gate && *gate == 0) return;   // conditional pass not requested
+  const int p = PC ? PC : p_arg;
   using M = Mma<T>;
   using v4 = typename M::v4;
   __shared__ T sW[64 * 16 * NB];        // W' of the step, row-major, ld 16 NB
   __shared__ double sN[4][16 * NB];     // per-wave column norms (kProj)
+  // the projection sums of column block mb live in LDS (sP[mb], NB blocks of
+  // 16 x 16, row = basis column within the block), so that the loop over a
+  // wave's blocks need not be unrolled to keep them in registers
+  constexpr bool kLdsAcc = true;
+  __shared__ double sP[4 * MBW][256 * NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ldw = 16 * NB;
@@ -85,13 +94,19 @@ k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const 
   const bool proj = (mode == kProj || mode == kUpdProj);
   const bool gram = (mode == kUpdGram || mode == kScaleGram);
 
-  double acc[MBW][NB][4];
+  constexpr int MBR = kLdsAcc ? 1 : MBW;   // projection blocks held in registers
+  double acc[MBR][NB][4];
 #pragma unroll
-  for (int a = 0; a < MBW; ++a)
+  for (int a = 0; a < MBR; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0.0;
+  if constexpr (kLdsAcc) {
+    if (proj)
+      for (int u = 0; u < MBW; ++u)
+        for (int e = lane; e < 256 * NB; e += 64) sP[wave + 4 * u][e] = 0.0;
+  }
   double nrm[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) nrm[b] = 0.0;
@@ -109,22 +124,27 @@ k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const 
     if (upd || scl) {
       const int K = upd ? np_cols : p;
       const int64_t row = r0 + li;   // A operand row of this lane
-      // four K-steps per iteration, every load issued before the products
-      for (int k0 = 0; k0 < K; k0 += 16) {
-        T a[4], bv[4][NB];
+      const int64_t rowc = row < n ? row : n - 1;
+      // KB K-steps per iteration (8 with one column block, 4 with two),
+      // every load issued before the products
+      constexpr int KB = NB == 1 ? 8 : 4;
+      for (int k0 = 0; k0 < K; k0 += 4 * KB) {
+        T a[KB], bv[KB][NB];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < KB; ++u) {
           const int kc = k0 + 4 * u + lk;
-          a[u] = T(0);
-          if (kc < K && row < n) a[u] = upd ? basis_at(V, n, p, row, kc) : W[row * p + kc];
+          const int kcc = kc < K ? kc : K - 1;
+          const T av = upd ? basis_at(V, n, p, rowc, kcc) : W[rowc * p + kcc];
+          a[u] = (kc < K && row < n) ? av : T(0);
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
             const int j = 16 * b + li;
-            bv[u][b] = (kc < K && j < p) ? T(C[int64_t(kc) * p + j]) : T(0);
+            const double cv = C[int64_t(kcc) * p + (j < p ? j : p - 1)];
+            bv[u][b] = (kc < K && j < p) ? T(cv) : T(0);
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < KB; ++u)
 #pragma unroll
           for (int b = 0; b < NB; ++b) d[b] = M::mma(a[u], bv[u][b], d[b]);
       }
@@ -150,6 +170,7 @@ k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const 
     __syncthreads();
     // ---- 2. contractions over the step's 64 rows
     if (proj) {
+#pragma unroll(kLdsAcc ? 1 : MBW)
       for (int u = 0; u < MBW; ++u) {
         const int mb = wave + 4 * u;
         if (mb >= nmb) break;
@@ -158,11 +179,13 @@ k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const 
 #pragma unroll
         for (int b = 0; b < NB; ++b) t[b] = v4{0, 0, 0, 0};
         // the 16 K-steps of the step's 64 rows: all 16 loads first
+        const int colc = col < np_cols ? col : np_cols - 1;
         T a[16];
 #pragma unroll
         for (int qs = 0; qs < 16; ++qs) {
           const int64_t row = st * 64 + 16 * (qs >> 2) + M::drow(lane, qs & 3);
-          a[qs] = (col < np_cols && row < n) ? basis_at(V, n, p, row, col) : T(0);
+          const T av = basis_at(V, n, p, row < n ? row : n - 1, colc);
+          a[qs] = (col < np_cols && row < n) ? av : T(0);
         }
 #pragma unroll
         for (int qs = 0; qs < 16; ++qs) {
@@ -170,10 +193,18 @@ k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const 
 #pragma unroll
           for (int b = 0; b < NB; ++b) t[b] = M::mma(a[qs], sW[i * ldw + 16 * b + li], t[b]);
         }
+        if constexpr (kLdsAcc) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+          for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[u][b][r] += double(t[b][r]);
+            for (int r = 0; r < 4; ++r)
+              sP[mb][256 * b + M::drow(lane, r) * 16 + li] += double(t[b][r]);
+        } else {
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[kLdsAcc ? 0 : u][b][r] += double(t[b][r]);
+        }
       }
     }
     if (gram_owner) {
@@ -205,7 +236,10 @@ k_orth_mma(int mode, int64_t n, int p, const T* __restrict__ V, int npan, const 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * mb + M::drow(lane, r), j = 16 * b + li;
-          if (col < np_cols && j < p) out[col * p + j] = acc[u][b][r];
+          double v;
+          if constexpr (kLdsAcc) v = sP[mb][256 * b + M::drow(lane, r) * 16 + li];
+          else v = acc[kLdsAcc ? 0 : u][b][r];
+          if (col < np_cols && j < p) out[col * p + j] = v;
         }
     }
   }
