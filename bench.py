@@ -5,7 +5,7 @@ Timed workload (one "step" = one full solve: every cycle, inner solve,
 orthogonalisation, projected solve, update, FP64 true residual and the final
 combination, with the plan and B already in HBM): the 3D upwind
 convection-diffusion operator on 128^3 (n = 2,097,152, 14.6 M nonzeros,
-nonsymmetric), ||tA||_1 = 1e3, B n x 16 Gaussian (seed 4), m = 20, k = 96,
+nonsymmetric), ||tA||_1 = 1e3, B n x 16 Gaussian (seed 4), m = 24, k = 128,
 FP64, stopped at an error bound of 1e-11 (the FP64 result then matches the
 oracle to 1e-10 entry by entry).  Prints one JSON line.
 
@@ -40,11 +40,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# block Arnoldi steps per cycle of the 128^3 workload (k = p floor(m / 3) = 96):
-# the configuration leaves m open; m = 20 needed 7 cycles and 8.0 s where
-# m = 10 needed 20 cycles and 9.5 s (m = 12, 14, 16 with their k: 8.6, 8.0,
-# 8.7 s), with the same accuracy against the oracle
-C4_M = 20
+# block Arnoldi steps per cycle of the 128^3 workload (k = p floor(m / 3) = 128):
+# the configuration leaves m open; with cheap restarts m = 24 needs 5 cycles
+# and 5.5 s, m = 20 7 cycles and 6.4 s, m = 12 15 cycles and 7.8 s, m = 28 and
+# 31 4 cycles and 5.5 and 5.6 s, with the same accuracy against the oracle
+C4_M = 24
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 # HBM bytes per launch of a kernel class on the timed workload from two
@@ -53,10 +53,10 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 MEASURED_TRAFFIC = {
     # profiles/psbfom_amg_bicgstab_convdiff128_p16_fp64_traffic.md:
     # k_amg_affine_pair<double, 4, 4, 256, false> on the finest level,
-    # 408,994.8 KiB fetched and 262,144.1 KiB written per dispatch
-    "amg_prolong": {"bytes": 1106056909,
+    # 407,272.2 KiB fetched and 262,144.2 KiB written per dispatch
+    "amg_prolong": {"bytes": 1102529126,
                     "sources": ["amg.hpp", "kernels.hpp", "expmv.hip"],
-                    "sha256": "9714a0d4a428c2c3c3e331c12f6c7ad7f63d22251991f3a040545a6c9ffc7d65"},
+                    "sha256": "d9a5d96c8f52f7595aabebfc877084d8a1fcdb190fbf81e8362dbbbb577b10fa"},
 }
 
 

@@ -80,7 +80,7 @@ typedef enum {
 typedef struct {
   int m;               /* block Arnoldi steps per cycle, 2..64; a call whose basis of
                           m + 1 blocks of p columns is wider than the block
-                          Gram-Schmidt takes ((m + 1) p <= 384 for p <= 32, else
+                          Gram-Schmidt takes ((m + 1) p <= 512 for p <= 32, else
                           (m + 1) p^2 doubles within 150 KB: m <= 17 at p = 32)
                           returns EXPMV_EINVAL, also from the workspace sizes   */
   int k;               /* Ritz vectors kept at a restart (multiple of p, k < m*p;

@@ -376,7 +376,7 @@ constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
 // blocks of 16 for p <= 32; the other path keeps a workgroup's npan p x p
 // projection partials and one row of the panels in LDS (150 KB).
 bool basis_fits(int npan, int p, size_t elem) {
-  if (p <= 32 && (npan * p + 15) / 16 <= 24) return true;
+  if (p <= 32 && (npan * p + 15) / 16 <= 32) return true;
   const size_t O = size_t(npan) * p * p + p;
   return O * 8 + (size_t(npan) * p + 2 * size_t(p)) * elem <= 150 * 1024;
 }
@@ -1316,13 +1316,13 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
   const bool use_v = (mode == kProj || mode == kUpdProj || mode == kUpdGram);
   const int npv = use_v ? npan : 0;
   const int O = proj ? npv * p * p + (mode == kProj ? p : 0) : (gram ? p * p : 0);
-  // matrix-core path: up to 24 column blocks of 16 (4 waves x MBW)
+  // matrix-core path: up to 32 column blocks of 16 (4 waves x MBW)
   const int nmb = (npv * p + 15) / 16;
-  if (p <= 32 && nmb <= 24) {
+  if (p <= 32 && nmb <= 32) {
     const int64_t steps = (pl->n + 63) / 64;
     const int grid = int(std::max<int64_t>(1, std::min<int64_t>(kOrthGrid, steps)));
     const int NB = (p + 15) / 16;
-    const int MBW = nmb <= 8 ? 2 : (nmb <= 16 ? 4 : 6);
+    const int MBW = nmb <= 8 ? 2 : (nmb <= 16 ? 4 : (nmb <= 24 ? 6 : 8));
     const bool upd = (mode == kUpdProj || mode == kUpdGram);
     // timed bytes: the panels of V used and W read once, W' written (all
     // modes but the projection); the conditional third pass is not timed
@@ -1346,11 +1346,13 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
     if (NB == 1) {
       if (MBW == 2) ORTH_MMA(1, 2);
       else if (MBW == 4) ORTH_MMA(1, 4);
-      else ORTH_MMA(1, 6);
+      else if (MBW == 6) ORTH_MMA(1, 6);
+      else ORTH_MMA(1, 8);
     } else {
       if (MBW == 2) ORTH_MMA(2, 2);
       else if (MBW == 4) ORTH_MMA(2, 4);
-      else ORTH_MMA(2, 6);
+      else if (MBW == 6) ORTH_MMA(2, 6);
+      else ORTH_MMA(2, 8);
     }
 #undef ORTH_MMA
     return (proj || gram) ? grid : 0;

@@ -75,7 +75,7 @@ def check_sample(Z, g, bar, B, key="Z", fro="fro", maxabs="maxabs", what="Z"):
 
 @pytest.fixture(scope="module")
 def convdiff128():
-    W = wl.c4(precision="fp64", m=20)   # the benchmark's m (k = 96)
+    W = wl.c4(precision="fp64", m=24)   # the benchmark's m (k = 128)
     return W, torch.from_numpy(W.B).to(DEV)
 
 
