@@ -82,7 +82,6 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
   // the projection sums of column block mb live in LDS (sP[mb], NB blocks of
   // 16 x 16, row = basis column within the block), so that the loop over a
   // wave's blocks need not be unrolled to keep them in registers
-  constexpr bool kLdsAcc = true;
   __shared__ double sP[4 * MBW][256 * NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -94,19 +93,10 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
   const bool proj = (mode == kProj || mode == kUpdProj);
   const bool gram = (mode == kUpdGram || mode == kScaleGram);
 
-  constexpr int MBR = kLdsAcc ? 1 : MBW;   // projection blocks held in registers
-  double acc[MBR][NB][4];
-#pragma unroll
-  for (int a = 0; a < MBR; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0.0;
-  if constexpr (kLdsAcc) {
-    if (proj)
-      for (int u = 0; u < MBW; ++u)
-        for (int e = lane; e < 256 * NB; e += 64) sP[wave + 4 * u][e] = 0.0;
-  }
+  double gacc[4] = {0.0, 0.0, 0.0, 0.0};   // Gram block of this wave
+  if (proj)
+    for (int u = 0; u < MBW; ++u)
+      for (int e = lane; e < 256 * NB; e += 64) sP[wave + 4 * u][e] = 0.0;
   double nrm[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) nrm[b] = 0.0;
@@ -170,7 +160,7 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
     __syncthreads();
     // ---- 2. contractions over the step's 64 rows
     if (proj) {
-#pragma unroll(kLdsAcc ? 1 : MBW)
+#pragma unroll 1
       for (int u = 0; u < MBW; ++u) {
         const int mb = wave + 4 * u;
         if (mb >= nmb) break;
@@ -193,18 +183,11 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 #pragma unroll
           for (int b = 0; b < NB; ++b) t[b] = M::mma(a[qs], sW[i * ldw + 16 * b + li], t[b]);
         }
-        if constexpr (kLdsAcc) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              sP[mb][256 * b + M::drow(lane, r) * 16 + li] += double(t[b][r]);
-        } else {
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[kLdsAcc ? 0 : u][b][r] += double(t[b][r]);
-        }
+          for (int r = 0; r < 4; ++r)
+            sP[mb][256 * b + M::drow(lane, r) * 16 + li] += double(t[b][r]);
       }
     }
     if (gram_owner) {
@@ -218,7 +201,7 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[0][0][r] += double(t[r]);
+      for (int r = 0; r < 4; ++r) gacc[r] += double(t[r]);
     }
     __syncthreads();
   }
@@ -236,10 +219,7 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * mb + M::drow(lane, r), j = 16 * b + li;
-          double v;
-          if constexpr (kLdsAcc) v = sP[mb][256 * b + M::drow(lane, r) * 16 + li];
-          else v = acc[kLdsAcc ? 0 : u][b][r];
-          if (col < np_cols && j < p) out[col * p + j] = v;
+          if (col < np_cols && j < p) out[col * p + j] = sP[mb][256 * b + M::drow(lane, r) * 16 + li];
         }
     }
   }
@@ -260,7 +240,7 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int a = 16 * g1 + M::drow(lane, r), j = 16 * g2 + li;
-      if (a < p && j < p) out[a * p + j] = acc[0][0][r];
+      if (a < p && j < p) out[a * p + j] = gacc[r];
     }
   }
 }
