@@ -52,11 +52,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # 256 MiB device copy), valid while the sources hash to the recorded value.
 MEASURED_TRAFFIC = {
     # profiles/psbfom_amg_bicgstab_convdiff128_p16_fp64_traffic.md:
-    # k_amg_affine_pair<double, 4, 4, 256, false> on the finest level,
-    # 407,759.8 KiB fetched and 262,144.2 KiB written per dispatch
-    "amg_prolong": {"bytes": 1103527731,
+    # k_amg_affine_pair_ad<double, 4, 4, 256, false> on the finest level,
+    # 422,739.1 KiB fetched and 262,151.1 KiB written per dispatch
+    "amg_prolong": {"bytes": 1134212403,
                     "sources": ["amg.hpp", "kernels.hpp", "expmv.hip"],
-                    "sha256": "88c06457630ea9b733b67d213fd78e4540d8c738810b24b94be4e88f835bdb35"},
+                    "sha256": "2e336eb0f5474df8e36e08ad802002d8f6e979aec61655778f07feaf317e3431"},
 }
 
 

@@ -167,7 +167,8 @@ __device__ inline void row_dot_split(const int32_t* __restrict__ colind,
 // together: accA over row ea0..ea1 of the operator with the scaled vector
 // s_j = dinv[j] * b[j], accP over row ep0..ep1 of Pf with xc.  Same split
 // over the G sub-lanes and the same order within each sum as row_dot_split.
-template <typename T, int PPL, int VW>
+// SA: the operator values already hold a_ij dinv[j] (no dinv gather).
+template <typename T, int PPL, int VW, bool SA = false>
 __device__ inline void row_dot_pair(const int32_t* __restrict__ aci, const T* __restrict__ av,
                                     const T* __restrict__ b, const T* __restrict__ dinv, int ea0,
                                     int ea1, const int32_t* __restrict__ pci,
@@ -196,9 +197,11 @@ __device__ inline void row_dot_pair(const int32_t* __restrict__ aci, const T* __
           for (int k = 0; k < VW; ++k) wa[u][k] = 0.0;
         } else {
           load_vw<VW>(b + int64_t(ja[u]) * ld + c0, wa[u]);
-          const double dj = double(dinv[ja[u]]);
+          if constexpr (!SA) {
+            const double dj = double(dinv[ja[u]]);
 #pragma unroll
-          for (int k = 0; k < VW; ++k) wa[u][k] *= dj;
+            for (int k = 0; k < VW; ++k) wa[u][k] *= dj;
+          }
         }
         if (jp[u] < 0) {
 #pragma unroll
@@ -361,22 +364,28 @@ k_amg_prolong(int k, const KrylovCtl* ctl, int n, int p, int G,
 //  * the finest level at degree 2, whose pre-smoothed iterate
 //      x1 = (1 + c1) x0 + a1 D^{-1} (b - A x0) = D^{-1} ((s0 + c1 s0 + a1) b - a1 s0 A D^{-1} b)
 //    is not stored: the prolongation x1 + P xc recomputes it.
-template <typename T, int PPL, int VW, int NT, bool SEG>
-__global__ void __launch_bounds__(NT)
-k_amg_affine_pair(int k, const KrylovCtl* ctl, int n, int p, int G,
-                  const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
-                  const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
-                  const int32_t* __restrict__ prp, const int32_t* __restrict__ pci,
-                  const T* __restrict__ pv, const T* __restrict__ xc, double alpha, double beta,
-                  T* __restrict__ out) {
+// The prolongation-plus-smoothing pass of one row range.  SA: av holds the
+// values of A D^{-1} (a_ij dinv[j]); dinv still scales the row's own term.
+template <typename T, int PPL, int VW, int NT, bool SEG, bool SA>
+__device__ __forceinline__ void affine_pair_rows(int k, const KrylovCtl* ctl, int n, int p, int G,
+                                                 const int32_t* __restrict__ arp,
+                                                 const int32_t* __restrict__ aci,
+                                                 const T* __restrict__ av,
+                                                 const T* __restrict__ dinv,
+                                                 const T* __restrict__ b,
+                                                 const int32_t* __restrict__ prp,
+                                                 const int32_t* __restrict__ pci,
+                                                 const T* __restrict__ pv,
+                                                 const T* __restrict__ xc, double alpha,
+                                                 double beta, T* __restrict__ out) {
   if (ctl && finished_by(ctl, k)) return;
   const int c0 = VW * (threadIdx.x % PPL);
   const int g = (threadIdx.x / PPL) % G;
   for (RowRange<NT, PPL, SEG> rr(n, G); rr.r < rr.end; rr.r += rr.step) {
     const int64_t row = rr.r;
     double ab[VW], corr[VW];
-    row_dot_pair<T, PPL, VW>(aci, av, b, dinv, arp[row], arp[row + 1], pci, pv, xc, prp[row],
-                             prp[row + 1], p, c0, c0 < p, g, G, ab, corr);
+    row_dot_pair<T, PPL, VW, SA>(aci, av, b, dinv, arp[row], arp[row + 1], pci, pv, xc,
+                                 prp[row], prp[row + 1], p, c0, c0 < p, g, G, ab, corr);
     if (c0 >= p || g != 0) continue;
     const int64_t i = row * p + c0;
     double bi[VW], o[VW];
@@ -386,6 +395,33 @@ k_amg_affine_pair(int k, const KrylovCtl* ctl, int n, int p, int G,
     for (int q = 0; q < VW; ++q) o[q] = dr * (alpha * bi[q] - beta * ab[q]) + corr[q];
     store_vw<VW>(out + i, o);
   }
+}
+
+template <typename T, int PPL, int VW, int NT, bool SEG>
+__global__ void __launch_bounds__(NT)
+k_amg_affine_pair(int k, const KrylovCtl* ctl, int n, int p, int G,
+                  const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                  const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
+                  const int32_t* __restrict__ prp, const int32_t* __restrict__ pci,
+                  const T* __restrict__ pv, const T* __restrict__ xc, double alpha, double beta,
+                  T* __restrict__ out) {
+  affine_pair_rows<T, PPL, VW, NT, SEG, false>(k, ctl, n, p, G, arp, aci, av, dinv, b, prp, pci,
+                                               pv, xc, alpha, beta, out);
+}
+
+// The same pass with av = A D^{-1}: one gather per nonzero of A instead of
+// two; held to 128 VGPRs (4 waves per SIMD, as the kernel above runs at four
+// columns per lane)
+template <typename T, int PPL, int VW, int NT, bool SEG>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_amg_affine_pair_ad(int k, const KrylovCtl* ctl, int n, int p, int G,
+                     const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                     const T* __restrict__ adv, const T* __restrict__ dinv,
+                     const T* __restrict__ b, const int32_t* __restrict__ prp,
+                     const int32_t* __restrict__ pci, const T* __restrict__ pv,
+                     const T* __restrict__ xc, double alpha, double beta, T* __restrict__ out) {
+  affine_pair_rows<T, PPL, VW, NT, SEG, true>(k, ctl, n, p, G, arp, aci, adv, dinv, b, prp, pci,
+                                              pv, xc, alpha, beta, out);
 }
 
 // x = M b with M dense nr x ncols (row-major, FP64): the coarsest solve

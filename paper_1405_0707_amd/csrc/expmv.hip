@@ -191,6 +191,10 @@ struct AmgDevLevel {
   bool fused = false;
   DevBuf<int32_t> Rfrp, Rfci, Pfrp, Pfci;
   DevBuf<double> Rfv, Pfv;
+  // values of A D^{-1} (a_ij dinv[j], FP64) for the FP64 prolongation-plus-
+  // smoothing pass of a fused degree-1 level: its sum over A needs no
+  // gather of dinv
+  DevBuf<double> ADv;
   DevBuf<float> Rfv32, Pfv32;
   double avg_rf = 0.0, avg_pf = 0.0;
   char *vb = nullptr, *vu = nullptr, *vv = nullptr, *vd = nullptr, *vr = nullptr,
@@ -733,6 +737,24 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
                           k, ctl, nc, p, GR, L.Rfrp.p, L.Rfci.p, lv.rf, b, bc);
     amg_level<T, PPL * VW>(pl, H, l + 1, p, bc, xc, k, ctl, nullptr);
   };
+  // the prolongation-plus-smoothing pass (256-thread workgroups over the
+  // XCD's eighth of the rows); in FP64 at four columns per lane its sum over
+  // A reads A D^{-1}
+  auto launch_pair = [&](int G, const KtEv& e, const T* xc) {
+    if constexpr (std::is_same<T, double>::value && VW == 4) {
+      if (L.ADv.p) {
+        hipExtLaunchKernelGGL((k_amg_affine_pair_ad<T, PPL, VW, kThreads, false>),
+                              dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0, k,
+                              ctl, n, p, G, L.arp, L.aci, L.ADv.p, dinv, b, L.Pfrp.p, L.Pfci.p,
+                              lv.pf, xc, L.alpha, L.beta, out);
+        return;
+      }
+    }
+    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
+                          dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0, k, ctl,
+                          n, p, G, L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf, xc,
+                          L.alpha, L.beta, out);
+  };
   // prolongation plus the post-smoothing step in one pass (fused levels)
   const double pair_bytes = csr(n, L.nnz_a) + es * n + blk + csr(n, L.nnz_pf) + cblk + blk;
   if (!fine && L.fused) {
@@ -740,10 +762,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     restrict_fused(reinterpret_cast<T*>(C.vb), xc, l + 2 == int(H.lv.size()) && H.cinvR.p);
     const int G = std::max(row_split(L.avg_a, PPL), row_split(L.avg_pf, PPL));
     const KtEv e = kt_take(pl, c_prol, pair_bytes);
-    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
-                          dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0,
-                          k, ctl, n, p, G, L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf,
-                          xc, L.alpha, L.beta, out);
+    launch_pair(G, e, xc);
     return;
   }
   const int gfine = cg_grid(n, PP);
@@ -783,10 +802,7 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
     // coarse levels (this kernel writes no partial sums, so it need not
     // keep the inner solver's launch shape): 0.467 against 0.493 ms per
     // launch on the 128^3 workload in 1024-thread row segments
-    hipExtLaunchKernelGGL((k_amg_affine_pair<T, PPL, VW, kThreads, false>),
-                          dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0, k, ctl,
-                          n, p, G, L.arp, L.aci, lv.a, dinv, b, L.Pfrp.p, L.Pfci.p, lv.pf, xc,
-                          L.alpha, L.beta, out);
+    launch_pair(G, e, xc);
     return;
   }
   if (fine && L.fused && L.degree == 2) {
@@ -2485,6 +2501,16 @@ expmv_status build_amg(expmv_plan_s* pl, int tr) {
         L.fused = true;
       }
     }
+  }
+  for (int l = 0; l + 1 < nlev; ++l) {
+    AmgDevLevel& L = *H->lv[l];
+    if (!L.fused || L.degree != 1) continue;
+    const AmgLevelHost& Lh = h.lv[l];
+    std::vector<double> adv(Lh.A.v.size());
+    for (int64_t i = 0; i < Lh.A.nrows; ++i)
+      for (int64_t e = Lh.A.rp[i]; e < Lh.A.rp[i + 1]; ++e)
+        adv[e] = Lh.A.v[e] * Lh.dinv[Lh.A.ci[e]];
+    upload_vec(L.ADv, adv);
   }
   if (dense_last) {
     // Inv R for the level above the coarsest: nc x n_l dense, built from the
