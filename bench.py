@@ -52,11 +52,11 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # 256 MiB device copy), valid while the sources hash to the recorded value.
 MEASURED_TRAFFIC = {
     # profiles/psbfom_amg_bicgstab_convdiff128_p16_fp64_traffic.md:
-    # k_amg_affine_pair_ad<double, 4, 4, 256, false> on the finest level,
-    # 422,739.1 KiB fetched and 262,151.1 KiB written per dispatch
-    "amg_prolong": {"bytes": 1134212403,
+    # k_amg_affine_pair_q<double, 4, 256> on the finest level,
+    # 420,490.5 KiB fetched and 262,146.0 KiB written per dispatch
+    "amg_prolong": {"bytes": 1129602048,
                     "sources": ["amg.hpp", "kernels.hpp", "expmv.hip"],
-                    "sha256": "2e336eb0f5474df8e36e08ad802002d8f6e979aec61655778f07feaf317e3431"},
+                    "sha256": "056f10a736f047ca7f794bac06ffe4e5c05b762775cbb655eb223eab2493a4ab"},
 }
 
 

@@ -364,6 +364,83 @@ k_amg_prolong(int k, const KrylovCtl* ctl, int n, int p, int G,
 //  * the finest level at degree 2, whose pre-smoothed iterate
 //      x1 = (1 + c1) x0 + a1 D^{-1} (b - A x0) = D^{-1} ((s0 + c1 s0 + a1) b - a1 s0 A D^{-1} b)
 //    is not stored: the prolongation x1 + P xc recomputes it.
+// Quad broadcast: the value of lane I of each group of four consecutive
+// lanes to all four (DPP quad_perm [I, I, I, I]).  Every lane of the quad
+// must be active.
+template <int I>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, I * 0x55, 0xf, 0xf, false);
+}
+template <int I>
+__device__ __forceinline__ double quad_bcast(double v) {
+  const int lo = quad_bcast<I>(__double2loint(v));
+  const int hi = quad_bcast<I>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// row_dot_pair for four lanes per row (one quad) and av = A D^{-1}: each
+// lane of the quad loads one of four consecutive nonzeros of a row and the
+// quad exchanges them by broadcasts, so one index load serves four
+// nonzeros.  Sub-lane g owns the groups starting at e0 + 4 (g + G u).  A
+// column outside [0, nb) of A or [0, nx) of Pf is skipped.
+template <typename T, int VW>
+__device__ inline void row_dot_pair_q(const int32_t* __restrict__ aci, const T* __restrict__ av,
+                                      const T* __restrict__ b, int nb, int ea0, int ea1,
+                                      const int32_t* __restrict__ pci, const T* __restrict__ pv,
+                                      const T* __restrict__ xc, int nx, int ep0, int ep1, int ld,
+                                      int c0, bool active, int g, int G, double (&accA)[VW],
+                                      double (&accP)[VW]) {
+  const int q = threadIdx.x & 3;
+#pragma unroll
+  for (int k = 0; k < VW; ++k) accA[k] = accP[k] = 0.0;
+  for (int ea = ea0 + 4 * g, ep = ep0 + 4 * g; ea < ea1 || ep < ep1; ea += 4 * G, ep += 4 * G) {
+    const bool oa = ea + q < ea1, op = ep + q < ep1;
+    const int mja = oa ? aci[ea + q] : -1;
+    const double mva = oa ? double(av[ea + q]) : 0.0;
+    const int mjp = op ? pci[ep + q] : -1;
+    const double mvp = op ? double(pv[ep + q]) : 0.0;
+    int ja[4], jp[4];
+    double va[4], vp[4];
+    ja[0] = quad_bcast<0>(mja); ja[1] = quad_bcast<1>(mja);
+    ja[2] = quad_bcast<2>(mja); ja[3] = quad_bcast<3>(mja);
+    va[0] = quad_bcast<0>(mva); va[1] = quad_bcast<1>(mva);
+    va[2] = quad_bcast<2>(mva); va[3] = quad_bcast<3>(mva);
+    jp[0] = quad_bcast<0>(mjp); jp[1] = quad_bcast<1>(mjp);
+    jp[2] = quad_bcast<2>(mjp); jp[3] = quad_bcast<3>(mjp);
+    vp[0] = quad_bcast<0>(mvp); vp[1] = quad_bcast<1>(mvp);
+    vp[2] = quad_bcast<2>(mvp); vp[3] = quad_bcast<3>(mvp);
+    double wa[4][VW], wp[4][VW];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (active && ja[u] >= 0 && ja[u] < nb) {
+        load_vw<VW>(b + int64_t(ja[u]) * ld + c0, wa[u]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) wa[u][k] = 0.0;
+      }
+      if (active && jp[u] >= 0 && jp[u] < nx) {
+        load_vw<VW>(xc + int64_t(jp[u]) * ld + c0, wp[u]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) wp[u][k] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < VW; ++k) {
+        accA[k] += va[u] * wa[u][k];
+        accP[k] += vp[u] * wp[u][k];
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < VW; ++k)
+    for (int off = 4; off < 4 * G; off <<= 1) {
+      accA[k] += __shfl_xor(accA[k], off, 64);
+      accP[k] += __shfl_xor(accP[k], off, 64);
+    }
+}
+
 // The prolongation-plus-smoothing pass of one row range.  SA: av holds the
 // values of A D^{-1} (a_ij dinv[j]); dinv still scales the row's own term.
 template <typename T, int PPL, int VW, int NT, bool SEG, bool SA>
@@ -422,6 +499,36 @@ k_amg_affine_pair_ad(int k, const KrylovCtl* ctl, int n, int p, int G,
                      const T* __restrict__ xc, double alpha, double beta, T* __restrict__ out) {
   affine_pair_rows<T, PPL, VW, NT, SEG, true>(k, ctl, n, p, G, arp, aci, adv, dinv, b, prp, pci,
                                               pv, xc, alpha, beta, out);
+}
+
+// k_amg_affine_pair_ad with four lanes per row sharing their index loads
+// (row_dot_pair_q); nx = rows of xc
+template <typename T, int VW, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_amg_affine_pair_q(int k, const KrylovCtl* ctl, int n, int p, int G,
+                    const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
+                    const T* __restrict__ adv, const T* __restrict__ dinv,
+                    const T* __restrict__ b, const int32_t* __restrict__ prp,
+                    const int32_t* __restrict__ pci, const T* __restrict__ pv,
+                    const T* __restrict__ xc, int nx, double alpha, double beta,
+                    T* __restrict__ out) {
+  if (ctl && finished_by(ctl, k)) return;
+  const int c0 = VW * (threadIdx.x % 4);
+  const int g = (threadIdx.x / 4) % G;
+  for (RowRange<NT, 4, false> rr(n, G); rr.r < rr.end; rr.r += rr.step) {
+    const int64_t row = rr.r;
+    double ab[VW], corr[VW];
+    row_dot_pair_q<T, VW>(aci, adv, b, n, arp[row], arp[row + 1], pci, pv, xc, nx, prp[row],
+                          prp[row + 1], p, c0, c0 < p, g, G, ab, corr);
+    if (c0 >= p || g != 0) continue;
+    const int64_t i = row * p + c0;
+    double bi[VW], o[VW];
+    load_vw<VW>(b + i, bi);
+    const double dr = double(dinv[row]);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) o[q] = dr * (alpha * bi[q] - beta * ab[q]) + corr[q];
+    store_vw<VW>(out + i, o);
+  }
 }
 
 // x = M b with M dense nr x ncols (row-major, FP64): the coarsest solve

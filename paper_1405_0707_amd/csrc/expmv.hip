@@ -742,6 +742,14 @@ void amg_level_vw(expmv_plan_s* pl, AmgDev& H, int l, int p, const T* b, T* out,
   // A reads A D^{-1}
   auto launch_pair = [&](int G, const KtEv& e, const T* xc) {
     if constexpr (std::is_same<T, double>::value && VW == 4) {
+      if (L.ADv.p && PPL == 4) {
+        const int nx = int(H.lv[l + 1]->n);
+        hipExtLaunchKernelGGL((k_amg_affine_pair_q<T, VW, kThreads>),
+                              dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0, k,
+                              ctl, n, p, G, L.arp, L.aci, L.ADv.p, dinv, b, L.Pfrp.p, L.Pfci.p,
+                              lv.pf, xc, nx, L.alpha, L.beta, out);
+        return;
+      }
       if (L.ADv.p) {
         hipExtLaunchKernelGGL((k_amg_affine_pair_ad<T, PPL, VW, kThreads, false>),
                               dim3(grid_amg(n, PPL * G)), dim3(kThreads), 0, s, e.e0, e.e1, 0, k,
