@@ -140,10 +140,11 @@ struct Carver {
 
 constexpr int kAmgMaxDeg = 4;
 constexpr double kAmgEigRatio = 20.0;   // Chebyshev interval [lmax / ratio, lmax]
-// one smoothing step (damped Jacobi, weight 2 / (lmax (1 + 1/ratio))): the
-// 128^3 convection-diffusion solve needed 1,356 BiCGStab iterations at ratio
-// 20 (weight 1.90 / lmax), 1,148 at 6, 1,136 at 8 (1.78 / lmax), 1,199 at 11
-constexpr double kAmgJacobiRatio = 8.0;
+// one smoothing step (damped Jacobi, weight 2 / (lmax (1 + 1/ratio))): with
+// the nonsymmetric prolongator weight 1.6 / lmax the 128^3
+// convection-diffusion solve needed 964 BiCGStab iterations at ratio 6, 942
+// at 8, 926 at 11 (weight 1.83 / lmax), 979 at 14 and 1,043 at 20
+constexpr double kAmgJacobiRatio = 11.0;
 constexpr int64_t kAmgFuseGrowth = 16;  // fused operators: at most this many times nnz(A) + nnz(P)
 constexpr int kKtSlots = 4096;   // timed launches between two collections (opts.profile > 0)
 

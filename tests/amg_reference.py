@@ -10,7 +10,7 @@ V-cycle on level l with right-hand side b:
   x = S(b, x)             the same smoothing polynomial
 with the coarsest level solved exactly.  Chebyshev smoothing on D^{-1} A
 over [lmax / ratio, lmax] (Saad, Algorithm 12.1), ratio 20 for two or more
-steps and 8 for one (damped Jacobi with weight 2 / (lmax (1 + 1/8))), as the
+steps and 11 for one (damped Jacobi with weight 2 / (lmax (1 + 1/11))), as the
 library chooses them:
   step 0: d = (1/theta) D^{-1} (b - A x);  x += d
   step k: d = rho_k rho_{k-1} d + (2 rho_k / delta) D^{-1} (b - A x);  x += d
@@ -21,7 +21,7 @@ import numpy as np
 import scipy.sparse as sp
 
 EIG_RATIO = 20.0
-JACOBI_RATIO = 8.0
+JACOBI_RATIO = 11.0
 
 
 def chebyshev_coefficients(lmax: float, degree: int, ratio: float | None = None):
