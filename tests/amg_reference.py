@@ -9,7 +9,7 @@ V-cycle on level l with right-hand side b:
   x += P_l V(P_l^T (b - A_l x), l + 1)
   x = S(b, x)             the same smoothing polynomial
 with the coarsest level solved exactly.  Chebyshev smoothing on D^{-1} A
-over [lmax / ratio, lmax] (Saad, Algorithm 12.1), ratio 20 for two or more
+over [lmax / ratio, lmax] (Saad, Algorithm 12.1), ratio 10 for two or more
 steps and 11 for one (damped Jacobi with weight 2 / (lmax (1 + 1/11))), as the
 library chooses them:
   step 0: d = (1/theta) D^{-1} (b - A x);  x += d
@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-EIG_RATIO = 20.0
+EIG_RATIO = 10.0
 JACOBI_RATIO = 11.0
 
 
