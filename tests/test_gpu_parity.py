@@ -345,7 +345,7 @@ def test_toeplitz_execute_matches_direct_rational(n, p):
 
 
 def test_toeplitz_full_size_properties():
-    """n = 2^20, p = 16, m = 10 (the full Toeplitz workload): properties that
+    """n = 2^20, p = 16, m = 17 (the full Toeplitz workload): properties that
     hold at any size, contraction and the symmetric adjoint identity (the
     oracle parity at this size is test_gpu_full_size.py's
     test_toeplitz2p20_matches_oracle)."""
