@@ -45,6 +45,11 @@ HBM_PEAK_GBS = 8000.0
 # and 5.5 s, m = 20 7 cycles and 6.4 s, m = 12 15 cycles and 7.8 s, m = 28 and
 # 31 4 cycles and 5.5 and 5.6 s, with the same accuracy against the oracle
 C4_M = 24
+# block steps per cycle of the 1024^2 workload: both forms converge within one
+# cycle, the FP64 form at m = 10 (m = 7, 8, 9 take a second cycle: 0.75-0.88 s
+# forward), the mixed form (tol 1e-6) at m = 8 (0.24 s forward against 0.30 s
+# at m = 10)
+C5_M = {"fp64": 10, "mixed": 8}
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 # HBM bytes per launch of a kernel class on the timed workload from two
@@ -258,8 +263,9 @@ def main():
         c5 = {}
         golden5 = os.path.join(GOLDEN, "vardiff1024.npz")
         for prec, tol in (("fp64", 1e-10), ("mixed", tolmx)):
-            pl5 = Plan.csr(V.A.rowptr, V.A.colind, V.A.val, V.t, device=dev, m=V.m, k=V.k,
-                           precision=prec, inner_maxit=200000)
+            m5 = C5_M[prec]
+            pl5 = Plan.csr(V.A.rowptr, V.A.colind, V.A.val, V.t, device=dev, m=m5,
+                           k=V.p * (m5 // 3), precision=prec, inner_maxit=200000)
             s_f, (Z5, if5) = timed(lambda: pl5.execute(B5, tol=tol), args.extra_reps)
             s_b, (gB, gt, ib5) = timed(lambda: pl5.adjoint(G5, B5, tol=tol), args.extra_reps)
             rec = {"forward_s": round(s_f, 4), "adjoint_s": round(s_b, 4),
