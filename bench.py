@@ -41,9 +41,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # block Arnoldi steps per cycle of the 128^3 workload (k = p floor(m / 3) = 128):
-# the configuration leaves m open; with cheap restarts m = 24 needs 5 cycles
-# and 5.5 s, m = 20 7 cycles and 6.4 s, m = 12 15 cycles and 7.8 s, m = 28 and
-# 31 4 cycles and 5.5 and 5.6 s, with the same accuracy against the oracle
+# the configuration leaves m open; m = 24 needs 5 cycles and 4.0 s, m = 20 7
+# cycles and 4.5 s, m = 28 4 cycles and 4.0 s (mixed form 1.65, 1.92, 2.00 s),
+# with the same accuracy against the oracle
 C4_M = 24
 # block steps per cycle of the 1024^2 workload: both forms converge within one
 # cycle, the FP64 form at m = 10 (m = 7, 8, 9 take a second cycle: 0.75-0.88 s
