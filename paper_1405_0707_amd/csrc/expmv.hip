@@ -342,6 +342,23 @@ constexpr bool kWide8 = sizeof(T) == 4 && PP >= 16;
     }                                                                        \
   } while (0)
 
+// Lane width of the BiCGStab vector updates (k_bcg_u1/u2/u3): four FP64
+// columns per lane (two 16-byte accesses) for blocks of 16 or more columns
+// with p a multiple of 4, else as the SpMMs.  On the 128^3 workload u1 and u3
+// took 0.247 / 0.472 ms at two columns and 0.228 / 0.450 ms at four, while
+// the SpMMs lost at four (0.309 against 0.293 ms).
+#define UPD_DISPATCH(T, PP, p, ...)                                          \
+  do {                                                                       \
+    if constexpr (PP >= 16 && sizeof(T) == 8) {                              \
+      if ((p) % 4 == 0) {                                                    \
+        constexpr int PPL_ = PP / 4, VW_ = 4;                                \
+        __VA_ARGS__;                                                         \
+        break;                                                               \
+      }                                                                      \
+    }                                                                        \
+    SPMM_DISPATCH(T, PP, p, __VA_ARGS__);                                    \
+  } while (0)
+
 // CG kernels (working type T): PPL_ lanes per row with VW_ adjacent columns
 // each, PPL_ VW_ = PP: VW_ = 8 for FP32 blocks of 16 or more columns with p a
 // multiple of 8 (kWide8), else 4 when p is a multiple of 4 and the block is
@@ -1059,7 +1076,7 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
       kt.sampling = pl->opts.profile > 0 && ((i + 1) % pl->opts.profile) == 0;
       DISPATCH_PP(PP, {
         const KtEv e1 = kt_take(pl, EXPMV_KT_BCG_U1, 4 * blk);
-        SPMM_DISPATCH(T, P_, p,
+        UPD_DISPATCH(T, P_, p,
                       hipExtLaunchKernelGGL((k_bcg_u1<T, PPL_, VW_>), dim3(grid),
                                             dim3(kCgThreads), 0, s, e1.e0, e1.e1, 0, i, int(n),
                                             p, r, pv, v, w.bcgst, w.ctl, w.part_rr, tol2, maxit));
@@ -1067,7 +1084,7 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
         bcg_spmm<T, P_, 1>(s, kt_take(pl, EXPMV_KT_BCG_SPMM1, by_s), grid, i, int(n), p, A.rowptr,
                            A.colind, A.val, dscale, H ? ph : pv, rh, v, w.ctl, w.part_sig);
         const KtEv e2 = kt_take(pl, EXPMV_KT_BCG_U2, 3 * blk);
-        SPMM_DISPATCH(T, P_, p,
+        UPD_DISPATCH(T, P_, p,
                       hipExtLaunchKernelGGL((k_bcg_u2<T, PPL_, VW_>), dim3(grid),
                                             dim3(kCgThreads), 0, s, e2.e0, e2.e1, 0, i, int(n),
                                             p, r, v, sv, w.bcgst, w.ctl, w.part_sig));
@@ -1075,7 +1092,7 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
         bcg_spmm<T, P_, 2>(s, kt_take(pl, EXPMV_KT_BCG_SPMM2, by_s), grid, i, int(n), p, A.rowptr,
                            A.colind, A.val, dscale, H ? sh : sv, sv, tv, w.ctl, w.part_sig);
         const KtEv e3 = kt_take(pl, EXPMV_KT_BCG_U3, by_u3);
-        SPMM_DISPATCH(T, P_, p,
+        UPD_DISPATCH(T, P_, p,
                       hipExtLaunchKernelGGL((k_bcg_u3<T, PPL_, VW_>), dim3(grid),
                                             dim3(kCgThreads), 0, s, e3.e0, e3.e1, 0, i, int(n),
                                             p, A.dinv, pv, sv, tv, rh, ph, sh, out, r, w.bcgst,
