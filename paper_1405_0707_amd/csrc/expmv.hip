@@ -1535,8 +1535,16 @@ void panel_gemm(expmv_plan_s* pl, int p, const T* V, int npan, const double* C, 
     const int64_t steps = (pl->n + 16 * RB - 1) / (16 * RB);
     const int grid = int(std::max<int64_t>(1, std::min<int64_t>(2048, steps)));
 #define PG_MMA(NBW_, RB_)                                                                         \
-  hipLaunchKernelGGL((k_panel_gemm_mma<T, TO, NBW_, RB_>), dim3(grid), dim3(kThreads), 0,          \
-                     pl->stream, pl->n, p, V, npan, C, ldc, nout, out, chunk_stride, ldo, accumulate)
+  do {                                                                                            \
+    if (p == 16)                                                                                  \
+      hipLaunchKernelGGL((k_panel_gemm_mma<T, TO, NBW_, RB_, 16>), dim3(grid), dim3(kThreads), 0,  \
+                         pl->stream, pl->n, p, V, npan, C, ldc, nout, out, chunk_stride, ldo,     \
+                         accumulate);                                                             \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_panel_gemm_mma<T, TO, NBW_, RB_>), dim3(grid), dim3(kThreads), 0,      \
+                         pl->stream, pl->n, p, V, npan, C, ldc, nout, out, chunk_stride, ldo,     \
+                         accumulate);                                                             \
+  } while (0)
     if (NBW <= 1) PG_MMA(1, 4);
     else if (NBW <= 2) PG_MMA(2, 4);
     else if (NBW <= 4) PG_MMA(4, 2);

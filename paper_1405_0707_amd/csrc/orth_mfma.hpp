@@ -253,11 +253,12 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 // n p, ldo = p).  A workgroup handles 16 RB rows per step; wave w computes
 // the 16-column output blocks w, w + 4, ... (NBW of them) for all RB row
 // blocks, so V is read from memory once and C once per step.
-template <typename T, typename TO, int NBW, int RB>
+template <typename T, typename TO, int NBW, int RB, int PC = 0>
 __global__ void __launch_bounds__(kThreads)
-k_panel_gemm_mma(int64_t n, int p, const T* __restrict__ V, int npan, const double* __restrict__ C,
-                 int ldc, int nout, TO* __restrict__ out, int64_t chunk_stride, int64_t ldo,
-                 int accumulate) {
+k_panel_gemm_mma(int64_t n, int p_arg, const T* __restrict__ V, int npan,
+                 const double* __restrict__ C, int ldc, int nout, TO* __restrict__ out,
+                 int64_t chunk_stride, int64_t ldo, int accumulate) {
+  const int p = PC ? PC : p_arg;   // PC: p known at compile time
   using M = Mma<double>;
   using v4 = M::v4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
