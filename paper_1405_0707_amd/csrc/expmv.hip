@@ -281,7 +281,9 @@ namespace expmv {
 namespace {
 
 constexpr int kCgGrid = 512;   // workgroups of the inner-solver kernels
-constexpr int kOrthGrid = 512; // most workgroups (partial sums) of an orthogonalisation pass
+constexpr int kOrthGrid = 768; // most workgroups (partial sums) of an orthogonalisation pass
+constexpr int kCUs = 256;
+constexpr size_t kLdsPerCU = 160 * 1024;
 constexpr int64_t kAmgFusedMax = int64_t(1) << 21;   // entries of the fused Inv R (16 MB)
 constexpr int kMaxTimes = 32;  // times of one expmv_execute_times call
 
@@ -1355,6 +1357,15 @@ OrthLaunch orth_config(int64_t n, int p, int npan, int O, size_t elem) {
   return L;
 }
 
+// Workgroups of a matrix-core Gram-Schmidt pass: as many as the CUs hold at
+// once by the kernel's LDS, up to three per CU (its registers allow three
+// waves per SIMD), and no more than the 64-row steps; a second generation
+// of workgroups would only start once the first had finished its rows.
+int orth_mma_grid(size_t lds, int64_t steps) {
+  const int per_cu = int(std::max<size_t>(1, std::min<size_t>(3, kLdsPerCU / lds)));
+  return int(std::max<int64_t>(1, std::min<int64_t>(int64_t(kCUs) * per_cu, steps)));
+}
+
 // One streaming pass; returns the number of workgroups whose partials are
 // in ws.partial (0 when the mode writes no partials).
 template <typename T>
@@ -1369,7 +1380,7 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
   const int nmb = (npv * p + 15) / 16;
   if (p <= 32 && nmb <= 32) {
     const int64_t steps = (pl->n + 63) / 64;
-    const int grid = int(std::max<int64_t>(1, std::min<int64_t>(kOrthGrid, steps)));
+    int grid = 1;
     const int NB = (p + 15) / 16;
     const int MBW = nmb <= 8 ? 2 : (nmb <= 16 ? 4 : (nmb <= 24 ? 6 : 8));
     const bool upd = (mode == kUpdProj || mode == kUpdGram);
@@ -1383,6 +1394,7 @@ int orth_pass(expmv_plan_s* pl, int mode, int p, const T* V, int npan, const T* 
     hipEvent_t e0 = ev.e0, e1 = ev.e1;
 #define ORTH_MMA(NB_, MBW_)                                                                     \
   do {                                                                                          \
+    grid = orth_mma_grid(orth_mma_lds<T, NB_, MBW_>(), steps);                                  \
     if (p == 16 * NB_)                                                                          \
       hipExtLaunchKernelGGL((k_orth_mma<T, NB_, MBW_, 16 * NB_>), dim3(grid), dim3(kThreads), 0, \
                             pl->stream, e0, e1, 0, mode, pl->n, p, V, npv, Win, Wout, C,        \

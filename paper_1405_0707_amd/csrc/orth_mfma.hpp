@@ -63,6 +63,20 @@ __device__ inline T basis_at(const T* __restrict__ V, int64_t n, int p, int64_t 
   return V[int64_t(pan) * n * p + row * p + (col - pan * p)];
 }
 
+// Projection column blocks per wave whose sums k_orth_mma keeps in registers
+// rather than LDS: one with six FP64 blocks per wave, none otherwise.
+template <typename T, int MBW>
+constexpr int orth_reg_blocks() {
+  return (MBW == 6 && sizeof(T) == 8) ? 1 : 0;
+}
+
+// LDS bytes of k_orth_mma<T, NB, MBW, *>: sW, sN and sP
+template <typename T, int NB, int MBW>
+constexpr size_t orth_mma_lds() {
+  return sizeof(T) * 64 * 16 * NB + sizeof(double) * 4 * 16 * NB +
+         sizeof(double) * 4 * (MBW - orth_reg_blocks<T, MBW>()) * 256 * NB;
+}
+
 // NB = 16-column blocks of W (p <= 16 NB); MBW = projection column blocks
 // per wave (npan p <= 64 MBW); PC = p when it is known at compile time (16 NB:
 // panel and column offsets by shifts), else 0.  Basis and W loads clamp
@@ -81,8 +95,12 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
   __shared__ double sN[4][16 * NB];     // per-wave column norms (kProj)
   // the projection sums of column block mb live in LDS (sP[mb], NB blocks of
   // 16 x 16, row = basis column within the block), so that the loop over a
-  // wave's blocks need not be unrolled to keep them in registers
-  __shared__ double sP[4 * MBW][256 * NB];
+  // wave's blocks need not be unrolled to keep them in registers; with six
+  // FP64 blocks per wave the first one (u = 0) keeps its sums in registers
+  // (racc) instead, which brings the kernel's LDS to 48.5 KB: three
+  // workgroups per CU rather than two
+  constexpr int RB = orth_reg_blocks<T, MBW>();
+  __shared__ double sP[4 * (MBW - RB)][256 * NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ldw = 16 * NB;
@@ -95,8 +113,13 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 
   double gacc[4] = {0.0, 0.0, 0.0, 0.0};   // Gram block of this wave
   if (proj)
-    for (int u = 0; u < MBW; ++u)
+    for (int u = 0; u < MBW - RB; ++u)
       for (int e = lane; e < 256 * NB; e += 64) sP[wave + 4 * u][e] = 0.0;
+  double racc[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) racc[b][r] = 0.0;
   double nrm[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) nrm[b] = 0.0;
@@ -183,11 +206,18 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 #pragma unroll
           for (int b = 0; b < NB; ++b) t[b] = M::mma(a[qs], sW[i * ldw + 16 * b + li], t[b]);
         }
+        if (RB && u == 0) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+          for (int b = 0; b < NB; ++b)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            sP[mb][256 * b + M::drow(lane, r) * 16 + li] += double(t[b][r]);
+            for (int r = 0; r < 4; ++r) racc[b][r] += double(t[b][r]);
+        } else {
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              sP[mb - 4 * RB][256 * b + M::drow(lane, r) * 16 + li] += double(t[b][r]);
+        }
       }
     }
     if (gram_owner) {
@@ -219,7 +249,10 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * mb + M::drow(lane, r), j = 16 * b + li;
-          if (col < np_cols && j < p) out[col * p + j] = sP[mb][256 * b + M::drow(lane, r) * 16 + li];
+          if (col < np_cols && j < p)
+            out[col * p + j] = (RB && u == 0)
+                                   ? racc[b][r]
+                                   : sP[mb - 4 * RB][256 * b + M::drow(lane, r) * 16 + li];
         }
     }
   }
