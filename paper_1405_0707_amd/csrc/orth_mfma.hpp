@@ -64,17 +64,22 @@ __device__ inline T basis_at(const T* __restrict__ V, int64_t n, int p, int64_t 
 }
 
 // Projection column blocks per wave whose sums k_orth_mma keeps in registers
-// rather than LDS: one with six FP64 blocks per wave, none otherwise.
-template <typename T, int MBW>
+// rather than LDS (at most three), chosen so that one more workgroup fits a
+// CU's 160 KB: FP64 with one column block of W and six blocks per wave
+// (56.5 -> 48.5 KB, three per CU), and with two column blocks of W, FP64 at
+// four (81 -> 65 KB) or six (113 -> 65 KB) and FP32 at six (105 -> 73 KB):
+// two per CU.
+template <typename T, int NB, int MBW>
 constexpr int orth_reg_blocks() {
-  return (MBW == 6 && sizeof(T) == 8) ? 1 : 0;
+  return sizeof(T) == 8 ? (NB == 1 ? (MBW == 6 ? 1 : 0) : (MBW == 4 ? 1 : (MBW == 6 ? 3 : 0)))
+                        : (NB == 2 && MBW == 6 ? 2 : 0);
 }
 
 // LDS bytes of k_orth_mma<T, NB, MBW, *>: sW, sN and sP
 template <typename T, int NB, int MBW>
 constexpr size_t orth_mma_lds() {
   return sizeof(T) * 64 * 16 * NB + sizeof(double) * 4 * 16 * NB +
-         sizeof(double) * 4 * (MBW - orth_reg_blocks<T, MBW>()) * 256 * NB;
+         sizeof(double) * 4 * (MBW - orth_reg_blocks<T, NB, MBW>()) * 256 * NB;
 }
 
 // NB = 16-column blocks of W (p <= 16 NB); MBW = projection column blocks
@@ -95,11 +100,11 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
   __shared__ double sN[4][16 * NB];     // per-wave column norms (kProj)
   // the projection sums of column block mb live in LDS (sP[mb], NB blocks of
   // 16 x 16, row = basis column within the block), so that the loop over a
-  // wave's blocks need not be unrolled to keep them in registers; with six
-  // FP64 blocks per wave the first one (u = 0) keeps its sums in registers
-  // (racc) instead, which brings the kernel's LDS to 48.5 KB: three
-  // workgroups per CU rather than two
-  constexpr int RB = orth_reg_blocks<T, MBW>();
+  // wave's blocks need not be unrolled to keep them in registers; the first
+  // RB blocks (u < RB) keep their sums in registers (racc0 .. racc2)
+  // instead, so that one more workgroup fits a CU
+  constexpr int RB = orth_reg_blocks<T, NB, MBW>();
+  static_assert(RB <= 3 && RB < MBW, "at most three projection blocks in registers");
   __shared__ double sP[4 * (MBW - RB)][256 * NB];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -115,11 +120,11 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
   if (proj)
     for (int u = 0; u < MBW - RB; ++u)
       for (int e = lane; e < 256 * NB; e += 64) sP[wave + 4 * u][e] = 0.0;
-  double racc[NB][4];
+  double racc0[NB][4], racc1[NB][4], racc2[NB][4];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) racc[b][r] = 0.0;
+    for (int r = 0; r < 4; ++r) racc0[b][r] = racc1[b][r] = racc2[b][r] = 0.0;
   double nrm[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) nrm[b] = 0.0;
@@ -206,11 +211,21 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
 #pragma unroll
           for (int b = 0; b < NB; ++b) t[b] = M::mma(a[qs], sW[i * ldw + 16 * b + li], t[b]);
         }
-        if (RB && u == 0) {
+        if (RB > 0 && u == 0) {
 #pragma unroll
           for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) racc[b][r] += double(t[b][r]);
+            for (int r = 0; r < 4; ++r) racc0[b][r] += double(t[b][r]);
+        } else if (RB > 1 && u == 1) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) racc1[b][r] += double(t[b][r]);
+        } else if (RB > 2 && u == 2) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) racc2[b][r] += double(t[b][r]);
         } else {
 #pragma unroll
           for (int b = 0; b < NB; ++b)
@@ -250,9 +265,9 @@ k_orth_mma(int mode, int64_t n, int p_arg, const T* __restrict__ V, int npan, co
         for (int r = 0; r < 4; ++r) {
           const int col = 16 * mb + M::drow(lane, r), j = 16 * b + li;
           if (col < np_cols && j < p)
-            out[col * p + j] = (RB && u == 0)
-                                   ? racc[b][r]
-                                   : sP[mb - 4 * RB][256 * b + M::drow(lane, r) * 16 + li];
+            out[col * p + j] =
+                u < RB ? (u == 0 ? racc0[b][r] : (u == 1 ? racc1[b][r] : racc2[b][r]))
+                       : sP[mb - 4 * RB][256 * b + M::drow(lane, r) * 16 + li];
         }
     }
   }
