@@ -321,11 +321,15 @@ k_panel_gemm_mma(int64_t n, int p_arg, const T* __restrict__ V, int npan,
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int u = 0; u < NBW; ++u) acc[rb][u] = v4{0, 0, 0, 0};
-    // two K-steps per iteration, every load issued before the products
-    for (int k0 = 0; k0 < np_cols; k0 += 8) {
-      double a[2][RB], bv[2][NBW];
+    // KH K-steps per iteration, every load issued before the products: four
+    // with up to two row blocks (the X update: 10.7 against 11.4 ms at
+    // m = 24, p = 16), two with four (the restart rotation, where four
+    // measured slower)
+    constexpr int KH = RB <= 2 ? 4 : 2;
+    for (int k0 = 0; k0 < np_cols; k0 += 4 * KH) {
+      double a[KH][RB], bv[KH][NBW];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < KH; ++h) {
         const int kc = k0 + 4 * h + lk;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -339,7 +343,7 @@ k_panel_gemm_mma(int64_t n, int p_arg, const T* __restrict__ V, int npan,
         }
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < KH; ++h)
 #pragma unroll
         for (int u = 0; u < NBW; ++u) {
           if (wave + 4 * u >= nnb) break;
