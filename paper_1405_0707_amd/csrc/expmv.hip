@@ -1061,11 +1061,11 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
   T* sh = H ? reinterpret_cast<T*>(w.ksh) : nullptr;   // M^{-1} s
   const T* dscale = H ? nullptr : A.dinv;
   DISPATCH_PP(PP, hipLaunchKernelGGL((k_bcg_init<T, T, P_>), dim3(grid), dim3(kCgThreads), 0, s,
-                                     int(n), p, sign, src, out, r, rh, pv, v, w.ctl,
-                                     w.part_rr));
+                                     int(n), p, sign, src, out, r, rh, w.ctl, w.part_rr));
   // timed bytes per launch: each SpMM reads K (CSR), its input (gathered)
   // and the vector its partials pair with, and writes its output (+ D^{-1}
-  // for Jacobi); u1 reads r, p, v and writes p; u2 reads r, v, writes s; u3
+  // for Jacobi); u1 reads r, p, v and writes p (reads r only at i = 0);
+  // u2 reads r, v, writes s; u3
   // reads p^, s^ (or p, s and D^{-1}), s, t, r~ and x, writes x and r
   const double es = double(sizeof(T)), blk = es * double(n) * p;
   const double by_s = csr_bytes(n, pl->nnz) + 3 * blk + (H ? 0.0 : es * n);
@@ -1077,7 +1077,7 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
       kt.cur_iter = i;
       kt.sampling = pl->opts.profile > 0 && ((i + 1) % pl->opts.profile) == 0;
       DISPATCH_PP(PP, {
-        const KtEv e1 = kt_take(pl, EXPMV_KT_BCG_U1, 4 * blk);
+        const KtEv e1 = kt_take(pl, EXPMV_KT_BCG_U1, (i == 0 ? 2 : 4) * blk);
         UPD_DISPATCH(T, P_, p,
                       hipExtLaunchKernelGGL((k_bcg_u1<T, PPL_, VW_>), dim3(grid),
                                             dim3(kCgThreads), 0, s, e1.e0, e1.e1, 0, i, int(n),

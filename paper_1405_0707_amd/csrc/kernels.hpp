@@ -760,7 +760,9 @@ k_cg_b(int k, int n, int p, const T* __restrict__ dinv, T* __restrict__ r, const
 // previous kernel's partials.
 // Iteration i:
 //   U1: rho_i = (r^, r), |r|^2 (partials of U3_{i-1} or init); convergence;
-//       beta = (rho_i / rho_{i-1}) (alpha / omega); p = r + beta (p - omega v)
+//       beta = (rho_i / rho_{i-1}) (alpha / omega); p = r + beta (p - omega v),
+//       p = r at i = 0 (p and v start at zero, so they are neither stored by
+//       the init nor read here)
 //   S1: v = K D^{-1} p, partial (r^, v)
 //   U2: alpha = rho_i / (r^, v); s = r - alpha v
 //   S2: t = K D^{-1} s, partials (t, s), (t, t)
@@ -784,8 +786,7 @@ struct BcgState {
 template <typename T, typename TS, int PP>
 __global__ void __launch_bounds__(kCgThreads)
 k_bcg_init(int n, int p, double sign, const TS* __restrict__ src, T* __restrict__ x,
-           T* __restrict__ r, T* __restrict__ rhat, T* __restrict__ pv, T* __restrict__ v,
-           KrylovCtl* ctl, double* __restrict__ part_rr) {
+           T* __restrict__ r, T* __restrict__ rhat, KrylovCtl* ctl, double* __restrict__ part_rr) {
   __shared__ double red[kCgThreads];
   const int c = threadIdx.x % PP;
   double bb = 0.0;
@@ -798,8 +799,6 @@ k_bcg_init(int n, int p, double sign, const TS* __restrict__ src, T* __restrict_
       r[i] = b;
       rhat[i] = b;
       x[i] = T(0);
-      pv[i] = T(0);
-      v[i] = T(0);
       bb += double(b) * double(b);
     }
   }
@@ -899,8 +898,13 @@ k_bcg_u1(int i, int n, int p, const T* __restrict__ r, T* __restrict__ pv, const
   for (int64_t row = seg0 + threadIdx.x / PPL; row < seg1; row += kCgThreads / PPL) {
     if (c0 < p) {
       const int64_t idx = row * p + c0;
-      T rv[VW], pw[VW], vv[VW];
+      T rv[VW];
       ld_vw<VW>(r + idx, rv);
+      if (i == 0) {
+        st_vw<VW>(pv + idx, rv);
+        continue;
+      }
+      T pw[VW], vv[VW];
       ld_vw<VW>(pv + idx, pw);
       ld_vw<VW>(v + idx, vv);
 #pragma unroll
