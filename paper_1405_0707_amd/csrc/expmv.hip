@@ -1065,11 +1065,11 @@ InnerResult inner_bicgstab(expmv_plan_s* pl, int transpose, const T* src, double
   // timed bytes per launch: each SpMM reads K (CSR), its input (gathered)
   // and the vector its partials pair with, and writes its output (+ D^{-1}
   // for Jacobi); u1 reads r, p, v and writes p (reads r only at i = 0);
-  // u2 reads r, v, writes s; u3
-  // reads p^, s^ (or p, s and D^{-1}), s, t, r~ and x, writes x and r
+  // u2 reads r, v, writes s; u3 reads p^ and s^ (Jacobi: p and D^{-1}), s,
+  // t, r~ and x, writes x and r
   const double es = double(sizeof(T)), blk = es * double(n) * p;
   const double by_s = csr_bytes(n, pl->nnz) + 3 * blk + (H ? 0.0 : es * n);
-  const double by_u3 = 8 * blk + (H ? 0.0 : es * n);
+  const double by_u3 = H ? 8 * blk : 7 * blk + es * n;
   KernelTimer& kt = pl->kt;
   InnerResult res = run_inner_loop(pl, maxit, [&](int launched, int chunk) {
     for (int it = 0; it < chunk; ++it) {
